@@ -1,0 +1,206 @@
+/*
+ * vp.h -- C ABI of libvp, a gfx950 (MI355X) evaluator of the 2-D volume
+ * potential
+ *
+ *     u(x) = (1/2pi) int_Omega log|x - y| f(y) dA_y
+ *
+ * over an unstructured mesh of straight triangles, after Shen & Serkh,
+ * "Accelerating potential evaluation over unstructured meshes in two
+ * dimensions" (problem statement: Sec. 1 and Sec. 3.6; method: Sec. 3-4).
+ *
+ * The density is given by its values at the interpolation nodes of every
+ * triangle (vp_ref_nodes); per triangle it is represented by the degree-p
+ * interpolant f_h (Sec. 2.2 interpolation matrix, Sec. 3.5).  The library
+ * returns, at every target x_t,
+ *
+ *   u(x_t) = (1/2pi) sum_Delta sum_j w_j |J_Delta| f_h(y_j) log|x_t - y_j|
+ *          + sum_{Delta in S(x_t) u N(x_t)} sum_k R_{t,Delta,k} c_k(Delta)
+ *
+ * i.e. the far rule applied to every triangle (Sec. 3.2, coupled as point
+ * charges as in Sec. 3.6) plus the subtract-and-add correction (Sec. 3.6)
+ * over the self and near triangles of the target, where the near field is
+ * the union of three Bernstein ellipses per triangle (Sec. 4.1, eqs. rho0,
+ * Erho0, threeE) and the correction row R = (A - B)/2pi holds the accurate
+ * integral A (near: adaptive subdivision, Sec. 3.3 with the Sec. 4.1
+ * stopping rule; self: radius-arc-length coordinates, Sec. 3.4, eq.
+ * volpot_self_single) minus the far rule's own contribution B, both against
+ * the Koornwinder basis (Sec. 2.1).
+ *
+ * Conventions shared by every call
+ *  - Every function returns a vp_status.  On an error the library sets a
+ *    thread-local message (vp_last_error) and leaves every output untouched,
+ *    except that after VP_EDEVICE the contents of u_out are unspecified.
+ *  - Reference simplex T = {(x,y): x,y >= 0, x + y <= 1}.  A triangle is
+ *    stored as three vertex indices (A, B, C); if det[B-A, C-A] < 0 the
+ *    library swaps its local vertices 1 and 2 (B <-> C).  Node xi of triangle
+ *    (A, B, C) sits at A + xi_1 (B - A) + xi_2 (C - A), using the oriented
+ *    order.  The collapsed quadrature rules collapse onto vertex B.
+ *  - All coordinates, densities and potentials cross the ABI as double.
+ *  - Host arrays stay owned by the caller; the library copies what it needs
+ *    during the call and keeps no host pointer.  With VP_DEVICE_PTRS the
+ *    density / output pointers are device pointers owned by the caller; they
+ *    must stay valid until the call's work has finished on the context's
+ *    stream (immediately, unless VP_ASYNC).
+ *  - The library owns all mesh and plan device memory.  A mesh must outlive
+ *    its plans (vp_mesh_destroy returns VP_EBUSY while plans exist).
+ *  - One context per host thread, or external serialisation.  Plans are
+ *    read-only after creation.
+ *  - No PyTorch (or other framework) type crosses this ABI: device memory
+ *    and streams arrive as raw pointers and hipStream_t (as void*).
+ */
+#ifndef VP_H
+#define VP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VP_OK = 0,
+  VP_EINVAL = 1,     /* invalid argument (sizes, orders, degenerate geometry, NaN) */
+  VP_ENOMEM = 2,     /* device allocation failed or the context's HBM budget is exceeded */
+  VP_EDEVICE = 3,    /* a HIP runtime call or kernel failed */
+  VP_ENOTSUP = 4,    /* valid request this build does not support */
+  VP_EBUSY = 5,      /* object still in use (mesh with live plans) */
+  VP_EINTERNAL = 6   /* internal limit hit (reported with the message) */
+} vp_status;
+
+typedef enum {
+  VP_FP64 = 0,   /* all per-solve arithmetic in double */
+  VP_MIXED = 1   /* reserved: FP32 far field / corrections (returns VP_ENOTSUP) */
+} vp_precision;
+
+/* vp_execute flags */
+#define VP_DEVICE_PTRS 1u  /* density and u_out are device pointers */
+#define VP_FAR_ONLY    2u  /* skip the self/near corrections: u = far sum only */
+#define VP_ASYNC       4u  /* return without synchronising the stream (device pointers only) */
+
+typedef struct vp_ctx vp_ctx;
+typedef struct vp_mesh vp_mesh;
+typedef struct vp_plan vp_plan;
+
+/* Optional plan parameters; a NULL pointer selects the defaults. */
+typedef struct {
+  double c_n;       /* C_N of eq. rho0 (default 1.0: the larger, sufficient ellipse E' of Sec. 4.1) */
+  int q_near;       /* points per direction of the sub-triangle rule, N_n = 2 q_near - 1 (default 7) */
+  int n_l;          /* Gauss-Legendre points per arc-length panel, N_l (default 16) */
+  double tau;       /* barycentric tolerance of the self test (default 1e-13) */
+  int depth_cap;    /* maximum subdivision depth of a near pair (default 50) */
+  int dyadic_cap;   /* maximum dyadic levels per side of a self piece (default 60) */
+} vp_plan_opts;
+
+/* Sizes and statistics of a plan. */
+typedef struct {
+  int64_t n_tri;           /* triangles of the quadrature mesh */
+  int64_t n_src;           /* far-field sources = n_tri * q^2 */
+  int64_t n_tgt;           /* targets */
+  int64_t n_pairs;         /* self + near (target, triangle) pairs */
+  int64_t n_self;          /* self pairs */
+  int64_t near_subtri;     /* near-rule leaves summed over all near pairs (paper's s_n times pairs) */
+  int64_t self_panels;     /* arc-length panels summed over all self pairs (paper's s_l) */
+  int64_t capped_leaves;   /* near leaves integrated at the depth cap */
+  int64_t bytes_resident;  /* device bytes held by the plan */
+  int32_t p, q, n_p, n_f;  /* orders; n_p = (p+1)(p+2)/2 nodes, n_f = q^2 far nodes per triangle */
+  double eps;
+  double ms_classify;      /* device time of the near-list construction */
+  double ms_rows;          /* device time of the correction-row precompute */
+} vp_plan_stats;
+
+/* Context on HIP device `device`.  `hip_stream_or_null` is a hipStream_t the
+ * context issues all work on (NULL: the device's null stream).
+ * `hbm_budget_bytes` caps the device memory its meshes and plans may hold
+ * (0: no cap).  *out receives the context. */
+vp_status vp_ctx_create(int device, void* hip_stream_or_null, uint64_t hbm_budget_bytes, vp_ctx** out);
+vp_status vp_ctx_destroy(vp_ctx* ctx);
+
+/* Message of the last error on the calling thread ("" if none).  Valid until
+ * the next call into the library on this thread. */
+const char* vp_last_error(void);
+
+/* Reference interpolation nodes of order p, 1 <= p <= 10 (stand-in for the
+ * Vioreanu-Rokhlin nodes of Sec. 2.2): the interior Blyth-Pozrikidis nodes
+ * built from the Gauss-Lobatto-Legendre points of order p + 3.  Writes
+ * n_p = (p+1)(p+2)/2 into *n_p_out and, if xy_out is not NULL, the nodes as
+ * [n_p][2] doubles.  The density passed to vp_execute is sampled at these
+ * nodes, in this order. */
+vp_status vp_ref_nodes(int p, double* xy_out, int* n_p_out);
+
+/* Reference quadrature rules the plans are built from (host-side data, no
+ * device needed), for inspection:
+ *   which = 0  n-point Gauss-Legendre on [0,1]            -> x, w
+ *           1  n-point Gauss rule for -log(r) on [0,1]    -> x, w
+ *           2  n x n collapsed Gauss rule on the simplex  -> x, y, w (n^2 nodes;
+ *              Sec. 3.2 far rule / Sec. 3.3 near rule)
+ *           3  radial rule for interpolation order n      -> x = r, y = alpha,
+ *              w = beta: node j contributes (alpha_j log r0 + beta_j) phi(r_j)
+ *              to int_0^1 r log(r0 r) phi(r) dr (Sec. 3.4)
+ *           4  per-edge weights w-hat of the n x n collapsed rule (edges AB,
+ *              BC, CA) used in eq. rho0 -> w[0..2]
+ * *count receives the number of entries; any output may be NULL. */
+vp_status vp_ref_rule(int which, int n, double* x, double* y, double* w, int* count);
+
+/* Upload a triangle mesh: vert_xy [n_vert][2] doubles, tri [n_tri][3]
+ * int32 vertex indices.  Rejects (VP_EINVAL) indices out of range,
+ * non-finite coordinates and degenerate triangles (|det| <= 1e-14 times
+ * the squared size of the triangle's bounding box). */
+vp_status vp_mesh_create(vp_ctx* ctx, int64_t n_vert, const double* vert_xy, int64_t n_tri,
+                         const int32_t* tri, vp_mesh** out);
+vp_status vp_mesh_destroy(vp_mesh* mesh);
+
+/* Build the plan for (mesh, p, q, eps, targets): rule tables, far sources,
+ * the CSR list of self/near pairs per target (Def. of near field, Sec. 3.2;
+ * ellipse union, Sec. 4.1) and the FP64 correction rows of every pair.
+ *   p     interpolation order, 1..10
+ *   q     far rule: q x q collapsed Gauss (exact through degree N = 2q-1), 2..32
+ *   eps   far/near tolerance of eq. precise_far (> 0)
+ *   tgt_xy [n_tgt][2] host doubles, n_tgt >= 0
+ * The work runs on the device; the call returns when the plan is complete. */
+vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double eps, int64_t n_tgt,
+                         const double* tgt_xy, const vp_plan_opts* opts_or_null, vp_plan** out);
+vp_status vp_plan_info(const vp_plan* plan, vp_plan_stats* out);
+
+/* Host copies of the plan's pair list (for inspection and tests):
+ * row_ptr [n_tgt+1] int64 (CSR by target), tri [n_pairs] int32 (ascending
+ * within a target), kind [n_pairs] uint8 (0 = self, 1 = near).  Any pointer
+ * may be NULL. */
+vp_status vp_plan_pairs(const vp_plan* plan, int64_t* row_ptr_out, int32_t* tri_out, uint8_t* kind_out);
+
+/* Host copy of the correction rows [n_pairs][n_p] doubles, pair order as in
+ * vp_plan_pairs: row = (A - B) / 2pi (Sec. 3.6 subtract-and-add). */
+vp_status vp_plan_rows(const vp_plan* plan, double* rows_out);
+
+/* Evaluate the potential for n_rhs >= 1 densities at once.
+ *   density [n_tri][n_p][n_rhs] doubles (values at the interpolation nodes,
+ *           right-hand side fastest), u_out [n_tgt][n_rhs] doubles.
+ *   prec    VP_FP64.
+ *   flags   VP_DEVICE_PTRS | VP_FAR_ONLY | VP_ASYNC.
+ * Steps: per-triangle coefficients c = V^{-1} F (Sec. 2.2) and far charges,
+ * the direct far sum over all sources, then the correction rows applied to
+ * c. */
+vp_status vp_execute(vp_plan* plan, int64_t n_rhs, const double* density, double* u_out,
+                     vp_precision prec, uint32_t flags);
+
+/* Intermediates of vp_execute, for inspection: coefficients
+ * [n_tri][n_p][n_rhs] (Sec. 2.2: c = V^{-1} F per triangle) and far charges
+ * [n_src][n_rhs] = w_j |J| f_h(y_j) / (4 pi) (the 1/2 of log r = log(r^2)/2
+ * folded in), sources ordered triangle-major, node index a*q + b of the
+ * collapsed rule.  Either output may be NULL.  Same pointer flags as
+ * vp_execute. */
+vp_status vp_coefficients(vp_plan* plan, int64_t n_rhs, const double* density, double* coef_out,
+                          double* charge_out, uint32_t flags);
+
+/* Far-source positions [n_src][2] (host copy). */
+vp_status vp_plan_sources(const vp_plan* plan, double* xy_out);
+
+vp_status vp_plan_destroy(vp_plan* plan);
+
+/* Wait for all work issued on the context's stream. */
+vp_status vp_sync(vp_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VP_H */

@@ -1,0 +1,613 @@
+// C ABI of libvp (declared in include/vp.h): argument checks, device memory
+// ownership, host rule tables, and the order in which the kernels run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vp_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+vp_status fail(vp_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+vp_status hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) return fail(VP_ENOMEM, "%s: out of device memory", what);
+  return fail(VP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define VP_HIP(call, what)                  \
+  do {                                      \
+    hipError_t e_ = (call);                 \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+vp_plan_opts default_opts() {
+  vp_plan_opts o;
+  o.c_n = 1.0;
+  o.q_near = 7;
+  o.n_l = 16;
+  o.tau = 1e-13;
+  o.depth_cap = 50;
+  o.dyadic_cap = 60;
+  return o;
+}
+
+void free_plan_memory(vp_plan* pl) {
+  for (void* p : pl->allocs) (void)hipFree(p);
+  pl->allocs.clear();
+  double* ws[] = {pl->ws_f, pl->ws_c, pl->ws_q, pl->ws_part, pl->ws_u};
+  for (double* p : ws)
+    if (p) (void)hipFree(p);
+  pl->ws_f = pl->ws_c = pl->ws_q = pl->ws_part = pl->ws_u = nullptr;
+}
+
+struct PlanGuard {
+  vp_plan* pl;
+  bool keep = false;
+  ~PlanGuard() {
+    if (!keep && pl) {
+      free_plan_memory(pl);
+      delete pl;
+    }
+  }
+};
+
+template <class T>
+hipError_t upload(vp_plan* pl, T** dst, const T* src, size_t n, hipStream_t st) {
+  size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+  hipError_t e = hipMalloc((void**)dst, bytes);
+  if (e != hipSuccess) return e;
+  pl->allocs.push_back(*dst);
+  pl->bytes += bytes;
+  if (n) e = hipMemcpyAsync(*dst, src, n * sizeof(T), hipMemcpyHostToDevice, st);
+  return e;
+}
+
+hipError_t plan_alloc(vp_plan* pl, void** dst, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 8);
+  hipError_t e = hipMalloc(dst, bytes);
+  if (e != hipSuccess) return e;
+  pl->allocs.push_back(*dst);
+  pl->bytes += bytes;
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vp_last_error(void) { return g_err.c_str(); }
+
+vp_status vp_ctx_create(int device, void* stream, uint64_t budget, vp_ctx** out) {
+  if (!out) return fail(VP_EINVAL, "vp_ctx_create: out is NULL");
+  int n = 0;
+  VP_HIP(hipGetDeviceCount(&n), "hipGetDeviceCount");
+  if (device < 0 || device >= n) return fail(VP_EINVAL, "vp_ctx_create: device %d of %d", device, n);
+  VP_HIP(hipSetDevice(device), "hipSetDevice");
+  vp_ctx* c = new vp_ctx;
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  c->budget = budget;
+  *out = c;
+  return VP_OK;
+}
+
+vp_status vp_ctx_destroy(vp_ctx* ctx) {
+  if (!ctx) return VP_OK;
+  if (ctx->live_meshes) return fail(VP_EBUSY, "vp_ctx_destroy: %d meshes still alive", ctx->live_meshes);
+  delete ctx;
+  return VP_OK;
+}
+
+vp_status vp_sync(vp_ctx* ctx) {
+  if (!ctx) return fail(VP_EINVAL, "vp_sync: ctx is NULL");
+  VP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  VP_HIP(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+  return VP_OK;
+}
+
+vp_status vp_ref_nodes(int p, double* xy, int* n_p) {
+  if (p < 1 || p > vp::kMaxP) return fail(VP_EINVAL, "vp_ref_nodes: p = %d outside [1, %d]", p, vp::kMaxP);
+  vp::Rule2D r = vp::interp_nodes(p);
+  if (n_p) *n_p = (int)r.x.size();
+  if (xy)
+    for (size_t i = 0; i < r.x.size(); ++i) {
+      xy[2 * i] = r.x[i];
+      xy[2 * i + 1] = r.y[i];
+    }
+  return VP_OK;
+}
+
+vp_status vp_ref_rule(int which, int n, double* x, double* y, double* w, int* count) {
+  if (n < 1 || n > 64) return fail(VP_EINVAL, "vp_ref_rule: n = %d outside [1, 64]", n);
+  std::vector<double> rx, ry, rw;
+  switch (which) {
+    case 0: {
+      vp::Rule1D r = vp::gauss_legendre01(n);
+      rx = r.x;
+      rw = r.w;
+    } break;
+    case 1: {
+      if (n > 16) return fail(VP_EINVAL, "vp_ref_rule: log rule limited to 16 points");
+      vp::Rule1D r = vp::gauss_log01(n);
+      rx = r.x;
+      rw = r.w;
+    } break;
+    case 2: {
+      vp::Rule2D r = vp::collapsed_gauss(n);
+      rx = r.x;
+      ry = r.y;
+      rw = r.w;
+    } break;
+    case 3: {
+      if (n > vp::kMaxP) return fail(VP_EINVAL, "vp_ref_rule: order %d outside [1, %d]", n, vp::kMaxP);
+      vp::radial_rule(n, rx, ry, rw);
+    } break;
+    case 4: {
+      vp::Rule2D r = vp::collapsed_gauss(n);
+      rw.resize(3);
+      vp::edge_weights(r, n, rw.data());
+    } break;
+    default:
+      return fail(VP_EINVAL, "vp_ref_rule: unknown rule %d", which);
+  }
+  if (count) *count = (int)rw.size();
+  for (size_t i = 0; i < rw.size(); ++i) {
+    if (x && i < rx.size()) x[i] = rx[i];
+    if (y && i < ry.size()) y[i] = ry[i];
+    if (w) w[i] = rw[i];
+  }
+  return VP_OK;
+}
+
+vp_status vp_mesh_create(vp_ctx* ctx, int64_t n_vert, const double* vert, int64_t n_tri, const int32_t* tri,
+                         vp_mesh** out) {
+  if (!ctx || !out) return fail(VP_EINVAL, "vp_mesh_create: NULL argument");
+  if (n_vert < 0 || n_tri < 0 || n_tri > 0x7fffffffLL) return fail(VP_EINVAL, "vp_mesh_create: bad sizes");
+  if (n_tri > 0 && (!vert || !tri)) return fail(VP_EINVAL, "vp_mesh_create: NULL arrays");
+  VP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  const size_t bytes = 7 * sizeof(double) * std::max<int64_t>(n_tri, 1);
+  if (ctx->budget && ctx->in_use + bytes > ctx->budget)
+    return fail(VP_ENOMEM, "vp_mesh_create: %zu bytes exceed the HBM budget", bytes);
+  vp_mesh* m = new vp_mesh;
+  m->ctx = ctx;
+  m->n_tri = n_tri;
+  double* base = nullptr;
+  hipError_t e = hipMalloc((void**)&base, bytes);
+  if (e != hipSuccess) {
+    delete m;
+    return hip_fail(e, "vp_mesh_create: hipMalloc");
+  }
+  const size_t T = std::max<int64_t>(n_tri, 1);
+  m->ax = base;
+  m->ay = base + T;
+  m->bx = base + 2 * T;
+  m->by = base + 3 * T;
+  m->cx = base + 4 * T;
+  m->cy = base + 5 * T;
+  m->det = base + 6 * T;
+  m->bytes = bytes;
+  hipStream_t st = ctx->stream;
+  double* d_vert = nullptr;
+  int32_t* d_tri = nullptr;
+  int* d_bad = nullptr;
+  auto cleanup = [&](bool all) {
+    if (d_vert) (void)hipFree(d_vert);
+    if (d_tri) (void)hipFree(d_tri);
+    if (d_bad) (void)hipFree(d_bad);
+    if (all) {
+      (void)hipFree(base);
+      delete m;
+    }
+  };
+  int bad = 0;
+  if ((e = hipMalloc((void**)&d_vert, sizeof(double) * 2 * std::max<int64_t>(n_vert, 1))) != hipSuccess ||
+      (e = hipMalloc((void**)&d_tri, sizeof(int32_t) * 3 * T)) != hipSuccess ||
+      (e = hipMalloc((void**)&d_bad, sizeof(int))) != hipSuccess ||
+      (e = hipMemsetAsync(d_bad, 0, sizeof(int), st)) != hipSuccess ||
+      (n_vert && (e = hipMemcpyAsync(d_vert, vert, sizeof(double) * 2 * n_vert, hipMemcpyHostToDevice, st)) !=
+                     hipSuccess) ||
+      (n_tri && (e = hipMemcpyAsync(d_tri, tri, sizeof(int32_t) * 3 * n_tri, hipMemcpyHostToDevice, st)) !=
+                    hipSuccess) ||
+      (e = vp::launch_mesh_geom(d_vert, n_vert, d_tri, n_tri, m, d_bad, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess) {
+    cleanup(true);
+    return hip_fail(e, "vp_mesh_create");
+  }
+  cleanup(false);
+  if (bad) {
+    (void)hipFree(base);
+    delete m;
+    const char* why = bad == 1 ? "vertex index out of range" : bad == 2 ? "non-finite coordinate"
+                                                                       : "degenerate triangle";
+    return fail(VP_EINVAL, "vp_mesh_create: %s", why);
+  }
+  ctx->in_use += bytes;
+  ctx->live_meshes++;
+  *out = m;
+  return VP_OK;
+}
+
+vp_status vp_mesh_destroy(vp_mesh* m) {
+  if (!m) return VP_OK;
+  if (m->live_plans) return fail(VP_EBUSY, "vp_mesh_destroy: %d plans still use this mesh", m->live_plans);
+  (void)hipSetDevice(m->ctx->device);
+  (void)hipFree(m->ax);
+  m->ctx->in_use -= m->bytes;
+  m->ctx->live_meshes--;
+  delete m;
+  return VP_OK;
+}
+
+vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double eps, int64_t n_tgt,
+                         const double* tgt_xy, const vp_plan_opts* opts, vp_plan** out) {
+  if (!ctx || !mesh || !out) return fail(VP_EINVAL, "vp_plan_create: NULL argument");
+  if (mesh->ctx != ctx) return fail(VP_EINVAL, "vp_plan_create: mesh belongs to another context");
+  if (p < 1 || p > vp::kMaxP) return fail(VP_EINVAL, "vp_plan_create: p = %d outside [1, %d]", p, vp::kMaxP);
+  if (q < 2 || q > vp::kMaxQ) return fail(VP_EINVAL, "vp_plan_create: q = %d outside [2, %d]", q, vp::kMaxQ);
+  if (!(eps > 0.0) || !std::isfinite(eps)) return fail(VP_EINVAL, "vp_plan_create: eps must be > 0");
+  if (n_tgt < 0 || n_tgt > 0x7fffffffLL) return fail(VP_EINVAL, "vp_plan_create: bad n_tgt");
+  if (n_tgt > 0 && !tgt_xy) return fail(VP_EINVAL, "vp_plan_create: tgt_xy is NULL");
+  vp_plan_opts o = opts ? *opts : default_opts();
+  if (!(o.c_n > 0.0) || o.q_near < 2 || o.q_near > vp::kMaxQ || o.n_l < 2 || o.n_l > 64 || !(o.tau >= 0.0) ||
+      o.depth_cap < 1 || o.depth_cap > 60 || o.dyadic_cap < 1 || o.dyadic_cap > 100)
+    return fail(VP_EINVAL, "vp_plan_create: invalid options");
+  VP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t st = ctx->stream;
+
+  vp_plan* pl = new vp_plan;
+  PlanGuard guard{pl};
+  pl->ctx = ctx;
+  pl->mesh = mesh;
+  pl->p = p;
+  pl->q = q;
+  pl->n_p = vp::n_basis(p);
+  pl->n_f = q * q;
+  pl->eps = eps;
+  pl->opts = o;
+  pl->n_tri = mesh->n_tri;
+  pl->n_src = mesh->n_tri * pl->n_f;
+  pl->n_tgt = n_tgt;
+
+  // host reference rules
+  vp::Rule2D far = vp::collapsed_gauss(q);
+  vp::Rule2D nr = vp::collapsed_gauss(o.q_near);
+  vp::Rule1D gl = vp::gauss_legendre01(o.n_l);
+  vp::Rule2D nodes = vp::interp_nodes(p);
+  std::vector<double> rr, ra, rb;
+  vp::radial_rule(p, rr, ra, rb);
+  vp::edge_weights(far, q, pl->far_what);
+  vp::edge_weights(nr, o.q_near, pl->near_what);
+  pl->n_r = (int)rr.size();
+
+  hipError_t e;
+#define UP(dst, vec) \
+  if ((e = upload(pl, &(dst), (vec).data(), (vec).size(), st)) != hipSuccess) return hip_fail(e, "vp_plan_create: upload")
+  UP(pl->far_x, far.x);
+  UP(pl->far_y, far.y);
+  UP(pl->far_w, far.w);
+  UP(pl->near_x, nr.x);
+  UP(pl->near_y, nr.y);
+  UP(pl->near_w, nr.w);
+  UP(pl->gl_s, gl.x);
+  UP(pl->gl_w, gl.w);
+  UP(pl->rad_r, rr);
+  UP(pl->rad_a, ra);
+  UP(pl->rad_b, rb);
+#undef UP
+  const int NP = pl->n_p;
+  if ((e = plan_alloc(pl, (void**)&pl->vinv, sizeof(double) * NP * NP)) != hipSuccess ||
+      (e = plan_alloc(pl, (void**)&pl->efar, sizeof(double) * pl->n_f * NP)) != hipSuccess)
+    return hip_fail(e, "vp_plan_create: hipMalloc");
+  // Vandermonde inverse (device, FP64)
+  {
+    double* scratch = nullptr;
+    const size_t sbytes = sizeof(double) * (2 * NP + 2 * NP * NP) + sizeof(int) * 2;
+    if ((e = hipMalloc((void**)&scratch, sbytes)) != hipSuccess) return hip_fail(e, "vp_plan_create: hipMalloc");
+    std::vector<double> nxy(2 * NP);
+    for (int i = 0; i < NP; ++i) {
+      nxy[i] = nodes.x[i];
+      nxy[NP + i] = nodes.y[i];
+    }
+    int bad = 0;
+    int* d_bad = (int*)(scratch + 2 * NP + 2 * NP * NP);
+    if ((e = hipMemcpyAsync(scratch, nxy.data(), sizeof(double) * 2 * NP, hipMemcpyHostToDevice, st)) !=
+            hipSuccess ||
+        (e = hipMemsetAsync(d_bad, 0, sizeof(int), st)) != hipSuccess ||
+        (e = vp::launch_basis_tables(pl, scratch, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+      (void)hipFree(scratch);
+      return hip_fail(e, "vp_plan_create: basis tables");
+    }
+    (void)hipFree(scratch);
+    if (bad) return fail(VP_EINTERNAL, "vp_plan_create: singular Vandermonde matrix");
+  }
+  // sources and targets
+  if ((e = plan_alloc(pl, (void**)&pl->xs, sizeof(double) * pl->n_src)) != hipSuccess ||
+      (e = plan_alloc(pl, (void**)&pl->ys, sizeof(double) * pl->n_src)) != hipSuccess ||
+      (e = plan_alloc(pl, (void**)&pl->xt, sizeof(double) * n_tgt)) != hipSuccess ||
+      (e = plan_alloc(pl, (void**)&pl->yt, sizeof(double) * n_tgt)) != hipSuccess)
+    return hip_fail(e, "vp_plan_create: hipMalloc");
+  if ((e = vp::launch_sources(pl, st)) != hipSuccess) return hip_fail(e, "vp_plan_create: sources");
+  {
+    double* d_xy = nullptr;
+    int* d_bad = nullptr;
+    int bad = 0;
+    if ((e = hipMalloc((void**)&d_xy, sizeof(double) * 2 * std::max<int64_t>(n_tgt, 1))) != hipSuccess)
+      return hip_fail(e, "vp_plan_create: hipMalloc");
+    if ((e = hipMalloc((void**)&d_bad, sizeof(int))) != hipSuccess) {
+      (void)hipFree(d_xy);
+      return hip_fail(e, "vp_plan_create: hipMalloc");
+    }
+    if ((e = hipMemsetAsync(d_bad, 0, sizeof(int), st)) != hipSuccess ||
+        (n_tgt && (e = hipMemcpyAsync(d_xy, tgt_xy, sizeof(double) * 2 * n_tgt, hipMemcpyHostToDevice, st)) !=
+                      hipSuccess) ||
+        (e = vp::launch_split_xy(d_xy, n_tgt, pl->xt, pl->yt, d_bad, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+      (void)hipFree(d_xy);
+      (void)hipFree(d_bad);
+      return hip_fail(e, "vp_plan_create: targets");
+    }
+    (void)hipFree(d_xy);
+    (void)hipFree(d_bad);
+    if (bad) return fail(VP_EINVAL, "vp_plan_create: non-finite target coordinate");
+  }
+  // near-field pair list
+  hipEvent_t ev0, ev1, ev2;
+  VP_HIP(hipEventCreate(&ev0), "hipEventCreate");
+  VP_HIP(hipEventCreate(&ev1), "hipEventCreate");
+  VP_HIP(hipEventCreate(&ev2), "hipEventCreate");
+  struct EvGuard {
+    hipEvent_t a, b, c;
+    ~EvGuard() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      (void)hipEventDestroy(c);
+    }
+  } evg{ev0, ev1, ev2};
+  VP_HIP(hipEventRecord(ev0, st), "hipEventRecord");
+  {
+    std::string err;
+    e = vp::build_pairs(pl, st, err);
+    if (e != hipSuccess) {
+      if (!err.empty()) return fail(VP_ENOMEM, "vp_plan_create: %s", err.c_str());
+      return hip_fail(e, "vp_plan_create: near-field list");
+    }
+  }
+  VP_HIP(hipEventRecord(ev1, st), "hipEventRecord");
+  // correction rows
+  if ((e = plan_alloc(pl, (void**)&pl->rows, sizeof(double) * pl->n_pairs * NP)) != hipSuccess)
+    return hip_fail(e, "vp_plan_create: rows");
+  {
+    int* d_flag = nullptr;
+    int64_t* d_stats = nullptr;
+    if ((e = hipMalloc((void**)&d_flag, sizeof(int))) != hipSuccess) return hip_fail(e, "vp_plan_create: hipMalloc");
+    if ((e = hipMalloc((void**)&d_stats, sizeof(int64_t) * 3)) != hipSuccess) {
+      (void)hipFree(d_flag);
+      return hip_fail(e, "vp_plan_create: hipMalloc");
+    }
+    int flag = 0;
+    if ((e = hipMemsetAsync(d_flag, 0, sizeof(int), st)) != hipSuccess ||
+        (e = hipMemsetAsync(d_stats, 0, sizeof(int64_t) * 3, st)) != hipSuccess ||
+        (e = vp::launch_rows(pl, d_flag, d_stats, st)) != hipSuccess ||
+        (e = hipEventRecord(ev2, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(&flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(pl->stats, d_stats, sizeof(int64_t) * 3, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+      (void)hipFree(d_flag);
+      (void)hipFree(d_stats);
+      return hip_fail(e, "vp_plan_create: correction rows");
+    }
+    (void)hipFree(d_flag);
+    (void)hipFree(d_stats);
+    if (flag) return fail(VP_EINTERNAL, "vp_plan_create: near subdivision exceeded its per-level capacity");
+  }
+  float ms1 = 0.f, ms2 = 0.f;
+  (void)hipEventElapsedTime(&ms1, ev0, ev1);
+  (void)hipEventElapsedTime(&ms2, ev1, ev2);
+  pl->ms_classify = ms1;
+  pl->ms_rows = ms2;
+  if (ctx->budget && ctx->in_use + pl->bytes > ctx->budget)
+    return fail(VP_ENOMEM, "vp_plan_create: %zu bytes exceed the HBM budget", pl->bytes);
+  ctx->in_use += pl->bytes;
+  const_cast<vp_mesh*>(mesh)->live_plans++;
+  guard.keep = true;
+  *out = pl;
+  return VP_OK;
+}
+
+vp_status vp_plan_info(const vp_plan* pl, vp_plan_stats* out) {
+  if (!pl || !out) return fail(VP_EINVAL, "vp_plan_info: NULL argument");
+  out->n_tri = pl->n_tri;
+  out->n_src = pl->n_src;
+  out->n_tgt = pl->n_tgt;
+  out->n_pairs = pl->n_pairs;
+  out->n_self = pl->n_self;
+  out->near_subtri = pl->stats[0];
+  out->self_panels = pl->stats[1];
+  out->capped_leaves = pl->stats[2];
+  out->bytes_resident = (int64_t)(pl->bytes + pl->ws_bytes);
+  out->p = pl->p;
+  out->q = pl->q;
+  out->n_p = pl->n_p;
+  out->n_f = pl->n_f;
+  out->eps = pl->eps;
+  out->ms_classify = pl->ms_classify;
+  out->ms_rows = pl->ms_rows;
+  return VP_OK;
+}
+
+vp_status vp_plan_pairs(const vp_plan* pl, int64_t* row_ptr, int32_t* tri, uint8_t* kind) {
+  if (!pl) return fail(VP_EINVAL, "vp_plan_pairs: plan is NULL");
+  VP_HIP(hipSetDevice(pl->ctx->device), "hipSetDevice");
+  hipStream_t st = pl->ctx->stream;
+  if (row_ptr)
+    VP_HIP(hipMemcpyAsync(row_ptr, pl->row_ptr, sizeof(int64_t) * (pl->n_tgt + 1), hipMemcpyDeviceToHost, st),
+           "hipMemcpy");
+  if (tri && pl->n_pairs)
+    VP_HIP(hipMemcpyAsync(tri, pl->pair_tri, sizeof(int32_t) * pl->n_pairs, hipMemcpyDeviceToHost, st), "hipMemcpy");
+  if (kind && pl->n_pairs)
+    VP_HIP(hipMemcpyAsync(kind, pl->pair_kind, pl->n_pairs, hipMemcpyDeviceToHost, st), "hipMemcpy");
+  VP_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+  return VP_OK;
+}
+
+vp_status vp_plan_rows(const vp_plan* pl, double* rows) {
+  if (!pl || !rows) return fail(VP_EINVAL, "vp_plan_rows: NULL argument");
+  VP_HIP(hipSetDevice(pl->ctx->device), "hipSetDevice");
+  if (pl->n_pairs)
+    VP_HIP(hipMemcpyAsync(rows, pl->rows, sizeof(double) * pl->n_pairs * pl->n_p, hipMemcpyDeviceToHost,
+                          pl->ctx->stream),
+           "hipMemcpy");
+  VP_HIP(hipStreamSynchronize(pl->ctx->stream), "hipStreamSynchronize");
+  return VP_OK;
+}
+
+vp_status vp_plan_sources(const vp_plan* pl, double* xy) {
+  if (!pl || !xy) return fail(VP_EINVAL, "vp_plan_sources: NULL argument");
+  VP_HIP(hipSetDevice(pl->ctx->device), "hipSetDevice");
+  std::vector<double> x(pl->n_src), y(pl->n_src);
+  if (pl->n_src) {
+    VP_HIP(hipMemcpy(x.data(), pl->xs, sizeof(double) * pl->n_src, hipMemcpyDeviceToHost), "hipMemcpy");
+    VP_HIP(hipMemcpy(y.data(), pl->ys, sizeof(double) * pl->n_src, hipMemcpyDeviceToHost), "hipMemcpy");
+  }
+  for (int64_t i = 0; i < pl->n_src; ++i) {
+    xy[2 * i] = x[i];
+    xy[2 * i + 1] = y[i];
+  }
+  return VP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int64_t choose_split(const vp_plan* pl) {
+  const int64_t bx = (pl->n_tgt + 255) / 256;
+  const int64_t want = (2048 + bx - 1) / std::max<int64_t>(bx, 1);
+  const int64_t most = std::max<int64_t>(1, (pl->n_src + 255) / 256);
+  return std::max<int64_t>(1, std::min(want, most));
+}
+
+// grow the execute workspace to n_rhs right-hand sides
+vp_status ensure_workspace(vp_plan* pl, int64_t R) {
+  const int64_t split = choose_split(pl);
+  if (pl->ws_rhs >= R && pl->ws_split == split && pl->ws_c) return VP_OK;
+  double* ws[] = {pl->ws_f, pl->ws_c, pl->ws_q, pl->ws_part, pl->ws_u};
+  for (double* p : ws)
+    if (p) (void)hipFree(p);
+  pl->ws_f = pl->ws_c = pl->ws_q = pl->ws_part = pl->ws_u = nullptr;
+  pl->ctx->in_use -= pl->ws_bytes;
+  pl->ws_bytes = 0;
+  pl->ws_rhs = 0;
+  const size_t nF = (size_t)pl->n_tri * pl->n_p * R;
+  const size_t nQ = (size_t)pl->n_src * R;
+  const size_t nP = (size_t)split * pl->n_tgt * R;
+  const size_t nU = (size_t)pl->n_tgt * R;
+  const size_t bytes = 8 * (2 * nF + nQ + nP + nU) + 5 * 8;
+  if (pl->ctx->budget && pl->ctx->in_use + bytes > pl->ctx->budget)
+    return fail(VP_ENOMEM, "vp_execute: workspace of %zu bytes exceeds the HBM budget", bytes);
+  hipError_t e;
+  if ((e = hipMalloc((void**)&pl->ws_f, 8 * std::max<size_t>(nF, 1))) != hipSuccess ||
+      (e = hipMalloc((void**)&pl->ws_c, 8 * std::max<size_t>(nF, 1))) != hipSuccess ||
+      (e = hipMalloc((void**)&pl->ws_q, 8 * std::max<size_t>(nQ, 1))) != hipSuccess ||
+      (e = hipMalloc((void**)&pl->ws_part, 8 * std::max<size_t>(nP, 1))) != hipSuccess ||
+      (e = hipMalloc((void**)&pl->ws_u, 8 * std::max<size_t>(nU, 1))) != hipSuccess) {
+    return hip_fail(e, "vp_execute: workspace");
+  }
+  pl->ws_rhs = R;
+  pl->ws_split = split;
+  pl->ws_bytes = bytes;
+  pl->ctx->in_use += bytes;
+  return VP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vp_status vp_execute(vp_plan* pl, int64_t R, const double* density, double* u_out, vp_precision prec,
+                     uint32_t flags) {
+  if (!pl) return fail(VP_EINVAL, "vp_execute: plan is NULL");
+  if (R < 1) return fail(VP_EINVAL, "vp_execute: n_rhs must be >= 1");
+  if (prec != VP_FP64) return fail(VP_ENOTSUP, "vp_execute: only VP_FP64 is available");
+  if ((!density && pl->n_tri) || (!u_out && pl->n_tgt)) return fail(VP_EINVAL, "vp_execute: NULL array");
+  const bool dev = flags & VP_DEVICE_PTRS;
+  if ((flags & VP_ASYNC) && !dev) return fail(VP_EINVAL, "vp_execute: VP_ASYNC needs VP_DEVICE_PTRS");
+  VP_HIP(hipSetDevice(pl->ctx->device), "hipSetDevice");
+  vp_status s = ensure_workspace(pl, R);
+  if (s != VP_OK) return s;
+  hipStream_t st = pl->ctx->stream;
+  const size_t nF = (size_t)pl->n_tri * pl->n_p * R;
+  const double* F = density;
+  if (!dev && nF) {
+    VP_HIP(hipMemcpyAsync(pl->ws_f, density, 8 * nF, hipMemcpyHostToDevice, st), "vp_execute: upload");
+    F = pl->ws_f;
+  }
+  double* U = dev ? u_out : pl->ws_u;
+  VP_HIP(vp::launch_coefficients(pl, F, R, pl->ws_c, pl->ws_q, st), "vp_execute: coefficients");
+  VP_HIP(vp::launch_far(pl, pl->ws_q, R, pl->ws_split, pl->ws_part, st), "vp_execute: far field");
+  VP_HIP(vp::launch_finish(pl, pl->ws_part, pl->ws_split, pl->ws_c, R, (flags & VP_FAR_ONLY) != 0, U, st),
+         "vp_execute: corrections");
+  if (!dev && pl->n_tgt)
+    VP_HIP(hipMemcpyAsync(u_out, U, 8 * (size_t)pl->n_tgt * R, hipMemcpyDeviceToHost, st), "vp_execute: download");
+  if (!(flags & VP_ASYNC)) VP_HIP(hipStreamSynchronize(st), "vp_execute: synchronize");
+  return VP_OK;
+}
+
+vp_status vp_coefficients(vp_plan* pl, int64_t R, const double* density, double* coef_out, double* charge_out,
+                          uint32_t flags) {
+  if (!pl) return fail(VP_EINVAL, "vp_coefficients: plan is NULL");
+  if (R < 1) return fail(VP_EINVAL, "vp_coefficients: n_rhs must be >= 1");
+  if (!density && pl->n_tri) return fail(VP_EINVAL, "vp_coefficients: NULL density");
+  const bool dev = flags & VP_DEVICE_PTRS;
+  VP_HIP(hipSetDevice(pl->ctx->device), "hipSetDevice");
+  vp_status s = ensure_workspace(pl, R);
+  if (s != VP_OK) return s;
+  hipStream_t st = pl->ctx->stream;
+  const size_t nF = (size_t)pl->n_tri * pl->n_p * R;
+  const double* F = density;
+  if (!dev && nF) {
+    VP_HIP(hipMemcpyAsync(pl->ws_f, density, 8 * nF, hipMemcpyHostToDevice, st), "vp_coefficients: upload");
+    F = pl->ws_f;
+  }
+  VP_HIP(vp::launch_coefficients(pl, F, R, pl->ws_c, pl->ws_q, st), "vp_coefficients");
+  const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (coef_out && nF) VP_HIP(hipMemcpyAsync(coef_out, pl->ws_c, 8 * nF, kind, st), "vp_coefficients: copy");
+  if (charge_out && pl->n_src)
+    VP_HIP(hipMemcpyAsync(charge_out, pl->ws_q, 8 * (size_t)pl->n_src * R, kind, st), "vp_coefficients: copy");
+  if (!(flags & VP_ASYNC)) VP_HIP(hipStreamSynchronize(st), "vp_coefficients: synchronize");
+  return VP_OK;
+}
+
+vp_status vp_plan_destroy(vp_plan* pl) {
+  if (!pl) return VP_OK;
+  (void)hipSetDevice(pl->ctx->device);
+  (void)hipStreamSynchronize(pl->ctx->stream);
+  pl->ctx->in_use -= pl->bytes + pl->ws_bytes;
+  const_cast<vp_mesh*>(pl->mesh)->live_plans--;
+  free_plan_memory(pl);
+  delete pl;
+  return VP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+// Internal declarations of libvp: host-side rule construction, device data
+// of meshes and plans, kernel launchers, and the device Koornwinder basis.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/vp.h"
+
+namespace vp {
+
+constexpr int kMaxP = 10;
+constexpr int kMaxQ = 32;
+constexpr int kWave = 64;
+
+inline int n_basis(int p) { return (p + 1) * (p + 2) / 2; }
+
+// ---------------------------------------------------------------------------
+// Host-side reference rules (vp_rules.cpp).  All built in long double from
+// three-term recurrences: nodes by Sturm-sequence bisection on the Jacobi
+// matrix, weights as Christoffel numbers.
+// ---------------------------------------------------------------------------
+struct Rule1D {
+  std::vector<double> x, w;
+};
+struct Rule2D {
+  std::vector<double> x, y, w;  // reference-simplex nodes and weights
+};
+Rule1D gauss_legendre01(int n);
+Rule1D gauss_log01(int n);                  // weight -log(r) on [0,1]
+Rule2D collapsed_gauss(int q);              // q x q, node index a*q + b
+void edge_weights(const Rule2D& r, int q, double out[3]);
+Rule2D interp_nodes(int p);                 // interior Blyth-Pozrikidis nodes
+int radial_half(int p);
+// radial rule: r, alpha (multiplies log r0), beta (constant)
+void radial_rule(int p, std::vector<double>& r, std::vector<double>& alpha, std::vector<double>& beta);
+
+// ---------------------------------------------------------------------------
+// Device Koornwinder basis (Sec. 2.1), division-free in the collapsed
+// coordinate:  K_mn(x,y) = c_mn P^{(2m+1,0)}_{n-m}(2x-1) Q_m(x,y) with
+// Q_m = (1-x)^m P_m(2y/(1-x) - 1) from the scaled Legendre recurrence
+//   (m+1) Q_{m+1} = (2m+1)(2y-1+x) Q_m - m (1-x)^2 Q_{m-1}.
+// `emit(k, value)` is called once per basis function, k = n(n+1)/2 + m.
+// ---------------------------------------------------------------------------
+template <int P, class Emit>
+__device__ __forceinline__ void koornwinder_emit(double x, double y, Emit&& emit) {
+  const double t = 1.0 - x;
+  const double s = 2.0 * y - t;
+  const double tt = t * t;
+  const double z = 2.0 * x - 1.0;
+  double Q[P + 1];
+  Q[0] = 1.0;
+  if (P >= 1) Q[1] = s;
+#pragma unroll
+  for (int m = 1; m < P; ++m) {
+    Q[m + 1] = ((2.0 * m + 1.0) * s * Q[m] - (double)m * tt * Q[m - 1]) * (1.0 / (m + 1.0));
+  }
+#pragma unroll
+  for (int m = 0; m <= P; ++m) {
+    const double a = 2.0 * m + 1.0;
+    double jm2 = 0.0, jm1 = 1.0;
+#pragma unroll
+    for (int k = 0; k + m <= P; ++k) {
+      double jk;
+      if (k == 0) {
+        jk = 1.0;
+      } else if (k == 1) {
+        jk = 0.5 * ((a + 2.0) * z + a);
+      } else {
+        const double kk = (double)k;
+        const double c1 = (2.0 * kk + a - 1.0);
+        const double c2 = (2.0 * kk + a) * (2.0 * kk + a - 2.0);
+        const double c3 = 2.0 * (kk + a - 1.0) * (kk - 1.0) * (2.0 * kk + a);
+        const double inv = 1.0 / (2.0 * kk * (kk + a) * (2.0 * kk + a - 2.0));
+        jk = (c1 * (c2 * z + a * a) * jm1 - c3 * jm2) * inv;
+      }
+      if (k >= 1) {
+        jm2 = jm1;
+      }
+      jm1 = jk;
+      const int n = m + k;
+      const double cmn = __builtin_sqrt(2.0 * (2.0 * m + 1.0) * (n + 1.0));
+      emit(n * (n + 1) / 2 + m, cmn * jk * Q[m]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Device-side objects
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace vp
+
+struct vp_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint64_t budget = 0;
+  uint64_t in_use = 0;
+  int live_meshes = 0;
+};
+
+struct vp_mesh {
+  vp_ctx* ctx = nullptr;
+  int64_t n_tri = 0;
+  // oriented geometry, SoA [n_tri] each: A, B, C, D = det[B-A, C-A] > 0
+  double *ax = nullptr, *ay = nullptr, *bx = nullptr, *by = nullptr, *cx = nullptr, *cy = nullptr,
+         *det = nullptr;
+  size_t bytes = 0;
+  int live_plans = 0;
+};
+
+struct vp_plan {
+  vp_ctx* ctx = nullptr;
+  const vp_mesh* mesh = nullptr;
+  int p = 0, q = 0, n_p = 0, n_f = 0;
+  double eps = 0.0;
+  vp_plan_opts opts{};
+  int64_t n_tri = 0, n_src = 0, n_tgt = 0, n_pairs = 0, n_self = 0;
+  int64_t stats[3] = {0, 0, 0};  // near leaves, self panels, capped leaves
+  double ms_classify = 0.0, ms_rows = 0.0;
+  // rule tables (device)
+  double* vinv = nullptr;   // [n_p][n_p]
+  double* efar = nullptr;   // [n_f][n_p] Koornwinder values at far nodes
+  double* far_x = nullptr;  // [n_f]
+  double* far_y = nullptr;
+  double* far_w = nullptr;
+  double* near_x = nullptr;  // [q_near^2]
+  double* near_y = nullptr;
+  double* near_w = nullptr;
+  double* gl_s = nullptr;  // [n_l]
+  double* gl_w = nullptr;
+  double* rad_r = nullptr;  // [n_r]
+  double* rad_a = nullptr;
+  double* rad_b = nullptr;
+  int n_r = 0;
+  double far_what[3] = {0, 0, 0}, near_what[3] = {0, 0, 0};
+  // sources and targets (device)
+  double *xs = nullptr, *ys = nullptr;  // [n_src]
+  double *xt = nullptr, *yt = nullptr;  // [n_tgt]
+  // pair list (device)
+  int64_t* row_ptr = nullptr;  // [n_tgt+1]
+  int32_t* pair_tri = nullptr;  // [n_pairs]
+  int32_t* pair_tgt = nullptr;  // [n_pairs]
+  uint8_t* pair_kind = nullptr;  // [n_pairs]
+  double* rows = nullptr;  // [n_pairs][n_p]
+  // execute workspace
+  int64_t ws_rhs = 0;
+  int64_t ws_split = 0;
+  double *ws_f = nullptr, *ws_c = nullptr, *ws_q = nullptr, *ws_part = nullptr, *ws_u = nullptr;
+  size_t ws_bytes = 0;
+  std::vector<void*> allocs;  // everything above except the workspace
+  size_t bytes = 0;
+};
+
+namespace vp {
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (vp_*.hip).  All enqueue on `st` and return the launch
+// status.
+// ---------------------------------------------------------------------------
+hipError_t launch_mesh_geom(const double* vert, int64_t n_vert, const int32_t* tri, int64_t n_tri,
+                            vp_mesh* m, int* d_bad, hipStream_t st);
+hipError_t launch_split_xy(const double* xy, int64_t n, double* x, double* y, int* d_bad, hipStream_t st);
+hipError_t launch_basis_tables(vp_plan* pl, double* scratch, hipStream_t st);
+hipError_t launch_sources(vp_plan* pl, hipStream_t st);
+hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err);  // near-list construction
+hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t st);
+hipError_t launch_coefficients(const vp_plan* pl, const double* F, int64_t R, double* C, double* Q,
+                               hipStream_t st);
+hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, int64_t n_split, double* partial,
+                      hipStream_t st);
+hipError_t launch_finish(const vp_plan* pl, const double* partial, int64_t n_split, const double* C,
+                         int64_t R, bool far_only, double* U, hipStream_t st);
+hipError_t exclusive_scan_i32(const int32_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t st);
+size_t exclusive_scan_tmp_bytes(int64_t n);
+
+}  // namespace vp

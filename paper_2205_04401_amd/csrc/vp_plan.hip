@@ -1,0 +1,663 @@
+// Plan-time kernels: mesh geometry, basis tables, far sources and the
+// near-field pair list (Def. of far/near field, Sec. 3.2; Bernstein-ellipse
+// union, Sec. 4.1, eqs. rho0 and threeE; nearby-element query, App. A.5,
+// replaced by a uniform grid of cells over the targets).
+#include <algorithm>
+#include <cmath>
+
+#include "vp_internal.h"
+
+namespace vp {
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned blocks_for(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// mesh geometry: orientation (swap local vertices 1 and 2 if clockwise),
+// det = |J| = 2 area, rejection of bad input
+// ---------------------------------------------------------------------------
+__global__ void k_mesh_geom(const double* __restrict__ vert, int64_t n_vert, const int32_t* __restrict__ tri,
+                            int64_t n_tri, double* ax, double* ay, double* bx, double* by, double* cx,
+                            double* cy, double* det, int* bad) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tri) return;
+  int32_t i0 = tri[3 * t], i1 = tri[3 * t + 1], i2 = tri[3 * t + 2];
+  if (i0 < 0 || i1 < 0 || i2 < 0 || i0 >= n_vert || i1 >= n_vert || i2 >= n_vert) {
+    atomicMax(bad, 1);
+    return;
+  }
+  double x0 = vert[2 * i0], y0 = vert[2 * i0 + 1];
+  double x1 = vert[2 * i1], y1 = vert[2 * i1 + 1];
+  double x2 = vert[2 * i2], y2 = vert[2 * i2 + 1];
+  if (!isfinite(x0) || !isfinite(y0) || !isfinite(x1) || !isfinite(y1) || !isfinite(x2) || !isfinite(y2)) {
+    atomicMax(bad, 2);
+    return;
+  }
+  double d = (x1 - x0) * (y2 - y0) - (y1 - y0) * (x2 - x0);
+  if (d < 0.0) {
+    double tx = x1, ty = y1;
+    x1 = x2;
+    y1 = y2;
+    x2 = tx;
+    y2 = ty;
+    d = -d;
+  }
+  double w = fmax(fmax(x0, x1), x2) - fmin(fmin(x0, x1), x2);
+  double h = fmax(fmax(y0, y1), y2) - fmin(fmin(y0, y1), y2);
+  double ext = fmax(w, h);
+  if (!(d > 1e-14 * ext * ext)) {
+    atomicMax(bad, 3);
+  }
+  ax[t] = x0;
+  ay[t] = y0;
+  bx[t] = x1;
+  by[t] = y1;
+  cx[t] = x2;
+  cy[t] = y2;
+  det[t] = d;
+}
+
+__global__ void k_split_xy(const double* __restrict__ xy, int64_t n, double* x, double* y, int* bad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = xy[2 * i], b = xy[2 * i + 1];
+  if (!isfinite(a) || !isfinite(b)) atomicMax(bad, 2);
+  x[i] = a;
+  y[i] = b;
+}
+
+// ---------------------------------------------------------------------------
+// basis tables: V (Koornwinder at the interpolation nodes) inverted by
+// Gauss-Jordan with partial pivoting (one workgroup), and E = Koornwinder at
+// the far nodes.  Sec. 2.2: V^{-1} maps node values to coefficients.
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ void k_vandermonde_inverse(const double* __restrict__ nx, const double* __restrict__ ny,
+                                      double* aug /* [NP][2 NP] */, double* vinv, int* bad) {
+  constexpr int NP = (P + 1) * (P + 2) / 2;
+  constexpr int W2 = 2 * NP;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < NP; i += blockDim.x) {
+    double* row = aug + (size_t)i * W2;
+    koornwinder_emit<P>(nx[i], ny[i], [&](int k, double v) { row[k] = v; });
+    for (int j = 0; j < NP; ++j) row[NP + j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  __shared__ int piv;
+  for (int c = 0; c < NP; ++c) {
+    if (tid == 0) {
+      int best = c;
+      double bv = fabs(aug[(size_t)c * W2 + c]);
+      for (int r = c + 1; r < NP; ++r) {
+        double v = fabs(aug[(size_t)r * W2 + c]);
+        if (v > bv) {
+          bv = v;
+          best = r;
+        }
+      }
+      piv = best;
+      if (!(bv > 0.0)) atomicMax(bad, 4);
+    }
+    __syncthreads();
+    const int pr = piv;
+    if (pr != c) {
+      for (int j = tid; j < W2; j += blockDim.x) {
+        double a = aug[(size_t)c * W2 + j];
+        aug[(size_t)c * W2 + j] = aug[(size_t)pr * W2 + j];
+        aug[(size_t)pr * W2 + j] = a;
+      }
+    }
+    __syncthreads();
+    const double inv = 1.0 / aug[(size_t)c * W2 + c];
+    __syncthreads();
+    for (int j = tid; j < W2; j += blockDim.x) aug[(size_t)c * W2 + j] *= inv;
+    __syncthreads();
+    for (int idx = tid; idx < NP * W2; idx += blockDim.x) {
+      int r = idx / W2, j = idx % W2;
+      if (r == c || j == c) continue;
+      aug[idx] -= aug[(size_t)r * W2 + c] * aug[(size_t)c * W2 + j];
+    }
+    __syncthreads();
+    for (int r = tid; r < NP; r += blockDim.x)
+      if (r != c) aug[(size_t)r * W2 + c] = 0.0;
+    __syncthreads();
+  }
+  // aug = [I | V^{-1}]; V^{-1}[k][i] maps value i to coefficient k
+  for (int idx = tid; idx < NP * NP; idx += blockDim.x) {
+    int k = idx / NP, i = idx % NP;
+    vinv[idx] = aug[(size_t)k * W2 + NP + i];
+  }
+}
+
+template <int P>
+__global__ void k_basis_at(const double* __restrict__ x, const double* __restrict__ y, int n, double* out) {
+  constexpr int NP = (P + 1) * (P + 2) / 2;
+  int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double* row = out + (size_t)j * NP;
+  koornwinder_emit<P>(x[j], y[j], [&](int k, double v) { row[k] = v; });
+}
+
+// far sources: node j of triangle t at A + xi_1 (B-A) + xi_2 (C-A)
+__global__ void k_sources(const double* __restrict__ ax, const double* __restrict__ ay,
+                          const double* __restrict__ bx, const double* __restrict__ by,
+                          const double* __restrict__ cx, const double* __restrict__ cy,
+                          const double* __restrict__ fx, const double* __restrict__ fy, int nf, int64_t n_tri,
+                          double* xs, double* ys) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_tri * nf) return;
+  int64_t t = i / nf;
+  int j = (int)(i - t * nf);
+  double a0 = ax[t], a1 = ay[t];
+  xs[i] = a0 + fx[j] * (bx[t] - a0) + fy[j] * (cx[t] - a0);
+  ys[i] = a1 + fx[j] * (by[t] - a1) + fy[j] * (cy[t] - a1);
+}
+
+// ---------------------------------------------------------------------------
+// near-field geometry per triangle: focal-sum thresholds of the three edge
+// ellipses (negative when rho <= 1, i.e. empty) and an axis-aligned box that
+// contains the triangle (with the self-test tolerance) and its ellipses.
+// ---------------------------------------------------------------------------
+__global__ void k_tri_ellipses(const double* __restrict__ ax, const double* __restrict__ ay,
+                               const double* __restrict__ bx, const double* __restrict__ by,
+                               const double* __restrict__ cx, const double* __restrict__ cy,
+                               const double* __restrict__ det, int64_t n_tri, double w0, double w1, double w2,
+                               double eps_cn, double inv_order, double* thr /* [3][n_tri] */,
+                               double* box /* [4][n_tri] */) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tri) return;
+  const double px[3] = {ax[t], bx[t], cx[t]};
+  const double py[3] = {ay[t], by[t], cy[t]};
+  const double wh[3] = {w0, w1, w2};
+  const double D = det[t];
+  double x0 = fmin(fmin(px[0], px[1]), px[2]), x1 = fmax(fmax(px[0], px[1]), px[2]);
+  double y0 = fmin(fmin(py[0], py[1]), py[2]), y1 = fmax(fmax(py[0], py[1]), py[2]);
+  const double ext = fmax(x1 - x0, y1 - y0);
+  // the self test accepts barycentric coordinates down to -tau: pad the box
+  const double pad = 1e-9 * ext;
+  x0 -= pad;
+  x1 += pad;
+  y0 -= pad;
+  y1 += pad;
+  for (int e = 0; e < 3; ++e) {
+    const double Px = px[e], Py = py[e], Qx = px[(e + 1) % 3], Qy = py[(e + 1) % 3];
+    const double rho = pow(wh[e] * D / eps_cn, inv_order);
+    const double ell = sqrt((Qx - Px) * (Qx - Px) + (Qy - Py) * (Qy - Py));
+    double s = -1.0;
+    if (rho > 1.0) {
+      s = 0.5 * ell * (rho + 1.0 / rho);
+      const double a = 0.5 * s, c = 0.5 * ell;
+      const double b = sqrt(fmax(a * a - c * c, 0.0));
+      const double ux = (Qx - Px) / ell, uy = (Qy - Py) / ell;
+      const double hx = sqrt(a * a * ux * ux + b * b * uy * uy) * (1.0 + 1e-9) + pad;
+      const double hy = sqrt(a * a * uy * uy + b * b * ux * ux) * (1.0 + 1e-9) + pad;
+      const double mx = 0.5 * (Px + Qx), my = 0.5 * (Py + Qy);
+      x0 = fmin(x0, mx - hx);
+      x1 = fmax(x1, mx + hx);
+      y0 = fmin(y0, my - hy);
+      y1 = fmax(y1, my + hy);
+    }
+    thr[e * n_tri + t] = s;
+  }
+  box[t] = x0;
+  box[n_tri + t] = y0;
+  box[2 * n_tri + t] = x1;
+  box[3 * n_tri + t] = y1;
+}
+
+// bounding box of the targets and mean box extent: partial reductions
+__global__ void k_extent_partial(const double* __restrict__ xt, const double* __restrict__ yt, int64_t n_tgt,
+                                 const double* __restrict__ box, int64_t n_tri, double* part /* [grid][5] */) {
+  __shared__ double s[5][kBlock];
+  double mnx = 1e300, mny = 1e300, mxx = -1e300, mxy = -1e300, sum = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_tgt; i += stride) {
+    mnx = fmin(mnx, xt[i]);
+    mxx = fmax(mxx, xt[i]);
+    mny = fmin(mny, yt[i]);
+    mxy = fmax(mxy, yt[i]);
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_tri; i += stride) {
+    sum += fmax(box[2 * n_tri + i] - box[i], box[3 * n_tri + i] - box[n_tri + i]);
+  }
+  const int tid = threadIdx.x;
+  s[0][tid] = mnx;
+  s[1][tid] = mny;
+  s[2][tid] = mxx;
+  s[3][tid] = mxy;
+  s[4][tid] = sum;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if (tid < o) {
+      s[0][tid] = fmin(s[0][tid], s[0][tid + o]);
+      s[1][tid] = fmin(s[1][tid], s[1][tid + o]);
+      s[2][tid] = fmax(s[2][tid], s[2][tid + o]);
+      s[3][tid] = fmax(s[3][tid], s[3][tid + o]);
+      s[4][tid] = s[4][tid] + s[4][tid + o];
+    }
+    __syncthreads();
+  }
+  if (tid < 5) part[blockIdx.x * 5 + tid] = s[tid][0];
+}
+
+struct Grid {
+  double x0, y0, inv_h;
+  int nx, ny;
+};
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__device__ __forceinline__ bool box_cells(const Grid g, double bx0, double by0, double bx1, double by1, int& i0,
+                                          int& i1, int& j0, int& j1) {
+  double fx0 = (bx0 - g.x0) * g.inv_h, fx1 = (bx1 - g.x0) * g.inv_h;
+  double fy0 = (by0 - g.y0) * g.inv_h, fy1 = (by1 - g.y0) * g.inv_h;
+  if (fx1 < 0.0 || fy1 < 0.0 || fx0 >= (double)g.nx || fy0 >= (double)g.ny) return false;
+  i0 = clampi((int)floor(fx0), 0, g.nx - 1);
+  i1 = clampi((int)floor(fx1), 0, g.nx - 1);
+  j0 = clampi((int)floor(fy0), 0, g.ny - 1);
+  j1 = clampi((int)floor(fy1), 0, g.ny - 1);
+  return true;
+}
+
+__global__ void k_cell_count(const double* __restrict__ box, int64_t n_tri, Grid g, int32_t* cnt) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tri) return;
+  int i0, i1, j0, j1;
+  if (!box_cells(g, box[t], box[n_tri + t], box[2 * n_tri + t], box[3 * n_tri + t], i0, i1, j0, j1)) return;
+  for (int j = j0; j <= j1; ++j)
+    for (int i = i0; i <= i1; ++i) atomicAdd(&cnt[(int64_t)j * g.nx + i], 1);
+}
+
+__global__ void k_cell_fill(const double* __restrict__ box, int64_t n_tri, Grid g, const int64_t* __restrict__ ptr,
+                            int32_t* fill, int32_t* cell_tri) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tri) return;
+  int i0, i1, j0, j1;
+  if (!box_cells(g, box[t], box[n_tri + t], box[2 * n_tri + t], box[3 * n_tri + t], i0, i1, j0, j1)) return;
+  for (int j = j0; j <= j1; ++j)
+    for (int i = i0; i <= i1; ++i) {
+      int64_t c = (int64_t)j * g.nx + i;
+      int slot = atomicAdd(&fill[c], 1);
+      cell_tri[ptr[c] + slot] = (int32_t)t;
+    }
+}
+
+// deterministic order inside each cell (ascending triangle index)
+__global__ void k_cell_sort(const int64_t* __restrict__ ptr, int64_t n_cells, int32_t* cell_tri) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  int64_t b = ptr[c], e = ptr[c + 1];
+  for (int64_t i = b + 1; i < e; ++i) {
+    int32_t v = cell_tri[i];
+    int64_t j = i - 1;
+    while (j >= b && cell_tri[j] > v) {
+      cell_tri[j + 1] = cell_tri[j];
+      --j;
+    }
+    cell_tri[j + 1] = v;
+  }
+}
+
+struct TriView {
+  const double *ax, *ay, *bx, *by, *cx, *cy, *det, *thr;
+  int64_t n_tri;
+};
+
+// 0 = self, 1 = near, 2 = far
+__device__ __forceinline__ int classify(const TriView& tv, int32_t t, double x, double y, double tau) {
+  const double Ax = tv.ax[t], Ay = tv.ay[t], Bx = tv.bx[t], By = tv.by[t], Cx = tv.cx[t], Cy = tv.cy[t];
+  const double D = tv.det[t];
+  const double d0 = x - Ax, d1 = y - Ay;
+  const double e1x = Bx - Ax, e1y = By - Ay, e2x = Cx - Ax, e2y = Cy - Ay;
+  const double xi1 = (d0 * e2y - d1 * e2x) / D;
+  const double xi2 = (e1x * d1 - e1y * d0) / D;
+  const double lmin = fmin(fmin(1.0 - xi1 - xi2, xi1), xi2);
+  if (lmin >= -tau) return 0;
+  const double px[3] = {Ax, Bx, Cx}, py[3] = {Ay, By, Cy};
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const double s = tv.thr[e * tv.n_tri + t];
+    if (s <= 0.0) continue;
+    const double Px = px[e], Py = py[e], Qx = px[(e + 1) % 3], Qy = py[(e + 1) % 3];
+    const double fs = sqrt((x - Px) * (x - Px) + (y - Py) * (y - Py)) + sqrt((x - Qx) * (x - Qx) + (y - Qy) * (y - Qy));
+    if (fs < s) return 1;
+  }
+  return 2;
+}
+
+__device__ __forceinline__ int64_t cell_of(const Grid g, double x, double y) {
+  int i = clampi((int)floor((x - g.x0) * g.inv_h), 0, g.nx - 1);
+  int j = clampi((int)floor((y - g.y0) * g.inv_h), 0, g.ny - 1);
+  return (int64_t)j * g.nx + i;
+}
+
+__global__ void k_pair_count(const double* __restrict__ xt, const double* __restrict__ yt, int64_t n_tgt, Grid g,
+                             const int64_t* __restrict__ cptr, const int32_t* __restrict__ ctri, TriView tv,
+                             double tau, int32_t* cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_tgt) return;
+  const double x = xt[i], y = yt[i];
+  const int64_t c = cell_of(g, x, y);
+  int n = 0;
+  for (int64_t k = cptr[c]; k < cptr[c + 1]; ++k) n += (classify(tv, ctri[k], x, y, tau) < 2);
+  cnt[i] = n;
+}
+
+__global__ void k_pair_fill(const double* __restrict__ xt, const double* __restrict__ yt, int64_t n_tgt, Grid g,
+                            const int64_t* __restrict__ cptr, const int32_t* __restrict__ ctri, TriView tv,
+                            double tau, const int64_t* __restrict__ row_ptr, int32_t* pair_tri,
+                            int32_t* pair_tgt, uint8_t* pair_kind, int32_t* self_cnt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_tgt) return;
+  const double x = xt[i], y = yt[i];
+  const int64_t c = cell_of(g, x, y);
+  int64_t o = row_ptr[i];
+  int ns = 0;
+  for (int64_t k = cptr[c]; k < cptr[c + 1]; ++k) {
+    const int32_t t = ctri[k];
+    const int kind = classify(tv, t, x, y, tau);
+    if (kind < 2) {
+      pair_tri[o] = t;
+      pair_tgt[o] = (int32_t)i;
+      pair_kind[o] = (uint8_t)kind;
+      ns += (kind == 0);
+      ++o;
+    }
+  }
+  self_cnt[i] = ns;
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int32 counts into int64 offsets (out[n] = total)
+// ---------------------------------------------------------------------------
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t& total) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int o = 1; o < kBlock; o <<= 1) {
+    int64_t a = (tid >= o) ? sh[tid - o] : 0;
+    __syncthreads();
+    sh[tid] += a;
+    __syncthreads();
+  }
+  total = sh[kBlock - 1];
+  int64_t incl = sh[tid];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void k_scan_tiles(const int32_t* __restrict__ in, int64_t n, int64_t* out, int64_t* tile_sums) {
+  __shared__ int64_t sh[kBlock];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int64_t loc[kScanItems];
+  int64_t s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t i = base + k;
+    loc[k] = (i < n) ? (int64_t)in[i] : 0;
+    s += loc[k];
+  }
+  int64_t total;
+  int64_t off = block_exclusive_scan(s, sh, total);
+  for (int k = 0; k < kScanItems; ++k) {
+    int64_t i = base + k;
+    if (i < n) out[i] = off;
+    off += loc[k];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_sums(int64_t* tile_sums, int64_t n_tiles, int64_t* grand) {
+  __shared__ int64_t sh[kBlock];
+  int64_t carry = 0;
+  for (int64_t b = 0; b < n_tiles; b += kBlock) {
+    int64_t i = b + threadIdx.x;
+    int64_t v = (i < n_tiles) ? tile_sums[i] : 0;
+    int64_t total;
+    int64_t ex = block_exclusive_scan(v, sh, total);
+    if (i < n_tiles) tile_sums[i] = carry + ex;
+    carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *grand = carry;
+}
+
+__global__ void k_scan_add(int64_t* out, int64_t n, const int64_t* __restrict__ tile_sums) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  const int64_t add = tile_sums[blockIdx.x];
+  for (int k = threadIdx.x; k < kScanTile; k += kBlock) {
+    int64_t i = base + k;
+    if (i < n) out[i] += add;
+  }
+}
+
+__global__ void k_count_sum(const int32_t* __restrict__ v, int64_t n, unsigned long long* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t s = (i < n) ? v[i] : 0;
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0 && s) atomicAdd(out, (unsigned long long)s);
+}
+
+}  // namespace
+
+size_t exclusive_scan_tmp_bytes(int64_t n) {
+  int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  return (size_t)(tiles + 1) * sizeof(int64_t);
+}
+
+hipError_t exclusive_scan_i32(const int32_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t st) {
+  int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  int64_t* sums = (int64_t*)tmp;
+  if (tiles > 0) {
+    k_scan_tiles<<<(unsigned)tiles, kBlock, 0, st>>>(in, n, out, sums);
+  }
+  k_scan_sums<<<1, kBlock, 0, st>>>(sums, tiles, out + n);
+  if (tiles > 0) {
+    k_scan_add<<<(unsigned)tiles, kBlock, 0, st>>>(out, n, sums);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_mesh_geom(const double* vert, int64_t n_vert, const int32_t* tri, int64_t n_tri, vp_mesh* m,
+                            int* d_bad, hipStream_t st) {
+  if (n_tri > 0)
+    k_mesh_geom<<<blocks_for(n_tri), kBlock, 0, st>>>(vert, n_vert, tri, n_tri, m->ax, m->ay, m->bx, m->by, m->cx,
+                                                      m->cy, m->det, d_bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_xy(const double* xy, int64_t n, double* x, double* y, int* d_bad, hipStream_t st) {
+  if (n > 0) k_split_xy<<<blocks_for(n), kBlock, 0, st>>>(xy, n, x, y, d_bad);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t basis_tables_p(vp_plan* pl, double* scratch, int* d_bad, hipStream_t st) {
+  k_vandermonde_inverse<P><<<1, 256, 0, st>>>(scratch, scratch + pl->n_p, scratch + 2 * pl->n_p, pl->vinv, d_bad);
+  k_basis_at<P><<<blocks_for(pl->n_f), kBlock, 0, st>>>(pl->far_x, pl->far_y, pl->n_f, pl->efar);
+  return hipGetLastError();
+}
+
+// scratch layout: [n_p] node x, [n_p] node y, [n_p][2 n_p] augmented matrix,
+// then an int flag
+hipError_t launch_basis_tables(vp_plan* pl, double* scratch, hipStream_t st) {
+  int* d_bad = (int*)(scratch + 2 * pl->n_p + 2 * pl->n_p * pl->n_p);
+  switch (pl->p) {
+    case 1: return basis_tables_p<1>(pl, scratch, d_bad, st);
+    case 2: return basis_tables_p<2>(pl, scratch, d_bad, st);
+    case 3: return basis_tables_p<3>(pl, scratch, d_bad, st);
+    case 4: return basis_tables_p<4>(pl, scratch, d_bad, st);
+    case 5: return basis_tables_p<5>(pl, scratch, d_bad, st);
+    case 6: return basis_tables_p<6>(pl, scratch, d_bad, st);
+    case 7: return basis_tables_p<7>(pl, scratch, d_bad, st);
+    case 8: return basis_tables_p<8>(pl, scratch, d_bad, st);
+    case 9: return basis_tables_p<9>(pl, scratch, d_bad, st);
+    case 10: return basis_tables_p<10>(pl, scratch, d_bad, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sources(vp_plan* pl, hipStream_t st) {
+  const vp_mesh* m = pl->mesh;
+  int64_t n = pl->n_src;
+  if (n > 0)
+    k_sources<<<blocks_for(n), kBlock, 0, st>>>(m->ax, m->ay, m->bx, m->by, m->cx, m->cy, pl->far_x, pl->far_y,
+                                                pl->n_f, pl->n_tri, pl->xs, pl->ys);
+  return hipGetLastError();
+}
+
+// Near-list construction.  Allocates the CSR arrays of the plan.
+hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
+  const vp_mesh* m = pl->mesh;
+  const int64_t T = pl->n_tri, NT = pl->n_tgt;
+  hipError_t e;
+  auto alloc = [&](void** p, size_t bytes) -> hipError_t {
+    hipError_t r = hipMalloc(p, bytes ? bytes : 8);
+    if (r == hipSuccess) {
+      pl->allocs.push_back(*p);
+      pl->bytes += bytes;
+    }
+    return r;
+  };
+  e = alloc((void**)&pl->row_ptr, sizeof(int64_t) * (NT + 1));
+  if (e != hipSuccess) return e;
+  if (NT == 0 || T == 0) {
+    e = hipMemsetAsync(pl->row_ptr, 0, sizeof(int64_t) * (NT + 1), st);
+    pl->n_pairs = 0;
+    pl->n_self = 0;
+    e = alloc((void**)&pl->pair_tri, 4);
+    if (e == hipSuccess) e = alloc((void**)&pl->pair_tgt, 4);
+    if (e == hipSuccess) e = alloc((void**)&pl->pair_kind, 4);
+    return e;
+  }
+  // temporaries
+  std::vector<void*> tmp;
+  auto talloc = [&](void** p, size_t bytes) -> hipError_t {
+    hipError_t r = hipMalloc(p, bytes ? bytes : 8);
+    if (r == hipSuccess) tmp.push_back(*p);
+    return r;
+  };
+  auto cleanup = [&]() {
+    for (void* p : tmp) (void)hipFree(p);
+  };
+  double *thr = nullptr, *box = nullptr, *part = nullptr;
+  const int nred = 256;
+  if ((e = talloc((void**)&thr, sizeof(double) * 3 * T)) != hipSuccess ||
+      (e = talloc((void**)&box, sizeof(double) * 4 * T)) != hipSuccess ||
+      (e = talloc((void**)&part, sizeof(double) * 5 * nred)) != hipSuccess) {
+    cleanup();
+    return e;
+  }
+  const double eps_cn = pl->eps * pl->opts.c_n;
+  const double inv_order = 1.0 / (2.0 * pl->q - 1.0);
+  k_tri_ellipses<<<blocks_for(T), kBlock, 0, st>>>(m->ax, m->ay, m->bx, m->by, m->cx, m->cy, m->det, T,
+                                                   pl->far_what[0], pl->far_what[1], pl->far_what[2], eps_cn,
+                                                   inv_order, thr, box);
+  k_extent_partial<<<nred, kBlock, 0, st>>>(pl->xt, pl->yt, NT, box, T, part);
+  if ((e = hipGetLastError()) != hipSuccess) {
+    cleanup();
+    return e;
+  }
+  std::vector<double> hp(5 * nred);
+  if ((e = hipMemcpyAsync(hp.data(), part, sizeof(double) * 5 * nred, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess) {
+    cleanup();
+    return e;
+  }
+  double gx0 = 1e300, gy0 = 1e300, gx1 = -1e300, gy1 = -1e300, sum = 0.0;
+  for (int i = 0; i < nred; ++i) {
+    gx0 = std::min(gx0, hp[5 * i]);
+    gy0 = std::min(gy0, hp[5 * i + 1]);
+    gx1 = std::max(gx1, hp[5 * i + 2]);
+    gy1 = std::max(gy1, hp[5 * i + 3]);
+    sum += hp[5 * i + 4];
+  }
+  // cell size: the mean extent of the triangles' near-field boxes, enlarged
+  // if the grid would exceed 2^24 cells
+  double h = std::max(sum / (double)T, 1e-300);
+  double wx = std::max(gx1 - gx0, 0.0), wy = std::max(gy1 - gy0, 0.0);
+  double cells = (wx / h + 1.0) * (wy / h + 1.0);
+  if (cells > 16777216.0) h *= std::sqrt(cells / 16777216.0);
+  Grid g;
+  g.x0 = gx0;
+  g.y0 = gy0;
+  g.inv_h = 1.0 / h;
+  g.nx = std::max(1, (int)std::ceil(wx / h) + 1);
+  g.ny = std::max(1, (int)std::ceil(wy / h) + 1);
+  const int64_t nc = (int64_t)g.nx * g.ny;
+  int32_t *ccnt = nullptr, *cfill = nullptr, *ctri = nullptr, *pcnt = nullptr, *scnt = nullptr;
+  int64_t* cptr = nullptr;
+  void* stmp = nullptr;
+  const int64_t nscan = std::max(nc, NT);
+  if ((e = talloc((void**)&ccnt, sizeof(int32_t) * nc)) != hipSuccess ||
+      (e = talloc((void**)&cfill, sizeof(int32_t) * nc)) != hipSuccess ||
+      (e = talloc((void**)&cptr, sizeof(int64_t) * (nc + 1))) != hipSuccess ||
+      (e = talloc(&stmp, exclusive_scan_tmp_bytes(nscan))) != hipSuccess ||
+      (e = talloc((void**)&pcnt, sizeof(int32_t) * NT)) != hipSuccess ||
+      (e = talloc((void**)&scnt, sizeof(int32_t) * NT)) != hipSuccess) {
+    cleanup();
+    return e;
+  }
+  hipMemsetAsync(ccnt, 0, sizeof(int32_t) * nc, st);
+  hipMemsetAsync(cfill, 0, sizeof(int32_t) * nc, st);
+  k_cell_count<<<blocks_for(T), kBlock, 0, st>>>(box, T, g, ccnt);
+  exclusive_scan_i32(ccnt, cptr, nc, stmp, st);
+  int64_t n_entries = 0;
+  if ((e = hipMemcpyAsync(&n_entries, cptr + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess) {
+    cleanup();
+    return e;
+  }
+  if ((e = talloc((void**)&ctri, sizeof(int32_t) * std::max<int64_t>(n_entries, 1))) != hipSuccess) {
+    cleanup();
+    return e;
+  }
+  k_cell_fill<<<blocks_for(T), kBlock, 0, st>>>(box, T, g, cptr, cfill, ctri);
+  k_cell_sort<<<blocks_for(nc), kBlock, 0, st>>>(cptr, nc, ctri);
+  TriView tv{m->ax, m->ay, m->bx, m->by, m->cx, m->cy, m->det, thr, T};
+  k_pair_count<<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, tv, pl->opts.tau, pcnt);
+  exclusive_scan_i32(pcnt, pl->row_ptr, NT, stmp, st);
+  if ((e = hipGetLastError()) != hipSuccess) {
+    cleanup();
+    return e;
+  }
+  int64_t np = 0;
+  if ((e = hipMemcpyAsync(&np, pl->row_ptr + NT, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess) {
+    cleanup();
+    return e;
+  }
+  pl->n_pairs = np;
+  if (pl->ctx->budget && pl->ctx->in_use + pl->bytes + (size_t)np * (9 + 8 * pl->n_p) > pl->ctx->budget) {
+    err = "plan exceeds the context's HBM budget";
+    cleanup();
+    return hipErrorOutOfMemory;
+  }
+  if ((e = alloc((void**)&pl->pair_tri, sizeof(int32_t) * np)) != hipSuccess ||
+      (e = alloc((void**)&pl->pair_tgt, sizeof(int32_t) * np)) != hipSuccess ||
+      (e = alloc((void**)&pl->pair_kind, std::max<int64_t>(np, 1))) != hipSuccess) {
+    cleanup();
+    return e;
+  }
+  k_pair_fill<<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, tv, pl->opts.tau, pl->row_ptr,
+                                                 pl->pair_tri, pl->pair_tgt, pl->pair_kind, scnt);
+  unsigned long long* d_sum = (unsigned long long*)part;
+  hipMemsetAsync(d_sum, 0, sizeof(unsigned long long), st);
+  k_count_sum<<<blocks_for(NT), kBlock, 0, st>>>(scnt, NT, d_sum);
+  unsigned long long ns = 0;
+  if ((e = hipGetLastError()) != hipSuccess ||
+      (e = hipMemcpyAsync(&ns, d_sum, sizeof(ns), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess) {
+    cleanup();
+    return e;
+  }
+  pl->n_self = (int64_t)ns;
+  cleanup();
+  return hipSuccess;
+}
+
+}  // namespace vp

@@ -1,0 +1,343 @@
+// Correction rows (FP64), one wavefront per (target, triangle) pair.
+//
+// row_k = (A_k - B_k) / 2pi for k < n_p, the subtract-and-add correction of
+// Sec. 3.6 against the Koornwinder basis:
+//   B_k  the far rule's own contribution, sum_j w_j |J| log|x - y_j| K_k(xi_j)
+//        (a pair at distance exactly 0 contributes 0, as in the far sum);
+//   A_k  the accurate integral of log|x - y| K_k(rho^{-1} y) over the triangle:
+//        near pair: adaptive subdivision (Sec. 3.3, eq. sum_near); a
+//          sub-triangle is integrated by the near rule once the target lies
+//          outside its three Bernstein ellipses (Sec. 4.1, eq. rho0 with the
+//          weight scaled by the sub-triangle's |J|), else split in four by
+//          edge midpoints; the levels are processed breadth-first with the
+//          lanes testing sub-triangles and integrating leaf nodes in
+//          parallel;
+//        self pair: the triangle split at the target into three pieces, each
+//          in radius-arc-length coordinates (Sec. 3.4, Thm. tensor_smooth_new
+//          and eq. volpot_self_single) with dyadic panels in arc length
+//          toward the target's foot point and the radial rule in r; the
+//          lanes share the (panel, arc node, radial node) triples.
+// Each lane accumulates n_p partial sums; a butterfly reduction finishes.
+//
+// Sub-triangles of the reference simplex are stored as (a_x, a_y, s): the
+// triangle a, a + s e_1, a + s e_2.  Children of (a, s):
+//   (a, s/2), (a + s e_1/2, s/2), (a + s e_2/2, s/2), (a + s (e_1+e_2)/2, -s/2)
+// i.e. the three corner triangles and the inverted middle one, each with the
+// vertex order that keeps its orientation and its collapse vertex.
+#include <cmath>
+
+#include "vp_internal.h"
+
+namespace vp {
+namespace {
+
+constexpr int kCap = 128;  // sub-triangles per level per pair
+constexpr double kInv2Pi = 0.15915494309189533577;
+
+struct RowsArgs {
+  const int32_t* pair_tri;
+  const int32_t* pair_tgt;
+  const uint8_t* pair_kind;
+  int64_t n_pairs;
+  const double *xt, *yt;
+  const double *ax, *ay, *bx, *by, *cx, *cy, *det;
+  const double *far_x, *far_y, *far_w, *efar;
+  int nf;
+  const double *near_x, *near_y, *near_w;
+  int nn;
+  double nwhat0, nwhat1, nwhat2;
+  double inv_near_order;
+  const double *gl_s, *gl_w;
+  int nl;
+  const double *rad_r, *rad_a, *rad_b;
+  int nr;
+  double eps_cn, tau;
+  int depth_cap, dyadic_cap;
+  double* rows;
+  int* flag;
+  int64_t* stats;  // near leaves, self panels, capped leaves
+};
+
+__device__ __forceinline__ bool outside_ellipses(double x, double y, double p0x, double p0y, double p1x, double p1y,
+                                                 double p2x, double p2y, double area2, const RowsArgs& a) {
+  const double px[3] = {p0x, p1x, p2x}, py[3] = {p0y, p1y, p2y};
+  const double wh[3] = {a.nwhat0, a.nwhat1, a.nwhat2};
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const double rho = pow(wh[e] * area2 / a.eps_cn, a.inv_near_order);
+    if (!(rho > 1.0)) continue;
+    const double Px = px[e], Py = py[e], Qx = px[(e + 1) % 3], Qy = py[(e + 1) % 3];
+    const double ell = sqrt((Qx - Px) * (Qx - Px) + (Qy - Py) * (Qy - Py));
+    const double thr = 0.5 * ell * (rho + 1.0 / rho);
+    const double fs = sqrt((x - Px) * (x - Px) + (y - Py) * (y - Py)) + sqrt((x - Qx) * (x - Qx) + (y - Qy) * (y - Qy));
+    if (fs < thr) return false;
+  }
+  return true;
+}
+
+__device__ __forceinline__ int dyadic_count(double len, double d, int cap) {
+  int n = 0;
+  double w = len;
+  while (!(w < d) && n < cap) {
+    w *= 0.5;
+    ++n;
+  }
+  return n;
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
+  constexpr int NP = (P + 1) * (P + 2) / 2;
+  __shared__ double lv[2][kCap * 3];
+  __shared__ double leaf[kCap * 3];
+  const int lane = threadIdx.x;
+  const int64_t pr = blockIdx.x;
+  if (pr >= a.n_pairs) return;
+  const int32_t t = a.pair_tri[pr];
+  const int32_t it = a.pair_tgt[pr];
+  const int kind = a.pair_kind[pr];
+  const double x = a.xt[it], y = a.yt[it];
+  const double Ax = a.ax[t], Ay = a.ay[t], Bx = a.bx[t], By = a.by[t], Cx = a.cx[t], Cy = a.cy[t];
+  const double D = a.det[t];
+  const double e1x = Bx - Ax, e1y = By - Ay, e2x = Cx - Ax, e2y = Cy - Ay;
+  const double invD = 1.0 / D;
+
+  double acc[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) acc[k] = 0.0;
+
+  // ---- B: the far rule's own contribution (subtracted) ----
+  for (int j = lane; j < a.nf; j += kWave) {
+    const double fx = a.far_x[j], fy = a.far_y[j];
+    const double yx = Ax + fx * e1x + fy * e2x, yy = Ay + fx * e1y + fy * e2y;
+    const double dx = x - yx, dy = y - yy;
+    const double r2 = dx * dx + dy * dy;
+    const double w = (r2 > 0.0) ? -0.5 * log(r2) * a.far_w[j] * D : 0.0;
+    const double* E = a.efar + (size_t)j * NP;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc[k] = fma(w, E[k], acc[k]);
+  }
+
+  int64_t n_leaves = 0, n_panels = 0, n_capped = 0;
+  if (kind == 1) {
+    // ---- A, near pair: breadth-first subdivision ----
+    double* cur = lv[0];
+    double* nxt = lv[1];
+    if (lane == 0) {
+      cur[0] = 0.0;
+      cur[1] = 0.0;
+      cur[2] = 1.0;
+    }
+    __syncthreads();
+    int n_cur = 1;
+    for (int level = 0; n_cur > 0; ++level) {
+      int n_next = 0, n_leaf = 0;
+      for (int base = 0; base < n_cur; base += kWave) {
+        const int i = base + lane;
+        bool valid = i < n_cur;
+        double sa = 0.0, sb = 0.0, ss = 0.0;
+        bool split = false;
+        if (valid) {
+          sa = cur[3 * i];
+          sb = cur[3 * i + 1];
+          ss = cur[3 * i + 2];
+          // physical vertices of the sub-triangle
+          const double p0x = Ax + sa * e1x + sb * e2x, p0y = Ay + sa * e1y + sb * e2y;
+          const double p1x = p0x + ss * e1x, p1y = p0y + ss * e1y;
+          const double p2x = p0x + ss * e2x, p2y = p0y + ss * e2y;
+          split = (level < a.depth_cap) && !outside_ellipses(x, y, p0x, p0y, p1x, p1y, p2x, p2y, ss * ss * D, a);
+        }
+        const bool is_leaf = valid && !split;
+        const uint64_t msplit = __ballot(split);
+        const uint64_t mleaf = __ballot(is_leaf);
+        const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        if (split) {
+          const int o = n_next + 4 * __popcll(msplit & lt);
+          if (o + 4 <= kCap) {
+            const double h = 0.5 * ss;
+            double* c = nxt + 3 * o;
+            c[0] = sa;          c[1] = sb;          c[2] = h;
+            c[3] = sa + h;      c[4] = sb;          c[5] = h;
+            c[6] = sa;          c[7] = sb + h;      c[8] = h;
+            c[9] = sa + h;      c[10] = sb + h;     c[11] = -h;
+          }
+        }
+        if (is_leaf) {
+          const int o = n_leaf + __popcll(mleaf & lt);
+          if (o < kCap) {
+            leaf[3 * o] = sa;
+            leaf[3 * o + 1] = sb;
+            leaf[3 * o + 2] = ss;
+          }
+        }
+        n_next += 4 * __popcll(msplit);
+        n_leaf += __popcll(mleaf);
+      }
+      if (level >= a.depth_cap) n_capped += n_leaf;
+      if (n_next > kCap || n_leaf > kCap) {
+        if (lane == 0) atomicMax(a.flag, 1);
+        n_next = 0;
+        n_leaf = n_leaf > kCap ? kCap : n_leaf;
+      }
+      __syncthreads();
+      n_leaves += n_leaf;
+      // integrate this level's leaves with the near rule
+      const int items = n_leaf * a.nn;
+      for (int item = lane; item < items; item += kWave) {
+        const int l = item / a.nn, nd = item - l * a.nn;
+        const double sa = leaf[3 * l], sb = leaf[3 * l + 1], ss = leaf[3 * l + 2];
+        const double xi1 = sa + ss * a.near_x[nd], xi2 = sb + ss * a.near_y[nd];
+        const double yx = Ax + xi1 * e1x + xi2 * e2x, yy = Ay + xi1 * e1y + xi2 * e2y;
+        const double dx = x - yx, dy = y - yy;
+        const double w = 0.5 * log(dx * dx + dy * dy) * a.near_w[nd] * ss * ss * D;
+        koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { acc[k] = fma(w, v, acc[k]); });
+      }
+      __syncthreads();
+      double* sw = cur;
+      cur = nxt;
+      nxt = sw;
+      n_cur = n_next;
+    }
+  } else {
+    // ---- A, self pair: three pieces in radius-arc-length coordinates ----
+    const double area = 0.5 * D;
+    const double vx[3] = {Ax, Bx, Cx}, vy[3] = {Ay, By, Cy};
+    for (int side = 0; side < 3; ++side) {
+      const double Px = vx[side], Py = vy[side], Qx = vx[(side + 1) % 3], Qy = vy[(side + 1) % 3];
+      const double sub = 0.5 * fabs((Px - x) * (Qy - y) - (Py - y) * (Qx - x));
+      if (sub <= a.tau * area) continue;
+      const double L = sqrt((Qx - Px) * (Qx - Px) + (Qy - Py) * (Qy - Py));
+      const double ux = (Qx - Px) / L, uy = (Qy - Py) / L;
+      const double h = fabs((Px - x) * (Qy - Py) - (Py - y) * (Qx - Px)) / L;
+      const double st = fmin(fmax((x - Px) * ux + (y - Py) * uy, 0.0), L);
+      const double fx = Px + st * ux, fy = Py + st * uy;
+      const double d = sqrt((x - fx) * (x - fx) + (y - fy) * (y - fy));
+      const double rest = L - st;
+      const int n1 = (st > 0.0) ? dyadic_count(st, d, a.dyadic_cap) : -1;
+      const int n2 = (rest > 0.0) ? dyadic_count(rest, d, a.dyadic_cap) : -1;
+      const int nleft = n1 + 1, nright = n2 + 1;  // panels per side (0 if empty)
+      const int np = nleft + nright;
+      n_panels += np;
+      const int per_panel = a.nl * a.nr;
+      const int items = np * per_panel;
+      for (int item = lane; item < items; item += kWave) {
+        const int ip = item / per_panel;
+        const int rem = item - ip * per_panel;
+        const int il = rem / a.nr, ir = rem - il * a.nr;
+        double s0, s1;
+        if (ip < nleft) {
+          if (ip < n1) {
+            s0 = (1.0 - ldexp(1.0, -ip)) * st;
+            s1 = (1.0 - ldexp(1.0, -(ip + 1))) * st;
+          } else {
+            s0 = (1.0 - ldexp(1.0, -n1)) * st;
+            s1 = st;
+          }
+        } else {
+          const int jp = ip - nleft;
+          if (jp < n2) {
+            s0 = L - (1.0 - ldexp(1.0, -(jp + 1))) * rest;
+            s1 = L - (1.0 - ldexp(1.0, -jp)) * rest;
+          } else {
+            s0 = st;
+            s1 = L - (1.0 - ldexp(1.0, -n2)) * rest;
+          }
+        }
+        const double s = s0 + (s1 - s0) * a.gl_s[il];
+        const double ws = (s1 - s0) * a.gl_w[il];
+        const double gx = Px + s * ux, gy = Py + s * uy;
+        const double r0 = sqrt((gx - x) * (gx - x) + (gy - y) * (gy - y));
+        const double rr = a.rad_r[ir];
+        const double px = x + rr * (gx - x), py = y + rr * (gy - y);
+        const double w = h * ws * (a.rad_a[ir] * log(r0) + a.rad_b[ir]);
+        const double dx = px - Ax, dy = py - Ay;
+        const double xi1 = (dx * e2y - dy * e2x) * invD;
+        const double xi2 = (e1x * dy - e1y * dx) * invD;
+        koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { acc[k] = fma(w, v, acc[k]); });
+      }
+    }
+  }
+
+  // ---- wave reduction and store ----
+  double* out = a.rows + (size_t)pr * NP;
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    double v = acc[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == (k & 63)) out[k] = v * kInv2Pi;
+  }
+  if (lane == 0) {
+    if (n_leaves) atomicAdd((unsigned long long*)&a.stats[0], (unsigned long long)n_leaves);
+    if (n_panels) atomicAdd((unsigned long long*)&a.stats[1], (unsigned long long)n_panels);
+    if (n_capped) atomicAdd((unsigned long long*)&a.stats[2], (unsigned long long)n_capped);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t st) {
+  if (pl->n_pairs == 0) return hipSuccess;
+  const vp_mesh* m = pl->mesh;
+  RowsArgs a;
+  a.pair_tri = pl->pair_tri;
+  a.pair_tgt = pl->pair_tgt;
+  a.pair_kind = pl->pair_kind;
+  a.n_pairs = pl->n_pairs;
+  a.xt = pl->xt;
+  a.yt = pl->yt;
+  a.ax = m->ax;
+  a.ay = m->ay;
+  a.bx = m->bx;
+  a.by = m->by;
+  a.cx = m->cx;
+  a.cy = m->cy;
+  a.det = m->det;
+  a.far_x = pl->far_x;
+  a.far_y = pl->far_y;
+  a.far_w = pl->far_w;
+  a.efar = pl->efar;
+  a.nf = pl->n_f;
+  a.near_x = pl->near_x;
+  a.near_y = pl->near_y;
+  a.near_w = pl->near_w;
+  a.nn = pl->opts.q_near * pl->opts.q_near;
+  a.nwhat0 = pl->near_what[0];
+  a.nwhat1 = pl->near_what[1];
+  a.nwhat2 = pl->near_what[2];
+  a.inv_near_order = 1.0 / (2.0 * pl->opts.q_near - 1.0);
+  a.gl_s = pl->gl_s;
+  a.gl_w = pl->gl_w;
+  a.nl = pl->opts.n_l;
+  a.rad_r = pl->rad_r;
+  a.rad_a = pl->rad_a;
+  a.rad_b = pl->rad_b;
+  a.nr = pl->n_r;
+  a.eps_cn = pl->eps * pl->opts.c_n;
+  a.tau = pl->opts.tau;
+  a.depth_cap = pl->opts.depth_cap;
+  a.dyadic_cap = pl->opts.dyadic_cap;
+  a.rows = pl->rows;
+  a.flag = d_flag;
+  a.stats = d_stats;
+  // one 64-lane workgroup per pair; the grid's x dimension takes up to 2^31 - 1
+  const int64_t max_grid = 2147483647LL;
+  if (pl->n_pairs > max_grid) return hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)pl->n_pairs);
+  switch (pl->p) {
+    case 1: k_rows<1><<<grid, 64, 0, st>>>(a); break;
+    case 2: k_rows<2><<<grid, 64, 0, st>>>(a); break;
+    case 3: k_rows<3><<<grid, 64, 0, st>>>(a); break;
+    case 4: k_rows<4><<<grid, 64, 0, st>>>(a); break;
+    case 5: k_rows<5><<<grid, 64, 0, st>>>(a); break;
+    case 6: k_rows<6><<<grid, 64, 0, st>>>(a); break;
+    case 7: k_rows<7><<<grid, 64, 0, st>>>(a); break;
+    case 8: k_rows<8><<<grid, 64, 0, st>>>(a); break;
+    case 9: k_rows<9><<<grid, 64, 0, st>>>(a); break;
+    case 10: k_rows<10><<<grid, 64, 0, st>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace vp

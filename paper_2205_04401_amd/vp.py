@@ -1,0 +1,257 @@
+"""ctypes binding of libvp (include/vp.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts numpy
+arrays / torch tensors to pointers and raises on a non-zero status.  Loading
+fails loudly (``VPError``) when ``libvp.so`` is missing: there is no fallback.
+
+    ctx = Context()                       # device 0, default stream
+    mesh = ctx.mesh(vert, tri)            # [n_vert, 2] float64, [n_tri, 3] int32
+    plan = ctx.plan(mesh, p=6, q=8, eps=1e-13, targets=tgt)
+    u = plan.execute(F)                   # F [n_tri, n_p] or [n_tri, n_p, R]
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvp.so")
+
+VP_OK, VP_EINVAL, VP_ENOMEM, VP_EDEVICE, VP_ENOTSUP, VP_EBUSY, VP_EINTERNAL = range(7)
+VP_FP64, VP_MIXED = 0, 1
+VP_DEVICE_PTRS, VP_FAR_ONLY, VP_ASYNC = 1, 2, 4
+STATUS_NAMES = {0: "VP_OK", 1: "VP_EINVAL", 2: "VP_ENOMEM", 3: "VP_EDEVICE", 4: "VP_ENOTSUP",
+                5: "VP_EBUSY", 6: "VP_EINTERNAL"}
+
+# every symbol include/vp.h declares
+EXPORTS = ["vp_ctx_create", "vp_ctx_destroy", "vp_last_error", "vp_ref_nodes", "vp_ref_rule", "vp_mesh_create",
+           "vp_mesh_destroy", "vp_plan_create", "vp_plan_info", "vp_plan_pairs", "vp_plan_rows",
+           "vp_execute", "vp_coefficients", "vp_plan_sources", "vp_plan_destroy", "vp_sync"]
+
+
+class VPError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("c_n", ctypes.c_double), ("q_near", ctypes.c_int), ("n_l", ctypes.c_int),
+                ("tau", ctypes.c_double), ("depth_cap", ctypes.c_int), ("dyadic_cap", ctypes.c_int)]
+
+
+class PlanStats(ctypes.Structure):
+    _fields_ = [("n_tri", ctypes.c_int64), ("n_src", ctypes.c_int64), ("n_tgt", ctypes.c_int64),
+                ("n_pairs", ctypes.c_int64), ("n_self", ctypes.c_int64), ("near_subtri", ctypes.c_int64),
+                ("self_panels", ctypes.c_int64), ("capped_leaves", ctypes.c_int64),
+                ("bytes_resident", ctypes.c_int64), ("p", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("n_p", ctypes.c_int32), ("n_f", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("ms_classify", ctypes.c_double), ("ms_rows", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+P = ctypes.c_void_p
+I64 = ctypes.c_int64
+DP = ctypes.POINTER(ctypes.c_double)
+
+
+def load(path=LIB_PATH):
+    """Load libvp.so (once).  Raises VPError if it is not there."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise VPError(VP_EDEVICE, f"{path} not found: build it with `python -m paper_2205_04401_amd.build`")
+    lib = ctypes.CDLL(path)
+    sig = {
+        "vp_ctx_create": [ctypes.c_int, P, ctypes.c_uint64, ctypes.POINTER(P)],
+        "vp_ctx_destroy": [P],
+        "vp_ref_nodes": [ctypes.c_int, P, ctypes.POINTER(ctypes.c_int)],
+        "vp_ref_rule": [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.POINTER(ctypes.c_int)],
+        "vp_mesh_create": [P, I64, P, I64, P, ctypes.POINTER(P)],
+        "vp_mesh_destroy": [P],
+        "vp_plan_create": [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_double, I64, P, P, ctypes.POINTER(P)],
+        "vp_plan_info": [P, ctypes.POINTER(PlanStats)],
+        "vp_plan_pairs": [P, P, P, P],
+        "vp_plan_rows": [P, P],
+        "vp_execute": [P, I64, P, P, ctypes.c_int, ctypes.c_uint32],
+        "vp_coefficients": [P, I64, P, P, P, ctypes.c_uint32],
+        "vp_plan_sources": [P, P],
+        "vp_plan_destroy": [P],
+        "vp_sync": [P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.vp_last_error.argtypes = []
+    lib.vp_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != VP_OK:
+        raise VPError(status, _lib.vp_last_error().decode())
+
+
+def _ptr(a):
+    """Pointer of a contiguous numpy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(P)
+    return P(a.data_ptr())
+
+
+def _is_device(a):
+    return a is not None and not isinstance(a, np.ndarray) and getattr(a, "is_cuda", False)
+
+
+def ref_nodes(p):
+    """Reference interpolation nodes [n_p, 2] of order p."""
+    lib = load()
+    n = ctypes.c_int()
+    _check(lib.vp_ref_nodes(p, None, ctypes.byref(n)))
+    out = np.empty((n.value, 2))
+    _check(lib.vp_ref_nodes(p, _ptr(out), ctypes.byref(n)))
+    return out
+
+
+def ref_rule(which, n):
+    """Reference rule `which` (see vp_ref_rule) as (x, y, w) arrays."""
+    lib = load()
+    cnt = ctypes.c_int()
+    _check(lib.vp_ref_rule(which, n, None, None, None, ctypes.byref(cnt)))
+    x, y, w = np.zeros(cnt.value), np.zeros(cnt.value), np.zeros(cnt.value)
+    _check(lib.vp_ref_rule(which, n, _ptr(x), _ptr(y), _ptr(w), ctypes.byref(cnt)))
+    return x, y, w
+
+
+class Context:
+    def __init__(self, device=0, stream=None, hbm_budget_bytes=0):
+        lib = load()
+        h = P()
+        sp = None if stream is None else P(int(stream))
+        _check(lib.vp_ctx_create(device, sp, hbm_budget_bytes, ctypes.byref(h)))
+        self.h = h
+        self.device = device
+
+    def mesh(self, vert, tri):
+        return Mesh(self, vert, tri)
+
+    def plan(self, mesh, p, q, eps, targets, **opts):
+        return Plan(self, mesh, p, q, eps, targets, **opts)
+
+    def sync(self):
+        _check(load().vp_sync(self.h))
+
+    def close(self):
+        if self.h:
+            _check(load().vp_ctx_destroy(self.h))
+            self.h = None
+
+
+class Mesh:
+    def __init__(self, ctx, vert, tri):
+        vert = np.ascontiguousarray(vert, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        h = P()
+        _check(load().vp_mesh_create(ctx.h, vert.shape[0], _ptr(vert), tri.shape[0], _ptr(tri), ctypes.byref(h)))
+        self.h = h
+        self.ctx = ctx
+        self.n_tri = tri.shape[0]
+
+    def close(self):
+        if self.h:
+            _check(load().vp_mesh_destroy(self.h))
+            self.h = None
+
+
+class Plan:
+    def __init__(self, ctx, mesh, p, q, eps, targets, c_n=1.0, q_near=7, n_l=16, tau=1e-13, depth_cap=50,
+                 dyadic_cap=60):
+        tgt = np.ascontiguousarray(np.asarray(targets, dtype=np.float64).reshape(-1, 2))
+        opts = PlanOpts(c_n, q_near, n_l, tau, depth_cap, dyadic_cap)
+        h = P()
+        _check(load().vp_plan_create(ctx.h, mesh.h, p, q, eps, tgt.shape[0], _ptr(tgt), ctypes.byref(opts),
+                                     ctypes.byref(h)))
+        self.h = h
+        self.ctx = ctx
+        self.mesh = mesh
+        st = self.info()
+        self.n_tri, self.n_tgt, self.n_p, self.n_src = st["n_tri"], st["n_tgt"], st["n_p"], st["n_src"]
+        self.n_pairs = st["n_pairs"]
+
+    def info(self):
+        s = PlanStats()
+        _check(load().vp_plan_info(self.h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def pairs(self):
+        """(row_ptr [n_tgt+1] int64, tri [n_pairs] int32, kind [n_pairs] uint8)."""
+        st = self.info()
+        rp = np.empty(st["n_tgt"] + 1, dtype=np.int64)
+        tri = np.empty(st["n_pairs"], dtype=np.int32)
+        kind = np.empty(st["n_pairs"], dtype=np.uint8)
+        _check(load().vp_plan_pairs(self.h, _ptr(rp), _ptr(tri), _ptr(kind)))
+        return rp, tri, kind
+
+    def rows(self):
+        st = self.info()
+        out = np.empty((st["n_pairs"], st["n_p"]))
+        _check(load().vp_plan_rows(self.h, _ptr(out)))
+        return out
+
+    def sources(self):
+        out = np.empty((self.n_src, 2))
+        _check(load().vp_plan_sources(self.h, _ptr(out)))
+        return out
+
+    def _density(self, F):
+        if _is_device(F):
+            if F.dim() == 2:
+                F = F.unsqueeze(-1)
+            R = F.shape[2]
+            return F.contiguous(), R, True
+        F = np.asarray(F, dtype=np.float64)
+        if F.ndim == 2:
+            F = F[:, :, None]
+        if F.shape[:2] != (self.n_tri, self.n_p):
+            raise VPError(VP_EINVAL, f"density shape {F.shape} != ({self.n_tri}, {self.n_p}, R)")
+        return np.ascontiguousarray(F), F.shape[2], False
+
+    def execute(self, F, far_only=False, out=None, asynchronous=False):
+        """u [n_tgt] (one density) or [n_tgt, R].  Device tensors in ->
+        device tensor out (written into `out` if given)."""
+        single = (F.ndim if hasattr(F, "ndim") else F.dim()) == 2
+        Fc, R, dev = self._density(F)
+        flags = (VP_FAR_ONLY if far_only else 0)
+        if dev:
+            import torch
+            if out is None:
+                out = torch.empty((self.n_tgt, R), dtype=torch.float64, device=Fc.device)
+            flags |= VP_DEVICE_PTRS | (VP_ASYNC if asynchronous else 0)
+        else:
+            out = np.empty((self.n_tgt, R))
+        _check(load().vp_execute(self.h, R, _ptr(Fc), _ptr(out), VP_FP64, flags))
+        return out[:, 0] if single else out
+
+    def coefficients(self, F):
+        """(coefficients [n_tri, n_p, R], charges [n_src, R]) as host arrays."""
+        Fc, R, dev = self._density(F)
+        if dev:
+            raise VPError(VP_EINVAL, "coefficients() takes host arrays")
+        coef = np.empty((self.n_tri, self.n_p, R))
+        charge = np.empty((self.n_src, R))
+        _check(load().vp_coefficients(self.h, R, _ptr(Fc), _ptr(coef), _ptr(charge), 0))
+        return coef, charge
+
+    def close(self):
+        if self.h:
+            _check(load().vp_plan_destroy(self.h))
+            self.h = None

@@ -1,0 +1,88 @@
+"""The C-ABI library loads on the CPU, exports every symbol include/vp.h
+declares, and its host-side reference data agrees with the oracle's
+independently built tables (no device call is made here)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import rules
+from paper_2205_04401_amd import vp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vp.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vp_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(vp.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(vp.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    saved = vp._lib
+    vp._lib = None
+    try:
+        with pytest.raises(vp.VPError):
+            vp.load(str(tmp_path / "missing.so"))
+    finally:
+        vp._lib = saved
+
+
+@pytest.mark.parametrize("p", range(1, 11))
+def test_reference_nodes_match_oracle(p):
+    assert np.abs(vp.ref_nodes(p) - rules.interp_nodes(p)).max() < 2e-15
+
+
+@pytest.mark.parametrize("n", [2, 4, 8, 10, 16, 24])
+def test_gauss_legendre_matches_oracle(n):
+    x, _, w = vp.ref_rule(0, n)
+    gx, gw = rules.gauss_legendre01(n)
+    assert np.abs(x - gx).max() < 4e-16 and np.abs(w - gw).max() < 4e-15
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6, 8])
+def test_log_rule_matches_oracle(n):
+    x, _, w = vp.ref_rule(1, n)
+    gx, gw = rules.log_gauss01(n)
+    assert np.abs(x - gx).max() < 4e-16 and np.abs(w - gw).max() < 4e-16
+
+
+@pytest.mark.parametrize("q", [2, 3, 4, 7, 8, 12, 16, 20, 32])
+def test_collapsed_rule_and_edge_weights_match_oracle(q):
+    x, y, w = vp.ref_rule(2, q)
+    X, W = rules.collapsed_gauss(q)
+    assert np.abs(x - X[:, 0]).max() < 4e-16 and np.abs(y - X[:, 1]).max() < 4e-16
+    assert np.abs(w - W).max() < 4e-16
+    _, _, ew = vp.ref_rule(4, q)
+    assert np.abs(ew - rules.edge_weights(q)).max() < 4e-16
+
+
+@pytest.mark.parametrize("p", [1, 3, 4, 6, 8, 10])
+def test_radial_rule_matches_oracle(p):
+    r, a, b = vp.ref_rule(3, p)
+    R, A, B = rules.radial_rule(p)
+    assert np.abs(r - R).max() < 4e-16 and np.abs(a - A).max() < 4e-16 and np.abs(b - B).max() < 4e-16
+
+
+def test_invalid_rule_requests_are_rejected():
+    with pytest.raises(vp.VPError) as e:
+        vp.ref_rule(7, 4)
+    assert e.value.status == vp.VP_EINVAL
+    with pytest.raises(vp.VPError):
+        vp.ref_nodes(0)
+    with pytest.raises(vp.VPError):
+        vp.ref_nodes(11)

@@ -1,0 +1,318 @@
+"""GPU parity: the HIP library (through its C ABI) against the oracle.
+
+Bars (FP64 path): far sum alone <= 1e-13 relative L-infinity, end to end
+<= 1e-11 relative L-infinity (max_t |u_gpu - u_oracle| / max_t |u_oracle|
+per right-hand side), pair lists equal except pairs whose classification
+margin is within 1e-12 of the decision boundary (both sides then sit within
+rounding of an ellipse or an edge, where either answer meets eps).
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import potential, rules
+from paper_2205_04401_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL_FAR = 1e-13
+REL_E2E = 1e-11
+BAND = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def vp_ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a device"
+    from paper_2205_04401_amd import vp
+    ctx = vp.Context(0)
+    yield ctx
+
+
+def rel_linf(a, b):
+    a = np.asarray(a).reshape(len(a), -1)
+    b = np.asarray(b).reshape(len(b), -1)
+    return float((np.abs(a - b).max(0) / np.abs(b).max(0)).max())
+
+
+def oracle_pairs_rows(o, targets):
+    pairs, rows = [], {}
+    for i, x in enumerate(targets):
+        for t, k in o.classify_target(x):
+            pairs.append((i, t, k))
+            rows[(i, t)] = o.row(t, x, k)
+    return pairs, rows
+
+
+def margin(o, x, t, kind_gpu):
+    """Relative distance of (x, t) from the boundary of the test that decides
+    its class: self test (barycentric vs -tau) and each ellipse."""
+    lam = o.barycentric(t, x)
+    m = [abs(lam.min() + o.tau)]
+    N = 2 * o.q - 1
+    P3 = (o.A[t], o.B[t], o.C[t])
+    for e in range(3):
+        P, Q = P3[e], P3[(e + 1) % 3]
+        rho, thr = o.ellipse_params(P, Q, o.D[t], o.far_what[e], N)
+        if rho > 1:
+            fs = math.hypot(*(x - P)) + math.hypot(*(x - Q))
+            m.append(abs(fs - thr) / thr)
+    return min(m)
+
+
+def compare_pairs(plan, o, targets, sample=None):
+    """Pair lists of the plan vs the oracle's classification.  Returns the
+    number of band flips; fails on any other difference."""
+    rp, tri, kind = plan.pairs()
+    idx = range(len(targets)) if sample is None else sample
+    flips = 0
+    for i in idx:
+        x = targets[i]
+        g = {(int(t), int(k)) for t, k in zip(tri[rp[i]:rp[i + 1]], kind[rp[i]:rp[i + 1]])}
+        r = set(o.classify_target(x))
+        assert list(tri[rp[i]:rp[i + 1]]) == sorted(tri[rp[i]:rp[i + 1]]), "triangles not ascending"
+        for t, k in g ^ r:
+            assert margin(o, x, t, k) < BAND, (i, t, k, margin(o, x, t, k))
+            flips += 1
+    return flips
+
+
+# ---------------------------------------------------------------------------
+# unit square, p = 4, q = 8, eps = 1e-13 (1920 targets, 128 triangles)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c1(vp_ctx):
+    p, q, eps = 4, 8, 1e-13
+    vq, tq = W.unit_square(8, "/")
+    vt, tt = W.unit_square(8, "\\")
+    nodes = rules.interp_nodes(p)
+    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    F = W.sample_density(W.gaussian_bump, vq, tq, nodes)
+    say("c1: oracle")
+    o = potential.Oracle(vq, tq, p, q, eps)
+    pairs, rows = oracle_pairs_rows(o, tg)
+    c = o.coefficients(F)
+    pos, charge = o.far_sources(c)
+    u_far = o.far_sum(pos, charge, tg)[:, 0] / (2 * math.pi)
+    corr = np.zeros(len(tg))
+    for i, t, k in pairs:
+        corr[i] += rows[(i, t)] @ c[t]
+    say("c1: plan")
+    mesh = vp_ctx.mesh(vq, tq)
+    plan = vp_ctx.plan(mesh, p, q, eps, tg)
+    return dict(o=o, tg=tg, F=F, pairs=pairs, rows=rows, u_far=u_far, u=u_far + corr, c=c, pos=pos,
+                charge=charge, plan=plan, mesh=mesh, vq=vq, tq=tq)
+
+
+def test_c1_coefficients_and_charges(c1):
+    coef, charge = c1["plan"].coefficients(c1["F"])
+    assert np.abs(coef[:, :, 0] - c1["c"]).max() <= 1e-13 * np.abs(c1["c"]).max()
+    ref = c1["charge"][:, 0] / (4 * math.pi)
+    assert np.abs(charge[:, 0] - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert np.abs(c1["plan"].sources() - c1["pos"]).max() < 1e-15
+
+
+def test_c1_pair_lists(c1):
+    flips = compare_pairs(c1["plan"], c1["o"], c1["tg"])
+    info = c1["plan"].info()
+    say("c1 pairs", info["n_pairs"], "oracle", len(c1["pairs"]), "band flips", flips)
+    assert abs(info["n_pairs"] - len(c1["pairs"])) <= flips
+    assert info["n_self"] == sum(1 for _, _, k in c1["pairs"] if k == 0)
+
+
+def test_c1_rows(c1):
+    rp, tri, kind = c1["plan"].pairs()
+    rows = c1["plan"].rows()
+    scale = max(np.abs(r).max() for r in c1["rows"].values())
+    worst = 0.0
+    for i in range(len(c1["tg"])):
+        for p_ in range(rp[i], rp[i + 1]):
+            key = (i, int(tri[p_]))
+            if key in c1["rows"]:
+                worst = max(worst, np.abs(rows[p_] - c1["rows"][key]).max())
+    say("c1 rows worst abs diff", worst, "scale", scale)
+    assert worst <= 1e-12 * scale
+
+
+def test_c1_far_only(c1):
+    u = c1["plan"].execute(c1["F"], far_only=True)
+    err = rel_linf(u, c1["u_far"])
+    say("c1 far-only rel", err)
+    assert err <= REL_FAR
+
+
+def test_c1_end_to_end(c1):
+    u = c1["plan"].execute(c1["F"])
+    err = rel_linf(u, c1["u"])
+    say("c1 end-to-end rel", err)
+    assert err <= REL_E2E
+
+
+def test_c1_multi_rhs_and_device_pointers(c1):
+    import torch
+    F3 = np.stack([c1["F"], 2.0 * c1["F"] - 1.0, np.sin(c1["F"])], -1)
+    u3 = c1["plan"].execute(F3)
+    for r in range(3):
+        ur = c1["plan"].execute(np.ascontiguousarray(F3[:, :, r]))
+        assert np.abs(u3[:, r] - ur).max() <= 1e-15 * np.abs(ur).max()
+    Fd = torch.from_numpy(F3).cuda()
+    ud = c1["plan"].execute(Fd).cpu().numpy()
+    assert np.array_equal(ud, u3)
+
+
+def test_c1_deterministic(c1, vp_ctx):
+    plan2 = vp_ctx.plan(c1["mesh"], 4, 8, 1e-13, c1["tg"])
+    a, b = c1["plan"].pairs(), plan2.pairs()
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    assert np.array_equal(c1["plan"].rows(), plan2.rows())
+    assert np.array_equal(c1["plan"].execute(c1["F"]), plan2.execute(c1["F"]))
+    plan2.close()
+
+
+# ---------------------------------------------------------------------------
+# independent closed forms and edge cases
+# ---------------------------------------------------------------------------
+
+def test_disk_unit_density_polygon_closed_form(vp_ctx):
+    import pins
+    v, t = W.disk_mesh(n_tri=496, n_boundary=60, seed=1)
+    rng = np.random.default_rng(2)
+    r = rng.uniform(0, 3, 400)
+    a = rng.uniform(0, 2 * math.pi, 400)
+    tg = np.stack([r * np.cos(a), r * np.sin(a)], 1)
+    mesh = vp_ctx.mesh(v, t)
+    plan = vp_ctx.plan(mesh, 2, 8, 1e-13, tg)
+    u = plan.execute(np.ones((len(t), 6)))
+    ex = np.array([pins.mesh_unit_potential(v, t, x) for x in tg])
+    err = rel_linf(u, ex)
+    say("disk rel vs polygon closed form", err)
+    assert err <= REL_E2E
+    plan.close()
+    mesh.close()
+
+
+def test_targets_on_vertices_edges_far_and_ragged(vp_ctx):
+    """Targets exactly on vertices and edges (several self pairs), outside
+    every near field (no pair), and a count that is not a multiple of any
+    block size."""
+    p, q = 3, 6
+    vq, tq = W.unit_square(4, "/")
+    rng = np.random.default_rng(11)
+    tg = np.concatenate([vq, (vq[tq[:, 0]] + vq[tq[:, 1]]) / 2, rng.uniform(-0.2, 1.2, (251, 2)),
+                         np.array([[5.0, 5.0], [-40.0, 3.0]])])
+    nodes = rules.interp_nodes(p)
+    F = W.sample_density(lambda x, y: np.cos(3 * x) * y + 0.5, vq, tq, nodes)
+    o = potential.Oracle(vq, tq, p, q, 1e-12)
+    mesh = vp_ctx.mesh(vq, tq)
+    plan = vp_ctx.plan(mesh, p, q, 1e-12, tg)
+    compare_pairs(plan, o, tg)
+    rp, _, _ = plan.pairs()
+    assert rp[-2] == rp[-3] and rp[-1] == rp[-2]  # far-away targets: no pairs
+    u = plan.execute(F)
+    ref = o.evaluate(F, tg)
+    err = rel_linf(u, ref)
+    say("edge-case targets rel", err)
+    assert err <= REL_E2E
+    plan.close()
+    mesh.close()
+
+
+def test_empty_target_set_and_single_triangle(vp_ctx):
+    v = np.array([[0.0, 0.0], [1.0, 0.2], [0.1, 0.9]])
+    t = np.array([[0, 2, 1]], dtype=np.int32)  # clockwise: the library swaps B and C
+    mesh = vp_ctx.mesh(v, t)
+    plan = vp_ctx.plan(mesh, 2, 5, 1e-12, np.zeros((0, 2)))
+    assert plan.execute(np.ones((1, 6))).shape == (0,)
+    plan.close()
+    tg = np.array([[0.3, 0.3], [0.0, 0.0], [1.5, 1.5], [0.55, 0.1]])
+    plan = vp_ctx.plan(mesh, 2, 5, 1e-12, tg)
+    o = potential.Oracle(v, t, 2, 5, 1e-12)
+    F = np.arange(6.0)[None, :] * 0.1 + 1.0
+    assert rel_linf(plan.execute(F), o.evaluate(F, tg)) <= REL_E2E
+    plan.close()
+    mesh.close()
+
+
+def test_error_paths(vp_ctx):
+    from paper_2205_04401_amd import vp
+    vq, tq = W.unit_square(2, "/")
+    mesh = vp_ctx.mesh(vq, tq)
+    tg = np.array([[0.5, 0.5]])
+    for kw in (dict(p=0, q=8, eps=1e-12), dict(p=11, q=8, eps=1e-12), dict(p=2, q=1, eps=1e-12),
+               dict(p=2, q=33, eps=1e-12), dict(p=2, q=8, eps=0.0), dict(p=2, q=8, eps=-1.0)):
+        with pytest.raises(vp.VPError) as e:
+            vp_ctx.plan(mesh, kw["p"], kw["q"], kw["eps"], tg)
+        assert e.value.status == vp.VP_EINVAL
+    with pytest.raises(vp.VPError) as e:
+        vp_ctx.plan(mesh, 2, 8, 1e-12, np.array([[np.nan, 0.0]]))
+    assert e.value.status == vp.VP_EINVAL
+    bad = np.array([[0.0, 0.0], [1.0, 1.0], [2.0, 2.0]])
+    with pytest.raises(vp.VPError) as e:
+        vp_ctx.mesh(bad, np.array([[0, 1, 2]]))
+    assert e.value.status == vp.VP_EINVAL
+    with pytest.raises(vp.VPError) as e:
+        vp_ctx.mesh(vq, np.array([[0, 1, 99]]))
+    assert e.value.status == vp.VP_EINVAL
+    plan = vp_ctx.plan(mesh, 2, 8, 1e-12, tg)
+    with pytest.raises(vp.VPError) as e:
+        mesh.close()
+    assert e.value.status == vp.VP_EBUSY
+    with pytest.raises(vp.VPError) as e:  # n_rhs = 0
+        vp._check(vp.load().vp_execute(plan.h, 0, None, None, vp.VP_FP64, 0))
+    assert e.value.status == vp.VP_EINVAL
+    with pytest.raises(vp.VPError) as e:  # mixed precision is not built yet
+        vp._check(vp.load().vp_execute(plan.h, 1, vp._ptr(np.ones((len(tq), 6))), vp._ptr(np.zeros(1)),
+                                       vp.VP_MIXED, 0))
+    assert e.value.status == vp.VP_ENOTSUP
+    plan.close()
+    mesh.close()
+    small = vp.Context(0, hbm_budget_bytes=4096)
+    m2 = small.mesh(vq, tq)
+    with pytest.raises(vp.VPError) as e:
+        small.plan(m2, 6, 16, 1e-13, np.random.default_rng(0).uniform(0, 1, (500, 2)))
+    assert e.value.status == vp.VP_ENOMEM
+    m2.close()
+    small.close()
+
+
+# ---------------------------------------------------------------------------
+# full-size star (the benchmark's workload): sampled targets vs the oracle
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("q", [8])
+def test_star_full_size_sampled(vp_ctx, q):
+    p, eps = 6, 1e-13
+    vq, tq = W.star_mesh(n_tri=20000, seed=20)
+    vt, tt = W.star_mesh(n_tri=20000, seed=21, staggered=True)
+    nodes = rules.interp_nodes(p)
+    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    F = W.sample_density(W.gaussian_sum(22, vq, tq), vq, tq, nodes)
+    say("star: plan", len(tq), "triangles", len(tg), "targets")
+    mesh = vp_ctx.mesh(vq, tq)
+    plan = vp_ctx.plan(mesh, p, q, eps, tg)
+    u = plan.execute(F)
+    u_far = plan.execute(F, far_only=True)
+    info = plan.info()
+    say("star plan", {k: info[k] for k in ("n_pairs", "n_self", "near_subtri", "self_panels", "ms_classify",
+                                          "ms_rows", "capped_leaves")})
+    rng = np.random.default_rng(123)
+    sample = np.sort(rng.choice(len(tg), 24, replace=False))
+    o = potential.Oracle(vq, tq, p, q, eps)
+    compare_pairs(plan, o, tg, sample)
+    ref_u, ref_far, _, _ = o.evaluate(F, tg[sample], return_parts=True)
+    e_far = np.abs(u_far[sample] - ref_far).max() / np.abs(ref_far).max()
+    e_all = np.abs(u[sample] - ref_u).max() / np.abs(ref_u).max()
+    say("star sampled rel far", e_far, "end-to-end", e_all)
+    assert e_far <= REL_FAR
+    assert e_all <= REL_E2E
+    plan.close()
+    mesh.close()
