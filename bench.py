@@ -1,0 +1,227 @@
+"""Benchmark: potential evaluations per second on one MI355X (FP64 path).
+
+One step is one pass of the whole hot path for one density on the star
+workload: plan creation (far sources, near-field pair lists from the
+Bernstein-ellipse test, FP64 correction rows) followed by one evaluation
+(coefficients and far charges, the direct far-field sum, the correction
+apply).  Mesh, targets and density are resident in device memory before the
+timed region; the output stays on the device.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--q 8] [--sweep]
+
+Prints one JSON line (the contract); --sweep first prints one line per far
+order q (the near/far trade-off, Sec. 4.2).
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "potential evals/s at rel err 1e-11 (FP64) vs 1e-6 (mixed); p50/p99 solve latency"
+# MI355X published peaks
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+FLOPS_PER_PAIR = 8  # 2 sub, 1 mul, 1 FMA (r^2), 1 FMA (accumulate), log counted as 1
+
+
+def workload(p):
+    from paper_2205_04401_amd import vp
+    from paper_2205_04401_amd import workloads as W
+    vq, tq = W.star_mesh(n_tri=20000, n_boundary=2000, seed=20)
+    vt, tt = W.star_mesh(n_tri=20000, n_boundary=2000, seed=21, staggered=True)
+    nodes = vp.ref_nodes(p)
+    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    F = W.sample_density(W.gaussian_sum(22, vq, tq), vq, tq, nodes)
+    return vq, tq, tg, F
+
+
+def cpu_baseline(vq, tq, tg, F, p, q, eps, n_sample):
+    """The oracle (unchanged) on a seeded sample of targets of the same
+    workload, single-threaded; evals/s = sampled targets / seconds."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import potential
+    rng = np.random.default_rng(7)
+    sample = np.sort(rng.choice(len(tg), n_sample, replace=False))
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        o = potential.Oracle(vq, tq, p, q, eps)
+        o.evaluate(F, tg[sample])
+        dt = time.perf_counter() - t0
+    return {"value": n_sample / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_sample} seeded targets of the same star workload (all {len(tq) * q * q} far sources, "
+                      f"their self/near corrections), {dt:.1f} s single-threaded"}
+
+
+def measured_traffic(q):
+    """HBM bytes per far-kernel launch from the committed counter summary
+    (two rocprofv3 --pmc runs, FETCH_SIZE and WRITE_SIZE, calibrated on a
+    plain copy), or None when that summary was taken on another workload or
+    on a different version of the kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_far_fp64_star20k_q{q}_counters.md")
+    src = os.path.join(ROOT, "paper_2205_04401_amd", "csrc", "vp_exec.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#", "`")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if fields.get("kernel_source_sha256_16") != digest or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def copy_probe(n_bytes=1 << 29, reps=3):
+    """A plain device-to-device copy of known size (the calibration kernel
+    for the FETCH_SIZE / WRITE_SIZE counters)."""
+    import torch
+    a = torch.empty(n_bytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n_bytes, "reps": reps}), flush=True)
+
+
+def run(args):
+    import torch
+    from paper_2205_04401_amd import vp
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    dev = torch.device("cuda:0")
+    p, eps = 6, 1e-13
+    vq, tq, tg, F = workload(p)
+    stream = torch.cuda.current_stream()
+    ctx = vp.Context(0, stream=stream.cuda_stream)
+    mesh = ctx.mesh(vq, tq)
+    tg_d = torch.from_numpy(tg).to(dev)
+    F_d = torch.from_numpy(F).to(dev)
+    out = torch.empty((len(tg), 1), dtype=torch.float64, device=dev)
+
+    def step(q):
+        plan = ctx.plan(mesh, p, q, eps, tg_d)
+        plan.execute(F_d, out=out)
+        info = plan.info()
+        plan.close()
+        return info
+
+    def measure(q, steps, warmup):
+        for _ in range(warmup):
+            step(q)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = step(q)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        tm = ctx.timings()
+        ctx.profile(False)
+        return dt, info, tm
+
+    sweep = []
+    if args.sweep:
+        for q in (4, 5, 6, 8, 10, 12, 16):
+            dt, info, tm = measure(q, 2, 1)
+            line = {"q": q, "ms_per_step": dt * 1e3, "evals_per_s": len(tg) / dt,
+                    "far_ms": tm["far"][0] / 2, "rows_ms": tm["rows"][0] / 2, "classify_ms": tm["classify"][0] / 2,
+                    "n_pairs": info["n_pairs"], "pairs_per_target": info["n_pairs"] / len(tg),
+                    "near_subtri": info["near_subtri"], "n_src": info["n_src"]}
+            sweep.append(line)
+            print(json.dumps({"sweep": line}), flush=True)
+
+    q = args.q
+    dt, info, tm = measure(q, args.steps, args.warmup)
+    n_tgt, n_src = info["n_tgt"], info["n_src"]
+    far_ms, far_launches = tm["far"]
+    far_avg_s = far_ms / 1e3 / max(far_launches, 1)
+    pairs = n_src * n_tgt  # one launch covers all pairs for one RHS
+    achieved = FLOPS_PER_PAIR * pairs / far_avg_s / 1e12
+    exec_ms = (tm["coef"][0] + tm["far"][0] + tm["finish"][0]) / args.steps
+    plan_ms = (tm["classify"][0] + tm["rows"][0]) / args.steps
+    result = {
+        "metric": METRIC,
+        "value": n_tgt / dt,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"star r=1+0.3cos(5t): {len(tq)} triangles (2000 boundary points, seed 20), staggered "
+                        f"target mesh (seed 21) -> {n_tgt} targets; p={p} ({info['n_p']} nodes/triangle), "
+                        f"q={q} collapsed Gauss ({q * q} nodes/triangle -> {n_src} sources), eps={eps}, "
+                        f"1 density (10-Gaussian sum, seed 22); step = plan (near lists + FP64 rows) + evaluation",
+            "p": p, "q": q, "eps": eps, "n_rhs": 1, "precision": "fp64",
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP64_VECTOR_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
+            "traffic": measured_traffic(q),
+            "kernel": "k_far (FP64 direct far sum)",
+            "flops_per_pair": FLOPS_PER_PAIR,
+            "pairs_per_launch": pairs,
+            "avg_launch_ms": far_avg_s * 1e3,
+        },
+        "breakdown_ms": {k: v[0] / args.steps for k, v in tm.items()},
+        "execute_ms": exec_ms,
+        "plan_ms": plan_ms,
+        "far_pairs_per_s": pairs / far_avg_s,
+        "pairs_per_target": info["n_pairs"] / n_tgt,
+        "near_subtri_per_near_pair": info["near_subtri"] / max(1, info["n_pairs"] - info["n_self"]),
+        "self_panels_per_self_pair": info["self_panels"] / max(1, info["n_self"]),
+    }
+    if sweep:
+        result["q_sweep"] = sweep
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(vq, tq, tg, F, p, q, eps, args.cpu_sample)
+    mesh.close()
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--q", type=int, default=8)
+    ap.add_argument("--sweep", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=600)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="only run a 512 MiB device copy (counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the far sum, near lists and corrections of this build run on a single "
+              "MI355X; multi-GPU sharding is a design note only (targets would split across GPUs with one "
+              "all-gather of the far charges).", file=sys.stderr)
+        raise SystemExit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
+    run(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -89,6 +89,7 @@ typedef struct {
   double tau;       /* barycentric tolerance of the self test (default 1e-13) */
   int depth_cap;    /* maximum subdivision depth of a near pair (default 50) */
   int dyadic_cap;   /* maximum dyadic levels per side of a self piece (default 60) */
+  uint32_t flags;   /* VP_DEVICE_PTRS: tgt_xy of vp_plan_create is a device pointer (default 0) */
 } vp_plan_opts;
 
 /* Sizes and statistics of a plan. */
@@ -198,6 +199,23 @@ vp_status vp_plan_destroy(vp_plan* plan);
 
 /* Wait for all work issued on the context's stream. */
 vp_status vp_sync(vp_ctx* ctx);
+
+/* Device-time accounting (for benchmarks).  With profiling on, every plan
+ * creation and every vp_execute on the context brackets its stages with HIP
+ * events on the context's stream and adds their durations (ms) and launch
+ * counts to the context's accumulators, indexed by vp_stage.  Reading
+ * synchronises the stream; vp_ctx_profile(ctx, on) also resets the
+ * accumulators. */
+typedef enum {
+  VP_STAGE_CLASSIFY = 0, /* near-field pair list (Sec. 4.1) */
+  VP_STAGE_ROWS = 1,     /* correction rows (Sec. 3.3, 3.4, 3.6) */
+  VP_STAGE_COEF = 2,     /* coefficients and far charges (Sec. 2.2, 3.6) */
+  VP_STAGE_FAR = 3,      /* far-field direct sum: one k_far launch per RHS block */
+  VP_STAGE_FINISH = 4,   /* partial sums + corrections */
+  VP_N_STAGES = 5
+} vp_stage;
+vp_status vp_ctx_profile(vp_ctx* ctx, int on);
+vp_status vp_ctx_timings(vp_ctx* ctx, double* ms_out /* [VP_N_STAGES] */, int64_t* launches_out /* [VP_N_STAGES] */);
 
 #ifdef __cplusplus
 }

@@ -45,6 +45,7 @@ vp_plan_opts default_opts() {
   o.tau = 1e-13;
   o.depth_cap = 50;
   o.dyadic_cap = 60;
+  o.flags = 0;
   return o;
 }
 
@@ -88,9 +89,71 @@ hipError_t plan_alloc(vp_plan* pl, void** dst, size_t bytes) {
   return e;
 }
 
+// Stage bracket: records an event pair on the context's stream when
+// profiling is on.
+struct StageTimer {
+  vp_ctx* ctx;
+  int stage;
+  hipEvent_t a = nullptr, b = nullptr;
+  StageTimer(vp_ctx* c, int s) : ctx(c), stage(s) {
+    if (!ctx->profile) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      ctx->profile = false;
+      return;
+    }
+    (void)hipEventRecord(a, ctx->stream);
+  }
+  void stop(int64_t launches) {
+    if (!a || !ctx->profile) return;
+    (void)hipEventRecord(b, ctx->stream);
+    ctx->pending.push_back({stage, a, b, launches});
+    a = b = nullptr;
+  }
+  ~StageTimer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+void fold_timings(vp_ctx* ctx) {
+  for (auto& p : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      ctx->ms[p.stage] += ms;
+      ctx->launches[p.stage] += p.launches;
+    }
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  ctx->pending.clear();
+}
+
 }  // namespace
 
 extern "C" {
+
+vp_status vp_ctx_profile(vp_ctx* ctx, int on) {
+  if (!ctx) return fail(VP_EINVAL, "vp_ctx_profile: ctx is NULL");
+  VP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  fold_timings(ctx);
+  for (int i = 0; i < VP_N_STAGES; ++i) {
+    ctx->ms[i] = 0.0;
+    ctx->launches[i] = 0;
+  }
+  ctx->profile = on != 0;
+  return VP_OK;
+}
+
+vp_status vp_ctx_timings(vp_ctx* ctx, double* ms_out, int64_t* launches_out) {
+  if (!ctx) return fail(VP_EINVAL, "vp_ctx_timings: ctx is NULL");
+  VP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  fold_timings(ctx);
+  for (int i = 0; i < VP_N_STAGES; ++i) {
+    if (ms_out) ms_out[i] = ctx->ms[i];
+    if (launches_out) launches_out[i] = ctx->launches[i];
+  }
+  return VP_OK;
+}
 
 const char* vp_last_error(void) { return g_err.c_str(); }
 
@@ -111,6 +174,8 @@ vp_status vp_ctx_create(int device, void* stream, uint64_t budget, vp_ctx** out)
 vp_status vp_ctx_destroy(vp_ctx* ctx) {
   if (!ctx) return VP_OK;
   if (ctx->live_meshes) return fail(VP_EBUSY, "vp_ctx_destroy: %d meshes still alive", ctx->live_meshes);
+  (void)hipSetDevice(ctx->device);
+  fold_timings(ctx);
   delete ctx;
   return VP_OK;
 }
@@ -265,6 +330,9 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
   if (!(eps > 0.0) || !std::isfinite(eps)) return fail(VP_EINVAL, "vp_plan_create: eps must be > 0");
   if (n_tgt < 0 || n_tgt > 0x7fffffffLL) return fail(VP_EINVAL, "vp_plan_create: bad n_tgt");
   if (n_tgt > 0 && !tgt_xy) return fail(VP_EINVAL, "vp_plan_create: tgt_xy is NULL");
+  if ((int64_t)q * q * mesh->n_tri > 0x7fffff00LL)
+    return fail(VP_EINVAL, "vp_plan_create: n_tri * q^2 = %lld far sources exceed 2^31",
+                (long long)((int64_t)q * q * mesh->n_tri));
   vp_plan_opts o = opts ? *opts : default_opts();
   if (!(o.c_n > 0.0) || o.q_near < 2 || o.q_near > vp::kMaxQ || o.n_l < 2 || o.n_l > 64 || !(o.tau >= 0.0) ||
       o.depth_cap < 1 || o.depth_cap > 60 || o.dyadic_cap < 1 || o.dyadic_cap > 100)
@@ -341,8 +409,16 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
     if (bad) return fail(VP_EINTERNAL, "vp_plan_create: singular Vandermonde matrix");
   }
   // sources and targets
-  if ((e = plan_alloc(pl, (void**)&pl->xs, sizeof(double) * pl->n_src)) != hipSuccess ||
-      (e = plan_alloc(pl, (void**)&pl->ys, sizeof(double) * pl->n_src)) != hipSuccess ||
+  pl->n_src_pad = ((pl->n_src + 255) / 256) * 256;
+  {
+    double2 lt[65];
+    vp::log_table(lt);
+    if ((e = plan_alloc(pl, (void**)&pl->logtab, sizeof(double2) * 65)) != hipSuccess ||
+        (e = hipMemcpyAsync(pl->logtab, lt, sizeof(lt), hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+      return hip_fail(e, "vp_plan_create: log table");
+  }
+  if ((e = plan_alloc(pl, (void**)&pl->sxy, sizeof(double2) * pl->n_src_pad)) != hipSuccess ||
       (e = plan_alloc(pl, (void**)&pl->xt, sizeof(double) * n_tgt)) != hipSuccess ||
       (e = plan_alloc(pl, (void**)&pl->yt, sizeof(double) * n_tgt)) != hipSuccess)
     return hip_fail(e, "vp_plan_create: hipMalloc");
@@ -357,9 +433,9 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
       (void)hipFree(d_xy);
       return hip_fail(e, "vp_plan_create: hipMalloc");
     }
+    const hipMemcpyKind kind = (o.flags & VP_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     if ((e = hipMemsetAsync(d_bad, 0, sizeof(int), st)) != hipSuccess ||
-        (n_tgt && (e = hipMemcpyAsync(d_xy, tgt_xy, sizeof(double) * 2 * n_tgt, hipMemcpyHostToDevice, st)) !=
-                      hipSuccess) ||
+        (n_tgt && (e = hipMemcpyAsync(d_xy, tgt_xy, sizeof(double) * 2 * n_tgt, kind, st)) != hipSuccess) ||
         (e = vp::launch_split_xy(d_xy, n_tgt, pl->xt, pl->yt, d_bad, st)) != hipSuccess ||
         (e = hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess) {
@@ -385,6 +461,7 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
     }
   } evg{ev0, ev1, ev2};
   VP_HIP(hipEventRecord(ev0, st), "hipEventRecord");
+  StageTimer tm_classify(ctx, VP_STAGE_CLASSIFY);
   {
     std::string err;
     e = vp::build_pairs(pl, st, err);
@@ -393,7 +470,9 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
       return hip_fail(e, "vp_plan_create: near-field list");
     }
   }
+  tm_classify.stop(1);
   VP_HIP(hipEventRecord(ev1, st), "hipEventRecord");
+  StageTimer tm_rows(ctx, VP_STAGE_ROWS);
   // correction rows
   if ((e = plan_alloc(pl, (void**)&pl->rows, sizeof(double) * pl->n_pairs * NP)) != hipSuccess)
     return hip_fail(e, "vp_plan_create: rows");
@@ -409,7 +488,7 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
     if ((e = hipMemsetAsync(d_flag, 0, sizeof(int), st)) != hipSuccess ||
         (e = hipMemsetAsync(d_stats, 0, sizeof(int64_t) * 3, st)) != hipSuccess ||
         (e = vp::launch_rows(pl, d_flag, d_stats, st)) != hipSuccess ||
-        (e = hipEventRecord(ev2, st)) != hipSuccess ||
+        (e = hipEventRecord(ev2, st)) != hipSuccess || (tm_rows.stop(1), false) ||
         (e = hipMemcpyAsync(&flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipMemcpyAsync(pl->stats, d_stats, sizeof(int64_t) * 3, hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess) {
@@ -485,14 +564,10 @@ vp_status vp_plan_rows(const vp_plan* pl, double* rows) {
 vp_status vp_plan_sources(const vp_plan* pl, double* xy) {
   if (!pl || !xy) return fail(VP_EINVAL, "vp_plan_sources: NULL argument");
   VP_HIP(hipSetDevice(pl->ctx->device), "hipSetDevice");
-  std::vector<double> x(pl->n_src), y(pl->n_src);
   if (pl->n_src) {
-    VP_HIP(hipMemcpy(x.data(), pl->xs, sizeof(double) * pl->n_src, hipMemcpyDeviceToHost), "hipMemcpy");
-    VP_HIP(hipMemcpy(y.data(), pl->ys, sizeof(double) * pl->n_src, hipMemcpyDeviceToHost), "hipMemcpy");
-  }
-  for (int64_t i = 0; i < pl->n_src; ++i) {
-    xy[2 * i] = x[i];
-    xy[2 * i + 1] = y[i];
+    VP_HIP(hipMemcpyAsync(xy, pl->sxy, sizeof(double2) * pl->n_src, hipMemcpyDeviceToHost, pl->ctx->stream),
+           "hipMemcpy");
+    VP_HIP(hipStreamSynchronize(pl->ctx->stream), "hipStreamSynchronize");
   }
   return VP_OK;
 }
@@ -501,10 +576,15 @@ vp_status vp_plan_sources(const vp_plan* pl, double* xy) {
 
 namespace {
 
+// Source chunks of the far sum: enough blocks (about 16 per CU of a
+// 256-CU device) for an even finish, a multiple of 8 so each chunk's blocks
+// share an XCD, and chunks of at least 256 sources.
 int64_t choose_split(const vp_plan* pl) {
-  const int64_t bx = (pl->n_tgt + 255) / 256;
-  const int64_t want = (2048 + bx - 1) / std::max<int64_t>(bx, 1);
-  const int64_t most = std::max<int64_t>(1, (pl->n_src + 255) / 256);
+  const int64_t tpb = vp::far_targets_per_block();
+  const int64_t n_tb = std::max<int64_t>(1, (pl->n_tgt + tpb - 1) / tpb);
+  int64_t want = (4096 + n_tb - 1) / n_tb;
+  want = ((want + 7) / 8) * 8;
+  const int64_t most = std::max<int64_t>(1, std::min<int64_t>(pl->n_src_pad / 256, (1LL << 23) / n_tb));
   return std::max<int64_t>(1, std::min(want, most));
 }
 
@@ -520,7 +600,7 @@ vp_status ensure_workspace(vp_plan* pl, int64_t R) {
   pl->ws_bytes = 0;
   pl->ws_rhs = 0;
   const size_t nF = (size_t)pl->n_tri * pl->n_p * R;
-  const size_t nQ = (size_t)pl->n_src * R;
+  const size_t nQ = (size_t)pl->n_src_pad * R;
   const size_t nP = (size_t)split * pl->n_tgt * R;
   const size_t nU = (size_t)pl->n_tgt * R;
   const size_t bytes = 8 * (2 * nF + nQ + nP + nU) + 5 * 8;
@@ -531,7 +611,8 @@ vp_status ensure_workspace(vp_plan* pl, int64_t R) {
       (e = hipMalloc((void**)&pl->ws_c, 8 * std::max<size_t>(nF, 1))) != hipSuccess ||
       (e = hipMalloc((void**)&pl->ws_q, 8 * std::max<size_t>(nQ, 1))) != hipSuccess ||
       (e = hipMalloc((void**)&pl->ws_part, 8 * std::max<size_t>(nP, 1))) != hipSuccess ||
-      (e = hipMalloc((void**)&pl->ws_u, 8 * std::max<size_t>(nU, 1))) != hipSuccess) {
+      (e = hipMalloc((void**)&pl->ws_u, 8 * std::max<size_t>(nU, 1))) != hipSuccess ||
+      (e = hipMemsetAsync(pl->ws_q, 0, 8 * std::max<size_t>(nQ, 1), pl->ctx->stream)) != hipSuccess) {
     return hip_fail(e, "vp_execute: workspace");
   }
   pl->ws_rhs = R;
@@ -564,10 +645,24 @@ vp_status vp_execute(vp_plan* pl, int64_t R, const double* density, double* u_ou
     F = pl->ws_f;
   }
   double* U = dev ? u_out : pl->ws_u;
-  VP_HIP(vp::launch_coefficients(pl, F, R, pl->ws_c, pl->ws_q, st), "vp_execute: coefficients");
-  VP_HIP(vp::launch_far(pl, pl->ws_q, R, pl->ws_split, pl->ws_part, st), "vp_execute: far field");
-  VP_HIP(vp::launch_finish(pl, pl->ws_part, pl->ws_split, pl->ws_c, R, (flags & VP_FAR_ONLY) != 0, U, st),
-         "vp_execute: corrections");
+  vp_ctx* ctx = pl->ctx;
+  {
+    StageTimer tm(ctx, VP_STAGE_COEF);
+    VP_HIP(vp::launch_coefficients(pl, F, R, pl->ws_c, pl->ws_q, st), "vp_execute: coefficients");
+    tm.stop(2);
+  }
+  {
+    StageTimer tm(ctx, VP_STAGE_FAR);
+    int64_t nl = 0;
+    VP_HIP(vp::launch_far(pl, pl->ws_q, R, pl->ws_split, pl->ws_part, st, &nl), "vp_execute: far field");
+    tm.stop(nl);
+  }
+  {
+    StageTimer tm(ctx, VP_STAGE_FINISH);
+    VP_HIP(vp::launch_finish(pl, pl->ws_part, pl->ws_split, pl->ws_c, R, (flags & VP_FAR_ONLY) != 0, U, st),
+           "vp_execute: corrections");
+    tm.stop(1);
+  }
   if (!dev && pl->n_tgt)
     VP_HIP(hipMemcpyAsync(u_out, U, 8 * (size_t)pl->n_tgt * R, hipMemcpyDeviceToHost, st), "vp_execute: download");
   if (!(flags & VP_ASYNC)) VP_HIP(hipStreamSynchronize(st), "vp_execute: synchronize");

@@ -17,28 +17,35 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr double kInv4Pi = 0.07957747154594766788;
+constexpr int kFarTPT = 2;  // targets per thread in the far sum
 
-inline unsigned blocks_for(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+// Grid of a grid-stride launch: at most 2^20 blocks, so that a launch stays
+// far below 2^32 work-items.
+inline unsigned blocks_for(int64_t n, int b = kBlock) {
+  const int64_t nb = (n + b - 1) / b;
+  return (unsigned)(nb < (1 << 20) ? (nb > 0 ? nb : 1) : (1 << 20));
+}
 
 // one thread per (triangle, rhs); F and C are [T][NP][R]
 template <int P>
 __global__ void k_coef(const double* __restrict__ F, const double* __restrict__ vinv, int64_t n_tri, int64_t R,
                        double* __restrict__ C) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n_tri * R) return;
-  const int64_t t = g / R, r = g - t * R;
-  const double* f = F + (size_t)t * NP * R + r;
-  double v[NP];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_tri * R; g += stride) {
+    const int64_t t = g / R, r = g - t * R;
+    const double* f = F + (size_t)t * NP * R + r;
+    double v[NP];
 #pragma unroll
-  for (int i = 0; i < NP; ++i) v[i] = f[(size_t)i * R];
-  double* c = C + (size_t)t * NP * R + r;
+    for (int i = 0; i < NP; ++i) v[i] = f[(size_t)i * R];
+    double* c = C + (size_t)t * NP * R + r;
 #pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    double s = 0.0;
+    for (int k = 0; k < NP; ++k) {
+      double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < NP; ++i) s = fma(vinv[k * NP + i], v[i], s);
-    c[(size_t)k * R] = s;
+      for (int i = 0; i < NP; ++i) s = fma(vinv[k * NP + i], v[i], s);
+      c[(size_t)k * R] = s;
+    }
   }
 }
 
@@ -48,67 +55,121 @@ __global__ void k_charges(const double* __restrict__ C, const double* __restrict
                           const double* __restrict__ far_w, const double* __restrict__ det, int nf,
                           int64_t n_tri, int64_t R, double* __restrict__ Q) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n_src = n_tri * nf;
-  if (g >= n_src * R) return;
-  const int64_t src = g / R, r = g - src * R;
-  const int64_t t = src / nf;
-  const int j = (int)(src - t * nf);
-  const double* c = C + (size_t)t * NP * R + r;
-  const double* E = efar + (size_t)j * NP;
-  double s = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_src * R; g += stride) {
+    const int64_t src = g / R, r = g - src * R;
+    const int64_t t = src / nf;
+    const int j = (int)(src - t * nf);
+    const double* c = C + (size_t)t * NP * R + r;
+    const double* E = efar + (size_t)j * NP;
+    double s = 0.0;
 #pragma unroll
-  for (int k = 0; k < NP; ++k) s = fma(E[k], c[(size_t)k * R], s);
-  Q[g] = s * far_w[j] * det[t] * kInv4Pi;
+    for (int k = 0; k < NP; ++k) s = fma(E[k], c[(size_t)k * R], s);
+    Q[g] = s * far_w[j] * det[t] * kInv4Pi;
+  }
 }
 
-// Direct far sum.  Block = 256 threads = 256 targets; grid.y splits the
-// sources.  RB right-hand sides share one logarithm per pair.  Each LDS
-// tile's 256 terms are summed on their own before joining the running total
-// (two-level summation).
-template <int RB>
-__global__ __launch_bounds__(kBlock) void k_far(const double* __restrict__ xs, const double* __restrict__ ys,
-                                                const double* __restrict__ Q, int64_t n_src, int64_t R, int64_t r0,
+// Natural logarithm of x > 0 (normal) in FP64, table-driven (Tang's
+// method): x = m 2^e with m in [1/2, 1); the top six fraction bits select a
+// sub-interval of width 1/128 with centre c_i; with inv_c_i the double
+// nearest 1/c_i, r = m inv_c_i - 1 (|r| <= 1/128) comes from one FMA and
+//   log x = e ln2 - log(inv_c_i) + log1p(r),
+// with log1p(r) from its Taylor series through r^7 (truncation < 2e-18).
+// tab[i] = {inv_c_i, -log(inv_c_i)} for i < 64 and tab[64] = {ln2_hi,
+// ln2_lo}, ln2_hi holding 32 bits so that e ln2_hi is exact.  Error: a few
+// units in the last place of the result.  x = 0 gives a finite value
+// (callers mask it); subnormal x is not supported.
+__device__ __forceinline__ double vp_log(double x, const double2* tab) {
+  const unsigned hi = (unsigned)__double2hiint(x);
+  const int lo = __double2loint(x);
+  const unsigned i = (hi >> 14) & 63u;
+  const double ed = (double)((int)(hi >> 20) - 1022);
+  const double m = __hiloint2double((int)((hi & 0x000FFFFFu) | 0x3FE00000u), lo);
+  const double2 t = tab[i];
+  const double2 l2 = tab[64];
+  const double r = fma(m, t.x, -1.0);
+  double p = fma(r, 1.0 / 7.0, -1.0 / 6.0);
+  p = fma(r, p, 1.0 / 5.0);
+  p = fma(r, p, -0.25);
+  p = fma(r, p, 1.0 / 3.0);
+  p = fma(r, p, -0.5);
+  p = fma(r, p, 1.0);
+  p = p * r;
+  return fma(ed, l2.x, t.y) + fma(ed, l2.y, p);
+}
+
+// Direct far sum.  Each thread owns TPT targets (strided by the block
+// size); the sources are read with wavefront-uniform addresses (scalar
+// loads), RB right-hand sides share one logarithm per pair.  A linear block
+// id b takes source chunk b % n_split and target block b / n_split, so with
+// n_split a multiple of 8 the blocks that share a chunk sit on one XCD and
+// its L2.  Each 256-source tile is summed on its own before it joins the
+// running total (two-level summation).  Sources are padded to a multiple of
+// 4 with zero charges; a pair at distance 0 contributes 0.
+template <int RB, int TPT>
+__global__ __launch_bounds__(kBlock) void k_far(const double2* __restrict__ sxy, const double* __restrict__ Q,
+                                                int64_t n_src_pad, int64_t R, int64_t r0,
                                                 const double* __restrict__ xt, const double* __restrict__ yt,
-                                                int64_t n_tgt, int64_t per_split, double* __restrict__ partial) {
-  __shared__ double sx[kBlock], sy[kBlock], sq[kBlock * RB];
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const bool active = t < n_tgt;
-  const double x = active ? xt[t] : 0.0, y = active ? yt[t] : 0.0;
-  const int64_t s_begin = (int64_t)blockIdx.y * per_split;
-  const int64_t s_end = min(n_src, s_begin + per_split);
-  double acc[RB];
+                                                int64_t n_tgt, int64_t per_split, int64_t n_split,
+                                                const double2* __restrict__ logtab, double* __restrict__ partial) {
+  __shared__ double2 tab[65];
+  if (threadIdx.x < 65) tab[threadIdx.x] = logtab[threadIdx.x];
+  __syncthreads();
+  const int64_t b = blockIdx.x;
+  const int64_t chunk = b % n_split, tb = b / n_split;
+  double x[TPT], y[TPT];
+  int64_t t[TPT];
 #pragma unroll
-  for (int r = 0; r < RB; ++r) acc[r] = 0.0;
-  for (int64_t base = s_begin; base < s_end; base += kBlock) {
-    const int64_t j = base + threadIdx.x;
-    if (j < s_end) {
-      sx[threadIdx.x] = xs[j];
-      sy[threadIdx.x] = ys[j];
-#pragma unroll
-      for (int r = 0; r < RB; ++r) sq[threadIdx.x * RB + r] = (r0 + r < R) ? Q[j * R + r0 + r] : 0.0;
-    }
-    __syncthreads();
-    const int cnt = (int)min((int64_t)kBlock, s_end - base);
-    double tile[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) tile[r] = 0.0;
-    for (int i = 0; i < cnt; ++i) {
-      const double dx = x - sx[i], dy = y - sy[i];
-      const double r2 = fma(dx, dx, dy * dy);
-      const double lg = (r2 > 0.0) ? log(r2) : 0.0;
-#pragma unroll
-      for (int r = 0; r < RB; ++r) tile[r] = fma(sq[i * RB + r], lg, tile[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < RB; ++r) acc[r] += tile[r];
-    __syncthreads();
+  for (int k = 0; k < TPT; ++k) {
+    t[k] = tb * (kBlock * TPT) + k * kBlock + threadIdx.x;
+    const bool act = t[k] < n_tgt;
+    x[k] = act ? xt[t[k]] : 0.0;
+    y[k] = act ? yt[t[k]] : 0.0;
   }
-  if (active) {
+  const int64_t s_begin = chunk * per_split;
+  const int64_t s_end = min(n_src_pad, s_begin + per_split);
+  double acc[TPT][RB];
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
-      if (r0 + r < R) partial[((size_t)blockIdx.y * n_tgt + t) * R + r0 + r] = acc[r];
+  for (int k = 0; k < TPT; ++k)
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[k][r] = 0.0;
+  for (int64_t j0 = s_begin; j0 < s_end; j0 += 256) {
+    const int64_t j1 = min(s_end, j0 + 256);
+    double tile[TPT][RB];
+#pragma unroll
+    for (int k = 0; k < TPT; ++k)
+#pragma unroll
+      for (int r = 0; r < RB; ++r) tile[k][r] = 0.0;
+    for (int64_t j = j0; j < j1; j += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double2 s = sxy[j + u];
+        double q[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) q[r] = Q[(j + u) * R + r0 + r];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+          const double dx = x[k] - s.x, dy = y[k] - s.y;
+          const double r2 = fma(dx, dx, dy * dy);
+          double lg = vp_log(r2, tab);
+          lg = (r2 > 0.0) ? lg : 0.0;
+#pragma unroll
+          for (int r = 0; r < RB; ++r) tile[k][r] = fma(q[r], lg, tile[k][r]);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < TPT; ++k)
+#pragma unroll
+      for (int r = 0; r < RB; ++r) acc[k][r] += tile[k][r];
   }
+#pragma unroll
+  for (int k = 0; k < TPT; ++k)
+    if (t[k] < n_tgt) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r) partial[((size_t)chunk * n_tgt + t[k]) * R + r0 + r] = acc[k][r];
+    }
 }
 
 // one thread per (target, rhs)
@@ -118,22 +179,23 @@ __global__ void k_finish(const double* __restrict__ partial, int64_t n_split, in
                          const double* __restrict__ rows, const double* __restrict__ C, int far_only,
                          double* __restrict__ U) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n_tgt * R) return;
-  const int64_t t = g / R, r = g - t * R;
-  double u = 0.0;
-  for (int64_t s = 0; s < n_split; ++s) u += partial[((size_t)s * n_tgt + t) * R + r];
-  if (!far_only) {
-    double corr = 0.0;
-    for (int64_t p = row_ptr[t]; p < row_ptr[t + 1]; ++p) {
-      const double* row = rows + (size_t)p * NP;
-      const double* c = C + (size_t)pair_tri[p] * NP * R + r;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_tgt * R; g += stride) {
+    const int64_t t = g / R, r = g - t * R;
+    double u = 0.0;
+    for (int64_t s = 0; s < n_split; ++s) u += partial[((size_t)s * n_tgt + t) * R + r];
+    if (!far_only) {
+      double corr = 0.0;
+      for (int64_t p = row_ptr[t]; p < row_ptr[t + 1]; ++p) {
+        const double* row = rows + (size_t)p * NP;
+        const double* c = C + (size_t)pair_tri[p] * NP * R + r;
 #pragma unroll
-      for (int k = 0; k < NP; ++k) corr = fma(row[k], c[(size_t)k * R], corr);
+        for (int k = 0; k < NP; ++k) corr = fma(row[k], c[(size_t)k * R], corr);
+      }
+      u += corr;
     }
-    u += corr;
+    U[g] = u;
   }
-  U[g] = u;
 }
 
 }  // namespace
@@ -164,23 +226,32 @@ hipError_t launch_coefficients(const vp_plan* pl, const double* F, int64_t R, do
   return hipGetLastError();
 }
 
+int64_t far_targets_per_block() { return kBlock * kFarTPT; }
+
 hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, int64_t n_split, double* partial,
-                      hipStream_t st) {
-  const int64_t NT = pl->n_tgt, NS = pl->n_src;
+                      hipStream_t st, int64_t* n_launches) {
+  const int64_t NT = pl->n_tgt, NS = pl->n_src_pad;
   if (NT == 0) return hipSuccess;
   int64_t per = (NS + n_split - 1) / n_split;
-  per = ((per + kBlock - 1) / kBlock) * kBlock;
-  dim3 grid(blocks_for(NT), (unsigned)n_split);
+  per = ((per + 255) / 256) * 256;
+  const int64_t n_tb = (NT + kBlock * kFarTPT - 1) / (kBlock * kFarTPT);
+  const int64_t nb = n_tb * n_split;
+  if (nb * kBlock >= (1LL << 32)) return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)nb);
   int64_t r0 = 0;
   while (r0 < R) {
     const int64_t left = R - r0;
     const int rb = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+#define VP_FAR(RBV) \
+  k_far<RBV, kFarTPT><<<grid, kBlock, 0, st>>>(pl->sxy, Q, NS, R, r0, pl->xt, pl->yt, NT, per, n_split, pl->logtab, partial)
     switch (rb) {
-      case 8: k_far<8><<<grid, kBlock, 0, st>>>(pl->xs, pl->ys, Q, NS, R, r0, pl->xt, pl->yt, NT, per, partial); break;
-      case 4: k_far<4><<<grid, kBlock, 0, st>>>(pl->xs, pl->ys, Q, NS, R, r0, pl->xt, pl->yt, NT, per, partial); break;
-      case 2: k_far<2><<<grid, kBlock, 0, st>>>(pl->xs, pl->ys, Q, NS, R, r0, pl->xt, pl->yt, NT, per, partial); break;
-      default: k_far<1><<<grid, kBlock, 0, st>>>(pl->xs, pl->ys, Q, NS, R, r0, pl->xt, pl->yt, NT, per, partial); break;
+      case 8: VP_FAR(8); break;
+      case 4: VP_FAR(4); break;
+      case 2: VP_FAR(2); break;
+      default: VP_FAR(1); break;
     }
+#undef VP_FAR
+    if (n_launches) ++*n_launches;
     r0 += rb;
   }
   return hipGetLastError();

@@ -88,14 +88,6 @@ __device__ __forceinline__ void koornwinder_emit(double x, double y, Emit&& emit
   }
 }
 
-// ---------------------------------------------------------------------------
-// Device-side objects
-// ---------------------------------------------------------------------------
-struct DevBuf {
-  void* ptr = nullptr;
-  size_t bytes = 0;
-};
-
 }  // namespace vp
 
 struct vp_ctx {
@@ -104,6 +96,16 @@ struct vp_ctx {
   uint64_t budget = 0;
   uint64_t in_use = 0;
   int live_meshes = 0;
+  // profiling: pending event pairs per stage, folded into the totals on read
+  bool profile = false;
+  struct Pending {
+    int stage;
+    hipEvent_t a, b;
+    int64_t launches;
+  };
+  std::vector<Pending> pending;
+  double ms[VP_N_STAGES] = {0, 0, 0, 0, 0};
+  int64_t launches[VP_N_STAGES] = {0, 0, 0, 0, 0};
 };
 
 struct vp_mesh {
@@ -142,7 +144,9 @@ struct vp_plan {
   int n_r = 0;
   double far_what[3] = {0, 0, 0}, near_what[3] = {0, 0, 0};
   // sources and targets (device)
-  double *xs = nullptr, *ys = nullptr;  // [n_src]
+  int64_t n_src_pad = 0;                // n_src rounded up to a multiple of 256
+  double2* sxy = nullptr;               // [n_src_pad] source positions
+  double2* logtab = nullptr;            // [65] table of the far-field logarithm
   double *xt = nullptr, *yt = nullptr;  // [n_tgt]
   // pair list (device)
   int64_t* row_ptr = nullptr;  // [n_tgt+1]
@@ -175,9 +179,11 @@ hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t s
 hipError_t launch_coefficients(const vp_plan* pl, const double* F, int64_t R, double* C, double* Q,
                                hipStream_t st);
 hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, int64_t n_split, double* partial,
-                      hipStream_t st);
+                      hipStream_t st, int64_t* n_launches = nullptr);
 hipError_t launch_finish(const vp_plan* pl, const double* partial, int64_t n_split, const double* C,
                          int64_t R, bool far_only, double* U, hipStream_t st);
+int64_t far_targets_per_block();
+void log_table(double2 out[65]);
 hipError_t exclusive_scan_i32(const int32_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t st);
 size_t exclusive_scan_tmp_bytes(int64_t n);
 

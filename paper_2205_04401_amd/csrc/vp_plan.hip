@@ -140,19 +140,23 @@ __global__ void k_basis_at(const double* __restrict__ x, const double* __restric
   koornwinder_emit<P>(x[j], y[j], [&](int k, double v) { row[k] = v; });
 }
 
-// far sources: node j of triangle t at A + xi_1 (B-A) + xi_2 (C-A)
+// far sources: node j of triangle t at A + xi_1 (B-A) + xi_2 (C-A); the
+// padding entries past n_tri * nf sit at the origin (their charge is 0)
 __global__ void k_sources(const double* __restrict__ ax, const double* __restrict__ ay,
                           const double* __restrict__ bx, const double* __restrict__ by,
                           const double* __restrict__ cx, const double* __restrict__ cy,
                           const double* __restrict__ fx, const double* __restrict__ fy, int nf, int64_t n_tri,
-                          double* xs, double* ys) {
+                          int64_t n_pad, double2* sxy) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_tri * nf) return;
+  if (i >= n_pad) return;
+  if (i >= n_tri * nf) {
+    sxy[i] = make_double2(0.0, 0.0);
+    return;
+  }
   int64_t t = i / nf;
   int j = (int)(i - t * nf);
   double a0 = ax[t], a1 = ay[t];
-  xs[i] = a0 + fx[j] * (bx[t] - a0) + fy[j] * (cx[t] - a0);
-  ys[i] = a1 + fx[j] * (by[t] - a1) + fy[j] * (cy[t] - a1);
+  sxy[i] = make_double2(a0 + fx[j] * (bx[t] - a0) + fy[j] * (cx[t] - a0), a1 + fx[j] * (by[t] - a1) + fy[j] * (cy[t] - a1));
 }
 
 // ---------------------------------------------------------------------------
@@ -503,10 +507,10 @@ hipError_t launch_basis_tables(vp_plan* pl, double* scratch, hipStream_t st) {
 
 hipError_t launch_sources(vp_plan* pl, hipStream_t st) {
   const vp_mesh* m = pl->mesh;
-  int64_t n = pl->n_src;
+  int64_t n = pl->n_src_pad;
   if (n > 0)
     k_sources<<<blocks_for(n), kBlock, 0, st>>>(m->ax, m->ay, m->bx, m->by, m->cx, m->cy, pl->far_x, pl->far_y,
-                                                pl->n_f, pl->n_tri, pl->xs, pl->ys);
+                                                pl->n_f, pl->n_tri, n, pl->sxy);
   return hipGetLastError();
 }
 

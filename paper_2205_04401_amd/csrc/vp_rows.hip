@@ -24,6 +24,7 @@
 //   (a, s/2), (a + s e_1/2, s/2), (a + s e_2/2, s/2), (a + s (e_1+e_2)/2, -s/2)
 // i.e. the three corner triangles and the inverted middle one, each with the
 // vertex order that keeps its orientation and its collapse vertex.
+#include <algorithm>
 #include <cmath>
 
 #include "vp_internal.h"
@@ -91,8 +92,7 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
   __shared__ double lv[2][kCap * 3];
   __shared__ double leaf[kCap * 3];
   const int lane = threadIdx.x;
-  const int64_t pr = blockIdx.x;
-  if (pr >= a.n_pairs) return;
+  for (int64_t pr = blockIdx.x; pr < a.n_pairs; pr += gridDim.x) {
   const int32_t t = a.pair_tri[pr];
   const int32_t it = a.pair_tgt[pr];
   const int kind = a.pair_kind[pr];
@@ -272,6 +272,8 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
     if (n_panels) atomicAdd((unsigned long long*)&a.stats[1], (unsigned long long)n_panels);
     if (n_capped) atomicAdd((unsigned long long*)&a.stats[2], (unsigned long long)n_capped);
   }
+  __syncthreads();
+  }  // pair loop
 }
 
 }  // namespace
@@ -320,10 +322,9 @@ hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t s
   a.rows = pl->rows;
   a.flag = d_flag;
   a.stats = d_stats;
-  // one 64-lane workgroup per pair; the grid's x dimension takes up to 2^31 - 1
-  const int64_t max_grid = 2147483647LL;
-  if (pl->n_pairs > max_grid) return hipErrorInvalidConfiguration;
-  dim3 grid((unsigned)pl->n_pairs);
+  // one 64-lane workgroup per pair, grid-stride beyond 2^20 workgroups (a
+  // launch must stay below 2^32 work-items)
+  dim3 grid((unsigned)std::min<int64_t>(pl->n_pairs, 1 << 20));
   switch (pl->p) {
     case 1: k_rows<1><<<grid, 64, 0, st>>>(a); break;
     case 2: k_rows<2><<<grid, 64, 0, st>>>(a); break;

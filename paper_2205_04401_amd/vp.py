@@ -27,7 +27,9 @@ STATUS_NAMES = {0: "VP_OK", 1: "VP_EINVAL", 2: "VP_ENOMEM", 3: "VP_EDEVICE", 4: 
 # every symbol include/vp.h declares
 EXPORTS = ["vp_ctx_create", "vp_ctx_destroy", "vp_last_error", "vp_ref_nodes", "vp_ref_rule", "vp_mesh_create",
            "vp_mesh_destroy", "vp_plan_create", "vp_plan_info", "vp_plan_pairs", "vp_plan_rows",
-           "vp_execute", "vp_coefficients", "vp_plan_sources", "vp_plan_destroy", "vp_sync"]
+           "vp_execute", "vp_coefficients", "vp_plan_sources", "vp_plan_destroy", "vp_sync",
+           "vp_ctx_profile", "vp_ctx_timings"]
+STAGES = ["classify", "rows", "coef", "far", "finish"]
 
 
 class VPError(RuntimeError):
@@ -38,7 +40,8 @@ class VPError(RuntimeError):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("c_n", ctypes.c_double), ("q_near", ctypes.c_int), ("n_l", ctypes.c_int),
-                ("tau", ctypes.c_double), ("depth_cap", ctypes.c_int), ("dyadic_cap", ctypes.c_int)]
+                ("tau", ctypes.c_double), ("depth_cap", ctypes.c_int), ("dyadic_cap", ctypes.c_int),
+                ("flags", ctypes.c_uint32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -83,6 +86,8 @@ def load(path=LIB_PATH):
         "vp_plan_sources": [P, P],
         "vp_plan_destroy": [P],
         "vp_sync": [P],
+        "vp_ctx_profile": [P, ctypes.c_int],
+        "vp_ctx_timings": [P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -150,6 +155,17 @@ class Context:
     def sync(self):
         _check(load().vp_sync(self.h))
 
+    def profile(self, on=True):
+        """Turn stage timing on/off (resets the accumulators)."""
+        _check(load().vp_ctx_profile(self.h, 1 if on else 0))
+
+    def timings(self):
+        """{stage: (total ms, launches)} accumulated since profile(True)."""
+        ms = np.zeros(len(STAGES))
+        n = np.zeros(len(STAGES), dtype=np.int64)
+        _check(load().vp_ctx_timings(self.h, _ptr(ms), _ptr(n)))
+        return {s: (float(ms[i]), int(n[i])) for i, s in enumerate(STAGES)}
+
     def close(self):
         if self.h:
             _check(load().vp_ctx_destroy(self.h))
@@ -175,8 +191,13 @@ class Mesh:
 class Plan:
     def __init__(self, ctx, mesh, p, q, eps, targets, c_n=1.0, q_near=7, n_l=16, tau=1e-13, depth_cap=50,
                  dyadic_cap=60):
-        tgt = np.ascontiguousarray(np.asarray(targets, dtype=np.float64).reshape(-1, 2))
-        opts = PlanOpts(c_n, q_near, n_l, tau, depth_cap, dyadic_cap)
+        if _is_device(targets):
+            tgt = targets.contiguous()
+            flags = VP_DEVICE_PTRS
+        else:
+            tgt = np.ascontiguousarray(np.asarray(targets, dtype=np.float64).reshape(-1, 2))
+            flags = 0
+        opts = PlanOpts(c_n, q_near, n_l, tau, depth_cap, dyadic_cap, flags)
         h = P()
         _check(load().vp_plan_create(ctx.h, mesh.h, p, q, eps, tgt.shape[0], _ptr(tgt), ctypes.byref(opts),
                                      ctypes.byref(h)))
