@@ -69,7 +69,9 @@ typedef enum {
 
 typedef enum {
   VP_FP64 = 0,   /* all per-solve arithmetic in double */
-  VP_MIXED = 1   /* reserved: FP32 far field / corrections (returns VP_ENOTSUP) */
+  VP_MIXED = 1   /* far-field sum in FP32 (differences rounded from FP64, hardware
+                    log2, FP32 sums per 256-source tile joined in FP64); the
+                    correction rows stay FP64.  Relative error ~1e-7. */
 } vp_precision;
 
 /* vp_execute flags */
@@ -175,7 +177,7 @@ vp_status vp_plan_rows(const vp_plan* plan, double* rows_out);
 /* Evaluate the potential for n_rhs >= 1 densities at once.
  *   density [n_tri][n_p][n_rhs] doubles (values at the interpolation nodes,
  *           right-hand side fastest), u_out [n_tgt][n_rhs] doubles.
- *   prec    VP_FP64.
+ *   prec    VP_FP64 or VP_MIXED.
  *   flags   VP_DEVICE_PTRS | VP_FAR_ONLY | VP_ASYNC.
  * Steps: per-triangle coefficients c = V^{-1} F (Sec. 2.2) and far charges,
  * the direct far sum over all sources, then the correction rows applied to

@@ -55,7 +55,9 @@ void free_plan_memory(vp_plan* pl) {
   double* ws[] = {pl->ws_f, pl->ws_c, pl->ws_q, pl->ws_part, pl->ws_u};
   for (double* p : ws)
     if (p) (void)hipFree(p);
+  if (pl->ws_q32) (void)hipFree(pl->ws_q32);
   pl->ws_f = pl->ws_c = pl->ws_q = pl->ws_part = pl->ws_u = nullptr;
+  pl->ws_q32 = nullptr;
 }
 
 struct PlanGuard {
@@ -411,9 +413,9 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
   // sources and targets
   pl->n_src_pad = ((pl->n_src + 255) / 256) * 256;
   {
-    double2 lt[65];
+    double2 lt[vp::kLogTab + 1];
     vp::log_table(lt);
-    if ((e = plan_alloc(pl, (void**)&pl->logtab, sizeof(double2) * 65)) != hipSuccess ||
+    if ((e = plan_alloc(pl, (void**)&pl->logtab, sizeof(lt))) != hipSuccess ||
         (e = hipMemcpyAsync(pl->logtab, lt, sizeof(lt), hipMemcpyHostToDevice, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
       return hip_fail(e, "vp_plan_create: log table");
@@ -595,7 +597,9 @@ vp_status ensure_workspace(vp_plan* pl, int64_t R) {
   double* ws[] = {pl->ws_f, pl->ws_c, pl->ws_q, pl->ws_part, pl->ws_u};
   for (double* p : ws)
     if (p) (void)hipFree(p);
+  if (pl->ws_q32) (void)hipFree(pl->ws_q32);
   pl->ws_f = pl->ws_c = pl->ws_q = pl->ws_part = pl->ws_u = nullptr;
+  pl->ws_q32 = nullptr;
   pl->ctx->in_use -= pl->ws_bytes;
   pl->ws_bytes = 0;
   pl->ws_rhs = 0;
@@ -603,7 +607,7 @@ vp_status ensure_workspace(vp_plan* pl, int64_t R) {
   const size_t nQ = (size_t)pl->n_src_pad * R;
   const size_t nP = (size_t)split * pl->n_tgt * R;
   const size_t nU = (size_t)pl->n_tgt * R;
-  const size_t bytes = 8 * (2 * nF + nQ + nP + nU) + 5 * 8;
+  const size_t bytes = 8 * (2 * nF + nQ + nP + nU) + 4 * nQ + 6 * 8;
   if (pl->ctx->budget && pl->ctx->in_use + bytes > pl->ctx->budget)
     return fail(VP_ENOMEM, "vp_execute: workspace of %zu bytes exceeds the HBM budget", bytes);
   hipError_t e;
@@ -612,6 +616,7 @@ vp_status ensure_workspace(vp_plan* pl, int64_t R) {
       (e = hipMalloc((void**)&pl->ws_q, 8 * std::max<size_t>(nQ, 1))) != hipSuccess ||
       (e = hipMalloc((void**)&pl->ws_part, 8 * std::max<size_t>(nP, 1))) != hipSuccess ||
       (e = hipMalloc((void**)&pl->ws_u, 8 * std::max<size_t>(nU, 1))) != hipSuccess ||
+      (e = hipMalloc((void**)&pl->ws_q32, 4 * std::max<size_t>(nQ, 1))) != hipSuccess ||
       (e = hipMemsetAsync(pl->ws_q, 0, 8 * std::max<size_t>(nQ, 1), pl->ctx->stream)) != hipSuccess) {
     return hip_fail(e, "vp_execute: workspace");
   }
@@ -630,7 +635,7 @@ vp_status vp_execute(vp_plan* pl, int64_t R, const double* density, double* u_ou
                      uint32_t flags) {
   if (!pl) return fail(VP_EINVAL, "vp_execute: plan is NULL");
   if (R < 1) return fail(VP_EINVAL, "vp_execute: n_rhs must be >= 1");
-  if (prec != VP_FP64) return fail(VP_ENOTSUP, "vp_execute: only VP_FP64 is available");
+  if (prec != VP_FP64 && prec != VP_MIXED) return fail(VP_EINVAL, "vp_execute: unknown precision %d", (int)prec);
   if ((!density && pl->n_tri) || (!u_out && pl->n_tgt)) return fail(VP_EINVAL, "vp_execute: NULL array");
   const bool dev = flags & VP_DEVICE_PTRS;
   if ((flags & VP_ASYNC) && !dev) return fail(VP_EINVAL, "vp_execute: VP_ASYNC needs VP_DEVICE_PTRS");
@@ -654,7 +659,9 @@ vp_status vp_execute(vp_plan* pl, int64_t R, const double* density, double* u_ou
   {
     StageTimer tm(ctx, VP_STAGE_FAR);
     int64_t nl = 0;
-    VP_HIP(vp::launch_far(pl, pl->ws_q, R, pl->ws_split, pl->ws_part, st, &nl), "vp_execute: far field");
+    VP_HIP(vp::launch_far(pl, pl->ws_q, R, pl->ws_split, pl->ws_part, st, &nl,
+                          prec == VP_MIXED ? pl->ws_q32 : nullptr),
+           "vp_execute: far field");
     tm.stop(nl);
   }
   {

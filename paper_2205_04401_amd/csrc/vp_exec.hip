@@ -17,7 +17,10 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr double kInv4Pi = 0.07957747154594766788;
-constexpr int kFarTPT = 2;  // targets per thread in the far sum
+#ifndef VP_FAR_TPT
+#define VP_FAR_TPT 2
+#endif
+constexpr int kFarTPT = VP_FAR_TPT;  // targets per thread in the far sum
 
 // Grid of a grid-stride launch: at most 2^20 blocks, so that a launch stays
 // far below 2^32 work-items.
@@ -70,35 +73,6 @@ __global__ void k_charges(const double* __restrict__ C, const double* __restrict
   }
 }
 
-// Natural logarithm of x > 0 (normal) in FP64, table-driven (Tang's
-// method): x = m 2^e with m in [1/2, 1); the top six fraction bits select a
-// sub-interval of width 1/128 with centre c_i; with inv_c_i the double
-// nearest 1/c_i, r = m inv_c_i - 1 (|r| <= 1/128) comes from one FMA and
-//   log x = e ln2 - log(inv_c_i) + log1p(r),
-// with log1p(r) from its Taylor series through r^7 (truncation < 2e-18).
-// tab[i] = {inv_c_i, -log(inv_c_i)} for i < 64 and tab[64] = {ln2_hi,
-// ln2_lo}, ln2_hi holding 32 bits so that e ln2_hi is exact.  Error: a few
-// units in the last place of the result.  x = 0 gives a finite value
-// (callers mask it); subnormal x is not supported.
-__device__ __forceinline__ double vp_log(double x, const double2* tab) {
-  const unsigned hi = (unsigned)__double2hiint(x);
-  const int lo = __double2loint(x);
-  const unsigned i = (hi >> 14) & 63u;
-  const double ed = (double)((int)(hi >> 20) - 1022);
-  const double m = __hiloint2double((int)((hi & 0x000FFFFFu) | 0x3FE00000u), lo);
-  const double2 t = tab[i];
-  const double2 l2 = tab[64];
-  const double r = fma(m, t.x, -1.0);
-  double p = fma(r, 1.0 / 7.0, -1.0 / 6.0);
-  p = fma(r, p, 1.0 / 5.0);
-  p = fma(r, p, -0.25);
-  p = fma(r, p, 1.0 / 3.0);
-  p = fma(r, p, -0.5);
-  p = fma(r, p, 1.0);
-  p = p * r;
-  return fma(ed, l2.x, t.y) + fma(ed, l2.y, p);
-}
-
 // Direct far sum.  Each thread owns TPT targets (strided by the block
 // size); the sources are read with wavefront-uniform addresses (scalar
 // loads), RB right-hand sides share one logarithm per pair.  A linear block
@@ -113,8 +87,8 @@ __global__ __launch_bounds__(kBlock) void k_far(const double2* __restrict__ sxy,
                                                 const double* __restrict__ xt, const double* __restrict__ yt,
                                                 int64_t n_tgt, int64_t per_split, int64_t n_split,
                                                 const double2* __restrict__ logtab, double* __restrict__ partial) {
-  __shared__ double2 tab[65];
-  if (threadIdx.x < 65) tab[threadIdx.x] = logtab[threadIdx.x];
+  __shared__ double2 tab[kLogTab + 1];
+  for (int i = threadIdx.x; i <= kLogTab; i += blockDim.x) tab[i] = logtab[i];
   __syncthreads();
   const int64_t b = blockIdx.x;
   const int64_t chunk = b % n_split, tb = b / n_split;
@@ -170,6 +144,79 @@ __global__ __launch_bounds__(kBlock) void k_far(const double2* __restrict__ sxy,
 #pragma unroll
       for (int r = 0; r < RB; ++r) partial[((size_t)chunk * n_tgt + t[k]) * R + r0 + r] = acc[k][r];
     }
+}
+
+// Mixed-precision far sum (same decomposition as k_far): the pair
+// difference is taken in FP64 and rounded to FP32, r^2 and the base-2
+// logarithm (the hardware v_log_f32) are FP32, the charges are FP32 with ln 2
+// folded in (Q32 = Q ln 2, so Q32 log2(r^2) = Q log(r^2)), each 256-source
+// tile is summed in FP32 and the tiles are summed in FP64.
+template <int RB, int TPT>
+__global__ __launch_bounds__(kBlock) void k_far32(const double2* __restrict__ sxy, const float* __restrict__ Q32,
+                                                  int64_t n_src_pad, int64_t R, int64_t r0,
+                                                  const double* __restrict__ xt, const double* __restrict__ yt,
+                                                  int64_t n_tgt, int64_t per_split, int64_t n_split,
+                                                  double* __restrict__ partial) {
+  const int64_t b = blockIdx.x;
+  const int64_t chunk = b % n_split, tb = b / n_split;
+  double x[TPT], y[TPT];
+  int64_t t[TPT];
+#pragma unroll
+  for (int k = 0; k < TPT; ++k) {
+    t[k] = tb * (kBlock * TPT) + k * kBlock + threadIdx.x;
+    const bool act = t[k] < n_tgt;
+    x[k] = act ? xt[t[k]] : 0.0;
+    y[k] = act ? yt[t[k]] : 0.0;
+  }
+  const int64_t s_begin = chunk * per_split;
+  const int64_t s_end = min(n_src_pad, s_begin + per_split);
+  double acc[TPT][RB];
+#pragma unroll
+  for (int k = 0; k < TPT; ++k)
+#pragma unroll
+    for (int r = 0; r < RB; ++r) acc[k][r] = 0.0;
+  for (int64_t j0 = s_begin; j0 < s_end; j0 += 256) {
+    const int64_t j1 = min(s_end, j0 + 256);
+    float tile[TPT][RB];
+#pragma unroll
+    for (int k = 0; k < TPT; ++k)
+#pragma unroll
+      for (int r = 0; r < RB; ++r) tile[k][r] = 0.0f;
+    for (int64_t j = j0; j < j1; j += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double2 s = sxy[j + u];
+        float q[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) q[r] = Q32[(j + u) * R + r0 + r];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+          const float dx = (float)(x[k] - s.x), dy = (float)(y[k] - s.y);
+          const float r2 = fmaf(dx, dx, dy * dy);
+          float lg = __builtin_amdgcn_logf(r2);
+          lg = (r2 > 0.0f) ? lg : 0.0f;
+#pragma unroll
+          for (int r = 0; r < RB; ++r) tile[k][r] = fmaf(q[r], lg, tile[k][r]);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < TPT; ++k)
+#pragma unroll
+      for (int r = 0; r < RB; ++r) acc[k][r] += (double)tile[k][r];
+  }
+#pragma unroll
+  for (int k = 0; k < TPT; ++k)
+    if (t[k] < n_tgt) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r) partial[((size_t)chunk * n_tgt + t[k]) * R + r0 + r] = acc[k][r];
+    }
+}
+
+__global__ void k_to_f32_ln2(const double* __restrict__ Q, int64_t n, float* __restrict__ Q32) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    Q32[i] = (float)(Q[i] * 0.69314718055994530942);
 }
 
 // one thread per (target, rhs)
@@ -229,7 +276,7 @@ hipError_t launch_coefficients(const vp_plan* pl, const double* F, int64_t R, do
 int64_t far_targets_per_block() { return kBlock * kFarTPT; }
 
 hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, int64_t n_split, double* partial,
-                      hipStream_t st, int64_t* n_launches) {
+                      hipStream_t st, int64_t* n_launches, float* Q32) {
   const int64_t NT = pl->n_tgt, NS = pl->n_src_pad;
   if (NT == 0) return hipSuccess;
   int64_t per = (NS + n_split - 1) / n_split;
@@ -238,12 +285,18 @@ hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, int64_t n_s
   const int64_t nb = n_tb * n_split;
   if (nb * kBlock >= (1LL << 32)) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)nb);
+  if (Q32) k_to_f32_ln2<<<blocks_for(NS * R), kBlock, 0, st>>>(Q, NS * R, Q32);
   int64_t r0 = 0;
   while (r0 < R) {
     const int64_t left = R - r0;
     const int rb = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
-#define VP_FAR(RBV) \
-  k_far<RBV, kFarTPT><<<grid, kBlock, 0, st>>>(pl->sxy, Q, NS, R, r0, pl->xt, pl->yt, NT, per, n_split, pl->logtab, partial)
+#define VP_FAR(RBV)                                                                                             \
+  if (Q32)                                                                                                      \
+    k_far32<RBV, kFarTPT><<<grid, kBlock, 0, st>>>(pl->sxy, Q32, NS, R, r0, pl->xt, pl->yt, NT, per, n_split, \
+                                                   partial);                                                    \
+  else                                                                                                          \
+    k_far<RBV, kFarTPT><<<grid, kBlock, 0, st>>>(pl->sxy, Q, NS, R, r0, pl->xt, pl->yt, NT, per, n_split,     \
+                                                 pl->logtab, partial)
     switch (rb) {
       case 8: VP_FAR(8); break;
       case 4: VP_FAR(4); break;

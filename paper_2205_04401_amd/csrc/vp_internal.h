@@ -88,6 +88,33 @@ __device__ __forceinline__ void koornwinder_emit(double x, double y, Emit&& emit
   }
 }
 
+// Natural logarithm of x > 0 (normal) in FP64, table-driven (Tang's
+// method): x = m 2^e with m in [1/2, 1); the top eight fraction bits select
+// a sub-interval of width 1/512 with centre c_i; with inv_c_i the double
+// nearest 1/c_i, r = m inv_c_i - 1 (|r| <= 1/512) comes from one FMA and
+//   log x = e ln2 - log(inv_c_i) + log1p(r),
+// with log1p(r) from its Taylor series through r^5 (truncation < 1e-17).
+// tab[i] = {inv_c_i, -log(inv_c_i)} for i < 256 and tab[256] = {ln2_hi,
+// ln2_lo}, ln2_hi holding 32 bits so that e ln2_hi is exact.  Error: a few
+// units in the last place of the result.  x = 0 gives a finite value
+// (callers mask it); subnormal x is not supported.
+constexpr int kLogTab = 256;
+__device__ __forceinline__ double vp_log(double x, const double2* tab) {
+  const unsigned hi = (unsigned)__double2hiint(x);
+  const int lo = __double2loint(x);
+  const unsigned i = (hi >> 12) & 255u;
+  const double ed = (double)((int)(hi >> 20) - 1022);
+  const double m = __hiloint2double((int)((hi & 0x000FFFFFu) | 0x3FE00000u), lo);
+  const double2 t = tab[i];
+  const double2 l2 = tab[kLogTab];
+  const double r = fma(m, t.x, -1.0);
+  double p = fma(r, 0.2, -0.25);
+  p = fma(r, p, 1.0 / 3.0);
+  p = fma(r, p, -0.5);
+  p = fma(r * r, p, r);
+  return fma(ed, l2.x, t.y) + fma(ed, l2.y, p);
+}
+
 }  // namespace vp
 
 struct vp_ctx {
@@ -146,7 +173,7 @@ struct vp_plan {
   // sources and targets (device)
   int64_t n_src_pad = 0;                // n_src rounded up to a multiple of 256
   double2* sxy = nullptr;               // [n_src_pad] source positions
-  double2* logtab = nullptr;            // [65] table of the far-field logarithm
+  double2* logtab = nullptr;            // [kLogTab + 1] table of the FP64 logarithm
   double *xt = nullptr, *yt = nullptr;  // [n_tgt]
   // pair list (device)
   int64_t* row_ptr = nullptr;  // [n_tgt+1]
@@ -158,6 +185,7 @@ struct vp_plan {
   int64_t ws_rhs = 0;
   int64_t ws_split = 0;
   double *ws_f = nullptr, *ws_c = nullptr, *ws_q = nullptr, *ws_part = nullptr, *ws_u = nullptr;
+  float* ws_q32 = nullptr;
   size_t ws_bytes = 0;
   std::vector<void*> allocs;  // everything above except the workspace
   size_t bytes = 0;
@@ -178,12 +206,14 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err);  // near-
 hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t st);
 hipError_t launch_coefficients(const vp_plan* pl, const double* F, int64_t R, double* C, double* Q,
                                hipStream_t st);
+// Q32 != nullptr selects the mixed-precision far sum (Q32: [n_src_pad][R]
+// scratch for the FP32 charges).
 hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, int64_t n_split, double* partial,
-                      hipStream_t st, int64_t* n_launches = nullptr);
+                      hipStream_t st, int64_t* n_launches = nullptr, float* Q32 = nullptr);
 hipError_t launch_finish(const vp_plan* pl, const double* partial, int64_t n_split, const double* C,
                          int64_t R, bool far_only, double* U, hipStream_t st);
 int64_t far_targets_per_block();
-void log_table(double2 out[65]);
+void log_table(double2 out[kLogTab + 1]);
 hipError_t exclusive_scan_i32(const int32_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t st);
 size_t exclusive_scan_tmp_bytes(int64_t n);
 

@@ -530,7 +530,7 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
   e = alloc((void**)&pl->row_ptr, sizeof(int64_t) * (NT + 1));
   if (e != hipSuccess) return e;
   if (NT == 0 || T == 0) {
-    e = hipMemsetAsync(pl->row_ptr, 0, sizeof(int64_t) * (NT + 1), st);
+    if ((e = hipMemsetAsync(pl->row_ptr, 0, sizeof(int64_t) * (NT + 1), st)) != hipSuccess) return e;
     pl->n_pairs = 0;
     pl->n_self = 0;
     e = alloc((void**)&pl->pair_tri, 4);
@@ -606,12 +606,15 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
     cleanup();
     return e;
   }
-  hipMemsetAsync(ccnt, 0, sizeof(int32_t) * nc, st);
-  hipMemsetAsync(cfill, 0, sizeof(int32_t) * nc, st);
+  if ((e = hipMemsetAsync(ccnt, 0, sizeof(int32_t) * nc, st)) != hipSuccess ||
+      (e = hipMemsetAsync(cfill, 0, sizeof(int32_t) * nc, st)) != hipSuccess) {
+    cleanup();
+    return e;
+  }
   k_cell_count<<<blocks_for(T), kBlock, 0, st>>>(box, T, g, ccnt);
-  exclusive_scan_i32(ccnt, cptr, nc, stmp, st);
   int64_t n_entries = 0;
-  if ((e = hipMemcpyAsync(&n_entries, cptr + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+  if ((e = exclusive_scan_i32(ccnt, cptr, nc, stmp, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(&n_entries, cptr + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess) {
     cleanup();
     return e;
@@ -624,8 +627,7 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
   k_cell_sort<<<blocks_for(nc), kBlock, 0, st>>>(cptr, nc, ctri);
   TriView tv{m->ax, m->ay, m->bx, m->by, m->cx, m->cy, m->det, thr, T};
   k_pair_count<<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, tv, pl->opts.tau, pcnt);
-  exclusive_scan_i32(pcnt, pl->row_ptr, NT, stmp, st);
-  if ((e = hipGetLastError()) != hipSuccess) {
+  if ((e = exclusive_scan_i32(pcnt, pl->row_ptr, NT, stmp, st)) != hipSuccess) {
     cleanup();
     return e;
   }
@@ -650,7 +652,10 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
   k_pair_fill<<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, tv, pl->opts.tau, pl->row_ptr,
                                                  pl->pair_tri, pl->pair_tgt, pl->pair_kind, scnt);
   unsigned long long* d_sum = (unsigned long long*)part;
-  hipMemsetAsync(d_sum, 0, sizeof(unsigned long long), st);
+  if ((e = hipMemsetAsync(d_sum, 0, sizeof(unsigned long long), st)) != hipSuccess) {
+    cleanup();
+    return e;
+  }
   k_count_sum<<<blocks_for(NT), kBlock, 0, st>>>(scnt, NT, d_sum);
   unsigned long long ns = 0;
   if ((e = hipGetLastError()) != hipSuccess ||

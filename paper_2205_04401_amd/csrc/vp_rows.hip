@@ -54,27 +54,11 @@ struct RowsArgs {
   int nr;
   double eps_cn, tau;
   int depth_cap, dyadic_cap;
+  const double2* logtab;
   double* rows;
   int* flag;
   int64_t* stats;  // near leaves, self panels, capped leaves
 };
-
-__device__ __forceinline__ bool outside_ellipses(double x, double y, double p0x, double p0y, double p1x, double p1y,
-                                                 double p2x, double p2y, double area2, const RowsArgs& a) {
-  const double px[3] = {p0x, p1x, p2x}, py[3] = {p0y, p1y, p2y};
-  const double wh[3] = {a.nwhat0, a.nwhat1, a.nwhat2};
-#pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    const double rho = pow(wh[e] * area2 / a.eps_cn, a.inv_near_order);
-    if (!(rho > 1.0)) continue;
-    const double Px = px[e], Py = py[e], Qx = px[(e + 1) % 3], Qy = py[(e + 1) % 3];
-    const double ell = sqrt((Qx - Px) * (Qx - Px) + (Qy - Py) * (Qy - Py));
-    const double thr = 0.5 * ell * (rho + 1.0 / rho);
-    const double fs = sqrt((x - Px) * (x - Px) + (y - Py) * (y - Py)) + sqrt((x - Qx) * (x - Qx) + (y - Qy) * (y - Qy));
-    if (fs < thr) return false;
-  }
-  return true;
-}
 
 __device__ __forceinline__ int dyadic_count(double len, double d, int cap) {
   int n = 0;
@@ -87,11 +71,14 @@ __device__ __forceinline__ int dyadic_count(double len, double d, int cap) {
 }
 
 template <int P>
-__global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
+__global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
   __shared__ double lv[2][kCap * 3];
   __shared__ double leaf[kCap * 3];
+  __shared__ double2 tab[kLogTab + 1];
   const int lane = threadIdx.x;
+  for (int i = lane; i <= kLogTab; i += kWave) tab[i] = a.logtab[i];
+  __syncthreads();
   for (int64_t pr = blockIdx.x; pr < a.n_pairs; pr += gridDim.x) {
   const int32_t t = a.pair_tri[pr];
   const int32_t it = a.pair_tgt[pr];
@@ -112,7 +99,7 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
     const double yx = Ax + fx * e1x + fy * e2x, yy = Ay + fx * e1y + fy * e2y;
     const double dx = x - yx, dy = y - yy;
     const double r2 = dx * dx + dy * dy;
-    const double w = (r2 > 0.0) ? -0.5 * log(r2) * a.far_w[j] * D : 0.0;
+    const double w = (r2 > 0.0) ? -0.5 * vp_log(r2, tab) * a.far_w[j] * D : 0.0;
     const double* E = a.efar + (size_t)j * NP;
 #pragma unroll
     for (int k = 0; k < NP; ++k) acc[k] = fma(w, E[k], acc[k]);
@@ -121,6 +108,17 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
   int64_t n_leaves = 0, n_panels = 0, n_capped = 0;
   if (kind == 1) {
     // ---- A, near pair: breadth-first subdivision ----
+    // The ellipses of a level-L sub-triangle (|s| = 2^-L, area 4^-L of the
+    // triangle's) have rho_e = rho0_e 2^(-2L/N_n) and edges l_e 2^-L.
+    const double px[3] = {Ax, Bx, Cx}, py[3] = {Ay, By, Cy};
+    const double wh[3] = {a.nwhat0, a.nwhat1, a.nwhat2};
+    double rho0[3], ell0[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      rho0[e] = pow(wh[e] * D / a.eps_cn, a.inv_near_order);
+      const double ex = px[(e + 1) % 3] - px[e], ey = py[(e + 1) % 3] - py[e];
+      ell0[e] = sqrt(ex * ex + ey * ey);
+    }
     double* cur = lv[0];
     double* nxt = lv[1];
     if (lane == 0) {
@@ -132,6 +130,16 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
     int n_cur = 1;
     for (int level = 0; n_cur > 0; ++level) {
       int n_next = 0, n_leaf = 0;
+      double thr[3];
+      {
+        const double f = exp2(-2.0 * level * a.inv_near_order);
+        const double hl = ldexp(0.5, -level);
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+          const double rho = rho0[e] * f;
+          thr[e] = (rho > 1.0) ? hl * ell0[e] * (rho + 1.0 / rho) : -1.0;
+        }
+      }
       for (int base = 0; base < n_cur; base += kWave) {
         const int i = base + lane;
         bool valid = i < n_cur;
@@ -145,7 +153,10 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
           const double p0x = Ax + sa * e1x + sb * e2x, p0y = Ay + sa * e1y + sb * e2y;
           const double p1x = p0x + ss * e1x, p1y = p0y + ss * e1y;
           const double p2x = p0x + ss * e2x, p2y = p0y + ss * e2y;
-          split = (level < a.depth_cap) && !outside_ellipses(x, y, p0x, p0y, p1x, p1y, p2x, p2y, ss * ss * D, a);
+          const double d0 = sqrt((x - p0x) * (x - p0x) + (y - p0y) * (y - p0y));
+          const double d1 = sqrt((x - p1x) * (x - p1x) + (y - p1y) * (y - p1y));
+          const double d2 = sqrt((x - p2x) * (x - p2x) + (y - p2y) * (y - p2y));
+          split = (level < a.depth_cap) && (d0 + d1 < thr[0] || d1 + d2 < thr[1] || d2 + d0 < thr[2]);
         }
         const bool is_leaf = valid && !split;
         const uint64_t msplit = __ballot(split);
@@ -189,7 +200,7 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
         const double xi1 = sa + ss * a.near_x[nd], xi2 = sb + ss * a.near_y[nd];
         const double yx = Ax + xi1 * e1x + xi2 * e2x, yy = Ay + xi1 * e1y + xi2 * e2y;
         const double dx = x - yx, dy = y - yy;
-        const double w = 0.5 * log(dx * dx + dy * dy) * a.near_w[nd] * ss * ss * D;
+        const double w = 0.5 * vp_log(dx * dx + dy * dy, tab) * a.near_w[nd] * ss * ss * D;
         koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { acc[k] = fma(w, v, acc[k]); });
       }
       __syncthreads();
@@ -246,10 +257,10 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
         const double s = s0 + (s1 - s0) * a.gl_s[il];
         const double ws = (s1 - s0) * a.gl_w[il];
         const double gx = Px + s * ux, gy = Py + s * uy;
-        const double r0 = sqrt((gx - x) * (gx - x) + (gy - y) * (gy - y));
+        const double r0sq = (gx - x) * (gx - x) + (gy - y) * (gy - y);
         const double rr = a.rad_r[ir];
         const double px = x + rr * (gx - x), py = y + rr * (gy - y);
-        const double w = h * ws * (a.rad_a[ir] * log(r0) + a.rad_b[ir]);
+        const double w = h * ws * (a.rad_a[ir] * 0.5 * vp_log(r0sq, tab) + a.rad_b[ir]);
         const double dx = px - Ax, dy = py - Ay;
         const double xi1 = (dx * e2y - dy * e2x) * invD;
         const double xi2 = (e1x * dy - e1y * dx) * invD;
@@ -319,12 +330,14 @@ hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t s
   a.tau = pl->opts.tau;
   a.depth_cap = pl->opts.depth_cap;
   a.dyadic_cap = pl->opts.dyadic_cap;
+  a.logtab = pl->logtab;
   a.rows = pl->rows;
   a.flag = d_flag;
   a.stats = d_stats;
-  // one 64-lane workgroup per pair, grid-stride beyond 2^20 workgroups (a
-  // launch must stay below 2^32 work-items)
-  dim3 grid((unsigned)std::min<int64_t>(pl->n_pairs, 1 << 20));
+  // one 64-lane workgroup per pair (the dispatcher balances the uneven
+  // pairs), grid-stride beyond 2^25 workgroups (a launch must stay below
+  // 2^32 work-items)
+  dim3 grid((unsigned)std::min<int64_t>(pl->n_pairs, 1 << 25));
   switch (pl->p) {
     case 1: k_rows<1><<<grid, 64, 0, st>>>(a); break;
     case 2: k_rows<2><<<grid, 64, 0, st>>>(a); break;

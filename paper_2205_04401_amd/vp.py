@@ -246,7 +246,7 @@ class Plan:
             raise VPError(VP_EINVAL, f"density shape {F.shape} != ({self.n_tri}, {self.n_p}, R)")
         return np.ascontiguousarray(F), F.shape[2], False
 
-    def execute(self, F, far_only=False, out=None, asynchronous=False):
+    def execute(self, F, far_only=False, out=None, asynchronous=False, mixed=False):
         """u [n_tgt] (one density) or [n_tgt, R].  Device tensors in ->
         device tensor out (written into `out` if given)."""
         single = (F.ndim if hasattr(F, "ndim") else F.dim()) == 2
@@ -259,7 +259,7 @@ class Plan:
             flags |= VP_DEVICE_PTRS | (VP_ASYNC if asynchronous else 0)
         else:
             out = np.empty((self.n_tgt, R))
-        _check(load().vp_execute(self.h, R, _ptr(Fc), _ptr(out), VP_FP64, flags))
+        _check(load().vp_execute(self.h, R, _ptr(Fc), _ptr(out), VP_MIXED if mixed else VP_FP64, flags))
         return out[:, 0] if single else out
 
     def coefficients(self, F):

@@ -158,6 +158,19 @@ def test_c1_end_to_end(c1):
     assert err <= REL_E2E
 
 
+REL_MIXED = 1e-6
+
+
+def test_c1_mixed_precision(c1):
+    """Mixed path (FP32 far sum, FP64 rows) against the FP64 oracle."""
+    u = c1["plan"].execute(c1["F"], mixed=True)
+    err = rel_linf(u, c1["u"])
+    say("c1 mixed rel", err)
+    assert err <= REL_MIXED
+    u_far = c1["plan"].execute(c1["F"], mixed=True, far_only=True)
+    assert rel_linf(u_far, c1["u_far"]) <= REL_MIXED
+
+
 def test_c1_multi_rhs_and_device_pointers(c1):
     import torch
     F3 = np.stack([c1["F"], 2.0 * c1["F"] - 1.0, np.sin(c1["F"])], -1)
@@ -270,10 +283,9 @@ def test_error_paths(vp_ctx):
     with pytest.raises(vp.VPError) as e:  # n_rhs = 0
         vp._check(vp.load().vp_execute(plan.h, 0, None, None, vp.VP_FP64, 0))
     assert e.value.status == vp.VP_EINVAL
-    with pytest.raises(vp.VPError) as e:  # mixed precision is not built yet
-        vp._check(vp.load().vp_execute(plan.h, 1, vp._ptr(np.ones((len(tq), 6))), vp._ptr(np.zeros(1)),
-                                       vp.VP_MIXED, 0))
-    assert e.value.status == vp.VP_ENOTSUP
+    with pytest.raises(vp.VPError) as e:  # unknown precision
+        vp._check(vp.load().vp_execute(plan.h, 1, vp._ptr(np.ones((len(tq), 6))), vp._ptr(np.zeros(1)), 7, 0))
+    assert e.value.status == vp.VP_EINVAL
     plan.close()
     mesh.close()
     small = vp.Context(0, hbm_budget_bytes=4096)
@@ -288,6 +300,27 @@ def test_error_paths(vp_ctx):
 # ---------------------------------------------------------------------------
 # full-size star (the benchmark's workload): sampled targets vs the oracle
 # ---------------------------------------------------------------------------
+
+def test_star_mixed_loose_eps_plan(vp_ctx):
+    """A mixed-precision plan with eps = 1e-8 (smaller near field) still meets
+    1e-6 against the FP64, eps = 1e-13 oracle."""
+    p, q = 6, 6
+    vq, tq = W.star_mesh(n_tri=20000, seed=20)
+    vt, tt = W.star_mesh(n_tri=20000, seed=21, staggered=True)
+    nodes = rules.interp_nodes(p)
+    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    F = W.sample_density(W.gaussian_sum(22, vq, tq), vq, tq, nodes)
+    mesh = vp_ctx.mesh(vq, tq)
+    plan = vp_ctx.plan(mesh, p, q, 1e-8, tg)
+    u = plan.execute(F, mixed=True)
+    rng = np.random.default_rng(99)
+    sample = np.sort(rng.choice(len(tg), 12, replace=False))
+    ref = potential.Oracle(vq, tq, p, q, 1e-13).evaluate(F, tg[sample])
+    err = np.abs(u[sample] - ref).max() / np.abs(ref).max()
+    say("star mixed eps=1e-8 plan: pairs/target", plan.info()["n_pairs"] / len(tg), "rel", err)
+    assert err <= REL_MIXED
+    plan.close()
+    mesh.close()
 
 @pytest.mark.parametrize("q", [8, 4])
 def test_star_full_size_sampled(vp_ctx, q):
@@ -315,8 +348,11 @@ def test_star_full_size_sampled(vp_ctx, q):
     ref_u, ref_far, _, _ = o.evaluate(F, tg[sample], return_parts=True)
     e_far = np.abs(u_far[sample] - ref_far).max() / np.abs(ref_far).max()
     e_all = np.abs(u[sample] - ref_u).max() / np.abs(ref_u).max()
-    say("star sampled rel far", e_far, "end-to-end", e_all)
+    u_mix = plan.execute(F, mixed=True)
+    e_mix = np.abs(u_mix[sample] - ref_u).max() / np.abs(ref_u).max()
+    say("star sampled rel far", e_far, "end-to-end", e_all, "mixed", e_mix)
     assert e_far <= REL_FAR
     assert e_all <= REL_E2E
+    assert e_mix <= REL_MIXED
     plan.close()
     mesh.close()
