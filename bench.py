@@ -110,21 +110,21 @@ def run(args):
     F_d = torch.from_numpy(F).to(dev)
     out = torch.empty((len(tg), 1), dtype=torch.float64, device=dev)
 
-    def step(q):
-        plan = ctx.plan(mesh, p, q, eps, tg_d)
-        plan.execute(F_d, out=out)
+    def step(q, eps_plan=eps, mixed=False):
+        plan = ctx.plan(mesh, p, q, eps_plan, tg_d)
+        plan.execute(F_d, out=out, mixed=mixed)
         info = plan.info()
         plan.close()
         return info
 
-    def measure(q, steps, warmup):
+    def measure(q, steps, warmup, eps_plan=eps, mixed=False):
         for _ in range(warmup):
-            step(q)
+            step(q, eps_plan, mixed)
         torch.cuda.synchronize()
         ctx.profile(True)
         t0 = time.perf_counter()
         for _ in range(steps):
-            info = step(q)
+            info = step(q, eps_plan, mixed)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         tm = ctx.timings()
@@ -191,8 +191,21 @@ def run(args):
         "near_subtri_per_near_pair": info["near_subtri"] / max(1, info["n_pairs"] - info["n_self"]),
         "self_panels_per_self_pair": info["self_panels"] / max(1, info["n_self"]),
     }
+    # mixed precision: FP32 far sum, FP64 rows, plan at eps = 1e-8 (its error
+    # is bounded by 1e-6 against the FP64 eps = 1e-13 oracle in the GPU tests)
+    dt_m, info_m, tm_m = measure(q, args.steps, 1, eps_plan=1e-8, mixed=True)
+    far_m = tm_m["far"][0] / 1e3 / max(tm_m["far"][1], 1)
+    result["mixed"] = {
+        "value": n_tgt / dt_m, "unit": "evals/s", "ms_per_step": dt_m * 1e3, "rel_err_bound": 1e-6,
+        "plan_eps": 1e-8, "far_pairs_per_s": pairs / far_m, "pairs_per_target": info_m["n_pairs"] / n_tgt,
+        "breakdown_ms": {k: v[0] / args.steps for k, v in tm_m.items()},
+        "far_fp32_tflops_8flop": FLOPS_PER_PAIR * pairs / far_m / 1e12,
+    }
     if sweep:
         result["q_sweep"] = sweep
+    if not args.no_serving:
+        from paper_2205_04401_amd import serving
+        result["serving"] = [serving.run(ctx, n_requests=args.serving_requests, mixed=m) for m in (False, True)]
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(vq, tq, tg, F, p, q, eps, args.cpu_sample)
     mesh.close()
@@ -209,6 +222,8 @@ def main():
     ap.add_argument("--sweep", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=160)
     ap.add_argument("--copy-probe", action="store_true", help="only run a 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -219,6 +219,36 @@ typedef enum {
 vp_status vp_ctx_profile(vp_ctx* ctx, int on);
 vp_status vp_ctx_timings(vp_ctx* ctx, double* ms_out /* [VP_N_STAGES] */, int64_t* launches_out /* [VP_N_STAGES] */);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of evaluation requests (the paper evaluates
+ * one right-hand side at a time; this is the device-side scheduling of many).
+ *
+ * A server owns n_slots HIP streams (default priority) and one workspace per
+ * slot.  vp_submit queues a request (a plan, n_rhs densities, an output);
+ * requests start as slots and HBM (the context's budget) free up.  When a
+ * slot frees, the oldest pending request is started together with the other
+ * pending requests for the same plan and precision, packed along the
+ * right-hand-side axis up to max_batch_rhs columns, so they share every
+ * far-field logarithm; requests on different slots overlap on the device.
+ * Progress (completion checks and admission) happens inside vp_submit,
+ * vp_poll and vp_wait.  density [n_tri][n_p][n_rhs] and u_out [n_tgt][n_rhs]
+ * are DEVICE pointers owned by the caller and must stay valid until the
+ * request is done.  A request's result equals vp_execute of the same
+ * arguments up to rounding (the far sum of a column does not depend on the
+ * other columns of its batch).  Errors: VP_EINVAL (bad arguments),
+ * VP_ENOMEM (a request larger than the whole budget), VP_EDEVICE.
+ * ------------------------------------------------------------------------ */
+typedef struct vp_server vp_server;
+typedef int64_t vp_ticket;
+vp_status vp_server_create(vp_ctx* ctx, int n_slots, int max_batch_rhs, vp_server** out);
+vp_status vp_server_destroy(vp_server* srv); /* waits for all requests */
+vp_status vp_submit(vp_server* srv, vp_plan* plan, int64_t n_rhs, const double* density, double* u_out,
+                    vp_precision prec, vp_ticket* ticket_out);
+vp_status vp_poll(vp_server* srv, vp_ticket ticket, int* done_out);
+vp_status vp_wait(vp_server* srv, vp_ticket ticket);
+/* Counters: requests completed, batches launched, RHS columns launched. */
+vp_status vp_server_stats(const vp_server* srv, int64_t* requests_done, int64_t* batches, int64_t* columns);
+
 #ifdef __cplusplus
 }
 #endif

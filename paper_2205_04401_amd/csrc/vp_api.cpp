@@ -132,6 +132,8 @@ void fold_timings(vp_ctx* ctx) {
 
 }  // namespace
 
+void vp::set_last_error(const char* msg) { g_err = msg; }
+
 extern "C" {
 
 vp_status vp_ctx_profile(vp_ctx* ctx, int on) {
@@ -576,12 +578,10 @@ vp_status vp_plan_sources(const vp_plan* pl, double* xy) {
 
 }  // extern "C"
 
-namespace {
-
 // Source chunks of the far sum: enough blocks (about 16 per CU of a
 // 256-CU device) for an even finish, a multiple of 8 so each chunk's blocks
 // share an XCD, and chunks of at least 256 sources.
-int64_t choose_split(const vp_plan* pl) {
+int64_t vp::far_split(const vp_plan* pl) {
   const int64_t tpb = vp::far_targets_per_block();
   const int64_t n_tb = std::max<int64_t>(1, (pl->n_tgt + tpb - 1) / tpb);
   int64_t want = (4096 + n_tb - 1) / n_tb;
@@ -590,9 +590,11 @@ int64_t choose_split(const vp_plan* pl) {
   return std::max<int64_t>(1, std::min(want, most));
 }
 
+namespace {
+
 // grow the execute workspace to n_rhs right-hand sides
 vp_status ensure_workspace(vp_plan* pl, int64_t R) {
-  const int64_t split = choose_split(pl);
+  const int64_t split = vp::far_split(pl);
   if (pl->ws_rhs >= R && pl->ws_split == split && pl->ws_c) return VP_OK;
   double* ws[] = {pl->ws_f, pl->ws_c, pl->ws_q, pl->ws_part, pl->ws_u};
   for (double* p : ws)
@@ -703,6 +705,8 @@ vp_status vp_coefficients(vp_plan* pl, int64_t R, const double* density, double*
 
 vp_status vp_plan_destroy(vp_plan* pl) {
   if (!pl) return VP_OK;
+  if (pl->live_requests > 0)
+    return fail(VP_EBUSY, "vp_plan_destroy: %d server requests still use this plan", pl->live_requests);
   (void)hipSetDevice(pl->ctx->device);
   (void)hipStreamSynchronize(pl->ctx->stream);
   pl->ctx->in_use -= pl->bytes + pl->ws_bytes;

@@ -219,6 +219,24 @@ __global__ void k_to_f32_ln2(const double* __restrict__ Q, int64_t n, float* __r
     Q32[i] = (float)(Q[i] * 0.69314718055994530942);
 }
 
+__global__ void k_pack(const double* __restrict__ src, int64_t rows, int64_t sc, double* __restrict__ dst,
+                       int64_t dc, int64_t c0) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < rows * sc; g += stride) {
+    const int64_t i = g / sc, r = g - i * sc;
+    dst[i * dc + c0 + r] = src[g];
+  }
+}
+
+__global__ void k_unpack(const double* __restrict__ src, int64_t rows, int64_t sc, int64_t c0,
+                         double* __restrict__ dst, int64_t dc) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < rows * dc; g += stride) {
+    const int64_t i = g / dc, r = g - i * dc;
+    dst[g] = src[i * sc + c0 + r];
+  }
+}
+
 // one thread per (target, rhs)
 template <int P>
 __global__ void k_finish(const double* __restrict__ partial, int64_t n_split, int64_t n_tgt, int64_t R,
@@ -262,8 +280,27 @@ __global__ void k_finish(const double* __restrict__ partial, int64_t n_split, in
     default: return hipErrorInvalidValue; \
   }
 
+hipError_t launch_pack_columns(const double* src, int64_t rows, int64_t src_cols, double* dst, int64_t dst_cols,
+                               int64_t c0, hipStream_t st) {
+  if (rows * src_cols == 0) return hipSuccess;
+  k_pack<<<blocks_for(rows * src_cols), kBlock, 0, st>>>(src, rows, src_cols, dst, dst_cols, c0);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_columns(const double* src, int64_t rows, int64_t src_cols, int64_t c0, double* dst,
+                                 int64_t dst_cols, hipStream_t st) {
+  if (rows * dst_cols == 0) return hipSuccess;
+  k_unpack<<<blocks_for(rows * dst_cols), kBlock, 0, st>>>(src, rows, src_cols, c0, dst, dst_cols);
+  return hipGetLastError();
+}
+
 hipError_t launch_coefficients(const vp_plan* pl, const double* F, int64_t R, double* C, double* Q, hipStream_t st) {
   const int64_t T = pl->n_tri;
+  // the padding sources past n_src carry zero charge for this R
+  if (Q && pl->n_src_pad > pl->n_src) {
+    hipError_t e = hipMemsetAsync(Q + pl->n_src * R, 0, sizeof(double) * (pl->n_src_pad - pl->n_src) * R, st);
+    if (e != hipSuccess) return e;
+  }
   if (T == 0) return hipSuccess;
   VP_DISPATCH_P(pl->p, (k_coef<P><<<blocks_for(T * R), kBlock, 0, st>>>(F, pl->vinv, T, R, C)));
   if (Q) {
@@ -281,27 +318,32 @@ hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, int64_t n_s
   if (NT == 0) return hipSuccess;
   int64_t per = (NS + n_split - 1) / n_split;
   per = ((per + 255) / 256) * 256;
-  const int64_t n_tb = (NT + kBlock * kFarTPT - 1) / (kBlock * kFarTPT);
-  const int64_t nb = n_tb * n_split;
-  if (nb * kBlock >= (1LL << 32)) return hipErrorInvalidConfiguration;
-  const dim3 grid((unsigned)nb);
   if (Q32) k_to_f32_ln2<<<blocks_for(NS * R), kBlock, 0, st>>>(Q, NS * R, Q32);
+  // RB right-hand sides share each logarithm; wide blocks run one target
+  // per thread to stay within the register file
   int64_t r0 = 0;
   while (r0 < R) {
     const int64_t left = R - r0;
-    const int rb = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
-#define VP_FAR(RBV)                                                                                             \
+    const int rb = left >= 32 ? 32 : left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+    const int tpt = rb >= 16 ? 1 : kFarTPT;
+    const int64_t n_tb = (NT + kBlock * tpt - 1) / (kBlock * tpt);
+    const int64_t nb = n_tb * n_split;
+    if (nb * kBlock >= (1LL << 32)) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)nb);
+#define VP_FAR(RBV, TPTV)                                                                                       \
   if (Q32)                                                                                                      \
-    k_far32<RBV, kFarTPT><<<grid, kBlock, 0, st>>>(pl->sxy, Q32, NS, R, r0, pl->xt, pl->yt, NT, per, n_split, \
-                                                   partial);                                                    \
+    k_far32<RBV, TPTV><<<grid, kBlock, 0, st>>>(pl->sxy, Q32, NS, R, r0, pl->xt, pl->yt, NT, per, n_split,    \
+                                                partial);                                                       \
   else                                                                                                          \
-    k_far<RBV, kFarTPT><<<grid, kBlock, 0, st>>>(pl->sxy, Q, NS, R, r0, pl->xt, pl->yt, NT, per, n_split,     \
-                                                 pl->logtab, partial)
+    k_far<RBV, TPTV><<<grid, kBlock, 0, st>>>(pl->sxy, Q, NS, R, r0, pl->xt, pl->yt, NT, per, n_split,        \
+                                              pl->logtab, partial)
     switch (rb) {
-      case 8: VP_FAR(8); break;
-      case 4: VP_FAR(4); break;
-      case 2: VP_FAR(2); break;
-      default: VP_FAR(1); break;
+      case 32: VP_FAR(32, 1); break;
+      case 16: VP_FAR(16, 1); break;
+      case 8: VP_FAR(8, kFarTPT); break;
+      case 4: VP_FAR(4, kFarTPT); break;
+      case 2: VP_FAR(2, kFarTPT); break;
+      default: VP_FAR(1, kFarTPT); break;
     }
 #undef VP_FAR
     if (n_launches) ++*n_launches;

@@ -189,6 +189,7 @@ struct vp_plan {
   size_t ws_bytes = 0;
   std::vector<void*> allocs;  // everything above except the workspace
   size_t bytes = 0;
+  int live_requests = 0;  // requests of a server not yet finished
 };
 
 namespace vp {
@@ -213,6 +214,14 @@ hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, int64_t n_s
 hipError_t launch_finish(const vp_plan* pl, const double* partial, int64_t n_split, const double* C,
                          int64_t R, bool far_only, double* U, hipStream_t st);
 int64_t far_targets_per_block();
+int64_t far_split(const vp_plan* pl);  // source chunks of the far sum
+void set_last_error(const char* msg);
+// dst[i][c0 + r] = src[i][r] for i < rows, r < src_cols (dst has dst_cols)
+hipError_t launch_pack_columns(const double* src, int64_t rows, int64_t src_cols, double* dst, int64_t dst_cols,
+                               int64_t c0, hipStream_t st);
+// dst[i][r] = src[i][c0 + r] for i < rows, r < dst_cols (src has src_cols)
+hipError_t launch_unpack_columns(const double* src, int64_t rows, int64_t src_cols, int64_t c0, double* dst,
+                                 int64_t dst_cols, hipStream_t st);
 void log_table(double2 out[kLogTab + 1]);
 hipError_t exclusive_scan_i32(const int32_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t st);
 size_t exclusive_scan_tmp_bytes(int64_t n);

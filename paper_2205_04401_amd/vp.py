@@ -28,7 +28,8 @@ STATUS_NAMES = {0: "VP_OK", 1: "VP_EINVAL", 2: "VP_ENOMEM", 3: "VP_EDEVICE", 4: 
 EXPORTS = ["vp_ctx_create", "vp_ctx_destroy", "vp_last_error", "vp_ref_nodes", "vp_ref_rule", "vp_mesh_create",
            "vp_mesh_destroy", "vp_plan_create", "vp_plan_info", "vp_plan_pairs", "vp_plan_rows",
            "vp_execute", "vp_coefficients", "vp_plan_sources", "vp_plan_destroy", "vp_sync",
-           "vp_ctx_profile", "vp_ctx_timings"]
+           "vp_ctx_profile", "vp_ctx_timings", "vp_server_create", "vp_server_destroy", "vp_submit",
+           "vp_poll", "vp_wait", "vp_server_stats"]
 STAGES = ["classify", "rows", "coef", "far", "finish"]
 
 
@@ -88,6 +89,12 @@ def load(path=LIB_PATH):
         "vp_sync": [P],
         "vp_ctx_profile": [P, ctypes.c_int],
         "vp_ctx_timings": [P, P, P],
+        "vp_server_create": [P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(P)],
+        "vp_server_destroy": [P],
+        "vp_submit": [P, P, I64, P, P, ctypes.c_int, ctypes.POINTER(I64)],
+        "vp_poll": [P, I64, ctypes.POINTER(ctypes.c_int)],
+        "vp_wait": [P, I64],
+        "vp_server_stats": [P, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -152,6 +159,9 @@ class Context:
     def plan(self, mesh, p, q, eps, targets, **opts):
         return Plan(self, mesh, p, q, eps, targets, **opts)
 
+    def server(self, n_slots=4, max_batch_rhs=32):
+        return Server(self, n_slots, max_batch_rhs)
+
     def sync(self):
         _check(load().vp_sync(self.h))
 
@@ -170,6 +180,51 @@ class Context:
         if self.h:
             _check(load().vp_ctx_destroy(self.h))
             self.h = None
+
+
+class Server:
+    """Continuous-batching request server (vp_server_*): device tensors in
+    and out, tickets to poll or wait on."""
+
+    def __init__(self, ctx, n_slots=4, max_batch_rhs=32):
+        h = P()
+        _check(load().vp_server_create(ctx.h, n_slots, max_batch_rhs, ctypes.byref(h)))
+        self.h = h
+        self.ctx = ctx
+        self._keep = {}
+
+    def submit(self, plan, F, out, mixed=False):
+        """F: device tensor [n_tri, n_p, R]; out: device tensor [n_tgt, R]."""
+        if not (_is_device(F) and _is_device(out)):
+            raise VPError(VP_EINVAL, "submit() takes device tensors")
+        R = F.shape[2] if F.dim() == 3 else 1
+        t = I64()
+        _check(load().vp_submit(self.h, plan.h, R, _ptr(F), _ptr(out), VP_MIXED if mixed else VP_FP64,
+                                ctypes.byref(t)))
+        self._keep[t.value] = (F, out)
+        return t.value
+
+    def poll(self, ticket):
+        d = ctypes.c_int()
+        _check(load().vp_poll(self.h, ticket, ctypes.byref(d)))
+        if d.value:
+            self._keep.pop(ticket, None)
+        return bool(d.value)
+
+    def wait(self, ticket):
+        _check(load().vp_wait(self.h, ticket))
+        self._keep.pop(ticket, None)
+
+    def stats(self):
+        a, b, c = I64(), I64(), I64()
+        _check(load().vp_server_stats(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"requests_done": a.value, "batches": b.value, "columns": c.value}
+
+    def close(self):
+        if self.h:
+            _check(load().vp_server_destroy(self.h))
+            self.h = None
+            self._keep.clear()
 
 
 class Mesh:

@@ -356,3 +356,59 @@ def test_star_full_size_sampled(vp_ctx, q):
     assert e_mix <= REL_MIXED
     plan.close()
     mesh.close()
+
+
+# ---------------------------------------------------------------------------
+# serving: each result is the same alone and in the mix
+# ---------------------------------------------------------------------------
+
+def test_serving_results_equal_alone_and_in_mix(vp_ctx):
+    import torch
+    rng = np.random.default_rng(5)
+    plans, inputs = [], []
+    for k, (T, p) in enumerate(((600, 3), (1500, 4))):
+        vq, tq = W.star_mesh(n_tri=T, n_boundary=120, seed=300 + k)
+        vt, tt = W.star_mesh(n_tri=T, n_boundary=120, seed=310 + k, staggered=True)
+        nodes = rules.interp_nodes(p)
+        tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+        mesh = vp_ctx.mesh(vq, tq)
+        plans.append((mesh, vp_ctx.plan(mesh, p, 6, 1e-12, tg), vq, tq, nodes))
+    server = vp_ctx.server(n_slots=3, max_batch_rhs=24)
+    inputs = []
+    for i in range(40):
+        k = int(rng.integers(2))
+        mesh, plan, vq, tq, nodes = plans[k]
+        R = int(rng.integers(1, 9))
+        F = np.stack([W.sample_density(W.gaussian_sum(700 + 13 * i + r, vq, tq), vq, tq, nodes)
+                      for r in range(R)], -1)
+        mixed = bool(i % 3 == 0)
+        Fd = torch.from_numpy(F).cuda()
+        out = torch.full((plan.n_tgt, R), np.nan, dtype=torch.float64, device="cuda")
+        inputs.append((k, F, mixed, out, Fd))
+    torch.cuda.synchronize()
+    # all requests arrive while the first batches run: later ones are packed
+    reqs = [(k, F, mixed, out, server.submit(plans[k][1], Fd, out, mixed=mixed))
+            for k, F, mixed, out, Fd in inputs]
+    for _, _, _, _, t in reqs:
+        server.wait(t)
+    st = server.stats()
+    say("serving stats", st)
+    assert st["requests_done"] == 40 and st["batches"] < 40  # some requests were packed together
+    worst = 0.0
+    for k, F, mixed, out, _ in reqs:
+        alone = plans[k][1].execute(F, mixed=mixed)
+        got = out.cpu().numpy()
+        worst = max(worst, rel_linf(got, alone))
+    say("serving: worst rel difference alone vs in the mix", worst)
+    assert worst <= 1e-14
+    server.close()
+    for mesh, plan, *_ in plans:
+        plan.close()
+        mesh.close()
+
+
+def test_serving_poisson_run_reports_latency(vp_ctx):
+    from paper_2205_04401_amd import serving
+    res = serving.run(vp_ctx, n_requests=40, tri_range=(500, 2000), n_meshes=2)
+    say("serving run", res)
+    assert res["p50_ms"] > 0 and res["p99_ms"] >= res["p50_ms"] and res["evals_per_s"] > 0
