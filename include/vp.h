@@ -104,6 +104,8 @@ typedef struct {
   int64_t near_subtri;     /* near-rule leaves summed over all near pairs (paper's s_n times pairs) */
   int64_t self_panels;     /* arc-length panels summed over all self pairs (paper's s_l) */
   int64_t capped_leaves;   /* near leaves integrated at the depth cap */
+  int64_t depth_first_pairs; /* near pairs whose subdivision was too wide for the breadth-first
+                                level buffers and ran depth-first (slivers) */
   int64_t bytes_resident;  /* device bytes held by the plan */
   int32_t p, q, n_p, n_f;  /* orders; n_p = (p+1)(p+2)/2 nodes, n_f = q^2 far nodes per triangle */
   double eps;

@@ -484,17 +484,17 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
     int* d_flag = nullptr;
     int64_t* d_stats = nullptr;
     if ((e = hipMalloc((void**)&d_flag, sizeof(int))) != hipSuccess) return hip_fail(e, "vp_plan_create: hipMalloc");
-    if ((e = hipMalloc((void**)&d_stats, sizeof(int64_t) * 3)) != hipSuccess) {
+    if ((e = hipMalloc((void**)&d_stats, sizeof(int64_t) * 4)) != hipSuccess) {
       (void)hipFree(d_flag);
       return hip_fail(e, "vp_plan_create: hipMalloc");
     }
     int flag = 0;
     if ((e = hipMemsetAsync(d_flag, 0, sizeof(int), st)) != hipSuccess ||
-        (e = hipMemsetAsync(d_stats, 0, sizeof(int64_t) * 3, st)) != hipSuccess ||
+        (e = hipMemsetAsync(d_stats, 0, sizeof(int64_t) * 4, st)) != hipSuccess ||
         (e = vp::launch_rows(pl, d_flag, d_stats, st)) != hipSuccess ||
         (e = hipEventRecord(ev2, st)) != hipSuccess || (tm_rows.stop(1), false) ||
         (e = hipMemcpyAsync(&flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(pl->stats, d_stats, sizeof(int64_t) * 3, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(pl->stats, d_stats, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess) {
       (void)hipFree(d_flag);
       (void)hipFree(d_stats);
@@ -502,7 +502,7 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
     }
     (void)hipFree(d_flag);
     (void)hipFree(d_stats);
-    if (flag) return fail(VP_EINTERNAL, "vp_plan_create: near subdivision exceeded its per-level capacity");
+    if (flag) return fail(VP_EINTERNAL, "vp_plan_create: near subdivision exceeded its depth-first stack");
   }
   float ms1 = 0.f, ms2 = 0.f;
   (void)hipEventElapsedTime(&ms1, ev0, ev1);
@@ -528,6 +528,7 @@ vp_status vp_plan_info(const vp_plan* pl, vp_plan_stats* out) {
   out->near_subtri = pl->stats[0];
   out->self_panels = pl->stats[1];
   out->capped_leaves = pl->stats[2];
+  out->depth_first_pairs = pl->stats[3];
   out->bytes_resident = (int64_t)(pl->bytes + pl->ws_bytes);
   out->p = pl->p;
   out->q = pl->q;

@@ -57,7 +57,7 @@ struct RowsArgs {
   const double2* logtab;
   double* rows;
   int* flag;
-  int64_t* stats;  // near leaves, self panels, capped leaves
+  int64_t* stats;  // near leaves, self panels, capped leaves, depth-first pairs
 };
 
 __device__ __forceinline__ int dyadic_count(double len, double d, int cap) {
@@ -94,16 +94,19 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
   for (int k = 0; k < NP; ++k) acc[k] = 0.0;
 
   // ---- B: the far rule's own contribution (subtracted) ----
-  for (int j = lane; j < a.nf; j += kWave) {
-    const double fx = a.far_x[j], fy = a.far_y[j];
-    const double yx = Ax + fx * e1x + fy * e2x, yy = Ay + fx * e1y + fy * e2y;
-    const double dx = x - yx, dy = y - yy;
-    const double r2 = dx * dx + dy * dy;
-    const double w = (r2 > 0.0) ? -0.5 * vp_log(r2, tab) * a.far_w[j] * D : 0.0;
-    const double* E = a.efar + (size_t)j * NP;
+  auto add_far_rule = [&]() {
+    for (int j = lane; j < a.nf; j += kWave) {
+      const double fx = a.far_x[j], fy = a.far_y[j];
+      const double yx = Ax + fx * e1x + fy * e2x, yy = Ay + fx * e1y + fy * e2y;
+      const double dx = x - yx, dy = y - yy;
+      const double r2 = dx * dx + dy * dy;
+      const double w = (r2 > 0.0) ? -0.5 * vp_log(r2, tab) * a.far_w[j] * D : 0.0;
+      const double* E = a.efar + (size_t)j * NP;
 #pragma unroll
-    for (int k = 0; k < NP; ++k) acc[k] = fma(w, E[k], acc[k]);
-  }
+      for (int k = 0; k < NP; ++k) acc[k] = fma(w, E[k], acc[k]);
+    }
+  };
+  add_far_rule();
 
   int64_t n_leaves = 0, n_panels = 0, n_capped = 0;
   if (kind == 1) {
@@ -128,6 +131,7 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
     }
     __syncthreads();
     int n_cur = 1;
+    bool overflow = false;
     for (int level = 0; n_cur > 0; ++level) {
       int n_next = 0, n_leaf = 0;
       double thr[3];
@@ -185,10 +189,10 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
         n_leaf += __popcll(mleaf);
       }
       if (level >= a.depth_cap) n_capped += n_leaf;
-      if (n_next > kCap || n_leaf > kCap) {
-        if (lane == 0) atomicMax(a.flag, 1);
-        n_next = 0;
-        n_leaf = n_leaf > kCap ? kCap : n_leaf;
+      if (n_next > kCap || n_leaf > kCap) {  // a level too wide: redo depth-first below
+        overflow = true;
+        __syncthreads();
+        break;
       }
       __syncthreads();
       n_leaves += n_leaf;
@@ -208,6 +212,76 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
       cur = nxt;
       nxt = sw;
       n_cur = n_next;
+    }
+    if (overflow) {
+      if (lane == 0) atomicAdd((unsigned long long*)&a.stats[3], 1ull);
+      // Depth-first walk of the same subdivision, one sub-triangle at a
+      // time (lanes share its near-rule nodes); the stack holds at most
+      // 3 depth_cap + 1 entries, within the two level buffers.
+#pragma unroll
+      for (int k = 0; k < NP; ++k) acc[k] = 0.0;
+      n_leaves = 0;
+      n_capped = 0;
+      add_far_rule();
+      double* stk = &lv[0][0];
+      constexpr int kStack = 2 * kCap;
+      if (lane == 0) {
+        stk[0] = 0.0;
+        stk[1] = 0.0;
+        stk[2] = 1.0;
+      }
+      __syncthreads();
+      int sp = 1;
+      while (sp > 0) {
+        --sp;
+        const double sa = stk[3 * sp], sb = stk[3 * sp + 1], ss = stk[3 * sp + 2];
+        __syncthreads();
+        const int level = -ilogb(fabs(ss));
+        const double f = exp2(-2.0 * level * a.inv_near_order);
+        const double hl = ldexp(0.5, -level);
+        bool split = false;
+        if (level < a.depth_cap) {
+          const double p0x = Ax + sa * e1x + sb * e2x, p0y = Ay + sa * e1y + sb * e2y;
+          const double p1x = p0x + ss * e1x, p1y = p0y + ss * e1y;
+          const double p2x = p0x + ss * e2x, p2y = p0y + ss * e2y;
+          const double d0 = sqrt((x - p0x) * (x - p0x) + (y - p0y) * (y - p0y));
+          const double d1 = sqrt((x - p1x) * (x - p1x) + (y - p1y) * (y - p1y));
+          const double d2 = sqrt((x - p2x) * (x - p2x) + (y - p2y) * (y - p2y));
+          const double dd[3] = {d0 + d1, d1 + d2, d2 + d0};
+#pragma unroll
+          for (int e = 0; e < 3; ++e) {
+            const double rho = rho0[e] * f;
+            if (rho > 1.0 && dd[e] < hl * ell0[e] * (rho + 1.0 / rho)) split = true;
+          }
+        }
+        if (split) {
+          if (sp + 4 > kStack) {
+            if (lane == 0) atomicMax(a.flag, 1);
+            break;
+          }
+          if (lane == 0) {
+            const double h = 0.5 * ss;
+            double* c = stk + 3 * sp;
+            c[0] = sa;          c[1] = sb;          c[2] = h;
+            c[3] = sa + h;      c[4] = sb;          c[5] = h;
+            c[6] = sa;          c[7] = sb + h;      c[8] = h;
+            c[9] = sa + h;      c[10] = sb + h;     c[11] = -h;
+          }
+          sp += 4;
+          __syncthreads();
+        } else {
+          ++n_leaves;
+          if (level >= a.depth_cap) ++n_capped;
+          for (int nd = lane; nd < a.nn; nd += kWave) {
+            const double xi1 = sa + ss * a.near_x[nd], xi2 = sb + ss * a.near_y[nd];
+            const double yx = Ax + xi1 * e1x + xi2 * e2x, yy = Ay + xi1 * e1y + xi2 * e2y;
+            const double dx = x - yx, dy = y - yy;
+            const double w = 0.5 * vp_log(dx * dx + dy * dy, tab) * a.near_w[nd] * ss * ss * D;
+            koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { acc[k] = fma(w, v, acc[k]); });
+          }
+        }
+      }
+      __syncthreads();
     }
   } else {
     // ---- A, self pair: three pieces in radius-arc-length coordinates ----

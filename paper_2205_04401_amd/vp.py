@@ -49,6 +49,7 @@ class PlanStats(ctypes.Structure):
     _fields_ = [("n_tri", ctypes.c_int64), ("n_src", ctypes.c_int64), ("n_tgt", ctypes.c_int64),
                 ("n_pairs", ctypes.c_int64), ("n_self", ctypes.c_int64), ("near_subtri", ctypes.c_int64),
                 ("self_panels", ctypes.c_int64), ("capped_leaves", ctypes.c_int64),
+                ("depth_first_pairs", ctypes.c_int64),
                 ("bytes_resident", ctypes.c_int64), ("p", ctypes.c_int32), ("q", ctypes.c_int32),
                 ("n_p", ctypes.c_int32), ("n_f", ctypes.c_int32), ("eps", ctypes.c_double),
                 ("ms_classify", ctypes.c_double), ("ms_rows", ctypes.c_double)]

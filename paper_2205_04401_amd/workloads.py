@@ -192,55 +192,74 @@ def gaussian_sum(seed, vert, tri, n_terms=10, width=(0.05, 0.3)):
 # ----------------------------------------------------------------------------
 
 def l_shape_graded(n_tri=250000, seed=50, staggered=False, grade=0.5):
-    """[-1,1]^2 minus [0,1]^2 with local size h ~ max(r, 1e-3)^grade toward
-    the re-entrant corner (points by rejection sampling with density
-    proportional to h^-2), boundary points spaced by the same size."""
+    """[-1,1]^2 minus [0,1]^2 with local size h ~ r^grade toward the
+    re-entrant corner (grade = 0.5).  Points: a jittered hexagonal lattice in
+    a reference plane xi, mapped by x = xi |xi|^(1/grade - 1), which spreads
+    uniform spacing into h ~ |x|^grade (radial and tangential stretches
+    differ by the factor 1/grade, so triangles stay within aspect ~2);
+    boundary points spaced by the same local size; Delaunay; triangles with
+    centroid in the removed quadrant dropped.  The staggered copy shifts the
+    lattice by (h/2, h sqrt(3)/6) and the boundary by half a step."""
     rng = np.random.default_rng(seed)
+    alpha = 1.0 / grade - 1.0
 
-    def hfun(p):
-        r = np.hypot(p[..., 0], p[..., 1])
-        return np.maximum(r, 1e-3) ** grade
+    def fwd(xi):
+        rr = np.hypot(xi[:, 0], xi[:, 1])
+        return xi * (rr ** alpha)[:, None]
 
-    # boundary polyline, counter-clockwise around the domain
+    def inside(pts):
+        return ((np.abs(pts[:, 0]) < 1) & (np.abs(pts[:, 1]) < 1) & ~((pts[:, 0] > 0) & (pts[:, 1] > 0)))
+
     corners = np.array([[0.0, 0.0], [0.0, 1.0], [-1.0, 1.0], [-1.0, -1.0], [1.0, -1.0], [1.0, 0.0]])
-    # global scale h0 so that the triangle count is met (about 2 per point)
-    probe = rng.uniform(-1, 1, size=(200000, 2))
-    probe = probe[~((probe[:, 0] > 0) & (probe[:, 1] > 0))]
-    mean_inv_h2 = np.mean(hfun(probe) ** -2.0) * 3.0  # area 3
-    n_pts_goal = n_tri / 2.0
-    h0 = math.sqrt(mean_inv_h2 * 2.0 / (math.sqrt(3.0) * n_pts_goal))
-    # boundary points spaced by the local size (staggered copy: half a step on)
-    bpts = []
-    for k in range(len(corners)):
-        p0, p1 = corners[k], corners[(k + 1) % len(corners)]
-        L = float(np.hypot(*(p1 - p0)))
-        s = 0.5 * h0 * float(hfun(p0)) if staggered else 0.0
-        while s < L:
-            pt = p0 + (p1 - p0) * (s / L)
-            bpts.append(pt)
-            s += h0 * float(hfun(pt))
-    bnd = np.array(bpts)
-    # interior by rejection
-    n_int = int(n_pts_goal - len(bnd))
-    pts = []
-    total = 0
-    hmin = h0 * 1e-3 ** grade
-    while total < n_int:
-        cand = rng.uniform(-1, 1, size=(4 * n_int, 2))
-        cand = cand[~((cand[:, 0] >= 0) & (cand[:, 1] >= 0))]
-        acc = rng.uniform(size=len(cand)) < (hmin / (h0 * hfun(cand))) ** 2
-        cand = cand[acc]
-        pts.append(cand)
-        total += len(cand)
-    inner = np.concatenate(pts)[:n_int]
-    tree = cKDTree(bnd)
-    dist, _ = tree.query(inner)
-    inner = inner[dist > 0.5 * h0 * hfun(inner)]
-    allp = np.concatenate([bnd, inner])
-    dl = Delaunay(allp)
-    tri = dl.simplices
-    cen = allp[tri].mean(axis=1)
-    tri = tri[~((cen[:, 0] > 0) & (cen[:, 1] > 0))]
+    rmax = math.sqrt(2.0) ** (1.0 / (1.0 + alpha))
+    h = math.sqrt(2.0 * 1.6 / (math.sqrt(3.0) * n_tri / 2.0))
+    for _ in range(5):
+        ny = int(math.ceil(2 * rmax / (h * math.sqrt(3) / 2))) + 2
+        nx = int(math.ceil(2 * rmax / h)) + 2
+        jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+        px = -rmax - h + ii * h + (jj % 2) * (h / 2)
+        py = -rmax - h + jj * (h * math.sqrt(3) / 2)
+        if staggered:
+            px = px + h / 2
+            py = py + h * math.sqrt(3) / 6
+        xi = np.stack([px.ravel(), py.ravel()], axis=1)
+        xi = xi + rng.uniform(-0.15 * h, 0.15 * h, size=xi.shape)
+        pts = fwd(xi)
+        rxi = np.hypot(xi[:, 0], xi[:, 1])
+        hloc = h * (1.0 + alpha) * np.maximum(rxi, h) ** alpha  # local size in x
+        keep = inside(pts)
+        pts, hloc = pts[keep], hloc[keep]
+        # distance to the boundary polyline
+        dmin = np.full(len(pts), np.inf)
+        for k in range(len(corners)):
+            p0, p1 = corners[k], corners[(k + 1) % len(corners)]
+            d = p1 - p0
+            t = np.clip(((pts - p0) @ d) / (d @ d), 0.0, 1.0)
+            dmin = np.minimum(dmin, np.hypot(*(pts - (p0 + t[:, None] * d)).T))
+        pts = pts[dmin > 0.5 * hloc]
+        # boundary points spaced by the local size
+        bpts = []
+        for k in range(len(corners)):
+            p0, p1 = corners[k], corners[(k + 1) % len(corners)]
+            L = float(np.hypot(*(p1 - p0)))
+            bpts.append(p0)  # corners always belong to the boundary
+            rloc = math.hypot(p0[0], p0[1]) ** (1.0 / (1.0 + alpha))
+            s = h * (1.0 + alpha) * max(rloc, h) ** alpha * (0.5 if staggered else 1.0)
+            while s < L:
+                pt = p0 + (p1 - p0) * (s / L)
+                rloc = math.hypot(pt[0], pt[1]) ** (1.0 / (1.0 + alpha))
+                step = h * (1.0 + alpha) * max(rloc, h) ** alpha
+                if L - s > 0.5 * step:
+                    bpts.append(pt)
+                s += step
+        allp = np.concatenate([np.array(bpts), pts])
+        dl = Delaunay(allp)
+        tri = dl.simplices
+        cen = allp[tri].mean(axis=1)
+        tri = tri[inside(cen)]
+        if abs(len(tri) - n_tri) <= 0.02 * n_tri:
+            break
+        h *= math.sqrt(len(tri) / n_tri)
     return allp, _ccw(allp, tri)
 
 

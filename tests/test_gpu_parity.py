@@ -256,6 +256,30 @@ def test_empty_target_set_and_single_triangle(vp_ctx):
     mesh.close()
 
 
+def test_sliver_triangles_depth_first_subdivision(vp_ctx):
+    """Near pairs of triangles with aspect ratio ~1e3 need more sub-triangles
+    per level than the breadth-first buffers hold; the kernel then walks the
+    subdivision depth-first.  Results must still match the oracle."""
+    vert = np.array([[0.0, 0.0], [1.0, 0.0], [0.5, 1e-3], [0.5, -8e-4], [1.2, 0.3], [-0.1, 0.25]])
+    tri = np.array([[0, 1, 2], [0, 3, 1], [1, 4, 2], [0, 2, 5]], dtype=np.int32)
+    p, q = 3, 6
+    tg = np.array([[0.3, 2e-3], [0.7, -1.5e-3], [0.5, 0.01], [0.45, 4e-4], [0.2, -3e-4], [0.9, 0.05]])
+    nodes = rules.interp_nodes(p)
+    F = W.sample_density(lambda x, y: np.cos(2 * x) + y * y, vert, tri, nodes)
+    mesh = vp_ctx.mesh(vert, tri)
+    plan = vp_ctx.plan(mesh, p, q, 1e-12, tg)
+    info = plan.info()
+    say("sliver plan", {k: info[k] for k in ("n_pairs", "near_subtri", "depth_first_pairs", "capped_leaves")})
+    assert info["depth_first_pairs"] > 0
+    o = potential.Oracle(vert, tri, p, q, 1e-12)
+    compare_pairs(plan, o, tg)
+    err = rel_linf(plan.execute(F), o.evaluate(F, tg))
+    say("sliver rel", err)
+    assert err <= REL_E2E
+    plan.close()
+    mesh.close()
+
+
 def test_error_paths(vp_ctx):
     from paper_2205_04401_amd import vp
     vq, tq = W.unit_square(2, "/")
@@ -412,3 +436,69 @@ def test_serving_poisson_run_reports_latency(vp_ctx):
     res = serving.run(vp_ctx, n_requests=40, tri_range=(500, 2000), n_meshes=2)
     say("serving run", res)
     assert res["p50_ms"] > 0 and res["p99_ms"] >= res["p50_ms"] and res["evals_per_s"] > 0
+
+
+# ---------------------------------------------------------------------------
+# graded L-shape (about 250k triangles, p = 4, the 16-node far rule, 3.7M
+# targets) and the batched star (100k triangles, 64 densities)
+# ---------------------------------------------------------------------------
+
+def test_graded_l_shape_full_size_sampled(vp_ctx):
+    p, q, eps = 4, 4, 1e-13
+    vq, tq = W.l_shape_graded(n_tri=250000, seed=50)
+    vt, tt = W.l_shape_graded(n_tri=250000, seed=51, staggered=True)
+    nodes = rules.interp_nodes(p)
+    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    F = W.sample_density(W.l_shape_density(52), vq, tq, nodes)
+    say("L-shape:", len(tq), "triangles", len(tg), "targets")
+    mesh = vp_ctx.mesh(vq, tq)
+    plan = vp_ctx.plan(mesh, p, q, eps, tg)
+    info = plan.info()
+    say("L-shape plan", {k: info[k] for k in ("n_pairs", "n_self", "near_subtri", "ms_classify", "ms_rows",
+                                              "capped_leaves", "bytes_resident")})
+    assert info["near_subtri"] >= info["n_pairs"] - info["n_self"]
+    u = plan.execute(F)
+    u_mix = plan.execute(F, mixed=True)
+    rng = np.random.default_rng(55)
+    sample = np.sort(np.concatenate([rng.choice(len(tg), 6, replace=False),
+                                     np.argsort(np.hypot(tg[:, 0], tg[:, 1]))[:2]]))  # two next to the corner
+    o = potential.Oracle(vq, tq, p, q, eps)
+    compare_pairs(plan, o, tg, sample)
+    ref = o.evaluate(F, tg[sample])
+    e = np.abs(u[sample] - ref).max() / np.abs(ref).max()
+    e_mix = np.abs(u_mix[sample] - ref).max() / np.abs(ref).max()
+    say("L-shape sampled rel", e, "mixed", e_mix)
+    assert e <= REL_E2E and e_mix <= REL_MIXED
+    plan.close()
+    mesh.close()
+
+
+@pytest.mark.parametrize("q", [8, 12])
+def test_batched_star_100k_64_densities(vp_ctx, q):
+    import torch
+    p, eps, R = 6, 1e-13, 64
+    vq, tq = W.star_mesh(n_tri=100000, n_boundary=2000, seed=30)
+    vt, tt = W.star_mesh(n_tri=100000, n_boundary=2000, seed=31, staggered=True)
+    nodes = rules.interp_nodes(p)
+    tg_all = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    rng = np.random.default_rng(33)
+    tg = tg_all[np.sort(rng.choice(len(tg_all), 2048, replace=False))]  # seeded target subset
+    F = np.stack([W.sample_density(W.gaussian_sum(1000 + r, vq, tq), vq, tq, nodes) for r in range(R)], -1)
+    mesh = vp_ctx.mesh(vq, tq)
+    plan = vp_ctx.plan(mesh, p, q, eps, tg)
+    Fd = torch.from_numpy(F).cuda()
+    u = plan.execute(Fd).cpu().numpy()
+    u_mix = plan.execute(Fd, mixed=True).cpu().numpy()
+    # every column equals its own single-density evaluation (batch invariance)
+    for r in (0, 17, 63):
+        assert rel_linf(u[:, r], plan.execute(np.ascontiguousarray(F[:, :, r]))) <= 1e-14
+    # oracle on a few targets and columns
+    cols = [0, 31, 63]
+    sample = np.array([5, 700, 2047])
+    ref = potential.Oracle(vq, tq, p, q, eps).evaluate(np.ascontiguousarray(F[:, :, cols]), tg[sample])
+    e = rel_linf(u[sample][:, cols], ref)
+    e_mix = rel_linf(u_mix[sample][:, cols], ref)
+    say(f"batched star q={q}: rel {e}, mixed {e_mix}")
+    assert e <= REL_E2E and e_mix <= REL_MIXED
+    plan.close()
+    mesh.close()
