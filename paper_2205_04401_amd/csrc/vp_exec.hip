@@ -80,7 +80,11 @@ __global__ void k_charges(const double* __restrict__ C, const double* __restrict
 // n_split a multiple of 8 the blocks that share a chunk sit on one XCD and
 // its L2.  Each 256-source tile is summed on its own before it joins the
 // running total (two-level summation).  Sources are padded to a multiple of
-// 4 with zero charges; a pair at distance 0 contributes 0.
+// 256 with zero charges.  A pair at distance 0 gets the finite value
+// vp_log(0), exactly as in the subtracted far rule of the correction rows,
+// so it cancels in the potential.  With one right-hand side the exponent
+// part of the logarithm is accumulated apart (sum Q e, times ln 2 at the
+// end), which saves an instruction per pair.
 template <int RB, int TPT>
 __global__ __launch_bounds__(kBlock) void k_far(const double2* __restrict__ sxy, const double* __restrict__ Q,
                                                 int64_t n_src_pad, int64_t R, int64_t r0,
@@ -90,6 +94,7 @@ __global__ __launch_bounds__(kBlock) void k_far(const double2* __restrict__ sxy,
   __shared__ double2 tab[kLogTab + 1];
   for (int i = threadIdx.x; i <= kLogTab; i += blockDim.x) tab[i] = logtab[i];
   __syncthreads();
+  constexpr bool kSplitExp = (RB == 1);
   const int64_t b = blockIdx.x;
   const int64_t chunk = b % n_split, tb = b / n_split;
   double x[TPT], y[TPT];
@@ -103,18 +108,22 @@ __global__ __launch_bounds__(kBlock) void k_far(const double2* __restrict__ sxy,
   }
   const int64_t s_begin = chunk * per_split;
   const int64_t s_end = min(n_src_pad, s_begin + per_split);
-  double acc[TPT][RB];
+  double acc[TPT][RB], acc_e[TPT];
 #pragma unroll
-  for (int k = 0; k < TPT; ++k)
+  for (int k = 0; k < TPT; ++k) {
+    acc_e[k] = 0.0;
 #pragma unroll
     for (int r = 0; r < RB; ++r) acc[k][r] = 0.0;
+  }
   for (int64_t j0 = s_begin; j0 < s_end; j0 += 256) {
     const int64_t j1 = min(s_end, j0 + 256);
-    double tile[TPT][RB];
+    double tile[TPT][RB], tile_e[TPT];
 #pragma unroll
-    for (int k = 0; k < TPT; ++k)
+    for (int k = 0; k < TPT; ++k) {
+      tile_e[k] = 0.0;
 #pragma unroll
       for (int r = 0; r < RB; ++r) tile[k][r] = 0.0;
+    }
     for (int64_t j = j0; j < j1; j += 4) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -126,21 +135,31 @@ __global__ __launch_bounds__(kBlock) void k_far(const double2* __restrict__ sxy,
         for (int k = 0; k < TPT; ++k) {
           const double dx = x[k] - s.x, dy = y[k] - s.y;
           const double r2 = fma(dx, dx, dy * dy);
-          double lg = vp_log(r2, tab);
-          lg = (r2 > 0.0) ? lg : 0.0;
+          if (kSplitExp) {
+            double e, rest;
+            vp_log_parts(r2, tab, e, rest);
+            tile_e[k] = fma(q[0], e, tile_e[k]);
+            tile[k][0] = fma(q[0], rest, tile[k][0]);
+          } else {
+            const double lg = vp_log(r2, tab);
 #pragma unroll
-          for (int r = 0; r < RB; ++r) tile[k][r] = fma(q[r], lg, tile[k][r]);
+            for (int r = 0; r < RB; ++r) tile[k][r] = fma(q[r], lg, tile[k][r]);
+          }
         }
       }
     }
 #pragma unroll
-    for (int k = 0; k < TPT; ++k)
+    for (int k = 0; k < TPT; ++k) {
+      acc_e[k] += tile_e[k];
 #pragma unroll
       for (int r = 0; r < RB; ++r) acc[k][r] += tile[k][r];
+    }
   }
+  const double2 l2 = tab[kLogTab];
 #pragma unroll
   for (int k = 0; k < TPT; ++k)
     if (t[k] < n_tgt) {
+      if (kSplitExp) acc[k][0] += fma(acc_e[k], l2.x, acc_e[k] * l2.y);
 #pragma unroll
       for (int r = 0; r < RB; ++r) partial[((size_t)chunk * n_tgt + t[k]) * R + r0 + r] = acc[k][r];
     }
@@ -150,13 +169,17 @@ __global__ __launch_bounds__(kBlock) void k_far(const double2* __restrict__ sxy,
 // difference is taken in FP64 and rounded to FP32, r^2 and the base-2
 // logarithm (the hardware v_log_f32) are FP32, the charges are FP32 with ln 2
 // folded in (Q32 = Q ln 2, so Q32 log2(r^2) = Q log(r^2)), each 256-source
-// tile is summed in FP32 and the tiles are summed in FP64.
+// tile is summed in FP32 and the tiles are summed in FP64.  A pair at
+// distance 0 gets vp_log(0) / ln 2, the value the FP64 correction rows
+// subtract for it.
 template <int RB, int TPT>
 __global__ __launch_bounds__(kBlock) void k_far32(const double2* __restrict__ sxy, const float* __restrict__ Q32,
                                                   int64_t n_src_pad, int64_t R, int64_t r0,
                                                   const double* __restrict__ xt, const double* __restrict__ yt,
                                                   int64_t n_tgt, int64_t per_split, int64_t n_split,
+                                                  const double2* __restrict__ logtab,
                                                   double* __restrict__ partial) {
+  const float log2_at_zero = (float)(vp_log(0.0, logtab) * 1.44269504088896340736);
   const int64_t b = blockIdx.x;
   const int64_t chunk = b % n_split, tb = b / n_split;
   double x[TPT], y[TPT];
@@ -194,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void k_far32(const double2* __restrict__ sx
           const float dx = (float)(x[k] - s.x), dy = (float)(y[k] - s.y);
           const float r2 = fmaf(dx, dx, dy * dy);
           float lg = __builtin_amdgcn_logf(r2);
-          lg = (r2 > 0.0f) ? lg : 0.0f;
+          lg = (r2 > 0.0f) ? lg : log2_at_zero;
 #pragma unroll
           for (int r = 0; r < RB; ++r) tile[k][r] = fmaf(q[r], lg, tile[k][r]);
         }
@@ -333,7 +356,7 @@ hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, int64_t n_s
 #define VP_FAR(RBV, TPTV)                                                                                       \
   if (Q32)                                                                                                      \
     k_far32<RBV, TPTV><<<grid, kBlock, 0, st>>>(pl->sxy, Q32, NS, R, r0, pl->xt, pl->yt, NT, per, n_split,    \
-                                                partial);                                                       \
+                                                pl->logtab, partial);                                           \
   else                                                                                                          \
     k_far<RBV, TPTV><<<grid, kBlock, 0, st>>>(pl->sxy, Q, NS, R, r0, pl->xt, pl->yt, NT, per, n_split,        \
                                               pl->logtab, partial)

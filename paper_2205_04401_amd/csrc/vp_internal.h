@@ -91,28 +91,39 @@ __device__ __forceinline__ void koornwinder_emit(double x, double y, Emit&& emit
 // Natural logarithm of x > 0 (normal) in FP64, table-driven (Tang's
 // method): x = m 2^e with m in [1/2, 1); the top eight fraction bits select
 // a sub-interval of width 1/512 with centre c_i; with inv_c_i the double
-// nearest 1/c_i, r = m inv_c_i - 1 (|r| <= 1/512) comes from one FMA and
+// nearest 1/c_i, r = m inv_c_i - 1 = x (inv_c_i 2^-e) - 1 (|r| <= 1/512)
+// comes from one FMA with the scaled table entry, and
 //   log x = e ln2 - log(inv_c_i) + log1p(r),
 // with log1p(r) from its Taylor series through r^5 (truncation < 1e-17).
 // tab[i] = {inv_c_i, -log(inv_c_i)} for i < 256 and tab[256] = {ln2_hi,
 // ln2_lo}, ln2_hi holding 32 bits so that e ln2_hi is exact.  Error: a few
-// units in the last place of the result.  x = 0 gives a finite value
-// (callers mask it); subnormal x is not supported.
+// units in the last place of the result.  x = 0 gives a finite value, the
+// same in every caller (vp_log and vp_log_parts share the reduction);
+// subnormal x is not supported.
 constexpr int kLogTab = 256;
-__device__ __forceinline__ double vp_log(double x, const double2* tab) {
+
+// The two parts of vp_log kept apart: log x = e ln2 + rest, e = exponent of x
+// as a double.  Sums over many x can accumulate e and rest separately.
+__device__ __forceinline__ void vp_log_parts(double x, const double2* tab, double& e_out, double& rest_out) {
   const unsigned hi = (unsigned)__double2hiint(x);
-  const int lo = __double2loint(x);
   const unsigned i = (hi >> 12) & 255u;
-  const double ed = (double)((int)(hi >> 20) - 1022);
-  const double m = __hiloint2double((int)((hi & 0x000FFFFFu) | 0x3FE00000u), lo);
+  const int neg_e = 1022 - (int)(hi >> 20);
   const double2 t = tab[i];
-  const double2 l2 = tab[kLogTab];
-  const double r = fma(m, t.x, -1.0);
+  // m inv_c - 1 with m = x 2^-e: scale the table entry instead of x
+  const double r = fma(x, ldexp(t.x, neg_e), -1.0);
   double p = fma(r, 0.2, -0.25);
   p = fma(r, p, 1.0 / 3.0);
   p = fma(r, p, -0.5);
   p = fma(r * r, p, r);
-  return fma(ed, l2.x, t.y) + fma(ed, l2.y, p);
+  e_out = -(double)neg_e;
+  rest_out = t.y + p;
+}
+
+__device__ __forceinline__ double vp_log(double x, const double2* tab) {
+  double e, rest;
+  vp_log_parts(x, tab, e, rest);
+  const double2 l2 = tab[kLogTab];
+  return fma(e, l2.x, rest) + e * l2.y;
 }
 
 }  // namespace vp

@@ -240,6 +240,30 @@ def test_targets_on_vertices_edges_far_and_ragged(vp_ctx):
     mesh.close()
 
 
+def test_targets_on_far_nodes(vp_ctx):
+    """Targets exactly at far quadrature nodes: the library gives such a pair
+    the same finite kernel value in the far sum and in the subtracted rule,
+    which cancel; the oracle skips the pair in both.  The potentials agree
+    (FP64 and mixed)."""
+    p, q = 3, 5
+    vq, tq = W.unit_square(3, "/")
+    nodes = rules.interp_nodes(p)
+    F = W.sample_density(lambda x, y: 1.0 + x * y, vq, tq, nodes)
+    mesh = vp_ctx.mesh(vq, tq)
+    probe = vp_ctx.plan(mesh, p, q, 1e-12, np.zeros((1, 2)))
+    src = probe.sources()
+    probe.close()
+    tg = np.concatenate([src[::7], np.array([[0.31, 0.52]])])
+    plan = vp_ctx.plan(mesh, p, q, 1e-12, tg)
+    ref = potential.Oracle(vq, tq, p, q, 1e-12).evaluate(F, tg)
+    e64 = rel_linf(plan.execute(F), ref)
+    emx = rel_linf(plan.execute(F, mixed=True), ref)
+    say("targets on far nodes: rel", e64, "mixed", emx)
+    assert e64 <= REL_E2E and emx <= 1e-6
+    plan.close()
+    mesh.close()
+
+
 def test_empty_target_set_and_single_triangle(vp_ctx):
     v = np.array([[0.0, 0.0], [1.0, 0.2], [0.1, 0.9]])
     t = np.array([[0, 2, 1]], dtype=np.int32)  # clockwise: the library swaps B and C
