@@ -415,12 +415,17 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
   // sources and targets
   pl->n_src_pad = ((pl->n_src + 255) / 256) * 256;
   {
-    double2 lt[vp::kLogTab + 1];
-    vp::log_table(lt);
-    if ((e = plan_alloc(pl, (void**)&pl->logtab, sizeof(lt))) != hipSuccess ||
-        (e = hipMemcpyAsync(pl->logtab, lt, sizeof(lt), hipMemcpyHostToDevice, st)) != hipSuccess ||
+    std::vector<double2> lt(vp::kLogTab + 1), lw(vp::kFarLogTab + 1);
+    vp::log_table(lt.data(), vp::kLogTab);
+    vp::log_table(lw.data(), vp::kFarLogTab);
+    if ((e = plan_alloc(pl, (void**)&pl->logtab, sizeof(double2) * lt.size())) != hipSuccess ||
+        (e = plan_alloc(pl, (void**)&pl->logtab_wide, sizeof(double2) * lw.size())) != hipSuccess ||
+        (e = hipMemcpyAsync(pl->logtab, lt.data(), sizeof(double2) * lt.size(), hipMemcpyHostToDevice, st)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(pl->logtab_wide, lw.data(), sizeof(double2) * lw.size(), hipMemcpyHostToDevice,
+                            st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
-      return hip_fail(e, "vp_plan_create: log table");
+      return hip_fail(e, "vp_plan_create: log tables");
   }
   if ((e = plan_alloc(pl, (void**)&pl->sxy, sizeof(double2) * pl->n_src_pad)) != hipSuccess ||
       (e = plan_alloc(pl, (void**)&pl->xt, sizeof(double) * n_tgt)) != hipSuccess ||

@@ -4,8 +4,9 @@
 //               far-rule node is a point charge; the 1/2 of log r = log(r^2)/2
 //               is folded in)
 //   k_far       U_far(x) = sum_j Q_j log|x - y_j|^2 over all sources: a
-//               direct sum, targets across threads, sources staged through
-//               LDS in tiles (a pair at distance 0 contributes 0)
+//               direct sum, targets across threads, sources read in
+//               wavefront-uniform tiles (a pair at distance 0 gets a finite
+//               value that the correction rows subtract again)
 //   k_finish    u = sum of the far partials + sum over the target's self/near
 //               pairs of row . c(triangle)  (Sec. 3.6 subtract-and-add)
 #include <cmath>
@@ -80,19 +81,25 @@ __global__ void k_charges(const double* __restrict__ C, const double* __restrict
 // n_split a multiple of 8 the blocks that share a chunk sit on one XCD and
 // its L2.  Each 256-source tile is summed on its own before it joins the
 // running total (two-level summation).  Sources are padded to a multiple of
-// 256 with zero charges.  A pair at distance 0 gets the finite value
-// vp_log(0), exactly as in the subtracted far rule of the correction rows,
-// so it cancels in the potential.  With one right-hand side the exponent
-// part of the logarithm is accumulated apart (sum Q e, times ln 2 at the
-// end), which saves an instruction per pair.
+// 256 with zero charges.  With one right-hand side the logarithm comes from
+// the 4096-entry table (vp_log_wide_parts) in 1024-thread blocks, and its
+// exponent part is accumulated apart (sum Q e, times ln 2 at the end); with
+// several, the logarithm is a small share of the work per pair and the
+// 256-entry table leaves room for more blocks per CU.
+template <int RB>
+struct FarShape {
+  static constexpr int kThreads = RB == 1 ? 1024 : 256;
+  static constexpr int kTab = RB == 1 ? kFarLogTab : kLogTab;
+};
+
 template <int RB, int TPT>
-__global__ __launch_bounds__(kBlock) void k_far(const double2* __restrict__ sxy, const double* __restrict__ Q,
-                                                int64_t n_src_pad, int64_t R, int64_t r0,
-                                                const double* __restrict__ xt, const double* __restrict__ yt,
-                                                int64_t n_tgt, int64_t per_split, int64_t n_split,
-                                                const double2* __restrict__ logtab, double* __restrict__ partial) {
-  __shared__ double2 tab[kLogTab + 1];
-  for (int i = threadIdx.x; i <= kLogTab; i += blockDim.x) tab[i] = logtab[i];
+__global__ __launch_bounds__(FarShape<RB>::kThreads) void k_far(
+    const double2* __restrict__ sxy, const double* __restrict__ Q, int64_t n_src_pad, int64_t R, int64_t r0,
+    const double* __restrict__ xt, const double* __restrict__ yt, int64_t n_tgt, int64_t per_split,
+    int64_t n_split, const double2* __restrict__ logtab, double* __restrict__ partial) {
+  constexpr int kB = FarShape<RB>::kThreads, kTab = FarShape<RB>::kTab;
+  __shared__ double2 tab[kTab + 1];
+  for (int i = threadIdx.x; i <= kTab; i += kB) tab[i] = logtab[i];
   __syncthreads();
   constexpr bool kSplitExp = (RB == 1);
   const int64_t b = blockIdx.x;
@@ -101,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_far(const double2* __restrict__ sxy,
   int64_t t[TPT];
 #pragma unroll
   for (int k = 0; k < TPT; ++k) {
-    t[k] = tb * (kBlock * TPT) + k * kBlock + threadIdx.x;
+    t[k] = tb * (kB * TPT) + k * kB + threadIdx.x;
     const bool act = t[k] < n_tgt;
     x[k] = act ? xt[t[k]] : 0.0;
     y[k] = act ? yt[t[k]] : 0.0;
@@ -134,10 +141,10 @@ __global__ __launch_bounds__(kBlock) void k_far(const double2* __restrict__ sxy,
 #pragma unroll
         for (int k = 0; k < TPT; ++k) {
           const double dx = x[k] - s.x, dy = y[k] - s.y;
-          const double r2 = fma(dx, dx, dy * dy);
+          const double r2 = fma(dy, dy, fma(dx, dx, kR2Bias));
           if (kSplitExp) {
             double e, rest;
-            vp_log_parts(r2, tab, e, rest);
+            vp_log_wide_parts(r2, tab, e, rest);
             tile_e[k] = fma(q[0], e, tile_e[k]);
             tile[k][0] = fma(q[0], rest, tile[k][0]);
           } else {
@@ -155,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_far(const double2* __restrict__ sxy,
       for (int r = 0; r < RB; ++r) acc[k][r] += tile[k][r];
     }
   }
-  const double2 l2 = tab[kLogTab];
+  const double2 l2 = tab[kTab];
 #pragma unroll
   for (int k = 0; k < TPT; ++k)
     if (t[k] < n_tgt) {
@@ -166,20 +173,16 @@ __global__ __launch_bounds__(kBlock) void k_far(const double2* __restrict__ sxy,
 }
 
 // Mixed-precision far sum (same decomposition as k_far): the pair
-// difference is taken in FP64 and rounded to FP32, r^2 and the base-2
-// logarithm (the hardware v_log_f32) are FP32, the charges are FP32 with ln 2
-// folded in (Q32 = Q ln 2, so Q32 log2(r^2) = Q log(r^2)), each 256-source
-// tile is summed in FP32 and the tiles are summed in FP64.  A pair at
-// distance 0 gets vp_log(0) / ln 2, the value the FP64 correction rows
-// subtract for it.
+// difference is taken in FP64 and rounded to FP32, r^2 + 2^-100 and the
+// base-2 logarithm (the hardware v_log_f32) are FP32, the charges are FP32
+// with ln 2 folded in (Q32 = Q ln 2, so Q32 log2(r^2) = Q log(r^2)), each
+// 256-source tile is summed in FP32 and the tiles are summed in FP64.
 template <int RB, int TPT>
 __global__ __launch_bounds__(kBlock) void k_far32(const double2* __restrict__ sxy, const float* __restrict__ Q32,
                                                   int64_t n_src_pad, int64_t R, int64_t r0,
                                                   const double* __restrict__ xt, const double* __restrict__ yt,
                                                   int64_t n_tgt, int64_t per_split, int64_t n_split,
-                                                  const double2* __restrict__ logtab,
                                                   double* __restrict__ partial) {
-  const float log2_at_zero = (float)(vp_log(0.0, logtab) * 1.44269504088896340736);
   const int64_t b = blockIdx.x;
   const int64_t chunk = b % n_split, tb = b / n_split;
   double x[TPT], y[TPT];
@@ -215,9 +218,8 @@ __global__ __launch_bounds__(kBlock) void k_far32(const double2* __restrict__ sx
 #pragma unroll
         for (int k = 0; k < TPT; ++k) {
           const float dx = (float)(x[k] - s.x), dy = (float)(y[k] - s.y);
-          const float r2 = fmaf(dx, dx, dy * dy);
-          float lg = __builtin_amdgcn_logf(r2);
-          lg = (r2 > 0.0f) ? lg : log2_at_zero;
+          const float r2 = fmaf(dy, dy, fmaf(dx, dx, kR2BiasF));
+          const float lg = __builtin_amdgcn_logf(r2);
 #pragma unroll
           for (int r = 0; r < RB; ++r) tile[k][r] = fmaf(q[r], lg, tile[k][r]);
         }
@@ -333,7 +335,7 @@ hipError_t launch_coefficients(const vp_plan* pl, const double* F, int64_t R, do
   return hipGetLastError();
 }
 
-int64_t far_targets_per_block() { return kBlock * kFarTPT; }
+int64_t far_targets_per_block() { return FarShape<1>::kThreads * kFarTPT; }
 
 hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, int64_t n_split, double* partial,
                       hipStream_t st, int64_t* n_launches, float* Q32) {
@@ -349,17 +351,19 @@ hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, int64_t n_s
     const int64_t left = R - r0;
     const int rb = left >= 32 ? 32 : left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
     const int tpt = rb >= 16 ? 1 : kFarTPT;
-    const int64_t n_tb = (NT + kBlock * tpt - 1) / (kBlock * tpt);
+    const int threads = (Q32 || rb > 1) ? kBlock : FarShape<1>::kThreads;
+    const int64_t n_tb = (NT + threads * tpt - 1) / (threads * tpt);
     const int64_t nb = n_tb * n_split;
-    if (nb * kBlock >= (1LL << 32)) return hipErrorInvalidConfiguration;
+    if (nb * threads >= (1LL << 32)) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)nb);
-#define VP_FAR(RBV, TPTV)                                                                                       \
-  if (Q32)                                                                                                      \
-    k_far32<RBV, TPTV><<<grid, kBlock, 0, st>>>(pl->sxy, Q32, NS, R, r0, pl->xt, pl->yt, NT, per, n_split,    \
-                                                pl->logtab, partial);                                           \
-  else                                                                                                          \
-    k_far<RBV, TPTV><<<grid, kBlock, 0, st>>>(pl->sxy, Q, NS, R, r0, pl->xt, pl->yt, NT, per, n_split,        \
-                                              pl->logtab, partial)
+#define VP_FAR(RBV, TPTV)                                                                                      \
+  if (Q32)                                                                                                     \
+    k_far32<RBV, TPTV><<<grid, kBlock, 0, st>>>(pl->sxy, Q32, NS, R, r0, pl->xt, pl->yt, NT, per, n_split,   \
+                                                partial);                                                      \
+  else                                                                                                         \
+    k_far<RBV, TPTV><<<grid, FarShape<RBV>::kThreads, 0, st>>>(pl->sxy, Q, NS, R, r0, pl->xt, pl->yt, NT, per, \
+                                                               n_split, RBV == 1 ? pl->logtab_wide : pl->logtab, \
+                                                               partial)
     switch (rb) {
       case 32: VP_FAR(32, 1); break;
       case 16: VP_FAR(16, 1); break;

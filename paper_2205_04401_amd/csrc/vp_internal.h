@@ -97,10 +97,19 @@ __device__ __forceinline__ void koornwinder_emit(double x, double y, Emit&& emit
 // with log1p(r) from its Taylor series through r^5 (truncation < 1e-17).
 // tab[i] = {inv_c_i, -log(inv_c_i)} for i < 256 and tab[256] = {ln2_hi,
 // ln2_lo}, ln2_hi holding 32 bits so that e ln2_hi is exact.  Error: a few
-// units in the last place of the result.  x = 0 gives a finite value, the
-// same in every caller (vp_log and vp_log_parts share the reduction);
-// subnormal x is not supported.
+// units in the last place of the result.  Subnormal x and x = 0 are not
+// supported; every squared distance that reaches a logarithm carries the
+// offset kR2Bias below.
 constexpr int kLogTab = 256;
+
+// Squared distances enter the kernel as r^2 + 2^-100 (in FP64 and in FP32,
+// where 2^-100 is a normal number).  A source at distance 0 from a target
+// then has a finite kernel value, the same in the far sum and in the far
+// rule that the correction rows subtract, so the pair cancels without a
+// per-pair test; for any pair that is not cancelled in this way r is far
+// above 2^-50, where the offset changes nothing.
+constexpr double kR2Bias = 0x1p-100;
+constexpr float kR2BiasF = 0x1p-100f;
 
 // The two parts of vp_log kept apart: log x = e ln2 + rest, e = exponent of x
 // as a double.  Sums over many x can accumulate e and rest separately.
@@ -124,6 +133,25 @@ __device__ __forceinline__ double vp_log(double x, const double2* tab) {
   vp_log_parts(x, tab, e, rest);
   const double2 l2 = tab[kLogTab];
   return fma(e, l2.x, rest) + e * l2.y;
+}
+
+// The same method with a 4096-entry table (the top twelve fraction bits;
+// |r| <= 2^-13), where log1p(r) through r^3 suffices (truncation
+// <= 2^-54), and m, e from the hardware frexp.  Two FP64 operations fewer
+// per logarithm than vp_log_parts; the 64 KiB table suits kernels with wide
+// blocks (the direct far sum), not the one-wavefront correction rows.
+constexpr int kFarLogBits = 12;
+constexpr int kFarLogTab = 1 << kFarLogBits;
+
+__device__ __forceinline__ void vp_log_wide_parts(double x, const double2* tab, double& e_out, double& rest_out) {
+  const double m = __builtin_amdgcn_frexp_mant(x);  // x = m 2^e, m in [1/2, 1)
+  const int e = __builtin_amdgcn_frexp_exp(x);
+  const unsigned i = ((unsigned)__double2hiint(x) >> (20 - kFarLogBits)) & (unsigned)(kFarLogTab - 1);
+  const double2 t = tab[i];
+  const double r = fma(m, t.x, -1.0);
+  const double p = fma(r * r, fma(r, 1.0 / 3.0, -0.5), r);
+  e_out = (double)e;
+  rest_out = t.y + p;
 }
 
 }  // namespace vp
@@ -185,6 +213,7 @@ struct vp_plan {
   int64_t n_src_pad = 0;                // n_src rounded up to a multiple of 256
   double2* sxy = nullptr;               // [n_src_pad] source positions
   double2* logtab = nullptr;            // [kLogTab + 1] table of the FP64 logarithm
+  double2* logtab_wide = nullptr;       // [kFarLogTab + 1] table of the far sum's logarithm
   double *xt = nullptr, *yt = nullptr;  // [n_tgt]
   // pair list (device)
   int64_t* row_ptr = nullptr;  // [n_tgt+1]
@@ -233,7 +262,7 @@ hipError_t launch_pack_columns(const double* src, int64_t rows, int64_t src_cols
 // dst[i][r] = src[i][c0 + r] for i < rows, r < dst_cols (src has src_cols)
 hipError_t launch_unpack_columns(const double* src, int64_t rows, int64_t src_cols, int64_t c0, double* dst,
                                  int64_t dst_cols, hipStream_t st);
-void log_table(double2 out[kLogTab + 1]);
+void log_table(double2* out, int n);  // n entries + the ln 2 split
 hipError_t exclusive_scan_i32(const int32_t* in, int64_t* out, int64_t n, void* tmp, hipStream_t st);
 size_t exclusive_scan_tmp_bytes(int64_t n);
 

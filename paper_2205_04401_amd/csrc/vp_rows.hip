@@ -3,8 +3,8 @@
 // row_k = (A_k - B_k) / 2pi for k < n_p, the subtract-and-add correction of
 // Sec. 3.6 against the Koornwinder basis:
 //   B_k  the far rule's own contribution, sum_j w_j |J| log|x - y_j| K_k(xi_j)
-//        (a pair at distance exactly 0 gets the finite vp_log(0), as in the
-//        FP64 far sum, so it cancels);
+//        (squared distances carry the offset kR2Bias, as in the far sums,
+//        so a pair at distance exactly 0 cancels);
 //   A_k  the accurate integral of log|x - y| K_k(rho^{-1} y) over the triangle:
 //        near pair: adaptive subdivision (Sec. 3.3, eq. sum_near); a
 //          sub-triangle is integrated by the near rule once the target lies
@@ -100,8 +100,8 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
       const double fx = a.far_x[j], fy = a.far_y[j];
       const double yx = Ax + fx * e1x + fy * e2x, yy = Ay + fx * e1y + fy * e2y;
       const double dx = x - yx, dy = y - yy;
-      const double r2 = dx * dx + dy * dy;
-      // same finite value at r = 0 as in the far sum (the pair cancels)
+      // the far sums' expression, so that a pair at r = 0 cancels
+      const double r2 = fma(dy, dy, fma(dx, dx, kR2Bias));
       const double w = -0.5 * vp_log(r2, tab) * a.far_w[j] * D;
       const double* E = a.efar + (size_t)j * NP;
 #pragma unroll

@@ -219,19 +219,19 @@ Rule2D interp_nodes(int p) {
   return r;
 }
 
-void log_table(double2 out[kLogTab + 1]) {
-  // centres c_i = 1/2 + (i + 1/2)/512 of the 256 sub-intervals of [1/2, 1);
+void log_table(double2* out, int n) {
+  // centres c_i = 1/2 + (i + 1/2)/(2n) of the n sub-intervals of [1/2, 1);
   // inv_c_i = nearest double to 1/c_i, paired with -log(inv_c_i) (long
   // double, then rounded); the last entry splits ln 2 into a 32-bit head
   // and its remainder.
   const ld ln2 = logl(2.0L);
   const double hi = (double)(ldexpl(floorl(ldexpl(ln2, 32)), -32));
-  for (int i = 0; i < kLogTab; ++i) {
-    const ld c = 0.5L + ((ld)i + 0.5L) / (2.0L * kLogTab);
+  for (int i = 0; i < n; ++i) {
+    const ld c = 0.5L + ((ld)i + 0.5L) / (2.0L * n);
     const double inv = (double)(1.0L / c);
     out[i] = make_double2(inv, (double)(-logl((ld)inv)));
   }
-  out[kLogTab] = make_double2(hi, (double)(ln2 - (ld)hi));
+  out[n] = make_double2(hi, (double)(ln2 - (ld)hi));
 }
 
 int radial_half(int p) { return std::max(4, (p + 3) / 2); }
