@@ -238,6 +238,145 @@ __global__ __launch_bounds__(kBlock) void k_far32(const double2* __restrict__ sx
     }
 }
 
+// Far sum for 16 NT right-hand sides at once on the matrix cores: the sum
+// U[t][r] = sum_j G[t][j] Q[j][r] with G[t][j] = log(r_tj^2) is a product
+// of a generated matrix with the charge matrix.  Each wavefront owns 16 MT
+// targets (MT tiles of 16) and walks its source chunk 4 sources at a time;
+// lane l generates G for target 16 m + (l & 15) and source l >> 4 of the
+// step, i.e. exactly the A operand of a 16x16x4 MFMA, and loads
+// Q[source l >> 4][16 n + (l & 15)], the B operand; every pair costs one
+// logarithm however many right-hand sides share it.  Element v of lane l of
+// the result tile holds RHS l & 15 of target (l >> 4) + 4 v (FP64 MFMA) or
+// 4 (l >> 4) + v (FP32 MFMA).  Source chunks, padding and the XCD-aware
+// block order are those of k_far.
+//   k_far_mfma64  FP64 G (the 4096-entry table logarithm), FP64 MFMA
+//   k_far_mfma32  FP32 G (v_log_f32 of the FP32 r^2, charges times ln 2),
+//                 FP32 MFMA over 256-source tiles, tiles summed in FP64
+typedef double vp_d4 __attribute__((ext_vector_type(4)));
+typedef float vp_f4 __attribute__((ext_vector_type(4)));
+constexpr int kMfmaMT = 4;                               // 16-target tiles per wavefront
+constexpr int kMfmaTargets = (kBlock / 64) * 16 * kMfmaMT;  // targets per block
+
+template <int NT>
+__global__ __launch_bounds__(kBlock, 2) void k_far_mfma64(
+    const double2* __restrict__ sxy, const double* __restrict__ Q, int64_t n_src_pad, int64_t R, int64_t r0,
+    const double* __restrict__ xt, const double* __restrict__ yt, int64_t n_tgt, int64_t per_split,
+    int64_t n_split, const double2* __restrict__ logtab, double* __restrict__ partial) {
+  constexpr int MT = kMfmaMT;
+  __shared__ double2 tab[kFarLogTab + 1];
+  for (int i = threadIdx.x; i <= kFarLogTab; i += kBlock) tab[i] = logtab[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, kk = lane >> 4, nn = lane & 15;
+  const int64_t b = blockIdx.x;
+  const int64_t chunk = b % n_split, tb = b / n_split;
+  const int64_t t0 = tb * kMfmaTargets + (threadIdx.x >> 6) * (16 * MT);
+  double x[MT], y[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int64_t t = t0 + 16 * m + nn;
+    x[m] = t < n_tgt ? xt[t] : 0.0;
+    y[m] = t < n_tgt ? yt[t] : 0.0;
+  }
+  const int64_t s_begin = chunk * per_split;
+  const int64_t s_end = min(n_src_pad, s_begin + per_split);
+  const double2 l2 = tab[kFarLogTab];
+  vp_d4 acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[m][n] = vp_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+  for (int64_t j = s_begin + kk; j < s_end; j += 4) {
+    const double2 s = sxy[j];
+    double q[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) q[n] = Q[j * R + r0 + 16 * n + nn];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const double dx = x[m] - s.x, dy = y[m] - s.y;
+      const double r2 = fma(dy, dy, fma(dx, dx, kR2Bias));
+      double e, rest;
+      vp_log_wide_parts(r2, tab, e, rest);
+      const double g = fma(e, l2.x, fma(e, l2.y, rest));
+#pragma unroll
+      for (int n = 0; n < NT; ++n) acc[m][n] = __builtin_amdgcn_mfma_f64_16x16x4f64(g, q[n], acc[m][n], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t t = t0 + 16 * m + kk + 4 * v;
+      if (t < n_tgt) {
+#pragma unroll
+        for (int n = 0; n < NT; ++n) partial[((size_t)chunk * n_tgt + t) * R + r0 + 16 * n + nn] = acc[m][n][v];
+      }
+    }
+}
+
+template <int NT>
+__global__ __launch_bounds__(kBlock, 2) void k_far_mfma32(
+    const double2* __restrict__ sxy, const float* __restrict__ Q32, int64_t n_src_pad, int64_t R, int64_t r0,
+    const double* __restrict__ xt, const double* __restrict__ yt, int64_t n_tgt, int64_t per_split,
+    int64_t n_split, double* __restrict__ partial) {
+  constexpr int MT = kMfmaMT;
+  const int lane = threadIdx.x & 63, kk = lane >> 4, nn = lane & 15;
+  const int64_t b = blockIdx.x;
+  const int64_t chunk = b % n_split, tb = b / n_split;
+  const int64_t t0 = tb * kMfmaTargets + (threadIdx.x >> 6) * (16 * MT);
+  double x[MT], y[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int64_t t = t0 + 16 * m + nn;
+    x[m] = t < n_tgt ? xt[t] : 0.0;
+    y[m] = t < n_tgt ? yt[t] : 0.0;
+  }
+  const int64_t s_begin = chunk * per_split;
+  const int64_t s_end = min(n_src_pad, s_begin + per_split);
+  vp_d4 acc[MT][NT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[m][n] = vp_d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t j0 = s_begin; j0 < s_end; j0 += 256) {
+    vp_f4 tile[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int n = 0; n < NT; ++n) tile[m][n] = vp_f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 2
+    for (int64_t j = j0 + kk; j < j0 + 256; j += 4) {
+      const double2 s = sxy[j];
+      float q[NT];
+#pragma unroll
+      for (int n = 0; n < NT; ++n) q[n] = Q32[j * R + r0 + 16 * n + nn];
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const float dx = (float)(x[m] - s.x), dy = (float)(y[m] - s.y);
+        const float g = __builtin_amdgcn_logf(fmaf(dy, dy, fmaf(dx, dx, kR2BiasF)));
+#pragma unroll
+        for (int n = 0; n < NT; ++n) tile[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, q[n], tile[m][n], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int n = 0; n < NT; ++n)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[m][n][v] += (double)tile[m][n][v];
+  }
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t t = t0 + 16 * m + 4 * kk + v;
+      if (t < n_tgt) {
+#pragma unroll
+        for (int n = 0; n < NT; ++n) partial[((size_t)chunk * n_tgt + t) * R + r0 + 16 * n + nn] = acc[m][n][v];
+      }
+    }
+}
+
 __global__ void k_to_f32_ln2(const double* __restrict__ Q, int64_t n, float* __restrict__ Q32) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
@@ -344,13 +483,35 @@ hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, int64_t n_s
   int64_t per = (NS + n_split - 1) / n_split;
   per = ((per + 255) / 256) * 256;
   if (Q32) k_to_f32_ln2<<<blocks_for(NS * R), kBlock, 0, st>>>(Q, NS * R, Q32);
-  // RB right-hand sides share each logarithm; wide blocks run one target
-  // per thread to stay within the register file
   int64_t r0 = 0;
+  // blocks of 16, 32 or 64 right-hand sides on the matrix cores
+  while (R - r0 >= 16) {
+    const int64_t left = R - r0;
+    const int nt = left >= 64 ? 4 : left >= 32 ? 2 : 1;
+    const int64_t nb = (NT + kMfmaTargets - 1) / kMfmaTargets * n_split;
+    if (nb * kBlock >= (1LL << 32)) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)nb);
+#define VP_FAR_MFMA(NTV)                                                                                     \
+  if (Q32)                                                                                                   \
+    k_far_mfma32<NTV><<<grid, kBlock, 0, st>>>(pl->sxy, Q32, NS, R, r0, pl->xt, pl->yt, NT, per, n_split,  \
+                                               partial);                                                     \
+  else                                                                                                       \
+    k_far_mfma64<NTV><<<grid, kBlock, 0, st>>>(pl->sxy, Q, NS, R, r0, pl->xt, pl->yt, NT, per, n_split,    \
+                                               pl->logtab_wide, partial)
+    switch (nt) {
+      case 4: VP_FAR_MFMA(4); break;
+      case 2: VP_FAR_MFMA(2); break;
+      default: VP_FAR_MFMA(1); break;
+    }
+#undef VP_FAR_MFMA
+    if (n_launches) ++*n_launches;
+    r0 += 16 * nt;
+  }
+  // the remaining right-hand sides on the vector ALUs
   while (r0 < R) {
     const int64_t left = R - r0;
-    const int rb = left >= 32 ? 32 : left >= 16 ? 16 : left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
-    const int tpt = rb >= 16 ? 1 : kFarTPT;
+    const int rb = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+    const int tpt = kFarTPT;  // RB right-hand sides share each logarithm
     const int threads = (Q32 || rb > 1) ? kBlock : FarShape<1>::kThreads;
     const int64_t n_tb = (NT + threads * tpt - 1) / (threads * tpt);
     const int64_t nb = n_tb * n_split;
@@ -365,8 +526,6 @@ hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, int64_t n_s
                                                                n_split, RBV == 1 ? pl->logtab_wide : pl->logtab, \
                                                                partial)
     switch (rb) {
-      case 32: VP_FAR(32, 1); break;
-      case 16: VP_FAR(16, 1); break;
       case 8: VP_FAR(8, kFarTPT); break;
       case 4: VP_FAR(4, kFarTPT); break;
       case 2: VP_FAR(2, kFarTPT); break;

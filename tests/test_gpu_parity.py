@@ -183,6 +183,42 @@ def test_c1_multi_rhs_and_device_pointers(c1):
     assert np.array_equal(ud, u3)
 
 
+def c1_oracle_u(c1, F):
+    """Oracle potential of the C1 targets for density F, reusing the pairs
+    and rows the fixture computed."""
+    o = c1["o"]
+    c = o.coefficients(F)
+    pos, charge = o.far_sources(c)
+    u = o.far_sum(pos, charge, c1["tg"])[:, 0] / (2 * math.pi)
+    for i, t, k in c1["pairs"]:
+        u[i] += c1["rows"][(i, t)] @ c[t]
+    return u
+
+
+def test_c1_many_rhs_matrix_core_blocks(c1):
+    """87 right-hand sides: the far sum runs blocks of 64 and 16 on the
+    matrix cores (FP64 MFMA, and FP32 MFMA in mixed precision) and the last
+    seven on the vector ALUs (4 + 2 + 1).  Every column matches its
+    single-RHS evaluation; three columns, one from each kind of block, also
+    match the oracle."""
+    rng = np.random.default_rng(87)
+    base, R = c1["F"], 87
+    coef = rng.uniform(-1.0, 1.0, (R, 3))
+    FR = np.ascontiguousarray(np.stack(
+        [coef[r, 0] * base + coef[r, 1] + coef[r, 2] * np.sin(3.0 * base + r) for r in range(R)], -1))
+    plan = c1["plan"]
+    u64 = plan.execute(FR)
+    umx = plan.execute(FR, mixed=True)
+    e64 = emx = 0.0
+    for r in range(R):
+        ur = plan.execute(np.ascontiguousarray(FR[:, :, r]))
+        e64 = max(e64, rel_linf(u64[:, r], ur))
+        emx = max(emx, rel_linf(umx[:, r], ur))
+    eo = max(rel_linf(u64[:, r], c1_oracle_u(c1, np.ascontiguousarray(FR[:, :, r]))) for r in (5, 70, 86))
+    say("c1 87 RHS: fp64 vs single", e64, "mixed vs fp64 single", emx, "fp64 vs oracle", eo)
+    assert e64 <= REL_FAR and emx <= 1e-6 and eo <= REL_E2E
+
+
 def test_c1_deterministic(c1, vp_ctx):
     plan2 = vp_ctx.plan(c1["mesh"], 4, 8, 1e-13, c1["tg"])
     a, b = c1["plan"].pairs(), plan2.pairs()
