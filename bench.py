@@ -10,7 +10,10 @@ timed region; the output stays on the device.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--q 8] [--sweep]
 
 Prints one JSON line (the contract); --sweep first prints one line per far
-order q (the near/far trade-off, Sec. 4.2).
+order q (the near/far trade-off, Sec. 4.2).  Beside the FP64 headline the
+line carries the mixed-precision path, a batched section (64 densities per
+evaluation, far sum on the matrix cores), the serving run and the oracle's
+own rate on the host.
 """
 
 import argparse
@@ -28,6 +31,9 @@ sys.path.insert(0, ROOT)
 METRIC = "potential evals/s at rel err 1e-11 (FP64) vs 1e-6 (mixed); p50/p99 solve latency"
 # MI355X published peaks
 PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
 FLOPS_PER_PAIR = 8  # 2 sub, 1 mul, 1 FMA (r^2), 1 FMA (accumulate), log counted as 1
 
 
@@ -60,14 +66,87 @@ def cpu_baseline(vq, tq, tg, F, p, q, eps, n_sample):
                       f"their self/near corrections), {dt:.1f} s single-threaded"}
 
 
+def batched(ctx, mesh, tg_d, vq, tq, p, q, R, steps):
+    """Many densities per evaluation: R seeded Gaussian-sum densities (seeds
+    1000...), plan built once, one step = one vp_execute over all R.  The far
+    sum runs in blocks of 64 right-hand sides on the matrix cores (FP64 MFMA,
+    or FP32 MFMA in mixed precision); its roofline counts 2 flops per
+    (pair, RHS) against the MFMA peak of that precision."""
+    import torch
+    from paper_2205_04401_amd import vp
+    from paper_2205_04401_amd import workloads as W
+    nodes = vp.ref_nodes(p)
+    FR = np.ascontiguousarray(np.stack(
+        [W.sample_density(W.gaussian_sum(1000 + r, vq, tq), vq, tq, nodes) for r in range(R)], -1))
+    FR_d = torch.from_numpy(FR).cuda()
+    out = []
+    for mixed, eps_plan in ((False, 1e-13), (True, 1e-8)):
+        plan = ctx.plan(mesh, p, q, eps_plan, tg_d)
+        info = plan.info()
+        u = torch.empty((info["n_tgt"], R), dtype=torch.float64, device="cuda:0")
+        plan.execute(FR_d, out=u, mixed=mixed)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.execute(FR_d, out=u, mixed=mixed)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        tm = ctx.timings()
+        ctx.profile(False)
+        plan.close()
+        far_s = tm["far"][0] / 1e3 / steps
+        pair_rhs = info["n_src"] * info["n_tgt"] * R
+        peak = PEAK_FP32_MFMA_TFLOPS if mixed else PEAK_FP64_MFMA_TFLOPS
+        achieved = 2.0 * pair_rhs / far_s / 1e12
+        out.append({
+            "precision": "mixed" if mixed else "fp64", "plan_eps": eps_plan, "n_rhs": R,
+            "evals_per_s": info["n_tgt"] * R / dt, "ms_per_execute": dt * 1e3,
+            "plan_ms": info["ms_classify"] + info["ms_rows"],
+            "far_pair_rhs_per_s": pair_rhs / far_s,
+            "far_roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                             "frac": achieved / peak, "flops_per_pair_rhs": 2,
+                             "kernel": "k_far_mfma32<4>" if mixed else "k_far_mfma64<4>"},
+            "breakdown_ms": {k: v[0] / steps for k, v in tm.items() if v[1]},
+        })
+        print(json.dumps({"batched": out[-1]}), flush=True)
+    return out
+
+
+def finish_roofline(info, tm, steps):
+    """Correction apply + partial-sum join (k_finish), one RHS: algorithmic
+    HBM bytes = far partials (far_split per target) + rows + row pointers +
+    pair triangles + coefficients + output, against the HBM peak."""
+    n_tgt, n_pairs, n_p = info["n_tgt"], info["n_pairs"], info["n_p"]
+    nbytes = 8 * (info["far_split"] * n_tgt + n_pairs * n_p + (n_tgt + 1) + info["n_tri"] * n_p + n_tgt) + 4 * n_pairs
+    sec = tm["finish"][0] / 1e3 / steps
+    achieved = nbytes / sec / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS, "bytes_per_launch": nbytes, "avg_launch_ms": sec * 1e3,
+            "kernel": "k_finish<6>"}
+
+
+def far_kernel_digest():
+    """First 16 hex digits of the SHA-256 of the source text the FP64
+    one-RHS far kernel is built from: FarShape and k_far in vp_exec.hip,
+    and the bias constants and the wide-table logarithm in vp_internal.h."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2205_04401_amd", "csrc")
+    exe = open(os.path.join(csrc, "vp_exec.hip")).read()
+    hdr = open(os.path.join(csrc, "vp_internal.h")).read()
+    a = exe.index("template <int RB>\nstruct FarShape")
+    b = exe.index("\n}\n", exe.index("void k_far(", a)) + 3
+    c = hdr.index("constexpr double kR2Bias")
+    d = hdr.index("\n}\n", hdr.index("void vp_log_wide_parts(", c)) + 3
+    return hashlib.sha256((exe[a:b] + hdr[c:d]).encode()).hexdigest()[:16]
+
+
 def measured_traffic(q):
     """HBM bytes per far-kernel launch from the committed counter summary
     (two rocprofv3 --pmc runs, FETCH_SIZE and WRITE_SIZE, calibrated on a
     plain copy), or None when that summary was taken on another workload or
     on a different version of the kernel source."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"k_far_fp64_star20k_q{q}_counters.md")
-    src = os.path.join(ROOT, "paper_2205_04401_amd", "csrc", "vp_exec.hip")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -75,7 +154,7 @@ def measured_traffic(q):
         if ":" in line and not line.startswith(("|", "#", "`")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    digest = far_kernel_digest()
     if fields.get("kernel_source_sha256_16") != digest or "traffic_bytes_per_launch" not in fields:
         return None
     return float(fields["traffic_bytes_per_launch"])
@@ -190,6 +269,8 @@ def run(args):
         "pairs_per_target": info["n_pairs"] / n_tgt,
         "near_subtri_per_near_pair": info["near_subtri"] / max(1, info["n_pairs"] - info["n_self"]),
         "self_panels_per_self_pair": info["self_panels"] / max(1, info["n_self"]),
+        "correction_apply_roofline": finish_roofline(info, tm, args.steps),
+        "rows_pairs_per_s": info["n_pairs"] / (tm["rows"][0] / 1e3 / args.steps),
     }
     # mixed precision: FP32 far sum, FP64 rows, plan at eps = 1e-8 (its error
     # is bounded by 1e-6 against the FP64 eps = 1e-13 oracle in the GPU tests)
@@ -203,6 +284,8 @@ def run(args):
     }
     if sweep:
         result["q_sweep"] = sweep
+    if args.batched_rhs:
+        result["batched"] = batched(ctx, mesh, tg_d, vq, tq, p, q, args.batched_rhs, args.batched_steps)
     if not args.no_serving:
         from paper_2205_04401_amd import serving
         result["serving"] = [serving.run(ctx, n_requests=args.serving_requests, mixed=m) for m in (False, True)]
@@ -224,6 +307,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=160)
+    ap.add_argument("--batched-rhs", type=int, default=64, help="densities of the batched section (0: skip)")
+    ap.add_argument("--batched-steps", type=int, default=2)
     ap.add_argument("--copy-probe", action="store_true", help="only run a 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))

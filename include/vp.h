@@ -111,6 +111,7 @@ typedef struct {
   double eps;
   double ms_classify;      /* device time of the near-list construction */
   double ms_rows;          /* device time of the correction-row precompute */
+  int64_t far_split;       /* source chunks of the far sum (partial sums per target and RHS) */
 } vp_plan_stats;
 
 /* Context on HIP device `device`.  `hip_stream_or_null` is a hipStream_t the
@@ -214,7 +215,7 @@ typedef enum {
   VP_STAGE_CLASSIFY = 0, /* near-field pair list (Sec. 4.1) */
   VP_STAGE_ROWS = 1,     /* correction rows (Sec. 3.3, 3.4, 3.6) */
   VP_STAGE_COEF = 2,     /* coefficients and far charges (Sec. 2.2, 3.6) */
-  VP_STAGE_FAR = 3,      /* far-field direct sum: one k_far launch per RHS block */
+  VP_STAGE_FAR = 3,      /* far-field direct sum: one launch per RHS block */
   VP_STAGE_FINISH = 4,   /* partial sums + corrections */
   VP_N_STAGES = 5
 } vp_stage;

@@ -542,6 +542,7 @@ vp_status vp_plan_info(const vp_plan* pl, vp_plan_stats* out) {
   out->eps = pl->eps;
   out->ms_classify = pl->ms_classify;
   out->ms_rows = pl->ms_rows;
+  out->far_split = vp::far_split(pl);
   return VP_OK;
 }
 

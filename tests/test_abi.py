@@ -26,6 +26,29 @@ def test_header_and_binding_agree():
     assert declared_functions() == sorted(vp.EXPORTS)
 
 
+C_TYPES = {"double": ctypes.c_double, "int": ctypes.c_int, "int32_t": ctypes.c_int32,
+           "int64_t": ctypes.c_int64, "uint32_t": ctypes.c_uint32}
+
+
+def header_struct(name):
+    """(field, ctypes type) of a `typedef struct {...} name;` in vp.h, in order."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + r"\s*;", src).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ctype, names = decl.split(None, 1)
+        fields += [(n.strip(), C_TYPES[ctype]) for n in names.split(",")]
+    return fields
+
+
+@pytest.mark.parametrize("cname, pyclass", [("vp_plan_opts", vp.PlanOpts), ("vp_plan_stats", vp.PlanStats)])
+def test_struct_layouts_match_header(cname, pyclass):
+    assert header_struct(cname) == list(pyclass._fields_)
+
+
 def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(vp.LIB_PATH)
     for name in declared_functions():
