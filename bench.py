@@ -113,6 +113,40 @@ def batched(ctx, mesh, tg_d, vq, tq, p, q, R, steps):
     return out
 
 
+# Algorithmic FP64 flops of one node evaluation in the correction rows:
+# geometry and weight 10, the log counted as 1, then per basis function
+# 3 for the Koornwinder recurrence and 2 to accumulate (n_p functions).
+def rows_flops_per_node(n_p):
+    return 11 + 5 * n_p
+
+
+def stage_rooflines(info, tm, steps, q_near=7, n_l=16):
+    """Every stage of the step against the resource that bounds it:
+    correction rows (FP64 vector, the node-evaluation convention above),
+    near lists and coefficients/charges (algorithmic HBM bytes)."""
+    n_p, n_tgt, n_pairs, T = info["n_p"], info["n_tgt"], info["n_pairs"], info["n_tri"]
+    n_r = 2 * max(4, (info["p"] + 3) // 2)
+    nodes = (info["near_subtri"] * q_near * q_near + info["self_panels"] * n_l * n_r + n_pairs * info["n_f"])
+    out = {}
+    sec = tm["rows"][0] / 1e3 / steps
+    ach = nodes * rows_flops_per_node(n_p) / sec / 1e12
+    out["k_rows"] = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "node_evaluations": nodes,
+                     "flops_per_node": rows_flops_per_node(n_p), "avg_ms": sec * 1e3}
+    # near lists: targets read in the count and fill passes, CSR and pairs written
+    nbytes = 2 * 16 * n_tgt + 8 * (n_tgt + 1) + 9 * n_pairs
+    sec = tm["classify"][0] / 1e3 / steps
+    out["near_lists"] = {"bound": "hbm", "achieved": nbytes / sec / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": nbytes / sec / 1e9 / PEAK_HBM_GBS, "bytes": nbytes, "avg_ms": sec * 1e3}
+    # coefficients and charges, one RHS: F in, C out, C in, Q out
+    nbytes = 8 * (3 * T * n_p + info["n_src"])
+    sec = tm["coef"][0] / 1e3 / steps
+    out["coefficients_charges"] = {"bound": "hbm", "achieved": nbytes / sec / 1e9, "peak": PEAK_HBM_GBS,
+                                   "unit": "GB/s", "frac": nbytes / sec / 1e9 / PEAK_HBM_GBS, "bytes": nbytes,
+                                   "avg_ms": sec * 1e3}
+    return out
+
+
 def finish_roofline(info, tm, steps):
     """Correction apply + partial-sum join (k_finish), one RHS: algorithmic
     HBM bytes = far partials (far_split per target) + rows + row pointers +
@@ -270,6 +304,7 @@ def run(args):
         "near_subtri_per_near_pair": info["near_subtri"] / max(1, info["n_pairs"] - info["n_self"]),
         "self_panels_per_self_pair": info["self_panels"] / max(1, info["n_self"]),
         "correction_apply_roofline": finish_roofline(info, tm, args.steps),
+        "stage_rooflines": stage_rooflines(info, tm, args.steps),
         "rows_pairs_per_s": info["n_pairs"] / (tm["rows"][0] / 1e3 / args.steps),
     }
     # mixed precision: FP32 far sum, FP64 rows, plan at eps = 1e-8 (its error
@@ -284,6 +319,11 @@ def run(args):
     }
     if sweep:
         result["q_sweep"] = sweep
+    if args.ablation:
+        from paper_2205_04401_amd import ablation
+        res = ablation.run(ctx)
+        print(ablation.table(res), file=sys.stderr, flush=True)
+        result["ablation"] = {k: v for k, v in res.items() if k not in ("problem", "sample_same", "sample_stag")}
     if args.batched_rhs:
         result["batched"] = batched(ctx, mesh, tg_d, vq, tq, p, q, args.batched_rhs, args.batched_steps)
     if not args.no_serving:
@@ -309,6 +349,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=160)
     ap.add_argument("--batched-rhs", type=int, default=64, help="densities of the batched section (0: skip)")
     ap.add_argument("--batched-steps", type=int, default=2)
+    ap.add_argument("--ablation", action="store_true",
+                    help="ellipse vs naive-ball near field, staggered vs same-mesh targets (star, 5k triangles)")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))

@@ -92,7 +92,16 @@ typedef struct {
   int depth_cap;    /* maximum subdivision depth of a near pair (default 50) */
   int dyadic_cap;   /* maximum dyadic levels per side of a self piece (default 60) */
   uint32_t flags;   /* VP_DEVICE_PTRS: tgt_xy of vp_plan_create is a device pointer (default 0) */
+  int near_model;   /* VP_NEAR_ELLIPSES (default): the union of Bernstein ellipses of Sec. 4.1;
+                       VP_NEAR_BALL: the naive near field the paper compares against (the opening
+                       of Sec. 4; the superscript-0 setting of Table near_corr), for ablation: a
+                       target is near a triangle, and a near sub-triangle is split, when it lies
+                       within ball_factor * R of the centroid c, R = the largest vertex distance
+                       from c */
+  double ball_factor; /* kappa of VP_NEAR_BALL (default 2.0; 0 < kappa <= 64) */
 } vp_plan_opts;
+
+enum { VP_NEAR_ELLIPSES = 0, VP_NEAR_BALL = 1 };
 
 /* Sizes and statistics of a plan. */
 typedef struct {

@@ -82,10 +82,19 @@ class Oracle:
     C_N the paper does not tabulate), q_near = points per direction of the
     rule used on sub-triangles (N_n = 2 q_near - 1), n_l = Gauss-Legendre
     points per arc-length panel, tau = barycentric tolerance of the self test.
+    near_model = "ellipse" (the union of Bernstein ellipses, Sec. 4.1) or
+    "ball" (the naive near field the paper compares against, the opening of Sec. 4 and
+    the superscript-0 setting of Table near_corr): a target is near a
+    triangle, and a sub-triangle is split, when the target lies within
+    ball_factor times R of the centroid c, R = the largest vertex distance
+    from c (reading: the paper tunes the ball's size, not its shape).
     """
 
     def __init__(self, vert, tri, p, q, eps, c_n=1.0, q_near=7, n_l=16, tau=1e-13,
-                 depth_cap=50, dyadic_cap=60):
+                 depth_cap=50, dyadic_cap=60, near_model="ellipse", ball_factor=2.0):
+        if near_model not in ("ellipse", "ball"):
+            raise ValueError("near_model must be 'ellipse' or 'ball'")
+        self.near_model, self.ball_factor = near_model, float(ball_factor)
         self.p, self.q, self.eps, self.c_n = int(p), int(q), float(eps), float(c_n)
         self.q_near, self.n_l, self.tau = int(q_near), int(n_l), float(tau)
         self.depth_cap, self.dyadic_cap = int(depth_cap), int(dyadic_cap)
@@ -175,6 +184,21 @@ class Oracle:
                 return True
         return False
 
+    def in_ball(self, x, P3):
+        """True if x lies within ball_factor R of the centroid c of the
+        triangle P3[0..2], R = max_i |P3[i] - c| (the naive near field).
+        Distances as sqrt(dx^2 + dy^2), so that a decision is the same in
+        any IEEE evaluation of this formula."""
+        cx = (P3[0][0] + P3[1][0] + P3[2][0]) / 3.0
+        cy = (P3[0][1] + P3[1][1] + P3[2][1]) / 3.0
+
+        def dist(ax, ay):
+            dx, dy = ax - cx, ay - cy
+            return math.sqrt(dx * dx + dy * dy)
+
+        R = max(dist(P3[i][0], P3[i][1]) for i in range(3))
+        return dist(x[0], x[1]) < self.ball_factor * R
+
     def barycentric(self, t_idx, x):
         """Barycentric coordinates (lambda_A, lambda_B, lambda_C) of x with
         respect to triangle t_idx."""
@@ -187,7 +211,8 @@ class Oracle:
         triangles ascending.  Self: x in the closure of the triangle, up to a
         barycentric tolerance tau (a target on a shared edge or vertex is self
         for every triangle containing it).  Near: not self and inside the
-        ellipse union of the far rule (N = 2q - 1).  Everything else is far.
+        ellipse union of the far rule (N = 2q - 1), or, for the ball model,
+        inside the naive ball (``in_ball``).  Everything else is far.
         The tests are those of ``barycentric`` and ``in_ellipses``, written
         over all triangles at once."""
         x = np.asarray(x, dtype=np.float64)
@@ -200,12 +225,22 @@ class Oracle:
         is_self = lam_min >= -self.tau
         N = 2 * self.q - 1
         is_near = np.zeros(self.T, dtype=bool)
-        for e, (P, Q) in enumerate(((self.A, self.B), (self.B, self.C), (self.C, self.A))):
-            rho = (self.far_what[e] * self.D / (self.eps * self.c_n)) ** (1.0 / N)
-            ell = np.hypot(Q[:, 0] - P[:, 0], Q[:, 1] - P[:, 1])
-            thr = 0.5 * ell * (rho + 1.0 / rho)
-            fs = np.hypot(x[0] - P[:, 0], x[1] - P[:, 1]) + np.hypot(x[0] - Q[:, 0], x[1] - Q[:, 1])
-            is_near |= (rho > 1.0) & (fs < thr)
+        if self.near_model == "ball":
+            c = (self.A + self.B + self.C) / 3.0
+
+            def dist(P):
+                d = P - c
+                return np.sqrt(d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1])
+
+            R = np.maximum(np.maximum(dist(self.A), dist(self.B)), dist(self.C))
+            is_near = dist(np.broadcast_to(x, c.shape)) < self.ball_factor * R
+        else:
+            for e, (P, Q) in enumerate(((self.A, self.B), (self.B, self.C), (self.C, self.A))):
+                rho = (self.far_what[e] * self.D / (self.eps * self.c_n)) ** (1.0 / N)
+                ell = np.hypot(Q[:, 0] - P[:, 0], Q[:, 1] - P[:, 1])
+                thr = 0.5 * ell * (rho + 1.0 / rho)
+                fs = np.hypot(x[0] - P[:, 0], x[1] - P[:, 1]) + np.hypot(x[0] - Q[:, 0], x[1] - Q[:, 1])
+                is_near |= (rho > 1.0) & (fs < thr)
         is_near &= ~is_self
         out = [(int(t), 0 if is_self[t] else 1) for t in np.nonzero(is_self | is_near)[0]]
         return out
@@ -248,7 +283,11 @@ class Oracle:
                 ref_area2 = abs((b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]))
                 area2 = ref_area2 * D
                 P3 = to_physical(A, B, C, np.stack([a, b, c]))
-                if depth < self.depth_cap and self.in_ellipses(x, P3, area2, self.near_what, Nn):
+                if self.near_model == "ball":
+                    split = self.in_ball(x, P3)
+                else:
+                    split = self.in_ellipses(x, P3, area2, self.near_what, Nn)
+                if depth < self.depth_cap and split:
                     mab, mbc, mca = (a + b) / 2, (b + c) / 2, (c + a) / 2
                     stack.extend([(a, mab, mca, depth + 1), (mab, b, mbc, depth + 1),
                                   (mca, mbc, c, depth + 1), (mbc, mca, mab, depth + 1)])

@@ -46,6 +46,8 @@ vp_plan_opts default_opts() {
   o.depth_cap = 50;
   o.dyadic_cap = 60;
   o.flags = 0;
+  o.near_model = VP_NEAR_ELLIPSES;
+  o.ball_factor = 2.0;
   return o;
 }
 
@@ -339,7 +341,9 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
                 (long long)((int64_t)q * q * mesh->n_tri));
   vp_plan_opts o = opts ? *opts : default_opts();
   if (!(o.c_n > 0.0) || o.q_near < 2 || o.q_near > vp::kMaxQ || o.n_l < 2 || o.n_l > 64 || !(o.tau >= 0.0) ||
-      o.depth_cap < 1 || o.depth_cap > 60 || o.dyadic_cap < 1 || o.dyadic_cap > 100)
+      o.depth_cap < 1 || o.depth_cap > 60 || o.dyadic_cap < 1 || o.dyadic_cap > 100 ||
+      (o.near_model != VP_NEAR_ELLIPSES && o.near_model != VP_NEAR_BALL) ||
+      (o.near_model == VP_NEAR_BALL && !(o.ball_factor > 0.0 && o.ball_factor <= 64.0)))
     return fail(VP_EINVAL, "vp_plan_create: invalid options");
   VP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t st = ctx->stream;

@@ -88,6 +88,41 @@ __device__ __forceinline__ void koornwinder_emit(double x, double y, Emit&& emit
   }
 }
 
+// The naive ball test of the near-field ablation (near: within kappa R of
+// the centroid c, R = the largest vertex distance from c), evaluated with
+// separately rounded operations in a fixed order (no contraction into
+// FMA), so that its decisions equal those of a plain IEEE evaluation of
+// the same formulas: vertex = (A + xi1 (B - A)) + xi2 (C - A),
+// c = ((p0 + p1) + p2) / 3, distances sqrt(dx dx + dy dy).
+__device__ __forceinline__ double ball_dist(double ax, double ay, double bx, double by) {
+  const double dx = __dadd_rn(ax, -bx), dy = __dadd_rn(ay, -by);
+  return sqrt(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)));
+}
+
+__device__ __forceinline__ bool in_ball3(double x, double y, const double px[3], const double py[3], double kappa) {
+  const double gx = __dadd_rn(__dadd_rn(px[0], px[1]), px[2]) / 3.0;
+  const double gy = __dadd_rn(__dadd_rn(py[0], py[1]), py[2]) / 3.0;
+  const double R = fmax(fmax(ball_dist(px[0], py[0], gx, gy), ball_dist(px[1], py[1], gx, gy)),
+                        ball_dist(px[2], py[2], gx, gy));
+  return ball_dist(x, y, gx, gy) < __dmul_rn(kappa, R);
+}
+
+// Ball test of the sub-triangle (sa, sb, ss) of triangle A + xi1 e1 + xi2 e2:
+// reference vertices (sa, sb), (sa + ss, sb), (sa, sb + ss) (exact dyadic
+// values), each mapped directly.
+__device__ __forceinline__ bool in_ball_sub(double x, double y, double Ax, double Ay, double e1x, double e1y,
+                                            double e2x, double e2y, double sa, double sb, double ss,
+                                            double kappa) {
+  const double r1[3] = {sa, sa + ss, sa}, r2[3] = {sb, sb, sb + ss};
+  double px[3], py[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    px[i] = __dadd_rn(__dadd_rn(Ax, __dmul_rn(r1[i], e1x)), __dmul_rn(r2[i], e2x));
+    py[i] = __dadd_rn(__dadd_rn(Ay, __dmul_rn(r1[i], e1y)), __dmul_rn(r2[i], e2y));
+  }
+  return in_ball3(x, y, px, py, kappa);
+}
+
 // Natural logarithm of x > 0 (normal) in FP64, table-driven (Tang's
 // method): x = m 2^e with m in [1/2, 1); the top eight fraction bits select
 // a sub-interval of width 1/512 with centre c_i; with inv_c_i the double

@@ -168,8 +168,8 @@ __global__ void k_tri_ellipses(const double* __restrict__ ax, const double* __re
                                const double* __restrict__ bx, const double* __restrict__ by,
                                const double* __restrict__ cx, const double* __restrict__ cy,
                                const double* __restrict__ det, int64_t n_tri, double w0, double w1, double w2,
-                               double eps_cn, double inv_order, double* thr /* [3][n_tri] */,
-                               double* box /* [4][n_tri] */) {
+                               double eps_cn, double inv_order, int ball, double kappa,
+                               double* thr /* [3][n_tri] */, double* box /* [4][n_tri] */) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_tri) return;
   const double px[3] = {ax[t], bx[t], cx[t]};
@@ -185,6 +185,26 @@ __global__ void k_tri_ellipses(const double* __restrict__ ax, const double* __re
   x1 += pad;
   y0 -= pad;
   y1 += pad;
+  if (ball) {
+    // naive near field: the ball of radius kappa R about the centroid (the
+    // test itself is in_ball3; this is its bounding box)
+    const double gx = (px[0] + px[1] + px[2]) / 3.0, gy = (py[0] + py[1] + py[2]) / 3.0;
+    double R = 0.0;
+    for (int e = 0; e < 3; ++e) R = fmax(R, sqrt((px[e] - gx) * (px[e] - gx) + (py[e] - gy) * (py[e] - gy)));
+    const double rad = kappa * R * (1.0 + 1e-9) + pad;
+    x0 = fmin(x0, gx - rad);
+    x1 = fmax(x1, gx + rad);
+    y0 = fmin(y0, gy - rad);
+    y1 = fmax(y1, gy + rad);
+    thr[t] = kappa * R;
+    thr[n_tri + t] = -1.0;
+    thr[2 * n_tri + t] = -1.0;
+    box[t] = x0;
+    box[n_tri + t] = y0;
+    box[2 * n_tri + t] = x1;
+    box[3 * n_tri + t] = y1;
+    return;
+  }
   for (int e = 0; e < 3; ++e) {
     const double Px = px[e], Py = py[e], Qx = px[(e + 1) % 3], Qy = py[(e + 1) % 3];
     const double rho = pow(wh[e] * D / eps_cn, inv_order);
@@ -307,6 +327,8 @@ __global__ void k_cell_sort(const int64_t* __restrict__ ptr, int64_t n_cells, in
 struct TriView {
   const double *ax, *ay, *bx, *by, *cx, *cy, *det, *thr;
   int64_t n_tri;
+  int ball;      // naive ball model (in_ball3)
+  double kappa;  // its factor
 };
 
 // 0 = self, 1 = near, 2 = far
@@ -319,6 +341,10 @@ __device__ __forceinline__ int classify(const TriView& tv, int32_t t, double x, 
   const double xi2 = (e1x * d1 - e1y * d0) / D;
   const double lmin = fmin(fmin(1.0 - xi1 - xi2, xi1), xi2);
   if (lmin >= -tau) return 0;
+  if (tv.ball) {
+    const double px[3] = {Ax, Bx, Cx}, py[3] = {Ay, By, Cy};
+    return in_ball3(x, y, px, py, tv.kappa) ? 1 : 2;
+  }
   const double px[3] = {Ax, Bx, Cx}, py[3] = {Ay, By, Cy};
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
@@ -560,7 +586,8 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
   const double inv_order = 1.0 / (2.0 * pl->q - 1.0);
   k_tri_ellipses<<<blocks_for(T), kBlock, 0, st>>>(m->ax, m->ay, m->bx, m->by, m->cx, m->cy, m->det, T,
                                                    pl->far_what[0], pl->far_what[1], pl->far_what[2], eps_cn,
-                                                   inv_order, thr, box);
+                                                   inv_order, pl->opts.near_model == VP_NEAR_BALL ? 1 : 0,
+                                                   pl->opts.ball_factor, thr, box);
   k_extent_partial<<<nred, kBlock, 0, st>>>(pl->xt, pl->yt, NT, box, T, part);
   if ((e = hipGetLastError()) != hipSuccess) {
     cleanup();
@@ -625,7 +652,8 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
   }
   k_cell_fill<<<blocks_for(T), kBlock, 0, st>>>(box, T, g, cptr, cfill, ctri);
   k_cell_sort<<<blocks_for(nc), kBlock, 0, st>>>(cptr, nc, ctri);
-  TriView tv{m->ax, m->ay, m->bx, m->by, m->cx, m->cy, m->det, thr, T};
+  TriView tv{m->ax, m->ay, m->bx, m->by, m->cx, m->cy, m->det, thr, T, pl->opts.near_model == VP_NEAR_BALL ? 1 : 0,
+             pl->opts.ball_factor};
   k_pair_count<<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, tv, pl->opts.tau, pcnt);
   if ((e = exclusive_scan_i32(pcnt, pl->row_ptr, NT, stmp, st)) != hipSuccess) {
     cleanup();

@@ -55,6 +55,8 @@ struct RowsArgs {
   int nr;
   double eps_cn, tau;
   int depth_cap, dyadic_cap;
+  int ball;            // naive ball model for the near subdivision
+  double ball_factor;  // its kappa
   const double2* logtab;
   double* rows;
   int* flag;
@@ -159,10 +161,15 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
           const double p0x = Ax + sa * e1x + sb * e2x, p0y = Ay + sa * e1y + sb * e2y;
           const double p1x = p0x + ss * e1x, p1y = p0y + ss * e1y;
           const double p2x = p0x + ss * e2x, p2y = p0y + ss * e2y;
-          const double d0 = sqrt((x - p0x) * (x - p0x) + (y - p0y) * (y - p0y));
-          const double d1 = sqrt((x - p1x) * (x - p1x) + (y - p1y) * (y - p1y));
-          const double d2 = sqrt((x - p2x) * (x - p2x) + (y - p2y) * (y - p2y));
-          split = (level < a.depth_cap) && (d0 + d1 < thr[0] || d1 + d2 < thr[1] || d2 + d0 < thr[2]);
+          if (a.ball) {
+            split = (level < a.depth_cap) && in_ball_sub(x, y, Ax, Ay, e1x, e1y, e2x, e2y, sa, sb, ss,
+                                                         a.ball_factor);
+          } else {
+            const double d0 = sqrt((x - p0x) * (x - p0x) + (y - p0y) * (y - p0y));
+            const double d1 = sqrt((x - p1x) * (x - p1x) + (y - p1y) * (y - p1y));
+            const double d2 = sqrt((x - p2x) * (x - p2x) + (y - p2y) * (y - p2y));
+            split = (level < a.depth_cap) && (d0 + d1 < thr[0] || d1 + d2 < thr[1] || d2 + d0 < thr[2]);
+          }
         }
         const bool is_leaf = valid && !split;
         const uint64_t msplit = __ballot(split);
@@ -242,7 +249,9 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
         const double f = exp2(-2.0 * level * a.inv_near_order);
         const double hl = ldexp(0.5, -level);
         bool split = false;
-        if (level < a.depth_cap) {
+        if (level < a.depth_cap && a.ball) {
+          split = in_ball_sub(x, y, Ax, Ay, e1x, e1y, e2x, e2y, sa, sb, ss, a.ball_factor);
+        } else if (level < a.depth_cap) {
           const double p0x = Ax + sa * e1x + sb * e2x, p0y = Ay + sa * e1y + sb * e2y;
           const double p1x = p0x + ss * e1x, p1y = p0y + ss * e1y;
           const double p2x = p0x + ss * e2x, p2y = p0y + ss * e2y;
@@ -405,6 +414,8 @@ hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t s
   a.eps_cn = pl->eps * pl->opts.c_n;
   a.tau = pl->opts.tau;
   a.depth_cap = pl->opts.depth_cap;
+  a.ball = pl->opts.near_model == VP_NEAR_BALL ? 1 : 0;
+  a.ball_factor = pl->opts.ball_factor;
   a.dyadic_cap = pl->opts.dyadic_cap;
   a.logtab = pl->logtab;
   a.rows = pl->rows;

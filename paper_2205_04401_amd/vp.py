@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libvp.so")
 VP_OK, VP_EINVAL, VP_ENOMEM, VP_EDEVICE, VP_ENOTSUP, VP_EBUSY, VP_EINTERNAL = range(7)
 VP_FP64, VP_MIXED = 0, 1
 VP_DEVICE_PTRS, VP_FAR_ONLY, VP_ASYNC = 1, 2, 4
+NEAR_MODELS = {"ellipse": 0, "ball": 1}  # VP_NEAR_ELLIPSES, VP_NEAR_BALL
 STATUS_NAMES = {0: "VP_OK", 1: "VP_EINVAL", 2: "VP_ENOMEM", 3: "VP_EDEVICE", 4: "VP_ENOTSUP",
                 5: "VP_EBUSY", 6: "VP_EINTERNAL"}
 
@@ -42,7 +43,7 @@ class VPError(RuntimeError):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("c_n", ctypes.c_double), ("q_near", ctypes.c_int), ("n_l", ctypes.c_int),
                 ("tau", ctypes.c_double), ("depth_cap", ctypes.c_int), ("dyadic_cap", ctypes.c_int),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("near_model", ctypes.c_int), ("ball_factor", ctypes.c_double)]
 
 
 class PlanStats(ctypes.Structure):
@@ -246,14 +247,16 @@ class Mesh:
 
 class Plan:
     def __init__(self, ctx, mesh, p, q, eps, targets, c_n=1.0, q_near=7, n_l=16, tau=1e-13, depth_cap=50,
-                 dyadic_cap=60):
+                 dyadic_cap=60, near_model="ellipse", ball_factor=2.0):
         if _is_device(targets):
             tgt = targets.contiguous()
             flags = VP_DEVICE_PTRS
         else:
             tgt = np.ascontiguousarray(np.asarray(targets, dtype=np.float64).reshape(-1, 2))
             flags = 0
-        opts = PlanOpts(c_n, q_near, n_l, tau, depth_cap, dyadic_cap, flags)
+        if near_model not in NEAR_MODELS:
+            raise VPError(VP_EINVAL, f"near_model must be one of {sorted(NEAR_MODELS)}")
+        opts = PlanOpts(c_n, q_near, n_l, tau, depth_cap, dyadic_cap, flags, NEAR_MODELS[near_model], ball_factor)
         h = P()
         _check(load().vp_plan_create(ctx.h, mesh.h, p, q, eps, tgt.shape[0], _ptr(tgt), ctypes.byref(opts),
                                      ctypes.byref(h)))

@@ -59,6 +59,10 @@ def margin(o, x, t, kind_gpu):
     m = [abs(lam.min() + o.tau)]
     N = 2 * o.q - 1
     P3 = (o.A[t], o.B[t], o.C[t])
+    if o.near_model == "ball":
+        c = (P3[0] + P3[1] + P3[2]) / 3.0
+        r = o.ball_factor * max(math.hypot(*(v - c)) for v in P3)
+        return min(m + [abs(math.hypot(*(x - c)) - r) / r])
     for e in range(3):
         P, Q = P3[e], P3[(e + 1) % 3]
         rho, thr = o.ellipse_params(P, Q, o.D[t], o.far_what[e], N)
@@ -298,6 +302,54 @@ def test_targets_on_far_nodes(vp_ctx):
     assert e64 <= REL_E2E and emx <= 1e-6
     plan.close()
     mesh.close()
+
+
+def test_naive_ball_near_model_matches_oracle(vp_ctx):
+    """The naive ball near field (ablation model): pair sets, every row and
+    u equal the oracle's running the same model (kappa = 2)."""
+    p, q, eps, kappa = 3, 4, 1e-12, 2.0
+    vq, tq = W.unit_square(4, "/")
+    vt, tt = W.unit_square(4, "\\")
+    nodes = rules.interp_nodes(p)
+    rng = np.random.default_rng(17)
+    tg = np.concatenate([W.node_positions(vt, tt, nodes).reshape(-1, 2), rng.uniform(-0.3, 1.3, (40, 2))])
+    F = W.sample_density(W.gaussian_bump, vq, tq, nodes)
+    mesh = vp_ctx.mesh(vq, tq)
+    plan = vp_ctx.plan(mesh, p, q, eps, tg, near_model="ball", ball_factor=kappa)
+    o = potential.Oracle(vq, tq, p, q, eps, near_model="ball", ball_factor=kappa)
+    flips = compare_pairs(plan, o, tg)
+    rp, tri, kind = plan.pairs()
+    rows = plan.rows()
+    worst = scale = 0.0
+    for i in range(0, len(tg), 3):
+        for j in range(rp[i], rp[i + 1]):
+            ref = o.row(int(tri[j]), tg[i], int(kind[j]))
+            worst = max(worst, np.abs(rows[j] - ref).max())
+            scale = max(scale, np.abs(ref).max())
+    e = rel_linf(plan.execute(F), o.evaluate(F, tg))
+    say("ball model: flips", flips, "worst row abs", worst, "scale", scale, "u rel", e, plan.info()["near_subtri"])
+    assert flips == 0 and worst <= 1e-12 * scale and e <= REL_E2E
+    plan.close()
+    mesh.close()
+
+
+def test_ablation_driver_small_star(vp_ctx):
+    """The ablation driver on a small star: its eps = 1e-15 reference agrees
+    with the oracle, every setting stays within its tolerance, and the
+    ellipse near field needs fewer corrections than the ball tuned to the
+    same error."""
+    from paper_2205_04401_amd import ablation
+    res = ablation.run(vp_ctx, eps_list=(1e-10,), q=6, n_tri=600, n_sample=6, seed=60)
+    prob = res["problem"]
+    o = potential.Oracle(prob["vq"], prob["tq"], prob["p"], 6, 1e-15)
+    x = prob["stag"][res["sample_stag"][:3]]
+    ref = ablation.reference(vp_ctx, vp_ctx.mesh(prob["vq"], prob["tq"]), prob, 6, x)
+    e_ref = rel_linf(ref, o.evaluate(prob["F"], x))
+    r = res["rows"][0]
+    say("ablation small:", ablation.table(res), "reference vs oracle", e_ref)
+    assert e_ref <= REL_E2E
+    assert r["star"]["E_abs"] < 1e-8 and r["plus"]["E_abs"] < 1e-8 and r["zero"]["E_abs"] <= 2 * r["star"]["E_abs"]
+    assert r["star"]["c"] < r["zero"]["c"]
 
 
 def test_empty_target_set_and_single_triangle(vp_ctx):

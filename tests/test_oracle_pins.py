@@ -131,6 +131,29 @@ def test_far_only_differs_and_corrections_matter():
 
 # -- P4: disk closed form (spec check) --------------------------------
 
+def test_naive_ball_model_converges_to_the_exact_integral():
+    """The naive near field (a ball of kappa times the centroid radius, the
+    paper's comparison setting) reaches the exact integral only as kappa
+    grows, and at far more sub-triangles than the Bernstein ellipses need
+    for a smaller error (Sec. 4.1, Remark rem:near_zero)."""
+    vq, tq = W.unit_square(4, "/")
+    rng = np.random.default_rng(5)
+    tg = rng.uniform(-0.2, 1.2, (40, 2))
+    exact = np.array([pins.mesh_unit_potential(vq, tq, x) for x in tg])
+    F = np.ones((len(tq), rules.n_basis(1)))
+    errs, subs = [], []
+    for kappa in (1.0, 2.0, 3.0, 5.0):
+        o = potential.Oracle(vq, tq, 1, 4, 1e-12, near_model="ball", ball_factor=kappa)
+        errs.append(np.abs(o.evaluate(F, tg) - exact).max() / np.abs(exact).max())
+        subs.append(o.stats["near_subtriangles"])
+    assert all(b < 0.2 * a for a, b in zip(errs, errs[1:])), errs
+    assert errs[0] > 1e-7 and errs[-1] < 1e-10
+    o = potential.Oracle(vq, tq, 1, 4, 1e-12)
+    e_ell = np.abs(o.evaluate(F, tg) - exact).max() / np.abs(exact).max()
+    assert e_ell < 1e-12 and e_ell < errs[-1]
+    assert o.stats["near_subtriangles"] < subs[-1] / 4
+
+
 def test_disk_unit_density_polygon_exact_and_circle_converges():
     R = 1.0
     rng = np.random.default_rng(2)
