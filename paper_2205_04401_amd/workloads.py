@@ -158,6 +158,53 @@ def disk_mesh(n_tri=500, n_boundary=60, seed=1, radius=1.0):
                                 n_tri, n_boundary, seed)
 
 
+def polar_curved_sides(vert, tri, radius_fn, n_boundary, staggered=False, deg=16):
+    """Curved sides for a mesh of ``_radial_polygon_mesh``: every triangle
+    edge joining consecutive boundary points k, k+1 becomes the arc of
+    r(theta) between them, given as deg+1 points at the Chebyshev-Lobatto
+    parameters u_i = (1 - cos(pi i / deg)) / 2 of theta between the two
+    vertices (end points copied from ``vert``).  Returns (curved_tri,
+    curved_side, curved_pts [n, deg+1, 2]); side e is the edge from local
+    vertex e to local vertex e+1."""
+    vert = np.asarray(vert, dtype=np.float64)
+    tri = np.asarray(tri)
+    dth = 2.0 * math.pi / n_boundary
+    off = 0.5 * dth if staggered else 0.0
+    u = 0.5 * (1.0 - np.cos(np.pi * np.arange(deg + 1) / deg))
+    ct, cs, cp = [], [], []
+    for t in range(len(tri)):
+        sides = []
+        for e in range(3):
+            a, b = int(tri[t, e]), int(tri[t, (e + 1) % 3])
+            if a < n_boundary and b < n_boundary and (b - a) % n_boundary in (1, n_boundary - 1):
+                sides.append((e, a, b))
+        if len(sides) > 1:
+            raise ValueError("a triangle with two boundary edges cannot take one curved side")
+        for e, a, b in sides:
+            step = dth if (b - a) % n_boundary == 1 else -dth
+            th = a * dth + off + u * step
+            r = radius_fn(th)
+            pts = np.stack([r * np.cos(th), r * np.sin(th)], 1)
+            pts[0], pts[-1] = vert[a], vert[b]
+            ct.append(t)
+            cs.append(e)
+            cp.append(pts)
+    return np.array(ct, dtype=np.int32), np.array(cs, dtype=np.int32), np.array(cp)
+
+
+def curved_disk(n_tri=500, n_boundary=60, seed=1, radius=1.0, deg=16):
+    """The disk mesh with its boundary edges replaced by circular arcs:
+    (vert, tri, curved_tri, curved_side, curved_pts)."""
+    v, t = disk_mesh(n_tri=n_tri, n_boundary=n_boundary, seed=seed, radius=radius)
+    return (v, t) + polar_curved_sides(v, t, lambda th: np.full_like(th, radius), n_boundary, deg=deg)
+
+
+def curved_star(n_tri=20000, n_boundary=2000, seed=20, staggered=False, deg=12):
+    """The star mesh with its boundary edges on r = 1 + 0.3 cos(5 theta)."""
+    v, t = star_mesh(n_tri=n_tri, n_boundary=n_boundary, seed=seed, staggered=staggered)
+    return (v, t) + polar_curved_sides(v, t, star_radius, n_boundary, staggered=staggered, deg=deg)
+
+
 def polygon_area(vert, tri):
     a, b, c = vert[tri[:, 0]], vert[tri[:, 1]], vert[tri[:, 2]]
     return 0.5 * np.abs((b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1])

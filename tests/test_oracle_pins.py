@@ -376,3 +376,81 @@ def test_planted_mistakes_are_caught(monkeypatch):
                 continue
             worst = max(worst, abs(o4.far_B(0, x)[0] / SQRT2 - pins.triangle_log_integral(*big, x)))
     assert worst > 2 * o4.eps
+
+
+# ---------------------------------------------------------------------------
+# curved boundary elements (Sec. 3.1, eq. blend)
+# ---------------------------------------------------------------------------
+
+def _disk_targets(seed=2):
+    rng = np.random.default_rng(seed)
+    r = np.concatenate([rng.uniform(0, 0.99, 6), [1.0, 1.0], rng.uniform(1.01, 3, 4), [0.995, 1.005]])
+    a = rng.uniform(0, 2 * math.pi, len(r))
+    return r, np.stack([r * np.cos(a), r * np.sin(a)], 1)
+
+
+def test_curved_disk_area_and_unit_density_closed_form():
+    """Boundary triangles with circular sides: the far rule integrates the
+    disk's area, and unit density reproduces u = r^2/4 - 1/4 inside,
+    (1/2) log r outside (the disk closed form, R = 1) to rounding, at
+    targets inside, outside and on the circle."""
+    from oracle import curved
+    v, t, ct, cs, cp = W.curved_disk(n_tri=200, n_boundary=30, seed=1, deg=16)
+    o = curved.CurvedOracle(v, t, ct, cs, cp, 1, 8, 1e-12)
+    F = np.ones((len(t), rules.n_basis(1)))
+    _, charge = o.far_sources(o.coefficients(F))
+    assert abs(charge.sum() - math.pi) < 1e-14
+    r, tg = _disk_targets()
+    exact = np.where(r <= 1, r ** 2 / 4 - 0.25, 0.5 * np.log(r))
+    u = o.evaluate(F, tg)
+    assert np.abs(u - exact).max() < 1e-12 * np.abs(exact).max()
+
+
+def test_curved_disk_r2_density_converges_to_closed_form():
+    """f = r^2 on the curved disk: u = r^4/16 - 1/16 inside, (1/4) log r
+    outside.  f composed with the blending map is not a polynomial, so the
+    error is the interpolant's, falling with p."""
+    from oracle import curved
+    v, t, ct, cs, cp = W.curved_disk(n_tri=200, n_boundary=30, seed=1, deg=16)
+    r, tg = _disk_targets(3)
+    exact = np.where(r <= 1, r ** 4 / 16 - 1 / 16, 0.25 * np.log(r))
+    errs = []
+    for p in (4, 6, 8):
+        o = curved.CurvedOracle(v, t, ct, cs, cp, p, 8, 1e-13)
+        Y = o.node_positions(rules.interp_nodes(p))
+        u = o.evaluate(Y[:, :, 0] ** 2 + Y[:, :, 1] ** 2, tg)
+        errs.append(np.abs(u - exact).max() / np.abs(exact).max())
+    assert errs[0] < 1e-8 and errs[1] < 1e-12 and errs[2] < 1e-13 and errs[2] < errs[0] / 1e4, errs
+
+
+def test_curved_map_inverse_round_trip_and_straight_limit():
+    """Newton inversion undoes the blending map; with every 'curved' side
+    placed on its chord the curved oracle equals the straight one."""
+    from oracle import curved
+    v, t, ct, cs, cp = W.curved_disk(n_tri=120, n_boundary=24, seed=4, deg=10)
+    o = curved.CurvedOracle(v, t, ct, cs, cp, 3, 6, 1e-12)
+    rng = np.random.default_rng(9)
+    X = rng.dirichlet([1, 1, 1], 20)[:, 1:]
+    for tc in list(o.curves)[:5]:
+        Y = o.blend(tc, X)[0]
+        Z = np.array([o.inverse(tc, y) for y in Y])
+        assert np.abs(Z - X).max() < 1e-13
+    # straight limit: points on the chords
+    u01 = curved.lobatto_params(cp.shape[1] - 1)
+    flat = np.array([[v[t[k, e]] + s * (v[t[k, (e + 1) % 3]] - v[t[k, e]]) for s in u01] for k, e in zip(ct, cs)])
+    of = curved.CurvedOracle(v, t, ct, cs, flat, 3, 6, 1e-12)
+    os_ = potential.Oracle(v, t, 3, 6, 1e-12)
+    # a global cubic, reproduced exactly by both interpolants (each samples
+    # it at its own node positions: a curved triangle orders its vertices
+    # from its curved side)
+    X = rules.interp_nodes(3)
+
+    def f(Y):
+        x, y = Y[..., 0], Y[..., 1]
+        return 1.0 + x + 2.0 * y * y - x * y + x ** 3
+
+    Ys = os_.A[:, None, :] + X[None, :, :1] * (os_.B - os_.A)[:, None, :] + X[None, :, 1:2] * (os_.C - os_.A)[:, None, :]
+    _, tg = _disk_targets(5)
+    ref = os_.evaluate(f(Ys), tg)
+    assert np.abs(of.evaluate(f(of.node_positions(X)), tg) - ref).max() < 1e-12 * np.abs(ref).max()
+
