@@ -164,6 +164,35 @@ vp_status vp_mesh_create(vp_ctx* ctx, int64_t n_vert, const double* vert_xy, int
                          const int32_t* tri, vp_mesh** out);
 vp_status vp_mesh_destroy(vp_mesh* mesh);
 
+/* Curved boundary sides (Sec. 3.1, eq. blend).  Entry i gives triangle
+ * tri[i] one curved side: the edge from its local vertex side[i] to local
+ * vertex side[i]+1 mod 3 (vertex order as passed to vp_mesh_create), as
+ * pts [n][deg+1][2]: the side at the Chebyshev-Lobatto parameters
+ * u_j = (1 - cos(pi j / deg)) / 2, pts[i][0] and pts[i][deg] equal to the
+ * edge's two vertices (to 1e-13 of the triangle's size).  The side
+ * becomes the polynomial gamma through these points; with B = gamma(0),
+ * A = gamma(1) (swapped, with the curve reversed, to keep (A, B, C)
+ * counter-clockwise) and C the opposite vertex, the triangle is the image
+ * of the reference simplex under
+ *   rho(xi, eta) = A + xi (B - A) + eta (C - A) + ((u - eta) / u) beta(u),
+ *   u = 1 - xi, beta(u) = gamma(u) - (B + u (A - B)),
+ * and the density of vp_execute is sampled at rho(interpolation nodes)
+ * (vp_mesh_map_points).  Far rule: nodes rho(xi_j), weights w_j |J(xi_j)|
+ * (Thm. smooth_int_jac); self pairs: found by Newton's method for
+ * rho^{-1}(x), integrated in radius-arc-length coordinates of the reference
+ * simplex about rho^{-1}(x); near pairs: the curved side treated as its
+ * chord for the ellipse tests (Sec. 4.1), with the largest |J| at the far
+ * nodes.  1 <= deg <= 32; each triangle at most once; one call per mesh,
+ * before any plan (VP_EBUSY otherwise).  The library copies the arrays. */
+vp_status vp_mesh_set_curved_sides(vp_mesh* mesh, int64_t n, const int32_t* tri, const int32_t* side, int deg,
+                                   const double* pts);
+
+/* Physical positions of n_ref reference points (ref_xy [n_ref][2], xi < 1)
+ * on every triangle: out_xy [n_tri][n_ref][2] (host), the affine map of a
+ * straight triangle (vertex order after vp_mesh_create's orientation) or
+ * the blending map of a curved one.  n_ref <= 4096. */
+vp_status vp_mesh_map_points(const vp_mesh* mesh, int n_ref, const double* ref_xy, double* out_xy);
+
 /* Build the plan for (mesh, p, q, eps, targets): rule tables, far sources,
  * the CSR list of self/near pairs per target (Def. of near field, Sec. 3.2;
  * ellipse union, Sec. 4.1) and the FP64 correction rows of every pair.

@@ -321,9 +321,202 @@ vp_status vp_mesh_destroy(vp_mesh* m) {
   if (m->live_plans) return fail(VP_EBUSY, "vp_mesh_destroy: %d plans still use this mesh", m->live_plans);
   (void)hipSetDevice(m->ctx->device);
   (void)hipFree(m->ax);
+  for (void* q : {(void*)m->curve_of, (void*)m->curve_tri, (void*)m->curve_coef, (void*)m->curve_box})
+    if (q) (void)hipFree(q);
   m->ctx->in_use -= m->bytes;
   m->ctx->live_meshes--;
   delete m;
+  return VP_OK;
+}
+
+namespace {
+
+// Chebyshev coefficients of the polynomial through values f_j at
+// s_j = -cos(pi j / d), j = 0..d (a discrete cosine transform, long double).
+void cheb_from_lobatto(const long double* f, int d, long double* c) {
+  const long double pi = acosl(-1.0L);
+  for (int k = 0; k <= d; ++k) {
+    long double acc = 0.0L;
+    for (int m = 0; m <= d; ++m) {
+      // s = cos(pi m / d) is the node j = d - m
+      const long double w = (m == 0 || m == d) ? 0.5L : 1.0L;
+      acc += w * f[d - m] * cosl(pi * k * m / d);
+    }
+    c[k] = acc * 2.0L / d;
+  }
+  c[0] *= 0.5L;
+  c[d] *= 0.5L;
+}
+
+// coefficients of d/ds of sum c_k T_k
+void cheb_derivative(const long double* c, int d, long double* dc) {
+  for (int k = 0; k <= d; ++k) dc[k] = 0.0L;
+  if (d == 0) return;
+  long double b2 = 0.0L, b1 = 0.0L;  // dc_{k+1}, dc_{k+2} from the top
+  for (int k = d; k >= 1; --k) {
+    const long double v = b1 + 2.0L * k * c[k];  // dc_{k-1} = dc_{k+1} + 2 k c_k
+    dc[k - 1] = v;
+    b1 = b2;
+    b2 = v;
+  }
+  dc[0] *= 0.5L;
+}
+
+}  // namespace
+
+vp_status vp_mesh_set_curved_sides(vp_mesh* m, int64_t n, const int32_t* tri, const int32_t* side, int deg,
+                                   const double* pts) {
+  if (!m || (n > 0 && (!tri || !side || !pts))) return fail(VP_EINVAL, "vp_mesh_set_curved_sides: NULL argument");
+  if (n < 0 || n > m->n_tri) return fail(VP_EINVAL, "vp_mesh_set_curved_sides: bad count");
+  if (deg < 1 || deg > vp::kCurveMax - 1)
+    return fail(VP_EINVAL, "vp_mesh_set_curved_sides: degree %d outside [1, %d]", deg, vp::kCurveMax - 1);
+  if (m->live_plans) return fail(VP_EBUSY, "vp_mesh_set_curved_sides: the mesh already has plans");
+  if (m->n_curved) return fail(VP_EINVAL, "vp_mesh_set_curved_sides: curved sides are already set");
+  if (n == 0) return VP_OK;
+  VP_HIP(hipSetDevice(m->ctx->device), "hipSetDevice");
+  hipStream_t st = m->ctx->stream;
+  const int64_t T = m->n_tri;
+  std::vector<double> g(7 * T);
+  VP_HIP(hipMemcpyAsync(g.data(), m->ax, sizeof(double) * 7 * T, hipMemcpyDeviceToHost, st), "hipMemcpy");
+  VP_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+  double *ax = g.data(), *ay = ax + T, *bx = ax + 2 * T, *by = ax + 3 * T, *cx = ax + 4 * T, *cy = ax + 5 * T,
+         *det = ax + 6 * T;
+  std::vector<int32_t> of(T, -1), ctri(n);
+  std::vector<double> coef((size_t)n * 4 * vp::kCurveMax, 0.0), box((size_t)n * 4);
+  std::vector<long double> fx(deg + 1), fy(deg + 1), c(deg + 1), dc(deg + 1);
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t t = tri[i];
+    if (t < 0 || t >= T || side[i] < 0 || side[i] > 2)
+      return fail(VP_EINVAL, "vp_mesh_set_curved_sides: entry %lld: bad triangle or side", (long long)i);
+    if (of[t] >= 0) return fail(VP_EINVAL, "vp_mesh_set_curved_sides: triangle %d listed twice", t);
+    const double* P = pts + (size_t)i * (deg + 1) * 2;
+    for (int j = 0; j <= 2 * deg + 1; ++j)
+      if (!std::isfinite(P[j])) return fail(VP_EINVAL, "vp_mesh_set_curved_sides: non-finite point");
+    // the side's end points are two of the triangle's vertices
+    const double vx[3] = {ax[t], bx[t], cx[t]}, vy[3] = {ay[t], by[t], cy[t]};
+    const double ext = std::max(std::max(std::fabs(vx[1] - vx[0]), std::fabs(vy[1] - vy[0])),
+                                std::max(std::fabs(vx[2] - vx[0]), std::fabs(vy[2] - vy[0])));
+    auto vertex_at = [&](double x, double y) {
+      for (int k = 0; k < 3; ++k)
+        if (std::fabs(vx[k] - x) <= 1e-13 * ext && std::fabs(vy[k] - y) <= 1e-13 * ext) return k;
+      return -1;
+    };
+    const int kb = vertex_at(P[0], P[1]), ka = vertex_at(P[2 * deg], P[2 * deg + 1]);
+    if (kb < 0 || ka < 0 || ka == kb)
+      return fail(VP_EINVAL, "vp_mesh_set_curved_sides: entry %lld: the side's end points are not two vertices "
+                             "of triangle %d", (long long)i, t);
+    const int kc = 3 - ka - kb;
+    double Ax = vx[ka], Ay = vy[ka], Bx = vx[kb], By = vy[kb];
+    const double Cx = vx[kc], Cy = vy[kc];
+    bool rev = false;
+    if ((Bx - Ax) * (Cy - Ay) - (By - Ay) * (Cx - Ax) < 0) {  // keep (A, B, C) counter-clockwise
+      std::swap(Ax, Bx);
+      std::swap(Ay, By);
+      rev = true;
+    }
+    for (int j = 0; j <= deg; ++j) {
+      const int jj = rev ? deg - j : j;
+      fx[j] = P[2 * jj];
+      fy[j] = P[2 * jj + 1];
+    }
+    fx[0] = Bx;
+    fy[0] = By;
+    fx[deg] = Ax;
+    fy[deg] = Ay;
+    double* cf = coef.data() + (size_t)i * 4 * vp::kCurveMax;
+    cheb_from_lobatto(fx.data(), deg, c.data());
+    cheb_derivative(c.data(), deg, dc.data());
+    for (int k = 0; k <= deg; ++k) {
+      cf[k] = (double)c[k];
+      cf[2 * vp::kCurveMax + k] = (double)dc[k];
+    }
+    cheb_from_lobatto(fy.data(), deg, c.data());
+    cheb_derivative(c.data(), deg, dc.data());
+    for (int k = 0; k <= deg; ++k) {
+      cf[vp::kCurveMax + k] = (double)c[k];
+      cf[3 * vp::kCurveMax + k] = (double)dc[k];
+    }
+    // element box: the opposite vertex and 129 points of the side, padded
+    double x0 = Cx, x1 = Cx, y0 = Cy, y1 = Cy;
+    for (int j = 0; j <= 128; ++j) {
+      const double sp = 2.0 * (j / 128.0) - 1.0;
+      const double px = vp::cheb_clenshaw(cf, deg + 1, sp), py = vp::cheb_clenshaw(cf + vp::kCurveMax, deg + 1, sp);
+      x0 = std::min(x0, px);
+      x1 = std::max(x1, px);
+      y0 = std::min(y0, py);
+      y1 = std::max(y1, py);
+    }
+    const double pad = 0.05 * std::max(x1 - x0, y1 - y0);
+    box[4 * i] = x0 - pad;
+    box[4 * i + 1] = y0 - pad;
+    box[4 * i + 2] = x1 + pad;
+    box[4 * i + 3] = y1 + pad;
+    ax[t] = Ax;
+    ay[t] = Ay;
+    bx[t] = Bx;
+    by[t] = By;
+    cx[t] = Cx;
+    cy[t] = Cy;
+    det[t] = (Bx - Ax) * (Cy - Ay) - (By - Ay) * (Cx - Ax);
+    if (!(det[t] > 0.0)) return fail(VP_EINVAL, "vp_mesh_set_curved_sides: degenerate triangle %d", t);
+    of[t] = (int32_t)i;
+    ctri[i] = t;
+  }
+  const size_t bytes = sizeof(int32_t) * (T + n) + sizeof(double) * (coef.size() + box.size());
+  if (m->ctx->budget && m->ctx->in_use + bytes > m->ctx->budget)
+    return fail(VP_ENOMEM, "vp_mesh_set_curved_sides: %zu bytes exceed the HBM budget", bytes);
+  hipError_t e;
+  if ((e = hipMalloc((void**)&m->curve_of, sizeof(int32_t) * T)) != hipSuccess ||
+      (e = hipMalloc((void**)&m->curve_tri, sizeof(int32_t) * n)) != hipSuccess ||
+      (e = hipMalloc((void**)&m->curve_coef, sizeof(double) * coef.size())) != hipSuccess ||
+      (e = hipMalloc((void**)&m->curve_box, sizeof(double) * box.size())) != hipSuccess ||
+      (e = hipMemcpyAsync(m->curve_of, of.data(), sizeof(int32_t) * T, hipMemcpyHostToDevice, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(m->curve_tri, ctri.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(m->curve_coef, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, st)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(m->curve_box, box.data(), sizeof(double) * box.size(), hipMemcpyHostToDevice, st)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(m->ax, g.data(), sizeof(double) * 7 * T, hipMemcpyHostToDevice, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess) {
+    for (void* q : {(void*)m->curve_of, (void*)m->curve_tri, (void*)m->curve_coef, (void*)m->curve_box})
+      if (q) (void)hipFree(q);
+    m->curve_of = m->curve_tri = nullptr;
+    m->curve_coef = m->curve_box = nullptr;
+    return hip_fail(e, "vp_mesh_set_curved_sides");
+  }
+  m->n_curved = n;
+  m->curve_deg = deg;
+  m->bytes += bytes;
+  m->ctx->in_use += bytes;
+  return VP_OK;
+}
+
+vp_status vp_mesh_map_points(const vp_mesh* m, int n_ref, const double* ref_xy, double* out_xy) {
+  if (!m || (n_ref > 0 && (!ref_xy || !out_xy))) return fail(VP_EINVAL, "vp_mesh_map_points: NULL argument");
+  if (n_ref < 0 || n_ref > 4096) return fail(VP_EINVAL, "vp_mesh_map_points: n_ref outside [0, 4096]");
+  for (int i = 0; i < 2 * n_ref; ++i)
+    if (!std::isfinite(ref_xy[i])) return fail(VP_EINVAL, "vp_mesh_map_points: non-finite point");
+  for (int i = 0; i < n_ref; ++i)
+    if (!(ref_xy[2 * i] < 1.0)) return fail(VP_EINVAL, "vp_mesh_map_points: reference points need xi < 1");
+  if (n_ref == 0 || m->n_tri == 0) return VP_OK;
+  VP_HIP(hipSetDevice(m->ctx->device), "hipSetDevice");
+  hipStream_t st = m->ctx->stream;
+  const size_t nout = (size_t)m->n_tri * n_ref * 2;
+  double *d_ref = nullptr, *d_out = nullptr;
+  hipError_t e;
+  if ((e = hipMalloc((void**)&d_ref, sizeof(double) * 2 * n_ref)) != hipSuccess ||
+      (e = hipMalloc((void**)&d_out, sizeof(double) * nout)) != hipSuccess ||
+      (e = hipMemcpyAsync(d_ref, ref_xy, sizeof(double) * 2 * n_ref, hipMemcpyHostToDevice, st)) != hipSuccess ||
+      (e = vp::launch_map_points(m, n_ref, d_ref, d_out, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(out_xy, d_out, sizeof(double) * nout, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess) {
+    if (d_ref) (void)hipFree(d_ref);
+    if (d_out) (void)hipFree(d_out);
+    return hip_fail(e, "vp_mesh_map_points");
+  }
+  (void)hipFree(d_ref);
+  (void)hipFree(d_out);
   return VP_OK;
 }
 
@@ -367,8 +560,9 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
   vp::Rule2D nr = vp::collapsed_gauss(o.q_near);
   vp::Rule1D gl = vp::gauss_legendre01(o.n_l);
   vp::Rule2D nodes = vp::interp_nodes(p);
-  std::vector<double> rr, ra, rb;
+  std::vector<double> rr, ra, rb, rcr, rca, rcb;
   vp::radial_rule(p, rr, ra, rb);
+  vp::radial_rule(2 * vp::kCurvedRadial - 3, rcr, rca, rcb);  // kCurvedRadial points per part
   vp::edge_weights(far, q, pl->far_what);
   vp::edge_weights(nr, o.q_near, pl->near_what);
   pl->n_r = (int)rr.size();
@@ -387,6 +581,10 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
   UP(pl->rad_r, rr);
   UP(pl->rad_a, ra);
   UP(pl->rad_b, rb);
+  UP(pl->rad_c_r, rcr);
+  UP(pl->rad_c_a, rca);
+  UP(pl->rad_c_b, rcb);
+  pl->n_rc = (int)rcr.size();
 #undef UP
   const int NP = pl->n_p;
   if ((e = plan_alloc(pl, (void**)&pl->vinv, sizeof(double) * NP * NP)) != hipSuccess ||
@@ -432,6 +630,8 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
       return hip_fail(e, "vp_plan_create: log tables");
   }
   if ((e = plan_alloc(pl, (void**)&pl->sxy, sizeof(double2) * pl->n_src_pad)) != hipSuccess ||
+      (e = plan_alloc(pl, (void**)&pl->swj, sizeof(double) * pl->n_src_pad)) != hipSuccess ||
+      (e = plan_alloc(pl, (void**)&pl->deff, sizeof(double) * std::max<int64_t>(pl->n_tri, 1))) != hipSuccess ||
       (e = plan_alloc(pl, (void**)&pl->xt, sizeof(double) * n_tgt)) != hipSuccess ||
       (e = plan_alloc(pl, (void**)&pl->yt, sizeof(double) * n_tgt)) != hipSuccess)
     return hip_fail(e, "vp_plan_create: hipMalloc");
@@ -511,7 +711,8 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
     }
     (void)hipFree(d_flag);
     (void)hipFree(d_stats);
-    if (flag) return fail(VP_EINTERNAL, "vp_plan_create: near subdivision exceeded its depth-first stack");
+    if (flag == 1) return fail(VP_EINTERNAL, "vp_plan_create: near subdivision exceeded its depth-first stack");
+    if (flag) return fail(VP_EINTERNAL, "vp_plan_create: a self pair's point location on a curved triangle failed");
   }
   float ms1 = 0.f, ms2 = 0.f;
   (void)hipEventElapsedTime(&ms1, ev0, ev1);

@@ -1,6 +1,6 @@
 // Per-solve kernels (FP64):
 //   k_coef      c = V^{-1} F per triangle (Sec. 2.2 interpolation matrix)
-//   k_charges   far charges Q_j = w_j |J| f_h(y_j) / (4 pi) (Sec. 3.6: every
+//   k_charges   far charges Q_j = w_j |J(xi_j)| f_h(y_j) / (4 pi) (Sec. 3.6: every
 //               far-rule node is a point charge; the 1/2 of log r = log(r^2)/2
 //               is folded in)
 //   k_far       U_far(x) = sum_j Q_j log|x - y_j|^2 over all sources: a
@@ -56,8 +56,7 @@ __global__ void k_coef(const double* __restrict__ F, const double* __restrict__ 
 // one thread per (source, rhs); Q is [n_src][R]
 template <int P>
 __global__ void k_charges(const double* __restrict__ C, const double* __restrict__ efar,
-                          const double* __restrict__ far_w, const double* __restrict__ det, int nf,
-                          int64_t n_tri, int64_t R, double* __restrict__ Q) {
+                          const double* __restrict__ swj, int nf, int64_t n_tri, int64_t R, double* __restrict__ Q) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
   const int64_t n_src = n_tri * nf;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -70,7 +69,7 @@ __global__ void k_charges(const double* __restrict__ C, const double* __restrict
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < NP; ++k) s = fma(E[k], c[(size_t)k * R], s);
-    Q[g] = s * far_w[j] * det[t] * kInv4Pi;
+    Q[g] = s * swj[src] * kInv4Pi;
   }
 }
 
@@ -469,7 +468,7 @@ hipError_t launch_coefficients(const vp_plan* pl, const double* F, int64_t R, do
   VP_DISPATCH_P(pl->p, (k_coef<P><<<blocks_for(T * R), kBlock, 0, st>>>(F, pl->vinv, T, R, C)));
   if (Q) {
     VP_DISPATCH_P(pl->p, (k_charges<P><<<blocks_for(T * pl->n_f * R), kBlock, 0, st>>>(
-                              C, pl->efar, pl->far_w, pl->mesh->det, pl->n_f, T, R, Q)));
+                              C, pl->efar, pl->swj, pl->n_f, T, R, Q)));
   }
   return hipGetLastError();
 }

@@ -123,6 +123,90 @@ __device__ __forceinline__ bool in_ball_sub(double x, double y, double Ax, doubl
   return in_ball3(x, y, px, py, kappa);
 }
 
+// ---------------------------------------------------------------------------
+// Curved boundary triangles (Sec. 3.1, eq. blend).  A curved triangle
+// stores A = gamma(1), B = gamma(0) (the ends of its curved side) and the
+// opposite vertex C, counter-clockwise, and gamma(u), u in [0, 1], as
+// Chebyshev coefficients in s = 2u - 1 (degree <= kCurveMax - 1), together
+// with those of d gamma / ds.  With beta(u) = gamma(u) - (B + u (A - B)),
+// the side's offset from its chord, and u = 1 - xi:
+//   rho(xi, eta) = A + xi (B - A) + eta (C - A) + ((u - eta) / u) beta(u).
+// ---------------------------------------------------------------------------
+constexpr int kCurveMax = 33;  // coefficients per coordinate
+
+struct CurveView {
+  const int32_t* of = nullptr;  // [T] index of the triangle's curve, -1 if straight
+  const double* coef = nullptr; // [n_curved][4][kCurveMax]: x, y, dx/ds, dy/ds
+  const double* box = nullptr;  // [n_curved][4]: x0, y0, x1, y1 of the element (padded)
+  int deg = 0;
+};
+
+__host__ __device__ __forceinline__ double cheb_clenshaw(const double* c, int n, double s) {
+  // sum_{k < n} c_k T_k(s)
+  double b1 = 0.0, b2 = 0.0;
+  for (int k = n - 1; k >= 1; --k) {
+    const double b0 = fma(2.0 * s, b1, c[k] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  return fma(s, b1, c[0] - b2);
+}
+
+// rho(xi, eta) of a curved triangle, and when dxi/deta are given its partial
+// derivatives.  Requires xi < 1 (u > 0); the vertex B itself is B.
+__host__ __device__ __forceinline__ void vp_blend(double Ax, double Ay, double Bx, double By, double Cx, double Cy,
+                                                  const double* cf, int deg, double xi, double eta, double& px,
+                                                  double& py, double* dxi = nullptr, double* deta = nullptr) {
+  const double u = 1.0 - xi, s = 2.0 * u - 1.0;
+  const double bx = cheb_clenshaw(cf, deg + 1, s) - (Bx + u * (Ax - Bx));
+  const double by = cheb_clenshaw(cf + kCurveMax, deg + 1, s) - (By + u * (Ay - By));
+  const double f = (u - eta) / u;
+  px = Ax + xi * (Bx - Ax) + eta * (Cx - Ax) + f * bx;
+  py = Ay + xi * (By - Ay) + eta * (Cy - Ay) + f * by;
+  if (dxi) {
+    const double dbx = 2.0 * cheb_clenshaw(cf + 2 * kCurveMax, deg, s) - (Ax - Bx);
+    const double dby = 2.0 * cheb_clenshaw(cf + 3 * kCurveMax, deg, s) - (Ay - By);
+    const double g = eta / (u * u), h = 1.0 - eta / u;
+    dxi[0] = (Bx - Ax) - g * bx - h * dbx;
+    dxi[1] = (By - Ay) - g * by - h * dby;
+    deta[0] = (Cx - Ax) - bx / u;
+    deta[1] = (Cy - Ay) - by / u;
+  }
+}
+
+__host__ __device__ __forceinline__ double vp_blend_jac(double Ax, double Ay, double Bx, double By, double Cx,
+                                                        double Cy, const double* cf, int deg, double xi, double eta,
+                                                        double& px, double& py) {
+  double dx[2], de[2];
+  vp_blend(Ax, Ay, Bx, By, Cx, Cy, cf, deg, xi, eta, px, py, dx, de);
+  return dx[0] * de[1] - dx[1] * de[0];
+}
+
+// rho^{-1}(x) by Newton's method from the chord's affine inverse; false if it
+// does not converge (a point far from the element).
+__host__ __device__ __forceinline__ bool vp_blend_inverse(double Ax, double Ay, double Bx, double By, double Cx,
+                                                          double Cy, double D, const double* cf, int deg, double x,
+                                                          double y, double& xi, double& eta) {
+  const double d0 = x - Ax, d1 = y - Ay;
+  xi = (d0 * (Cy - Ay) - d1 * (Cx - Ax)) / D;
+  eta = ((Bx - Ax) * d1 - (By - Ay) * d0) / D;
+  double step = 1.0;
+  for (int it = 0; it < 60; ++it) {
+    xi = fmin(xi, 1.0 - 1e-12);
+    double px, py, dx[2], de[2];
+    vp_blend(Ax, Ay, Bx, By, Cx, Cy, cf, deg, xi, eta, px, py, dx, de);
+    const double rx = px - x, ry = py - y;
+    const double J = dx[0] * de[1] - dx[1] * de[0];
+    const double sx = (de[1] * rx - de[0] * ry) / J, sy = (dx[0] * ry - dx[1] * rx) / J;
+    xi -= sx;
+    eta -= sy;
+    if (!(fabs(xi) < 1e6 && fabs(eta) < 1e6)) return false;
+    step = fabs(sx) + fabs(sy);
+    if (step < 1e-16) return true;
+  }
+  return step < 1e-12;
+}
+
 // Natural logarithm of x > 0 (normal) in FP64, table-driven (Tang's
 // method): x = m 2^e with m in [1/2, 1); the top eight fraction bits select
 // a sub-interval of width 1/512 with centre c_i; with inv_c_i the double
@@ -217,6 +301,21 @@ struct vp_mesh {
          *det = nullptr;
   size_t bytes = 0;
   int live_plans = 0;
+  // curved boundary triangles (vp_mesh_set_curved_sides): device arrays
+  int64_t n_curved = 0;
+  int curve_deg = 0;
+  int32_t* curve_of = nullptr;   // [n_tri]
+  int32_t* curve_tri = nullptr;  // [n_curved]
+  double* curve_coef = nullptr;  // [n_curved][4][kCurveMax]
+  double* curve_box = nullptr;   // [n_curved][4]
+  vp::CurveView curves() const {
+    vp::CurveView v;
+    v.of = curve_of;
+    v.coef = curve_coef;
+    v.box = curve_box;
+    v.deg = curve_deg;
+    return v;
+  }
 };
 
 struct vp_plan {
@@ -247,6 +346,12 @@ struct vp_plan {
   // sources and targets (device)
   int64_t n_src_pad = 0;                // n_src rounded up to a multiple of 256
   double2* sxy = nullptr;               // [n_src_pad] source positions
+  double* swj = nullptr;                // [n_src_pad] source weights w_j |J(xi_j)| (0 in the padding)
+  double* deff = nullptr;               // [T] |J| scale of the ellipse tests (det; the largest far-node |J| if curved)
+  double* rad_c_r = nullptr;            // radial rule of curved self pieces [n_rc]
+  double* rad_c_a = nullptr;
+  double* rad_c_b = nullptr;
+  int n_rc = 0;
   double2* logtab = nullptr;            // [kLogTab + 1] table of the FP64 logarithm
   double2* logtab_wide = nullptr;       // [kFarLogTab + 1] table of the far sum's logarithm
   double *xt = nullptr, *yt = nullptr;  // [n_tgt]
@@ -277,7 +382,9 @@ hipError_t launch_mesh_geom(const double* vert, int64_t n_vert, const int32_t* t
                             vp_mesh* m, int* d_bad, hipStream_t st);
 hipError_t launch_split_xy(const double* xy, int64_t n, double* x, double* y, int* d_bad, hipStream_t st);
 hipError_t launch_basis_tables(vp_plan* pl, double* scratch, hipStream_t st);
-hipError_t launch_sources(vp_plan* pl, hipStream_t st);
+hipError_t launch_sources(vp_plan* pl, hipStream_t st);  // positions, weights and |J| scales
+hipError_t launch_map_points(const vp_mesh* m, int n_ref, const double* ref, double* out, hipStream_t st);
+constexpr int kCurvedRadial = 12;  // points per part of the radial rule on curved self pieces
 hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err);  // near-list construction
 hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t st);
 hipError_t launch_coefficients(const vp_plan* pl, const double* F, int64_t R, double* C, double* Q,

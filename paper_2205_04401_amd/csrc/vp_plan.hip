@@ -142,21 +142,78 @@ __global__ void k_basis_at(const double* __restrict__ x, const double* __restric
 
 // far sources: node j of triangle t at A + xi_1 (B-A) + xi_2 (C-A); the
 // padding entries past n_tri * nf sit at the origin (their charge is 0)
+// Far sources: position rho(xi_j) and weight w_j |J(xi_j)| of every far node
+// of every triangle (Thm. smooth_int_jac; affine triangles have |J| = det),
+// zero in the padding.
 __global__ void k_sources(const double* __restrict__ ax, const double* __restrict__ ay,
                           const double* __restrict__ bx, const double* __restrict__ by,
                           const double* __restrict__ cx, const double* __restrict__ cy,
-                          const double* __restrict__ fx, const double* __restrict__ fy, int nf, int64_t n_tri,
-                          int64_t n_pad, double2* sxy) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_pad) return;
-  if (i >= n_tri * nf) {
-    sxy[i] = make_double2(0.0, 0.0);
-    return;
+                          const double* __restrict__ det, CurveView cv, const double* __restrict__ fx,
+                          const double* __restrict__ fy, const double* __restrict__ fw, int nf, int64_t n_tri,
+                          int64_t n_pad, double2* sxy, double* swj) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pad; i += stride) {
+    if (i >= n_tri * nf) {
+      sxy[i] = make_double2(0.0, 0.0);
+      swj[i] = 0.0;
+      continue;
+    }
+    const int64_t t = i / nf;
+    const int j = (int)(i - t * nf);
+    const double a0 = ax[t], a1 = ay[t];
+    const int c = cv.of ? cv.of[t] : -1;
+    if (c >= 0) {
+      double px, py;
+      const double J = vp_blend_jac(a0, a1, bx[t], by[t], cx[t], cy[t], cv.coef + (size_t)c * 4 * kCurveMax, cv.deg,
+                                    fx[j], fy[j], px, py);
+      sxy[i] = make_double2(px, py);
+      swj[i] = fw[j] * J;
+    } else {
+      sxy[i] = make_double2(a0 + fx[j] * (bx[t] - a0) + fy[j] * (cx[t] - a0),
+                            a1 + fx[j] * (by[t] - a1) + fy[j] * (cy[t] - a1));
+      swj[i] = fw[j] * det[t];
+    }
   }
-  int64_t t = i / nf;
-  int j = (int)(i - t * nf);
-  double a0 = ax[t], a1 = ay[t];
-  sxy[i] = make_double2(a0 + fx[j] * (bx[t] - a0) + fy[j] * (cx[t] - a0), a1 + fx[j] * (by[t] - a1) + fy[j] * (cy[t] - a1));
+}
+
+// |J| scale of the ellipse tests: det, or for a curved triangle the largest
+// |J| at its far nodes (its curved side treated as straight, Sec. 4.1).
+__global__ void k_deff(const double* __restrict__ det, int64_t n_tri, CurveView cv, const double* __restrict__ swj,
+                       const double* __restrict__ fw, int nf, double* __restrict__ deff) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tri; t += stride) {
+    if (cv.of && cv.of[t] >= 0) {
+      double mx = 0.0;
+      for (int j = 0; j < nf; ++j) mx = fmax(mx, swj[t * nf + j] / fw[j]);
+      deff[t] = mx;
+    } else {
+      deff[t] = det[t];
+    }
+  }
+}
+
+// Physical positions of reference points on every triangle: out[t][i].
+__global__ void k_map_points(const double* __restrict__ ax, const double* __restrict__ ay,
+                             const double* __restrict__ bx, const double* __restrict__ by,
+                             const double* __restrict__ cx, const double* __restrict__ cy, CurveView cv,
+                             int64_t n_tri, int n_ref, const double* __restrict__ ref, double* __restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_tri * n_ref; g += stride) {
+    const int64_t t = g / n_ref;
+    const int i = (int)(g - t * n_ref);
+    const double xi = ref[2 * i], eta = ref[2 * i + 1];
+    const int c = cv.of ? cv.of[t] : -1;
+    double px, py;
+    if (c >= 0) {
+      vp_blend(ax[t], ay[t], bx[t], by[t], cx[t], cy[t], cv.coef + (size_t)c * 4 * kCurveMax, cv.deg, xi, eta, px,
+               py);
+    } else {
+      px = ax[t] + xi * (bx[t] - ax[t]) + eta * (cx[t] - ax[t]);
+      py = ay[t] + xi * (by[t] - ay[t]) + eta * (cy[t] - ay[t]);
+    }
+    out[2 * g] = px;
+    out[2 * g + 1] = py;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -168,7 +225,7 @@ __global__ void k_tri_ellipses(const double* __restrict__ ax, const double* __re
                                const double* __restrict__ bx, const double* __restrict__ by,
                                const double* __restrict__ cx, const double* __restrict__ cy,
                                const double* __restrict__ det, int64_t n_tri, double w0, double w1, double w2,
-                               double eps_cn, double inv_order, int ball, double kappa,
+                               double eps_cn, double inv_order, int ball, double kappa, CurveView cv,
                                double* thr /* [3][n_tri] */, double* box /* [4][n_tri] */) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_tri) return;
@@ -185,6 +242,13 @@ __global__ void k_tri_ellipses(const double* __restrict__ ax, const double* __re
   x1 += pad;
   y0 -= pad;
   y1 += pad;
+  const int cc = cv.of ? cv.of[t] : -1;
+  if (cc >= 0) {  // a curved element: its own box (its side may bulge out of the chord triangle)
+    x0 = fmin(x0, cv.box[4 * cc]);
+    y0 = fmin(y0, cv.box[4 * cc + 1]);
+    x1 = fmax(x1, cv.box[4 * cc + 2]);
+    y1 = fmax(y1, cv.box[4 * cc + 3]);
+  }
   if (ball) {
     // naive near field: the ball of radius kappa R about the centroid (the
     // test itself is in_ball3; this is its bounding box)
@@ -329,6 +393,7 @@ struct TriView {
   int64_t n_tri;
   int ball;      // naive ball model (in_ball3)
   double kappa;  // its factor
+  CurveView cv;  // curved triangles
 };
 
 // 0 = self, 1 = near, 2 = far
@@ -340,7 +405,22 @@ __device__ __forceinline__ int classify(const TriView& tv, int32_t t, double x, 
   const double xi1 = (d0 * e2y - d1 * e2x) / D;
   const double xi2 = (e1x * d1 - e1y * d0) / D;
   const double lmin = fmin(fmin(1.0 - xi1 - xi2, xi1), xi2);
-  if (lmin >= -tau) return 0;
+  const int cc = tv.cv.of ? tv.cv.of[t] : -1;
+  if (cc >= 0) {
+    // curved element: self if rho^{-1}(x) is in the closed simplex; a point
+    // of the chord triangle outside the element is near
+    const double* bx4 = tv.cv.box + 4 * cc;
+    if (x >= bx4[0] && x <= bx4[2] && y >= bx4[1] && y <= bx4[3]) {
+      double z1, z2;
+      if (vp_blend_inverse(Ax, Ay, Bx, By, Cx, Cy, D, tv.cv.coef + (size_t)cc * 4 * kCurveMax, tv.cv.deg, x, y, z1,
+                           z2) &&
+          fmin(fmin(1.0 - z1 - z2, z1), z2) >= -tau)
+        return 0;
+    }
+    if (lmin >= -tau) return 1;
+  } else if (lmin >= -tau) {
+    return 0;
+  }
   if (tv.ball) {
     const double px[3] = {Ax, Bx, Cx}, py[3] = {Ay, By, Cy};
     return in_ball3(x, y, px, py, tv.kappa) ? 1 : 2;
@@ -534,9 +614,20 @@ hipError_t launch_basis_tables(vp_plan* pl, double* scratch, hipStream_t st) {
 hipError_t launch_sources(vp_plan* pl, hipStream_t st) {
   const vp_mesh* m = pl->mesh;
   int64_t n = pl->n_src_pad;
+  const CurveView cv = m->curves();
   if (n > 0)
-    k_sources<<<blocks_for(n), kBlock, 0, st>>>(m->ax, m->ay, m->bx, m->by, m->cx, m->cy, pl->far_x, pl->far_y,
-                                                pl->n_f, pl->n_tri, n, pl->sxy);
+    k_sources<<<blocks_for(n), kBlock, 0, st>>>(m->ax, m->ay, m->bx, m->by, m->cx, m->cy, m->det, cv, pl->far_x,
+                                                pl->far_y, pl->far_w, pl->n_f, pl->n_tri, n, pl->sxy, pl->swj);
+  if (pl->n_tri > 0)
+    k_deff<<<blocks_for(pl->n_tri), kBlock, 0, st>>>(m->det, pl->n_tri, cv, pl->swj, pl->far_w, pl->n_f, pl->deff);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_points(const vp_mesh* m, int n_ref, const double* ref, double* out, hipStream_t st) {
+  const int64_t n = m->n_tri * n_ref;
+  if (n > 0)
+    k_map_points<<<blocks_for(n), kBlock, 0, st>>>(m->ax, m->ay, m->bx, m->by, m->cx, m->cy, m->curves(), m->n_tri,
+                                                   n_ref, ref, out);
   return hipGetLastError();
 }
 
@@ -584,10 +675,10 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
   }
   const double eps_cn = pl->eps * pl->opts.c_n;
   const double inv_order = 1.0 / (2.0 * pl->q - 1.0);
-  k_tri_ellipses<<<blocks_for(T), kBlock, 0, st>>>(m->ax, m->ay, m->bx, m->by, m->cx, m->cy, m->det, T,
+  k_tri_ellipses<<<blocks_for(T), kBlock, 0, st>>>(m->ax, m->ay, m->bx, m->by, m->cx, m->cy, pl->deff, T,
                                                    pl->far_what[0], pl->far_what[1], pl->far_what[2], eps_cn,
                                                    inv_order, pl->opts.near_model == VP_NEAR_BALL ? 1 : 0,
-                                                   pl->opts.ball_factor, thr, box);
+                                                   pl->opts.ball_factor, m->curves(), thr, box);
   k_extent_partial<<<nred, kBlock, 0, st>>>(pl->xt, pl->yt, NT, box, T, part);
   if ((e = hipGetLastError()) != hipSuccess) {
     cleanup();
@@ -653,7 +744,7 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
   k_cell_fill<<<blocks_for(T), kBlock, 0, st>>>(box, T, g, cptr, cfill, ctri);
   k_cell_sort<<<blocks_for(nc), kBlock, 0, st>>>(cptr, nc, ctri);
   TriView tv{m->ax, m->ay, m->bx, m->by, m->cx, m->cy, m->det, thr, T, pl->opts.near_model == VP_NEAR_BALL ? 1 : 0,
-             pl->opts.ball_factor};
+             pl->opts.ball_factor, m->curves()};
   k_pair_count<<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, tv, pl->opts.tau, pcnt);
   if ((e = exclusive_scan_i32(pcnt, pl->row_ptr, NT, stmp, st)) != hipSuccess) {
     cleanup();

@@ -58,6 +58,12 @@ struct RowsArgs {
   int ball;            // naive ball model for the near subdivision
   double ball_factor;  // its kappa
   const double2* logtab;
+  const double2* sxy;   // the plan's far sources (positions) and their weights w_j |J|
+  const double* swj;
+  const double* deff;   // |J| scale of the ellipse tests per triangle
+  CurveView cv;         // curved triangles
+  const double *rad_c_r, *rad_c_a, *rad_c_b;  // radial rule of curved self pieces
+  int n_rc;
   double* rows;
   int* flag;
   int64_t* stats;  // near leaves, self panels, capped leaves, depth-first pairs
@@ -73,7 +79,9 @@ __device__ __forceinline__ int dyadic_count(double len, double d, int cap) {
   return n;
 }
 
-template <int P>
+// kCurved: the mesh has curved triangles (the straight-only instance carries
+// none of their code)
+template <int P, bool kCurved>
 __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
   __shared__ double lv[2][kCap * 3];
@@ -91,6 +99,37 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
   const double D = a.det[t];
   const double e1x = Bx - Ax, e1y = By - Ay, e2x = Cx - Ax, e2y = Cy - Ay;
   const double invD = 1.0 / D;
+  const int cvi = (kCurved && a.cv.of) ? a.cv.of[t] : -1;  // curve of a curved triangle, -1 if straight
+  const double* cf = (kCurved && cvi >= 0) ? a.cv.coef + (size_t)cvi * 4 * kCurveMax : nullptr;
+  // image of a reference point (the vertex B, where u = 0, maps to B)
+  auto map_vertex = [&](double r1, double r2, double& qx, double& qy) {
+    if (r1 >= 1.0) {
+      qx = Bx;
+      qy = By;
+    } else {
+      vp_blend(Ax, Ay, Bx, By, Cx, Cy, cf, a.cv.deg, r1, r2, qx, qy);
+    }
+  };
+  // the split test of a curved sub-triangle (sa, sb, ss): ellipses of its
+  // mapped vertices (edges as chords) with the level's rho, or the ball
+  auto curved_split = [&](double sa, double sb, double ss, const double* rho) {
+    double qx[3], qy[3];
+    map_vertex(sa, sb, qx[0], qy[0]);
+    map_vertex(sa + ss, sb, qx[1], qy[1]);
+    map_vertex(sa, sb + ss, qx[2], qy[2]);
+    if (a.ball) return in_ball3(x, y, qx, qy, a.ball_factor);
+    bool sp = false;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const int f2 = (e + 1) % 3;
+      if (!(rho[e] > 1.0)) continue;
+      const double ell = sqrt((qx[f2] - qx[e]) * (qx[f2] - qx[e]) + (qy[f2] - qy[e]) * (qy[f2] - qy[e]));
+      const double fs = sqrt((x - qx[e]) * (x - qx[e]) + (y - qy[e]) * (y - qy[e])) +
+                        sqrt((x - qx[f2]) * (x - qx[f2]) + (y - qy[f2]) * (y - qy[f2]));
+      if (fs < 0.5 * ell * (rho[e] + 1.0 / rho[e])) sp = true;
+    }
+    return sp;
+  };
 
   double acc[NP];
 #pragma unroll
@@ -99,12 +138,11 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
   // ---- B: the far rule's own contribution (subtracted) ----
   auto add_far_rule = [&]() {
     for (int j = lane; j < a.nf; j += kWave) {
-      const double fx = a.far_x[j], fy = a.far_y[j];
-      const double yx = Ax + fx * e1x + fy * e2x, yy = Ay + fx * e1y + fy * e2y;
-      const double dx = x - yx, dy = y - yy;
-      // the far sums' expression, so that a pair at r = 0 cancels
+      // the far sums' sources and expression, so that a pair at r = 0 cancels
+      const double2 sj = a.sxy[(int64_t)t * a.nf + j];
+      const double dx = x - sj.x, dy = y - sj.y;
       const double r2 = fma(dy, dy, fma(dx, dx, kR2Bias));
-      const double w = -0.5 * vp_log(r2, tab) * a.far_w[j] * D;
+      const double w = -0.5 * vp_log(r2, tab) * a.swj[(int64_t)t * a.nf + j];
       const double* E = a.efar + (size_t)j * NP;
 #pragma unroll
       for (int k = 0; k < NP; ++k) acc[k] = fma(w, E[k], acc[k]);
@@ -122,7 +160,7 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
     double rho0[3], ell0[3];
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
-      rho0[e] = pow(wh[e] * D / a.eps_cn, a.inv_near_order);
+      rho0[e] = pow(wh[e] * a.deff[t] / a.eps_cn, a.inv_near_order);
       const double ex = px[(e + 1) % 3] - px[e], ey = py[(e + 1) % 3] - py[e];
       ell0[e] = sqrt(ex * ex + ey * ey);
     }
@@ -139,8 +177,8 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
     for (int level = 0; n_cur > 0; ++level) {
       int n_next = 0, n_leaf = 0;
       double thr[3];
+      const double f = exp2(-2.0 * level * a.inv_near_order);
       {
-        const double f = exp2(-2.0 * level * a.inv_near_order);
         const double hl = ldexp(0.5, -level);
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
@@ -153,7 +191,15 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
         bool valid = i < n_cur;
         double sa = 0.0, sb = 0.0, ss = 0.0;
         bool split = false;
-        if (valid) {
+        if (valid && cf) {
+          sa = cur[3 * i];
+          sb = cur[3 * i + 1];
+          ss = cur[3 * i + 2];
+          double rho[3];
+#pragma unroll
+          for (int e = 0; e < 3; ++e) rho[e] = rho0[e] * f;
+          split = (level < a.depth_cap) && curved_split(sa, sb, ss, rho);
+        } else if (valid) {
           sa = cur[3 * i];
           sb = cur[3 * i + 1];
           ss = cur[3 * i + 2];
@@ -211,9 +257,15 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
         const int l = item / a.nn, nd = item - l * a.nn;
         const double sa = leaf[3 * l], sb = leaf[3 * l + 1], ss = leaf[3 * l + 2];
         const double xi1 = sa + ss * a.near_x[nd], xi2 = sb + ss * a.near_y[nd];
-        const double yx = Ax + xi1 * e1x + xi2 * e2x, yy = Ay + xi1 * e1y + xi2 * e2y;
+        double yx, yy, jac = D;
+        if (cf) {
+          jac = vp_blend_jac(Ax, Ay, Bx, By, Cx, Cy, cf, a.cv.deg, xi1, xi2, yx, yy);
+        } else {
+          yx = Ax + xi1 * e1x + xi2 * e2x;
+          yy = Ay + xi1 * e1y + xi2 * e2y;
+        }
         const double dx = x - yx, dy = y - yy;
-        const double w = 0.5 * vp_log(dx * dx + dy * dy, tab) * a.near_w[nd] * ss * ss * D;
+        const double w = 0.5 * vp_log(dx * dx + dy * dy, tab) * a.near_w[nd] * ss * ss * jac;
         koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { acc[k] = fma(w, v, acc[k]); });
       }
       __syncthreads();
@@ -249,7 +301,12 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
         const double f = exp2(-2.0 * level * a.inv_near_order);
         const double hl = ldexp(0.5, -level);
         bool split = false;
-        if (level < a.depth_cap && a.ball) {
+        if (level < a.depth_cap && cf) {
+          double rho[3];
+#pragma unroll
+          for (int e = 0; e < 3; ++e) rho[e] = rho0[e] * f;
+          split = curved_split(sa, sb, ss, rho);
+        } else if (level < a.depth_cap && a.ball) {
           split = in_ball_sub(x, y, Ax, Ay, e1x, e1y, e2x, e2y, sa, sb, ss, a.ball_factor);
         } else if (level < a.depth_cap) {
           const double p0x = Ax + sa * e1x + sb * e2x, p0y = Ay + sa * e1y + sb * e2y;
@@ -285,9 +342,15 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
           if (level >= a.depth_cap) ++n_capped;
           for (int nd = lane; nd < a.nn; nd += kWave) {
             const double xi1 = sa + ss * a.near_x[nd], xi2 = sb + ss * a.near_y[nd];
-            const double yx = Ax + xi1 * e1x + xi2 * e2x, yy = Ay + xi1 * e1y + xi2 * e2y;
+            double yx, yy, jac = D;
+            if (cf) {
+              jac = vp_blend_jac(Ax, Ay, Bx, By, Cx, Cy, cf, a.cv.deg, xi1, xi2, yx, yy);
+            } else {
+              yx = Ax + xi1 * e1x + xi2 * e2x;
+              yy = Ay + xi1 * e1y + xi2 * e2y;
+            }
             const double dx = x - yx, dy = y - yy;
-            const double w = 0.5 * vp_log(dx * dx + dy * dy, tab) * a.near_w[nd] * ss * ss * D;
+            const double w = 0.5 * vp_log(dx * dx + dy * dy, tab) * a.near_w[nd] * ss * ss * jac;
             koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { acc[k] = fma(w, v, acc[k]); });
           }
         }
@@ -296,6 +359,71 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
     }
   } else {
     // ---- A, self pair: three pieces in radius-arc-length coordinates ----
+    if (cf) {
+      // curved triangle: the same construction in the reference simplex about
+      // z = rho^{-1}(x); log|rho(y) - x| = log r + log(|rho(y) - x| / r), the
+      // radial rule's log-weight nodes take log r, its Gauss-Legendre nodes
+      // the smooth remainder; weights times |J|
+      double z1, z2;
+      if (!vp_blend_inverse(Ax, Ay, Bx, By, Cx, Cy, D, cf, a.cv.deg, x, y, z1, z2)) {
+        if (lane == 0) atomicMax(a.flag, 2);
+        z1 = z2 = 1.0 / 3.0;  // keeps the loops bounded; the plan reports the failure
+      }
+      const double rvx[3] = {0.0, 1.0, 0.0}, rvy[3] = {0.0, 0.0, 1.0};
+      const int per_panel = a.nl * a.n_rc;
+      for (int side = 0; side < 3; ++side) {
+        const double Px = rvx[side], Py = rvy[side], Qx = rvx[(side + 1) % 3], Qy = rvy[(side + 1) % 3];
+        const double sub = 0.5 * fabs((Px - z1) * (Qy - z2) - (Py - z2) * (Qx - z1));
+        if (sub <= a.tau * 0.5) continue;
+        const double L = sqrt((Qx - Px) * (Qx - Px) + (Qy - Py) * (Qy - Py));
+        const double ux = (Qx - Px) / L, uy = (Qy - Py) / L;
+        const double h = fabs((Px - z1) * (Qy - Py) - (Py - z2) * (Qx - Px)) / L;
+        const double st = fmin(fmax((z1 - Px) * ux + (z2 - Py) * uy, 0.0), L);
+        const double fx = Px + st * ux, fy = Py + st * uy;
+        const double d = sqrt((z1 - fx) * (z1 - fx) + (z2 - fy) * (z2 - fy));
+        const double rest = L - st;
+        const int n1 = (st > 0.0) ? dyadic_count(st, d, a.dyadic_cap) : -1;
+        const int n2 = (rest > 0.0) ? dyadic_count(rest, d, a.dyadic_cap) : -1;
+        const int nleft = n1 + 1, nright = n2 + 1;
+        const int np = nleft + nright;
+        n_panels += np;
+        const int items = np * per_panel;
+        for (int item = lane; item < items; item += kWave) {
+          const int ip = item / per_panel;
+          const int rem = item - ip * per_panel;
+          const int il = rem / a.n_rc, ir = rem - il * a.n_rc;
+          double s0, s1;
+          if (ip < nleft) {
+            if (ip < n1) {
+              s0 = (1.0 - ldexp(1.0, -ip)) * st;
+              s1 = (1.0 - ldexp(1.0, -(ip + 1))) * st;
+            } else {
+              s0 = (1.0 - ldexp(1.0, -n1)) * st;
+              s1 = st;
+            }
+          } else {
+            const int jp = ip - nleft;
+            if (jp < n2) {
+              s0 = L - (1.0 - ldexp(1.0, -(jp + 1))) * rest;
+              s1 = L - (1.0 - ldexp(1.0, -jp)) * rest;
+            } else {
+              s0 = st;
+              s1 = L - (1.0 - ldexp(1.0, -n2)) * rest;
+            }
+          }
+          const double sv = s0 + (s1 - s0) * a.gl_s[il];
+          const double ws = (s1 - s0) * a.gl_w[il];
+          const double gx = Px + sv * ux, gy = Py + sv * uy;
+          const double rr = a.rad_c_r[ir];
+          const double yr1 = z1 + rr * (gx - z1), yr2 = z2 + rr * (gy - z2);
+          double qx, qy;
+          const double jac = vp_blend_jac(Ax, Ay, Bx, By, Cx, Cy, cf, a.cv.deg, yr1, yr2, qx, qy);
+          const double lam = 0.5 * vp_log((qx - x) * (qx - x) + (qy - y) * (qy - y), tab) - vp_log(rr, tab);
+          const double w = h * ws * (a.rad_c_a[ir] * lam + a.rad_c_b[ir]) * jac;
+          koornwinder_emit<P>(yr1, yr2, [&](int k, double v) { acc[k] = fma(w, v, acc[k]); });
+        }
+      }
+    } else {
     const double area = 0.5 * D;
     const double vx[3] = {Ax, Bx, Cx}, vy[3] = {Ay, By, Cy};
     for (int side = 0; side < 3; ++side) {
@@ -352,6 +480,7 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
         koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { acc[k] = fma(w, v, acc[k]); });
       }
     }
+    }  // straight self pair
   }
 
   // ---- wave reduction and store ----
@@ -418,6 +547,14 @@ hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t s
   a.ball_factor = pl->opts.ball_factor;
   a.dyadic_cap = pl->opts.dyadic_cap;
   a.logtab = pl->logtab;
+  a.sxy = pl->sxy;
+  a.swj = pl->swj;
+  a.deff = pl->deff;
+  a.cv = m->curves();
+  a.rad_c_r = pl->rad_c_r;
+  a.rad_c_a = pl->rad_c_a;
+  a.rad_c_b = pl->rad_c_b;
+  a.n_rc = pl->n_rc;
   a.rows = pl->rows;
   a.flag = d_flag;
   a.stats = d_stats;
@@ -425,19 +562,28 @@ hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t s
   // pairs), grid-stride beyond 2^25 workgroups (a launch must stay below
   // 2^32 work-items)
   dim3 grid((unsigned)std::min<int64_t>(pl->n_pairs, 1 << 25));
+  const bool curved = m->n_curved > 0;
+#define VP_ROWS(PV)                                                   \
+  case PV:                                                            \
+    if (curved)                                                       \
+      k_rows<PV, true><<<grid, 64, 0, st>>>(a);                       \
+    else                                                              \
+      k_rows<PV, false><<<grid, 64, 0, st>>>(a);                      \
+    break
   switch (pl->p) {
-    case 1: k_rows<1><<<grid, 64, 0, st>>>(a); break;
-    case 2: k_rows<2><<<grid, 64, 0, st>>>(a); break;
-    case 3: k_rows<3><<<grid, 64, 0, st>>>(a); break;
-    case 4: k_rows<4><<<grid, 64, 0, st>>>(a); break;
-    case 5: k_rows<5><<<grid, 64, 0, st>>>(a); break;
-    case 6: k_rows<6><<<grid, 64, 0, st>>>(a); break;
-    case 7: k_rows<7><<<grid, 64, 0, st>>>(a); break;
-    case 8: k_rows<8><<<grid, 64, 0, st>>>(a); break;
-    case 9: k_rows<9><<<grid, 64, 0, st>>>(a); break;
-    case 10: k_rows<10><<<grid, 64, 0, st>>>(a); break;
+    VP_ROWS(1);
+    VP_ROWS(2);
+    VP_ROWS(3);
+    VP_ROWS(4);
+    VP_ROWS(5);
+    VP_ROWS(6);
+    VP_ROWS(7);
+    VP_ROWS(8);
+    VP_ROWS(9);
+    VP_ROWS(10);
     default: return hipErrorInvalidValue;
   }
+#undef VP_ROWS
   return hipGetLastError();
 }
 

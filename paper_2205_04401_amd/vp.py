@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "VP_OK", 1: "VP_EINVAL", 2: "VP_ENOMEM", 3: "VP_EDEVICE", 4: 
 
 # every symbol include/vp.h declares
 EXPORTS = ["vp_ctx_create", "vp_ctx_destroy", "vp_last_error", "vp_ref_nodes", "vp_ref_rule", "vp_mesh_create",
-           "vp_mesh_destroy", "vp_plan_create", "vp_plan_info", "vp_plan_pairs", "vp_plan_rows",
+           "vp_mesh_destroy", "vp_mesh_set_curved_sides", "vp_mesh_map_points", "vp_plan_create", "vp_plan_info", "vp_plan_pairs", "vp_plan_rows",
            "vp_execute", "vp_coefficients", "vp_plan_sources", "vp_plan_destroy", "vp_sync",
            "vp_ctx_profile", "vp_ctx_timings", "vp_server_create", "vp_server_destroy", "vp_submit",
            "vp_poll", "vp_wait", "vp_server_stats"]
@@ -80,6 +80,8 @@ def load(path=LIB_PATH):
         "vp_ref_rule": [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.POINTER(ctypes.c_int)],
         "vp_mesh_create": [P, I64, P, I64, P, ctypes.POINTER(P)],
         "vp_mesh_destroy": [P],
+        "vp_mesh_set_curved_sides": [P, I64, P, P, ctypes.c_int, P],
+        "vp_mesh_map_points": [P, ctypes.c_int, P, P],
         "vp_plan_create": [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_double, I64, P, P, ctypes.POINTER(P)],
         "vp_plan_info": [P, ctypes.POINTER(PlanStats)],
         "vp_plan_pairs": [P, P, P, P],
@@ -155,8 +157,8 @@ class Context:
         self.h = h
         self.device = device
 
-    def mesh(self, vert, tri):
-        return Mesh(self, vert, tri)
+    def mesh(self, vert, tri, curved=None):
+        return Mesh(self, vert, tri, curved)
 
     def plan(self, mesh, p, q, eps, targets, **opts):
         return Plan(self, mesh, p, q, eps, targets, **opts)
@@ -230,7 +232,9 @@ class Server:
 
 
 class Mesh:
-    def __init__(self, ctx, vert, tri):
+    def __init__(self, ctx, vert, tri, curved=None):
+        """curved = (curved_tri [n], curved_side [n], curved_pts [n, deg+1, 2])
+        or None (vp_mesh_set_curved_sides)."""
         vert = np.ascontiguousarray(vert, dtype=np.float64)
         tri = np.ascontiguousarray(tri, dtype=np.int32)
         h = P()
@@ -238,6 +242,24 @@ class Mesh:
         self.h = h
         self.ctx = ctx
         self.n_tri = tri.shape[0]
+        if curved is not None:
+            self.set_curved_sides(*curved)
+
+    def set_curved_sides(self, curved_tri, curved_side, curved_pts):
+        ct = np.ascontiguousarray(curved_tri, dtype=np.int32)
+        cs = np.ascontiguousarray(curved_side, dtype=np.int32)
+        cp = np.ascontiguousarray(curved_pts, dtype=np.float64)
+        if cp.ndim != 3 or cp.shape[0] != ct.shape[0] or cp.shape[2] != 2 or cs.shape != ct.shape:
+            raise VPError(VP_EINVAL, "curved sides: tri [n], side [n], pts [n, deg+1, 2]")
+        _check(load().vp_mesh_set_curved_sides(self.h, ct.shape[0], _ptr(ct), _ptr(cs), cp.shape[1] - 1, _ptr(cp)))
+
+    def map_points(self, ref_xy):
+        """[n_tri, n, 2] physical positions of the reference points on every
+        triangle (vp_mesh_map_points)."""
+        ref = np.ascontiguousarray(np.asarray(ref_xy, dtype=np.float64).reshape(-1, 2))
+        out = np.empty((self.n_tri, ref.shape[0], 2))
+        _check(load().vp_mesh_map_points(self.h, ref.shape[0], _ptr(ref), _ptr(out)))
+        return out
 
     def close(self):
         if self.h:
