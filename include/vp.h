@@ -290,6 +290,30 @@ vp_status vp_wait(vp_server* srv, vp_ticket ticket);
 /* Counters: requests completed, batches launched, RHS columns launched. */
 vp_status vp_server_stats(const vp_server* srv, int64_t* requests_done, int64_t* batches, int64_t* columns);
 
+/* Interpolation of the potential over a mesh (Sec. 3.5).  Given u at the
+ * order-p interpolation nodes (vp_ref_nodes; vp_mesh_map_points for their
+ * positions) of every triangle of `mesh` -- e.g. the staggered target mesh
+ * whose nodes were the targets of vp_execute -- u at any point x of the
+ * mesh is sum_k c_k K_k(rho^{-1}(x)), c = V^{-1} u of the triangle that
+ * contains x (Sec. 2.2 interpolation matrix; rho^{-1} affine, or Newton's
+ * method on a curved triangle).  The object references the mesh, which
+ * must outlive it (vp_mesh_destroy returns VP_EBUSY meanwhile). */
+typedef struct vp_interp vp_interp;
+vp_status vp_interp_create(vp_ctx* ctx, const vp_mesh* mesh, int p, vp_interp** out);
+vp_status vp_interp_destroy(vp_interp* it);
+/* Point location: tri_out[i] = the lowest-index triangle whose closure
+ * (barycentric tolerance 1e-13) contains pts_xy[i], -1 if none;
+ * ref_out [n][2] = rho^{-1}(pts_xy[i]) in it.  Host arrays. */
+vp_status vp_interp_locate(vp_interp* it, int64_t n, const double* pts_xy, int32_t* tri_out, double* ref_out);
+/* u at n (triangle, reference point) pairs: u_nodes [n_tri][n_p][n_rhs],
+ * tri [n], ref_xy [n][2] -> out [n][n_rhs] (NaN where tri[i] = -1).  The
+ * boundary trace of a curved side (Remark rem:bndry_interp): its point
+ * gamma(u) is at reference point (1 - u, 0) of its triangle, no Newton
+ * step needed.  Host arrays, or device pointers with VP_DEVICE_PTRS (then
+ * the work is queued on the context's stream: vp_sync before reading). */
+vp_status vp_interp_eval(vp_interp* it, int64_t n_rhs, const double* u_nodes, int64_t n, const int32_t* tri,
+                         const double* ref_xy, double* out, uint32_t flags);
+
 #ifdef __cplusplus
 }
 #endif

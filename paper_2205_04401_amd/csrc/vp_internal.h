@@ -384,6 +384,8 @@ hipError_t launch_split_xy(const double* xy, int64_t n, double* x, double* y, in
 hipError_t launch_basis_tables(vp_plan* pl, double* scratch, hipStream_t st);
 hipError_t launch_sources(vp_plan* pl, hipStream_t st);  // positions, weights and |J| scales
 hipError_t launch_map_points(const vp_mesh* m, int n_ref, const double* ref, double* out, hipStream_t st);
+hipError_t launch_vinv(int p, const double* nx, const double* ny, double* aug, double* vinv, int* bad,
+                       hipStream_t st);
 constexpr int kCurvedRadial = 12;  // points per part of the radial rule on curved self pieces
 hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err);  // near-list construction
 hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t st);

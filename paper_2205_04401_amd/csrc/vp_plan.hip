@@ -585,6 +585,29 @@ hipError_t launch_split_xy(const double* xy, int64_t n, double* x, double* y, in
   return hipGetLastError();
 }
 
+// V^{-1} of order p at the given nodes (one workgroup; aug: [n_p][2 n_p]
+// scratch), for other users of the interpolation matrix.
+hipError_t launch_vinv(int p, const double* nx, const double* ny, double* aug, double* vinv, int* bad,
+                       hipStream_t st) {
+  switch (p) {
+#define VP_VINV(PV) \
+  case PV: k_vandermonde_inverse<PV><<<1, 256, 0, st>>>(nx, ny, aug, vinv, bad); break
+    VP_VINV(1);
+    VP_VINV(2);
+    VP_VINV(3);
+    VP_VINV(4);
+    VP_VINV(5);
+    VP_VINV(6);
+    VP_VINV(7);
+    VP_VINV(8);
+    VP_VINV(9);
+    VP_VINV(10);
+#undef VP_VINV
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <int P>
 static hipError_t basis_tables_p(vp_plan* pl, double* scratch, int* d_bad, hipStream_t st) {
   k_vandermonde_inverse<P><<<1, 256, 0, st>>>(scratch, scratch + pl->n_p, scratch + 2 * pl->n_p, pl->vinv, d_bad);

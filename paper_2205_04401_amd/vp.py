@@ -30,7 +30,8 @@ EXPORTS = ["vp_ctx_create", "vp_ctx_destroy", "vp_last_error", "vp_ref_nodes", "
            "vp_mesh_destroy", "vp_mesh_set_curved_sides", "vp_mesh_map_points", "vp_plan_create", "vp_plan_info", "vp_plan_pairs", "vp_plan_rows",
            "vp_execute", "vp_coefficients", "vp_plan_sources", "vp_plan_destroy", "vp_sync",
            "vp_ctx_profile", "vp_ctx_timings", "vp_server_create", "vp_server_destroy", "vp_submit",
-           "vp_poll", "vp_wait", "vp_server_stats"]
+           "vp_poll", "vp_wait", "vp_server_stats", "vp_interp_create", "vp_interp_destroy", "vp_interp_locate",
+           "vp_interp_eval"]
 STAGES = ["classify", "rows", "coef", "far", "finish"]
 
 
@@ -99,6 +100,10 @@ def load(path=LIB_PATH):
         "vp_poll": [P, I64, ctypes.POINTER(ctypes.c_int)],
         "vp_wait": [P, I64],
         "vp_server_stats": [P, P, P, P],
+        "vp_interp_create": [P, P, ctypes.c_int, ctypes.POINTER(P)],
+        "vp_interp_destroy": [P],
+        "vp_interp_locate": [P, I64, P, P, P],
+        "vp_interp_eval": [P, I64, P, I64, P, P, P, ctypes.c_uint32],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -162,6 +167,9 @@ class Context:
 
     def plan(self, mesh, p, q, eps, targets, **opts):
         return Plan(self, mesh, p, q, eps, targets, **opts)
+
+    def interp(self, mesh, p):
+        return Interp(self, mesh, p)
 
     def server(self, n_slots=4, max_batch_rhs=32):
         return Server(self, n_slots, max_batch_rhs)
@@ -264,6 +272,46 @@ class Mesh:
     def close(self):
         if self.h:
             _check(load().vp_mesh_destroy(self.h))
+            self.h = None
+
+
+class Interp:
+    """Interpolation of the potential over a mesh (vp_interp_*): node values
+    [n_tri, n_p] or [n_tri, n_p, R] in, values anywhere out."""
+
+    def __init__(self, ctx, mesh, p):
+        h = P()
+        _check(load().vp_interp_create(ctx.h, mesh.h, int(p), ctypes.byref(h)))
+        self.h = h
+        self.mesh = mesh
+        self.p = int(p)
+
+    def locate(self, pts):
+        """(tri [n] int32, -1 outside; ref [n, 2])."""
+        pts = np.ascontiguousarray(np.asarray(pts, dtype=np.float64).reshape(-1, 2))
+        tri = np.empty(pts.shape[0], dtype=np.int32)
+        ref = np.empty((pts.shape[0], 2))
+        _check(load().vp_interp_locate(self.h, pts.shape[0], _ptr(pts), _ptr(tri), _ptr(ref)))
+        return tri, ref
+
+    def eval(self, u_nodes, tri, ref):
+        u = np.ascontiguousarray(np.asarray(u_nodes, dtype=np.float64))
+        single = u.ndim == 2
+        if single:
+            u = u[:, :, None]
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        ref = np.ascontiguousarray(np.asarray(ref, dtype=np.float64).reshape(-1, 2))
+        out = np.empty((tri.shape[0], u.shape[2]))
+        _check(load().vp_interp_eval(self.h, u.shape[2], _ptr(u), tri.shape[0], _ptr(tri), _ptr(ref), _ptr(out), 0))
+        return out[:, 0] if single else out
+
+    def __call__(self, u_nodes, pts):
+        tri, ref = self.locate(pts)
+        return self.eval(u_nodes, tri, ref)
+
+    def close(self):
+        if self.h:
+            _check(load().vp_interp_destroy(self.h))
             self.h = None
 
 

@@ -460,6 +460,78 @@ def test_curved_star_sampled(vp_ctx):
     mesh.close()
 
 
+# ---------------------------------------------------------------------------
+# the potential anywhere: interpolation over a mesh element (Sec. 3.5)
+# ---------------------------------------------------------------------------
+
+def test_interp_locate_and_eval_match_oracle(vp_ctx):
+    """Point location (straight and curved triangles, points on the curved
+    boundary, outside points) and evaluation match the oracle's."""
+    from numpy.polynomial import chebyshev as cheb
+    from oracle import curved, interp
+    v, t, ct, cs, cp = W.curved_star(n_tri=2000, n_boundary=300, seed=74, deg=12)
+    o = curved.CurvedOracle(v, t, ct, cs, cp, 4, 6, 1e-10)
+    mesh = vp_ctx.mesh(v, t, curved=(ct, cs, cp))
+    it = vp_ctx.interp(mesh, 4)
+    rng = np.random.default_rng(75)
+    th = rng.uniform(0, 2 * math.pi, 40)
+    rad = W.star_radius(th) * rng.uniform(0.0, 1.0, 40)
+    pts = [np.stack([rad * np.cos(th), rad * np.sin(th)], 1)]
+    for tc in list(o.curves)[:10]:  # points of curved sides
+        uu = rng.uniform(0.05, 0.95)
+        pts.append(np.array([[cheb.chebval(2 * uu - 1, o.curves[tc][0]), cheb.chebval(2 * uu - 1, o.curves[tc][1])]]))
+    pts.append(np.array([[2.0, 2.0], [-1.4, 0.0]]))
+    pts = np.concatenate(pts)
+    tri, ref = it.locate(pts)
+    n_same = worst_ref = 0
+    for i, x in enumerate(pts):
+        to, zo = interp.locate(o, x)
+        assert (tri[i] < 0) == (to < 0), (i, tri[i], to)
+        if to >= 0 and tri[i] == to:
+            n_same += 1
+            worst_ref = max(worst_ref, np.abs(ref[i] - zo).max())
+    Y = o.node_positions(rules.interp_nodes(4))
+    un = W.gaussian_sum(76, v, t)(Y[:, :, 0], Y[:, :, 1])
+    u = it.eval(un, tri, ref)
+    ref_u = np.array([interp.evaluate(4, un, tri[i], ref[i]) if tri[i] >= 0 else np.nan for i in range(len(pts))])
+    inside = tri >= 0
+    e = np.abs(u[inside] - ref_u[inside]).max() / np.abs(ref_u[inside]).max()
+    say("interp: located", inside.sum(), "same triangle as the oracle", n_same, "ref diff", worst_ref, "eval rel", e)
+    assert n_same >= inside.sum() - 2 and worst_ref < 1e-12 and e < 1e-13 and np.all(np.isnan(u[~inside]))
+    it.close()
+    mesh.close()
+
+
+def test_potential_anywhere_on_a_curved_disk(vp_ctx):
+    """Unit density on the curved disk: the potential computed at the p = 6
+    nodes of a second, curved target mesh of the disk, then interpolated to
+    arbitrary points and to points of the boundary (Sec. 3.5), matches the
+    disk closed form to the interpolation error."""
+    vq, tq, cq, sq, pq = W.curved_disk(n_tri=200, n_boundary=30, seed=1, deg=16)
+    vt, tt, ctt, stt, ptt = W.curved_disk(n_tri=160, n_boundary=26, seed=5, deg=16)
+    src = vp_ctx.mesh(vq, tq, curved=(cq, sq, pq))
+    tgt = vp_ctx.mesh(vt, tt, curved=(ctt, stt, ptt))
+    p = 6
+    nodes = tgt.map_points(rules.interp_nodes(p)).reshape(-1, 2)
+    plan = vp_ctx.plan(src, 1, 8, 1e-13, nodes)
+    u_nodes = plan.execute(np.ones((len(tq), 3))).reshape(len(tt), -1)
+    it = vp_ctx.interp(tgt, p)
+    rng = np.random.default_rng(77)
+    r = np.concatenate([np.sqrt(rng.uniform(0, 0.98, 30)), np.ones(10)])
+    a = rng.uniform(0, 2 * math.pi, len(r))
+    pts = np.stack([r * np.cos(a), r * np.sin(a)], 1)
+    tri, ref = it.locate(pts)
+    u = it.eval(u_nodes, tri, ref)
+    exact = r ** 2 / 4 - 0.25
+    e = np.abs(u - exact).max() / np.abs(exact).max()
+    say("potential anywhere: located", (tri >= 0).sum(), "of", len(pts), "rel vs closed form", e)
+    assert np.all(tri >= 0) and e < 1e-9
+    it.close()
+    plan.close()
+    tgt.close()
+    src.close()
+
+
 def test_empty_target_set_and_single_triangle(vp_ctx):
     v = np.array([[0.0, 0.0], [1.0, 0.2], [0.1, 0.9]])
     t = np.array([[0, 2, 1]], dtype=np.int32)  # clockwise: the library swaps B and C

@@ -454,3 +454,52 @@ def test_curved_map_inverse_round_trip_and_straight_limit():
     ref = os_.evaluate(f(Ys), tg)
     assert np.abs(of.evaluate(f(of.node_positions(X)), tg) - ref).max() < 1e-12 * np.abs(ref).max()
 
+
+
+# ---------------------------------------------------------------------------
+# interpolation of the potential over a mesh element (Sec. 3.5)
+# ---------------------------------------------------------------------------
+
+def test_interpolation_reproduces_polynomials_and_marks_outside_points():
+    """A global cubic given at the p = 3 nodes of every triangle is
+    reproduced exactly anywhere in the mesh; points outside give NaN."""
+    from oracle import interp
+    v, t = W.disk_mesh(n_tri=120, n_boundary=24, seed=4)
+    o = potential.Oracle(v, t, 3, 4, 1e-10)
+    X = rules.interp_nodes(3)
+    Y = o.A[:, None, :] + X[None, :, :1] * (o.B - o.A)[:, None, :] + X[None, :, 1:2] * (o.C - o.A)[:, None, :]
+
+    def g(x, y):
+        return 1.0 - 2.0 * x + x * y + 3.0 * y ** 3 - x * x * y
+
+    rng = np.random.default_rng(8)
+    r, a = np.sqrt(rng.uniform(0, 0.9, 30)), rng.uniform(0, 2 * math.pi, 30)
+    pts = np.stack([r * np.cos(a), r * np.sin(a)], 1)
+    u = interp.interpolate(o, 3, g(Y[..., 0], Y[..., 1]), pts)
+    assert np.abs(u - g(pts[:, 0], pts[:, 1])).max() < 1e-13
+    assert np.all(np.isnan(interp.interpolate(o, 3, g(Y[..., 0], Y[..., 1]), [[2.0, 0.0], [0.0, -1.5]])))
+
+
+def test_interpolation_boundary_trace_on_curved_sides():
+    """Remark rem:bndry_interp: the point gamma(u) of a curved side lies at
+    reference point (1 - u, 0) of its triangle (the side runs from B at
+    u = 0 to A at u = 1); point location by Newton's method finds it there,
+    and a polynomial in reference coordinates is reproduced."""
+    from oracle import curved, interp
+    from numpy.polynomial import chebyshev as cheb
+    v, t, ct, cs, cp = W.curved_disk(n_tri=120, n_boundary=24, seed=4, deg=12)
+    o = curved.CurvedOracle(v, t, ct, cs, cp, 4, 6, 1e-10)
+    X = rules.interp_nodes(4)
+    g = lambda a, b: 0.5 + a - 2.0 * b + a * b * b + a ** 4  # noqa: E731
+    un = np.broadcast_to(g(X[:, 0], X[:, 1])[None, :], (len(t), len(X)))
+    rng = np.random.default_rng(13)
+    worst_ref = worst_val = 0.0
+    for tc in list(o.curves)[:8]:
+        cx, cy = o.curves[tc][0], o.curves[tc][1]
+        for uu in rng.uniform(0.05, 0.95, 3):
+            x = np.array([cheb.chebval(2 * uu - 1, cx), cheb.chebval(2 * uu - 1, cy)])
+            tt, z = interp.locate(o, x)
+            assert tt == tc
+            worst_ref = max(worst_ref, abs(z[0] - (1 - uu)) + abs(z[1]))
+            worst_val = max(worst_val, abs(interp.evaluate(4, un, tt, z) - g(1 - uu, 0.0)))
+    assert worst_ref < 1e-12 and worst_val < 1e-11
