@@ -290,6 +290,21 @@ vp_status vp_wait(vp_server* srv, vp_ticket ticket);
 /* Counters: requests completed, batches launched, RHS columns launched. */
 vp_status vp_server_stats(const vp_server* srv, int64_t* requests_done, int64_t* batches, int64_t* columns);
 
+/* A captured evaluation (HIP graph) for repeated solves with new density
+ * values in the same device buffer: the launches of vp_execute (FP64 or
+ * VP_MIXED; flags 0 or VP_FAR_ONLY) for `plan`, n_rhs densities at
+ * density_dev [n_tri][n_p][n_rhs] and output u_dev [n_tgt][n_rhs] (device
+ * pointers that must stay valid), with a workspace of the graph's own.
+ * vp_graph_launch queues one replay on the context's stream (vp_sync to
+ * wait); the result equals vp_execute's.  The plan cannot be destroyed
+ * while a graph of it exists (VP_EBUSY).  For callers that run many small
+ * solves, where launch overhead matters. */
+typedef struct vp_graph vp_graph;
+vp_status vp_graph_create(vp_plan* plan, int64_t n_rhs, const double* density_dev, double* u_dev, vp_precision prec,
+                          uint32_t flags, vp_graph** out);
+vp_status vp_graph_launch(vp_graph* g);
+vp_status vp_graph_destroy(vp_graph* g);
+
 /* Interpolation of the potential over a mesh (Sec. 3.5).  Given u at the
  * order-p interpolation nodes (vp_ref_nodes; vp_mesh_map_points for their
  * positions) of every triangle of `mesh` -- e.g. the staggered target mesh

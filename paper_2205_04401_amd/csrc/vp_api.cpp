@@ -915,6 +915,101 @@ vp_status vp_coefficients(vp_plan* pl, int64_t R, const double* density, double*
   return VP_OK;
 }
 
+}  // extern "C"
+
+struct vp_graph {
+  vp_plan* plan = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double *c = nullptr, *q = nullptr, *part = nullptr;
+  float* q32 = nullptr;
+  size_t bytes = 0;
+};
+
+extern "C" {
+
+vp_status vp_graph_create(vp_plan* pl, int64_t R, const double* density, double* u_out, vp_precision prec,
+                          uint32_t flags, vp_graph** out) {
+  if (!pl || !out) return fail(VP_EINVAL, "vp_graph_create: NULL argument");
+  if (R < 1) return fail(VP_EINVAL, "vp_graph_create: n_rhs must be >= 1");
+  if (prec != VP_FP64 && prec != VP_MIXED) return fail(VP_EINVAL, "vp_graph_create: unknown precision");
+  if (flags & ~(uint32_t)VP_FAR_ONLY) return fail(VP_EINVAL, "vp_graph_create: flags other than VP_FAR_ONLY");
+  if ((!density && pl->n_tri) || (!u_out && pl->n_tgt)) return fail(VP_EINVAL, "vp_graph_create: NULL array");
+  VP_HIP(hipSetDevice(pl->ctx->device), "hipSetDevice");
+  vp_graph* g = new vp_graph;
+  g->plan = pl;
+  const int64_t split = vp::far_split(pl);
+  const size_t nC = (size_t)pl->n_tri * pl->n_p * R, nQ = (size_t)pl->n_src_pad * R,
+               nP = (size_t)split * pl->n_tgt * R;
+  g->bytes = 8 * (nC + nQ + nP) + (prec == VP_MIXED ? 4 * nQ : 0);
+  auto drop = [&](vp_graph* x) {
+    if (x->exec) (void)hipGraphExecDestroy(x->exec);
+    if (x->graph) (void)hipGraphDestroy(x->graph);
+    if (x->cap) (void)hipStreamDestroy(x->cap);
+    for (void* p : {(void*)x->c, (void*)x->q, (void*)x->part, (void*)x->q32})
+      if (p) (void)hipFree(p);
+    delete x;
+  };
+  if (pl->ctx->budget && pl->ctx->in_use + g->bytes > pl->ctx->budget) {
+    drop(g);
+    return fail(VP_ENOMEM, "vp_graph_create: workspace of %zu bytes exceeds the HBM budget", g->bytes);
+  }
+  hipError_t e;
+  if ((e = hipMalloc((void**)&g->c, 8 * std::max<size_t>(nC, 1))) != hipSuccess ||
+      (e = hipMalloc((void**)&g->q, 8 * std::max<size_t>(nQ, 1))) != hipSuccess ||
+      (e = hipMalloc((void**)&g->part, 8 * std::max<size_t>(nP, 1))) != hipSuccess ||
+      (prec == VP_MIXED && (e = hipMalloc((void**)&g->q32, 4 * std::max<size_t>(nQ, 1))) != hipSuccess) ||
+      (e = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking)) != hipSuccess) {
+    drop(g);
+    return hip_fail(e, "vp_graph_create");
+  }
+  // capture the evaluation's launches (no memsets, no host synchronisation)
+  const bool prof = pl->ctx->profile;
+  pl->ctx->profile = false;
+  hipError_t le = hipSuccess;
+  if ((e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal)) == hipSuccess) {
+    if ((le = vp::launch_coefficients(pl, density, R, g->c, g->q, g->cap)) == hipSuccess &&
+        (le = vp::launch_far(pl, g->q, R, split, g->part, g->cap, nullptr, prec == VP_MIXED ? g->q32 : nullptr)) ==
+            hipSuccess)
+      le = vp::launch_finish(pl, g->part, split, g->c, R, (flags & VP_FAR_ONLY) != 0, u_out, g->cap);
+    e = hipStreamEndCapture(g->cap, &g->graph);
+  }
+  pl->ctx->profile = prof;
+  if (e == hipSuccess) e = le;
+  if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    drop(g);
+    return hip_fail(e, "vp_graph_create: capture");
+  }
+  pl->ctx->in_use += g->bytes;
+  pl->live_requests++;
+  *out = g;
+  return VP_OK;
+}
+
+vp_status vp_graph_launch(vp_graph* g) {
+  if (!g) return fail(VP_EINVAL, "vp_graph_launch: NULL graph");
+  VP_HIP(hipSetDevice(g->plan->ctx->device), "hipSetDevice");
+  VP_HIP(hipGraphLaunch(g->exec, g->plan->ctx->stream), "vp_graph_launch");
+  return VP_OK;
+}
+
+vp_status vp_graph_destroy(vp_graph* g) {
+  if (!g) return VP_OK;
+  (void)hipSetDevice(g->plan->ctx->device);
+  (void)hipStreamSynchronize(g->plan->ctx->stream);
+  g->plan->ctx->in_use -= g->bytes;
+  g->plan->live_requests--;
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  (void)hipStreamDestroy(g->cap);
+  for (void* p : {(void*)g->c, (void*)g->q, (void*)g->part, (void*)g->q32})
+    if (p) (void)hipFree(p);
+  delete g;
+  return VP_OK;
+}
+
 vp_status vp_plan_destroy(vp_plan* pl) {
   if (!pl) return VP_OK;
   if (pl->live_requests > 0)

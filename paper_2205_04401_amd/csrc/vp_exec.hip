@@ -376,6 +376,11 @@ __global__ __launch_bounds__(kBlock, 2) void k_far_mfma32(
     }
 }
 
+__global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = v;
+}
+
 __global__ void k_to_f32_ln2(const double* __restrict__ Q, int64_t n, float* __restrict__ Q32) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
@@ -459,10 +464,11 @@ hipError_t launch_unpack_columns(const double* src, int64_t rows, int64_t src_co
 
 hipError_t launch_coefficients(const vp_plan* pl, const double* F, int64_t R, double* C, double* Q, hipStream_t st) {
   const int64_t T = pl->n_tri;
-  // the padding sources past n_src carry zero charge for this R
+  // the padding sources past n_src carry zero charge for this R (a fill
+  // kernel, not a memset, so that the sequence can be captured in a graph)
   if (Q && pl->n_src_pad > pl->n_src) {
-    hipError_t e = hipMemsetAsync(Q + pl->n_src * R, 0, sizeof(double) * (pl->n_src_pad - pl->n_src) * R, st);
-    if (e != hipSuccess) return e;
+    const int64_t nz = (pl->n_src_pad - pl->n_src) * R;
+    k_fill<<<blocks_for(nz), kBlock, 0, st>>>(Q + pl->n_src * R, nz, 0.0);
   }
   if (T == 0) return hipSuccess;
   VP_DISPATCH_P(pl->p, (k_coef<P><<<blocks_for(T * R), kBlock, 0, st>>>(F, pl->vinv, T, R, C)));

@@ -31,7 +31,7 @@ EXPORTS = ["vp_ctx_create", "vp_ctx_destroy", "vp_last_error", "vp_ref_nodes", "
            "vp_execute", "vp_coefficients", "vp_plan_sources", "vp_plan_destroy", "vp_sync",
            "vp_ctx_profile", "vp_ctx_timings", "vp_server_create", "vp_server_destroy", "vp_submit",
            "vp_poll", "vp_wait", "vp_server_stats", "vp_interp_create", "vp_interp_destroy", "vp_interp_locate",
-           "vp_interp_eval"]
+           "vp_interp_eval", "vp_graph_create", "vp_graph_launch", "vp_graph_destroy"]
 STAGES = ["classify", "rows", "coef", "far", "finish"]
 
 
@@ -100,6 +100,9 @@ def load(path=LIB_PATH):
         "vp_poll": [P, I64, ctypes.POINTER(ctypes.c_int)],
         "vp_wait": [P, I64],
         "vp_server_stats": [P, P, P, P],
+        "vp_graph_create": [P, I64, P, P, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(P)],
+        "vp_graph_launch": [P],
+        "vp_graph_destroy": [P],
         "vp_interp_create": [P, P, ctypes.c_int, ctypes.POINTER(P)],
         "vp_interp_destroy": [P],
         "vp_interp_locate": [P, I64, P, P, P],
@@ -272,6 +275,33 @@ class Mesh:
     def close(self):
         if self.h:
             _check(load().vp_mesh_destroy(self.h))
+            self.h = None
+
+
+class Graph:
+    """A captured evaluation (vp_graph_*) of a plan for device density and
+    output tensors that stay in place; launch() replays it asynchronously."""
+
+    def __init__(self, plan, F, out, mixed=False, far_only=False):
+        if not (_is_device(F) and _is_device(out)):
+            raise VPError(VP_EINVAL, "Graph needs device tensors for the density and the output")
+        import torch
+        F = F if F.dim() == 3 else F.unsqueeze(-1)
+        if not (F.is_contiguous() and out.is_contiguous()) or F.dtype != torch.float64 or out.dtype != torch.float64:
+            raise VPError(VP_EINVAL, "Graph needs contiguous float64 tensors")
+        h = P()
+        _check(load().vp_graph_create(plan.h, F.shape[2], _ptr(F), _ptr(out), VP_MIXED if mixed else VP_FP64,
+                                      VP_FAR_ONLY if far_only else 0, ctypes.byref(h)))
+        self.h = h
+        self.plan = plan
+        self.F, self.out = F, out
+
+    def launch(self):
+        _check(load().vp_graph_launch(self.h))
+
+    def close(self):
+        if self.h:
+            _check(load().vp_graph_destroy(self.h))
             self.h = None
 
 

@@ -233,6 +233,50 @@ def test_c1_many_rhs_matrix_core_blocks(c1):
     assert e64 <= REL_FAR and emx <= 1e-6 and eo <= REL_E2E
 
 
+def test_graph_replays_equal_eager(c1, vp_ctx):
+    """A captured evaluation (HIP graph), FP64 and mixed, replayed several
+    times with other eager work and output clears in between: every replay
+    equals vp_execute's result bit for bit, also after new density values
+    are written into the same buffer."""
+    import time
+    import torch
+    from paper_2205_04401_amd import vp
+    plan = c1["plan"]
+    F3 = np.ascontiguousarray(np.stack([c1["F"], 2.0 * c1["F"] - 1.0, np.sin(c1["F"])], -1))
+    Fd = torch.from_numpy(F3).cuda()
+    Ud = torch.empty((len(c1["tg"]), 3), dtype=torch.float64, device="cuda")
+    for mixed in (False, True):
+        g = vp.Graph(plan, Fd, Ud, mixed=mixed)
+        ref = plan.execute(Fd, mixed=mixed).cpu().numpy()
+        for k in range(4):
+            plan.execute(Fd * (k + 2.0), mixed=not mixed)
+            Ud.zero_()
+            torch.cuda.synchronize()
+            g.launch()
+            torch.cuda.synchronize()
+            assert np.array_equal(Ud.cpu().numpy(), ref), (mixed, k)
+        Fd.mul_(-0.5)
+        ref2 = plan.execute(Fd, mixed=mixed).cpu().numpy()
+        g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(Ud.cpu().numpy(), ref2)
+        Fd.mul_(-2.0)
+        if not mixed:
+            n = 200
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(n):
+                plan.execute(Fd, out=Ud, asynchronous=True)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(n):
+                g.launch()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            say("c1 evaluation latency: eager", (t1 - t0) / n * 1e6, "us, graph", (t2 - t1) / n * 1e6, "us")
+        g.close()
+
+
 def test_c1_deterministic(c1, vp_ctx):
     plan2 = vp_ctx.plan(c1["mesh"], 4, 8, 1e-13, c1["tg"])
     a, b = c1["plan"].pairs(), plan2.pairs()
