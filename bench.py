@@ -106,7 +106,7 @@ def batched(ctx, mesh, tg_d, vq, tq, p, q, R, steps):
             "far_pair_rhs_per_s": pair_rhs / far_s,
             "far_roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                              "frac": achieved / peak, "flops_per_pair_rhs": 2,
-                             "kernel": "k_far_mfma32<4>" if mixed else "k_far_mfma64<4>"},
+                             "kernel": "k_far_mfma32<4, 4>" if mixed else "k_far_mfma64<4, 4>"},
             "breakdown_ms": {k: v[0] / steps for k, v in tm.items() if v[1]},
         })
         print(json.dumps({"batched": out[-1]}), flush=True)
@@ -168,7 +168,7 @@ def far_kernel_digest():
     csrc = os.path.join(ROOT, "paper_2205_04401_amd", "csrc")
     exe = open(os.path.join(csrc, "vp_exec.hip")).read()
     hdr = open(os.path.join(csrc, "vp_internal.h")).read()
-    a = exe.index("template <int RB>\nstruct FarShape")
+    a = exe.index("template <int S, int RB>\nstruct FarShape")
     b = exe.index("\n}\n", exe.index("void k_far(", a)) + 3
     c = hdr.index("constexpr double kR2Bias")
     d = hdr.index("\n}\n", hdr.index("void vp_log_wide_parts(", c)) + 3

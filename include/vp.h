@@ -305,6 +305,45 @@ vp_status vp_graph_create(vp_plan* plan, int64_t n_rhs, const double* density_de
 vp_status vp_graph_launch(vp_graph* g);
 vp_status vp_graph_destroy(vp_graph* g);
 
+/* Launch shape of the direct far sum (the sum over all far-rule nodes of
+ * Sec. 3.6), kept per plan, right-hand-side count and precision.  Every
+ * shape gives the same potential up to rounding; only speed differs.
+ *   shape       kernel of the vector-ALU sums:
+ *               VP_FAR_WIDE     1024-thread blocks, 2 targets per thread,
+ *                               4096-entry logarithm table (large target sets)
+ *               VP_FAR_NARROW1  256-thread blocks, 1 target per thread,
+ *                               256-entry table (small target sets)
+ *               VP_FAR_NARROW2  256-thread blocks, 2 targets per thread
+ *               (sums of several right-hand sides and the FP32 sum always run
+ *               256-thread blocks; WIDE then means 2 targets per thread)
+ *   mfma_tiles  16-target tiles per wavefront of the matrix-core sums
+ *               (blocks of 16 right-hand sides): 1, 2 or 4
+ *   n_split     source chunks, 1 <= n_split <= max(1, n_src_pad / 64)
+ *               (n_src_pad: far sources rounded up to a multiple of 256;
+ *               chunks are whole multiples of 64 sources, so a large n_split
+ *               can leave chunks empty); each target gets n_split partial
+ *               sums that the correction step adds up.
+ * Without a stored shape a plan uses one chosen from its sizes.
+ * vp_plan_autotune times each candidate shape (far sum plus the step that
+ * adds the partials) on the context's stream with HIP events, `reps`
+ * launches each after one warm-up, stores the fastest for (n_rhs, prec) and
+ * returns it with its mean time in ms.  It runs the far sum on the
+ * workspace's zero charges and leaves no result; its cost is about
+ * (candidates x (reps + 1)) far sums.  Not to be called while work of the
+ * plan is queued on another stream, or while a server holds requests of it.
+ * vp_plan_set_far_config stores a given shape (VP_EINVAL if out of range);
+ * graphs and servers use the shape stored when they issue the work. */
+typedef struct {
+  int32_t shape;
+  int32_t mfma_tiles;
+  int64_t n_split;
+} vp_far_config;
+enum { VP_FAR_WIDE = 0, VP_FAR_NARROW1 = 1, VP_FAR_NARROW2 = 2 };
+vp_status vp_plan_far_config(const vp_plan* plan, int64_t n_rhs, vp_precision prec, vp_far_config* out);
+vp_status vp_plan_set_far_config(vp_plan* plan, int64_t n_rhs, vp_precision prec, const vp_far_config* cfg);
+vp_status vp_plan_autotune(vp_plan* plan, int64_t n_rhs, vp_precision prec, int reps, vp_far_config* best_out,
+                           double* best_ms_out);
+
 /* Interpolation of the potential over a mesh (Sec. 3.5).  Given u at the
  * order-p interpolation nodes (vp_ref_nodes; vp_mesh_map_points for their
  * positions) of every triangle of `mesh` -- e.g. the staggered target mesh

@@ -747,7 +747,7 @@ vp_status vp_plan_info(const vp_plan* pl, vp_plan_stats* out) {
   out->eps = pl->eps;
   out->ms_classify = pl->ms_classify;
   out->ms_rows = pl->ms_rows;
-  out->far_split = vp::far_split(pl);
+  out->far_split = vp::far_config(pl, 1, false).n_split;
   return VP_OK;
 }
 
@@ -790,24 +790,61 @@ vp_status vp_plan_sources(const vp_plan* pl, double* xy) {
 
 }  // extern "C"
 
-// Source chunks of the far sum: enough blocks (about 16 per CU of a
-// 256-CU device) for an even finish, a multiple of 8 so each chunk's blocks
-// share an XCD, and chunks of at least 256 sources.
-int64_t vp::far_split(const vp_plan* pl) {
-  const int64_t tpb = vp::far_targets_per_block();
+// Far-sum launch shape from the sizes.  Source chunks are set so that
+// the launch has about 16384 blocks on the FP64 vector ALUs (32768 for the
+// shorter FP32 sum, 4096 on the matrix cores, whose blocks hold 16x more
+// work per source), a multiple of 8 (the
+// blocks of one chunk then share an XCD), with chunks of at least 64
+// sources and at most 2^23 blocks: many short blocks keep the last round of
+// blocks on the device short, which outweighs the extra partial sums.  Wide
+// blocks for one right-hand side once they can make 4096 such blocks, else
+// narrow ones (the unit-square case with 1920 targets fills only one wide
+// block per chunk).
+namespace {
+vp_far_config far_for_shape(const vp_plan* pl, int64_t R, bool mixed, int shape, int mfma_tiles) {
+  vp_far_config c;
+  c.shape = shape;
+  c.mfma_tiles = mfma_tiles;
+  const int64_t tpb = vp::far_targets_per_block(c, R, mixed);
   const int64_t n_tb = std::max<int64_t>(1, (pl->n_tgt + tpb - 1) / tpb);
-  int64_t want = (4096 + n_tb - 1) / n_tb;
+  const int64_t blocks = R >= 16 ? 4096 : mixed ? 32768 : 16384;
+  int64_t want = (blocks + n_tb - 1) / n_tb;
   want = ((want + 7) / 8) * 8;
-  const int64_t most = std::max<int64_t>(1, std::min<int64_t>(pl->n_src_pad / 256, (1LL << 23) / n_tb));
-  return std::max<int64_t>(1, std::min(want, most));
+  const int64_t most = std::max<int64_t>(1, std::min<int64_t>(pl->n_src_pad / 64, (1LL << 23) / n_tb));
+  c.n_split = std::max<int64_t>(1, std::min(want, most));
+  return c;
+}
+}  // namespace
+
+vp_far_config vp::far_default(const vp_plan* pl, int64_t R, bool mixed) {
+  vp_far_config wide = far_for_shape(pl, R, mixed, VP_FAR_WIDE, 4);
+  vp_far_config w1 = wide;
+  w1.n_split = 1;
+  const int64_t tpb = far_targets_per_block(w1, 1, false);
+  const int64_t n_tb = std::max<int64_t>(1, (pl->n_tgt + tpb - 1) / tpb);
+  if (n_tb * std::max<int64_t>(1, pl->n_src_pad / 64) >= 4096) return wide;
+  return far_for_shape(pl, R, mixed, VP_FAR_NARROW1, 4);
+}
+
+vp_far_config vp::far_config(const vp_plan* pl, int64_t R, bool mixed) {
+  auto it = pl->far_tuned.find({R, mixed ? 1 : 0});
+  return it != pl->far_tuned.end() ? it->second : far_default(pl, R, mixed);
+}
+
+bool vp::far_config_valid(const vp_plan* pl, const vp_far_config& c) {
+  return c.shape >= VP_FAR_WIDE && c.shape <= VP_FAR_NARROW2 &&
+         (c.mfma_tiles == 1 || c.mfma_tiles == 2 || c.mfma_tiles == 4) && c.n_split >= 1 &&
+         c.n_split <= std::max<int64_t>(1, pl->n_src_pad / 64);
 }
 
 namespace {
 
 // grow the execute workspace to n_rhs right-hand sides
-vp_status ensure_workspace(vp_plan* pl, int64_t R) {
-  const int64_t split = vp::far_split(pl);
-  if (pl->ws_rhs >= R && pl->ws_split == split && pl->ws_c) return VP_OK;
+// (and at least `split` far partials per target and right-hand side)
+vp_status ensure_workspace(vp_plan* pl, int64_t R, int64_t split) {
+  if (pl->ws_rhs >= R && pl->ws_split >= split && pl->ws_c) return VP_OK;
+  R = std::max(R, pl->ws_rhs);
+  split = std::max(split, pl->ws_split);
   double* ws[] = {pl->ws_f, pl->ws_c, pl->ws_q, pl->ws_part, pl->ws_u};
   for (double* p : ws)
     if (p) (void)hipFree(p);
@@ -854,7 +891,8 @@ vp_status vp_execute(vp_plan* pl, int64_t R, const double* density, double* u_ou
   const bool dev = flags & VP_DEVICE_PTRS;
   if ((flags & VP_ASYNC) && !dev) return fail(VP_EINVAL, "vp_execute: VP_ASYNC needs VP_DEVICE_PTRS");
   VP_HIP(hipSetDevice(pl->ctx->device), "hipSetDevice");
-  vp_status s = ensure_workspace(pl, R);
+  const vp_far_config cfg = vp::far_config(pl, R, prec == VP_MIXED);
+  vp_status s = ensure_workspace(pl, R, cfg.n_split);
   if (s != VP_OK) return s;
   hipStream_t st = pl->ctx->stream;
   const size_t nF = (size_t)pl->n_tri * pl->n_p * R;
@@ -873,14 +911,14 @@ vp_status vp_execute(vp_plan* pl, int64_t R, const double* density, double* u_ou
   {
     StageTimer tm(ctx, VP_STAGE_FAR);
     int64_t nl = 0;
-    VP_HIP(vp::launch_far(pl, pl->ws_q, R, pl->ws_split, pl->ws_part, st, &nl,
+    VP_HIP(vp::launch_far(pl, pl->ws_q, R, cfg, pl->ws_part, st, &nl,
                           prec == VP_MIXED ? pl->ws_q32 : nullptr),
            "vp_execute: far field");
     tm.stop(nl);
   }
   {
     StageTimer tm(ctx, VP_STAGE_FINISH);
-    VP_HIP(vp::launch_finish(pl, pl->ws_part, pl->ws_split, pl->ws_c, R, (flags & VP_FAR_ONLY) != 0, U, st),
+    VP_HIP(vp::launch_finish(pl, pl->ws_part, cfg.n_split, pl->ws_c, R, (flags & VP_FAR_ONLY) != 0, U, st),
            "vp_execute: corrections");
     tm.stop(1);
   }
@@ -897,7 +935,7 @@ vp_status vp_coefficients(vp_plan* pl, int64_t R, const double* density, double*
   if (!density && pl->n_tri) return fail(VP_EINVAL, "vp_coefficients: NULL density");
   const bool dev = flags & VP_DEVICE_PTRS;
   VP_HIP(hipSetDevice(pl->ctx->device), "hipSetDevice");
-  vp_status s = ensure_workspace(pl, R);
+  vp_status s = ensure_workspace(pl, R, 1);
   if (s != VP_OK) return s;
   hipStream_t st = pl->ctx->stream;
   const size_t nF = (size_t)pl->n_tri * pl->n_p * R;
@@ -939,7 +977,8 @@ vp_status vp_graph_create(vp_plan* pl, int64_t R, const double* density, double*
   VP_HIP(hipSetDevice(pl->ctx->device), "hipSetDevice");
   vp_graph* g = new vp_graph;
   g->plan = pl;
-  const int64_t split = vp::far_split(pl);
+  const vp_far_config cfg = vp::far_config(pl, R, prec == VP_MIXED);
+  const int64_t split = cfg.n_split;
   const size_t nC = (size_t)pl->n_tri * pl->n_p * R, nQ = (size_t)pl->n_src_pad * R,
                nP = (size_t)split * pl->n_tgt * R;
   g->bytes = 8 * (nC + nQ + nP) + (prec == VP_MIXED ? 4 * nQ : 0);
@@ -970,7 +1009,7 @@ vp_status vp_graph_create(vp_plan* pl, int64_t R, const double* density, double*
   hipError_t le = hipSuccess;
   if ((e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal)) == hipSuccess) {
     if ((le = vp::launch_coefficients(pl, density, R, g->c, g->q, g->cap)) == hipSuccess &&
-        (le = vp::launch_far(pl, g->q, R, split, g->part, g->cap, nullptr, prec == VP_MIXED ? g->q32 : nullptr)) ==
+        (le = vp::launch_far(pl, g->q, R, cfg, g->part, g->cap, nullptr, prec == VP_MIXED ? g->q32 : nullptr)) ==
             hipSuccess)
       le = vp::launch_finish(pl, g->part, split, g->c, R, (flags & VP_FAR_ONLY) != 0, u_out, g->cap);
     e = hipStreamEndCapture(g->cap, &g->graph);
@@ -1007,6 +1046,118 @@ vp_status vp_graph_destroy(vp_graph* g) {
   for (void* p : {(void*)g->c, (void*)g->q, (void*)g->part, (void*)g->q32})
     if (p) (void)hipFree(p);
   delete g;
+  return VP_OK;
+}
+
+vp_status vp_plan_far_config(const vp_plan* pl, int64_t R, vp_precision prec, vp_far_config* out) {
+  if (!pl || !out) return fail(VP_EINVAL, "vp_plan_far_config: NULL argument");
+  if (R < 1) return fail(VP_EINVAL, "vp_plan_far_config: n_rhs must be >= 1");
+  if (prec != VP_FP64 && prec != VP_MIXED) return fail(VP_EINVAL, "vp_plan_far_config: unknown precision");
+  *out = vp::far_config(pl, R, prec == VP_MIXED);
+  return VP_OK;
+}
+
+vp_status vp_plan_set_far_config(vp_plan* pl, int64_t R, vp_precision prec, const vp_far_config* cfg) {
+  if (!pl || !cfg) return fail(VP_EINVAL, "vp_plan_set_far_config: NULL argument");
+  if (R < 1) return fail(VP_EINVAL, "vp_plan_set_far_config: n_rhs must be >= 1");
+  if (prec != VP_FP64 && prec != VP_MIXED) return fail(VP_EINVAL, "vp_plan_set_far_config: unknown precision");
+  if (!vp::far_config_valid(pl, *cfg))
+    return fail(VP_EINVAL,
+                "vp_plan_set_far_config: shape %d, mfma_tiles %d, n_split %lld out of range (n_split <= %lld)",
+                (int)cfg->shape, (int)cfg->mfma_tiles, (long long)cfg->n_split,
+                (long long)std::max<int64_t>(1, pl->n_src_pad / 64));
+  pl->far_tuned[{R, prec == VP_MIXED ? 1 : 0}] = *cfg;
+  return VP_OK;
+}
+
+// Candidates: the shapes that change a launch for this n_rhs (the one-RHS
+// FP64 kernel is the only one with wide blocks; the matrix-core tiles
+// matter from 16 right-hand sides on), each with the size rule's split and
+// 1/4, 1/2, 2 and 4 times it.  Candidates whose partial sums would exceed
+// 1 GiB are dropped unless they are the size rule's own choice.
+vp_status vp_plan_autotune(vp_plan* pl, int64_t R, vp_precision prec, int reps, vp_far_config* best_out,
+                           double* best_ms_out) {
+  if (!pl) return fail(VP_EINVAL, "vp_plan_autotune: plan is NULL");
+  if (R < 1) return fail(VP_EINVAL, "vp_plan_autotune: n_rhs must be >= 1");
+  if (prec != VP_FP64 && prec != VP_MIXED) return fail(VP_EINVAL, "vp_plan_autotune: unknown precision");
+  if (reps < 1 || reps > 1000) return fail(VP_EINVAL, "vp_plan_autotune: reps must be in [1, 1000]");
+  if (pl->live_requests > 0)
+    return fail(VP_EBUSY, "vp_plan_autotune: %d requests or graphs still use this plan", pl->live_requests);
+  const bool mixed = prec == VP_MIXED;
+  const vp_far_config def = vp::far_default(pl, R, mixed);
+  if (pl->n_tgt == 0 || pl->n_src == 0) {
+    pl->far_tuned[{R, mixed ? 1 : 0}] = def;
+    if (best_out) *best_out = def;
+    if (best_ms_out) *best_ms_out = 0.0;
+    return VP_OK;
+  }
+  VP_HIP(hipSetDevice(pl->ctx->device), "hipSetDevice");
+  const int64_t rem = R % 16;
+  std::vector<int> shapes;
+  if (R < 16 || rem != 0) {
+    if (!mixed && rem % 2 == 1) shapes.push_back(VP_FAR_WIDE);
+    shapes.push_back(VP_FAR_NARROW1);
+    shapes.push_back(VP_FAR_NARROW2);
+  } else {
+    shapes.push_back(def.shape);
+  }
+  std::vector<int> tiles = R >= 16 ? std::vector<int>{1, 2, 4} : std::vector<int>{def.mfma_tiles};
+  const int64_t max_split = std::max<int64_t>(1, pl->n_src_pad / 64);
+  const size_t per_split_bytes = 8 * (size_t)pl->n_tgt * R;
+  std::vector<vp_far_config> cand{def};
+  for (int sh : shapes)
+    for (int mt : tiles) {
+      const vp_far_config base = far_for_shape(pl, R, mixed, sh, mt);  // the size rule for this shape
+      for (int k = -2; k <= 2; ++k) {
+        vp_far_config c = base;
+        int64_t n = k < 0 ? base.n_split >> -k : base.n_split << k;
+        if (n >= 8) n = n / 8 * 8;
+        c.n_split = std::max<int64_t>(1, std::min<int64_t>(n, max_split));
+        if (c.n_split * per_split_bytes > (size_t(1) << 30)) continue;
+        bool dup = false;
+        for (const vp_far_config& o : cand)
+          dup = dup || (o.shape == c.shape && o.mfma_tiles == c.mfma_tiles && o.n_split == c.n_split);
+        if (!dup) cand.push_back(c);
+      }
+    }
+  int64_t need_split = 1;
+  for (const vp_far_config& c : cand) need_split = std::max(need_split, c.n_split);
+  vp_status s = ensure_workspace(pl, R, need_split);
+  if (s != VP_OK) return s;
+  hipStream_t st = pl->ctx->stream;
+  VP_HIP(hipMemsetAsync(pl->ws_c, 0, 8 * std::max<size_t>((size_t)pl->n_tri * pl->n_p * R, 1), st),
+         "vp_plan_autotune: clear");
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipError_t e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  double best_ms = 0.0;
+  vp_far_config best = def;
+  for (size_t i = 0; i < cand.size() && e == hipSuccess; ++i) {
+    const vp_far_config& c = cand[i];
+    auto one = [&]() {
+      hipError_t le = vp::launch_far(pl, pl->ws_q, R, c, pl->ws_part, st, nullptr, mixed ? pl->ws_q32 : nullptr);
+      if (le == hipSuccess) le = vp::launch_finish(pl, pl->ws_part, c.n_split, pl->ws_c, R, false, pl->ws_u, st);
+      return le;
+    };
+    if ((e = one()) != hipSuccess) break;  // warm-up
+    if ((e = hipEventRecord(ev[0], st)) != hipSuccess) break;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = one();
+    if (e != hipSuccess || (e = hipEventRecord(ev[1], st)) != hipSuccess) break;
+    if ((e = hipEventSynchronize(ev[1])) != hipSuccess) break;
+    float ms = 0.0f;
+    if ((e = hipEventElapsedTime(&ms, ev[0], ev[1])) != hipSuccess) break;
+    const double avg = (double)ms / reps;
+    if (i == 0 || avg < best_ms) {
+      best_ms = avg;
+      best = c;
+    }
+  }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  if (e != hipSuccess) return hip_fail(e, "vp_plan_autotune");
+  pl->far_tuned[{R, mixed ? 1 : 0}] = best;
+  if (best_out) *best_out = best;
+  if (best_ms_out) *best_ms_out = best_ms;
   return VP_OK;
 }
 

@@ -18,10 +18,6 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr double kInv4Pi = 0.07957747154594766788;
-#ifndef VP_FAR_TPT
-#define VP_FAR_TPT 2
-#endif
-constexpr int kFarTPT = VP_FAR_TPT;  // targets per thread in the far sum
 
 // Grid of a grid-stride launch: at most 2^20 blocks, so that a launch stays
 // far below 2^32 work-items.
@@ -79,24 +75,31 @@ __global__ void k_charges(const double* __restrict__ C, const double* __restrict
 // id b takes source chunk b % n_split and target block b / n_split, so with
 // n_split a multiple of 8 the blocks that share a chunk sit on one XCD and
 // its L2.  Each 256-source tile is summed on its own before it joins the
-// running total (two-level summation).  Sources are padded to a multiple of
-// 256 with zero charges.  With one right-hand side the logarithm comes from
-// the 4096-entry table (vp_log_wide_parts) in 1024-thread blocks, and its
-// exponent part is accumulated apart (sum Q e, times ln 2 at the end); with
-// several, the logarithm is a small share of the work per pair and the
-// 256-entry table leaves room for more blocks per CU.
-template <int RB>
+// running total (two-level summation).  Chunks are whole multiples of 64
+// sources and the sources are padded to a multiple of 256 with zero
+// charges.  With one right-hand side the exponent part of each logarithm is
+// accumulated apart (sum Q e, times ln 2 at the end).  The shapes
+// (VP_FAR_* of the C interface): WIDE runs 1024-thread blocks with the
+// 4096-entry table (vp_log_wide_parts), whose 64 KiB load a long source
+// chunk amortises; the NARROW shapes run 256-thread blocks with the
+// 256-entry table, for target sets too small to fill the device with wide
+// blocks.  With several right-hand sides the logarithm is a small share of
+// the work per pair and the blocks are always narrow.
+template <int S, int RB>
 struct FarShape {
-  static constexpr int kThreads = RB == 1 ? 1024 : 256;
-  static constexpr int kTab = RB == 1 ? kFarLogTab : kLogTab;
+  static constexpr bool kWide = S == VP_FAR_WIDE && RB == 1;
+  static constexpr int kThreads = kWide ? 1024 : 256;
+  static constexpr int kTPT = S == VP_FAR_NARROW1 ? 1 : 2;
+  static constexpr int kTab = kWide ? kFarLogTab : kLogTab;
 };
 
-template <int RB, int TPT>
-__global__ __launch_bounds__(FarShape<RB>::kThreads) void k_far(
+template <int RB, int S>
+__global__ __launch_bounds__((FarShape<S, RB>::kThreads)) void k_far(
     const double2* __restrict__ sxy, const double* __restrict__ Q, int64_t n_src_pad, int64_t R, int64_t r0,
     const double* __restrict__ xt, const double* __restrict__ yt, int64_t n_tgt, int64_t per_split,
     int64_t n_split, const double2* __restrict__ logtab, double* __restrict__ partial) {
-  constexpr int kB = FarShape<RB>::kThreads, kTab = FarShape<RB>::kTab;
+  using Sh = FarShape<S, RB>;
+  constexpr int kB = Sh::kThreads, kTab = Sh::kTab, TPT = Sh::kTPT;
   __shared__ double2 tab[kTab + 1];
   for (int i = threadIdx.x; i <= kTab; i += kB) tab[i] = logtab[i];
   __syncthreads();
@@ -143,7 +146,10 @@ __global__ __launch_bounds__(FarShape<RB>::kThreads) void k_far(
           const double r2 = fma(dy, dy, fma(dx, dx, kR2Bias));
           if (kSplitExp) {
             double e, rest;
-            vp_log_wide_parts(r2, tab, e, rest);
+            if (Sh::kWide)
+              vp_log_wide_parts(r2, tab, e, rest);
+            else
+              vp_log_parts(r2, tab, e, rest);
             tile_e[k] = fma(q[0], e, tile_e[k]);
             tile[k][0] = fma(q[0], rest, tile[k][0]);
           } else {
@@ -240,7 +246,9 @@ __global__ __launch_bounds__(kBlock) void k_far32(const double2* __restrict__ sx
 // Far sum for 16 NT right-hand sides at once on the matrix cores: the sum
 // U[t][r] = sum_j G[t][j] Q[j][r] with G[t][j] = log(r_tj^2) is a product
 // of a generated matrix with the charge matrix.  Each wavefront owns 16 MT
-// targets (MT tiles of 16) and walks its source chunk 4 sources at a time;
+// targets (MT = 1, 2 or 4 tiles of 16) and walks its source chunk 4 sources
+// at a time (chunks are multiples of 64 sources, so every lane of the
+// wavefront takes the same number of steps);
 // lane l generates G for target 16 m + (l & 15) and source l >> 4 of the
 // step, i.e. exactly the A operand of a 16x16x4 MFMA, and loads
 // Q[source l >> 4][16 n + (l & 15)], the B operand; every pair costs one
@@ -253,22 +261,20 @@ __global__ __launch_bounds__(kBlock) void k_far32(const double2* __restrict__ sx
 //                 FP32 MFMA over 256-source tiles, tiles summed in FP64
 typedef double vp_d4 __attribute__((ext_vector_type(4)));
 typedef float vp_f4 __attribute__((ext_vector_type(4)));
-constexpr int kMfmaMT = 4;                               // 16-target tiles per wavefront
-constexpr int kMfmaTargets = (kBlock / 64) * 16 * kMfmaMT;  // targets per block
 
-template <int NT>
+template <int NT, int MT>
 __global__ __launch_bounds__(kBlock, 2) void k_far_mfma64(
     const double2* __restrict__ sxy, const double* __restrict__ Q, int64_t n_src_pad, int64_t R, int64_t r0,
     const double* __restrict__ xt, const double* __restrict__ yt, int64_t n_tgt, int64_t per_split,
     int64_t n_split, const double2* __restrict__ logtab, double* __restrict__ partial) {
-  constexpr int MT = kMfmaMT;
+  constexpr int kTargets = (kBlock / 64) * 16 * MT;  // per block
   __shared__ double2 tab[kFarLogTab + 1];
   for (int i = threadIdx.x; i <= kFarLogTab; i += kBlock) tab[i] = logtab[i];
   __syncthreads();
   const int lane = threadIdx.x & 63, kk = lane >> 4, nn = lane & 15;
   const int64_t b = blockIdx.x;
   const int64_t chunk = b % n_split, tb = b / n_split;
-  const int64_t t0 = tb * kMfmaTargets + (threadIdx.x >> 6) * (16 * MT);
+  const int64_t t0 = tb * kTargets + (threadIdx.x >> 6) * (16 * MT);
   double x[MT], y[MT];
 #pragma unroll
   for (int m = 0; m < MT; ++m) {
@@ -313,16 +319,16 @@ __global__ __launch_bounds__(kBlock, 2) void k_far_mfma64(
     }
 }
 
-template <int NT>
+template <int NT, int MT>
 __global__ __launch_bounds__(kBlock, 2) void k_far_mfma32(
     const double2* __restrict__ sxy, const float* __restrict__ Q32, int64_t n_src_pad, int64_t R, int64_t r0,
     const double* __restrict__ xt, const double* __restrict__ yt, int64_t n_tgt, int64_t per_split,
     int64_t n_split, double* __restrict__ partial) {
-  constexpr int MT = kMfmaMT;
+  constexpr int kTargets = (kBlock / 64) * 16 * MT;  // per block
   const int lane = threadIdx.x & 63, kk = lane >> 4, nn = lane & 15;
   const int64_t b = blockIdx.x;
   const int64_t chunk = b % n_split, tb = b / n_split;
-  const int64_t t0 = tb * kMfmaTargets + (threadIdx.x >> 6) * (16 * MT);
+  const int64_t t0 = tb * kTargets + (threadIdx.x >> 6) * (16 * MT);
   double x[MT], y[MT];
 #pragma unroll
   for (int m = 0; m < MT; ++m) {
@@ -338,13 +344,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_far_mfma32(
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[m][n] = vp_d4{0.0, 0.0, 0.0, 0.0};
   for (int64_t j0 = s_begin; j0 < s_end; j0 += 256) {
+    const int64_t j1 = min(s_end, j0 + 256);
     vp_f4 tile[MT][NT];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
       for (int n = 0; n < NT; ++n) tile[m][n] = vp_f4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll 2
-    for (int64_t j = j0 + kk; j < j0 + 256; j += 4) {
+    for (int64_t j = j0 + kk; j < j1; j += 4) {
       const double2 s = sxy[j];
       float q[NT];
 #pragma unroll
@@ -405,21 +412,27 @@ __global__ void k_unpack(const double* __restrict__ src, int64_t rows, int64_t s
   }
 }
 
-// one thread per (target, rhs)
-template <int P>
-__global__ void k_finish(const double* __restrict__ partial, int64_t n_split, int64_t n_tgt, int64_t R,
-                         const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ pair_tri,
-                         const double* __restrict__ rows, const double* __restrict__ C, int far_only,
-                         double* __restrict__ U) {
+// G lanes per (target, rhs): the lanes share out the far partials and the
+// target's correction rows and are summed by a butterfly over the group.
+// G = 1 is one thread per (target, rhs); G = 4 or 16 serves target sets too
+// small to fill the device one thread each, where the serial walk over a
+// long near list would set the time.
+template <int P, int G>
+__global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ partial, int64_t n_split,
+                                                   int64_t n_tgt, int64_t R, const int64_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ pair_tri,
+                                                   const double* __restrict__ rows, const double* __restrict__ C,
+                                                   int far_only, double* __restrict__ U) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_tgt * R; g += stride) {
+  const int lane = (int)(threadIdx.x % G);
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / G);
+  for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; g < n_tgt * R; g += stride) {
     const int64_t t = g / R, r = g - t * R;
     double u = 0.0;
-    for (int64_t s = 0; s < n_split; ++s) u += partial[((size_t)s * n_tgt + t) * R + r];
+    for (int64_t s = lane; s < n_split; s += G) u += partial[((size_t)s * n_tgt + t) * R + r];
     if (!far_only) {
       double corr = 0.0;
-      for (int64_t p = row_ptr[t]; p < row_ptr[t + 1]; ++p) {
+      for (int64_t p = row_ptr[t] + lane; p < row_ptr[t + 1]; p += G) {
         const double* row = rows + (size_t)p * NP;
         const double* c = C + (size_t)pair_tri[p] * NP * R + r;
 #pragma unroll
@@ -427,7 +440,9 @@ __global__ void k_finish(const double* __restrict__ partial, int64_t n_split, in
       }
       u += corr;
     }
-    U[g] = u;
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) u += __shfl_xor(u, off, G);
+    if (lane == 0) U[g] = u;
   }
 }
 
@@ -479,76 +494,136 @@ hipError_t launch_coefficients(const vp_plan* pl, const double* F, int64_t R, do
   return hipGetLastError();
 }
 
-int64_t far_targets_per_block() { return FarShape<1>::kThreads * kFarTPT; }
+namespace {
 
-hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, int64_t n_split, double* partial,
+template <int RB, int S>
+hipError_t far_valu(const vp_plan* pl, const double* Q, int64_t R, int64_t r0, int64_t per, int64_t n_split,
+                    double* partial, hipStream_t st) {
+  using Sh = FarShape<S, RB>;
+  const int64_t NT = pl->n_tgt, tpb = (int64_t)Sh::kThreads * Sh::kTPT;
+  const int64_t nb = (NT + tpb - 1) / tpb * n_split;
+  if (nb * Sh::kThreads >= (1LL << 32)) return hipErrorInvalidConfiguration;
+  k_far<RB, S><<<dim3((unsigned)nb), Sh::kThreads, 0, st>>>(pl->sxy, Q, pl->n_src_pad, R, r0, pl->xt, pl->yt, NT,
+                                                            per, n_split, Sh::kWide ? pl->logtab_wide : pl->logtab,
+                                                            partial);
+  return hipSuccess;
+}
+
+template <int RB, int TPT>
+hipError_t far_valu32(const vp_plan* pl, const float* Q32, int64_t R, int64_t r0, int64_t per, int64_t n_split,
+                      double* partial, hipStream_t st) {
+  const int64_t NT = pl->n_tgt, tpb = (int64_t)kBlock * TPT;
+  const int64_t nb = (NT + tpb - 1) / tpb * n_split;
+  if (nb * kBlock >= (1LL << 32)) return hipErrorInvalidConfiguration;
+  k_far32<RB, TPT><<<dim3((unsigned)nb), kBlock, 0, st>>>(pl->sxy, Q32, pl->n_src_pad, R, r0, pl->xt, pl->yt, NT,
+                                                          per, n_split, partial);
+  return hipSuccess;
+}
+
+template <int NT, int MT>
+hipError_t far_mfma(const vp_plan* pl, const double* Q, const float* Q32, int64_t R, int64_t r0, int64_t per,
+                    int64_t n_split, double* partial, hipStream_t st) {
+  const int64_t N = pl->n_tgt, tpb = (int64_t)(kBlock / 64) * 16 * MT;
+  const int64_t nb = (N + tpb - 1) / tpb * n_split;
+  if (nb * kBlock >= (1LL << 32)) return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)nb);
+  if (Q32)
+    k_far_mfma32<NT, MT><<<grid, kBlock, 0, st>>>(pl->sxy, Q32, pl->n_src_pad, R, r0, pl->xt, pl->yt, N, per,
+                                                  n_split, partial);
+  else
+    k_far_mfma64<NT, MT><<<grid, kBlock, 0, st>>>(pl->sxy, Q, pl->n_src_pad, R, r0, pl->xt, pl->yt, N, per,
+                                                  n_split, pl->logtab_wide, partial);
+  return hipSuccess;
+}
+
+template <int NT>
+hipError_t far_mfma_mt(int mt, const vp_plan* pl, const double* Q, const float* Q32, int64_t R, int64_t r0,
+                       int64_t per, int64_t n_split, double* partial, hipStream_t st) {
+  switch (mt) {
+    case 1: return far_mfma<NT, 1>(pl, Q, Q32, R, r0, per, n_split, partial, st);
+    case 2: return far_mfma<NT, 2>(pl, Q, Q32, R, r0, per, n_split, partial, st);
+    default: return far_mfma<NT, 4>(pl, Q, Q32, R, r0, per, n_split, partial, st);
+  }
+}
+
+template <int RB>
+hipError_t far_valu_shape(int shape, const vp_plan* pl, const double* Q, const float* Q32, int64_t R, int64_t r0,
+                          int64_t per, int64_t n_split, double* partial, hipStream_t st) {
+  if (Q32)
+    return shape == VP_FAR_NARROW1 ? far_valu32<RB, 1>(pl, Q32, R, r0, per, n_split, partial, st)
+                                   : far_valu32<RB, 2>(pl, Q32, R, r0, per, n_split, partial, st);
+  switch (shape) {
+    case VP_FAR_NARROW1: return far_valu<RB, VP_FAR_NARROW1>(pl, Q, R, r0, per, n_split, partial, st);
+    case VP_FAR_NARROW2: return far_valu<RB, VP_FAR_NARROW2>(pl, Q, R, r0, per, n_split, partial, st);
+    default: return far_valu<RB, VP_FAR_WIDE>(pl, Q, R, r0, per, n_split, partial, st);
+  }
+}
+
+}  // namespace
+
+int64_t far_targets_per_block(const vp_far_config& cfg, int64_t R, bool mixed) {
+  if (R >= 16) return (int64_t)(kBlock / 64) * 16 * cfg.mfma_tiles;
+  const int64_t tpt = cfg.shape == VP_FAR_NARROW1 ? 1 : 2;
+  const int64_t threads = (!mixed && R == 1 && cfg.shape == VP_FAR_WIDE) ? 1024 : kBlock;
+  return threads * tpt;
+}
+
+hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, const vp_far_config& cfg, double* partial,
                       hipStream_t st, int64_t* n_launches, float* Q32) {
   const int64_t NT = pl->n_tgt, NS = pl->n_src_pad;
   if (NT == 0) return hipSuccess;
+  const int64_t n_split = cfg.n_split;
+  if (n_split < 1 || n_split > NS) return hipErrorInvalidValue;
+  // chunk length: a multiple of 64 sources
   int64_t per = (NS + n_split - 1) / n_split;
-  per = ((per + 255) / 256) * 256;
+  per = ((per + 63) / 64) * 64;
   if (Q32) k_to_f32_ln2<<<blocks_for(NS * R), kBlock, 0, st>>>(Q, NS * R, Q32);
+  hipError_t e = hipSuccess;
   int64_t r0 = 0;
   // blocks of 16, 32 or 64 right-hand sides on the matrix cores
-  while (R - r0 >= 16) {
+  while (R - r0 >= 16 && e == hipSuccess) {
     const int64_t left = R - r0;
     const int nt = left >= 64 ? 4 : left >= 32 ? 2 : 1;
-    const int64_t nb = (NT + kMfmaTargets - 1) / kMfmaTargets * n_split;
-    if (nb * kBlock >= (1LL << 32)) return hipErrorInvalidConfiguration;
-    const dim3 grid((unsigned)nb);
-#define VP_FAR_MFMA(NTV)                                                                                     \
-  if (Q32)                                                                                                   \
-    k_far_mfma32<NTV><<<grid, kBlock, 0, st>>>(pl->sxy, Q32, NS, R, r0, pl->xt, pl->yt, NT, per, n_split,  \
-                                               partial);                                                     \
-  else                                                                                                       \
-    k_far_mfma64<NTV><<<grid, kBlock, 0, st>>>(pl->sxy, Q, NS, R, r0, pl->xt, pl->yt, NT, per, n_split,    \
-                                               pl->logtab_wide, partial)
     switch (nt) {
-      case 4: VP_FAR_MFMA(4); break;
-      case 2: VP_FAR_MFMA(2); break;
-      default: VP_FAR_MFMA(1); break;
+      case 4: e = far_mfma_mt<4>(cfg.mfma_tiles, pl, Q, Q32, R, r0, per, n_split, partial, st); break;
+      case 2: e = far_mfma_mt<2>(cfg.mfma_tiles, pl, Q, Q32, R, r0, per, n_split, partial, st); break;
+      default: e = far_mfma_mt<1>(cfg.mfma_tiles, pl, Q, Q32, R, r0, per, n_split, partial, st); break;
     }
-#undef VP_FAR_MFMA
     if (n_launches) ++*n_launches;
     r0 += 16 * nt;
   }
-  // the remaining right-hand sides on the vector ALUs
-  while (r0 < R) {
+  // the remaining right-hand sides on the vector ALUs (RB of them share each logarithm)
+  while (r0 < R && e == hipSuccess) {
     const int64_t left = R - r0;
     const int rb = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
-    const int tpt = kFarTPT;  // RB right-hand sides share each logarithm
-    const int threads = (Q32 || rb > 1) ? kBlock : FarShape<1>::kThreads;
-    const int64_t n_tb = (NT + threads * tpt - 1) / (threads * tpt);
-    const int64_t nb = n_tb * n_split;
-    if (nb * threads >= (1LL << 32)) return hipErrorInvalidConfiguration;
-    const dim3 grid((unsigned)nb);
-#define VP_FAR(RBV, TPTV)                                                                                      \
-  if (Q32)                                                                                                     \
-    k_far32<RBV, TPTV><<<grid, kBlock, 0, st>>>(pl->sxy, Q32, NS, R, r0, pl->xt, pl->yt, NT, per, n_split,   \
-                                                partial);                                                      \
-  else                                                                                                         \
-    k_far<RBV, TPTV><<<grid, FarShape<RBV>::kThreads, 0, st>>>(pl->sxy, Q, NS, R, r0, pl->xt, pl->yt, NT, per, \
-                                                               n_split, RBV == 1 ? pl->logtab_wide : pl->logtab, \
-                                                               partial)
     switch (rb) {
-      case 8: VP_FAR(8, kFarTPT); break;
-      case 4: VP_FAR(4, kFarTPT); break;
-      case 2: VP_FAR(2, kFarTPT); break;
-      default: VP_FAR(1, kFarTPT); break;
+      case 8: e = far_valu_shape<8>(cfg.shape, pl, Q, Q32, R, r0, per, n_split, partial, st); break;
+      case 4: e = far_valu_shape<4>(cfg.shape, pl, Q, Q32, R, r0, per, n_split, partial, st); break;
+      case 2: e = far_valu_shape<2>(cfg.shape, pl, Q, Q32, R, r0, per, n_split, partial, st); break;
+      default: e = far_valu_shape<1>(cfg.shape, pl, Q, Q32, R, r0, per, n_split, partial, st); break;
     }
-#undef VP_FAR
     if (n_launches) ++*n_launches;
     r0 += rb;
   }
-  return hipGetLastError();
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 hipError_t launch_finish(const vp_plan* pl, const double* partial, int64_t n_split, const double* C, int64_t R,
                          bool far_only, double* U, hipStream_t st) {
   const int64_t NT = pl->n_tgt;
   if (NT == 0) return hipSuccess;
-  VP_DISPATCH_P(pl->p, (k_finish<P><<<blocks_for(NT * R), kBlock, 0, st>>>(
-                            partial, n_split, NT, R, pl->row_ptr, pl->pair_tri, pl->rows, C, far_only ? 1 : 0, U)));
+  // lanes per (target, rhs): enough work-items to fill the device
+  const int64_t n = NT * R;
+  const int G = n >= (1 << 17) ? 1 : n >= (1 << 15) ? 4 : 16;
+#define VP_FINISH(GV)                                                                                      \
+  VP_DISPATCH_P(pl->p, (k_finish<P, GV><<<blocks_for(n * GV), kBlock, 0, st>>>(                            \
+                            partial, n_split, NT, R, pl->row_ptr, pl->pair_tri, pl->rows, C, far_only ? 1 : 0, U)))
+  switch (G) {
+    case 16: VP_FINISH(16); break;
+    case 4: VP_FINISH(4); break;
+    default: VP_FINISH(1); break;
+  }
+#undef VP_FINISH
   return hipGetLastError();
 }
 

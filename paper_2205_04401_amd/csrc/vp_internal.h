@@ -5,7 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/vp.h"
@@ -364,6 +366,8 @@ struct vp_plan {
   // execute workspace
   int64_t ws_rhs = 0;
   int64_t ws_split = 0;
+  // far-sum launch shapes stored for (n_rhs, precision) by the tuner or the caller
+  std::map<std::pair<int64_t, int>, vp_far_config> far_tuned;
   double *ws_f = nullptr, *ws_c = nullptr, *ws_q = nullptr, *ws_part = nullptr, *ws_u = nullptr;
   float* ws_q32 = nullptr;
   size_t ws_bytes = 0;
@@ -393,12 +397,16 @@ hipError_t launch_coefficients(const vp_plan* pl, const double* F, int64_t R, do
                                hipStream_t st);
 // Q32 != nullptr selects the mixed-precision far sum (Q32: [n_src_pad][R]
 // scratch for the FP32 charges).
-hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, int64_t n_split, double* partial,
+hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, const vp_far_config& cfg, double* partial,
                       hipStream_t st, int64_t* n_launches = nullptr, float* Q32 = nullptr);
 hipError_t launch_finish(const vp_plan* pl, const double* partial, int64_t n_split, const double* C,
                          int64_t R, bool far_only, double* U, hipStream_t st);
-int64_t far_targets_per_block();
-int64_t far_split(const vp_plan* pl);  // source chunks of the far sum
+// targets per block of the far-sum launch that takes the first right-hand
+// side (the matrix-core kernel for n_rhs >= 16, else the vector one)
+int64_t far_targets_per_block(const vp_far_config& cfg, int64_t R, bool mixed);
+vp_far_config far_default(const vp_plan* pl, int64_t R, bool mixed);  // shape chosen from the sizes
+vp_far_config far_config(const vp_plan* pl, int64_t R, bool mixed);   // stored shape, else far_default
+bool far_config_valid(const vp_plan* pl, const vp_far_config& cfg);
 void set_last_error(const char* msg);
 // dst[i][c0 + r] = src[i][r] for i < rows, r < src_cols (dst has dst_cols)
 hipError_t launch_pack_columns(const double* src, int64_t rows, int64_t src_cols, double* dst, int64_t dst_cols,

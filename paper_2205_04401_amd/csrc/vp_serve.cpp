@@ -60,8 +60,8 @@ namespace {
 
 // Grow the slot's workspace for (plan, R).  Returns VP_ENOMEM when the
 // context budget cannot hold it right now.
-vp_status slot_reserve(vp_server* s, vp_server::Slot& sl, const vp_plan* pl, int64_t R) {
-  const int64_t split = vp::far_split(pl);
+vp_status slot_reserve(vp_server* s, vp_server::Slot& sl, const vp_plan* pl, int64_t R, bool mixed) {
+  const int64_t split = vp::far_config(pl, R, mixed).n_split;
   const size_t need[6] = {
       8 * (size_t)pl->n_tri * pl->n_p * R,  // F (packed)
       8 * (size_t)pl->n_tri * pl->n_p * R,  // C
@@ -115,11 +115,11 @@ vp_status issue(vp_server* s, int slot_id, const std::vector<int64_t>& batch) {
     if ((e = vp::launch_pack_columns(r.F, pl->n_tri * pl->n_p, r.R, F, R, c0, st)) != hipSuccess) break;
     c0 += r.R;
   }
-  const int64_t split = vp::far_split(pl);
+  const vp_far_config cfg = vp::far_config(pl, R, head.prec == VP_MIXED);
   if (e == hipSuccess) e = vp::launch_coefficients(pl, F, R, C, Q, st);
   if (e == hipSuccess)
-    e = vp::launch_far(pl, Q, R, split, part, st, nullptr, head.prec == VP_MIXED ? Q32 : nullptr);
-  if (e == hipSuccess) e = vp::launch_finish(pl, part, split, C, R, false, U, st);
+    e = vp::launch_far(pl, Q, R, cfg, part, st, nullptr, head.prec == VP_MIXED ? Q32 : nullptr);
+  if (e == hipSuccess) e = vp::launch_finish(pl, part, cfg.n_split, C, R, false, U, st);
   c0 = 0;
   for (int64_t id : batch) {
     if (e != hipSuccess) break;
@@ -181,7 +181,7 @@ vp_status progress(vp_server* s) {
         width += r.R;
       }
     }
-    vp_status st = slot_reserve(s, s->slots[free_slot], h.plan, width);
+    vp_status st = slot_reserve(s, s->slots[free_slot], h.plan, width, h.prec == VP_MIXED);
     if (st == VP_ENOMEM) {
       if (any_busy) break;  // memory frees up when a running batch retires
       // even alone on an idle device the request does not fit: fail it

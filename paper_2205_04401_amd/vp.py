@@ -31,7 +31,9 @@ EXPORTS = ["vp_ctx_create", "vp_ctx_destroy", "vp_last_error", "vp_ref_nodes", "
            "vp_execute", "vp_coefficients", "vp_plan_sources", "vp_plan_destroy", "vp_sync",
            "vp_ctx_profile", "vp_ctx_timings", "vp_server_create", "vp_server_destroy", "vp_submit",
            "vp_poll", "vp_wait", "vp_server_stats", "vp_interp_create", "vp_interp_destroy", "vp_interp_locate",
-           "vp_interp_eval", "vp_graph_create", "vp_graph_launch", "vp_graph_destroy"]
+           "vp_interp_eval", "vp_graph_create", "vp_graph_launch", "vp_graph_destroy", "vp_plan_far_config",
+           "vp_plan_set_far_config", "vp_plan_autotune"]
+FAR_SHAPES = {"wide": 0, "narrow1": 1, "narrow2": 2}
 STAGES = ["classify", "rows", "coef", "far", "finish"]
 
 
@@ -45,6 +47,13 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("c_n", ctypes.c_double), ("q_near", ctypes.c_int), ("n_l", ctypes.c_int),
                 ("tau", ctypes.c_double), ("depth_cap", ctypes.c_int), ("dyadic_cap", ctypes.c_int),
                 ("flags", ctypes.c_uint32), ("near_model", ctypes.c_int), ("ball_factor", ctypes.c_double)]
+
+
+class FarConfig(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int32), ("mfma_tiles", ctypes.c_int32), ("n_split", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class PlanStats(ctypes.Structure):
@@ -103,6 +112,10 @@ def load(path=LIB_PATH):
         "vp_graph_create": [P, I64, P, P, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(P)],
         "vp_graph_launch": [P],
         "vp_graph_destroy": [P],
+        "vp_plan_far_config": [P, I64, ctypes.c_int, ctypes.POINTER(FarConfig)],
+        "vp_plan_set_far_config": [P, I64, ctypes.c_int, ctypes.POINTER(FarConfig)],
+        "vp_plan_autotune": [P, I64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(FarConfig),
+                             ctypes.POINTER(ctypes.c_double)],
         "vp_interp_create": [P, P, ctypes.c_int, ctypes.POINTER(P)],
         "vp_interp_destroy": [P],
         "vp_interp_locate": [P, I64, P, P, P],
@@ -371,6 +384,26 @@ class Plan:
         s = PlanStats()
         _check(load().vp_plan_info(self.h, ctypes.byref(s)))
         return s.as_dict()
+
+    def far_config(self, n_rhs=1, mixed=False):
+        """Launch shape of the far sum used for n_rhs densities (dict)."""
+        c = FarConfig()
+        _check(load().vp_plan_far_config(self.h, n_rhs, VP_MIXED if mixed else VP_FP64, ctypes.byref(c)))
+        return c.as_dict()
+
+    def set_far_config(self, shape, mfma_tiles, n_split, n_rhs=1, mixed=False):
+        """Store a far-sum launch shape (shape: a FAR_SHAPES name or its value)."""
+        c = FarConfig(FAR_SHAPES.get(shape, shape), mfma_tiles, n_split)
+        _check(load().vp_plan_set_far_config(self.h, n_rhs, VP_MIXED if mixed else VP_FP64, ctypes.byref(c)))
+
+    def autotune(self, n_rhs=1, mixed=False, reps=3):
+        """Time the candidate far-sum shapes on the device and keep the
+        fastest; returns (config dict, mean ms of far sum + partial sums)."""
+        c = FarConfig()
+        ms = ctypes.c_double()
+        _check(load().vp_plan_autotune(self.h, n_rhs, VP_MIXED if mixed else VP_FP64, reps, ctypes.byref(c),
+                                       ctypes.byref(ms)))
+        return c.as_dict(), ms.value
 
     def pairs(self):
         """(row_ptr [n_tgt+1] int64, tri [n_pairs] int32, kind [n_pairs] uint8)."""

@@ -44,9 +44,16 @@ def header_struct(name):
     return fields
 
 
-@pytest.mark.parametrize("cname, pyclass", [("vp_plan_opts", vp.PlanOpts), ("vp_plan_stats", vp.PlanStats)])
+@pytest.mark.parametrize("cname, pyclass", [("vp_plan_opts", vp.PlanOpts), ("vp_plan_stats", vp.PlanStats),
+                                            ("vp_far_config", vp.FarConfig)])
 def test_struct_layouts_match_header(cname, pyclass):
     assert header_struct(cname) == list(pyclass._fields_)
+
+
+def test_far_shape_names_match_header():
+    src = open(HEADER).read()
+    for name, value in vp.FAR_SHAPES.items():
+        assert re.search(r"VP_FAR_" + name.upper() + r"\s*=\s*" + str(value) + r"\b", src), name
 
 
 def test_library_exports_every_declared_symbol():

@@ -277,6 +277,50 @@ def test_graph_replays_equal_eager(c1, vp_ctx):
         g.close()
 
 
+def test_c1_every_far_shape_and_autotune(c1, vp_ctx):
+    """Every launch shape of the far sum (wide / narrow blocks, 1, 2 or 4
+    matrix-core tiles, 1 to the most source chunks) gives the oracle's
+    potential for one density and the default shape's for 17 (16 on the
+    matrix cores + 1 on the vector ALUs), FP64 and mixed; the tuner returns
+    one of its candidates with a positive time, and out-of-range shapes are
+    refused."""
+    from paper_2205_04401_amd import vp
+    plan = vp_ctx.plan(c1["mesh"], 4, 8, 1e-13, c1["tg"])
+    most = max(1, (plan.info()["n_src"] + 255) // 256 * 256 // 64)
+    F1 = c1["F"]
+    F17 = np.ascontiguousarray(np.stack([(1.0 + 0.1 * r) * F1 - 0.01 * r for r in range(17)], -1))
+    ref17 = {m: plan.execute(F17, mixed=m) for m in (False, True)}
+    worst = {}
+    for mixed in (False, True):
+        tol = REL_MIXED if mixed else REL_E2E
+        for shape in ("wide", "narrow1", "narrow2"):
+            for split in (1, 8, 40, most):
+                plan.set_far_config(shape, 4, split, n_rhs=1, mixed=mixed)
+                assert plan.far_config(1, mixed) == dict(shape=vp.FAR_SHAPES[shape], mfma_tiles=4, n_split=split)
+                e = rel_linf(plan.execute(F1, mixed=mixed), c1["u"])
+                worst[(mixed, 1)] = max(worst.get((mixed, 1), 0.0), e)
+                assert e <= tol, (mixed, shape, split, e)
+            for tiles in (1, 2, 4):
+                for split in (8, most):
+                    plan.set_far_config(shape, tiles, split, n_rhs=17, mixed=mixed)
+                    u = plan.execute(F17, mixed=mixed)
+                    e = max(rel_linf(u[:, r], ref17[mixed][:, r]) for r in range(17))
+                    worst[(mixed, 17)] = max(worst.get((mixed, 17), 0.0), e)
+                    assert e <= (2e-6 if mixed else REL_FAR), (mixed, shape, tiles, split, e)
+    say("c1 far shapes: worst rel", worst)
+    for mixed in (False, True):
+        for R in (1, 17):
+            cfg, ms = plan.autotune(n_rhs=R, mixed=mixed, reps=2)
+            say("c1 autotune R", R, "mixed", mixed, cfg, f"{ms * 1e3:.1f} us")
+            assert ms > 0 and plan.far_config(R, mixed) == cfg and 1 <= cfg["n_split"] <= most
+    assert rel_linf(plan.execute(F1), c1["u"]) <= REL_E2E
+    for bad in (dict(shape=3, mfma_tiles=4, n_split=8), dict(shape=0, mfma_tiles=3, n_split=8),
+                dict(shape=0, mfma_tiles=4, n_split=0), dict(shape=0, mfma_tiles=4, n_split=most + 1)):
+        with pytest.raises(vp.VPError):
+            plan.set_far_config(bad["shape"], bad["mfma_tiles"], bad["n_split"])
+    plan.close()
+
+
 def test_c1_deterministic(c1, vp_ctx):
     plan2 = vp_ctx.plan(c1["mesh"], 4, 8, 1e-13, c1["tg"])
     a, b = c1["plan"].pairs(), plan2.pairs()
