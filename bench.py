@@ -107,10 +107,27 @@ def batched(ctx, mesh, tg_d, vq, tq, p, q, R, steps):
             "far_roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                              "frac": achieved / peak, "flops_per_pair_rhs": 2,
                              "kernel": "k_far_mfma32<4, 4>" if mixed else "k_far_mfma64<4, 4>"},
+            "corr_roofline": corr_mfma_roofline(info, tm, steps, R),
             "breakdown_ms": {k: v[0] / steps for k, v in tm.items() if v[1]},
         })
         print(json.dumps({"batched": out[-1]}), flush=True)
     return out
+
+
+def corr_mfma_roofline(info, tm, steps, R):
+    """Correction apply + partial-sum join on the FP64 matrix cores (blocks
+    of 16+ densities): useful flops 2 n_pairs n_p R against the FP64 MFMA
+    peak; `issued_frac` counts the padded 16-target x 4k blocks the MFMA
+    steps actually run, `row_fill` the share of those rows that are pairs."""
+    sec = tm["finish"][0] / 1e3 / steps
+    n_p, ent = info["n_p"], info["cluster_entries"]
+    useful = 2.0 * info["n_pairs"] * n_p * R
+    issued = 2.0 * ent * 16 * 4 * ((n_p + 3) // 4) * R
+    ach = useful / sec / 1e12
+    return {"bound": "mfma", "achieved": ach, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": ach / PEAK_FP64_MFMA_TFLOPS, "issued_frac": issued / sec / 1e12 / PEAK_FP64_MFMA_TFLOPS,
+            "row_fill": info["n_pairs"] / max(1, 16 * ent), "avg_ms": sec * 1e3,
+            "kernel": f"k_corr_mfma<{info['p']}, 4>"}
 
 
 # Algorithmic FP64 flops of one node evaluation in the correction rows:

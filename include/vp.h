@@ -121,6 +121,10 @@ typedef struct {
   double ms_classify;      /* device time of the near-list construction */
   double ms_rows;          /* device time of the correction-row precompute */
   int64_t far_split;       /* source chunks of the far sum (partial sums per target and RHS) */
+  int64_t cluster_entries; /* (16-target cluster, triangle) blocks of the matrix-core correction
+                              apply (used for blocks of 16+ densities; 0: not built, the apply then
+                              stays on the vector ALUs); n_pairs / (16 cluster_entries) is the
+                              share of those blocks' rows that are pairs, not padding */
 } vp_plan_stats;
 
 /* Context on HIP device `device`.  `hip_stream_or_null` is a hipStream_t the

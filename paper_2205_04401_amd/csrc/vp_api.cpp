@@ -588,7 +588,8 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
 #undef UP
   const int NP = pl->n_p;
   if ((e = plan_alloc(pl, (void**)&pl->vinv, sizeof(double) * NP * NP)) != hipSuccess ||
-      (e = plan_alloc(pl, (void**)&pl->efar, sizeof(double) * pl->n_f * NP)) != hipSuccess)
+      (e = plan_alloc(pl, (void**)&pl->efar, sizeof(double) * pl->n_f * NP)) != hipSuccess ||
+      (e = plan_alloc(pl, (void**)&pl->wfar, sizeof(double) * pl->n_f * NP)) != hipSuccess)
     return hip_fail(e, "vp_plan_create: hipMalloc");
   // Vandermonde inverse (device, FP64)
   {
@@ -682,6 +683,7 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
       if (!err.empty()) return fail(VP_ENOMEM, "vp_plan_create: %s", err.c_str());
       return hip_fail(e, "vp_plan_create: near-field list");
     }
+    if ((e = vp::build_clusters(pl, st)) != hipSuccess) return hip_fail(e, "vp_plan_create: target clusters");
   }
   tm_classify.stop(1);
   VP_HIP(hipEventRecord(ev1, st), "hipEventRecord");
@@ -748,6 +750,7 @@ vp_status vp_plan_info(const vp_plan* pl, vp_plan_stats* out) {
   out->ms_classify = pl->ms_classify;
   out->ms_rows = pl->ms_rows;
   out->far_split = vp::far_config(pl, 1, false).n_split;
+  out->cluster_entries = pl->n_entries;
   return VP_OK;
 }
 
@@ -790,16 +793,18 @@ vp_status vp_plan_sources(const vp_plan* pl, double* xy) {
 
 }  // extern "C"
 
-// Far-sum launch shape from the sizes.  Source chunks are set so that
-// the launch has about 16384 blocks on the FP64 vector ALUs (32768 for the
+// Far-sum launch shape from the sizes.  Source chunks are set so that the
+// launch has about 16384 blocks on the FP64 vector ALUs (32768 for the
 // shorter FP32 sum, 4096 on the matrix cores, whose blocks hold 16x more
-// work per source), a multiple of 8 (the
-// blocks of one chunk then share an XCD), with chunks of at least 64
-// sources and at most 2^23 blocks: many short blocks keep the last round of
-// blocks on the device short, which outweighs the extra partial sums.  Wide
-// blocks for one right-hand side once they can make 4096 such blocks, else
-// narrow ones (the unit-square case with 1920 targets fills only one wide
-// block per chunk).
+// work per source), with chunks of at least 64 sources and at most 2^23
+// blocks: many short blocks keep the last round of blocks on the device
+// short, which outweighs the extra partial sums.  The chunk count is a
+// multiple of 8: the blocks of one chunk then share an XCD and its L2 (with
+// 2 chunks instead of 8 the matrix-core sum of the 20k-triangle star at 64
+// right-hand sides runs 5% longer).
+// Wide blocks for one right-hand side once they can make 4096 such blocks,
+// else narrow ones (the unit-square case with 1920 targets fills only one
+// wide block per chunk).
 namespace {
 vp_far_config far_for_shape(const vp_plan* pl, int64_t R, bool mixed, int shape, int mfma_tiles) {
   vp_far_config c;

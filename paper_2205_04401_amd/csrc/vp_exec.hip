@@ -1,8 +1,9 @@
 // Per-solve kernels (FP64):
-//   k_coef      c = V^{-1} F per triangle (Sec. 2.2 interpolation matrix)
-//   k_charges   far charges Q_j = w_j |J(xi_j)| f_h(y_j) / (4 pi) (Sec. 3.6: every
-//               far-rule node is a point charge; the 1/2 of log r = log(r^2)/2
-//               is folded in)
+//   k_coef_charges  c = V^{-1} F per triangle (Sec. 2.2 interpolation matrix)
+//               and, in the same launch, the far charges
+//               Q_j = w_j |J(xi_j)| f_h(y_j) / (4 pi) (Sec. 3.6: every far-rule
+//               node is a point charge; the 1/2 of log r = log(r^2)/2 is
+//               folded in)
 //   k_far       U_far(x) = sum_j Q_j log|x - y_j|^2 over all sources: a
 //               direct sum, targets across threads, sources read in
 //               wavefront-uniform tiles (a pair at distance 0 gets a finite
@@ -26,46 +27,52 @@ inline unsigned blocks_for(int64_t n, int b = kBlock) {
   return (unsigned)(nb < (1 << 20) ? (nb > 0 ? nb : 1) : (1 << 20));
 }
 
-// one thread per (triangle, rhs); F and C are [T][NP][R]
+// Coefficients and far charges in one launch, as two independent parts:
+// blocks [0, nb_c) take one (triangle, rhs) each: c = V^{-1} F (F and C are
+// [T][NP][R]); the remaining blocks take one (source, rhs) each: the charge
+// Q_j = w_j |J| f_h(y_j) / (4 pi) with f_h(y_j) = sum_i W_ji f_i read from the
+// node values (W = E V^{-1}), zero in the source padding.  Q may be null.
 template <int P>
-__global__ void k_coef(const double* __restrict__ F, const double* __restrict__ vinv, int64_t n_tri, int64_t R,
-                       double* __restrict__ C) {
+__global__ void k_coef_charges(const double* __restrict__ F, const double* __restrict__ vinv,
+                               const double* __restrict__ wfar, const double* __restrict__ swj, int nf,
+                               int64_t n_tri, int64_t n_src_pad, int64_t R, unsigned nb_c, double* __restrict__ C,
+                               double* __restrict__ Q) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_tri * R; g += stride) {
-    const int64_t t = g / R, r = g - t * R;
-    const double* f = F + (size_t)t * NP * R + r;
-    double v[NP];
+  if (blockIdx.x < nb_c) {
+    const int64_t stride = (int64_t)nb_c * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_tri * R; g += stride) {
+      const int64_t t = g / R, r = g - t * R;
+      const double* f = F + (size_t)t * NP * R + r;
+      double v[NP];
 #pragma unroll
-    for (int i = 0; i < NP; ++i) v[i] = f[(size_t)i * R];
-    double* c = C + (size_t)t * NP * R + r;
+      for (int i = 0; i < NP; ++i) v[i] = f[(size_t)i * R];
+      double* c = C + (size_t)t * NP * R + r;
 #pragma unroll
-    for (int k = 0; k < NP; ++k) {
+      for (int k = 0; k < NP; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) s = fma(vinv[k * NP + i], v[i], s);
+        c[(size_t)k * R] = s;
+      }
+    }
+    return;
+  }
+  const int64_t n_src = n_tri * nf;
+  const int64_t stride = (int64_t)(gridDim.x - nb_c) * blockDim.x;
+  for (int64_t g = (int64_t)(blockIdx.x - nb_c) * blockDim.x + threadIdx.x; g < n_src_pad * R; g += stride) {
+    const int64_t src = g / R, r = g - src * R;
+    double q = 0.0;
+    if (src < n_src) {
+      const int64_t t = src / nf;
+      const int j = (int)(src - t * nf);
+      const double* f = F + (size_t)t * NP * R + r;
+      const double* W = wfar + (size_t)j * NP;
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < NP; ++i) s = fma(vinv[k * NP + i], v[i], s);
-      c[(size_t)k * R] = s;
+      for (int i = 0; i < NP; ++i) s = fma(W[i], f[(size_t)i * R], s);
+      q = s * swj[src] * kInv4Pi;
     }
-  }
-}
-
-// one thread per (source, rhs); Q is [n_src][R]
-template <int P>
-__global__ void k_charges(const double* __restrict__ C, const double* __restrict__ efar,
-                          const double* __restrict__ swj, int nf, int64_t n_tri, int64_t R, double* __restrict__ Q) {
-  constexpr int NP = (P + 1) * (P + 2) / 2;
-  const int64_t n_src = n_tri * nf;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_src * R; g += stride) {
-    const int64_t src = g / R, r = g - src * R;
-    const int64_t t = src / nf;
-    const int j = (int)(src - t * nf);
-    const double* c = C + (size_t)t * NP * R + r;
-    const double* E = efar + (size_t)j * NP;
-    double s = 0.0;
-#pragma unroll
-    for (int k = 0; k < NP; ++k) s = fma(E[k], c[(size_t)k * R], s);
-    Q[g] = s * swj[src] * kInv4Pi;
+    Q[g] = q;
   }
 }
 
@@ -383,10 +390,6 @@ __global__ __launch_bounds__(kBlock, 2) void k_far_mfma32(
     }
 }
 
-__global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = v;
-}
 
 __global__ void k_to_f32_ln2(const double* __restrict__ Q, int64_t n, float* __restrict__ Q32) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -419,16 +422,19 @@ __global__ void k_unpack(const double* __restrict__ src, int64_t rows, int64_t s
 // long near list would set the time.
 template <int P, int G>
 __global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ partial, int64_t n_split,
-                                                   int64_t n_tgt, int64_t R, const int64_t* __restrict__ row_ptr,
+                                                   int64_t n_tgt, int64_t R, int64_t r0,
+                                                   const int64_t* __restrict__ row_ptr,
                                                    const int32_t* __restrict__ pair_tri,
                                                    const double* __restrict__ rows, const double* __restrict__ C,
                                                    int far_only, double* __restrict__ U) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
   const int lane = (int)(threadIdx.x % G);
   const int64_t stride = (int64_t)gridDim.x * (blockDim.x / G);
-  for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; g < n_tgt * R; g += stride) {
-    const int64_t t = g / R, r = g - t * R;
+  const int64_t Rr = R - r0;  // columns r0 .. R-1
+  for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; g < n_tgt * Rr; g += stride) {
+    const int64_t t = g / Rr, r = r0 + (g - t * Rr);
     double u = 0.0;
+#pragma unroll 8
     for (int64_t s = lane; s < n_split; s += G) u += partial[((size_t)s * n_tgt + t) * R + r];
     if (!far_only) {
       double corr = 0.0;
@@ -442,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ pa
     }
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) u += __shfl_xor(u, off, G);
-    if (lane == 0) U[g] = u;
+    if (lane == 0) U[t * R + r] = u;
   }
 }
 
@@ -479,18 +485,12 @@ hipError_t launch_unpack_columns(const double* src, int64_t rows, int64_t src_co
 
 hipError_t launch_coefficients(const vp_plan* pl, const double* F, int64_t R, double* C, double* Q, hipStream_t st) {
   const int64_t T = pl->n_tri;
-  // the padding sources past n_src carry zero charge for this R (a fill
-  // kernel, not a memset, so that the sequence can be captured in a graph)
-  if (Q && pl->n_src_pad > pl->n_src) {
-    const int64_t nz = (pl->n_src_pad - pl->n_src) * R;
-    k_fill<<<blocks_for(nz), kBlock, 0, st>>>(Q + pl->n_src * R, nz, 0.0);
-  }
-  if (T == 0) return hipSuccess;
-  VP_DISPATCH_P(pl->p, (k_coef<P><<<blocks_for(T * R), kBlock, 0, st>>>(F, pl->vinv, T, R, C)));
-  if (Q) {
-    VP_DISPATCH_P(pl->p, (k_charges<P><<<blocks_for(T * pl->n_f * R), kBlock, 0, st>>>(
-                              C, pl->efar, pl->swj, pl->n_f, T, R, Q)));
-  }
+  if (T == 0 && !Q) return hipSuccess;
+  const unsigned nb_c = T > 0 ? blocks_for(T * R) : 0;
+  const unsigned nb_q = Q ? blocks_for(pl->n_src_pad * R) : 0;
+  if (nb_c + nb_q == 0) return hipSuccess;
+  VP_DISPATCH_P(pl->p, (k_coef_charges<P><<<nb_c + nb_q, kBlock, 0, st>>>(F, pl->vinv, pl->wfar, pl->swj, pl->n_f, T,
+                                                                          pl->n_src_pad, R, nb_c, C, Q)));
   return hipGetLastError();
 }
 
@@ -608,16 +608,33 @@ hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, const vp_fa
   return e != hipSuccess ? e : hipGetLastError();
 }
 
+// Below this many clusters (8192 targets) the vector-ALU apply with lane
+// groups is faster (unit square, 1920 targets, 32 right-hand sides: 44 us
+// against 75 us).
+constexpr int64_t kCorrMfmaMinClusters = 512;
+
 hipError_t launch_finish(const vp_plan* pl, const double* partial, int64_t n_split, const double* C, int64_t R,
                          bool far_only, double* U, hipStream_t st) {
   const int64_t NT = pl->n_tgt;
   if (NT == 0) return hipSuccess;
-  // lanes per (target, rhs): enough work-items to fill the device
-  const int64_t n = NT * R;
+  // blocks of 64, 32 or 16 right-hand sides on the matrix cores, once there
+  // are enough 16-target clusters (one wavefront each) to fill the device
+  int64_t r0 = 0;
+  while (pl->n_cl >= kCorrMfmaMinClusters && R - r0 >= 16) {
+    const int nt = R - r0 >= 64 ? 4 : R - r0 >= 32 ? 2 : 1;
+    const hipError_t e = launch_corr_mfma(pl, partial, n_split, C, R, r0, nt, far_only, U, st);
+    if (e != hipSuccess) return e;
+    r0 += 16 * nt;
+  }
+  if (r0 == R) return hipSuccess;
+  // the rest on the vector ALUs; lanes per (target, rhs): enough
+  // work-items to fill the device
+  const int64_t n = NT * (R - r0);
   const int G = n >= (1 << 17) ? 1 : n >= (1 << 15) ? 4 : 16;
 #define VP_FINISH(GV)                                                                                      \
   VP_DISPATCH_P(pl->p, (k_finish<P, GV><<<blocks_for(n * GV), kBlock, 0, st>>>(                            \
-                            partial, n_split, NT, R, pl->row_ptr, pl->pair_tri, pl->rows, C, far_only ? 1 : 0, U)))
+                            partial, n_split, NT, R, r0, pl->row_ptr, pl->pair_tri, pl->rows, C, far_only ? 1 : 0, \
+                            U)))
   switch (G) {
     case 16: VP_FINISH(16); break;
     case 4: VP_FINISH(4); break;

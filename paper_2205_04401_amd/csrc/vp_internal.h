@@ -332,6 +332,7 @@ struct vp_plan {
   // rule tables (device)
   double* vinv = nullptr;   // [n_p][n_p]
   double* efar = nullptr;   // [n_f][n_p] Koornwinder values at far nodes
+  double* wfar = nullptr;   // [n_f][n_p] efar V^{-1}: interpolant at far nodes from node values
   double* far_x = nullptr;  // [n_f]
   double* far_y = nullptr;
   double* far_w = nullptr;
@@ -363,6 +364,12 @@ struct vp_plan {
   int32_t* pair_tgt = nullptr;  // [n_pairs]
   uint8_t* pair_kind = nullptr;  // [n_pairs]
   double* rows = nullptr;  // [n_pairs][n_p]
+  // clusters of 16 consecutive targets for the matrix-core correction apply
+  // (0 clusters: not built, the apply stays on the vector ALUs)
+  int64_t n_cl = 0, n_entries = 0;
+  int64_t* cl_ptr = nullptr;    // [n_cl+1] entries of each cluster
+  int32_t* ent_tri = nullptr;   // [n_entries] triangle of the entry (ascending within a cluster)
+  int32_t* ent_pair = nullptr;  // [n_entries][16] pair index per cluster target, -1 if absent
   // execute workspace
   int64_t ws_rhs = 0;
   int64_t ws_split = 0;
@@ -401,6 +408,10 @@ hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, const vp_fa
                       hipStream_t st, int64_t* n_launches = nullptr, float* Q32 = nullptr);
 hipError_t launch_finish(const vp_plan* pl, const double* partial, int64_t n_split, const double* C,
                          int64_t R, bool far_only, double* U, hipStream_t st);
+hipError_t build_clusters(vp_plan* pl, hipStream_t st);  // after the pair list; allocates plan memory
+// U columns [r0, r0 + 16 nt) on the matrix cores (nt = 1, 2 or 4)
+hipError_t launch_corr_mfma(const vp_plan* pl, const double* partial, int64_t n_split, const double* C, int64_t R,
+                            int64_t r0, int nt, bool far_only, double* U, hipStream_t st);
 // targets per block of the far-sum launch that takes the first right-hand
 // side (the matrix-core kernel for n_rhs >= 16, else the vector one)
 int64_t far_targets_per_block(const vp_far_config& cfg, int64_t R, bool mixed);

@@ -608,10 +608,26 @@ hipError_t launch_vinv(int p, const double* nx, const double* ny, double* aug, d
   return hipGetLastError();
 }
 
+// W = E V^{-1} [nf][n_p]: the far-node values of the interpolant straight
+// from the node values, f_h(xi_j) = sum_i W_ji f_i (E_jk = K_k(xi_j))
+template <int P>
+__global__ void k_fold(const double* __restrict__ efar, const double* __restrict__ vinv, int nf,
+                       double* __restrict__ wfar) {
+  constexpr int NP = (P + 1) * (P + 2) / 2;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nf * NP) return;
+  const int j = g / NP, i = g - j * NP;
+  double s = 0.0;
+  for (int k = 0; k < NP; ++k) s = fma(efar[j * NP + k], vinv[k * NP + i], s);
+  wfar[g] = s;
+}
+
 template <int P>
 static hipError_t basis_tables_p(vp_plan* pl, double* scratch, int* d_bad, hipStream_t st) {
+  constexpr int NP = (P + 1) * (P + 2) / 2;
   k_vandermonde_inverse<P><<<1, 256, 0, st>>>(scratch, scratch + pl->n_p, scratch + 2 * pl->n_p, pl->vinv, d_bad);
   k_basis_at<P><<<blocks_for(pl->n_f), kBlock, 0, st>>>(pl->far_x, pl->far_y, pl->n_f, pl->efar);
+  k_fold<P><<<blocks_for((int64_t)pl->n_f * NP), kBlock, 0, st>>>(pl->efar, pl->vinv, pl->n_f, pl->wfar);
   return hipGetLastError();
 }
 

@@ -63,7 +63,8 @@ class PlanStats(ctypes.Structure):
                 ("depth_first_pairs", ctypes.c_int64),
                 ("bytes_resident", ctypes.c_int64), ("p", ctypes.c_int32), ("q", ctypes.c_int32),
                 ("n_p", ctypes.c_int32), ("n_f", ctypes.c_int32), ("eps", ctypes.c_double),
-                ("ms_classify", ctypes.c_double), ("ms_rows", ctypes.c_double), ("far_split", ctypes.c_int64)]
+                ("ms_classify", ctypes.c_double), ("ms_rows", ctypes.c_double), ("far_split", ctypes.c_int64),
+                ("cluster_entries", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

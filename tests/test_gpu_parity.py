@@ -321,6 +321,53 @@ def test_c1_every_far_shape_and_autotune(c1, vp_ctx):
     plan.close()
 
 
+def test_matrix_core_corrections_shuffled_ragged_targets(vp_ctx):
+    """The correction apply on the matrix cores (blocks of 16+ densities,
+    16-target clusters) on a 1000-triangle star whose 14 790 staggered
+    targets are shuffled (clusters of unrelated targets: long, mostly empty
+    union lists) plus 7 more targets (a ragged last cluster).  33 densities
+    (32 on the matrix cores, 1 on the vector ALUs) match each density's own
+    one-RHS evaluation, far-only included; the shuffled plan gives the
+    unshuffled plan's potential, and the oracle's at sampled targets."""
+    p, q, eps = 4, 6, 1e-12
+    vq, tq = W.star_mesh(n_tri=1000, n_boundary=200, seed=61)
+    vt, tt = W.star_mesh(n_tri=1000, n_boundary=200, seed=62, staggered=True)
+    nodes = rules.interp_nodes(p)
+    tg0 = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    rng = np.random.default_rng(33)
+    perm = rng.permutation(len(tg0))
+    tg = np.concatenate([tg0[perm], rng.uniform(-1.0, 1.0, (7, 2))])
+    mesh = vp_ctx.mesh(vq, tq)
+    plan = vp_ctx.plan(mesh, p, q, eps, tg)
+    info = plan.info()
+    say("shuffled star:", len(tg), "targets,", info["n_pairs"], "pairs,", info["cluster_entries"],
+        "cluster entries, row fill", info["n_pairs"] / (16 * info["cluster_entries"]))
+    assert info["cluster_entries"] > 0 and len(tg) >= 512 * 16
+    R = 33
+    F1 = W.sample_density(W.gaussian_sum(64, vq, tq), vq, tq, nodes)
+    FR = np.ascontiguousarray(np.stack([(1.0 + 0.2 * r) * F1 + np.cos(r + F1) for r in range(R)], -1))
+    for far_only in (False, True):
+        uR = plan.execute(FR, far_only=far_only)
+        worst = 0.0
+        for r in (0, 7, 15, 16, 31, 32):
+            u1 = plan.execute(np.ascontiguousarray(FR[:, :, r]), far_only=far_only)
+            worst = max(worst, rel_linf(uR[:, r], u1))
+        say("33 RHS, far_only", far_only, "worst rel vs one-RHS", worst)
+        assert worst <= REL_FAR
+    plan0 = vp_ctx.plan(mesh, p, q, eps, tg0)
+    u0 = plan0.execute(FR)
+    uR = plan.execute(FR)
+    assert rel_linf(uR[: len(perm)], u0[perm]) <= REL_FAR
+    sample = np.sort(rng.choice(len(tg), 12, replace=False))
+    ref = potential.Oracle(vq, tq, p, q, eps).evaluate(FR[:, :, 20], tg[sample])
+    e = rel_linf(uR[sample, 20], ref)
+    say("shuffled star sampled rel vs oracle", e)
+    assert e <= REL_E2E
+    plan0.close()
+    plan.close()
+    mesh.close()
+
+
 def test_c1_deterministic(c1, vp_ctx):
     plan2 = vp_ctx.plan(c1["mesh"], 4, 8, 1e-13, c1["tg"])
     a, b = c1["plan"].pairs(), plan2.pairs()
@@ -798,13 +845,19 @@ def test_serving_results_equal_alone_and_in_mix(vp_ctx):
     st = server.stats()
     say("serving stats", st)
     assert st["requests_done"] == 40 and st["batches"] < 40  # some requests were packed together
-    worst = 0.0
+    # FP64: the same up to summation order.  Mixed: a request packed with
+    # others into 16+ columns has its far sum on the FP32 matrix cores
+    # instead of the FP32 vector ALUs, a different FP32 rounding; both are
+    # within the mixed tolerance of the FP64 result, so they agree to twice it.
+    worst = {False: 0.0, True: 0.0}
     for k, F, mixed, out, _ in reqs:
         alone = plans[k][1].execute(F, mixed=mixed)
         got = out.cpu().numpy()
-        worst = max(worst, rel_linf(got, alone))
-    say("serving: worst rel difference alone vs in the mix", worst)
-    assert worst <= 1e-14
+        worst[mixed] = max(worst[mixed], rel_linf(got, alone))
+        if mixed:  # and within the mixed tolerance of the FP64 evaluation
+            assert rel_linf(got, plans[k][1].execute(F)) <= REL_MIXED
+    say("serving: worst rel difference alone vs in the mix (fp64, mixed)", worst[False], worst[True])
+    assert worst[False] <= 1e-14 and worst[True] <= 2 * REL_MIXED
     server.close()
     for mesh, plan, *_ in plans:
         plan.close()
