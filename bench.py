@@ -130,6 +130,51 @@ def corr_mfma_roofline(info, tm, steps, R):
             "kernel": f"k_corr_mfma<{info['p']}, 4>"}
 
 
+def small_case(ctx, n=300):
+    """The unit-square case (8x8 cells, 128 triangles, p = 4, q = 8, 1920
+    targets, one density): time per evaluation issued back to back, eager
+    (vp_execute, asynchronous) and as a captured HIP graph replay
+    (vp_graph_*), with the size rule's far-sum shape and after the tuner
+    (vp_plan_autotune)."""
+    import torch
+    from paper_2205_04401_amd import vp
+    from paper_2205_04401_amd import workloads as W
+    p, q = 4, 8
+    vq, tq = W.unit_square(8, "/")
+    vt, tt = W.unit_square(8, "\\")
+    nodes = vp.ref_nodes(p)
+    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    F = torch.from_numpy(W.sample_density(W.gaussian_bump, vq, tq, nodes)[:, :, None].copy()).cuda()
+    mesh = ctx.mesh(vq, tq)
+    plan = ctx.plan(mesh, p, q, 1e-13, tg)
+    U = torch.empty((len(tg), 1), dtype=torch.float64, device="cuda")
+
+    def per_eval_us(fn):
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n * 1e6
+
+    out = {"workload": "unit square 8x8 cells (128 triangles), p=4, q=8, 1920 targets, 1 density, FP64"}
+    for label in ("size_rule", "tuned"):
+        if label == "tuned":
+            cfg, ms = plan.autotune(n_rhs=1, reps=5)
+            out["tuned_config"] = cfg
+        g = vp.Graph(plan, F, U)
+        out[label] = {"far_config": plan.far_config(1),
+                      "eager_us": per_eval_us(lambda: plan.execute(F, out=U, asynchronous=True)),
+                      "graph_us": per_eval_us(g.launch)}
+        g.close()
+    plan.close()
+    mesh.close()
+    print(json.dumps({"small_case": out}), flush=True)
+    return out
+
+
 # Algorithmic FP64 flops of one node evaluation in the correction rows:
 # geometry and weight 10, the log counted as 1, then per basis function
 # 3 for the Koornwinder recurrence and 2 to accumulate (n_p functions).
@@ -341,6 +386,8 @@ def run(args):
         res = ablation.run(ctx)
         print(ablation.table(res), file=sys.stderr, flush=True)
         result["ablation"] = {k: v for k, v in res.items() if k not in ("problem", "sample_same", "sample_stag")}
+    if not args.no_small:
+        result["small_case"] = small_case(ctx)
     if args.batched_rhs:
         result["batched"] = batched(ctx, mesh, tg_d, vq, tq, p, q, args.batched_rhs, args.batched_steps)
     if not args.no_serving:
@@ -363,6 +410,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=600)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-small", action="store_true", help="skip the unit-square latency section")
     ap.add_argument("--serving-requests", type=int, default=160)
     ap.add_argument("--batched-rhs", type=int, default=64, help="densities of the batched section (0: skip)")
     ap.add_argument("--batched-steps", type=int, default=2)

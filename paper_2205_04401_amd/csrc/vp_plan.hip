@@ -611,7 +611,7 @@ hipError_t launch_vinv(int p, const double* nx, const double* ny, double* aug, d
 // W = E V^{-1} [nf][n_p]: the far-node values of the interpolant straight
 // from the node values, f_h(xi_j) = sum_i W_ji f_i (E_jk = K_k(xi_j))
 template <int P>
-__global__ void k_fold(const double* __restrict__ efar, const double* __restrict__ vinv, int nf,
+static __global__ void k_fold(const double* __restrict__ efar, const double* __restrict__ vinv, int nf,
                        double* __restrict__ wfar) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
