@@ -99,6 +99,14 @@ typedef struct {
                        within ball_factor * R of the centroid c, R = the largest vertex distance
                        from c */
   double ball_factor; /* kappa of VP_NEAR_BALL (default 2.0; 0 < kappa <= 64) */
+  int fmm_terms;      /* 0 (default): the far sum is the direct sum over all sources.  8..63: the
+                         far sum by a fast multipole method with this many expansion terms (the
+                         FMM coupling of Sec. 3.6): uniform quadtree over sources and targets,
+                         adjacent leaf boxes summed directly with the same kernel, the rest by
+                         complex multipole/local expansions, error <= 1.2 (sum |Q|) 0.547^p
+                         (p = 56: ~2e-15 sum |Q|); both precisions then run it in FP64 */
+  int fmm_leaf;       /* FMM: average far sources per leaf box of the full grid (default 128,
+                         8..4096); sets the number of levels */
 } vp_plan_opts;
 
 enum { VP_NEAR_ELLIPSES = 0, VP_NEAR_BALL = 1 };
@@ -125,6 +133,8 @@ typedef struct {
                               apply (used for blocks of 16+ densities; 0: not built, the apply then
                               stays on the vector ALUs); n_pairs / (16 cluster_entries) is the
                               share of those blocks' rows that are pairs, not padding */
+  int32_t fmm_terms;       /* expansion terms of the FMM far sum (0: direct sum) */
+  int32_t fmm_levels;      /* quadtree levels below the root (leaf level) */
 } vp_plan_stats;
 
 /* Context on HIP device `device`.  `hip_stream_or_null` is a hipStream_t the

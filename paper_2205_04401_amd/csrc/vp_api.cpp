@@ -48,6 +48,8 @@ vp_plan_opts default_opts() {
   o.flags = 0;
   o.near_model = VP_NEAR_ELLIPSES;
   o.ball_factor = 2.0;
+  o.fmm_terms = 0;
+  o.fmm_leaf = 128;
   return o;
 }
 
@@ -536,7 +538,9 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
   if (!(o.c_n > 0.0) || o.q_near < 2 || o.q_near > vp::kMaxQ || o.n_l < 2 || o.n_l > 64 || !(o.tau >= 0.0) ||
       o.depth_cap < 1 || o.depth_cap > 60 || o.dyadic_cap < 1 || o.dyadic_cap > 100 ||
       (o.near_model != VP_NEAR_ELLIPSES && o.near_model != VP_NEAR_BALL) ||
-      (o.near_model == VP_NEAR_BALL && !(o.ball_factor > 0.0 && o.ball_factor <= 64.0)))
+      (o.near_model == VP_NEAR_BALL && !(o.ball_factor > 0.0 && o.ball_factor <= 64.0)) ||
+      (o.fmm_terms != 0 && (o.fmm_terms < 8 || o.fmm_terms > 63)) ||
+      (o.fmm_terms != 0 && (o.fmm_leaf < 8 || o.fmm_leaf > 4096)))
     return fail(VP_EINVAL, "vp_plan_create: invalid options");
   VP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t st = ctx->stream;
@@ -684,6 +688,10 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
       return hip_fail(e, "vp_plan_create: near-field list");
     }
     if ((e = vp::build_clusters(pl, st)) != hipSuccess) return hip_fail(e, "vp_plan_create: target clusters");
+    if (o.fmm_terms > 0 && pl->n_src > 0 && pl->n_tgt > 0) {
+      pl->fmm_terms = o.fmm_terms;
+      if ((e = vp::build_fmm(pl, o.fmm_leaf, st)) != hipSuccess) return hip_fail(e, "vp_plan_create: FMM tree");
+    }
   }
   tm_classify.stop(1);
   VP_HIP(hipEventRecord(ev1, st), "hipEventRecord");
@@ -751,6 +759,8 @@ vp_status vp_plan_info(const vp_plan* pl, vp_plan_stats* out) {
   out->ms_rows = pl->ms_rows;
   out->far_split = vp::far_config(pl, 1, false).n_split;
   out->cluster_entries = pl->n_entries;
+  out->fmm_terms = pl->fmm_terms;
+  out->fmm_levels = pl->fmm_levels;
   return VP_OK;
 }
 
@@ -821,7 +831,12 @@ vp_far_config far_for_shape(const vp_plan* pl, int64_t R, bool mixed, int shape,
 }
 }  // namespace
 
+int64_t vp::far_partial_doubles(const vp_plan* pl, int64_t n_split, int64_t R) {
+  return n_split * pl->n_tgt * R + fmm_workspace_doubles(pl);
+}
+
 vp_far_config vp::far_default(const vp_plan* pl, int64_t R, bool mixed) {
+  if (pl->fmm_terms > 0) return vp_far_config{VP_FAR_WIDE, 4, 1};  // one partial sum per target
   vp_far_config wide = far_for_shape(pl, R, mixed, VP_FAR_WIDE, 4);
   vp_far_config w1 = wide;
   w1.n_split = 1;
@@ -837,6 +852,7 @@ vp_far_config vp::far_config(const vp_plan* pl, int64_t R, bool mixed) {
 }
 
 bool vp::far_config_valid(const vp_plan* pl, const vp_far_config& c) {
+  if (pl->fmm_terms > 0 && c.n_split != 1) return false;
   return c.shape >= VP_FAR_WIDE && c.shape <= VP_FAR_NARROW2 &&
          (c.mfma_tiles == 1 || c.mfma_tiles == 2 || c.mfma_tiles == 4) && c.n_split >= 1 &&
          c.n_split <= std::max<int64_t>(1, pl->n_src_pad / 64);
@@ -861,7 +877,7 @@ vp_status ensure_workspace(vp_plan* pl, int64_t R, int64_t split) {
   pl->ws_rhs = 0;
   const size_t nF = (size_t)pl->n_tri * pl->n_p * R;
   const size_t nQ = (size_t)pl->n_src_pad * R;
-  const size_t nP = (size_t)split * pl->n_tgt * R;
+  const size_t nP = (size_t)vp::far_partial_doubles(pl, split, R);
   const size_t nU = (size_t)pl->n_tgt * R;
   const size_t bytes = 8 * (2 * nF + nQ + nP + nU) + 4 * nQ + 6 * 8;
   if (pl->ctx->budget && pl->ctx->in_use + bytes > pl->ctx->budget)
@@ -985,7 +1001,7 @@ vp_status vp_graph_create(vp_plan* pl, int64_t R, const double* density, double*
   const vp_far_config cfg = vp::far_config(pl, R, prec == VP_MIXED);
   const int64_t split = cfg.n_split;
   const size_t nC = (size_t)pl->n_tri * pl->n_p * R, nQ = (size_t)pl->n_src_pad * R,
-               nP = (size_t)split * pl->n_tgt * R;
+               nP = (size_t)vp::far_partial_doubles(pl, split, R);
   g->bytes = 8 * (nC + nQ + nP) + (prec == VP_MIXED ? 4 * nQ : 0);
   auto drop = [&](vp_graph* x) {
     if (x->exec) (void)hipGraphExecDestroy(x->exec);
@@ -1110,6 +1126,7 @@ vp_status vp_plan_autotune(vp_plan* pl, int64_t R, vp_precision prec, int reps, 
   const int64_t max_split = std::max<int64_t>(1, pl->n_src_pad / 64);
   const size_t per_split_bytes = 8 * (size_t)pl->n_tgt * R;
   std::vector<vp_far_config> cand{def};
+  if (pl->fmm_terms > 0) shapes.clear();  // the FMM has no shapes to choose
   for (int sh : shapes)
     for (int mt : tiles) {
       const vp_far_config base = far_for_shape(pl, R, mixed, sh, mt);  // the size rule for this shape

@@ -572,6 +572,9 @@ hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, const vp_fa
                       hipStream_t st, int64_t* n_launches, float* Q32) {
   const int64_t NT = pl->n_tgt, NS = pl->n_src_pad;
   if (NT == 0) return hipSuccess;
+  // FMM plans: one partial sum per target, the FMM's workspace after it
+  // (FP64 also in mixed precision)
+  if (pl->fmm_terms > 0) return launch_fmm(pl, Q, R, partial, partial + NT * R, st, n_launches);
   const int64_t n_split = cfg.n_split;
   if (n_split < 1 || n_split > NS) return hipErrorInvalidValue;
   // chunk length: a multiple of 64 sources

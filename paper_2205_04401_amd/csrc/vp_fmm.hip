@@ -1,0 +1,596 @@
+// Far sum by the fast multipole method: an O(N + M) replacement of the
+// direct sum of the far-rule point charges (Sec. 3.6 couples the far rule
+// to an FMM as point charges; the paper uses a library FMM).  A plan option
+// (vp_plan_opts.fmm_terms > 0); the direct sum stays the default.
+//
+// U(x) = sum_j Q_j log|x - y_j|^2 = 2 Re sum_j Q_j log(z - w_j), z = x, w_j = y_j
+// as complex numbers.  Uniform quadtree over the bounding square of sources
+// and targets, levels 0..L (level l: 2^l x 2^l boxes of width s_l, row-major
+// box index iy 2^l + ix); every level is stored densely.  Expansions about a
+// box centre c with p terms, in units of the box width s:
+//   multipole  sum_k a_k (z - c)^-k + a_0 log(z - c),  stored ah_k = a_k / s^k
+//   local      sum_l b_l (z - c)^l,                     stored bh_l = b_l s^l
+// (Greengard-Rokhlin translation lemmas; with these scalings the M2M and L2L
+// operators depend only on the child's quadrant and the M2L operator only
+// on the integer offset between the boxes, so all are precomputed once per
+// plan; the one level-dependent term, a_0 log s of M2L, is added apart).
+// Interaction list: boxes of the same level that are not adjacent but whose
+// parents are; near field: the 3 x 3 adjacent leaf boxes, summed directly
+// with the direct sum's kernel log(r^2 + 2^-100), so a target on a source
+// still gets the value the correction rows subtract again.  The M2L bound
+// for adjacent-parent, non-adjacent boxes is (sum |Q|) 0.547^p / 0.83, so p
+// sets the accuracy (p = 56: ~2e-15 of sum |Q|).
+//   k_fmm_bbox_partial, k_fmm_keys, k_fmm_count, k_fmm_gather2  (plan time)
+//   k_fmm_p2m   one wavefront per leaf box: multipole of its sources
+//   k_fmm_m2m   one thread per (box, coefficient): the upward pass
+//   k_fmm_down  one thread per (box, coefficient): M2L over the interaction
+//               list plus L2L from the parent
+//   k_fmm_leaf  one wavefront per leaf box: the local expansion at each of
+//               its targets plus the direct sum over the 3 x 3 adjacent boxes
+#include <hipcub/hipcub.hpp>
+
+#include <climits>
+#include <cmath>
+#include <vector>
+
+#include "vp_internal.h"
+
+namespace vp {
+namespace {
+
+constexpr int kBlock = 256;
+
+inline unsigned blocks_for(int64_t n, int b = kBlock) {
+  const int64_t nb = (n + b - 1) / b;
+  return (unsigned)(nb < (1 << 20) ? (nb > 0 ? nb : 1) : (1 << 20));
+}
+
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {  // a b + c
+  return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// per-block min x, min y, max x, max y over sources and targets
+__global__ void k_fmm_bbox_partial(const double2* __restrict__ sxy, int64_t n_src, const double* __restrict__ xt,
+                                   const double* __restrict__ yt, int64_t n_tgt, double* __restrict__ part) {
+  __shared__ double red[4][kBlock];
+  double v[4] = {1e300, 1e300, -1e300, -1e300};
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_src + n_tgt; i += stride) {
+    const double x = i < n_src ? sxy[i].x : xt[i - n_src];
+    const double y = i < n_src ? sxy[i].y : yt[i - n_src];
+    v[0] = fmin(v[0], x);
+    v[1] = fmin(v[1], y);
+    v[2] = fmax(v[2], x);
+    v[3] = fmax(v[3], y);
+  }
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int h = kBlock / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + h]);
+      red[1][threadIdx.x] = fmin(red[1][threadIdx.x], red[1][threadIdx.x + h]);
+      red[2][threadIdx.x] = fmax(red[2][threadIdx.x], red[2][threadIdx.x + h]);
+      red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + h]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) part[4 * blockIdx.x + k] = red[k][0];
+}
+
+__device__ __forceinline__ uint32_t leaf_of(double x, double y, double x0, double y0, double inv_s, int n) {
+  int ix = (int)floor((x - x0) * inv_s), iy = (int)floor((y - y0) * inv_s);
+  ix = min(max(ix, 0), n - 1);
+  iy = min(max(iy, 0), n - 1);
+  return (uint32_t)(iy * n + ix);
+}
+
+// leaf keys and identity values of the sources (i < n_src) and targets
+__global__ void k_fmm_keys(const double2* __restrict__ sxy, int64_t n_src, const double* __restrict__ xt,
+                           const double* __restrict__ yt, int64_t n_tgt, double x0, double y0, double inv_s, int n,
+                           uint32_t* __restrict__ skey, int32_t* __restrict__ sval, uint32_t* __restrict__ tkey,
+                           int32_t* __restrict__ tval) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_src + n_tgt; i += stride) {
+    if (i < n_src) {
+      skey[i] = leaf_of(sxy[i].x, sxy[i].y, x0, y0, inv_s, n);
+      sval[i] = (int32_t)i;
+    } else {
+      const int64_t t = i - n_src;
+      tkey[t] = leaf_of(xt[t], yt[t], x0, y0, inv_s, n);
+      tval[t] = (int32_t)t;
+    }
+  }
+}
+
+__global__ void k_fmm_count(const uint32_t* __restrict__ key, int64_t n, int32_t* __restrict__ cnt) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) atomicAdd(&cnt[key[i]], 1);
+}
+
+__global__ void k_fmm_gather2(const double2* __restrict__ in, const int32_t* __restrict__ perm, int64_t n,
+                              double2* __restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = in[perm[i]];
+}
+
+// Multipole of every leaf box (one wavefront each): lanes take 64 sources
+// at a time; for each power k the wavefront sums Q t^k (t = (w - c)/s) and
+// lane k keeps ah_k = -sum Q t^k / k (lane 0: a_0 = sum Q).  Also writes
+// the charges in leaf order (Qs) for the near-field sum.
+__global__ __launch_bounds__(kBlock) void k_fmm_p2m(const double2* __restrict__ sxy_s,
+                                                    const int32_t* __restrict__ perm,
+                                                    const int64_t* __restrict__ ptr, const double* __restrict__ Q,
+                                                    int64_t R, int64_t r, int L, double x0, double y0, double s,
+                                                    int p, double2* __restrict__ M, double* __restrict__ Qs) {
+  const int lane = (int)(threadIdx.x & 63);
+  const int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int n = 1 << L;
+  if (b >= (int64_t)n * n) return;  // the whole wavefront
+  const int ix = (int)(b % n), iy = (int)(b / n);
+  const double cx = x0 + (ix + 0.5) * s, cy = y0 + (iy + 0.5) * s, inv_s = 1.0 / s;
+  double2 acc = make_double2(0.0, 0.0);
+  const int64_t j1 = ptr[b + 1];
+  for (int64_t j0 = ptr[b]; j0 < j1; j0 += 64) {
+    const int64_t j = j0 + lane;
+    const bool act = j < j1;
+    double q = 0.0;
+    double2 t = make_double2(0.0, 0.0);
+    if (act) {
+      q = Q[(int64_t)perm[j] * R + r];
+      Qs[j] = q;
+      const double2 w = sxy_s[j];
+      t = make_double2((w.x - cx) * inv_s, (w.y - cy) * inv_s);
+    }
+    const double s0 = wave_sum(q);
+    if (lane == 0) acc.x += s0;
+    double2 pw = make_double2(q, 0.0);  // q t^k
+    for (int k = 1; k <= p; ++k) {
+      pw = cmul(pw, t);
+      const double sx = wave_sum(pw.x), sy = wave_sum(pw.y);
+      if (lane == k) {
+        acc.x -= sx / k;
+        acc.y -= sy / k;
+      }
+    }
+  }
+  if (lane <= p) M[b * (p + 1) + lane] = acc;
+}
+
+// Upward pass at level l: the box's multipole from its 4 children's
+// (level l + 1), M2M operator of each child's quadrant.
+__global__ void k_fmm_m2m(const double2* __restrict__ Mc, const int32_t* __restrict__ cnt_c, int l, int p,
+                          const double2* __restrict__ m2m, double2* __restrict__ Mp) {
+  const int P1 = p + 1;
+  const int n = 1 << l;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)n * n * P1) return;
+  const int64_t b = g / P1;
+  const int k_out = (int)(g - b * P1);
+  const int ix = (int)(b % n), iy = (int)(b / n);
+  double2 acc = make_double2(0.0, 0.0);
+  for (int q = 0; q < 4; ++q) {
+    const int64_t c = (int64_t)(2 * iy + (q >> 1)) * (2 * n) + 2 * ix + (q & 1);
+    if (cnt_c[c] == 0) continue;
+    const double2* a = Mc + c * P1;
+    const double2* T = m2m + ((int64_t)q * P1 + k_out) * P1;
+    for (int k = 0; k <= k_out; ++k) acc = cfma(T[k], a[k], acc);
+  }
+  Mp[g] = acc;
+}
+
+// Downward pass at level l: local expansion = L2L from the parent (l > 2)
+// + M2L from every box of the interaction list that holds sources.  Boxes
+// with no targets below them are left at zero.
+__global__ void k_fmm_down(const double2* __restrict__ M, const int32_t* __restrict__ cnt_s,
+                           const int32_t* __restrict__ cnt_t, const double2* __restrict__ Lp, int l, int p,
+                           double log_s, const double2* __restrict__ m2l, const double2* __restrict__ l2l,
+                           double2* __restrict__ Lc) {
+  const int P1 = p + 1;
+  const int n = 1 << l;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)n * n * P1) return;
+  const int64_t b = g / P1;
+  const int m = (int)(g - b * P1);
+  double2 acc = make_double2(0.0, 0.0);
+  if (cnt_t[b] > 0) {
+    const int ix = (int)(b % n), iy = (int)(b / n);
+    if (Lp) {
+      const int64_t pb = (int64_t)(iy >> 1) * (n >> 1) + (ix >> 1);
+      const int q = (ix & 1) | ((iy & 1) << 1);
+      const double2* a = Lp + pb * P1;
+      const double2* T = l2l + ((int64_t)q * P1 + m) * P1;
+      for (int k = m; k <= p; ++k) acc = cfma(T[k], a[k], acc);
+    }
+    const int px = ix >> 1, py = iy >> 1;
+    for (int dy = -3; dy <= 3; ++dy) {
+      const int jy = iy + dy;
+      if (jy < 0 || jy >= n || abs((jy >> 1) - py) > 1) continue;
+      for (int dx = -3; dx <= 3; ++dx) {
+        const int jx = ix + dx;
+        if (jx < 0 || jx >= n || abs((jx >> 1) - px) > 1 || (abs(dx) <= 1 && abs(dy) <= 1)) continue;
+        const int64_t j = (int64_t)jy * n + jx;
+        if (cnt_s[j] == 0) continue;
+        const double2* a = M + j * P1;
+        const double2* T = m2l + ((int64_t)((dy + 3) * 7 + dx + 3) * P1 + m) * P1;
+        for (int k = 0; k <= p; ++k) acc = cfma(T[k], a[k], acc);
+        if (m == 0) acc.x = fma(a[0].x, log_s, acc.x);
+      }
+    }
+  }
+  Lc[g] = acc;
+}
+
+// Leaf boxes (one wavefront each, lanes over the box's targets 64 at a
+// time): 2 Re of the local expansion at the target, plus the direct sum of
+// Q log(r^2 + 2^-100) over the sources of the 3 x 3 adjacent leaf boxes
+// (wavefront-uniform source reads; 256-entry logarithm table in LDS, the
+// exponent part accumulated apart as in the direct far sum).
+__global__ __launch_bounds__(kBlock) void k_fmm_leaf(
+    const double2* __restrict__ Lc, const double2* __restrict__ sxy_s, const double* __restrict__ Qs,
+    const int64_t* __restrict__ sptr, const int32_t* __restrict__ tperm, const int64_t* __restrict__ tptr,
+    const double* __restrict__ xt, const double* __restrict__ yt, int L, double x0, double y0, double s, int p,
+    const double2* __restrict__ logtab, int64_t R, int64_t r, double* __restrict__ out) {
+  __shared__ double2 tab[kLogTab + 1];
+  for (int i = threadIdx.x; i <= kLogTab; i += kBlock) tab[i] = logtab[i];
+  __syncthreads();
+  const int lane = (int)(threadIdx.x & 63);
+  const int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int n = 1 << L;
+  if (b >= (int64_t)n * n) return;  // the whole wavefront
+  const int ix = (int)(b % n), iy = (int)(b / n);
+  const double cx = x0 + (ix + 0.5) * s, cy = y0 + (iy + 0.5) * s, inv_s = 1.0 / s;
+  const double2* lc = Lc + b * (p + 1);
+  const double2 l2 = tab[kLogTab];
+  const int64_t i1 = tptr[b + 1];
+  for (int64_t i0 = tptr[b]; i0 < i1; i0 += 64) {
+    const int64_t i = i0 + lane;
+    const bool act = i < i1;
+    const int64_t t = act ? tperm[i] : 0;
+    const double x = act ? xt[t] : cx, y = act ? yt[t] : cy;
+    // local expansion by Horner's rule
+    const double2 zh = make_double2((x - cx) * inv_s, (y - cy) * inv_s);
+    double2 v = lc[p];
+    for (int k = p - 1; k >= 0; --k) v = cfma(v, zh, lc[k]);
+    // adjacent boxes
+    double acc_e = 0.0, acc_r = 0.0;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int jy = iy + dy;
+      if (jy < 0 || jy >= n) continue;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int jx = ix + dx;
+        if (jx < 0 || jx >= n) continue;
+        const int64_t nb = (int64_t)jy * n + jx;
+        const int64_t j1 = sptr[nb + 1];
+        for (int64_t j = sptr[nb]; j < j1; ++j) {
+          const double2 w = sxy_s[j];
+          const double q = Qs[j];
+          const double ddx = x - w.x, ddy = y - w.y;
+          const double r2 = fma(ddy, ddy, fma(ddx, ddx, kR2Bias));
+          double e, rest;
+          vp_log_parts(r2, tab, e, rest);
+          acc_e = fma(q, e, acc_e);
+          acc_r = fma(q, rest, acc_r);
+        }
+      }
+    }
+    if (act) out[t * R + r] = 2.0 * v.x + acc_r + fma(acc_e, l2.x, acc_e * l2.y);
+  }
+}
+
+// Binomial coefficients up to n = 2 p in long double.
+std::vector<long double> binomials(int nmax) {
+  std::vector<long double> c((size_t)(nmax + 1) * (nmax + 1), 0.0L);
+  for (int i = 0; i <= nmax; ++i) {
+    c[(size_t)i * (nmax + 1)] = 1.0L;
+    for (int k = 1; k <= i; ++k)
+      c[(size_t)i * (nmax + 1) + k] = c[(size_t)(i - 1) * (nmax + 1) + k - 1] + (k < i ? c[(size_t)(i - 1) * (nmax + 1) + k] : 0.0L);
+  }
+  return c;
+}
+
+struct CLD {
+  long double x, y;
+};
+inline CLD cl_mul(CLD a, CLD b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+inline CLD cl_pow(CLD a, int k) {
+  CLD r{1.0L, 0.0L};
+  for (int i = 0; i < k; ++i) r = cl_mul(r, a);
+  return r;
+}
+inline CLD cl_inv(CLD a) {
+  const long double d = a.x * a.x + a.y * a.y;
+  return {a.x / d, -a.y / d};
+}
+
+// Translation operators of the scaled expansions (see the file header):
+//   M2M_q[l][k], child quadrant q (bit 0: +x half, bit 1: +y half), d = child
+//     centre - parent centre in parent widths:  [0][0] = 1,
+//     [l][0] = -d^l / l, [l][k] = 2^-k d^(l-k) C(l-1, k-1) for 1 <= k <= l
+//   L2L_q[m][l] = C(l, m) d^(l-m) 2^-m for l >= m
+//   M2L_o[l][k], o = (dy + 3) 7 + dx + 3, z0 = dx + i dy (source box centre -
+//     target box centre in box widths):  [0][0] = log(-z0), [0][k] = (-1)^k z0^-k,
+//     [l][0] = -1 / (l z0^l), [l][k] = (-1)^k C(l+k-1, k-1) z0^-(l+k)
+void fmm_operators(int p, std::vector<double2>& m2m, std::vector<double2>& l2l, std::vector<double2>& m2l) {
+  const int P1 = p + 1, nb = 2 * p + 1;
+  const std::vector<long double> C = binomials(nb);
+  auto bin = [&](int i, int k) { return (k < 0 || k > i) ? 0.0L : C[(size_t)i * (nb + 1) + k]; };
+  m2m.assign((size_t)4 * P1 * P1, make_double2(0.0, 0.0));
+  l2l.assign((size_t)4 * P1 * P1, make_double2(0.0, 0.0));
+  m2l.assign((size_t)49 * P1 * P1, make_double2(0.0, 0.0));
+  for (int q = 0; q < 4; ++q) {
+    const CLD d{(q & 1) ? 0.25L : -0.25L, (q & 2) ? 0.25L : -0.25L};
+    double2* M = m2m.data() + (size_t)q * P1 * P1;
+    double2* Lm = l2l.data() + (size_t)q * P1 * P1;
+    M[0] = make_double2(1.0, 0.0);
+    for (int l = 1; l <= p; ++l) {
+      const CLD dl = cl_pow(d, l);
+      M[(size_t)l * P1] = make_double2((double)(-dl.x / l), (double)(-dl.y / l));
+      for (int k = 1; k <= l; ++k) {
+        const CLD v = cl_pow(d, l - k);
+        const long double f = bin(l - 1, k - 1) * std::ldexp(1.0L, -k);
+        M[(size_t)l * P1 + k] = make_double2((double)(v.x * f), (double)(v.y * f));
+      }
+    }
+    for (int m = 0; m <= p; ++m)
+      for (int l = m; l <= p; ++l) {
+        const CLD v = cl_pow(d, l - m);
+        const long double f = bin(l, m) * std::ldexp(1.0L, -m);
+        Lm[(size_t)m * P1 + l] = make_double2((double)(v.x * f), (double)(v.y * f));
+      }
+  }
+  for (int dy = -3; dy <= 3; ++dy)
+    for (int dx = -3; dx <= 3; ++dx) {
+      if (std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+      double2* T = m2l.data() + (size_t)((dy + 3) * 7 + dx + 3) * P1 * P1;
+      const CLD z0{(long double)dx, (long double)dy};
+      const CLD iz = cl_inv(z0);
+      // log(-z0)
+      T[0] = make_double2((double)(0.5L * std::log(z0.x * z0.x + z0.y * z0.y)), (double)std::atan2(-z0.y, -z0.x));
+      std::vector<CLD> izp(2 * P1 + 1);
+      izp[0] = {1.0L, 0.0L};
+      for (int k = 1; k <= 2 * p; ++k) izp[k] = cl_mul(izp[k - 1], iz);
+      for (int k = 1; k <= p; ++k) {
+        const long double sg = (k & 1) ? -1.0L : 1.0L;
+        T[k] = make_double2((double)(sg * izp[k].x), (double)(sg * izp[k].y));
+      }
+      for (int l = 1; l <= p; ++l) {
+        T[(size_t)l * P1] = make_double2((double)(-izp[l].x / l), (double)(-izp[l].y / l));
+        for (int k = 1; k <= p; ++k) {
+          const long double f = ((k & 1) ? -1.0L : 1.0L) * bin(l + k - 1, k - 1);
+          T[(size_t)l * P1 + k] = make_double2((double)(f * izp[l + k].x), (double)(f * izp[l + k].y));
+        }
+      }
+    }
+}
+
+}  // namespace
+
+int64_t fmm_boxes(int L) {
+  int64_t n = 0;
+  for (int l = 0; l <= L; ++l) n += (int64_t)1 << (2 * l);
+  return n;
+}
+
+int64_t fmm_workspace_doubles(const vp_plan* pl) {
+  if (pl->fmm_terms <= 0) return 0;
+  // multipole and local coefficients (complex) of every box, charges in leaf order, 2 for alignment
+  return 2 * 2 * fmm_boxes(pl->fmm_levels) * (pl->fmm_terms + 1) + pl->n_src + 2;
+}
+
+hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
+  const int64_t NS = pl->n_src, NT = pl->n_tgt;
+  const int p = pl->fmm_terms;
+  auto alloc = [&](void** ptr, size_t bytes) -> hipError_t {
+    hipError_t r = hipMalloc(ptr, bytes ? bytes : 8);
+    if (r == hipSuccess) {
+      pl->allocs.push_back(*ptr);
+      pl->bytes += bytes;
+    }
+    return r;
+  };
+  hipError_t e;
+  // root square
+  const int nred = 256;
+  double* part = nullptr;
+  if ((e = hipMalloc((void**)&part, sizeof(double) * 4 * nred)) != hipSuccess) return e;
+  k_fmm_bbox_partial<<<nred, kBlock, 0, st>>>(pl->sxy, NS, pl->xt, pl->yt, NT, part);
+  std::vector<double> hp(4 * nred);
+  if ((e = hipGetLastError()) == hipSuccess &&
+      (e = hipMemcpyAsync(hp.data(), part, sizeof(double) * 4 * nred, hipMemcpyDeviceToHost, st)) == hipSuccess)
+    e = hipStreamSynchronize(st);
+  (void)hipFree(part);
+  if (e != hipSuccess) return e;
+  double x0 = 1e300, y0 = 1e300, x1 = -1e300, y1 = -1e300;
+  for (int i = 0; i < nred; ++i) {
+    x0 = std::min(x0, hp[4 * i]);
+    y0 = std::min(y0, hp[4 * i + 1]);
+    x1 = std::max(x1, hp[4 * i + 2]);
+    y1 = std::max(y1, hp[4 * i + 3]);
+  }
+  double w = std::max(x1 - x0, y1 - y0);
+  w = w > 0.0 ? w * (1.0 + 1e-12) : 1.0;
+  pl->fmm_x0 = 0.5 * (x0 + x1) - 0.5 * w;
+  pl->fmm_y0 = 0.5 * (y0 + y1) - 0.5 * w;
+  pl->fmm_width = w;
+  // levels: about `leaf` sources per leaf box of the full grid
+  int L = (int)std::lround(std::log((double)std::max<int64_t>(NS, 1) / leaf) / std::log(4.0));
+  L = std::min(std::max(L, 2), 10);
+  pl->fmm_levels = L;
+  const int n = 1 << L;
+  const int64_t nleaf = (int64_t)n * n;
+  // keys and stable sort by leaf box
+  uint32_t *skey = nullptr, *skey2 = nullptr, *tkey = nullptr, *tkey2 = nullptr;
+  int32_t *sval = nullptr, *tval = nullptr, *cnt = nullptr;
+  void* tmp = nullptr;
+  size_t tmp_s = 0, tmp_t = 0;
+  std::vector<void*> tmps;
+  auto talloc = [&](void** ptr, size_t bytes) -> hipError_t {
+    hipError_t r = hipMalloc(ptr, bytes ? bytes : 8);
+    if (r == hipSuccess) tmps.push_back(*ptr);
+    return r;
+  };
+  auto cleanup = [&]() {
+    for (void* x : tmps) (void)hipFree(x);
+  };
+  if ((e = alloc((void**)&pl->fmm_src_perm, sizeof(int32_t) * NS)) != hipSuccess ||
+      (e = alloc((void**)&pl->fmm_tgt_perm, sizeof(int32_t) * NT)) != hipSuccess ||
+      (e = alloc((void**)&pl->fmm_sxy, sizeof(double2) * NS)) != hipSuccess ||
+      (e = alloc((void**)&pl->fmm_src_ptr, sizeof(int64_t) * (nleaf + 1))) != hipSuccess ||
+      (e = alloc((void**)&pl->fmm_tgt_ptr, sizeof(int64_t) * (nleaf + 1))) != hipSuccess ||
+      (e = talloc((void**)&skey, sizeof(uint32_t) * NS)) != hipSuccess ||
+      (e = talloc((void**)&skey2, sizeof(uint32_t) * NS)) != hipSuccess ||
+      (e = talloc((void**)&sval, sizeof(int32_t) * NS)) != hipSuccess ||
+      (e = talloc((void**)&tkey, sizeof(uint32_t) * NT)) != hipSuccess ||
+      (e = talloc((void**)&tkey2, sizeof(uint32_t) * NT)) != hipSuccess ||
+      (e = talloc((void**)&tval, sizeof(int32_t) * NT)) != hipSuccess ||
+      (e = talloc((void**)&cnt, sizeof(int32_t) * 2 * nleaf)) != hipSuccess) {
+    cleanup();
+    return e;
+  }
+  k_fmm_keys<<<blocks_for(NS + NT), kBlock, 0, st>>>(pl->sxy, NS, pl->xt, pl->yt, NT, pl->fmm_x0, pl->fmm_y0,
+                                                     (double)n / w, n, skey, sval, tkey, tval);
+  const int bits = 2 * L;
+  if ((e = hipGetLastError()) != hipSuccess ||
+      (e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_s, skey, skey2, sval, pl->fmm_src_perm, (int)NS, 0, bits,
+                                              st)) != hipSuccess ||
+      (e = hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_t, tkey, tkey2, tval, pl->fmm_tgt_perm, (int)NT, 0, bits,
+                                              st)) != hipSuccess ||
+      (e = talloc(&tmp, std::max(tmp_s, tmp_t))) != hipSuccess) {
+    cleanup();
+    return e;
+  }
+  const size_t tmp_bytes = std::max(tmp_s, tmp_t);
+  size_t tb = tmp_bytes;
+  if ((e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, skey, skey2, sval, pl->fmm_src_perm, (int)NS, 0, bits, st)) !=
+      hipSuccess) {
+    cleanup();
+    return e;
+  }
+  tb = tmp_bytes;
+  if ((e = hipcub::DeviceRadixSort::SortPairs(tmp, tb, tkey, tkey2, tval, pl->fmm_tgt_perm, (int)NT, 0, bits, st)) !=
+      hipSuccess) {
+    cleanup();
+    return e;
+  }
+  // leaf counts -> CSR pointers and per-level counts (host)
+  if ((e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * 2 * nleaf, st)) != hipSuccess) {
+    cleanup();
+    return e;
+  }
+  k_fmm_count<<<blocks_for(NS), kBlock, 0, st>>>(skey, NS, cnt);
+  k_fmm_count<<<blocks_for(NT), kBlock, 0, st>>>(tkey, NT, cnt + nleaf);
+  k_fmm_gather2<<<blocks_for(NS), kBlock, 0, st>>>(pl->sxy, pl->fmm_src_perm, NS, pl->fmm_sxy);
+  std::vector<int32_t> hc(2 * nleaf);
+  if ((e = hipGetLastError()) != hipSuccess ||
+      (e = hipMemcpyAsync(hc.data(), cnt, sizeof(int32_t) * 2 * nleaf, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess) {
+    cleanup();
+    return e;
+  }
+  cleanup();
+  std::vector<int64_t> sp(nleaf + 1), tp(nleaf + 1);
+  sp[0] = tp[0] = 0;
+  for (int64_t i = 0; i < nleaf; ++i) {
+    sp[i + 1] = sp[i] + hc[i];
+    tp[i + 1] = tp[i] + hc[nleaf + i];
+  }
+  // per-level source and target counts, levels 0..L concatenated
+  const int64_t nbox = fmm_boxes(L);
+  std::vector<int32_t> cs(nbox), ct(nbox);
+  std::vector<int64_t> off(L + 2);
+  off[0] = 0;
+  for (int l = 0; l <= L; ++l) off[l + 1] = off[l] + ((int64_t)1 << (2 * l));
+  for (int64_t i = 0; i < nleaf; ++i) {
+    cs[off[L] + i] = hc[i];
+    ct[off[L] + i] = hc[nleaf + i];
+  }
+  for (int l = L - 1; l >= 0; --l) {
+    const int m = 1 << l;
+    for (int iy = 0; iy < m; ++iy)
+      for (int ix = 0; ix < m; ++ix) {
+        int32_t a = 0, c = 0;
+        for (int q = 0; q < 4; ++q) {
+          const int64_t ch = off[l + 1] + (int64_t)(2 * iy + (q >> 1)) * (2 * m) + 2 * ix + (q & 1);
+          a += cs[ch];
+          c += ct[ch];
+        }
+        cs[off[l] + (int64_t)iy * m + ix] = a;
+        ct[off[l] + (int64_t)iy * m + ix] = c;
+      }
+  }
+  for (int l = 0; l <= L; ++l) pl->fmm_off[l] = off[l];
+  std::vector<double2> m2m, l2l, m2l;
+  fmm_operators(p, m2m, l2l, m2l);
+  if ((e = alloc((void**)&pl->fmm_cnt_src, sizeof(int32_t) * nbox)) != hipSuccess ||
+      (e = alloc((void**)&pl->fmm_cnt_tgt, sizeof(int32_t) * nbox)) != hipSuccess ||
+      (e = alloc((void**)&pl->fmm_m2m, sizeof(double2) * m2m.size())) != hipSuccess ||
+      (e = alloc((void**)&pl->fmm_l2l, sizeof(double2) * l2l.size())) != hipSuccess ||
+      (e = alloc((void**)&pl->fmm_m2l, sizeof(double2) * m2l.size())) != hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(pl->fmm_src_ptr, sp.data(), sizeof(int64_t) * (nleaf + 1), hipMemcpyHostToDevice, st)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(pl->fmm_tgt_ptr, tp.data(), sizeof(int64_t) * (nleaf + 1), hipMemcpyHostToDevice, st)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(pl->fmm_cnt_src, cs.data(), sizeof(int32_t) * nbox, hipMemcpyHostToDevice, st)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(pl->fmm_cnt_tgt, ct.data(), sizeof(int32_t) * nbox, hipMemcpyHostToDevice, st)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(pl->fmm_m2m, m2m.data(), sizeof(double2) * m2m.size(), hipMemcpyHostToDevice, st)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(pl->fmm_l2l, l2l.data(), sizeof(double2) * l2l.size(), hipMemcpyHostToDevice, st)) !=
+          hipSuccess ||
+      (e = hipMemcpyAsync(pl->fmm_m2l, m2l.data(), sizeof(double2) * m2l.size(), hipMemcpyHostToDevice, st)) !=
+          hipSuccess)
+    return e;
+  return hipStreamSynchronize(st);  // the host vectors above go out of scope
+}
+
+// The far sum of every right-hand side by the FMM into out[t][R] (the
+// first n_tgt R doubles of `partial`); ws = the FMM workspace
+// (fmm_workspace_doubles).
+hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out, double* ws, hipStream_t st,
+                      int64_t* n_launches) {
+  const int p = pl->fmm_terms, P1 = p + 1, L = pl->fmm_levels;
+  const int64_t nbox = fmm_boxes(L);
+  // 16-byte alignment of the complex arrays
+  double2* Mall = (double2*)(ws + ((uintptr_t)ws % 16 ? 1 : 0));
+  double2* Lall = Mall + nbox * P1;
+  double* Qs = (double*)(Lall + nbox * P1);
+  const int n = 1 << L;
+  const int64_t nleaf = (int64_t)n * n;
+  const double sL = pl->fmm_width / n;
+  for (int64_t r = 0; r < R; ++r) {
+    k_fmm_p2m<<<(unsigned)((nleaf * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        pl->fmm_sxy, pl->fmm_src_perm, pl->fmm_src_ptr, Q, R, r, L, pl->fmm_x0, pl->fmm_y0, sL, p,
+        Mall + pl->fmm_off[L] * P1, Qs);
+    for (int l = L - 1; l >= 2; --l) {
+      const int64_t nt = ((int64_t)1 << (2 * l)) * P1;
+      k_fmm_m2m<<<blocks_for(nt), kBlock, 0, st>>>(Mall + pl->fmm_off[l + 1] * P1, pl->fmm_cnt_src + pl->fmm_off[l + 1],
+                                                   l, p, pl->fmm_m2m, Mall + pl->fmm_off[l] * P1);
+    }
+    for (int l = 2; l <= L; ++l) {
+      const int64_t nt = ((int64_t)1 << (2 * l)) * P1;
+      const double log_s = std::log(pl->fmm_width / (double)(1 << l));
+      k_fmm_down<<<blocks_for(nt), kBlock, 0, st>>>(Mall + pl->fmm_off[l] * P1, pl->fmm_cnt_src + pl->fmm_off[l],
+                                                    pl->fmm_cnt_tgt + pl->fmm_off[l],
+                                                    l > 2 ? Lall + pl->fmm_off[l - 1] * P1 : nullptr, l, p, log_s,
+                                                    pl->fmm_m2l, pl->fmm_l2l, Lall + pl->fmm_off[l] * P1);
+    }
+    k_fmm_leaf<<<(unsigned)((nleaf * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        Lall + pl->fmm_off[L] * P1, pl->fmm_sxy, Qs, pl->fmm_src_ptr, pl->fmm_tgt_perm, pl->fmm_tgt_ptr, pl->xt,
+        pl->yt, L, pl->fmm_x0, pl->fmm_y0, sL, p, pl->logtab, R, r, out);
+    if (n_launches) *n_launches += 2 * L - 1;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace vp

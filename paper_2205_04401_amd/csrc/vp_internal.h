@@ -373,6 +373,15 @@ struct vp_plan {
   // execute workspace
   int64_t ws_rhs = 0;
   int64_t ws_split = 0;
+  // FMM far sum (fmm_terms > 0; built at plan creation)
+  int fmm_terms = 0, fmm_levels = 0;
+  double fmm_x0 = 0.0, fmm_y0 = 0.0, fmm_width = 0.0;  // root square
+  int64_t fmm_off[12] = {};                           // first box of each level in the per-level arrays
+  int32_t *fmm_src_perm = nullptr, *fmm_tgt_perm = nullptr;  // leaf order -> source / target index
+  int64_t *fmm_src_ptr = nullptr, *fmm_tgt_ptr = nullptr;    // [4^L + 1] CSR by leaf box
+  double2* fmm_sxy = nullptr;                                // source positions in leaf order
+  int32_t *fmm_cnt_src = nullptr, *fmm_cnt_tgt = nullptr;    // sources / targets per box, all levels
+  double2 *fmm_m2m = nullptr, *fmm_l2l = nullptr, *fmm_m2l = nullptr;  // translation operators
   // far-sum launch shapes stored for (n_rhs, precision) by the tuner or the caller
   std::map<std::pair<int64_t, int>, vp_far_config> far_tuned;
   double *ws_f = nullptr, *ws_c = nullptr, *ws_q = nullptr, *ws_part = nullptr, *ws_u = nullptr;
@@ -418,6 +427,14 @@ int64_t far_targets_per_block(const vp_far_config& cfg, int64_t R, bool mixed);
 vp_far_config far_default(const vp_plan* pl, int64_t R, bool mixed);  // shape chosen from the sizes
 vp_far_config far_config(const vp_plan* pl, int64_t R, bool mixed);   // stored shape, else far_default
 bool far_config_valid(const vp_plan* pl, const vp_far_config& cfg);
+// doubles of the far-sum workspace: n_split partial sums per target and RHS,
+// then the FMM's expansions and leaf-ordered charges
+int64_t far_partial_doubles(const vp_plan* pl, int64_t n_split, int64_t R);
+int64_t fmm_boxes(int levels);
+int64_t fmm_workspace_doubles(const vp_plan* pl);
+hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st);  // after sources and targets; plan memory
+hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out, double* ws, hipStream_t st,
+                      int64_t* n_launches);
 void set_last_error(const char* msg);
 // dst[i][c0 + r] = src[i][r] for i < rows, r < src_cols (dst has dst_cols)
 hipError_t launch_pack_columns(const double* src, int64_t rows, int64_t src_cols, double* dst, int64_t dst_cols,

@@ -66,7 +66,7 @@ vp_status slot_reserve(vp_server* s, vp_server::Slot& sl, const vp_plan* pl, int
       8 * (size_t)pl->n_tri * pl->n_p * R,  // F (packed)
       8 * (size_t)pl->n_tri * pl->n_p * R,  // C
       8 * (size_t)pl->n_src_pad * R,        // Q
-      8 * (size_t)split * pl->n_tgt * R,    // far partials
+      8 * (size_t)vp::far_partial_doubles(pl, split, R),  // far partials (+ FMM workspace)
       8 * (size_t)pl->n_tgt * R,            // U (packed)
       4 * (size_t)pl->n_src_pad * R,        // Q32
   };

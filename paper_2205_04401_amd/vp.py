@@ -46,7 +46,8 @@ class VPError(RuntimeError):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("c_n", ctypes.c_double), ("q_near", ctypes.c_int), ("n_l", ctypes.c_int),
                 ("tau", ctypes.c_double), ("depth_cap", ctypes.c_int), ("dyadic_cap", ctypes.c_int),
-                ("flags", ctypes.c_uint32), ("near_model", ctypes.c_int), ("ball_factor", ctypes.c_double)]
+                ("flags", ctypes.c_uint32), ("near_model", ctypes.c_int), ("ball_factor", ctypes.c_double),
+                ("fmm_terms", ctypes.c_int), ("fmm_leaf", ctypes.c_int)]
 
 
 class FarConfig(ctypes.Structure):
@@ -64,7 +65,7 @@ class PlanStats(ctypes.Structure):
                 ("bytes_resident", ctypes.c_int64), ("p", ctypes.c_int32), ("q", ctypes.c_int32),
                 ("n_p", ctypes.c_int32), ("n_f", ctypes.c_int32), ("eps", ctypes.c_double),
                 ("ms_classify", ctypes.c_double), ("ms_rows", ctypes.c_double), ("far_split", ctypes.c_int64),
-                ("cluster_entries", ctypes.c_int64)]
+                ("cluster_entries", ctypes.c_int64), ("fmm_terms", ctypes.c_int32), ("fmm_levels", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -361,7 +362,7 @@ class Interp:
 
 class Plan:
     def __init__(self, ctx, mesh, p, q, eps, targets, c_n=1.0, q_near=7, n_l=16, tau=1e-13, depth_cap=50,
-                 dyadic_cap=60, near_model="ellipse", ball_factor=2.0):
+                 dyadic_cap=60, near_model="ellipse", ball_factor=2.0, fmm_terms=0, fmm_leaf=128):
         if _is_device(targets):
             tgt = targets.contiguous()
             flags = VP_DEVICE_PTRS
@@ -370,7 +371,8 @@ class Plan:
             flags = 0
         if near_model not in NEAR_MODELS:
             raise VPError(VP_EINVAL, f"near_model must be one of {sorted(NEAR_MODELS)}")
-        opts = PlanOpts(c_n, q_near, n_l, tau, depth_cap, dyadic_cap, flags, NEAR_MODELS[near_model], ball_factor)
+        opts = PlanOpts(c_n, q_near, n_l, tau, depth_cap, dyadic_cap, flags, NEAR_MODELS[near_model], ball_factor,
+                        fmm_terms, fmm_leaf)
         h = P()
         _check(load().vp_plan_create(ctx.h, mesh.h, p, q, eps, tgt.shape[0], _ptr(tgt), ctypes.byref(opts),
                                      ctypes.byref(h)))
