@@ -23,8 +23,9 @@
 //   k_fmm_bbox_partial, k_fmm_keys, k_fmm_count, k_fmm_gather2  (plan time)
 //   k_fmm_p2m   one wavefront per leaf box: multipole of its sources
 //   k_fmm_m2m   one thread per (box, coefficient): the upward pass
-//   k_fmm_down  one thread per (box, coefficient): M2L over the interaction
-//               list plus L2L from the parent
+//   k_fmm_m2l   16 boxes per wavefront: M2L over the interaction list on the
+//               FP64 matrix cores (real form of the complex operators)
+//   k_fmm_l2l   one thread per (box, coefficient): L2L from the parent
 //   k_fmm_leaf  one wavefront per leaf box: the local expansion at each of
 //               its targets plus the direct sum over the 3 x 3 adjacent boxes
 #include <hipcub/hipcub.hpp>
@@ -187,46 +188,96 @@ __global__ void k_fmm_m2m(const double2* __restrict__ Mc, const int32_t* __restr
   Mp[g] = acc;
 }
 
-// Downward pass at level l: local expansion = L2L from the parent (l > 2)
-// + M2L from every box of the interaction list that holds sources.  Boxes
-// with no targets below them are left at zero.
-__global__ void k_fmm_down(const double2* __restrict__ M, const int32_t* __restrict__ cnt_s,
-                           const int32_t* __restrict__ cnt_t, const double2* __restrict__ Lp, int l, int p,
-                           double log_s, const double2* __restrict__ m2l, const double2* __restrict__ l2l,
-                           double2* __restrict__ Lc) {
+// M2L at level l on the matrix cores.  In real form an M2L operator is a
+// (2 P1) x (2 P1) matrix (rows and columns: real parts of the P1
+// coefficients, then imaginary parts), padded to MP rows (multiple of 16)
+// and KP columns (multiple of 4) with zeros.  One wavefront takes 16
+// consecutive boxes (the 16 columns of the MFMA B operand) and one 16-row
+// tile of the result, and accumulates over the 40 offsets operator rows x
+// [multipoles of the 16 source boxes] (v_mfma_f64_16x16x4f64); a column
+// whose box does not have that offset in its interaction list, or whose
+// source box holds no sources, is zero.  The operators (49 MP KP doubles,
+// 2.1 MB at p = 32) are read from the L2 cache by every wavefront, with no
+// staging or barrier (measured against staging each operator in LDS for 4
+// wavefronts: 1.6 ms against 2.9 ms per evaluation on the 20k-triangle
+// star, and against one tile per wavefront for all row tiles: 5.6 ms; the
+// pass is bound by operand loads and latency, not the matrix cores).  The
+// level's a_0 log s term is added by the wavefront that holds row 0.  A
+// lane l holds A row 16 t + (l & 15), column 4 s + (l >> 4); B row
+// 4 s + (l >> 4), box l & 15; result element v of lane l: row
+// 16 t + (l >> 4) + 4 v, box l & 15.  Boxes with no targets below them get
+// zeros.
+typedef double vp_d4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kBlock) void k_fmm_m2l(const double2* __restrict__ M, const int32_t* __restrict__ cnt_s,
+                                                    const int32_t* __restrict__ cnt_t, int l, int p, int MP, int KP,
+                                                    double log_s, const double* __restrict__ m2l,
+                                                    double2* __restrict__ Lc) {
+  const int P1 = p + 1;
+  const int n = 1 << l;
+  const int64_t nb = (int64_t)n * n;
+  const int tiles = MP / 16;
+  const int lane = (int)(threadIdx.x & 63), r16 = lane & 15, kq = lane >> 4;
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t bg = w / tiles;
+  const int t = (int)(w - bg * tiles);
+  if (bg * 16 >= nb) return;  // the whole wavefront
+  const int64_t b = bg * 16 + r16;  // this lane's B box
+  const bool live = b < nb && cnt_t[b < nb ? b : 0] > 0;
+  const int ix = (int)(b % n), iy = (int)(b / n);
+  vp_d4 acc = vp_d4{0.0, 0.0, 0.0, 0.0};
+  double a0 = 0.0;  // sum of the used source boxes' a_0 (for the log s term)
+  for (int o = 0; o < 49; ++o) {
+    const int dy = o / 7 - 3, dx = o % 7 - 3;
+    if (abs(dx) <= 1 && abs(dy) <= 1) continue;
+    const int jx = ix + dx, jy = iy + dy;
+    bool use = live && jx >= 0 && jx < n && jy >= 0 && jy < n && abs((jx >> 1) - (ix >> 1)) <= 1 &&
+               abs((jy >> 1) - (iy >> 1)) <= 1;
+    if (use) use = cnt_s[(int64_t)jy * n + jx] > 0;
+    const double2* src = M + (use ? (int64_t)jy * n + jx : 0) * P1;
+    if (use) a0 += src[0].x;
+    const double* A = m2l + ((int64_t)o * MP + 16 * t + r16) * KP;
+    for (int s4 = 0; s4 < KP / 4; ++s4) {
+      const int k = 4 * s4 + kq;
+      const int kc = k < P1 ? k : (k < 2 * P1 ? k - P1 : 0);
+      const double2 mv = src[kc];
+      const double bv = (use && k < 2 * P1) ? (k < P1 ? mv.x : mv.y) : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[k], bv, acc, 0, 0, 0);
+    }
+  }
+  if (b < nb) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * t + kq + 4 * v;
+      double y = acc[v];
+      if (row == 0) y = fma(a0, log_s, y);
+      if (row < P1)
+        Lc[b * P1 + row].x = live ? y : 0.0;
+      else if (row < 2 * P1)
+        Lc[b * P1 + row - P1].y = live ? y : 0.0;
+    }
+  }
+}
+
+// L2L at level l > 2: every (box, coefficient) with targets below it adds
+// the parent's local expansion shifted to its centre.
+__global__ void k_fmm_l2l(const int32_t* __restrict__ cnt_t, const double2* __restrict__ Lp, int l, int p,
+                          const double2* __restrict__ l2l, double2* __restrict__ Lc) {
   const int P1 = p + 1;
   const int n = 1 << l;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= (int64_t)n * n * P1) return;
   const int64_t b = g / P1;
   const int m = (int)(g - b * P1);
-  double2 acc = make_double2(0.0, 0.0);
-  if (cnt_t[b] > 0) {
-    const int ix = (int)(b % n), iy = (int)(b / n);
-    if (Lp) {
-      const int64_t pb = (int64_t)(iy >> 1) * (n >> 1) + (ix >> 1);
-      const int q = (ix & 1) | ((iy & 1) << 1);
-      const double2* a = Lp + pb * P1;
-      const double2* T = l2l + ((int64_t)q * P1 + m) * P1;
-      for (int k = m; k <= p; ++k) acc = cfma(T[k], a[k], acc);
-    }
-    const int px = ix >> 1, py = iy >> 1;
-    for (int dy = -3; dy <= 3; ++dy) {
-      const int jy = iy + dy;
-      if (jy < 0 || jy >= n || abs((jy >> 1) - py) > 1) continue;
-      for (int dx = -3; dx <= 3; ++dx) {
-        const int jx = ix + dx;
-        if (jx < 0 || jx >= n || abs((jx >> 1) - px) > 1 || (abs(dx) <= 1 && abs(dy) <= 1)) continue;
-        const int64_t j = (int64_t)jy * n + jx;
-        if (cnt_s[j] == 0) continue;
-        const double2* a = M + j * P1;
-        const double2* T = m2l + ((int64_t)((dy + 3) * 7 + dx + 3) * P1 + m) * P1;
-        for (int k = 0; k <= p; ++k) acc = cfma(T[k], a[k], acc);
-        if (m == 0) acc.x = fma(a[0].x, log_s, acc.x);
-      }
-    }
-  }
-  Lc[g] = acc;
+  if (cnt_t[b] == 0) return;
+  const int ix = (int)(b % n), iy = (int)(b / n);
+  const int64_t pb = (int64_t)(iy >> 1) * (n >> 1) + (ix >> 1);
+  const int q = (ix & 1) | ((iy & 1) << 1);
+  const double2* a = Lp + pb * P1;
+  const double2* T = l2l + ((int64_t)q * P1 + m) * P1;
+  double2 v = Lc[g];
+  for (int k = m; k < P1; ++k) v = cfma(T[k], a[k], v);
+  Lc[g] = v;
 }
 
 // Leaf boxes (one wavefront each, lanes over the box's targets 64 at a
@@ -260,27 +311,28 @@ __global__ __launch_bounds__(kBlock) void k_fmm_leaf(
     const double2 zh = make_double2((x - cx) * inv_s, (y - cy) * inv_s);
     double2 v = lc[p];
     for (int k = p - 1; k >= 0; --k) v = cfma(v, zh, lc[k]);
-    // adjacent boxes
+    // adjacent boxes: in each of the 3 rows they are consecutive leaf
+    // boxes, so their sources form one contiguous range
     double acc_e = 0.0, acc_r = 0.0;
+    auto pair = [&](double2 w, double q) {
+      const double ddx = x - w.x, ddy = y - w.y;
+      const double r2 = fma(ddy, ddy, fma(ddx, ddx, kR2Bias));
+      double e, rest;
+      vp_log_parts(r2, tab, e, rest);
+      acc_e = fma(q, e, acc_e);
+      acc_r = fma(q, rest, acc_r);
+    };
     for (int dy = -1; dy <= 1; ++dy) {
       const int jy = iy + dy;
       if (jy < 0 || jy >= n) continue;
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int jx = ix + dx;
-        if (jx < 0 || jx >= n) continue;
-        const int64_t nb = (int64_t)jy * n + jx;
-        const int64_t j1 = sptr[nb + 1];
-        for (int64_t j = sptr[nb]; j < j1; ++j) {
-          const double2 w = sxy_s[j];
-          const double q = Qs[j];
-          const double ddx = x - w.x, ddy = y - w.y;
-          const double r2 = fma(ddy, ddy, fma(ddx, ddx, kR2Bias));
-          double e, rest;
-          vp_log_parts(r2, tab, e, rest);
-          acc_e = fma(q, e, acc_e);
-          acc_r = fma(q, rest, acc_r);
-        }
+      const int64_t row = (int64_t)jy * n;
+      const int64_t j0 = sptr[row + max(ix - 1, 0)], j1 = sptr[row + min(ix + 1, n - 1) + 1];
+      int64_t j = j0;
+      for (; j + 4 <= j1; j += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pair(sxy_s[j + u], Qs[j + u]);
       }
+      for (; j < j1; ++j) pair(sxy_s[j], Qs[j]);
     }
     if (act) out[t * R + r] = 2.0 * v.x + acc_r + fma(acc_e, l2.x, acc_e * l2.y);
   }
@@ -319,6 +371,27 @@ inline CLD cl_inv(CLD a) {
 //   M2L_o[l][k], o = (dy + 3) 7 + dx + 3, z0 = dx + i dy (source box centre -
 //     target box centre in box widths):  [0][0] = log(-z0), [0][k] = (-1)^k z0^-k,
 //     [l][0] = -1 / (l z0^l), [l][k] = (-1)^k C(l+k-1, k-1) z0^-(l+k)
+void fmm_operators(int p, std::vector<double2>& m2m, std::vector<double2>& l2l, std::vector<double2>& m2l);
+
+// The M2L operators in the real, padded form of k_fmm_m2l: [49][MP][KP].
+std::vector<double> fmm_m2l_real(int p, const std::vector<double2>& m2l, int MP, int KP) {
+  const int P1 = p + 1;
+  std::vector<double> out((size_t)49 * MP * KP, 0.0);
+  for (int o = 0; o < 49; ++o) {
+    const double2* T = m2l.data() + (size_t)o * P1 * P1;
+    double* R = out.data() + (size_t)o * MP * KP;
+    for (int r = 0; r < P1; ++r)
+      for (int c = 0; c < P1; ++c) {
+        const double2 t = T[(size_t)r * P1 + c];
+        R[(size_t)r * KP + c] = t.x;              // Re y <- Re T Re x
+        R[(size_t)r * KP + P1 + c] = -t.y;        //        - Im T Im x
+        R[(size_t)(P1 + r) * KP + c] = t.y;       // Im y <- Im T Re x
+        R[(size_t)(P1 + r) * KP + P1 + c] = t.x;  //        + Re T Im x
+      }
+  }
+  return out;
+}
+
 void fmm_operators(int p, std::vector<double2>& m2m, std::vector<double2>& l2l, std::vector<double2>& m2l) {
   const int P1 = p + 1, nb = 2 * p + 1;
   const std::vector<long double> C = binomials(nb);
@@ -530,11 +603,14 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
   for (int l = 0; l <= L; ++l) pl->fmm_off[l] = off[l];
   std::vector<double2> m2m, l2l, m2l;
   fmm_operators(p, m2m, l2l, m2l);
+  pl->fmm_mp = (2 * (p + 1) + 15) / 16 * 16;
+  pl->fmm_kp = (2 * (p + 1) + 3) / 4 * 4;
+  const std::vector<double> m2l_r = fmm_m2l_real(p, m2l, pl->fmm_mp, pl->fmm_kp);
   if ((e = alloc((void**)&pl->fmm_cnt_src, sizeof(int32_t) * nbox)) != hipSuccess ||
       (e = alloc((void**)&pl->fmm_cnt_tgt, sizeof(int32_t) * nbox)) != hipSuccess ||
       (e = alloc((void**)&pl->fmm_m2m, sizeof(double2) * m2m.size())) != hipSuccess ||
       (e = alloc((void**)&pl->fmm_l2l, sizeof(double2) * l2l.size())) != hipSuccess ||
-      (e = alloc((void**)&pl->fmm_m2l, sizeof(double2) * m2l.size())) != hipSuccess)
+      (e = alloc((void**)&pl->fmm_m2l, sizeof(double) * m2l_r.size())) != hipSuccess)
     return e;
   if ((e = hipMemcpyAsync(pl->fmm_src_ptr, sp.data(), sizeof(int64_t) * (nleaf + 1), hipMemcpyHostToDevice, st)) !=
           hipSuccess ||
@@ -548,7 +624,7 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
           hipSuccess ||
       (e = hipMemcpyAsync(pl->fmm_l2l, l2l.data(), sizeof(double2) * l2l.size(), hipMemcpyHostToDevice, st)) !=
           hipSuccess ||
-      (e = hipMemcpyAsync(pl->fmm_m2l, m2l.data(), sizeof(double2) * m2l.size(), hipMemcpyHostToDevice, st)) !=
+      (e = hipMemcpyAsync(pl->fmm_m2l, m2l_r.data(), sizeof(double) * m2l_r.size(), hipMemcpyHostToDevice, st)) !=
           hipSuccess)
     return e;
   return hipStreamSynchronize(st);  // the host vectors above go out of scope
@@ -578,17 +654,21 @@ hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out
                                                    l, p, pl->fmm_m2m, Mall + pl->fmm_off[l] * P1);
     }
     for (int l = 2; l <= L; ++l) {
-      const int64_t nt = ((int64_t)1 << (2 * l)) * P1;
+      const int64_t nbl = (int64_t)1 << (2 * l);
       const double log_s = std::log(pl->fmm_width / (double)(1 << l));
-      k_fmm_down<<<blocks_for(nt), kBlock, 0, st>>>(Mall + pl->fmm_off[l] * P1, pl->fmm_cnt_src + pl->fmm_off[l],
-                                                    pl->fmm_cnt_tgt + pl->fmm_off[l],
-                                                    l > 2 ? Lall + pl->fmm_off[l - 1] * P1 : nullptr, l, p, log_s,
-                                                    pl->fmm_m2l, pl->fmm_l2l, Lall + pl->fmm_off[l] * P1);
+      const int64_t waves = (nbl + 15) / 16 * (pl->fmm_mp / 16);
+      k_fmm_m2l<<<(unsigned)((waves * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+          Mall + pl->fmm_off[l] * P1, pl->fmm_cnt_src + pl->fmm_off[l], pl->fmm_cnt_tgt + pl->fmm_off[l], l, p,
+          pl->fmm_mp, pl->fmm_kp, log_s, pl->fmm_m2l, Lall + pl->fmm_off[l] * P1);
+      if (l > 2)
+        k_fmm_l2l<<<blocks_for(nbl * P1), kBlock, 0, st>>>(pl->fmm_cnt_tgt + pl->fmm_off[l],
+                                                          Lall + pl->fmm_off[l - 1] * P1, l, p, pl->fmm_l2l,
+                                                          Lall + pl->fmm_off[l] * P1);
     }
     k_fmm_leaf<<<(unsigned)((nleaf * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
         Lall + pl->fmm_off[L] * P1, pl->fmm_sxy, Qs, pl->fmm_src_ptr, pl->fmm_tgt_perm, pl->fmm_tgt_ptr, pl->xt,
         pl->yt, L, pl->fmm_x0, pl->fmm_y0, sL, p, pl->logtab, R, r, out);
-    if (n_launches) *n_launches += 2 * L - 1;
+    if (n_launches) *n_launches += 3 * L - 3;
   }
   return hipGetLastError();
 }

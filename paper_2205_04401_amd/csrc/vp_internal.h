@@ -381,7 +381,9 @@ struct vp_plan {
   int64_t *fmm_src_ptr = nullptr, *fmm_tgt_ptr = nullptr;    // [4^L + 1] CSR by leaf box
   double2* fmm_sxy = nullptr;                                // source positions in leaf order
   int32_t *fmm_cnt_src = nullptr, *fmm_cnt_tgt = nullptr;    // sources / targets per box, all levels
-  double2 *fmm_m2m = nullptr, *fmm_l2l = nullptr, *fmm_m2l = nullptr;  // translation operators
+  double2 *fmm_m2m = nullptr, *fmm_l2l = nullptr;  // translation operators (complex)
+  double* fmm_m2l = nullptr;                         // M2L operators, real form [49][fmm_mp][fmm_kp]
+  int fmm_mp = 0, fmm_kp = 0;
   // far-sum launch shapes stored for (n_rhs, precision) by the tuner or the caller
   std::map<std::pair<int64_t, int>, vp_far_config> far_tuned;
   double *ws_f = nullptr, *ws_c = nullptr, *ws_q = nullptr, *ws_part = nullptr, *ws_u = nullptr;
