@@ -386,6 +386,39 @@ def run(args):
         res = ablation.run(ctx)
         print(ablation.table(res), file=sys.stderr, flush=True)
         result["ablation"] = {k: v for k, v in res.items() if k not in ("problem", "sample_same", "sample_stag")}
+    if not args.no_fmm:
+        # the same step with the far sum by the FMM (plan option), at the
+        # size rule's q and at q = 16 (smaller near field, cheaper rows)
+        step(q)  # the FP64 direct-sum result to compare against
+        u_direct = out.clone()
+        result["fmm"] = []
+        for qf in sorted({q, 16}):
+            def step_fmm():
+                plan = ctx.plan(mesh, p, qf, eps, tg_d, fmm_terms=args.fmm_terms, fmm_leaf=64)
+                plan.execute(F_d, out=out)
+                info = plan.info()
+                plan.close()
+                return info
+            step_fmm()
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                info_f = step_fmm()
+            torch.cuda.synchronize()
+            dt_f = (time.perf_counter() - t0) / args.steps
+            tm_f = ctx.timings()
+            ctx.profile(False)
+            line = {"q": qf, "fmm_terms": info_f["fmm_terms"], "fmm_levels": info_f["fmm_levels"],
+                    "value": n_tgt / dt_f, "unit": "evals/s", "ms_per_step": dt_f * 1e3,
+                    "far_ms": tm_f["far"][0] / args.steps, "rows_ms": tm_f["rows"][0] / args.steps,
+                    "pairs_per_target": info_f["n_pairs"] / n_tgt,
+                    "fmm_near_pairs": info_f["fmm_near_pairs"], "fmm_m2l_pairs": info_f["fmm_m2l_pairs"],
+                    "breakdown_ms": {k: v[0] / args.steps for k, v in tm_f.items()}}
+            if qf == q:
+                line["rel_diff_vs_direct"] = float((out - u_direct).abs().max() / u_direct.abs().max())
+            result["fmm"].append(line)
+            print(json.dumps({"fmm": line}), flush=True)
     if not args.no_small:
         result["small_case"] = small_case(ctx)
     if args.batched_rhs:
@@ -411,6 +444,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-small", action="store_true", help="skip the unit-square latency section")
+    ap.add_argument("--no-fmm", action="store_true", help="skip the FMM far-sum section")
+    ap.add_argument("--fmm-terms", type=int, default=32)
     ap.add_argument("--serving-requests", type=int, default=160)
     ap.add_argument("--batched-rhs", type=int, default=64, help="densities of the batched section (0: skip)")
     ap.add_argument("--batched-steps", type=int, default=2)

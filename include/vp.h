@@ -135,6 +135,8 @@ typedef struct {
                               share of those blocks' rows that are pairs, not padding */
   int32_t fmm_terms;       /* expansion terms of the FMM far sum (0: direct sum) */
   int32_t fmm_levels;      /* quadtree levels below the root (leaf level) */
+  int64_t fmm_near_pairs;  /* target-source pairs the FMM sums directly (adjacent leaf boxes) */
+  int64_t fmm_m2l_pairs;   /* (target box, source box) M2L translations over all levels */
 } vp_plan_stats;
 
 /* Context on HIP device `device`.  `hip_stream_or_null` is a hipStream_t the

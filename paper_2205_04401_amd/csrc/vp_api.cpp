@@ -761,6 +761,8 @@ vp_status vp_plan_info(const vp_plan* pl, vp_plan_stats* out) {
   out->cluster_entries = pl->n_entries;
   out->fmm_terms = pl->fmm_terms;
   out->fmm_levels = pl->fmm_levels;
+  out->fmm_near_pairs = pl->fmm_near_pairs;
+  out->fmm_m2l_pairs = pl->fmm_m2l_pairs;
   return VP_OK;
 }
 

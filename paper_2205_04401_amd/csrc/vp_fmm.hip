@@ -601,6 +601,31 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
       }
   }
   for (int l = 0; l <= L; ++l) pl->fmm_off[l] = off[l];
+  // work counts: direct pairs of the adjacent leaf boxes, and M2L
+  // translations (target box with targets below, source box with sources)
+  pl->fmm_near_pairs = 0;
+  for (int iy = 0; iy < n; ++iy)
+    for (int ix = 0; ix < n; ++ix) {
+      const int64_t nt = hc[nleaf + (int64_t)iy * n + ix];
+      if (nt == 0) continue;
+      int64_t ns = 0;
+      for (int jy = std::max(iy - 1, 0); jy <= std::min(iy + 1, n - 1); ++jy)
+        for (int jx = std::max(ix - 1, 0); jx <= std::min(ix + 1, n - 1); ++jx) ns += hc[(int64_t)jy * n + jx];
+      pl->fmm_near_pairs += nt * ns;
+    }
+  pl->fmm_m2l_pairs = 0;
+  for (int l = 2; l <= L; ++l) {
+    const int m = 1 << l;
+    for (int iy = 0; iy < m; ++iy)
+      for (int ix = 0; ix < m; ++ix) {
+        if (ct[off[l] + (int64_t)iy * m + ix] == 0) continue;
+        for (int jy = std::max(iy - 3, 0); jy <= std::min(iy + 3, m - 1); ++jy)
+          for (int jx = std::max(ix - 3, 0); jx <= std::min(ix + 3, m - 1); ++jx)
+            if ((std::abs(jx - ix) > 1 || std::abs(jy - iy) > 1) && std::abs((jx >> 1) - (ix >> 1)) <= 1 &&
+                std::abs((jy >> 1) - (iy >> 1)) <= 1 && cs[off[l] + (int64_t)jy * m + jx] > 0)
+              ++pl->fmm_m2l_pairs;
+      }
+  }
   std::vector<double2> m2m, l2l, m2l;
   fmm_operators(p, m2m, l2l, m2l);
   pl->fmm_mp = (2 * (p + 1) + 15) / 16 * 16;

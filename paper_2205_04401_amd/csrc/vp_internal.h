@@ -384,6 +384,7 @@ struct vp_plan {
   double2 *fmm_m2m = nullptr, *fmm_l2l = nullptr;  // translation operators (complex)
   double* fmm_m2l = nullptr;                         // M2L operators, real form [49][fmm_mp][fmm_kp]
   int fmm_mp = 0, fmm_kp = 0;
+  int64_t fmm_near_pairs = 0, fmm_m2l_pairs = 0;  // work counts (plan statistics)
   // far-sum launch shapes stored for (n_rhs, precision) by the tuner or the caller
   std::map<std::pair<int64_t, int>, vp_far_config> far_tuned;
   double *ws_f = nullptr, *ws_c = nullptr, *ws_q = nullptr, *ws_part = nullptr, *ws_u = nullptr;

@@ -65,7 +65,8 @@ class PlanStats(ctypes.Structure):
                 ("bytes_resident", ctypes.c_int64), ("p", ctypes.c_int32), ("q", ctypes.c_int32),
                 ("n_p", ctypes.c_int32), ("n_f", ctypes.c_int32), ("eps", ctypes.c_double),
                 ("ms_classify", ctypes.c_double), ("ms_rows", ctypes.c_double), ("far_split", ctypes.c_int64),
-                ("cluster_entries", ctypes.c_int64), ("fmm_terms", ctypes.c_int32), ("fmm_levels", ctypes.c_int32)]
+                ("cluster_entries", ctypes.c_int64), ("fmm_terms", ctypes.c_int32), ("fmm_levels", ctypes.c_int32),
+                ("fmm_near_pairs", ctypes.c_int64), ("fmm_m2l_pairs", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
