@@ -338,6 +338,254 @@ __global__ __launch_bounds__(kBlock) void k_fmm_leaf(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Blocks of 16 densities.  The expansions of 16 right-hand sides are kept in
+// real form, [box][row][16] with rows 0..p the real parts of the
+// coefficients and p+1..2p+1 the imaginary parts (padded with zero rows),
+// so that P2M, M2L, L2P and the near-field sum all become products with 16
+// right-hand sides as the MFMA B-operand columns (v_mfma_f64_16x16x4f64;
+// lane l: A row l & 15, column l >> 4 of the step; B row l >> 4, column
+// l & 15; result element v: row (l >> 4) + 4 v, column l & 15).
+
+// Per plan: the P2M row of every source in leaf order, vsrc[j][0..MP) =
+// real and imaginary parts of (1, -t, -t^2/2, ..., -t^p/p), t = (w - c)/s
+// about its leaf centre; and the L2P row of every target in leaf order,
+// wtgt[i][0..KP) = 2 Re zh^l, then -2 Im zh^l (u = 2 Re sum b_l zh^l).
+__global__ void k_fmm_vsrc(const double2* __restrict__ sxy_s, int64_t n_src, double x0, double y0, double s, int L,
+                           int p, int MP, double* __restrict__ vsrc) {
+  const int n = 1 << L, P1 = p + 1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n_src; j += stride) {
+    const double2 w = sxy_s[j];
+    const uint32_t b = leaf_of(w.x, w.y, x0, y0, 1.0 / s, n);
+    const double cx = x0 + ((int)(b % n) + 0.5) * s, cy = y0 + ((int)(b / n) + 0.5) * s;
+    const double2 t = make_double2((w.x - cx) / s, (w.y - cy) / s);
+    double* v = vsrc + j * MP;
+    v[0] = 1.0;
+    v[P1] = 0.0;
+    double2 pw = t;
+    for (int m = 1; m <= p; ++m) {
+      v[m] = -pw.x / m;
+      v[P1 + m] = -pw.y / m;
+      pw = cmul(pw, t);
+    }
+    for (int r = 2 * P1; r < MP; ++r) v[r] = 0.0;
+  }
+}
+
+__global__ void k_fmm_wtgt(const double* __restrict__ xt, const double* __restrict__ yt,
+                           const int32_t* __restrict__ tperm, int64_t n_tgt, double x0, double y0, double s, int L,
+                           int p, int KP, double* __restrict__ wtgt) {
+  const int n = 1 << L, P1 = p + 1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_tgt; i += stride) {
+    const int64_t t = tperm[i];
+    const double x = xt[t], y = yt[t];
+    const uint32_t b = leaf_of(x, y, x0, y0, 1.0 / s, n);
+    const double cx = x0 + ((int)(b % n) + 0.5) * s, cy = y0 + ((int)(b / n) + 0.5) * s;
+    const double2 z = make_double2((x - cx) / s, (y - cy) / s);
+    double* w = wtgt + i * KP;
+    double2 zp = make_double2(1.0, 0.0);
+    for (int l = 0; l <= p; ++l) {
+      w[l] = 2.0 * zp.x;
+      w[P1 + l] = -2.0 * zp.y;
+      zp = cmul(zp, z);
+    }
+    for (int r = 2 * P1; r < KP; ++r) w[r] = 0.0;
+  }
+}
+
+// P2M of 16 densities (columns c0..c0+15): one wavefront per (leaf box, row
+// tile): rows of the real multipole = sum over the box's sources of
+// vsrc[j][row] Q[j][column].
+__global__ __launch_bounds__(kBlock) void k_fmmb_p2m(const double* __restrict__ vsrc, const int32_t* __restrict__ perm,
+                                                     const int64_t* __restrict__ ptr, const double* __restrict__ Q,
+                                                     int64_t R, int64_t c0, int64_t nleaf, int MP, int KP,
+                                                     double* __restrict__ Mb) {
+  const int tiles = MP / 16;
+  const int lane = (int)(threadIdx.x & 63), r16 = lane & 15, kq = lane >> 4;
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t b = w / tiles;
+  const int t = (int)(w - b * tiles);
+  if (b >= nleaf) return;  // the whole wavefront
+  const int64_t j0 = ptr[b], j1 = ptr[b + 1];
+  vp_d4 acc = vp_d4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t js = j0; js < j1; js += 4) {
+    const int64_t j = js + kq;
+    const bool ok = j < j1;
+    const int64_t jc = ok ? j : j0;
+    const double av = vsrc[jc * MP + 16 * t + r16];
+    const double bv = Q[(int64_t)perm[jc] * R + c0 + r16];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ok ? av : 0.0, ok ? bv : 0.0, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = 16 * t + kq + 4 * v;
+    if (row < KP) Mb[(b * KP + row) * 16 + r16] = acc[v];
+  }
+}
+
+// M2M / L2L of 16 densities in real form: one thread per (box, complex
+// coefficient m, column); M2M sums the 4 children (k <= m), L2L adds the
+// parent's expansion (k >= m) to the box's own.
+__global__ void k_fmmb_m2m(const double* __restrict__ Mc, const int32_t* __restrict__ cnt_c, int l, int p, int KP,
+                           const double2* __restrict__ m2m, double* __restrict__ Mp) {
+  const int P1 = p + 1, n = 1 << l;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)n * n * P1 * 16) return;
+  const int col = (int)(g & 15);
+  const int64_t bm = g >> 4;
+  const int64_t b = bm / P1;
+  const int m = (int)(bm - b * P1);
+  const int ix = (int)(b % n), iy = (int)(b / n);
+  double re = 0.0, im = 0.0;
+  for (int q = 0; q < 4; ++q) {
+    const int64_t c = (int64_t)(2 * iy + (q >> 1)) * (2 * n) + 2 * ix + (q & 1);
+    if (cnt_c[c] == 0) continue;
+    const double* a = Mc + c * KP * 16 + col;
+    const double2* T = m2m + ((int64_t)q * P1 + m) * P1;
+    for (int k = 0; k <= m; ++k) {
+      const double ar = a[k * 16], ai = a[(P1 + k) * 16];
+      re = fma(T[k].x, ar, fma(-T[k].y, ai, re));
+      im = fma(T[k].y, ar, fma(T[k].x, ai, im));
+    }
+  }
+  Mp[(b * KP + m) * 16 + col] = re;
+  Mp[(b * KP + P1 + m) * 16 + col] = im;
+  if (m == 0)
+    for (int r = 2 * P1; r < KP; ++r) Mp[(b * KP + r) * 16 + col] = 0.0;
+}
+
+__global__ void k_fmmb_l2l(const int32_t* __restrict__ cnt_t, const double* __restrict__ Lp, int l, int p, int KP,
+                           const double2* __restrict__ l2l, double* __restrict__ Lc) {
+  const int P1 = p + 1, n = 1 << l;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (int64_t)n * n * P1 * 16) return;
+  const int col = (int)(g & 15);
+  const int64_t bm = g >> 4;
+  const int64_t b = bm / P1;
+  const int m = (int)(bm - b * P1);
+  if (cnt_t[b] == 0) return;
+  const int ix = (int)(b % n), iy = (int)(b / n);
+  const int64_t pb = (int64_t)(iy >> 1) * (n >> 1) + (ix >> 1);
+  const int q = (ix & 1) | ((iy & 1) << 1);
+  const double* a = Lp + pb * KP * 16 + col;
+  const double2* T = l2l + ((int64_t)q * P1 + m) * P1;
+  double re = Lc[(b * KP + m) * 16 + col], im = Lc[(b * KP + P1 + m) * 16 + col];
+  for (int k = m; k < P1; ++k) {
+    const double ar = a[k * 16], ai = a[(P1 + k) * 16];
+    re = fma(T[k].x, ar, fma(-T[k].y, ai, re));
+    im = fma(T[k].y, ar, fma(T[k].x, ai, im));
+  }
+  Lc[(b * KP + m) * 16 + col] = re;
+  Lc[(b * KP + P1 + m) * 16 + col] = im;
+}
+
+// M2L of 16 densities: one wavefront per (box, row tile); the 16 columns
+// are the densities of the same box, so a whole offset is used or skipped.
+// The level's a_0 log s term is added per column to row 0.
+__global__ __launch_bounds__(kBlock) void k_fmmb_m2l(const double* __restrict__ Mb, const int32_t* __restrict__ cnt_s,
+                                                     const int32_t* __restrict__ cnt_t, int l, int MP, int KP,
+                                                     double log_s, const double* __restrict__ m2l,
+                                                     double* __restrict__ Lb) {
+  const int n = 1 << l;
+  const int64_t nb = (int64_t)n * n;
+  const int tiles = MP / 16;
+  const int lane = (int)(threadIdx.x & 63), r16 = lane & 15, kq = lane >> 4;
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t b = w / tiles;
+  const int t = (int)(w - b * tiles);
+  if (b >= nb) return;  // the whole wavefront
+  vp_d4 acc = vp_d4{0.0, 0.0, 0.0, 0.0};
+  double a0 = 0.0;
+  if (cnt_t[b] > 0) {
+    const int ix = (int)(b % n), iy = (int)(b / n);
+    for (int o = 0; o < 49; ++o) {
+      const int dy = o / 7 - 3, dx = o % 7 - 3;
+      const int jx = ix + dx, jy = iy + dy;
+      if ((abs(dx) <= 1 && abs(dy) <= 1) || jx < 0 || jx >= n || jy < 0 || jy >= n ||
+          abs((jx >> 1) - (ix >> 1)) > 1 || abs((jy >> 1) - (iy >> 1)) > 1)
+        continue;
+      const int64_t j = (int64_t)jy * n + jx;
+      if (cnt_s[j] == 0) continue;
+      const double* X = Mb + j * KP * 16 + r16;
+      a0 += X[0];
+      const double* A = m2l + ((int64_t)o * MP + 16 * t + r16) * KP;
+      for (int s4 = 0; s4 < KP / 4; ++s4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[4 * s4 + kq], X[(4 * s4 + kq) * 16], acc, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = 16 * t + kq + 4 * v;
+    double y = acc[v];
+    if (row == 0) y = fma(a0, log_s, y);
+    if (row < KP) Lb[(b * KP + row) * 16 + r16] = y;
+  }
+}
+
+// Leaf pass of 16 densities: one wavefront per (leaf box, 16 of its
+// targets): the local expansion (wtgt row x the box's local expansion) plus
+// the direct sum over the sources of the 3 x 3 adjacent boxes, both on the
+// matrix cores: A = G[target][source] = log(r^2 + 2^-100) generated by the
+// lanes (256-entry logarithm table in LDS), B = the sources' charges.
+__global__ __launch_bounds__(kBlock) void k_fmmb_leaf(
+    const double* __restrict__ Lb, const double* __restrict__ wtgt, const int2* __restrict__ ttile, int64_t n_tiles,
+    const double2* __restrict__ sxy_s, const int32_t* __restrict__ sperm, const int64_t* __restrict__ sptr,
+    const int32_t* __restrict__ tperm, const int64_t* __restrict__ tptr, const double* __restrict__ xt,
+    const double* __restrict__ yt, int L, int KP, const double2* __restrict__ logtab, const double* __restrict__ Q,
+    int64_t R, int64_t c0, double* __restrict__ out) {
+  __shared__ double2 tab[kLogTab + 1];
+  for (int i = threadIdx.x; i <= kLogTab; i += kBlock) tab[i] = logtab[i];
+  __syncthreads();
+  const int lane = (int)(threadIdx.x & 63), r16 = lane & 15, kq = lane >> 4;
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (w >= n_tiles) return;  // the whole wavefront
+  const int n = 1 << L;
+  const int2 tl = ttile[w];
+  const int64_t b = tl.x, i0 = tl.y, i1 = tptr[b + 1];
+  const int ix = (int)(b % n), iy = (int)(b / n);
+  const double2 l2 = tab[kLogTab];
+  // this lane's A-row target
+  const int64_t ia = i0 + r16;
+  const bool ta = ia < i1;
+  const int64_t tg = tperm[ta ? ia : i0];
+  const double x = xt[tg], y = yt[tg];
+  vp_d4 acc = vp_d4{0.0, 0.0, 0.0, 0.0};
+  // local expansion
+  const double* Xl = Lb + b * KP * 16 + r16;
+  const double* Wt = wtgt + (ta ? ia : i0) * KP;
+  for (int s4 = 0; s4 < KP / 4; ++s4) {
+    const int k = 4 * s4 + kq;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ta ? Wt[k] : 0.0, Xl[k * 16], acc, 0, 0, 0);
+  }
+  // adjacent boxes, row by row (consecutive boxes: one source range)
+  for (int dy = -1; dy <= 1; ++dy) {
+    const int jy = iy + dy;
+    if (jy < 0 || jy >= n) continue;
+    const int64_t row = (int64_t)jy * n;
+    const int64_t j0 = sptr[row + max(ix - 1, 0)], j1 = sptr[row + min(ix + 1, n - 1) + 1];
+    for (int64_t js = j0; js < j1; js += 4) {
+      const int64_t j = js + kq;
+      const bool ok = j < j1;
+      const int64_t jc = ok ? j : j0;
+      const double2 sw = sxy_s[jc];
+      const double ddx = x - sw.x, ddy = y - sw.y;
+      const double r2 = fma(ddy, ddy, fma(ddx, ddx, kR2Bias));
+      double e, rest;
+      vp_log_parts(r2, tab, e, rest);
+      const double g = fma(e, l2.x, fma(e, l2.y, rest));
+      const double qv = Q[(int64_t)sperm[jc] * R + c0 + r16];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ok && ta ? g : 0.0, ok ? qv : 0.0, acc, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t i = i0 + kq + 4 * v;
+    if (i < i1) out[(int64_t)tperm[i] * R + c0 + r16] = acc[v];
+  }
+}
+
 // Binomial coefficients up to n = 2 p in long double.
 std::vector<long double> binomials(int nmax) {
   std::vector<long double> c((size_t)(nmax + 1) * (nmax + 1), 0.0L);
@@ -455,8 +703,13 @@ int64_t fmm_boxes(int L) {
 
 int64_t fmm_workspace_doubles(const vp_plan* pl) {
   if (pl->fmm_terms <= 0) return 0;
-  // multipole and local coefficients (complex) of every box, charges in leaf order, 2 for alignment
-  return 2 * 2 * fmm_boxes(pl->fmm_levels) * (pl->fmm_terms + 1) + pl->n_src + 2;
+  const int64_t nbox = fmm_boxes(pl->fmm_levels);
+  // one density at a time: multipole and local coefficients (complex) of
+  // every box and the charges in leaf order; blocks of 16 densities: the
+  // real-form expansions [box][KP][16]; the two share the space; 2 for alignment
+  const int64_t one = 2 * 2 * nbox * (pl->fmm_terms + 1) + pl->n_src;
+  const int64_t blk = 2 * nbox * pl->fmm_kp * 16;
+  return std::max(one, blk) + 2;
 }
 
 hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
@@ -652,6 +905,26 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
       (e = hipMemcpyAsync(pl->fmm_m2l, m2l_r.data(), sizeof(double) * m2l_r.size(), hipMemcpyHostToDevice, st)) !=
           hipSuccess)
     return e;
+  // blocks of 16 densities: P2M rows of the sources, L2P rows of the
+  // targets, and the (leaf box, 16 targets) work list of the leaf pass
+  std::vector<int2> tiles;
+  for (int64_t b = 0; b < nleaf; ++b)
+    for (int64_t i = tp[b]; i < tp[b + 1]; i += 16) tiles.push_back(make_int2((int)b, (int)i));
+  pl->fmm_n_ttiles = (int64_t)tiles.size();
+  if ((e = alloc((void**)&pl->fmm_vsrc, sizeof(double) * NS * pl->fmm_mp)) != hipSuccess ||
+      (e = alloc((void**)&pl->fmm_wtgt, sizeof(double) * NT * pl->fmm_kp)) != hipSuccess ||
+      (e = alloc((void**)&pl->fmm_ttile, sizeof(int2) * std::max<size_t>(tiles.size(), 1))) != hipSuccess)
+    return e;
+  const double sL = w / n;
+  k_fmm_vsrc<<<blocks_for(NS), kBlock, 0, st>>>(pl->fmm_sxy, NS, pl->fmm_x0, pl->fmm_y0, sL, L, p, pl->fmm_mp,
+                                                pl->fmm_vsrc);
+  k_fmm_wtgt<<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, pl->fmm_tgt_perm, NT, pl->fmm_x0, pl->fmm_y0, sL, L, p,
+                                                pl->fmm_kp, pl->fmm_wtgt);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (!tiles.empty() &&
+      (e = hipMemcpyAsync(pl->fmm_ttile, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, st)) !=
+          hipSuccess)
+    return e;
   return hipStreamSynchronize(st);  // the host vectors above go out of scope
 }
 
@@ -669,7 +942,41 @@ hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out
   const int n = 1 << L;
   const int64_t nleaf = (int64_t)n * n;
   const double sL = pl->fmm_width / n;
-  for (int64_t r = 0; r < R; ++r) {
+  // blocks of 16 densities on the matrix cores
+  const int MP = pl->fmm_mp, KP = pl->fmm_kp, tiles = MP / 16;
+  double* Mb = (double*)Mall;
+  double* Lb = Mb + nbox * KP * 16;
+  const int64_t nblk = R / 16;
+  for (int64_t cb = 0; cb < nblk; ++cb) {
+    const int64_t c0 = 16 * cb;
+    k_fmmb_p2m<<<(unsigned)((nleaf * tiles * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        pl->fmm_vsrc, pl->fmm_src_perm, pl->fmm_src_ptr, Q, R, c0, nleaf, MP, KP, Mb + pl->fmm_off[L] * KP * 16);
+    for (int l = L - 1; l >= 2; --l) {
+      const int64_t nt = ((int64_t)1 << (2 * l)) * P1 * 16;
+      k_fmmb_m2m<<<blocks_for(nt), kBlock, 0, st>>>(Mb + pl->fmm_off[l + 1] * KP * 16,
+                                                    pl->fmm_cnt_src + pl->fmm_off[l + 1], l, p, KP, pl->fmm_m2m,
+                                                    Mb + pl->fmm_off[l] * KP * 16);
+    }
+    for (int l = 2; l <= L; ++l) {
+      const int64_t nbl = (int64_t)1 << (2 * l);
+      const double log_s = std::log(pl->fmm_width / (double)(1 << l));
+      k_fmmb_m2l<<<(unsigned)((nbl * tiles * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+          Mb + pl->fmm_off[l] * KP * 16, pl->fmm_cnt_src + pl->fmm_off[l], pl->fmm_cnt_tgt + pl->fmm_off[l], l, MP,
+          KP, log_s, pl->fmm_m2l, Lb + pl->fmm_off[l] * KP * 16);
+      if (l > 2)
+        k_fmmb_l2l<<<blocks_for(nbl * P1 * 16), kBlock, 0, st>>>(pl->fmm_cnt_tgt + pl->fmm_off[l],
+                                                                Lb + pl->fmm_off[l - 1] * KP * 16, l, p, KP,
+                                                                pl->fmm_l2l, Lb + pl->fmm_off[l] * KP * 16);
+    }
+    if (pl->fmm_n_ttiles > 0)
+      k_fmmb_leaf<<<(unsigned)((pl->fmm_n_ttiles * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+          Lb + pl->fmm_off[L] * KP * 16, pl->fmm_wtgt, pl->fmm_ttile, pl->fmm_n_ttiles, pl->fmm_sxy,
+          pl->fmm_src_perm, pl->fmm_src_ptr, pl->fmm_tgt_perm, pl->fmm_tgt_ptr, pl->xt, pl->yt, L, KP, pl->logtab, Q,
+          R, c0, out);
+    if (n_launches) *n_launches += 3 * L - 2;
+  }
+  // the remaining densities one at a time
+  for (int64_t r = 16 * nblk; r < R; ++r) {
     k_fmm_p2m<<<(unsigned)((nleaf * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
         pl->fmm_sxy, pl->fmm_src_perm, pl->fmm_src_ptr, Q, R, r, L, pl->fmm_x0, pl->fmm_y0, sL, p,
         Mall + pl->fmm_off[L] * P1, Qs);

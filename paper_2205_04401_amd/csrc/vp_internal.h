@@ -385,6 +385,11 @@ struct vp_plan {
   double* fmm_m2l = nullptr;                         // M2L operators, real form [49][fmm_mp][fmm_kp]
   int fmm_mp = 0, fmm_kp = 0;
   int64_t fmm_near_pairs = 0, fmm_m2l_pairs = 0;  // work counts (plan statistics)
+  // blocks of 16 densities: P2M rows [n_src][fmm_mp], L2P rows [n_tgt][fmm_kp]
+  // (both in leaf order), (leaf box, first target) of every 16-target tile
+  double *fmm_vsrc = nullptr, *fmm_wtgt = nullptr;
+  int2* fmm_ttile = nullptr;
+  int64_t fmm_n_ttiles = 0;
   // far-sum launch shapes stored for (n_rhs, precision) by the tuner or the caller
   std::map<std::pair<int64_t, int>, vp_far_config> far_tuned;
   double *ws_f = nullptr, *ws_c = nullptr, *ws_q = nullptr, *ws_part = nullptr, *ws_u = nullptr;

@@ -152,6 +152,35 @@ def test_fmm_star_matches_direct_sum(vp_ctx, terms, leaf):
     mesh.close()
 
 
+def test_fmm_star_blocks_of_16_densities(vp_ctx):
+    """33 densities on a 3000-triangle star: two blocks of 16 on the matrix
+    cores (P2M, M2L, L2P and the near-field sum as products with 16
+    densities as columns) and one density alone; every column's far sum
+    equals the direct far sum to <= 1e-13, and the potentials equal the
+    one-density FMM evaluations."""
+    p, q, eps = 6, 6, 1e-13
+    vq, tq = W.star_mesh(n_tri=3000, n_boundary=300, seed=43)
+    vt, tt = W.star_mesh(n_tri=3000, n_boundary=300, seed=143, staggered=True)
+    nodes = rules.interp_nodes(p)
+    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    R = 33
+    FR = np.ascontiguousarray(np.stack([W.sample_density(W.gaussian_sum(500 + r, vq, tq), vq, tq, nodes)
+                                        for r in range(R)], -1))
+    mesh = vp_ctx.mesh(vq, tq)
+    fmm = vp_ctx.plan(mesh, p, q, eps, tg, fmm_terms=40, fmm_leaf=64)
+    direct = vp_ctx.plan(mesh, p, q, eps, tg)
+    uf = fmm.execute(FR, far_only=True)
+    ud = direct.execute(FR, far_only=True)
+    e = rel_linf(uf, ud)
+    u = fmm.execute(FR)
+    e1 = max(rel_linf(u[:, r], fmm.execute(np.ascontiguousarray(FR[:, :, r]))) for r in (0, 15, 16, 31, 32))
+    say("fmm star 33 densities: far rel vs direct", e, "potential rel vs one-density FMM", e1)
+    assert e <= REL_FAR and e1 <= REL_FAR
+    fmm.close()
+    direct.close()
+    mesh.close()
+
+
 def test_fmm_option_errors(square, vp_ctx):
     from paper_2205_04401_amd import vp
     for terms, leaf in ((5, 128), (64, 128), (40, 4), (40, 5000)):
