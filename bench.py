@@ -111,6 +111,27 @@ def batched(ctx, mesh, tg_d, vq, tq, p, q, R, steps):
             "breakdown_ms": {k: v[0] / steps for k, v in tm.items() if v[1]},
         })
         print(json.dumps({"batched": out[-1]}), flush=True)
+    # the same densities with the far sum by the FMM (blocks of 16 densities
+    # on the matrix cores), FP64
+    plan = ctx.plan(mesh, p, q, 1e-13, tg_d, fmm_terms=32, fmm_leaf=64)
+    info = plan.info()
+    u = torch.empty((info["n_tgt"], R), dtype=torch.float64, device="cuda:0")
+    plan.execute(FR_d, out=u)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.execute(FR_d, out=u)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    tm = ctx.timings()
+    ctx.profile(False)
+    plan.close()
+    out.append({"precision": "fp64", "far": "fmm", "fmm_terms": info["fmm_terms"], "fmm_levels": info["fmm_levels"],
+                "plan_eps": 1e-13, "n_rhs": R, "evals_per_s": info["n_tgt"] * R / dt, "ms_per_execute": dt * 1e3,
+                "plan_ms": info["ms_classify"] + info["ms_rows"],
+                "breakdown_ms": {k: v[0] / steps for k, v in tm.items() if v[1]}})
+    print(json.dumps({"batched": out[-1]}), flush=True)
     return out
 
 
@@ -426,6 +447,7 @@ def run(args):
     if not args.no_serving:
         from paper_2205_04401_amd import serving
         result["serving"] = [serving.run(ctx, n_requests=args.serving_requests, mixed=m) for m in (False, True)]
+        result["serving"].append(serving.run(ctx, n_requests=args.serving_requests, mixed=False, fmm_terms=32))
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(vq, tq, tg, F, p, q, eps, args.cpu_sample)
     mesh.close()

@@ -21,7 +21,7 @@ from . import workloads as W
 
 
 def build_workload(ctx, n_meshes=4, tri_range=(1000, 8000), q=6, eps=1e-13, seed=40, n_requests=300,
-                   max_rhs=32, device="cuda:0"):
+                   max_rhs=32, device="cuda:0", fmm_terms=0):
     """Meshes (log-uniform triangle counts), plans (p = 4 or 6 per mesh) and
     a request list (mesh, R, density tensor).  Returns a dict."""
     import torch
@@ -35,7 +35,7 @@ def build_workload(ctx, n_meshes=4, tri_range=(1000, 8000), q=6, eps=1e-13, seed
         nodes = vp.ref_nodes(int(p))
         tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
         mesh = ctx.mesh(vq, tq)
-        plan = ctx.plan(mesh, int(p), q, eps, tg)
+        plan = ctx.plan(mesh, int(p), q, eps, tg, **({"fmm_terms": fmm_terms, "fmm_leaf": 64} if fmm_terms else {}))
         meshes.append(dict(vq=vq, tq=tq, tg=tg, p=int(p), nodes=nodes, mesh=mesh, plan=plan))
     reqs = []
     for i in range(n_requests):
@@ -106,6 +106,7 @@ def run(ctx, n_requests=300, mixed=False, eps=None, n_slots=4, max_batch_rhs=32,
         m["mesh"].close()
     return {
         "precision": "mixed" if mixed else "fp64",
+        "far": "fmm" if kw.get("fmm_terms") else "direct",
         "plan_eps": eps,
         "requests": len(wl["reqs"]),
         "meshes": [int(m["plan"].n_tri) for m in wl["meshes"]],
