@@ -834,7 +834,7 @@ vp_far_config far_for_shape(const vp_plan* pl, int64_t R, bool mixed, int shape,
 }  // namespace
 
 int64_t vp::far_partial_doubles(const vp_plan* pl, int64_t n_split, int64_t R) {
-  return n_split * pl->n_tgt * R + fmm_workspace_doubles(pl);
+  return n_split * pl->n_tgt * R + fmm_workspace_doubles(pl, R);
 }
 
 vp_far_config vp::far_default(const vp_plan* pl, int64_t R, bool mixed) {

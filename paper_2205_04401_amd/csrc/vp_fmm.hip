@@ -395,13 +395,19 @@ __global__ void k_fmm_wtgt(const double* __restrict__ xt, const double* __restri
   }
 }
 
-// P2M of 16 densities (columns c0..c0+15): one wavefront per (leaf box, row
-// tile): rows of the real multipole = sum over the box's sources of
-// vsrc[j][row] Q[j][column].
+// The passes below take NB blocks of 16 densities at once (columns
+// c0 .. c0 + 16 NB - 1, C = 16 NB columns in the real-form expansions
+// [box][KP][C]): every A operand (P2M rows, M2L operator rows, L2P rows,
+// the generated G) then serves NB MFMA steps, one per block of columns.
+
+// P2M: one wavefront per (leaf box, row tile): rows of the real multipole =
+// sum over the box's sources of vsrc[j][row] Q[j][column].
+template <int NB>
 __global__ __launch_bounds__(kBlock) void k_fmmb_p2m(const double* __restrict__ vsrc, const int32_t* __restrict__ perm,
                                                      const int64_t* __restrict__ ptr, const double* __restrict__ Q,
                                                      int64_t R, int64_t c0, int64_t nleaf, int MP, int KP,
                                                      double* __restrict__ Mb) {
+  constexpr int C = 16 * NB;
   const int tiles = MP / 16;
   const int lane = (int)(threadIdx.x & 63), r16 = lane & 15, kq = lane >> 4;
   const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -409,32 +415,38 @@ __global__ __launch_bounds__(kBlock) void k_fmmb_p2m(const double* __restrict__ 
   const int t = (int)(w - b * tiles);
   if (b >= nleaf) return;  // the whole wavefront
   const int64_t j0 = ptr[b], j1 = ptr[b + 1];
-  vp_d4 acc = vp_d4{0.0, 0.0, 0.0, 0.0};
+  vp_d4 acc[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) acc[u] = vp_d4{0.0, 0.0, 0.0, 0.0};
   for (int64_t js = j0; js < j1; js += 4) {
     const int64_t j = js + kq;
     const bool ok = j < j1;
     const int64_t jc = ok ? j : j0;
-    const double av = vsrc[jc * MP + 16 * t + r16];
-    const double bv = Q[(int64_t)perm[jc] * R + c0 + r16];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ok ? av : 0.0, ok ? bv : 0.0, acc, 0, 0, 0);
+    const double av = ok ? vsrc[jc * MP + 16 * t + r16] : 0.0;
+    const double* q = Q + (int64_t)perm[jc] * R + c0 + r16;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, ok ? q[16 * u] : 0.0, acc[u], 0, 0, 0);
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int row = 16 * t + kq + 4 * v;
-    if (row < KP) Mb[(b * KP + row) * 16 + r16] = acc[v];
+    if (row < KP) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u) Mb[(b * KP + row) * C + 16 * u + r16] = acc[u][v];
+    }
   }
 }
 
-// M2M / L2L of 16 densities in real form: one thread per (box, complex
-// coefficient m, column); M2M sums the 4 children (k <= m), L2L adds the
-// parent's expansion (k >= m) to the box's own.
-__global__ void k_fmmb_m2m(const double* __restrict__ Mc, const int32_t* __restrict__ cnt_c, int l, int p, int KP,
+// M2M / L2L in real form: one thread per (box, complex coefficient m,
+// column); M2M sums the 4 children (k <= m), L2L adds the parent's
+// expansion (k >= m) to the box's own.
+__global__ void k_fmmb_m2m(const double* __restrict__ Mc, const int32_t* __restrict__ cnt_c, int l, int p, int KP, int C,
                            const double2* __restrict__ m2m, double* __restrict__ Mp) {
   const int P1 = p + 1, n = 1 << l;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= (int64_t)n * n * P1 * 16) return;
-  const int col = (int)(g & 15);
-  const int64_t bm = g >> 4;
+  if (g >= (int64_t)n * n * P1 * C) return;
+  const int col = (int)(g % C);
+  const int64_t bm = g / C;
   const int64_t b = bm / P1;
   const int m = (int)(bm - b * P1);
   const int ix = (int)(b % n), iy = (int)(b / n);
@@ -442,52 +454,54 @@ __global__ void k_fmmb_m2m(const double* __restrict__ Mc, const int32_t* __restr
   for (int q = 0; q < 4; ++q) {
     const int64_t c = (int64_t)(2 * iy + (q >> 1)) * (2 * n) + 2 * ix + (q & 1);
     if (cnt_c[c] == 0) continue;
-    const double* a = Mc + c * KP * 16 + col;
+    const double* a = Mc + c * KP * C + col;
     const double2* T = m2m + ((int64_t)q * P1 + m) * P1;
     for (int k = 0; k <= m; ++k) {
-      const double ar = a[k * 16], ai = a[(P1 + k) * 16];
+      const double ar = a[k * C], ai = a[(P1 + k) * C];
       re = fma(T[k].x, ar, fma(-T[k].y, ai, re));
       im = fma(T[k].y, ar, fma(T[k].x, ai, im));
     }
   }
-  Mp[(b * KP + m) * 16 + col] = re;
-  Mp[(b * KP + P1 + m) * 16 + col] = im;
+  Mp[(b * KP + m) * C + col] = re;
+  Mp[(b * KP + P1 + m) * C + col] = im;
   if (m == 0)
-    for (int r = 2 * P1; r < KP; ++r) Mp[(b * KP + r) * 16 + col] = 0.0;
+    for (int r = 2 * P1; r < KP; ++r) Mp[(b * KP + r) * C + col] = 0.0;
 }
 
 __global__ void k_fmmb_l2l(const int32_t* __restrict__ cnt_t, const double* __restrict__ Lp, int l, int p, int KP,
-                           const double2* __restrict__ l2l, double* __restrict__ Lc) {
+                           int C, const double2* __restrict__ l2l, double* __restrict__ Lc) {
   const int P1 = p + 1, n = 1 << l;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= (int64_t)n * n * P1 * 16) return;
-  const int col = (int)(g & 15);
-  const int64_t bm = g >> 4;
+  if (g >= (int64_t)n * n * P1 * C) return;
+  const int col = (int)(g % C);
+  const int64_t bm = g / C;
   const int64_t b = bm / P1;
   const int m = (int)(bm - b * P1);
   if (cnt_t[b] == 0) return;
   const int ix = (int)(b % n), iy = (int)(b / n);
   const int64_t pb = (int64_t)(iy >> 1) * (n >> 1) + (ix >> 1);
   const int q = (ix & 1) | ((iy & 1) << 1);
-  const double* a = Lp + pb * KP * 16 + col;
+  const double* a = Lp + pb * KP * C + col;
   const double2* T = l2l + ((int64_t)q * P1 + m) * P1;
-  double re = Lc[(b * KP + m) * 16 + col], im = Lc[(b * KP + P1 + m) * 16 + col];
+  double re = Lc[(b * KP + m) * C + col], im = Lc[(b * KP + P1 + m) * C + col];
   for (int k = m; k < P1; ++k) {
-    const double ar = a[k * 16], ai = a[(P1 + k) * 16];
+    const double ar = a[k * C], ai = a[(P1 + k) * C];
     re = fma(T[k].x, ar, fma(-T[k].y, ai, re));
     im = fma(T[k].y, ar, fma(T[k].x, ai, im));
   }
-  Lc[(b * KP + m) * 16 + col] = re;
-  Lc[(b * KP + P1 + m) * 16 + col] = im;
+  Lc[(b * KP + m) * C + col] = re;
+  Lc[(b * KP + P1 + m) * C + col] = im;
 }
 
-// M2L of 16 densities: one wavefront per (box, row tile); the 16 columns
-// are the densities of the same box, so a whole offset is used or skipped.
-// The level's a_0 log s term is added per column to row 0.
+// M2L: one wavefront per (box, row tile); all columns belong to the same
+// box, so a whole offset is used or skipped.  The level's a_0 log s term
+// is added per column to row 0.
+template <int NB>
 __global__ __launch_bounds__(kBlock) void k_fmmb_m2l(const double* __restrict__ Mb, const int32_t* __restrict__ cnt_s,
                                                      const int32_t* __restrict__ cnt_t, int l, int MP, int KP,
                                                      double log_s, const double* __restrict__ m2l,
                                                      double* __restrict__ Lb) {
+  constexpr int C = 16 * NB;
   const int n = 1 << l;
   const int64_t nb = (int64_t)n * n;
   const int tiles = MP / 16;
@@ -496,8 +510,13 @@ __global__ __launch_bounds__(kBlock) void k_fmmb_m2l(const double* __restrict__ 
   const int64_t b = w / tiles;
   const int t = (int)(w - b * tiles);
   if (b >= nb) return;  // the whole wavefront
-  vp_d4 acc = vp_d4{0.0, 0.0, 0.0, 0.0};
-  double a0 = 0.0;
+  vp_d4 acc[NB];
+  double a0[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    acc[u] = vp_d4{0.0, 0.0, 0.0, 0.0};
+    a0[u] = 0.0;
+  }
   if (cnt_t[b] > 0) {
     const int ix = (int)(b % n), iy = (int)(b / n);
     for (int o = 0; o < 49; ++o) {
@@ -508,33 +527,46 @@ __global__ __launch_bounds__(kBlock) void k_fmmb_m2l(const double* __restrict__ 
         continue;
       const int64_t j = (int64_t)jy * n + jx;
       if (cnt_s[j] == 0) continue;
-      const double* X = Mb + j * KP * 16 + r16;
-      a0 += X[0];
+      const double* X = Mb + j * KP * C + r16;
+#pragma unroll
+      for (int u = 0; u < NB; ++u) a0[u] += X[16 * u];
       const double* A = m2l + ((int64_t)o * MP + 16 * t + r16) * KP;
-      for (int s4 = 0; s4 < KP / 4; ++s4)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[4 * s4 + kq], X[(4 * s4 + kq) * 16], acc, 0, 0, 0);
+      for (int s4 = 0; s4 < KP / 4; ++s4) {
+        const double av = A[4 * s4 + kq];
+        const double* x = X + (int64_t)(4 * s4 + kq) * C;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, x[16 * u], acc[u], 0, 0, 0);
+      }
     }
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int row = 16 * t + kq + 4 * v;
-    double y = acc[v];
-    if (row == 0) y = fma(a0, log_s, y);
-    if (row < KP) Lb[(b * KP + row) * 16 + r16] = y;
+    if (row < KP) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u) {
+        double y = acc[u][v];
+        if (row == 0) y = fma(a0[u], log_s, y);
+        Lb[(b * KP + row) * C + 16 * u + r16] = y;
+      }
+    }
   }
 }
 
-// Leaf pass of 16 densities: one wavefront per (leaf box, 16 of its
-// targets): the local expansion (wtgt row x the box's local expansion) plus
-// the direct sum over the sources of the 3 x 3 adjacent boxes, both on the
-// matrix cores: A = G[target][source] = log(r^2 + 2^-100) generated by the
-// lanes (256-entry logarithm table in LDS), B = the sources' charges.
+// Leaf pass: one wavefront per (leaf box, 16 of its targets): the local
+// expansion (wtgt row x the box's local expansion) plus the direct sum over
+// the sources of the 3 x 3 adjacent boxes, both on the matrix cores:
+// A = G[target][source] = log(r^2 + 2^-100) generated by the lanes
+// (256-entry logarithm table in LDS) once for all NB blocks, B = the
+// sources' charges.
+template <int NB>
 __global__ __launch_bounds__(kBlock) void k_fmmb_leaf(
     const double* __restrict__ Lb, const double* __restrict__ wtgt, const int2* __restrict__ ttile, int64_t n_tiles,
     const double2* __restrict__ sxy_s, const int32_t* __restrict__ sperm, const int64_t* __restrict__ sptr,
     const int32_t* __restrict__ tperm, const int64_t* __restrict__ tptr, const double* __restrict__ xt,
     const double* __restrict__ yt, int L, int KP, const double2* __restrict__ logtab, const double* __restrict__ Q,
     int64_t R, int64_t c0, double* __restrict__ out) {
+  constexpr int C = 16 * NB;
   __shared__ double2 tab[kLogTab + 1];
   for (int i = threadIdx.x; i <= kLogTab; i += kBlock) tab[i] = logtab[i];
   __syncthreads();
@@ -551,13 +583,17 @@ __global__ __launch_bounds__(kBlock) void k_fmmb_leaf(
   const bool ta = ia < i1;
   const int64_t tg = tperm[ta ? ia : i0];
   const double x = xt[tg], y = yt[tg];
-  vp_d4 acc = vp_d4{0.0, 0.0, 0.0, 0.0};
+  vp_d4 acc[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) acc[u] = vp_d4{0.0, 0.0, 0.0, 0.0};
   // local expansion
-  const double* Xl = Lb + b * KP * 16 + r16;
+  const double* Xl = Lb + b * KP * C + r16;
   const double* Wt = wtgt + (ta ? ia : i0) * KP;
   for (int s4 = 0; s4 < KP / 4; ++s4) {
     const int k = 4 * s4 + kq;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ta ? Wt[k] : 0.0, Xl[k * 16], acc, 0, 0, 0);
+    const double av = ta ? Wt[k] : 0.0;
+#pragma unroll
+    for (int u = 0; u < NB; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Xl[k * C + 16 * u], acc[u], 0, 0, 0);
   }
   // adjacent boxes, row by row (consecutive boxes: one source range)
   for (int dy = -1; dy <= 1; ++dy) {
@@ -574,15 +610,20 @@ __global__ __launch_bounds__(kBlock) void k_fmmb_leaf(
       const double r2 = fma(ddy, ddy, fma(ddx, ddx, kR2Bias));
       double e, rest;
       vp_log_parts(r2, tab, e, rest);
-      const double g = fma(e, l2.x, fma(e, l2.y, rest));
-      const double qv = Q[(int64_t)sperm[jc] * R + c0 + r16];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ok && ta ? g : 0.0, ok ? qv : 0.0, acc, 0, 0, 0);
+      const double g = (ok && ta) ? fma(e, l2.x, fma(e, l2.y, rest)) : 0.0;
+      const double* q = Q + (int64_t)sperm[jc] * R + c0 + r16;
+#pragma unroll
+      for (int u = 0; u < NB; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(g, ok ? q[16 * u] : 0.0, acc[u], 0, 0, 0);
     }
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int64_t i = i0 + kq + 4 * v;
-    if (i < i1) out[(int64_t)tperm[i] * R + c0 + r16] = acc[v];
+    if (i < i1) {
+      const int64_t o = (int64_t)tperm[i] * R + c0 + r16;
+#pragma unroll
+      for (int u = 0; u < NB; ++u) out[o + 16 * u] = acc[u][v];
+    }
   }
 }
 
@@ -701,14 +742,16 @@ int64_t fmm_boxes(int L) {
   return n;
 }
 
-int64_t fmm_workspace_doubles(const vp_plan* pl) {
+int64_t fmm_workspace_doubles(const vp_plan* pl, int64_t R) {
   if (pl->fmm_terms <= 0) return 0;
   const int64_t nbox = fmm_boxes(pl->fmm_levels);
   // one density at a time: multipole and local coefficients (complex) of
-  // every box and the charges in leaf order; blocks of 16 densities: the
-  // real-form expansions [box][KP][16]; the two share the space; 2 for alignment
+  // every box and the charges in leaf order; passes of 16, 32 or 64
+  // densities: the real-form expansions [box][KP][16 NB]; they share the
+  // space; 2 for alignment
   const int64_t one = 2 * 2 * nbox * (pl->fmm_terms + 1) + pl->n_src;
-  const int64_t blk = 2 * nbox * pl->fmm_kp * 16;
+  const int64_t cols = R >= 64 ? 64 : R >= 32 ? 32 : R >= 16 ? 16 : 0;
+  const int64_t blk = 2 * nbox * pl->fmm_kp * cols;
   return std::max(one, blk) + 2;
 }
 
@@ -942,41 +985,49 @@ hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out
   const int n = 1 << L;
   const int64_t nleaf = (int64_t)n * n;
   const double sL = pl->fmm_width / n;
-  // blocks of 16 densities on the matrix cores
+  // blocks of 16 densities on the matrix cores, up to 4 blocks per pass
   const int MP = pl->fmm_mp, KP = pl->fmm_kp, tiles = MP / 16;
-  double* Mb = (double*)Mall;
-  double* Lb = Mb + nbox * KP * 16;
-  const int64_t nblk = R / 16;
-  for (int64_t cb = 0; cb < nblk; ++cb) {
-    const int64_t c0 = 16 * cb;
-    k_fmmb_p2m<<<(unsigned)((nleaf * tiles * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-        pl->fmm_vsrc, pl->fmm_src_perm, pl->fmm_src_ptr, Q, R, c0, nleaf, MP, KP, Mb + pl->fmm_off[L] * KP * 16);
-    for (int l = L - 1; l >= 2; --l) {
-      const int64_t nt = ((int64_t)1 << (2 * l)) * P1 * 16;
-      k_fmmb_m2m<<<blocks_for(nt), kBlock, 0, st>>>(Mb + pl->fmm_off[l + 1] * KP * 16,
-                                                    pl->fmm_cnt_src + pl->fmm_off[l + 1], l, p, KP, pl->fmm_m2m,
-                                                    Mb + pl->fmm_off[l] * KP * 16);
+  int64_t c0 = 0;
+  while (R - c0 >= 16) {
+    const int nbk = R - c0 >= 64 ? 4 : R - c0 >= 32 ? 2 : 1;
+    const int C = 16 * nbk;
+    double* Mb = (double*)Mall;
+    double* Lb = Mb + nbox * KP * C;
+#define VP_FMMB(NBV)                                                                                              \
+  k_fmmb_p2m<NBV><<<(unsigned)((nleaf * tiles * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(                      \
+      pl->fmm_vsrc, pl->fmm_src_perm, pl->fmm_src_ptr, Q, R, c0, nleaf, MP, KP, Mb + pl->fmm_off[L] * KP * C);     \
+  for (int l = L - 1; l >= 2; --l) {                                                                              \
+    const int64_t nt = ((int64_t)1 << (2 * l)) * P1 * C;                                                           \
+    k_fmmb_m2m<<<blocks_for(nt), kBlock, 0, st>>>(Mb + pl->fmm_off[l + 1] * KP * C,                                 \
+                                                  pl->fmm_cnt_src + pl->fmm_off[l + 1], l, p, KP, C, pl->fmm_m2m,   \
+                                                  Mb + pl->fmm_off[l] * KP * C);                                    \
+  }                                                                                                               \
+  for (int l = 2; l <= L; ++l) {                                                                                  \
+    const int64_t nbl = (int64_t)1 << (2 * l);                                                                     \
+    const double log_s = std::log(pl->fmm_width / (double)(1 << l));                                              \
+    k_fmmb_m2l<NBV><<<(unsigned)((nbl * tiles * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(                      \
+        Mb + pl->fmm_off[l] * KP * C, pl->fmm_cnt_src + pl->fmm_off[l], pl->fmm_cnt_tgt + pl->fmm_off[l], l, MP, KP, \
+        log_s, pl->fmm_m2l, Lb + pl->fmm_off[l] * KP * C);                                                          \
+    if (l > 2)                                                                                                    \
+      k_fmmb_l2l<<<blocks_for(nbl * P1 * C), kBlock, 0, st>>>(pl->fmm_cnt_tgt + pl->fmm_off[l],                     \
+                                                             Lb + pl->fmm_off[l - 1] * KP * C, l, p, KP, C,          \
+                                                             pl->fmm_l2l, Lb + pl->fmm_off[l] * KP * C);             \
+  }                                                                                                               \
+  if (pl->fmm_n_ttiles > 0)                                                                                       \
+    k_fmmb_leaf<NBV><<<(unsigned)((pl->fmm_n_ttiles * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(                 \
+        Lb + pl->fmm_off[L] * KP * C, pl->fmm_wtgt, pl->fmm_ttile, pl->fmm_n_ttiles, pl->fmm_sxy, pl->fmm_src_perm,  \
+        pl->fmm_src_ptr, pl->fmm_tgt_perm, pl->fmm_tgt_ptr, pl->xt, pl->yt, L, KP, pl->logtab, Q, R, c0, out)
+    switch (nbk) {
+      case 4: VP_FMMB(4); break;
+      case 2: VP_FMMB(2); break;
+      default: VP_FMMB(1); break;
     }
-    for (int l = 2; l <= L; ++l) {
-      const int64_t nbl = (int64_t)1 << (2 * l);
-      const double log_s = std::log(pl->fmm_width / (double)(1 << l));
-      k_fmmb_m2l<<<(unsigned)((nbl * tiles * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-          Mb + pl->fmm_off[l] * KP * 16, pl->fmm_cnt_src + pl->fmm_off[l], pl->fmm_cnt_tgt + pl->fmm_off[l], l, MP,
-          KP, log_s, pl->fmm_m2l, Lb + pl->fmm_off[l] * KP * 16);
-      if (l > 2)
-        k_fmmb_l2l<<<blocks_for(nbl * P1 * 16), kBlock, 0, st>>>(pl->fmm_cnt_tgt + pl->fmm_off[l],
-                                                                Lb + pl->fmm_off[l - 1] * KP * 16, l, p, KP,
-                                                                pl->fmm_l2l, Lb + pl->fmm_off[l] * KP * 16);
-    }
-    if (pl->fmm_n_ttiles > 0)
-      k_fmmb_leaf<<<(unsigned)((pl->fmm_n_ttiles * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-          Lb + pl->fmm_off[L] * KP * 16, pl->fmm_wtgt, pl->fmm_ttile, pl->fmm_n_ttiles, pl->fmm_sxy,
-          pl->fmm_src_perm, pl->fmm_src_ptr, pl->fmm_tgt_perm, pl->fmm_tgt_ptr, pl->xt, pl->yt, L, KP, pl->logtab, Q,
-          R, c0, out);
+#undef VP_FMMB
     if (n_launches) *n_launches += 3 * L - 2;
+    c0 += C;
   }
   // the remaining densities one at a time
-  for (int64_t r = 16 * nblk; r < R; ++r) {
+  for (int64_t r = c0; r < R; ++r) {
     k_fmm_p2m<<<(unsigned)((nleaf * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
         pl->fmm_sxy, pl->fmm_src_perm, pl->fmm_src_ptr, Q, R, r, L, pl->fmm_x0, pl->fmm_y0, sL, p,
         Mall + pl->fmm_off[L] * P1, Qs);

@@ -439,7 +439,7 @@ bool far_config_valid(const vp_plan* pl, const vp_far_config& cfg);
 // then the FMM's expansions and leaf-ordered charges
 int64_t far_partial_doubles(const vp_plan* pl, int64_t n_split, int64_t R);
 int64_t fmm_boxes(int levels);
-int64_t fmm_workspace_doubles(const vp_plan* pl);
+int64_t fmm_workspace_doubles(const vp_plan* pl, int64_t R);
 hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st);  // after sources and targets; plan memory
 hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out, double* ws, hipStream_t st,
                       int64_t* n_launches);

@@ -153,19 +153,20 @@ def test_fmm_star_matches_direct_sum(vp_ctx, terms, leaf):
 
 
 def test_fmm_star_blocks_of_16_densities(vp_ctx):
-    """33 densities on a 3000-triangle star: two blocks of 16 on the matrix
-    cores (P2M, M2L, L2P and the near-field sum as products with 16
-    densities as columns) and one density alone; every column's far sum
-    equals the direct far sum to <= 1e-13, and the potentials equal the
+    """81 densities on a 3000-triangle star: a pass of 64 and a pass of 16
+    on the matrix cores (P2M, M2L, L2P and the near-field sum as products
+    with the densities as columns) and one density alone; every column's far
+    sum equals the direct far sum to <= 1e-13, and the potentials equal the
     one-density FMM evaluations."""
     p, q, eps = 6, 6, 1e-13
     vq, tq = W.star_mesh(n_tri=3000, n_boundary=300, seed=43)
     vt, tt = W.star_mesh(n_tri=3000, n_boundary=300, seed=143, staggered=True)
     nodes = rules.interp_nodes(p)
     tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
-    R = 33
-    FR = np.ascontiguousarray(np.stack([W.sample_density(W.gaussian_sum(500 + r, vq, tq), vq, tq, nodes)
-                                        for r in range(R)], -1))
+    R = 81
+    base = [W.sample_density(W.gaussian_sum(500 + r, vq, tq), vq, tq, nodes) for r in range(9)]
+    FR = np.ascontiguousarray(np.stack([(1.0 + 0.05 * r) * base[r % 9] - 0.3 * base[(r // 9) % 9] for r in range(R)],
+                                       -1))
     mesh = vp_ctx.mesh(vq, tq)
     fmm = vp_ctx.plan(mesh, p, q, eps, tg, fmm_terms=40, fmm_leaf=64)
     direct = vp_ctx.plan(mesh, p, q, eps, tg)
@@ -173,8 +174,8 @@ def test_fmm_star_blocks_of_16_densities(vp_ctx):
     ud = direct.execute(FR, far_only=True)
     e = rel_linf(uf, ud)
     u = fmm.execute(FR)
-    e1 = max(rel_linf(u[:, r], fmm.execute(np.ascontiguousarray(FR[:, :, r]))) for r in (0, 15, 16, 31, 32))
-    say("fmm star 33 densities: far rel vs direct", e, "potential rel vs one-density FMM", e1)
+    e1 = max(rel_linf(u[:, r], fmm.execute(np.ascontiguousarray(FR[:, :, r]))) for r in (0, 37, 63, 64, 79, 80))
+    say("fmm star 81 densities: far rel vs direct", e, "potential rel vs one-density FMM", e1)
     assert e <= REL_FAR and e1 <= REL_FAR
     fmm.close()
     direct.close()
