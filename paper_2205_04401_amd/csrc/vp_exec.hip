@@ -32,11 +32,15 @@ inline unsigned blocks_for(int64_t n, int b = kBlock) {
 // [T][NP][R]); the remaining blocks take one (source, rhs) each: the charge
 // Q_j = w_j |J| f_h(y_j) / (4 pi) with f_h(y_j) = sum_i W_ji f_i read from the
 // node values (W = E V^{-1}), zero in the source padding.  Q may be null.
+// With many right-hand sides (tri_charges), the coefficient thread of
+// (triangle, rhs) also writes that triangle's nf charges from the node
+// values it holds, so F is read once; the charge blocks then only zero the
+// padding.  With few, one thread per (source, rhs) keeps the device full.
 template <int P>
-__global__ void k_coef_charges(const double* __restrict__ F, const double* __restrict__ vinv,
+__global__ __launch_bounds__(kBlock) void k_coef_charges(const double* __restrict__ F, const double* __restrict__ vinv,
                                const double* __restrict__ wfar, const double* __restrict__ swj, int nf,
-                               int64_t n_tri, int64_t n_src_pad, int64_t R, unsigned nb_c, double* __restrict__ C,
-                               double* __restrict__ Q) {
+                               int64_t n_tri, int64_t n_src_pad, int64_t R, unsigned nb_c, int tri_charges,
+                               double* __restrict__ C, double* __restrict__ Q) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
   if (blockIdx.x < nb_c) {
     const int64_t stride = (int64_t)nb_c * blockDim.x;
@@ -54,12 +58,24 @@ __global__ void k_coef_charges(const double* __restrict__ F, const double* __res
         for (int i = 0; i < NP; ++i) s = fma(vinv[k * NP + i], v[i], s);
         c[(size_t)k * R] = s;
       }
+      if (tri_charges && Q) {
+#pragma unroll 1
+        for (int j = 0; j < nf; ++j) {
+          const double* W = wfar + (size_t)j * NP;
+          double s = 0.0;
+#pragma unroll
+          for (int i = 0; i < NP; ++i) s = fma(W[i], v[i], s);
+          const int64_t src = t * nf + j;
+          Q[src * R + r] = s * swj[src] * kInv4Pi;
+        }
+      }
     }
     return;
   }
   const int64_t n_src = n_tri * nf;
   const int64_t stride = (int64_t)(gridDim.x - nb_c) * blockDim.x;
-  for (int64_t g = (int64_t)(blockIdx.x - nb_c) * blockDim.x + threadIdx.x; g < n_src_pad * R; g += stride) {
+  const int64_t g0 = tri_charges ? n_src * R : 0;  // only the padding
+  for (int64_t g = g0 + (int64_t)(blockIdx.x - nb_c) * blockDim.x + threadIdx.x; g < n_src_pad * R; g += stride) {
     const int64_t src = g / R, r = g - src * R;
     double q = 0.0;
     if (src < n_src) {
@@ -486,11 +502,13 @@ hipError_t launch_unpack_columns(const double* src, int64_t rows, int64_t src_co
 hipError_t launch_coefficients(const vp_plan* pl, const double* F, int64_t R, double* C, double* Q, hipStream_t st) {
   const int64_t T = pl->n_tri;
   if (T == 0 && !Q) return hipSuccess;
+  // from 16 right-hand sides on, the coefficient threads write the charges
+  const int tri = R >= 16 ? 1 : 0;
   const unsigned nb_c = T > 0 ? blocks_for(T * R) : 0;
-  const unsigned nb_q = Q ? blocks_for(pl->n_src_pad * R) : 0;
+  const unsigned nb_q = Q ? blocks_for((tri ? pl->n_src_pad - pl->n_src : pl->n_src_pad) * R) : 0;
   if (nb_c + nb_q == 0) return hipSuccess;
   VP_DISPATCH_P(pl->p, (k_coef_charges<P><<<nb_c + nb_q, kBlock, 0, st>>>(F, pl->vinv, pl->wfar, pl->swj, pl->n_f, T,
-                                                                          pl->n_src_pad, R, nb_c, C, Q)));
+                                                                          pl->n_src_pad, R, nb_c, tri, C, Q)));
   return hipGetLastError();
 }
 
