@@ -918,6 +918,7 @@ vp_status vp_execute(vp_plan* pl, int64_t R, const double* density, double* u_ou
   vp_status s = ensure_workspace(pl, R, cfg.n_split);
   if (s != VP_OK) return s;
   hipStream_t st = pl->ctx->stream;
+  VP_HIP(vp::fmm_prepare_blocks(pl, R, st), "vp_execute: FMM tables");
   const size_t nF = (size_t)pl->n_tri * pl->n_p * R;
   const double* F = density;
   if (!dev && nF) {
@@ -1025,6 +1026,10 @@ vp_status vp_graph_create(vp_plan* pl, int64_t R, const double* density, double*
       (e = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking)) != hipSuccess) {
     drop(g);
     return hip_fail(e, "vp_graph_create");
+  }
+  if ((e = vp::fmm_prepare_blocks(pl, R, pl->ctx->stream)) != hipSuccess) {
+    drop(g);
+    return hip_fail(e, "vp_graph_create: FMM tables");
   }
   // capture the evaluation's launches (no memsets, no host synchronisation)
   const bool prof = pl->ctx->profile;
@@ -1149,6 +1154,7 @@ vp_status vp_plan_autotune(vp_plan* pl, int64_t R, vp_precision prec, int reps, 
   vp_status s = ensure_workspace(pl, R, need_split);
   if (s != VP_OK) return s;
   hipStream_t st = pl->ctx->stream;
+  VP_HIP(vp::fmm_prepare_blocks(pl, R, st), "vp_plan_autotune: FMM tables");
   VP_HIP(hipMemsetAsync(pl->ws_c, 0, 8 * std::max<size_t>((size_t)pl->n_tri * pl->n_p * R, 1), st),
          "vp_plan_autotune: clear");
   hipEvent_t ev[2] = {nullptr, nullptr};

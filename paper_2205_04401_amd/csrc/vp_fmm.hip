@@ -627,6 +627,28 @@ __global__ __launch_bounds__(kBlock) void k_fmmb_leaf(
   }
 }
 
+// Work counts of a plan (statistics): the direct pairs of the adjacent leaf
+// boxes (cnt[0]) and the M2L translations over all levels (cnt[1]), one
+// thread per box of the level.
+__global__ void k_fmm_work(const int32_t* __restrict__ cs, const int32_t* __restrict__ ct, int l, int leaf,
+                           unsigned long long* __restrict__ cnt) {
+  const int n = 1 << l;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= (int64_t)n * n || ct[b] == 0) return;
+  const int ix = (int)(b % n), iy = (int)(b / n);
+  unsigned long long m2l = 0, near = 0;
+  for (int jy = max(iy - 3, 0); jy <= min(iy + 3, n - 1); ++jy)
+    for (int jx = max(ix - 3, 0); jx <= min(ix + 3, n - 1); ++jx) {
+      const int32_t c = cs[(int64_t)jy * n + jx];
+      if (abs(jx - ix) <= 1 && abs(jy - iy) <= 1)
+        near += (unsigned long long)c;
+      else if (abs((jx >> 1) - (ix >> 1)) <= 1 && abs((jy >> 1) - (iy >> 1)) <= 1 && c > 0)
+        ++m2l;
+    }
+  if (l >= 2) atomicAdd(&cnt[1], m2l);
+  if (leaf) atomicAdd(&cnt[0], near * (unsigned long long)ct[b]);
+}
+
 // Binomial coefficients up to n = 2 p in long double.
 std::vector<long double> binomials(int nmax) {
   std::vector<long double> c((size_t)(nmax + 1) * (nmax + 1), 0.0L);
@@ -897,31 +919,6 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
       }
   }
   for (int l = 0; l <= L; ++l) pl->fmm_off[l] = off[l];
-  // work counts: direct pairs of the adjacent leaf boxes, and M2L
-  // translations (target box with targets below, source box with sources)
-  pl->fmm_near_pairs = 0;
-  for (int iy = 0; iy < n; ++iy)
-    for (int ix = 0; ix < n; ++ix) {
-      const int64_t nt = hc[nleaf + (int64_t)iy * n + ix];
-      if (nt == 0) continue;
-      int64_t ns = 0;
-      for (int jy = std::max(iy - 1, 0); jy <= std::min(iy + 1, n - 1); ++jy)
-        for (int jx = std::max(ix - 1, 0); jx <= std::min(ix + 1, n - 1); ++jx) ns += hc[(int64_t)jy * n + jx];
-      pl->fmm_near_pairs += nt * ns;
-    }
-  pl->fmm_m2l_pairs = 0;
-  for (int l = 2; l <= L; ++l) {
-    const int m = 1 << l;
-    for (int iy = 0; iy < m; ++iy)
-      for (int ix = 0; ix < m; ++ix) {
-        if (ct[off[l] + (int64_t)iy * m + ix] == 0) continue;
-        for (int jy = std::max(iy - 3, 0); jy <= std::min(iy + 3, m - 1); ++jy)
-          for (int jx = std::max(ix - 3, 0); jx <= std::min(ix + 3, m - 1); ++jx)
-            if ((std::abs(jx - ix) > 1 || std::abs(jy - iy) > 1) && std::abs((jx >> 1) - (ix >> 1)) <= 1 &&
-                std::abs((jy >> 1) - (iy >> 1)) <= 1 && cs[off[l] + (int64_t)jy * m + jx] > 0)
-              ++pl->fmm_m2l_pairs;
-      }
-  }
   std::vector<double2> m2m, l2l, m2l;
   fmm_operators(p, m2m, l2l, m2l);
   pl->fmm_mp = (2 * (p + 1) + 15) / 16 * 16;
@@ -948,27 +945,73 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
       (e = hipMemcpyAsync(pl->fmm_m2l, m2l_r.data(), sizeof(double) * m2l_r.size(), hipMemcpyHostToDevice, st)) !=
           hipSuccess)
     return e;
-  // blocks of 16 densities: P2M rows of the sources, L2P rows of the
-  // targets, and the (leaf box, 16 targets) work list of the leaf pass
+  // work counts (plan statistics)
+  {
+    unsigned long long* d_cnt = nullptr;
+    unsigned long long h_cnt[2] = {0, 0};
+    if ((e = hipMalloc((void**)&d_cnt, sizeof(h_cnt))) != hipSuccess) return e;
+    e = hipMemsetAsync(d_cnt, 0, sizeof(h_cnt), st);
+    for (int l = 2; l <= L && e == hipSuccess; ++l) {
+      k_fmm_work<<<blocks_for((int64_t)1 << (2 * l)), kBlock, 0, st>>>(pl->fmm_cnt_src + off[l], pl->fmm_cnt_tgt + off[l],
+                                                                     l, l == L ? 1 : 0, d_cnt);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(h_cnt, d_cnt, sizeof(h_cnt), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d_cnt);
+    if (e != hipSuccess) return e;
+    pl->fmm_near_pairs = (int64_t)h_cnt[0];
+    pl->fmm_m2l_pairs = (int64_t)h_cnt[1];
+  }
+  pl->fmm_tgt_ptr_host = tp;
+  return hipStreamSynchronize(st);  // the host vectors above go out of scope
+}
+
+// Tables of the passes of 16+ densities, built at the first evaluation
+// that needs them (they cost 8 (N_src MP + N_tgt KP) bytes): P2M rows of
+// the sources, L2P rows of the targets, and the (leaf box, first target)
+// work list of the leaf pass.  Synchronises the stream.
+hipError_t fmm_prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st) {
+  if (pl->fmm_terms <= 0 || R < 16 || pl->fmm_vsrc) return hipSuccess;
+  const int64_t NS = pl->n_src, NT = pl->n_tgt;
+  const int L = pl->fmm_levels, n = 1 << L, p = pl->fmm_terms;
+  const int64_t nleaf = (int64_t)n * n;
+  const std::vector<int64_t>& tp = pl->fmm_tgt_ptr_host;
   std::vector<int2> tiles;
   for (int64_t b = 0; b < nleaf; ++b)
     for (int64_t i = tp[b]; i < tp[b + 1]; i += 16) tiles.push_back(make_int2((int)b, (int)i));
-  pl->fmm_n_ttiles = (int64_t)tiles.size();
-  if ((e = alloc((void**)&pl->fmm_vsrc, sizeof(double) * NS * pl->fmm_mp)) != hipSuccess ||
-      (e = alloc((void**)&pl->fmm_wtgt, sizeof(double) * NT * pl->fmm_kp)) != hipSuccess ||
-      (e = alloc((void**)&pl->fmm_ttile, sizeof(int2) * std::max<size_t>(tiles.size(), 1))) != hipSuccess)
+  const size_t bytes = sizeof(double) * (NS * pl->fmm_mp + NT * pl->fmm_kp) + sizeof(int2) * std::max<size_t>(tiles.size(), 1);
+  if (pl->ctx->budget && pl->ctx->in_use + bytes > pl->ctx->budget) return hipErrorOutOfMemory;
+  double *vsrc = nullptr, *wtgt = nullptr;
+  int2* tt = nullptr;
+  hipError_t e;
+  if ((e = hipMalloc((void**)&vsrc, sizeof(double) * NS * pl->fmm_mp)) != hipSuccess ||
+      (e = hipMalloc((void**)&wtgt, sizeof(double) * NT * pl->fmm_kp)) != hipSuccess ||
+      (e = hipMalloc((void**)&tt, sizeof(int2) * std::max<size_t>(tiles.size(), 1))) != hipSuccess) {
+    for (void* x : {(void*)vsrc, (void*)wtgt, (void*)tt})
+      if (x) (void)hipFree(x);
     return e;
-  const double sL = w / n;
-  k_fmm_vsrc<<<blocks_for(NS), kBlock, 0, st>>>(pl->fmm_sxy, NS, pl->fmm_x0, pl->fmm_y0, sL, L, p, pl->fmm_mp,
-                                                pl->fmm_vsrc);
+  }
+  const double sL = pl->fmm_width / n;
+  k_fmm_vsrc<<<blocks_for(NS), kBlock, 0, st>>>(pl->fmm_sxy, NS, pl->fmm_x0, pl->fmm_y0, sL, L, p, pl->fmm_mp, vsrc);
   k_fmm_wtgt<<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, pl->fmm_tgt_perm, NT, pl->fmm_x0, pl->fmm_y0, sL, L, p,
-                                                pl->fmm_kp, pl->fmm_wtgt);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (!tiles.empty() &&
-      (e = hipMemcpyAsync(pl->fmm_ttile, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, st)) !=
-          hipSuccess)
+                                                pl->fmm_kp, wtgt);
+  e = hipGetLastError();
+  if (e == hipSuccess && !tiles.empty())
+    e = hipMemcpyAsync(tt, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    for (void* x : {(void*)vsrc, (void*)wtgt, (void*)tt}) (void)hipFree(x);
     return e;
-  return hipStreamSynchronize(st);  // the host vectors above go out of scope
+  }
+  for (void* x : {(void*)vsrc, (void*)wtgt, (void*)tt}) pl->allocs.push_back(x);
+  pl->fmm_vsrc = vsrc;
+  pl->fmm_wtgt = wtgt;
+  pl->fmm_ttile = tt;
+  pl->fmm_n_ttiles = (int64_t)tiles.size();
+  pl->bytes += bytes;
+  pl->ctx->in_use += bytes;
+  return hipSuccess;
 }
 
 // The far sum of every right-hand side by the FMM into out[t][R] (the
@@ -988,7 +1031,7 @@ hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out
   // blocks of 16 densities on the matrix cores, up to 4 blocks per pass
   const int MP = pl->fmm_mp, KP = pl->fmm_kp, tiles = MP / 16;
   int64_t c0 = 0;
-  while (R - c0 >= 16) {
+  while (pl->fmm_vsrc && R - c0 >= 16) {
     const int nbk = R - c0 >= 64 ? 4 : R - c0 >= 32 ? 2 : 1;
     const int C = 16 * nbk;
     double* Mb = (double*)Mall;

@@ -390,6 +390,7 @@ struct vp_plan {
   double *fmm_vsrc = nullptr, *fmm_wtgt = nullptr;
   int2* fmm_ttile = nullptr;
   int64_t fmm_n_ttiles = 0;
+  std::vector<int64_t> fmm_tgt_ptr_host;  // host copy of fmm_tgt_ptr (tile list)
   // far-sum launch shapes stored for (n_rhs, precision) by the tuner or the caller
   std::map<std::pair<int64_t, int>, vp_far_config> far_tuned;
   double *ws_f = nullptr, *ws_c = nullptr, *ws_q = nullptr, *ws_part = nullptr, *ws_u = nullptr;
@@ -441,6 +442,9 @@ int64_t far_partial_doubles(const vp_plan* pl, int64_t n_split, int64_t R);
 int64_t fmm_boxes(int levels);
 int64_t fmm_workspace_doubles(const vp_plan* pl, int64_t R);
 hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st);  // after sources and targets; plan memory
+// tables of the passes of 16+ densities (no-op unless an FMM plan, R >= 16
+// and not built yet); call before launch_far (not under graph capture)
+hipError_t fmm_prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st);
 hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out, double* ws, hipStream_t st,
                       int64_t* n_launches);
 void set_last_error(const char* msg);

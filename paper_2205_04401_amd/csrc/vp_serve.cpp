@@ -116,6 +116,8 @@ vp_status issue(vp_server* s, int slot_id, const std::vector<int64_t>& batch) {
     c0 += r.R;
   }
   const vp_far_config cfg = vp::far_config(pl, R, head.prec == VP_MIXED);
+  // FMM plans: the tables of 16+ densities are built once, on the context's stream
+  if (e == hipSuccess) e = vp::fmm_prepare_blocks(const_cast<vp_plan*>(pl), R, s->ctx->stream);
   if (e == hipSuccess) e = vp::launch_coefficients(pl, F, R, C, Q, st);
   if (e == hipSuccess)
     e = vp::launch_far(pl, Q, R, cfg, part, st, nullptr, head.prec == VP_MIXED ? Q32 : nullptr);
