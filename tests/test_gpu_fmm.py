@@ -182,6 +182,64 @@ def test_fmm_star_blocks_of_16_densities(vp_ctx):
     mesh.close()
 
 
+def test_fmm_curved_disk_closed_form(vp_ctx):
+    """Unit density on a disk with circular boundary sides (curved
+    triangles, blending map), far sum by the FMM: u = r^2/4 - 1/4 inside and
+    (1/2) log r outside, to within 1e-11, at targets inside, on and outside
+    the circle."""
+    v, t, ct, cs, cp = W.curved_disk(n_tri=200, n_boundary=30, seed=1, deg=16)
+    mesh = vp_ctx.mesh(v, t, curved=(ct, cs, cp))
+    rng = np.random.default_rng(11)
+    r = np.concatenate([rng.uniform(0, 0.99, 24), [1.0, 1.0, 1.0], rng.uniform(1.01, 3, 12), [0.995, 1.005]])
+    a = rng.uniform(0, 2 * math.pi, len(r))
+    tg = np.stack([r * np.cos(a), r * np.sin(a)], 1)
+    plan = vp_ctx.plan(mesh, 1, 8, 1e-13, tg, fmm_terms=40, fmm_leaf=16)
+    exact = np.where(r <= 1, r ** 2 / 4 - 0.25, 0.5 * np.log(r))
+    e = np.abs(plan.execute(np.ones((len(t), 3))) - exact).max() / np.abs(exact).max()
+    say("fmm curved disk: levels", plan.info()["fmm_levels"], "unit density vs closed form", e)
+    assert e <= 1e-11
+    plan.close()
+    mesh.close()
+
+
+def test_fmm_serving_alone_and_in_mix(vp_ctx):
+    """Requests of 1-8 densities on FMM plans through the continuous-batching
+    server: packed batches of 16+ columns run the matrix-core passes, a lone
+    request the one-density passes; every result agrees with the request's
+    own evaluation to 1e-13."""
+    import torch
+    rng = np.random.default_rng(9)
+    plans = []
+    for k, (T, p) in enumerate(((600, 3), (1500, 4))):
+        vq, tq = W.star_mesh(n_tri=T, n_boundary=120, seed=320 + k)
+        vt, tt = W.star_mesh(n_tri=T, n_boundary=120, seed=330 + k, staggered=True)
+        nodes = rules.interp_nodes(p)
+        tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+        mesh = vp_ctx.mesh(vq, tq)
+        plans.append((mesh, vp_ctx.plan(mesh, p, 6, 1e-12, tg, fmm_terms=40, fmm_leaf=32), vq, tq, nodes))
+    server = vp_ctx.server(n_slots=3, max_batch_rhs=32)
+    reqs = []
+    for i in range(30):
+        k = int(rng.integers(2))
+        mesh, plan, vq, tq, nodes = plans[k]
+        R = int(rng.integers(1, 9))
+        F = np.stack([W.sample_density(W.gaussian_sum(900 + 7 * i + r, vq, tq), vq, tq, nodes) for r in range(R)], -1)
+        out = torch.full((plan.n_tgt, R), np.nan, dtype=torch.float64, device="cuda")
+        reqs.append((k, F, out, torch.from_numpy(F).cuda()))
+    torch.cuda.synchronize()
+    tickets = [server.submit(plans[k][1], Fd, out) for k, F, out, Fd in reqs]
+    for t in tickets:
+        server.wait(t)
+    st = server.stats()
+    worst = max(rel_linf(out.cpu().numpy(), plans[k][1].execute(F)) for k, F, out, _ in reqs)
+    say("fmm serving:", st, "worst rel alone vs in the mix", worst)
+    assert st["requests_done"] == 30 and st["batches"] < 30 and worst <= 1e-13
+    server.close()
+    for mesh, plan, *_ in plans:
+        plan.close()
+        mesh.close()
+
+
 def test_fmm_option_errors(square, vp_ctx):
     from paper_2205_04401_amd import vp
     for terms, leaf in ((5, 128), (64, 128), (40, 4), (40, 5000)):
