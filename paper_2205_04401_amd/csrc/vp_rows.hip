@@ -87,8 +87,43 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
   __shared__ double lv[2][kCap * 3];
   __shared__ double leaf[kCap * 3];
   __shared__ double2 tab[kLogTab + 1];
+  // the small rule tables in LDS (read at every node; global loads there
+  // would put a cache round trip into each node's dependency chain):
+  // near-rule x, y, w [nn]; Gauss-Legendre s, w [nl]; radial r, a, b [nr];
+  // curved radial r, a, b [n_rc]
+  extern __shared__ double rule_tabs[];
+  double* const s_nx = rule_tabs;
+  double* const s_ny = s_nx + a.nn;
+  double* const s_nw = s_ny + a.nn;
+  double* const s_gs = s_nw + a.nn;
+  double* const s_gw = s_gs + a.nl;
+  double* const s_rr = s_gw + a.nl;
+  double* const s_ra = s_rr + a.nr;
+  double* const s_rb = s_ra + a.nr;
+  double* const s_cr = s_rb + a.nr;
+  double* const s_ca = s_cr + a.n_rc;
+  double* const s_cb = s_ca + a.n_rc;
   const int lane = threadIdx.x;
   for (int i = lane; i <= kLogTab; i += kWave) tab[i] = a.logtab[i];
+  for (int i = lane; i < a.nn; i += kWave) {
+    s_nx[i] = a.near_x[i];
+    s_ny[i] = a.near_y[i];
+    s_nw[i] = a.near_w[i];
+  }
+  for (int i = lane; i < a.nl; i += kWave) {
+    s_gs[i] = a.gl_s[i];
+    s_gw[i] = a.gl_w[i];
+  }
+  for (int i = lane; i < a.nr; i += kWave) {
+    s_rr[i] = a.rad_r[i];
+    s_ra[i] = a.rad_a[i];
+    s_rb[i] = a.rad_b[i];
+  }
+  for (int i = lane; i < a.n_rc; i += kWave) {
+    s_cr[i] = a.rad_c_r[i];
+    s_ca[i] = a.rad_c_a[i];
+    s_cb[i] = a.rad_c_b[i];
+  }
   __syncthreads();
   for (int64_t pr = blockIdx.x; pr < a.n_pairs; pr += gridDim.x) {
   const int32_t t = a.pair_tri[pr];
@@ -256,7 +291,7 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
       for (int item = lane; item < items; item += kWave) {
         const int l = item / a.nn, nd = item - l * a.nn;
         const double sa = leaf[3 * l], sb = leaf[3 * l + 1], ss = leaf[3 * l + 2];
-        const double xi1 = sa + ss * a.near_x[nd], xi2 = sb + ss * a.near_y[nd];
+        const double xi1 = sa + ss * s_nx[nd], xi2 = sb + ss * s_ny[nd];
         double yx, yy, jac = D;
         if (cf) {
           jac = vp_blend_jac(Ax, Ay, Bx, By, Cx, Cy, cf, a.cv.deg, xi1, xi2, yx, yy);
@@ -265,7 +300,7 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
           yy = Ay + xi1 * e1y + xi2 * e2y;
         }
         const double dx = x - yx, dy = y - yy;
-        const double w = 0.5 * vp_log(dx * dx + dy * dy, tab) * a.near_w[nd] * ss * ss * jac;
+        const double w = 0.5 * vp_log(dx * dx + dy * dy, tab) * s_nw[nd] * ss * ss * jac;
         koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { acc[k] = fma(w, v, acc[k]); });
       }
       __syncthreads();
@@ -341,7 +376,7 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
           ++n_leaves;
           if (level >= a.depth_cap) ++n_capped;
           for (int nd = lane; nd < a.nn; nd += kWave) {
-            const double xi1 = sa + ss * a.near_x[nd], xi2 = sb + ss * a.near_y[nd];
+            const double xi1 = sa + ss * s_nx[nd], xi2 = sb + ss * s_ny[nd];
             double yx, yy, jac = D;
             if (cf) {
               jac = vp_blend_jac(Ax, Ay, Bx, By, Cx, Cy, cf, a.cv.deg, xi1, xi2, yx, yy);
@@ -350,7 +385,7 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
               yy = Ay + xi1 * e1y + xi2 * e2y;
             }
             const double dx = x - yx, dy = y - yy;
-            const double w = 0.5 * vp_log(dx * dx + dy * dy, tab) * a.near_w[nd] * ss * ss * jac;
+            const double w = 0.5 * vp_log(dx * dx + dy * dy, tab) * s_nw[nd] * ss * ss * jac;
             koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { acc[k] = fma(w, v, acc[k]); });
           }
         }
@@ -411,15 +446,15 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
               s1 = L - (1.0 - ldexp(1.0, -n2)) * rest;
             }
           }
-          const double sv = s0 + (s1 - s0) * a.gl_s[il];
-          const double ws = (s1 - s0) * a.gl_w[il];
+          const double sv = s0 + (s1 - s0) * s_gs[il];
+          const double ws = (s1 - s0) * s_gw[il];
           const double gx = Px + sv * ux, gy = Py + sv * uy;
-          const double rr = a.rad_c_r[ir];
+          const double rr = s_cr[ir];
           const double yr1 = z1 + rr * (gx - z1), yr2 = z2 + rr * (gy - z2);
           double qx, qy;
           const double jac = vp_blend_jac(Ax, Ay, Bx, By, Cx, Cy, cf, a.cv.deg, yr1, yr2, qx, qy);
           const double lam = 0.5 * vp_log((qx - x) * (qx - x) + (qy - y) * (qy - y), tab) - vp_log(rr, tab);
-          const double w = h * ws * (a.rad_c_a[ir] * lam + a.rad_c_b[ir]) * jac;
+          const double w = h * ws * (s_ca[ir] * lam + s_cb[ir]) * jac;
           koornwinder_emit<P>(yr1, yr2, [&](int k, double v) { acc[k] = fma(w, v, acc[k]); });
         }
       }
@@ -442,12 +477,12 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
       const int nleft = n1 + 1, nright = n2 + 1;  // panels per side (0 if empty)
       const int np = nleft + nright;
       n_panels += np;
-      const int per_panel = a.nl * a.nr;
-      const int items = np * per_panel;
+      // lanes over (panel, arc node); the radial nodes of the ray share the
+      // ray's arc position and its log r0 term
+      const int items = np * a.nl;
       for (int item = lane; item < items; item += kWave) {
-        const int ip = item / per_panel;
-        const int rem = item - ip * per_panel;
-        const int il = rem / a.nr, ir = rem - il * a.nr;
+        const int ip = item / a.nl;
+        const int il = item - ip * a.nl;
         double s0, s1;
         if (ip < nleft) {
           if (ip < n1) {
@@ -467,17 +502,20 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
             s1 = L - (1.0 - ldexp(1.0, -n2)) * rest;
           }
         }
-        const double s = s0 + (s1 - s0) * a.gl_s[il];
-        const double ws = (s1 - s0) * a.gl_w[il];
+        const double s = s0 + (s1 - s0) * s_gs[il];
+        const double hws = h * (s1 - s0) * s_gw[il];
         const double gx = Px + s * ux, gy = Py + s * uy;
         const double r0sq = (gx - x) * (gx - x) + (gy - y) * (gy - y);
-        const double rr = a.rad_r[ir];
-        const double px = x + rr * (gx - x), py = y + rr * (gy - y);
-        const double w = h * ws * (a.rad_a[ir] * 0.5 * vp_log(r0sq, tab) + a.rad_b[ir]);
-        const double dx = px - Ax, dy = py - Ay;
-        const double xi1 = (dx * e2y - dy * e2x) * invD;
-        const double xi2 = (e1x * dy - e1y * dx) * invD;
-        koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { acc[k] = fma(w, v, acc[k]); });
+        const double hlog = 0.5 * vp_log(r0sq, tab);
+        // the ray from x to g in reference coordinates
+        const double ox = x - Ax, oy = y - Ay, gdx = gx - x, gdy = gy - y;
+        const double z1 = (ox * e2y - oy * e2x) * invD, z2 = (e1x * oy - e1y * ox) * invD;
+        const double d1 = (gdx * e2y - gdy * e2x) * invD, d2 = (e1x * gdy - e1y * gdx) * invD;
+        for (int ir = 0; ir < a.nr; ++ir) {
+          const double rr = s_rr[ir];
+          const double w = hws * fma(s_ra[ir], hlog, s_rb[ir]);
+          koornwinder_emit<P>(fma(rr, d1, z1), fma(rr, d2, z2), [&](int k, double v) { acc[k] = fma(w, v, acc[k]); });
+        }
       }
     }
     }  // straight self pair
@@ -563,12 +601,13 @@ hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t s
   // 2^32 work-items)
   dim3 grid((unsigned)std::min<int64_t>(pl->n_pairs, 1 << 25));
   const bool curved = m->n_curved > 0;
+  const size_t lds = sizeof(double) * (3 * (size_t)a.nn + 2 * (size_t)a.nl + 3 * (size_t)a.nr + 3 * (size_t)a.n_rc);
 #define VP_ROWS(PV)                                                   \
   case PV:                                                            \
     if (curved)                                                       \
-      k_rows<PV, true><<<grid, 64, 0, st>>>(a);                       \
+      k_rows<PV, true><<<grid, 64, lds, st>>>(a);                     \
     else                                                              \
-      k_rows<PV, false><<<grid, 64, 0, st>>>(a);                      \
+      k_rows<PV, false><<<grid, 64, lds, st>>>(a);                    \
     break
   switch (pl->p) {
     VP_ROWS(1);
