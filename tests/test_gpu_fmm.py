@@ -249,3 +249,5 @@ def test_fmm_option_errors(square, vp_ctx):
     with pytest.raises(vp.VPError):
         plan.set_far_config("wide", 4, 8)  # an FMM plan has one partial sum per target
     plan.set_far_config("wide", 4, 1)
+    cfg, ms = plan.autotune(n_rhs=1, reps=2)  # nothing to choose: times the one shape
+    assert cfg["n_split"] == 1 and ms > 0
