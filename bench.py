@@ -477,8 +477,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the far sum, near lists and corrections of this build run on a single "
-              "MI355X; multi-GPU sharding is a design note only (targets would split across GPUs with one "
+        print("bench.py measures one GPU: the far sum, near lists and corrections run on a single MI355X; "
+              "sharding over several GPUs is a design note only (targets would split across GPUs with one "
               "all-gather of the far charges).", file=sys.stderr)
         raise SystemExit(2)
     if args.copy_probe:

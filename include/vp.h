@@ -62,7 +62,7 @@ typedef enum {
   VP_EINVAL = 1,     /* invalid argument (sizes, orders, degenerate geometry, NaN) */
   VP_ENOMEM = 2,     /* device allocation failed or the context's HBM budget is exceeded */
   VP_EDEVICE = 3,    /* a HIP runtime call or kernel failed */
-  VP_ENOTSUP = 4,    /* valid request this build does not support */
+  VP_ENOTSUP = 4,    /* valid request the library does not support */
   VP_EBUSY = 5,      /* object still in use (mesh with live plans) */
   VP_EINTERNAL = 6   /* internal limit hit (reported with the message) */
 } vp_status;

@@ -129,7 +129,7 @@ def test_far_only_differs_and_corrections_matter():
     assert np.abs(u_far - ex).max() > 1e-6
 
 
-# -- P4: disk closed form (spec check) --------------------------------
+# -- P4: disk closed form ----------------------------------------------------
 
 def test_naive_ball_model_converges_to_the_exact_integral():
     """The naive near field (a ball of kappa times the centroid radius, the
