@@ -26,8 +26,8 @@
 //   k_fmm_m2l   16 boxes per wavefront: M2L over the interaction list on the
 //               FP64 matrix cores (real form of the complex operators)
 //   k_fmm_l2l   one thread per (box, coefficient): L2L from the parent
-//   k_fmm_leaf  one wavefront per leaf box: the local expansion at each of
-//               its targets plus the direct sum over the 3 x 3 adjacent boxes
+//   k_fmm_leaf  one wavefront per 16 targets of a leaf box: the local
+//               expansion plus the direct sum over the 3 x 3 adjacent boxes
 #include <hipcub/hipcub.hpp>
 
 #include <climits>
@@ -280,61 +280,62 @@ __global__ void k_fmm_l2l(const int32_t* __restrict__ cnt_t, const double2* __re
   Lc[g] = v;
 }
 
-// Leaf boxes (one wavefront each, lanes over the box's targets 64 at a
-// time): 2 Re of the local expansion at the target, plus the direct sum of
-// Q log(r^2 + 2^-100) over the sources of the 3 x 3 adjacent leaf boxes
-// (wavefront-uniform source reads; 256-entry logarithm table in LDS, the
-// exponent part accumulated apart as in the direct far sum).
+// Leaf pass of one density: one wavefront per (leaf box, 16 of its
+// targets), 4 lanes per target that take every fourth source of the
+// adjacent boxes (a box holds about as many targets as a few 16-target
+// tiles, so the lanes stay busy where one lane per target left a 64-lane
+// wavefront half empty), joined by a butterfly over the 4; the first lane
+// of each target adds 2 Re of the local expansion (Horner).  The direct sum
+// is Q log(r^2 + 2^-100) over the sources of the 3 x 3 adjacent leaf boxes
+// (256-entry logarithm table in LDS, exponent part accumulated apart as in
+// the direct far sum).
 __global__ __launch_bounds__(kBlock) void k_fmm_leaf(
-    const double2* __restrict__ Lc, const double2* __restrict__ sxy_s, const double* __restrict__ Qs,
-    const int64_t* __restrict__ sptr, const int32_t* __restrict__ tperm, const int64_t* __restrict__ tptr,
-    const double* __restrict__ xt, const double* __restrict__ yt, int L, double x0, double y0, double s, int p,
-    const double2* __restrict__ logtab, int64_t R, int64_t r, double* __restrict__ out) {
+    const double2* __restrict__ Lc, const int2* __restrict__ ttile, int64_t n_tiles, const double2* __restrict__ sxy_s,
+    const double* __restrict__ Qs, const int64_t* __restrict__ sptr, const int32_t* __restrict__ tperm,
+    const int64_t* __restrict__ tptr, const double* __restrict__ xt, const double* __restrict__ yt, int L, double x0,
+    double y0, double s, int p, const double2* __restrict__ logtab, int64_t R, int64_t r, double* __restrict__ out) {
   __shared__ double2 tab[kLogTab + 1];
   for (int i = threadIdx.x; i <= kLogTab; i += kBlock) tab[i] = logtab[i];
   __syncthreads();
-  const int lane = (int)(threadIdx.x & 63);
-  const int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = (int)(threadIdx.x & 63), r16 = lane & 15, kq = lane >> 4;
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (w >= n_tiles) return;  // the whole wavefront
   const int n = 1 << L;
-  if (b >= (int64_t)n * n) return;  // the whole wavefront
+  const int2 tl = ttile[w];
+  const int64_t b = tl.x, i = tl.y + r16, i1 = tptr[b + 1];
+  const bool act = i < i1;
   const int ix = (int)(b % n), iy = (int)(b / n);
   const double cx = x0 + (ix + 0.5) * s, cy = y0 + (iy + 0.5) * s, inv_s = 1.0 / s;
-  const double2* lc = Lc + b * (p + 1);
+  const int64_t t = act ? tperm[i] : 0;
+  const double x = act ? xt[t] : cx, y = act ? yt[t] : cy;
   const double2 l2 = tab[kLogTab];
-  const int64_t i1 = tptr[b + 1];
-  for (int64_t i0 = tptr[b]; i0 < i1; i0 += 64) {
-    const int64_t i = i0 + lane;
-    const bool act = i < i1;
-    const int64_t t = act ? tperm[i] : 0;
-    const double x = act ? xt[t] : cx, y = act ? yt[t] : cy;
-    // local expansion by Horner's rule
-    const double2 zh = make_double2((x - cx) * inv_s, (y - cy) * inv_s);
-    double2 v = lc[p];
-    for (int k = p - 1; k >= 0; --k) v = cfma(v, zh, lc[k]);
-    // adjacent boxes: in each of the 3 rows they are consecutive leaf
-    // boxes, so their sources form one contiguous range
-    double acc_e = 0.0, acc_r = 0.0;
-    auto pair = [&](double2 w, double q) {
-      const double ddx = x - w.x, ddy = y - w.y;
+  double acc_e = 0.0, acc_r = 0.0;
+  for (int dy = -1; dy <= 1; ++dy) {
+    const int jy = iy + dy;
+    if (jy < 0 || jy >= n) continue;
+    const int64_t row = (int64_t)jy * n;
+    const int64_t j0 = sptr[row + max(ix - 1, 0)], j1 = sptr[row + min(ix + 1, n - 1) + 1];
+    for (int64_t j = j0 + kq; j < j1; j += 4) {
+      const double2 sw = sxy_s[j];
+      const double q = Qs[j];
+      const double ddx = x - sw.x, ddy = y - sw.y;
       const double r2 = fma(ddy, ddy, fma(ddx, ddx, kR2Bias));
       double e, rest;
       vp_log_parts(r2, tab, e, rest);
       acc_e = fma(q, e, acc_e);
       acc_r = fma(q, rest, acc_r);
-    };
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int jy = iy + dy;
-      if (jy < 0 || jy >= n) continue;
-      const int64_t row = (int64_t)jy * n;
-      const int64_t j0 = sptr[row + max(ix - 1, 0)], j1 = sptr[row + min(ix + 1, n - 1) + 1];
-      int64_t j = j0;
-      for (; j + 4 <= j1; j += 4) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) pair(sxy_s[j + u], Qs[j + u]);
-      }
-      for (; j < j1; ++j) pair(sxy_s[j], Qs[j]);
     }
-    if (act) out[t * R + r] = 2.0 * v.x + acc_r + fma(acc_e, l2.x, acc_e * l2.y);
+  }
+  acc_e += __shfl_xor(acc_e, 16);
+  acc_r += __shfl_xor(acc_r, 16);
+  acc_e += __shfl_xor(acc_e, 32);
+  acc_r += __shfl_xor(acc_r, 32);
+  if (act && kq == 0) {
+    const double2* lc = Lc + b * (p + 1);
+    const double2 zh = make_double2((x - cx) * inv_s, (y - cy) * inv_s);
+    double2 v = lc[p];
+    for (int k = p - 1; k >= 0; --k) v = cfma(v, zh, lc[k]);
+    out[t * R + r] = 2.0 * v.x + acc_r + fma(acc_e, l2.x, acc_e * l2.y);
   }
 }
 
@@ -964,31 +965,33 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
     pl->fmm_m2l_pairs = (int64_t)h_cnt[1];
   }
   pl->fmm_tgt_ptr_host = tp;
+  // the (leaf box, first target) work list of the leaf passes: 16-target tiles
+  std::vector<int2> tiles;
+  for (int64_t b = 0; b < nleaf; ++b)
+    for (int64_t i = tp[b]; i < tp[b + 1]; i += 16) tiles.push_back(make_int2((int)b, (int)i));
+  pl->fmm_n_ttiles = (int64_t)tiles.size();
+  if ((e = alloc((void**)&pl->fmm_ttile, sizeof(int2) * std::max<size_t>(tiles.size(), 1))) != hipSuccess) return e;
+  if (!tiles.empty() &&
+      (e = hipMemcpyAsync(pl->fmm_ttile, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, st)) !=
+          hipSuccess)
+    return e;
   return hipStreamSynchronize(st);  // the host vectors above go out of scope
 }
 
 // Tables of the passes of 16+ densities, built at the first evaluation
 // that needs them (they cost 8 (N_src MP + N_tgt KP) bytes): P2M rows of
-// the sources, L2P rows of the targets, and the (leaf box, first target)
-// work list of the leaf pass.  Synchronises the stream.
+// the sources and L2P rows of the targets.  Synchronises the stream.
 hipError_t fmm_prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st) {
   if (pl->fmm_terms <= 0 || R < 16 || pl->fmm_vsrc) return hipSuccess;
   const int64_t NS = pl->n_src, NT = pl->n_tgt;
   const int L = pl->fmm_levels, n = 1 << L, p = pl->fmm_terms;
-  const int64_t nleaf = (int64_t)n * n;
-  const std::vector<int64_t>& tp = pl->fmm_tgt_ptr_host;
-  std::vector<int2> tiles;
-  for (int64_t b = 0; b < nleaf; ++b)
-    for (int64_t i = tp[b]; i < tp[b + 1]; i += 16) tiles.push_back(make_int2((int)b, (int)i));
-  const size_t bytes = sizeof(double) * (NS * pl->fmm_mp + NT * pl->fmm_kp) + sizeof(int2) * std::max<size_t>(tiles.size(), 1);
+  const size_t bytes = sizeof(double) * (NS * pl->fmm_mp + NT * pl->fmm_kp);
   if (pl->ctx->budget && pl->ctx->in_use + bytes > pl->ctx->budget) return hipErrorOutOfMemory;
   double *vsrc = nullptr, *wtgt = nullptr;
-  int2* tt = nullptr;
   hipError_t e;
   if ((e = hipMalloc((void**)&vsrc, sizeof(double) * NS * pl->fmm_mp)) != hipSuccess ||
-      (e = hipMalloc((void**)&wtgt, sizeof(double) * NT * pl->fmm_kp)) != hipSuccess ||
-      (e = hipMalloc((void**)&tt, sizeof(int2) * std::max<size_t>(tiles.size(), 1))) != hipSuccess) {
-    for (void* x : {(void*)vsrc, (void*)wtgt, (void*)tt})
+      (e = hipMalloc((void**)&wtgt, sizeof(double) * NT * pl->fmm_kp)) != hipSuccess) {
+    for (void* x : {(void*)vsrc, (void*)wtgt})
       if (x) (void)hipFree(x);
     return e;
   }
@@ -997,18 +1000,14 @@ hipError_t fmm_prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st) {
   k_fmm_wtgt<<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, pl->fmm_tgt_perm, NT, pl->fmm_x0, pl->fmm_y0, sL, L, p,
                                                 pl->fmm_kp, wtgt);
   e = hipGetLastError();
-  if (e == hipSuccess && !tiles.empty())
-    e = hipMemcpyAsync(tt, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
-    for (void* x : {(void*)vsrc, (void*)wtgt, (void*)tt}) (void)hipFree(x);
+    for (void* x : {(void*)vsrc, (void*)wtgt}) (void)hipFree(x);
     return e;
   }
-  for (void* x : {(void*)vsrc, (void*)wtgt, (void*)tt}) pl->allocs.push_back(x);
+  for (void* x : {(void*)vsrc, (void*)wtgt}) pl->allocs.push_back(x);
   pl->fmm_vsrc = vsrc;
   pl->fmm_wtgt = wtgt;
-  pl->fmm_ttile = tt;
-  pl->fmm_n_ttiles = (int64_t)tiles.size();
   pl->bytes += bytes;
   pl->ctx->in_use += bytes;
   return hipSuccess;
@@ -1091,9 +1090,10 @@ hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out
                                                           Lall + pl->fmm_off[l - 1] * P1, l, p, pl->fmm_l2l,
                                                           Lall + pl->fmm_off[l] * P1);
     }
-    k_fmm_leaf<<<(unsigned)((nleaf * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-        Lall + pl->fmm_off[L] * P1, pl->fmm_sxy, Qs, pl->fmm_src_ptr, pl->fmm_tgt_perm, pl->fmm_tgt_ptr, pl->xt,
-        pl->yt, L, pl->fmm_x0, pl->fmm_y0, sL, p, pl->logtab, R, r, out);
+    if (pl->fmm_n_ttiles > 0)
+      k_fmm_leaf<<<(unsigned)((pl->fmm_n_ttiles * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+          Lall + pl->fmm_off[L] * P1, pl->fmm_ttile, pl->fmm_n_ttiles, pl->fmm_sxy, Qs, pl->fmm_src_ptr,
+          pl->fmm_tgt_perm, pl->fmm_tgt_ptr, pl->xt, pl->yt, L, pl->fmm_x0, pl->fmm_y0, sL, p, pl->logtab, R, r, out);
     if (n_launches) *n_launches += 3 * L - 3;
   }
   return hipGetLastError();
