@@ -90,6 +90,72 @@ __device__ __forceinline__ void koornwinder_emit(double x, double y, Emit&& emit
   }
 }
 
+// acc[k] += w K_k(x, y) for every k: the same basis with the accumulation
+// folded into the recurrences.  Q_m is carried as Qh_m = d_m Q_m with
+// d_{m+1} = d_m (m+1)/(2m+1), which turns its recurrence into
+//   Qh_{m+1} = s Qh_m - e_m (1-x)^2 Qh_{m-1},  e_m = d_{m+1} m / ((m+1) d_{m-1}),
+// and each Jacobi sequence is carried already multiplied by c_mn / d_m,
+// with the three-term coefficients divided accordingly (all of them
+// compile-time constants), so that a basis function costs one FMA into acc
+// with w Qh_m formed once per m.  About 40% fewer operations per point than
+// emit + FMA; the values agree to rounding.
+template <int P>
+__device__ __forceinline__ void koornwinder_acc(double x, double y, double w, double* acc) {
+  const double t = 1.0 - x;
+  const double s = 2.0 * y - t;
+  const double tt = t * t;
+  const double z = 2.0 * x - 1.0;
+  double d[P + 2];
+  d[0] = 1.0;
+  d[1] = 1.0;
+#pragma unroll
+  for (int m = 1; m <= P; ++m) d[m + 1] = d[m] * (m + 1.0) / (2.0 * m + 1.0);
+  // m ascending, Qh_m advanced after its Jacobi sequence (two Qh live)
+  double qm1 = 0.0, qm = 1.0;
+#pragma unroll
+  for (int m = 0; m <= P; ++m) {
+    const double wq = w * qm;
+    const double a = 2.0 * m + 1.0;
+    double jm2 = 0.0, jm1 = 0.0, cprev = 1.0, cprev2 = 1.0;
+#pragma unroll
+    for (int k = 0; k + m <= P; ++k) {
+      const int n = m + k;
+      const double cmn = __builtin_sqrt(2.0 * (2.0 * m + 1.0) * (n + 1.0)) / d[m];
+      double jk;
+      if (k == 0) {
+        jk = cmn;
+      } else if (k == 1) {
+        jk = fma(0.5 * (a + 2.0) * cmn, z, 0.5 * a * cmn);
+      } else {
+        const double kk = (double)k;
+        const double c1 = (2.0 * kk + a - 1.0);
+        const double c2 = (2.0 * kk + a) * (2.0 * kk + a - 2.0);
+        const double c3 = 2.0 * (kk + a - 1.0) * (kk - 1.0) * (2.0 * kk + a);
+        const double inv = 1.0 / (2.0 * kk * (kk + a) * (2.0 * kk + a - 2.0));
+        const double al = c1 * c2 * inv * (cmn / cprev), be = c1 * a * a * inv * (cmn / cprev);
+        const double ga = c3 * inv * (cmn / cprev2);
+        jk = fma(fma(al, z, be), jm1, -ga * jm2);
+      }
+      cprev2 = cprev;
+      cprev = cmn;
+      jm2 = jm1;
+      jm1 = jk;
+      acc[n * (n + 1) / 2 + m] = fma(jk, wq, acc[n * (n + 1) / 2 + m]);
+    }
+    if (m < P) {
+      double qn;
+      if (m == 0) {
+        qn = s;
+      } else {
+        const double e = d[m + 1] * ((double)m / (m + 1.0)) / d[m - 1];
+        qn = fma(s, qm, (-e * tt) * qm1);
+      }
+      qm1 = qm;
+      qm = qn;
+    }
+  }
+}
+
 // The naive ball test of the near-field ablation (near: within kappa R of
 // the centroid c, R = the largest vertex distance from c), evaluated with
 // separately rounded operations in a fixed order (no contraction into

@@ -301,7 +301,7 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
         }
         const double dx = x - yx, dy = y - yy;
         const double w = 0.5 * vp_log(dx * dx + dy * dy, tab) * s_nw[nd] * ss * ss * jac;
-        koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { acc[k] = fma(w, v, acc[k]); });
+        koornwinder_acc<P>(xi1, xi2, w, acc);
       }
       __syncthreads();
       double* sw = cur;
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
             }
             const double dx = x - yx, dy = y - yy;
             const double w = 0.5 * vp_log(dx * dx + dy * dy, tab) * s_nw[nd] * ss * ss * jac;
-            koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { acc[k] = fma(w, v, acc[k]); });
+            koornwinder_acc<P>(xi1, xi2, w, acc);
           }
         }
       }
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
           const double jac = vp_blend_jac(Ax, Ay, Bx, By, Cx, Cy, cf, a.cv.deg, yr1, yr2, qx, qy);
           const double lam = 0.5 * vp_log((qx - x) * (qx - x) + (qy - y) * (qy - y), tab) - vp_log(rr, tab);
           const double w = h * ws * (s_ca[ir] * lam + s_cb[ir]) * jac;
-          koornwinder_emit<P>(yr1, yr2, [&](int k, double v) { acc[k] = fma(w, v, acc[k]); });
+          koornwinder_acc<P>(yr1, yr2, w, acc);
         }
       }
     } else {
@@ -514,7 +514,7 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
         for (int ir = 0; ir < a.nr; ++ir) {
           const double rr = s_rr[ir];
           const double w = hws * fma(s_ra[ir], hlog, s_rb[ir]);
-          koornwinder_emit<P>(fma(rr, d1, z1), fma(rr, d2, z2), [&](int k, double v) { acc[k] = fma(w, v, acc[k]); });
+          koornwinder_acc<P>(fma(rr, d1, z1), fma(rr, d2, z2), w, acc);
         }
       }
     }
