@@ -79,6 +79,52 @@ __device__ __forceinline__ int dyadic_count(double len, double d, int cap) {
   return n;
 }
 
+// Sum of C per-lane slots over the wavefront, scattered: at each offset
+// (32, 16, ..., 1) a lane and its partner (lane ^ OFF) hold the same
+// segment of row indices; the lane with the OFF bit clear keeps the first
+// half of the slots, its partner the second half (zero-padded when C is
+// odd), and each adds what the other sends.  Once one slot is left the
+// remaining offsets are a plain butterfly.  base and len track the row
+// index of slot 0 and the number of valid slots; the lanes that end with
+// duplicates (bits of the butterfly offsets set) report len = 0.
+template <int C, int OFF>
+struct ReduceScatter {
+  static __device__ __forceinline__ void run(double* v, int lane, int& base, int& len) {
+    constexpr int H = (C + 1) / 2;
+    const bool up = (lane & OFF) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double lo = v[i];
+      const double hi = (H + i < C) ? v[H + i] : 0.0;
+      const double recv = __shfl_xor(up ? lo : hi, OFF);
+      v[i] = (up ? hi : lo) + recv;
+    }
+    if (up) {
+      base += H;
+      len = max(len - H, 0);
+    } else {
+      len = min(len, H);
+    }
+    ReduceScatter<H, OFF / 2>::run(v, lane, base, len);
+  }
+};
+template <int OFF>
+struct ReduceScatter<1, OFF> {
+  static __device__ __forceinline__ void run(double* v, int lane, int& base, int& len) {
+#pragma unroll
+    for (int o = OFF; o > 0; o >>= 1) v[0] += __shfl_xor(v[0], o);
+    if (lane & (2 * OFF - 1)) len = 0;
+  }
+};
+template <int C>
+struct ReduceScatter<C, 0> {
+  static __device__ __forceinline__ void run(double*, int, int&, int&) {}
+};
+template <>
+struct ReduceScatter<1, 0> {
+  static __device__ __forceinline__ void run(double*, int, int&, int&) {}
+};
+
 // kCurved: the mesh has curved triangles (the straight-only instance carries
 // none of their code)
 template <int P, bool kCurved>
@@ -523,12 +569,12 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
 
   // ---- wave reduction and store ----
   double* out = a.rows + (size_t)pr * NP;
+  {
+    int base = 0, len = NP;
+    ReduceScatter<NP, 32>::run(acc, lane, base, len);
 #pragma unroll
-  for (int k = 0; k < NP; ++k) {
-    double v = acc[k];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (lane == (k & 63)) out[k] = v * kInv2Pi;
+    for (int i = 0; i < 2; ++i)
+      if (i < len) out[base + i] = acc[i] * kInv2Pi;
   }
   if (lane == 0) {
     if (n_leaves) atomicAdd((unsigned long long*)&a.stats[0], (unsigned long long)n_leaves);
