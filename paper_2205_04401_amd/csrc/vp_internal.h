@@ -307,12 +307,14 @@ __device__ __forceinline__ void vp_log_parts(double x, const double2* tab, doubl
   const double2 t = tab[i];
   // m inv_c - 1 with m = x 2^-e: scale the table entry instead of x
   const double r = fma(x, ldexp(t.x, neg_e), -1.0);
-  double p = fma(r, 0.2, -0.25);
-  p = fma(r, p, 1.0 / 3.0);
-  p = fma(r, p, -0.5);
-  p = fma(r * r, p, r);
+  // log1p(r) = r b(r), b = 1 - r/2 + r^2/3 - r^3/4 + r^4/5 by Horner; the
+  // table term joins in the last FMA
+  double b = fma(r, 0.2, -0.25);
+  b = fma(r, b, 1.0 / 3.0);
+  b = fma(r, b, -0.5);
+  b = fma(r, b, 1.0);
   e_out = -(double)neg_e;
-  rest_out = t.y + p;
+  rest_out = fma(b, r, t.y);
 }
 
 __device__ __forceinline__ double vp_log(double x, const double2* tab) {
@@ -336,9 +338,10 @@ __device__ __forceinline__ void vp_log_wide_parts(double x, const double2* tab, 
   const unsigned i = ((unsigned)__double2hiint(x) >> (20 - kFarLogBits)) & (unsigned)(kFarLogTab - 1);
   const double2 t = tab[i];
   const double r = fma(m, t.x, -1.0);
-  const double p = fma(r * r, fma(r, 1.0 / 3.0, -0.5), r);
+  // log1p(r) = r (1 - r/2 + r^2/3): three FMAs including the table term
+  const double b = fma(fma(r, 1.0 / 3.0, -0.5), r, 1.0);
   e_out = (double)e;
-  rest_out = t.y + p;
+  rest_out = fma(b, r, t.y);
 }
 
 }  // namespace vp
