@@ -642,10 +642,13 @@ hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t s
   a.rows = pl->rows;
   a.flag = d_flag;
   a.stats = d_stats;
-  // one 64-lane workgroup per pair (the dispatcher balances the uneven
-  // pairs), grid-stride beyond 2^25 workgroups (a launch must stay below
-  // 2^32 work-items)
-  dim3 grid((unsigned)std::min<int64_t>(pl->n_pairs, 1 << 25));
+  // one 64-lane workgroup per 8 pairs (strided over the pair list), so that
+  // the tables a workgroup stages in LDS serve several pairs while the
+  // dispatcher still balances workgroups of uneven cost; grid-stride beyond
+  // 2^25 workgroups (a launch must stay below 2^32 work-items).  A single
+  // device-wide work counter instead serialises on its atomic across the XCDs.
+  constexpr int64_t kPairsPerGroup = 8;
+  dim3 grid((unsigned)std::min<int64_t>((pl->n_pairs + kPairsPerGroup - 1) / kPairsPerGroup, 1 << 25));
   const bool curved = m->n_curved > 0;
   const size_t lds = sizeof(double) * (3 * (size_t)a.nn + 2 * (size_t)a.nl + 3 * (size_t)a.nr + 3 * (size_t)a.n_rc);
 #define VP_ROWS(PV)                                                   \

@@ -172,6 +172,33 @@ def test_c1_end_to_end(c1):
     assert err <= REL_E2E
 
 
+@pytest.mark.parametrize("p", list(range(1, 11)))
+def test_every_order_small_square(vp_ctx, p):
+    """Orders 1 to 10, every instantiation of the per-order kernels (basis,
+    coefficients, correction rows and their wavefront reduction, apply) on a
+    3 x 3 unit square with the staggered targets: the potential at up to 64
+    seeded targets against the oracle, and the two far-sum precisions."""
+    q, eps = 8, 1e-12
+    vq, tq = W.unit_square(3, "/")
+    vt, tt = W.unit_square(3, "\\")
+    nodes = rules.interp_nodes(p)
+    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    F = W.sample_density(W.gaussian_bump, vq, tq, nodes)
+    sample = np.sort(np.random.default_rng(100 + p).choice(len(tg), min(64, len(tg)), replace=False))
+    say(f"order {p}: {len(tg)} targets, {len(sample)} sampled")
+    mesh = vp_ctx.mesh(vq, tq)
+    plan = vp_ctx.plan(mesh, p, q, eps, tg)
+    u = plan.execute(F)
+    u_mixed = plan.execute(F, mixed=True)
+    plan.close()
+    mesh.close()
+    ref = potential.Oracle(vq, tq, p, q, eps).evaluate(F, tg[sample])
+    err = rel_linf(u[sample], ref)
+    say(f"order {p}: rel {err:.2e}")
+    assert err <= REL_E2E
+    assert rel_linf(u_mixed[sample], ref) <= 1e-6
+
+
 REL_MIXED = 1e-6
 
 
