@@ -290,6 +290,50 @@ def copy_probe(n_bytes=1 << 29, reps=3):
     print(json.dumps({"copy_probe_bytes": n_bytes, "reps": reps}), flush=True)
 
 
+def interp_section(ctx, u_d, p, n_pts=1 << 20, reps=5):
+    """The potential anywhere (Sec. 3.5): the evaluation's result at the
+    staggered target mesh's nodes interpolated at n_pts seeded points of the
+    star (radius fraction sqrt(U) of 0.98 r(theta)).  Point location runs
+    once with host arrays (PCIe-inclusive); the evaluation with device
+    arrays is timed over reps calls on the context's stream."""
+    import torch
+    from paper_2205_04401_amd import vp
+    from paper_2205_04401_amd import workloads as W
+    vt, tt = W.star_mesh(n_tri=20000, n_boundary=2000, seed=21, staggered=True)
+    tmesh = ctx.mesh(vt, tt)
+    it = vp.Interp(ctx, tmesh, p)
+    rng = np.random.default_rng(23)
+    th = rng.uniform(0.0, 2.0 * math.pi, n_pts)
+    rad = np.sqrt(rng.uniform(0.0, 1.0, n_pts)) * 0.98 * W.star_radius(th)
+    pts = np.stack([rad * np.cos(th), rad * np.sin(th)], axis=1)
+    t0 = time.perf_counter()
+    tri, ref = it.locate(pts)
+    t_loc = time.perf_counter() - t0
+    found = tri >= 0
+    tri_d = torch.from_numpy(np.ascontiguousarray(tri[found])).cuda()
+    ref_d = torch.from_numpy(np.ascontiguousarray(ref[found])).cuda()
+    n = int(found.sum())
+    u_nodes = u_d.reshape(len(tt), -1, 1).contiguous()
+    res = torch.empty((n, 1), dtype=torch.float64, device=u_d.device)
+    lib = vp.load()
+
+    def ev():
+        vp._check(lib.vp_interp_eval(it.h, 1, vp._ptr(u_nodes), n, vp._ptr(tri_d), vp._ptr(ref_d), vp._ptr(res),
+                                     vp.VP_DEVICE_PTRS))
+    ev()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ev()
+    torch.cuda.synchronize()
+    t_ev = (time.perf_counter() - t0) / reps
+    it.close()
+    tmesh.close()
+    return {"workload": f"{n_pts} seeded points in the star, u at the {len(tt)}-triangle target mesh's "
+                        f"order-{p} nodes", "located": n, "locate_points_per_s_host_arrays": n_pts / t_loc,
+            "eval_points_per_s": n / t_ev, "eval_ms": t_ev * 1e3}
+
+
 def run(args):
     import torch
     from paper_2205_04401_amd import vp
@@ -440,6 +484,10 @@ def run(args):
                 line["rel_diff_vs_direct"] = float((out - u_direct).abs().max() / u_direct.abs().max())
             result["fmm"].append(line)
             print(json.dumps({"fmm": line}), flush=True)
+    if not args.no_interp:
+        step(q)  # u at the targets (the target mesh's nodes) into out
+        result["interp"] = interp_section(ctx, out, p)
+        print(json.dumps({"interp": result["interp"]}), flush=True)
     if not args.no_small:
         result["small_case"] = small_case(ctx)
     if args.batched_rhs:
@@ -467,6 +515,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-small", action="store_true", help="skip the unit-square latency section")
     ap.add_argument("--no-fmm", action="store_true", help="skip the FMM far-sum section")
+    ap.add_argument("--no-interp", action="store_true", help="skip the interpolation section")
     ap.add_argument("--fmm-terms", type=int, default=32)
     ap.add_argument("--serving-requests", type=int, default=160)
     ap.add_argument("--batched-rhs", type=int, default=64, help="densities of the batched section (0: skip)")
