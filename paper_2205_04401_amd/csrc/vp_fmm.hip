@@ -40,6 +40,7 @@ namespace vp {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kFmmMaxLevels = 10;  // finest quadtree level
 
 inline unsigned blocks_for(int64_t n, int b = kBlock) {
   const int64_t nb = (n + b - 1) / b;
@@ -209,16 +210,38 @@ __global__ void k_fmm_m2m(const double2* __restrict__ Mc, const int32_t* __restr
 // zeros.
 typedef double vp_d4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(kBlock) void k_fmm_m2l(const double2* __restrict__ M, const int32_t* __restrict__ cnt_s,
-                                                    const int32_t* __restrict__ cnt_t, int l, int p, int MP, int KP,
-                                                    double log_s, const double* __restrict__ m2l,
-                                                    double2* __restrict__ Lc) {
+// All levels of the M2L pass in one launch (a level's translations read
+// only multipoles, which are complete, and write only that level's local
+// expansions): wavefronts are numbered level after level, coarsest first,
+// so the few long-running wavefronts of the coarse levels start at once and
+// overlap the many of the finest.
+struct FmmLevels {
+  int l0, l1;               // the levels l0..l1
+  int64_t wave_end[kFmmMaxLevels + 1];  // wavefronts of levels l0..l (cumulative)
+  int64_t off[kFmmMaxLevels + 1];       // first box of level l
+  double log_s[kFmmMaxLevels + 1];      // log of level l's box width
+};
+
+__global__ __launch_bounds__(kBlock) void k_fmm_m2l(const double2* __restrict__ M_all,
+                                                    const int32_t* __restrict__ cnt_s_all,
+                                                    const int32_t* __restrict__ cnt_t_all, FmmLevels lv, int p,
+                                                    int MP, int KP, const double* __restrict__ m2l,
+                                                    double2* __restrict__ Lc_all) {
   const int P1 = p + 1;
+  const int64_t w_all = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (w_all >= lv.wave_end[lv.l1]) return;  // the whole wavefront
+  int l = lv.l0;
+  while (w_all >= lv.wave_end[l]) ++l;
+  const int64_t w = w_all - (l > lv.l0 ? lv.wave_end[l - 1] : 0);
+  const double2* __restrict__ M = M_all + lv.off[l] * P1;
+  const int32_t* __restrict__ cnt_s = cnt_s_all + lv.off[l];
+  const int32_t* __restrict__ cnt_t = cnt_t_all + lv.off[l];
+  double2* __restrict__ Lc = Lc_all + lv.off[l] * P1;
+  const double log_s = lv.log_s[l];
   const int n = 1 << l;
   const int64_t nb = (int64_t)n * n;
   const int tiles = MP / 16;
   const int lane = (int)(threadIdx.x & 63), r16 = lane & 15, kq = lane >> 4;
-  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t bg = w / tiles;
   const int t = (int)(w - bg * tiles);
   if (bg * 16 >= nb) return;  // the whole wavefront
@@ -237,12 +260,34 @@ __global__ __launch_bounds__(kBlock) void k_fmm_m2l(const double2* __restrict__ 
     const double2* src = M + (use ? (int64_t)jy * n + jx : 0) * P1;
     if (use) a0 += src[0].x;
     const double* A = m2l + ((int64_t)o * MP + 16 * t + r16) * KP;
-    for (int s4 = 0; s4 < KP / 4; ++s4) {
-      const int k = 4 * s4 + kq;
-      const int kc = k < P1 ? k : (k < 2 * P1 ? k - P1 : 0);
-      const double2 mv = src[kc];
-      const double bv = (use && k < 2 * P1) ? (k < P1 ? mv.x : mv.y) : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[k], bv, acc, 0, 0, 0);
+    const double* srcd = reinterpret_cast<const double*>(src);  // re, im interleaved
+    // the operands of 8 steps are loaded before their 8 MFMAs, so that one
+    // cache round trip serves 8 steps (indices clamped into the operator
+    // row and the box past the last step; such steps are skipped)
+    const int KS = KP / 4;
+    for (int s0 = 0; s0 < KS; s0 += 8) {
+      double av[8], bv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool in = s0 + u < KS;  // the whole wavefront alike
+        const int k = 4 * (s0 + u) + kq;
+        const int kc2 = k < P1 ? 2 * k : (k < 2 * P1 ? 2 * (k - P1) + 1 : 0);
+        av[u] = A[in ? k : kq];
+        bv[u] = srcd[in ? kc2 : 0];
+      }
+      // empty register constraints once all 16 loads are issued: they keep
+      // the loads unconditional (the compiler otherwise turns the selects
+      // below into branches around them, each with a wait inside)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) asm volatile("" : "+v"(bv[u]));
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = 4 * (s0 + u) + kq;
+        bv[u] = (s0 + u < KS && use && k < 2 * P1) ? bv[u] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (s0 + u < KS) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
     }
   }
   if (b < nb) {
@@ -498,16 +543,27 @@ __global__ void k_fmmb_l2l(const int32_t* __restrict__ cnt_t, const double* __re
 // box, so a whole offset is used or skipped.  The level's a_0 log s term
 // is added per column to row 0.
 template <int NB>
-__global__ __launch_bounds__(kBlock) void k_fmmb_m2l(const double* __restrict__ Mb, const int32_t* __restrict__ cnt_s,
-                                                     const int32_t* __restrict__ cnt_t, int l, int MP, int KP,
-                                                     double log_s, const double* __restrict__ m2l,
-                                                     double* __restrict__ Lb) {
+__global__ __launch_bounds__(kBlock) void k_fmmb_m2l(const double* __restrict__ Mb_all,
+                                                     const int32_t* __restrict__ cnt_s_all,
+                                                     const int32_t* __restrict__ cnt_t_all, FmmLevels lv, int MP,
+                                                     int KP, const double* __restrict__ m2l,
+                                                     double* __restrict__ Lb_all) {
   constexpr int C = 16 * NB;
+  // all levels in one launch, numbered as in k_fmm_m2l
+  const int64_t w_all = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (w_all >= lv.wave_end[lv.l1]) return;  // the whole wavefront
+  int l = lv.l0;
+  while (w_all >= lv.wave_end[l]) ++l;
+  const int64_t w = w_all - (l > lv.l0 ? lv.wave_end[l - 1] : 0);
+  const double* __restrict__ Mb = Mb_all + lv.off[l] * KP * C;
+  const int32_t* __restrict__ cnt_s = cnt_s_all + lv.off[l];
+  const int32_t* __restrict__ cnt_t = cnt_t_all + lv.off[l];
+  double* __restrict__ Lb = Lb_all + lv.off[l] * KP * C;
+  const double log_s = lv.log_s[l];
   const int n = 1 << l;
   const int64_t nb = (int64_t)n * n;
   const int tiles = MP / 16;
   const int lane = (int)(threadIdx.x & 63), r16 = lane & 15, kq = lane >> 4;
-  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t b = w / tiles;
   const int t = (int)(w - b * tiles);
   if (b >= nb) return;  // the whole wavefront
@@ -532,6 +588,9 @@ __global__ __launch_bounds__(kBlock) void k_fmmb_m2l(const double* __restrict__ 
 #pragma unroll
       for (int u = 0; u < NB; ++u) a0[u] += X[16 * u];
       const double* A = m2l + ((int64_t)o * MP + 16 * t + r16) * KP;
+      // (each A operand serves NB MFMA steps, which hide its load: batching
+      // the loads of several steps here raised the registers and cost
+      // occupancy instead)
       for (int s4 = 0; s4 < KP / 4; ++s4) {
         const double av = A[4 * s4 + kq];
         const double* x = X + (int64_t)(4 * s4 + kq) * C;
@@ -815,7 +874,7 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
   pl->fmm_width = w;
   // levels: about `leaf` sources per leaf box of the full grid
   int L = (int)std::lround(std::log((double)std::max<int64_t>(NS, 1) / leaf) / std::log(4.0));
-  L = std::min(std::max(L, 2), 10);
+  L = std::min(std::max(L, 2), kFmmMaxLevels);
   pl->fmm_levels = L;
   const int n = 1 << L;
   const int64_t nleaf = (int64_t)n * n;
@@ -1029,6 +1088,23 @@ hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out
   const double sL = pl->fmm_width / n;
   // blocks of 16 densities on the matrix cores, up to 4 blocks per pass
   const int MP = pl->fmm_mp, KP = pl->fmm_kp, tiles = MP / 16;
+  // the M2L launches' level table (levels 2..L): one wavefront per (box,
+  // row tile) for the blocks of densities, per (16 boxes, row tile) for one
+  FmmLevels lv{}, lv1{};
+  lv.l0 = lv1.l0 = 2;
+  lv.l1 = lv1.l1 = L;
+  {
+    int64_t waves = 0, waves1 = 0;
+    for (int l = 2; l <= L; ++l) {
+      const int64_t nbl = (int64_t)1 << (2 * l);
+      waves += nbl * tiles;
+      waves1 += (nbl + 15) / 16 * tiles;
+      lv.wave_end[l] = waves;
+      lv1.wave_end[l] = waves1;
+      lv.off[l] = lv1.off[l] = pl->fmm_off[l];
+      lv.log_s[l] = lv1.log_s[l] = std::log(pl->fmm_width / (double)(1 << l));
+    }
+  }
   int64_t c0 = 0;
   while (pl->fmm_vsrc && R - c0 >= 16) {
     const int nbk = R - c0 >= 64 ? 4 : R - c0 >= 32 ? 2 : 1;
@@ -1044,16 +1120,13 @@ hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out
                                                   pl->fmm_cnt_src + pl->fmm_off[l + 1], l, p, KP, C, pl->fmm_m2m,   \
                                                   Mb + pl->fmm_off[l] * KP * C);                                    \
   }                                                                                                               \
-  for (int l = 2; l <= L; ++l) {                                                                                  \
+  k_fmmb_m2l<NBV><<<(unsigned)((lv.wave_end[L] * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(                    \
+      Mb, pl->fmm_cnt_src, pl->fmm_cnt_tgt, lv, MP, KP, pl->fmm_m2l, Lb);                                          \
+  for (int l = 3; l <= L; ++l) {                                                                                  \
     const int64_t nbl = (int64_t)1 << (2 * l);                                                                     \
-    const double log_s = std::log(pl->fmm_width / (double)(1 << l));                                              \
-    k_fmmb_m2l<NBV><<<(unsigned)((nbl * tiles * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(                      \
-        Mb + pl->fmm_off[l] * KP * C, pl->fmm_cnt_src + pl->fmm_off[l], pl->fmm_cnt_tgt + pl->fmm_off[l], l, MP, KP, \
-        log_s, pl->fmm_m2l, Lb + pl->fmm_off[l] * KP * C);                                                          \
-    if (l > 2)                                                                                                    \
-      k_fmmb_l2l<<<blocks_for(nbl * P1 * C), kBlock, 0, st>>>(pl->fmm_cnt_tgt + pl->fmm_off[l],                     \
-                                                             Lb + pl->fmm_off[l - 1] * KP * C, l, p, KP, C,          \
-                                                             pl->fmm_l2l, Lb + pl->fmm_off[l] * KP * C);             \
+    k_fmmb_l2l<<<blocks_for(nbl * P1 * C), kBlock, 0, st>>>(pl->fmm_cnt_tgt + pl->fmm_off[l],                       \
+                                                           Lb + pl->fmm_off[l - 1] * KP * C, l, p, KP, C,            \
+                                                           pl->fmm_l2l, Lb + pl->fmm_off[l] * KP * C);               \
   }                                                                                                               \
   if (pl->fmm_n_ttiles > 0)                                                                                       \
     k_fmmb_leaf<NBV><<<(unsigned)((pl->fmm_n_ttiles * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(                 \
@@ -1065,7 +1138,7 @@ hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out
       default: VP_FMMB(1); break;
     }
 #undef VP_FMMB
-    if (n_launches) *n_launches += 3 * L - 2;
+    if (n_launches) *n_launches += 2 * L - 1;
     c0 += C;
   }
   // the remaining densities one at a time
@@ -1078,23 +1151,19 @@ hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out
       k_fmm_m2m<<<blocks_for(nt), kBlock, 0, st>>>(Mall + pl->fmm_off[l + 1] * P1, pl->fmm_cnt_src + pl->fmm_off[l + 1],
                                                    l, p, pl->fmm_m2m, Mall + pl->fmm_off[l] * P1);
     }
-    for (int l = 2; l <= L; ++l) {
+    k_fmm_m2l<<<(unsigned)((lv1.wave_end[L] * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        Mall, pl->fmm_cnt_src, pl->fmm_cnt_tgt, lv1, p, MP, KP, pl->fmm_m2l, Lall);
+    for (int l = 3; l <= L; ++l) {
       const int64_t nbl = (int64_t)1 << (2 * l);
-      const double log_s = std::log(pl->fmm_width / (double)(1 << l));
-      const int64_t waves = (nbl + 15) / 16 * (pl->fmm_mp / 16);
-      k_fmm_m2l<<<(unsigned)((waves * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-          Mall + pl->fmm_off[l] * P1, pl->fmm_cnt_src + pl->fmm_off[l], pl->fmm_cnt_tgt + pl->fmm_off[l], l, p,
-          pl->fmm_mp, pl->fmm_kp, log_s, pl->fmm_m2l, Lall + pl->fmm_off[l] * P1);
-      if (l > 2)
-        k_fmm_l2l<<<blocks_for(nbl * P1), kBlock, 0, st>>>(pl->fmm_cnt_tgt + pl->fmm_off[l],
-                                                          Lall + pl->fmm_off[l - 1] * P1, l, p, pl->fmm_l2l,
-                                                          Lall + pl->fmm_off[l] * P1);
+      k_fmm_l2l<<<blocks_for(nbl * P1), kBlock, 0, st>>>(pl->fmm_cnt_tgt + pl->fmm_off[l],
+                                                        Lall + pl->fmm_off[l - 1] * P1, l, p, pl->fmm_l2l,
+                                                        Lall + pl->fmm_off[l] * P1);
     }
     if (pl->fmm_n_ttiles > 0)
       k_fmm_leaf<<<(unsigned)((pl->fmm_n_ttiles * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
           Lall + pl->fmm_off[L] * P1, pl->fmm_ttile, pl->fmm_n_ttiles, pl->fmm_sxy, Qs, pl->fmm_src_ptr,
           pl->fmm_tgt_perm, pl->fmm_tgt_ptr, pl->xt, pl->yt, L, pl->fmm_x0, pl->fmm_y0, sL, p, pl->logtab, R, r, out);
-    if (n_launches) *n_launches += 3 * L - 3;
+    if (n_launches) *n_launches += 2 * L - 1;
   }
   return hipGetLastError();
 }
