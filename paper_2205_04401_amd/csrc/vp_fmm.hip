@@ -53,11 +53,6 @@ __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {  // a
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
 }
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // per-block min x, min y, max x, max y over sources and targets
 __global__ void k_fmm_bbox_partial(const double2* __restrict__ sxy, int64_t n_src, const double* __restrict__ xt,
@@ -124,47 +119,64 @@ __global__ void k_fmm_gather2(const double2* __restrict__ in, const int32_t* __r
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) out[i] = in[perm[i]];
 }
 
-// Multipole of every leaf box (one wavefront each): lanes take 64 sources
-// at a time; for each power k the wavefront sums Q t^k (t = (w - c)/s) and
-// lane k keeps ah_k = -sum Q t^k / k (lane 0: a_0 = sum Q).  Also writes
-// the charges in leaf order (Qs) for the near-field sum.
+// Multipole of every leaf box (one wavefront each).  Lane l = g + 8 sl
+// sums Q t^k (t = (w - c)/s) for the powers k = g + 8 i (i = 0..7, k <= p)
+// over the box's sources sl, sl + 8, ...: t^g by binary powering, then
+// repeated products with t^8, so a lane holds 8 complex sums whatever p is
+// and the wavefront reduces once, over the 8 source lanes, at the end (a
+// wavefront sum per power and 64 sources cost more than the powers).  The
+// lanes with sl = 0 then hold ah_k = -sum Q t^k / k (a_0 = sum Q).  Also
+// writes the charges in leaf order (Qs) for the near-field sum.
 __global__ __launch_bounds__(kBlock) void k_fmm_p2m(const double2* __restrict__ sxy_s,
                                                     const int32_t* __restrict__ perm,
                                                     const int64_t* __restrict__ ptr, const double* __restrict__ Q,
                                                     int64_t R, int64_t r, int L, double x0, double y0, double s,
                                                     int p, double2* __restrict__ M, double* __restrict__ Qs) {
-  const int lane = (int)(threadIdx.x & 63);
+  const int lane = (int)(threadIdx.x & 63), g = lane & 7, sl = lane >> 3;
   const int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int n = 1 << L;
   if (b >= (int64_t)n * n) return;  // the whole wavefront
   const int ix = (int)(b % n), iy = (int)(b / n);
   const double cx = x0 + (ix + 0.5) * s, cy = y0 + (iy + 0.5) * s, inv_s = 1.0 / s;
-  double2 acc = make_double2(0.0, 0.0);
+  double2 acc[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) acc[i] = make_double2(0.0, 0.0);
   const int64_t j1 = ptr[b + 1];
-  for (int64_t j0 = ptr[b]; j0 < j1; j0 += 64) {
-    const int64_t j = j0 + lane;
-    const bool act = j < j1;
-    double q = 0.0;
-    double2 t = make_double2(0.0, 0.0);
-    if (act) {
-      q = Q[(int64_t)perm[j] * R + r];
-      Qs[j] = q;
-      const double2 w = sxy_s[j];
-      t = make_double2((w.x - cx) * inv_s, (w.y - cy) * inv_s);
+  for (int64_t j = ptr[b] + sl; j < j1; j += 8) {
+    const double q = Q[(int64_t)perm[j] * R + r];
+    if (g == 0) Qs[j] = q;
+    const double2 w = sxy_s[j];
+    const double2 t = make_double2((w.x - cx) * inv_s, (w.y - cy) * inv_s);
+    // v = q t^g; t8 = t^8
+    double2 v = make_double2(q, 0.0), t8 = t;
+#pragma unroll
+    for (int bit = 0; bit < 3; ++bit) {
+      if ((g >> bit) & 1) v = cmul(v, t8);
+      t8 = cmul(t8, t8);
     }
-    const double s0 = wave_sum(q);
-    if (lane == 0) acc.x += s0;
-    double2 pw = make_double2(q, 0.0);  // q t^k
-    for (int k = 1; k <= p; ++k) {
-      pw = cmul(pw, t);
-      const double sx = wave_sum(pw.x), sy = wave_sum(pw.y);
-      if (lane == k) {
-        acc.x -= sx / k;
-        acc.y -= sy / k;
-      }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      acc[i].x += v.x;
+      acc[i].y += v.y;
+      if (i < 7) v = cmul(v, t8);
     }
   }
-  if (lane <= p) M[b * (p + 1) + lane] = acc;
+  // sum over the 8 source lanes (lane bits 3..5)
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int o = 8; o < 64; o <<= 1) {
+      acc[i].x += __shfl_xor(acc[i].x, o);
+      acc[i].y += __shfl_xor(acc[i].y, o);
+    }
+  if (sl == 0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = g + 8 * i;
+      if (k <= p) M[b * (p + 1) + k] = k == 0 ? make_double2(acc[i].x, 0.0)
+                                              : make_double2(-acc[i].x / k, -acc[i].y / k);
+    }
+  }
 }
 
 // Upward pass at level l: the box's multipole from its 4 children's
