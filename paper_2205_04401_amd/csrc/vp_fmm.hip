@@ -26,7 +26,7 @@
 //   k_fmm_m2l   16 boxes per wavefront: M2L over the interaction list on the
 //               FP64 matrix cores (real form of the complex operators)
 //   k_fmm_l2l   one thread per (box, coefficient): L2L from the parent
-//   k_fmm_leaf  one wavefront per 16 targets of a leaf box: the local
+//   k_fmm_leaf  one wavefront per 16 targets in leaf order: the local
 //               expansion plus the direct sum over the 3 x 3 adjacent boxes
 #include <hipcub/hipcub.hpp>
 
@@ -337,30 +337,30 @@ __global__ void k_fmm_l2l(const int32_t* __restrict__ cnt_t, const double2* __re
   Lc[g] = v;
 }
 
-// Leaf pass of one density: one wavefront per (leaf box, 16 of its
-// targets), 4 lanes per target that take every fourth source of the
-// adjacent boxes (a box holds about as many targets as a few 16-target
-// tiles, so the lanes stay busy where one lane per target left a 64-lane
-// wavefront half empty), joined by a butterfly over the 4; the first lane
-// of each target adds 2 Re of the local expansion (Horner).  The direct sum
-// is Q log(r^2 + 2^-100) over the sources of the 3 x 3 adjacent leaf boxes
-// (256-entry logarithm table in LDS, exponent part accumulated apart as in
-// the direct far sum).
+// Leaf pass of one density: one wavefront per 16 consecutive targets in
+// leaf order (across box boundaries: a box of ~17 targets would otherwise
+// leave a second, nearly empty tile), 4 lanes per target that take every
+// fourth source of the target's adjacent boxes, joined by a butterfly over
+// the 4; the first lane of each target adds 2 Re of its box's local
+// expansion (Horner).  The direct sum is Q log(r^2 + 2^-100) over the
+// sources of the 3 x 3 adjacent leaf boxes (256-entry logarithm table in
+// LDS, exponent part accumulated apart as in the direct far sum).
 __global__ __launch_bounds__(kBlock) void k_fmm_leaf(
-    const double2* __restrict__ Lc, const int2* __restrict__ ttile, int64_t n_tiles, const double2* __restrict__ sxy_s,
-    const double* __restrict__ Qs, const int64_t* __restrict__ sptr, const int32_t* __restrict__ tperm,
-    const int64_t* __restrict__ tptr, const double* __restrict__ xt, const double* __restrict__ yt, int L, double x0,
-    double y0, double s, int p, const double2* __restrict__ logtab, int64_t R, int64_t r, double* __restrict__ out) {
+    const double2* __restrict__ Lc, const int32_t* __restrict__ tbox, int64_t n_tgt,
+    const double2* __restrict__ sxy_s, const double* __restrict__ Qs, const int64_t* __restrict__ sptr,
+    const int32_t* __restrict__ tperm, const double* __restrict__ xt, const double* __restrict__ yt, int L,
+    double x0, double y0, double s, int p, const double2* __restrict__ logtab, int64_t R, int64_t r,
+    double* __restrict__ out) {
   __shared__ double2 tab[kLogTab + 1];
   for (int i = threadIdx.x; i <= kLogTab; i += kBlock) tab[i] = logtab[i];
   __syncthreads();
   const int lane = (int)(threadIdx.x & 63), r16 = lane & 15, kq = lane >> 4;
-  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (w >= n_tiles) return;  // the whole wavefront
+  const int64_t i0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 16;
+  if (i0 >= n_tgt) return;  // the whole wavefront
   const int n = 1 << L;
-  const int2 tl = ttile[w];
-  const int64_t b = tl.x, i = tl.y + r16, i1 = tptr[b + 1];
-  const bool act = i < i1;
+  const int64_t i = i0 + r16;
+  const bool act = i < n_tgt;
+  const int64_t b = tbox[act ? i : i0];
   const int ix = (int)(b % n), iy = (int)(b / n);
   const double cx = x0 + (ix + 0.5) * s, cy = y0 + (iy + 0.5) * s, inv_s = 1.0 / s;
   const int64_t t = act ? tperm[i] : 0;
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(kBlock) void k_fmm_leaf(
   double acc_e = 0.0, acc_r = 0.0;
   for (int dy = -1; dy <= 1; ++dy) {
     const int jy = iy + dy;
-    if (jy < 0 || jy >= n) continue;
+    if (!act || jy < 0 || jy >= n) continue;
     const int64_t row = (int64_t)jy * n;
     const int64_t j0 = sptr[row + max(ix - 1, 0)], j1 = sptr[row + min(ix + 1, n - 1) + 1];
     for (int64_t j = j0 + kq; j < j1; j += 4) {
@@ -1036,10 +1036,18 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
     pl->fmm_m2l_pairs = (int64_t)h_cnt[1];
   }
   pl->fmm_tgt_ptr_host = tp;
-  // the (leaf box, first target) work list of the leaf passes: 16-target tiles
+  // the (leaf box, first target) work list of the passes of 16+ densities
+  // (16-target tiles), and the leaf box of every target in leaf order
   std::vector<int2> tiles;
-  for (int64_t b = 0; b < nleaf; ++b)
+  std::vector<int32_t> tbox(std::max<int64_t>(NT, 1));
+  for (int64_t b = 0; b < nleaf; ++b) {
     for (int64_t i = tp[b]; i < tp[b + 1]; i += 16) tiles.push_back(make_int2((int)b, (int)i));
+    for (int64_t i = tp[b]; i < tp[b + 1]; ++i) tbox[i] = (int32_t)b;
+  }
+  if ((e = alloc((void**)&pl->fmm_tbox, sizeof(int32_t) * tbox.size())) != hipSuccess ||
+      (e = hipMemcpyAsync(pl->fmm_tbox, tbox.data(), sizeof(int32_t) * tbox.size(), hipMemcpyHostToDevice, st)) !=
+          hipSuccess)
+    return e;
   pl->fmm_n_ttiles = (int64_t)tiles.size();
   if ((e = alloc((void**)&pl->fmm_ttile, sizeof(int2) * std::max<size_t>(tiles.size(), 1))) != hipSuccess) return e;
   if (!tiles.empty() &&
@@ -1171,10 +1179,9 @@ hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out
                                                         Lall + pl->fmm_off[l - 1] * P1, l, p, pl->fmm_l2l,
                                                         Lall + pl->fmm_off[l] * P1);
     }
-    if (pl->fmm_n_ttiles > 0)
-      k_fmm_leaf<<<(unsigned)((pl->fmm_n_ttiles * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-          Lall + pl->fmm_off[L] * P1, pl->fmm_ttile, pl->fmm_n_ttiles, pl->fmm_sxy, Qs, pl->fmm_src_ptr,
-          pl->fmm_tgt_perm, pl->fmm_tgt_ptr, pl->xt, pl->yt, L, pl->fmm_x0, pl->fmm_y0, sL, p, pl->logtab, R, r, out);
+    k_fmm_leaf<<<(unsigned)(((pl->n_tgt + 15) / 16 * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        Lall + pl->fmm_off[L] * P1, pl->fmm_tbox, pl->n_tgt, pl->fmm_sxy, Qs, pl->fmm_src_ptr, pl->fmm_tgt_perm,
+        pl->xt, pl->yt, L, pl->fmm_x0, pl->fmm_y0, sL, p, pl->logtab, R, r, out);
     if (n_launches) *n_launches += 2 * L - 1;
   }
   return hipGetLastError();
