@@ -234,7 +234,27 @@ struct FmmLevels {
   double log_s[kFmmMaxLevels + 1];      // log of level l's box width
 };
 
-__global__ __launch_bounds__(kBlock) void k_fmm_m2l(const double2* __restrict__ M_all,
+// The multipoles of levels l0..l1 in real row form for the M2L pass: level
+// l at Mr + 2 P1 off[l], [row][box], rows 0..P1-1 the real and P1..2P1-1 the
+// imaginary parts of the coefficients (16 consecutive boxes then share
+// cache lines in the M2L operand loads).
+__global__ void k_fmm_mreal(const double2* __restrict__ M_all, FmmLevels lv, int p, double* __restrict__ Mr_all) {
+  const int P1 = p + 1;
+  const int64_t first = lv.off[lv.l0], nbox = lv.off[lv.l1] + ((int64_t)1 << (2 * lv.l1)) - first;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nbox * P1) return;
+  const int64_t gb = first + g / P1;
+  const int k = (int)(g % P1);
+  int l = lv.l0;
+  while (l < lv.l1 && gb >= lv.off[l + 1]) ++l;
+  const int64_t box = gb - lv.off[l], nb = (int64_t)1 << (2 * l);
+  const double2 m = M_all[gb * P1 + k];
+  double* Mr = Mr_all + 2 * P1 * lv.off[l];
+  Mr[(int64_t)k * nb + box] = m.x;
+  Mr[(int64_t)(P1 + k) * nb + box] = m.y;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fmm_m2l(const double* __restrict__ Mr_all,
                                                     const int32_t* __restrict__ cnt_s_all,
                                                     const int32_t* __restrict__ cnt_t_all, FmmLevels lv, int p,
                                                     int MP, int KP, const double* __restrict__ m2l,
@@ -245,7 +265,7 @@ __global__ __launch_bounds__(kBlock) void k_fmm_m2l(const double2* __restrict__ 
   int l = lv.l0;
   while (w_all >= lv.wave_end[l]) ++l;
   const int64_t w = w_all - (l > lv.l0 ? lv.wave_end[l - 1] : 0);
-  const double2* __restrict__ M = M_all + lv.off[l] * P1;
+  const double* __restrict__ Mr = Mr_all + 2 * P1 * lv.off[l];
   const int32_t* __restrict__ cnt_s = cnt_s_all + lv.off[l];
   const int32_t* __restrict__ cnt_t = cnt_t_all + lv.off[l];
   double2* __restrict__ Lc = Lc_all + lv.off[l] * P1;
@@ -269,23 +289,21 @@ __global__ __launch_bounds__(kBlock) void k_fmm_m2l(const double2* __restrict__ 
     bool use = live && jx >= 0 && jx < n && jy >= 0 && jy < n && abs((jx >> 1) - (ix >> 1)) <= 1 &&
                abs((jy >> 1) - (iy >> 1)) <= 1;
     if (use) use = cnt_s[(int64_t)jy * n + jx] > 0;
-    const double2* src = M + (use ? (int64_t)jy * n + jx : 0) * P1;
-    if (use) a0 += src[0].x;
-    const double* A = m2l + ((int64_t)o * MP + 16 * t + r16) * KP;
-    const double* srcd = reinterpret_cast<const double*>(src);  // re, im interleaved
+    const int64_t j = use ? (int64_t)jy * n + jx : 0;
+    if (use) a0 += Mr[j];
+    const int KS = KP / 4;
+    const double* A = m2l + (int64_t)(o * tiles + t) * KS * 64 + lane;
     // the operands of 8 steps are loaded before their 8 MFMAs, so that one
     // cache round trip serves 8 steps (indices clamped into the operator
-    // row and the box past the last step; such steps are skipped)
-    const int KS = KP / 4;
+    // and the multipole rows past the last step; such steps are skipped)
     for (int s0 = 0; s0 < KS; s0 += 8) {
       double av[8], bv[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const bool in = s0 + u < KS;  // the whole wavefront alike
-        const int k = 4 * (s0 + u) + kq;
-        const int kc2 = k < P1 ? 2 * k : (k < 2 * P1 ? 2 * (k - P1) + 1 : 0);
-        av[u] = A[in ? k : kq];
-        bv[u] = srcd[in ? kc2 : 0];
+        const int row = min(4 * (s0 + u) + kq, 2 * P1 - 1);
+        av[u] = A[(in ? s0 + u : 0) * 64];
+        bv[u] = Mr[(int64_t)row * nb + j];
       }
       // empty register constraints once all 16 loads are issued: they keep
       // the loads unconditional (the compiler otherwise turns the selects
@@ -599,12 +617,12 @@ __global__ __launch_bounds__(kBlock) void k_fmmb_m2l(const double* __restrict__ 
       const double* X = Mb + j * KP * C + r16;
 #pragma unroll
       for (int u = 0; u < NB; ++u) a0[u] += X[16 * u];
-      const double* A = m2l + ((int64_t)o * MP + 16 * t + r16) * KP;
+      const double* A = m2l + (int64_t)(o * tiles + t) * (KP / 4) * 64 + lane;
       // (each A operand serves NB MFMA steps, which hide its load: batching
       // the loads of several steps here raised the registers and cost
       // occupancy instead)
       for (int s4 = 0; s4 < KP / 4; ++s4) {
-        const double av = A[4 * s4 + kq];
+        const double av = A[s4 * 64];
         const double* x = X + (int64_t)(4 * s4 + kq) * C;
 #pragma unroll
         for (int u = 0; u < NB; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, x[16 * u], acc[u], 0, 0, 0);
@@ -759,10 +777,10 @@ void fmm_operators(int p, std::vector<double2>& m2m, std::vector<double2>& l2l, 
 // The M2L operators in the real, padded form of k_fmm_m2l: [49][MP][KP].
 std::vector<double> fmm_m2l_real(int p, const std::vector<double2>& m2l, int MP, int KP) {
   const int P1 = p + 1;
-  std::vector<double> out((size_t)49 * MP * KP, 0.0);
+  std::vector<double> plain((size_t)49 * MP * KP, 0.0);
   for (int o = 0; o < 49; ++o) {
     const double2* T = m2l.data() + (size_t)o * P1 * P1;
-    double* R = out.data() + (size_t)o * MP * KP;
+    double* R = plain.data() + (size_t)o * MP * KP;
     for (int r = 0; r < P1; ++r)
       for (int c = 0; c < P1; ++c) {
         const double2 t = T[(size_t)r * P1 + c];
@@ -772,6 +790,17 @@ std::vector<double> fmm_m2l_real(int p, const std::vector<double2>& m2l, int MP,
         R[(size_t)(P1 + r) * KP + P1 + c] = t.x;  //        + Re T Im x
       }
   }
+  // stored in the A-operand order of the MFMA steps: entry
+  // ((o tiles + t) KS + s) 64 + lane holds row 16 t + (lane & 15), column
+  // 4 s + (lane >> 4), so a wavefront reads 64 consecutive doubles per step
+  const int tiles = MP / 16, KS = KP / 4;
+  std::vector<double> out(plain.size());
+  for (int o = 0; o < 49; ++o)
+    for (int t = 0; t < tiles; ++t)
+      for (int st = 0; st < KS; ++st)
+        for (int lane = 0; lane < 64; ++lane)
+          out[(((size_t)o * tiles + t) * KS + st) * 64 + lane] =
+              plain[((size_t)o * MP + 16 * t + (lane & 15)) * KP + 4 * st + (lane >> 4)];
   return out;
 }
 
@@ -840,10 +869,11 @@ int64_t fmm_workspace_doubles(const vp_plan* pl, int64_t R) {
   if (pl->fmm_terms <= 0) return 0;
   const int64_t nbox = fmm_boxes(pl->fmm_levels);
   // one density at a time: multipole and local coefficients (complex) of
-  // every box and the charges in leaf order; passes of 16, 32 or 64
+  // every box, the charges in leaf order and the multipoles in real row
+  // form; passes of 16, 32 or 64
   // densities: the real-form expansions [box][KP][16 NB]; they share the
   // space; 2 for alignment
-  const int64_t one = 2 * 2 * nbox * (pl->fmm_terms + 1) + pl->n_src;
+  const int64_t one = 3 * 2 * nbox * (pl->fmm_terms + 1) + pl->n_src;
   const int64_t cols = R >= 64 ? 64 : R >= 32 ? 32 : R >= 16 ? 16 : 0;
   const int64_t blk = 2 * nbox * pl->fmm_kp * cols;
   return std::max(one, blk) + 2;
@@ -1103,6 +1133,7 @@ hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out
   double2* Mall = (double2*)(ws + ((uintptr_t)ws % 16 ? 1 : 0));
   double2* Lall = Mall + nbox * P1;
   double* Qs = (double*)(Lall + nbox * P1);
+  double* Mr = Qs + pl->n_src;  // the multipoles in real row form (one density at a time)
   const int n = 1 << L;
   const int64_t nleaf = (int64_t)n * n;
   const double sL = pl->fmm_width / n;
@@ -1171,8 +1202,9 @@ hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out
       k_fmm_m2m<<<blocks_for(nt), kBlock, 0, st>>>(Mall + pl->fmm_off[l + 1] * P1, pl->fmm_cnt_src + pl->fmm_off[l + 1],
                                                    l, p, pl->fmm_m2m, Mall + pl->fmm_off[l] * P1);
     }
+    k_fmm_mreal<<<blocks_for((pl->fmm_off[L] + nleaf - pl->fmm_off[2]) * P1), kBlock, 0, st>>>(Mall, lv1, p, Mr);
     k_fmm_m2l<<<(unsigned)((lv1.wave_end[L] * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
-        Mall, pl->fmm_cnt_src, pl->fmm_cnt_tgt, lv1, p, MP, KP, pl->fmm_m2l, Lall);
+        Mr, pl->fmm_cnt_src, pl->fmm_cnt_tgt, lv1, p, MP, KP, pl->fmm_m2l, Lall);
     for (int l = 3; l <= L; ++l) {
       const int64_t nbl = (int64_t)1 << (2 * l);
       k_fmm_l2l<<<blocks_for(nbl * P1), kBlock, 0, st>>>(pl->fmm_cnt_tgt + pl->fmm_off[l],
@@ -1182,7 +1214,7 @@ hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out
     k_fmm_leaf<<<(unsigned)(((pl->n_tgt + 15) / 16 * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
         Lall + pl->fmm_off[L] * P1, pl->fmm_tbox, pl->n_tgt, pl->fmm_sxy, Qs, pl->fmm_src_ptr, pl->fmm_tgt_perm,
         pl->xt, pl->yt, L, pl->fmm_x0, pl->fmm_y0, sL, p, pl->logtab, R, r, out);
-    if (n_launches) *n_launches += 2 * L - 1;
+    if (n_launches) *n_launches += 2 * L;
   }
   return hipGetLastError();
 }
