@@ -184,6 +184,9 @@ vp_status vp_ctx_destroy(vp_ctx* ctx) {
   if (ctx->live_meshes) return fail(VP_EBUSY, "vp_ctx_destroy: %d meshes still alive", ctx->live_meshes);
   (void)hipSetDevice(ctx->device);
   fold_timings(ctx);
+  for (auto& kv : ctx->fmm_ops)
+    for (void* x : {(void*)kv.second.m2m, (void*)kv.second.l2l, (void*)kv.second.m2l})
+      if (x) (void)hipFree(x);
   delete ctx;
   return VP_OK;
 }

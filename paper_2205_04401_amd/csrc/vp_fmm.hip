@@ -113,6 +113,13 @@ __global__ void k_fmm_count(const uint32_t* __restrict__ key, int64_t n, int32_t
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) atomicAdd(&cnt[key[i]], 1);
 }
 
+// tbox[i] = the leaf box of target i in leaf order (one thread per box)
+__global__ void k_fmm_tbox(const int64_t* __restrict__ tptr, int64_t nleaf, int32_t* __restrict__ tbox) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nleaf) return;
+  for (int64_t i = tptr[b]; i < tptr[b + 1]; ++i) tbox[i] = (int32_t)b;
+}
+
 __global__ void k_fmm_gather2(const double2* __restrict__ in, const int32_t* __restrict__ perm, int64_t n,
                               double2* __restrict__ out) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -774,36 +781,30 @@ inline CLD cl_inv(CLD a) {
 //     [l][0] = -1 / (l z0^l), [l][k] = (-1)^k C(l+k-1, k-1) z0^-(l+k)
 void fmm_operators(int p, std::vector<double2>& m2m, std::vector<double2>& l2l, std::vector<double2>& m2l);
 
-// The M2L operators in the real, padded form of k_fmm_m2l: [49][MP][KP].
+// The M2L operators in the real, padded form ([49] of MP x KP: rows Re y then
+// Im y, columns Re x then Im x), stored in the A-operand order of the MFMA
+// steps: entry ((o tiles + t) KS + s) 64 + lane holds row 16 t + (lane & 15),
+// column 4 s + (lane >> 4), so a wavefront reads 64 consecutive doubles per
+// step.  Padding rows and columns are zero.
 std::vector<double> fmm_m2l_real(int p, const std::vector<double2>& m2l, int MP, int KP) {
-  const int P1 = p + 1;
-  std::vector<double> plain((size_t)49 * MP * KP, 0.0);
+  const int P1 = p + 1, tiles = MP / 16, KS = KP / 4;
+  std::vector<double> out((size_t)49 * MP * KP, 0.0);
+  auto at = [&](int o, int row, int col) -> double& {
+    return out[(((size_t)o * tiles + row / 16) * KS + col / 4) * 64 + (col % 4) * 16 + row % 16];
+  };
   for (int o = 0; o < 49; ++o) {
     const double2* T = m2l.data() + (size_t)o * P1 * P1;
-    double* R = plain.data() + (size_t)o * MP * KP;
     for (int r = 0; r < P1; ++r)
       for (int c = 0; c < P1; ++c) {
         const double2 t = T[(size_t)r * P1 + c];
-        R[(size_t)r * KP + c] = t.x;              // Re y <- Re T Re x
-        R[(size_t)r * KP + P1 + c] = -t.y;        //        - Im T Im x
-        R[(size_t)(P1 + r) * KP + c] = t.y;       // Im y <- Im T Re x
-        R[(size_t)(P1 + r) * KP + P1 + c] = t.x;  //        + Re T Im x
+        at(o, r, c) = t.x;            // Re y <- Re T Re x
+        at(o, r, P1 + c) = -t.y;      //        - Im T Im x
+        at(o, P1 + r, c) = t.y;       // Im y <- Im T Re x
+        at(o, P1 + r, P1 + c) = t.x;  //        + Re T Im x
       }
   }
-  // stored in the A-operand order of the MFMA steps: entry
-  // ((o tiles + t) KS + s) 64 + lane holds row 16 t + (lane & 15), column
-  // 4 s + (lane >> 4), so a wavefront reads 64 consecutive doubles per step
-  const int tiles = MP / 16, KS = KP / 4;
-  std::vector<double> out(plain.size());
-  for (int o = 0; o < 49; ++o)
-    for (int t = 0; t < tiles; ++t)
-      for (int st = 0; st < KS; ++st)
-        for (int lane = 0; lane < 64; ++lane)
-          out[(((size_t)o * tiles + t) * KS + st) * 64 + lane] =
-              plain[((size_t)o * MP + 16 * t + (lane & 15)) * KP + 4 * st + (lane >> 4)];
   return out;
 }
-
 void fmm_operators(int p, std::vector<double2>& m2m, std::vector<double2>& l2l, std::vector<double2>& m2l) {
   const int P1 = p + 1, nb = 2 * p + 1;
   const std::vector<long double> C = binomials(nb);
@@ -1021,16 +1022,43 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
       }
   }
   for (int l = 0; l <= L; ++l) pl->fmm_off[l] = off[l];
-  std::vector<double2> m2m, l2l, m2l;
-  fmm_operators(p, m2m, l2l, m2l);
   pl->fmm_mp = (2 * (p + 1) + 15) / 16 * 16;
   pl->fmm_kp = (2 * (p + 1) + 3) / 4 * 4;
-  const std::vector<double> m2l_r = fmm_m2l_real(p, m2l, pl->fmm_mp, pl->fmm_kp);
+  // the translation operators depend only on p: built once per context and
+  // order (a few ms of host work) and shared by its plans
+  std::vector<double2> m2m, l2l, m2l;
+  std::vector<double> m2l_r;
+  vp_ctx::FmmOps& ops = pl->ctx->fmm_ops[p];
+  if (!ops.m2l) {
+    fmm_operators(p, m2m, l2l, m2l);
+    m2l_r = fmm_m2l_real(p, m2l, pl->fmm_mp, pl->fmm_kp);
+    const size_t b1 = sizeof(double2) * m2m.size(), b2 = sizeof(double2) * l2l.size(),
+                 b3 = sizeof(double) * m2l_r.size();
+    double2 *d1 = nullptr, *d2 = nullptr;
+    double* d3 = nullptr;
+    if ((e = hipMalloc((void**)&d1, b1)) != hipSuccess || (e = hipMalloc((void**)&d2, b2)) != hipSuccess ||
+        (e = hipMalloc((void**)&d3, b3)) != hipSuccess ||
+        (e = hipMemcpyAsync(d1, m2m.data(), b1, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(d2, l2l.data(), b2, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(d3, m2l_r.data(), b3, hipMemcpyHostToDevice, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {  // before the host tables go
+      (void)hipStreamSynchronize(st);
+      for (void* x : {(void*)d1, (void*)d2, (void*)d3})
+        if (x) (void)hipFree(x);
+      pl->ctx->fmm_ops.erase(p);
+      return e;
+    }
+    ops.m2m = d1;
+    ops.l2l = d2;
+    ops.m2l = d3;
+    ops.bytes = b1 + b2 + b3;
+    pl->ctx->in_use += ops.bytes;
+  }
+  pl->fmm_m2m = ops.m2m;
+  pl->fmm_l2l = ops.l2l;
+  pl->fmm_m2l = ops.m2l;
   if ((e = alloc((void**)&pl->fmm_cnt_src, sizeof(int32_t) * nbox)) != hipSuccess ||
-      (e = alloc((void**)&pl->fmm_cnt_tgt, sizeof(int32_t) * nbox)) != hipSuccess ||
-      (e = alloc((void**)&pl->fmm_m2m, sizeof(double2) * m2m.size())) != hipSuccess ||
-      (e = alloc((void**)&pl->fmm_l2l, sizeof(double2) * l2l.size())) != hipSuccess ||
-      (e = alloc((void**)&pl->fmm_m2l, sizeof(double) * m2l_r.size())) != hipSuccess)
+      (e = alloc((void**)&pl->fmm_cnt_tgt, sizeof(int32_t) * nbox)) != hipSuccess)
     return e;
   if ((e = hipMemcpyAsync(pl->fmm_src_ptr, sp.data(), sizeof(int64_t) * (nleaf + 1), hipMemcpyHostToDevice, st)) !=
           hipSuccess ||
@@ -1039,12 +1067,6 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
       (e = hipMemcpyAsync(pl->fmm_cnt_src, cs.data(), sizeof(int32_t) * nbox, hipMemcpyHostToDevice, st)) !=
           hipSuccess ||
       (e = hipMemcpyAsync(pl->fmm_cnt_tgt, ct.data(), sizeof(int32_t) * nbox, hipMemcpyHostToDevice, st)) !=
-          hipSuccess ||
-      (e = hipMemcpyAsync(pl->fmm_m2m, m2m.data(), sizeof(double2) * m2m.size(), hipMemcpyHostToDevice, st)) !=
-          hipSuccess ||
-      (e = hipMemcpyAsync(pl->fmm_l2l, l2l.data(), sizeof(double2) * l2l.size(), hipMemcpyHostToDevice, st)) !=
-          hipSuccess ||
-      (e = hipMemcpyAsync(pl->fmm_m2l, m2l_r.data(), sizeof(double) * m2l_r.size(), hipMemcpyHostToDevice, st)) !=
           hipSuccess)
     return e;
   // work counts (plan statistics)
@@ -1066,41 +1088,36 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
     pl->fmm_m2l_pairs = (int64_t)h_cnt[1];
   }
   pl->fmm_tgt_ptr_host = tp;
-  // the (leaf box, first target) work list of the passes of 16+ densities
-  // (16-target tiles), and the leaf box of every target in leaf order
-  std::vector<int2> tiles;
-  std::vector<int32_t> tbox(std::max<int64_t>(NT, 1));
-  for (int64_t b = 0; b < nleaf; ++b) {
-    for (int64_t i = tp[b]; i < tp[b + 1]; i += 16) tiles.push_back(make_int2((int)b, (int)i));
-    for (int64_t i = tp[b]; i < tp[b + 1]; ++i) tbox[i] = (int32_t)b;
-  }
-  if ((e = alloc((void**)&pl->fmm_tbox, sizeof(int32_t) * tbox.size())) != hipSuccess ||
-      (e = hipMemcpyAsync(pl->fmm_tbox, tbox.data(), sizeof(int32_t) * tbox.size(), hipMemcpyHostToDevice, st)) !=
-          hipSuccess)
-    return e;
-  pl->fmm_n_ttiles = (int64_t)tiles.size();
-  if ((e = alloc((void**)&pl->fmm_ttile, sizeof(int2) * std::max<size_t>(tiles.size(), 1))) != hipSuccess) return e;
-  if (!tiles.empty() &&
-      (e = hipMemcpyAsync(pl->fmm_ttile, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, st)) !=
-          hipSuccess)
-    return e;
+  // the leaf box of every target in leaf order (the single-density leaf pass)
+  if ((e = alloc((void**)&pl->fmm_tbox, sizeof(int32_t) * std::max<int64_t>(NT, 1))) != hipSuccess) return e;
+  k_fmm_tbox<<<blocks_for(nleaf), kBlock, 0, st>>>(pl->fmm_tgt_ptr, nleaf, pl->fmm_tbox);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   return hipStreamSynchronize(st);  // the host vectors above go out of scope
 }
 
 // Tables of the passes of 16+ densities, built at the first evaluation
 // that needs them (they cost 8 (N_src MP + N_tgt KP) bytes): P2M rows of
-// the sources and L2P rows of the targets.  Synchronises the stream.
+// the sources, L2P rows of the targets, and the (leaf box, first target)
+// work list of their leaf pass.  Synchronises the stream.
 hipError_t fmm_prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st) {
   if (pl->fmm_terms <= 0 || R < 16 || pl->fmm_vsrc) return hipSuccess;
   const int64_t NS = pl->n_src, NT = pl->n_tgt;
   const int L = pl->fmm_levels, n = 1 << L, p = pl->fmm_terms;
-  const size_t bytes = sizeof(double) * (NS * pl->fmm_mp + NT * pl->fmm_kp);
+  const int64_t nleaf = (int64_t)n * n;
+  const std::vector<int64_t>& tp = pl->fmm_tgt_ptr_host;
+  std::vector<int2> tiles;
+  for (int64_t b = 0; b < nleaf; ++b)
+    for (int64_t i = tp[b]; i < tp[b + 1]; i += 16) tiles.push_back(make_int2((int)b, (int)i));
+  const size_t bytes =
+      sizeof(double) * (NS * pl->fmm_mp + NT * pl->fmm_kp) + sizeof(int2) * std::max<size_t>(tiles.size(), 1);
   if (pl->ctx->budget && pl->ctx->in_use + bytes > pl->ctx->budget) return hipErrorOutOfMemory;
   double *vsrc = nullptr, *wtgt = nullptr;
+  int2* tt = nullptr;
   hipError_t e;
   if ((e = hipMalloc((void**)&vsrc, sizeof(double) * NS * pl->fmm_mp)) != hipSuccess ||
-      (e = hipMalloc((void**)&wtgt, sizeof(double) * NT * pl->fmm_kp)) != hipSuccess) {
-    for (void* x : {(void*)vsrc, (void*)wtgt})
+      (e = hipMalloc((void**)&wtgt, sizeof(double) * NT * pl->fmm_kp)) != hipSuccess ||
+      (e = hipMalloc((void**)&tt, sizeof(int2) * std::max<size_t>(tiles.size(), 1))) != hipSuccess) {
+    for (void* x : {(void*)vsrc, (void*)wtgt, (void*)tt})
       if (x) (void)hipFree(x);
     return e;
   }
@@ -1109,14 +1126,18 @@ hipError_t fmm_prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st) {
   k_fmm_wtgt<<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, pl->fmm_tgt_perm, NT, pl->fmm_x0, pl->fmm_y0, sL, L, p,
                                                 pl->fmm_kp, wtgt);
   e = hipGetLastError();
+  if (e == hipSuccess && !tiles.empty())
+    e = hipMemcpyAsync(tt, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
-    for (void* x : {(void*)vsrc, (void*)wtgt}) (void)hipFree(x);
+    for (void* x : {(void*)vsrc, (void*)wtgt, (void*)tt}) (void)hipFree(x);
     return e;
   }
-  for (void* x : {(void*)vsrc, (void*)wtgt}) pl->allocs.push_back(x);
+  for (void* x : {(void*)vsrc, (void*)wtgt, (void*)tt}) pl->allocs.push_back(x);
   pl->fmm_vsrc = vsrc;
   pl->fmm_wtgt = wtgt;
+  pl->fmm_ttile = tt;
+  pl->fmm_n_ttiles = (int64_t)tiles.size();
   pl->bytes += bytes;
   pl->ctx->in_use += bytes;
   return hipSuccess;

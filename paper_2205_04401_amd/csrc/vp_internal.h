@@ -351,6 +351,14 @@ struct vp_ctx {
   hipStream_t stream = nullptr;
   uint64_t budget = 0;
   uint64_t in_use = 0;
+  // FMM translation operators per expansion order, shared by the context's
+  // plans (device memory, freed with the context)
+  struct FmmOps {
+    double2 *m2m = nullptr, *l2l = nullptr;
+    double* m2l = nullptr;
+    size_t bytes = 0;
+  };
+  std::map<int, FmmOps> fmm_ops;
   int live_meshes = 0;
   // profiling: pending event pairs per stage, folded into the totals on read
   bool profile = false;
