@@ -13,18 +13,22 @@
 // (Greengard-Rokhlin translation lemmas; with these scalings the M2M and L2L
 // operators depend only on the child's quadrant and the M2L operator only
 // on the integer offset between the boxes, so all are precomputed once per
-// plan; the one level-dependent term, a_0 log s of M2L, is added apart).
+// context and p; the one level-dependent term, a_0 log s of M2L, is added
+// apart).
 // Interaction list: boxes of the same level that are not adjacent but whose
 // parents are; near field: the 3 x 3 adjacent leaf boxes, summed directly
 // with the direct sum's kernel log(r^2 + 2^-100), so a target on a source
 // still gets the value the correction rows subtract again.  The M2L bound
 // for adjacent-parent, non-adjacent boxes is (sum |Q|) 0.547^p / 0.83, so p
 // sets the accuracy (p = 56: ~2e-15 of sum |Q|).
-//   k_fmm_bbox_partial, k_fmm_keys, k_fmm_count, k_fmm_gather2  (plan time)
+//   k_fmm_bbox_partial, k_fmm_keys, k_fmm_count, k_fmm_gather2,
+//   k_fmm_tbox  (plan time)
 //   k_fmm_p2m   one wavefront per leaf box: multipole of its sources
 //   k_fmm_m2m   one thread per (box, coefficient): the upward pass
-//   k_fmm_m2l   16 boxes per wavefront: M2L over the interaction list on the
-//               FP64 matrix cores (real form of the complex operators)
+//   k_fmm_mreal the multipoles in real row form, [row][box] per level
+//   k_fmm_m2l   16 boxes per wavefront, all levels in one launch: M2L over
+//               the interaction list on the FP64 matrix cores (real form of
+//               the complex operators)
 //   k_fmm_l2l   one thread per (box, coefficient): L2L from the parent
 //   k_fmm_leaf  one wavefront per 16 targets in leaf order: the local
 //               expansion plus the direct sum over the 3 x 3 adjacent boxes
