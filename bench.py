@@ -258,11 +258,11 @@ def far_kernel_digest():
     return hashlib.sha256((exe[a:b] + hdr[c:d]).encode()).hexdigest()[:16]
 
 
-def measured_traffic(q):
-    """HBM bytes per far-kernel launch from the committed counter summary
-    (two rocprofv3 --pmc runs, FETCH_SIZE and WRITE_SIZE, calibrated on a
-    plain copy), or None when that summary was taken on another workload or
-    on a different version of the kernel source."""
+def counter_field(q, name):
+    """A figure of the committed counter summary of the far kernel
+    (rocprofv3 --pmc runs on this workload), or None when that summary was
+    taken on another workload or on a different version of the kernel
+    source."""
     path = os.path.join(ROOT, "profiles", f"k_far_fp64_star20k_q{q}_counters.md")
     if not os.path.exists(path):
         return None
@@ -271,10 +271,31 @@ def measured_traffic(q):
         if ":" in line and not line.startswith(("|", "#", "`")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    digest = far_kernel_digest()
-    if fields.get("kernel_source_sha256_16") != digest or "traffic_bytes_per_launch" not in fields:
+    if fields.get("kernel_source_sha256_16") != far_kernel_digest() or name not in fields:
         return None
-    return float(fields["traffic_bytes_per_launch"])
+    return float(fields[name])
+
+
+def measured_traffic(q):
+    """HBM bytes per far-kernel launch (FETCH_SIZE and WRITE_SIZE, calibrated
+    on a plain copy)."""
+    return counter_field(q, "traffic_bytes_per_launch")
+
+
+# vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64
+# instruction occupies a 16-lane SIMD for 4 cycles)
+PEAK_VALU_LANE_INSTS = 256 * 4 * 16 * 2.4e9
+
+
+def valu_issue(q, pairs_per_s):
+    """The far kernel against the vector issue rate: measured vector
+    instructions per pair (SQ_INSTS_VALU x 64 / pairs) times pairs/s."""
+    ipp = counter_field(q, "valu_instructions_per_pair")
+    if ipp is None:
+        return None
+    achieved = ipp * pairs_per_s
+    return {"instructions_per_pair": ipp, "achieved_lane_insts_per_s": achieved,
+            "peak_lane_insts_per_s": PEAK_VALU_LANE_INSTS, "frac": achieved / PEAK_VALU_LANE_INSTS}
 
 
 def copy_probe(n_bytes=1 << 29, reps=3):
@@ -418,6 +439,7 @@ def run(args):
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
             "traffic": measured_traffic(q),
+            "valu_issue": valu_issue(q, pairs / far_avg_s),
             "kernel": "k_far (FP64 direct far sum)",
             "flops_per_pair": FLOPS_PER_PAIR,
             "pairs_per_launch": pairs,
