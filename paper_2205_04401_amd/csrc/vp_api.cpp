@@ -638,6 +638,8 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
       return hip_fail(e, "vp_plan_create: log tables");
   }
   if ((e = plan_alloc(pl, (void**)&pl->sxy, sizeof(double2) * pl->n_src_pad)) != hipSuccess ||
+      (e = plan_alloc(pl, (void**)&pl->sgrp, sizeof(double) * 3 * (pl->n_src_pad / 64))) != hipSuccess ||
+      (e = plan_alloc(pl, (void**)&pl->soff, sizeof(float2) * pl->n_src_pad)) != hipSuccess ||
       (e = plan_alloc(pl, (void**)&pl->swj, sizeof(double) * pl->n_src_pad)) != hipSuccess ||
       (e = plan_alloc(pl, (void**)&pl->deff, sizeof(double) * std::max<int64_t>(pl->n_tri, 1))) != hipSuccess ||
       (e = plan_alloc(pl, (void**)&pl->xt, sizeof(double) * n_tgt)) != hipSuccess ||

@@ -200,28 +200,68 @@ __global__ __launch_bounds__((FarShape<S, RB>::kThreads)) void k_far(
     }
 }
 
-// Mixed-precision far sum (same decomposition as k_far): the pair
-// difference is taken in FP64 and rounded to FP32, r^2 + 2^-100 and the
-// base-2 logarithm (the hardware v_log_f32) are FP32, the charges are FP32
-// with ln 2 folded in (Q32 = Q ln 2, so Q32 log2(r^2) = Q log(r^2)), each
-// 256-source tile is summed in FP32 and the tiles are summed in FP64.
+// Mixed-precision far sum (same decomposition as k_far): r^2 + 2^-100 and
+// the base-2 logarithm (the hardware v_log_f32) are FP32, the charges are
+// FP32 with ln 2 folded in (Q32 = Q ln 2, so Q32 log2(r^2) = Q log(r^2)),
+// each 256-source tile is summed in FP32 and the tiles are summed in FP64.
+// The pair difference, per group of 64 sources (centre c, radius a; each
+// source's FP32 offset s - c is a plan table): when the group's circle
+// lies 3a beyond the circle around the block's targets, every pair has
+// r >= 2a and |x - c| <= 1.5 r, so the FP32 offset x - c (once per target
+// and group) minus s - c gives the difference to a relative 3 2^-24 with
+// one FP32 subtraction per coordinate.  Nearer groups (including targets
+// on or next to a source) take the difference in FP64, rounded to FP32.
 template <int RB, int TPT>
-__global__ __launch_bounds__(kBlock) void k_far32(const double2* __restrict__ sxy, const float* __restrict__ Q32,
-                                                  int64_t n_src_pad, int64_t R, int64_t r0,
-                                                  const double* __restrict__ xt, const double* __restrict__ yt,
-                                                  int64_t n_tgt, int64_t per_split, int64_t n_split,
-                                                  double* __restrict__ partial) {
+__global__ __launch_bounds__(kBlock) void k_far32(const double2* __restrict__ sxy, const double* __restrict__ sgrp,
+                                                  const float2* __restrict__ soff,
+                                                  const float* __restrict__ Q32, int64_t n_src_pad, int64_t R,
+                                                  int64_t r0, const double* __restrict__ xt,
+                                                  const double* __restrict__ yt, int64_t n_tgt, int64_t per_split,
+                                                  int64_t n_split, double* __restrict__ partial) {
+  __shared__ double red[4][kBlock / 64];
   const int64_t b = blockIdx.x;
   const int64_t chunk = b % n_split, tb = b / n_split;
   double x[TPT], y[TPT];
   int64_t t[TPT];
+  double bx0 = 1e300, bx1 = -1e300, by0 = 1e300, by1 = -1e300;
 #pragma unroll
   for (int k = 0; k < TPT; ++k) {
     t[k] = tb * (kBlock * TPT) + k * kBlock + threadIdx.x;
     const bool act = t[k] < n_tgt;
     x[k] = act ? xt[t[k]] : 0.0;
     y[k] = act ? yt[t[k]] : 0.0;
+    if (act) {
+      bx0 = fmin(bx0, x[k]);
+      bx1 = fmax(bx1, x[k]);
+      by0 = fmin(by0, y[k]);
+      by1 = fmax(by1, y[k]);
+    }
   }
+  // the block's target bounding box: wavefront, then block
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    bx0 = fmin(bx0, __shfl_xor(bx0, o));
+    bx1 = fmax(bx1, __shfl_xor(bx1, o));
+    by0 = fmin(by0, __shfl_xor(by0, o));
+    by1 = fmax(by1, __shfl_xor(by1, o));
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wv] = bx0;
+    red[1][wv] = bx1;
+    red[2][wv] = by0;
+    red[3][wv] = by1;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) {
+    bx0 = fmin(bx0, red[0][w]);
+    bx1 = fmax(bx1, red[1][w]);
+    by0 = fmin(by0, red[2][w]);
+    by1 = fmax(by1, red[3][w]);
+  }
+  const double ox = 0.5 * (bx0 + bx1), oy = 0.5 * (by0 + by1);
+  const double rb = 0.5 * sqrt((bx1 - bx0) * (bx1 - bx0) + (by1 - by0) * (by1 - by0));
   const int64_t s_begin = chunk * per_split;
   const int64_t s_end = min(n_src_pad, s_begin + per_split);
   double acc[TPT][RB];
@@ -236,20 +276,51 @@ __global__ __launch_bounds__(kBlock) void k_far32(const double2* __restrict__ sx
     for (int k = 0; k < TPT; ++k)
 #pragma unroll
       for (int r = 0; r < RB; ++r) tile[k][r] = 0.0f;
-    for (int64_t j = j0; j < j1; j += 4) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double2 s = sxy[j + u];
-        float q[RB];
-#pragma unroll
-        for (int r = 0; r < RB; ++r) q[r] = Q32[(j + u) * R + r0 + r];
+    // chunks and tiles are multiples of 64 sources: whole groups
+    for (int64_t jg = j0; jg < j1; jg += 64) {
+      const double* G = sgrp + 3 * (jg >> 6);
+      const double gdx = G[0] - ox, gdy = G[1] - oy, lim = rb + 4.0 * G[2];
+      if (gdx * gdx + gdy * gdy >= lim * lim) {  // the whole block alike
+        float xg[TPT], yg[TPT];
 #pragma unroll
         for (int k = 0; k < TPT; ++k) {
-          const float dx = (float)(x[k] - s.x), dy = (float)(y[k] - s.y);
-          const float r2 = fmaf(dy, dy, fmaf(dx, dx, kR2BiasF));
-          const float lg = __builtin_amdgcn_logf(r2);
+          xg[k] = (float)(x[k] - G[0]);
+          yg[k] = (float)(y[k] - G[1]);
+        }
+        for (int64_t j = jg; j < jg + 64; j += 4) {
 #pragma unroll
-          for (int r = 0; r < RB; ++r) tile[k][r] = fmaf(q[r], lg, tile[k][r]);
+          for (int u = 0; u < 4; ++u) {
+            const float2 so = soff[j + u];
+            float q[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) q[r] = Q32[(j + u) * R + r0 + r];
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) {
+              const float dx = xg[k] - so.x, dy = yg[k] - so.y;
+              const float r2 = fmaf(dy, dy, fmaf(dx, dx, kR2BiasF));
+              const float lg = __builtin_amdgcn_logf(r2);
+#pragma unroll
+              for (int r = 0; r < RB; ++r) tile[k][r] = fmaf(q[r], lg, tile[k][r]);
+            }
+          }
+        }
+      } else {
+        for (int64_t j = jg; j < jg + 64; j += 4) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double2 s = sxy[j + u];
+            float q[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) q[r] = Q32[(j + u) * R + r0 + r];
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) {
+              const float dx = (float)(x[k] - s.x), dy = (float)(y[k] - s.y);
+              const float r2 = fmaf(dy, dy, fmaf(dx, dx, kR2BiasF));
+              const float lg = __builtin_amdgcn_logf(r2);
+#pragma unroll
+              for (int r = 0; r < RB; ++r) tile[k][r] = fmaf(q[r], lg, tile[k][r]);
+            }
+          }
         }
       }
     }
@@ -533,8 +604,8 @@ hipError_t far_valu32(const vp_plan* pl, const float* Q32, int64_t R, int64_t r0
   const int64_t NT = pl->n_tgt, tpb = (int64_t)kBlock * TPT;
   const int64_t nb = (NT + tpb - 1) / tpb * n_split;
   if (nb * kBlock >= (1LL << 32)) return hipErrorInvalidConfiguration;
-  k_far32<RB, TPT><<<dim3((unsigned)nb), kBlock, 0, st>>>(pl->sxy, Q32, pl->n_src_pad, R, r0, pl->xt, pl->yt, NT,
-                                                          per, n_split, partial);
+  k_far32<RB, TPT><<<dim3((unsigned)nb), kBlock, 0, st>>>(pl->sxy, pl->sgrp, pl->soff, Q32, pl->n_src_pad, R, r0,
+                                                          pl->xt, pl->yt, NT, per, n_split, partial);
   return hipSuccess;
 }
 

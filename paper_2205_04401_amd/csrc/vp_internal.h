@@ -426,6 +426,8 @@ struct vp_plan {
   // sources and targets (device)
   int64_t n_src_pad = 0;                // n_src rounded up to a multiple of 256
   double2* sxy = nullptr;               // [n_src_pad] source positions
+  double* sgrp = nullptr;               // [n_src_pad / 64][3] centre x, y and radius of each 64-source group
+  float2* soff = nullptr;               // [n_src_pad] each source's offset from its group's centre (FP32)
   double* swj = nullptr;                // [n_src_pad] source weights w_j |J(xi_j)| (0 in the padding)
   double* deff = nullptr;               // [T] |J| scale of the ellipse tests (det; the largest far-node |J| if curved)
   double* rad_c_r = nullptr;            // radial rule of curved self pieces [n_rc]

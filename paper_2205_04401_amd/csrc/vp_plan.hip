@@ -650,13 +650,42 @@ hipError_t launch_basis_tables(vp_plan* pl, double* scratch, hipStream_t st) {
   return hipErrorInvalidValue;
 }
 
+// Bounding circle (centre of the bounding box, half its diagonal) of every
+// group of 64 consecutive sources, and each source's offset from its
+// group's centre in FP32, for the mixed far sum (padding sources at the
+// origin are included: a larger circle)
+static __global__ void k_src_groups(const double2* __restrict__ sxy, int64_t n_grp, double* __restrict__ grp,
+                                    float2* __restrict__ soff) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_grp) return;
+  double x0 = sxy[64 * g].x, x1 = x0, y0 = sxy[64 * g].y, y1 = y0;
+  for (int i = 1; i < 64; ++i) {
+    const double2 s = sxy[64 * g + i];
+    x0 = fmin(x0, s.x);
+    x1 = fmax(x1, s.x);
+    y0 = fmin(y0, s.y);
+    y1 = fmax(y1, s.y);
+  }
+  const double cx = 0.5 * (x0 + x1), cy = 0.5 * (y0 + y1);
+  grp[3 * g] = cx;
+  grp[3 * g + 1] = cy;
+  // a hair above half the diagonal, so that the circle holds every source
+  grp[3 * g + 2] = 0.5 * sqrt((x1 - x0) * (x1 - x0) + (y1 - y0) * (y1 - y0)) * (1.0 + 1e-12);
+  for (int i = 0; i < 64; ++i) {
+    const double2 s = sxy[64 * g + i];
+    soff[64 * g + i] = make_float2((float)(s.x - cx), (float)(s.y - cy));
+  }
+}
+
 hipError_t launch_sources(vp_plan* pl, hipStream_t st) {
   const vp_mesh* m = pl->mesh;
   int64_t n = pl->n_src_pad;
   const CurveView cv = m->curves();
-  if (n > 0)
+  if (n > 0) {
     k_sources<<<blocks_for(n), kBlock, 0, st>>>(m->ax, m->ay, m->bx, m->by, m->cx, m->cy, m->det, cv, pl->far_x,
                                                 pl->far_y, pl->far_w, pl->n_f, pl->n_tri, n, pl->sxy, pl->swj);
+    k_src_groups<<<blocks_for(n / 64), kBlock, 0, st>>>(pl->sxy, n / 64, pl->sgrp, pl->soff);
+  }
   if (pl->n_tri > 0)
     k_deff<<<blocks_for(pl->n_tri), kBlock, 0, st>>>(m->det, pl->n_tri, cv, pl->swj, pl->far_w, pl->n_f, pl->deff);
   return hipGetLastError();
