@@ -254,7 +254,20 @@ vp_status vp_coefficients(vp_plan* plan, int64_t n_rhs, const double* density, d
 /* Far-source positions [n_src][2] (host copy). */
 vp_status vp_plan_sources(const vp_plan* plan, double* xy_out);
 
+/* Destroys the plan.  Waits for all work queued on the device (as hipFree
+ * does) and hands the plan's device blocks to its context, which keeps up to
+ * 16 GiB of them (and, with an HBM budget, no more than the budget leaves
+ * free) for later plans of similar sizes: a plan that is built and destroyed
+ * every step then neither allocates nor frees device memory after the first.
+ * Blocks beyond that limit are freed.  The context frees its cached blocks
+ * when an allocation finds the device out of memory, on vp_ctx_trim and on
+ * vp_ctx_destroy. */
 vp_status vp_plan_destroy(vp_plan* plan);
+
+/* Device bytes the context holds in cached blocks of destroyed plans
+ * (*bytes_out), and vp_ctx_trim: free all of them now. */
+vp_status vp_ctx_cached_bytes(const vp_ctx* ctx, uint64_t* bytes_out);
+vp_status vp_ctx_trim(vp_ctx* ctx);
 
 /* Wait for all work issued on the context's stream. */
 vp_status vp_sync(vp_ctx* ctx);

@@ -53,15 +53,28 @@ vp_plan_opts default_opts() {
   return o;
 }
 
-void free_plan_memory(vp_plan* pl) {
-  for (void* p : pl->allocs) (void)hipFree(p);
-  pl->allocs.clear();
-  double* ws[] = {pl->ws_f, pl->ws_c, pl->ws_q, pl->ws_part, pl->ws_u};
-  for (double* p : ws)
-    if (p) (void)hipFree(p);
-  if (pl->ws_q32) (void)hipFree(pl->ws_q32);
+// the execute workspace back to the context (queued work done first)
+void release_workspace(vp_plan* pl) {
+  void* ws[] = {pl->ws_f, pl->ws_c, pl->ws_q, pl->ws_part, pl->ws_u, pl->ws_q32};
+  bool any = false;
+  for (void* p : ws) any = any || p;
+  if (!any) return;
+  (void)hipDeviceSynchronize();
+  for (void* p : ws)
+    if (p) vp::ctx_release(pl->ctx, p);
   pl->ws_f = pl->ws_c = pl->ws_q = pl->ws_part = pl->ws_u = nullptr;
   pl->ws_q32 = nullptr;
+}
+
+void free_plan_memory(vp_plan* pl) {
+  if (!pl->allocs.empty()) {
+    // kernels of the plan's build or of executes on other streams may still
+    // read these blocks; the cache hands them out without a device wait
+    (void)hipDeviceSynchronize();
+    for (void* p : pl->allocs) vp::ctx_release(pl->ctx, p);
+  }
+  pl->allocs.clear();
+  release_workspace(pl);
 }
 
 struct PlanGuard {
@@ -77,21 +90,8 @@ struct PlanGuard {
 
 template <class T>
 hipError_t upload(vp_plan* pl, T** dst, const T* src, size_t n, hipStream_t st) {
-  size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
-  hipError_t e = hipMalloc((void**)dst, bytes);
-  if (e != hipSuccess) return e;
-  pl->allocs.push_back(*dst);
-  pl->bytes += bytes;
-  if (n) e = hipMemcpyAsync(*dst, src, n * sizeof(T), hipMemcpyHostToDevice, st);
-  return e;
-}
-
-hipError_t plan_alloc(vp_plan* pl, void** dst, size_t bytes) {
-  bytes = std::max<size_t>(bytes, 8);
-  hipError_t e = hipMalloc(dst, bytes);
-  if (e != hipSuccess) return e;
-  pl->allocs.push_back(*dst);
-  pl->bytes += bytes;
+  hipError_t e = vp::plan_alloc(pl, (void**)dst, std::max<size_t>(n, 1) * sizeof(T));
+  if (e == hipSuccess && n) e = hipMemcpyAsync(*dst, src, n * sizeof(T), hipMemcpyHostToDevice, st);
   return e;
 }
 
@@ -187,7 +187,21 @@ vp_status vp_ctx_destroy(vp_ctx* ctx) {
   for (auto& kv : ctx->fmm_ops)
     for (void* x : {(void*)kv.second.m2m, (void*)kv.second.l2l, (void*)kv.second.m2l})
       if (x) (void)hipFree(x);
+  vp::ctx_trim(ctx);
   delete ctx;
+  return VP_OK;
+}
+
+vp_status vp_ctx_cached_bytes(const vp_ctx* ctx, uint64_t* bytes_out) {
+  if (!ctx || !bytes_out) return fail(VP_EINVAL, "vp_ctx_cached_bytes: NULL argument");
+  *bytes_out = ctx->cached;
+  return VP_OK;
+}
+
+vp_status vp_ctx_trim(vp_ctx* ctx) {
+  if (!ctx) return fail(VP_EINVAL, "vp_ctx_trim: ctx is NULL");
+  VP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  vp::ctx_trim(ctx);
   return VP_OK;
 }
 
@@ -594,9 +608,9 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
   pl->n_rc = (int)rcr.size();
 #undef UP
   const int NP = pl->n_p;
-  if ((e = plan_alloc(pl, (void**)&pl->vinv, sizeof(double) * NP * NP)) != hipSuccess ||
-      (e = plan_alloc(pl, (void**)&pl->efar, sizeof(double) * pl->n_f * NP)) != hipSuccess ||
-      (e = plan_alloc(pl, (void**)&pl->wfar, sizeof(double) * pl->n_f * NP)) != hipSuccess)
+  if ((e = vp::plan_alloc(pl, (void**)&pl->vinv, sizeof(double) * NP * NP)) != hipSuccess ||
+      (e = vp::plan_alloc(pl, (void**)&pl->efar, sizeof(double) * pl->n_f * NP)) != hipSuccess ||
+      (e = vp::plan_alloc(pl, (void**)&pl->wfar, sizeof(double) * pl->n_f * NP)) != hipSuccess)
     return hip_fail(e, "vp_plan_create: hipMalloc");
   // Vandermonde inverse (device, FP64)
   {
@@ -628,8 +642,8 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
     std::vector<double2> lt(vp::kLogTab + 1), lw(vp::kFarLogTab + 1);
     vp::log_table(lt.data(), vp::kLogTab);
     vp::log_table(lw.data(), vp::kFarLogTab);
-    if ((e = plan_alloc(pl, (void**)&pl->logtab, sizeof(double2) * lt.size())) != hipSuccess ||
-        (e = plan_alloc(pl, (void**)&pl->logtab_wide, sizeof(double2) * lw.size())) != hipSuccess ||
+    if ((e = vp::plan_alloc(pl, (void**)&pl->logtab, sizeof(double2) * lt.size())) != hipSuccess ||
+        (e = vp::plan_alloc(pl, (void**)&pl->logtab_wide, sizeof(double2) * lw.size())) != hipSuccess ||
         (e = hipMemcpyAsync(pl->logtab, lt.data(), sizeof(double2) * lt.size(), hipMemcpyHostToDevice, st)) !=
             hipSuccess ||
         (e = hipMemcpyAsync(pl->logtab_wide, lw.data(), sizeof(double2) * lw.size(), hipMemcpyHostToDevice,
@@ -637,13 +651,13 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
         (e = hipStreamSynchronize(st)) != hipSuccess)
       return hip_fail(e, "vp_plan_create: log tables");
   }
-  if ((e = plan_alloc(pl, (void**)&pl->sxy, sizeof(double2) * pl->n_src_pad)) != hipSuccess ||
-      (e = plan_alloc(pl, (void**)&pl->sgrp, sizeof(double) * 3 * (pl->n_src_pad / 64))) != hipSuccess ||
-      (e = plan_alloc(pl, (void**)&pl->soff, sizeof(float2) * pl->n_src_pad)) != hipSuccess ||
-      (e = plan_alloc(pl, (void**)&pl->swj, sizeof(double) * pl->n_src_pad)) != hipSuccess ||
-      (e = plan_alloc(pl, (void**)&pl->deff, sizeof(double) * std::max<int64_t>(pl->n_tri, 1))) != hipSuccess ||
-      (e = plan_alloc(pl, (void**)&pl->xt, sizeof(double) * n_tgt)) != hipSuccess ||
-      (e = plan_alloc(pl, (void**)&pl->yt, sizeof(double) * n_tgt)) != hipSuccess)
+  if ((e = vp::plan_alloc(pl, (void**)&pl->sxy, sizeof(double2) * pl->n_src_pad)) != hipSuccess ||
+      (e = vp::plan_alloc(pl, (void**)&pl->sgrp, sizeof(double) * 3 * (pl->n_src_pad / 64))) != hipSuccess ||
+      (e = vp::plan_alloc(pl, (void**)&pl->soff, sizeof(float2) * pl->n_src_pad)) != hipSuccess ||
+      (e = vp::plan_alloc(pl, (void**)&pl->swj, sizeof(double) * pl->n_src_pad)) != hipSuccess ||
+      (e = vp::plan_alloc(pl, (void**)&pl->deff, sizeof(double) * std::max<int64_t>(pl->n_tri, 1))) != hipSuccess ||
+      (e = vp::plan_alloc(pl, (void**)&pl->xt, sizeof(double) * n_tgt)) != hipSuccess ||
+      (e = vp::plan_alloc(pl, (void**)&pl->yt, sizeof(double) * n_tgt)) != hipSuccess)
     return hip_fail(e, "vp_plan_create: hipMalloc");
   if ((e = vp::launch_sources(pl, st)) != hipSuccess) return hip_fail(e, "vp_plan_create: sources");
   {
@@ -702,7 +716,7 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
   VP_HIP(hipEventRecord(ev1, st), "hipEventRecord");
   StageTimer tm_rows(ctx, VP_STAGE_ROWS);
   // correction rows
-  if ((e = plan_alloc(pl, (void**)&pl->rows, sizeof(double) * pl->n_pairs * NP)) != hipSuccess)
+  if ((e = vp::plan_alloc(pl, (void**)&pl->rows, sizeof(double) * pl->n_pairs * NP)) != hipSuccess)
     return hip_fail(e, "vp_plan_create: rows");
   {
     int* d_flag = nullptr;
@@ -873,13 +887,8 @@ vp_status ensure_workspace(vp_plan* pl, int64_t R, int64_t split) {
   if (pl->ws_rhs >= R && pl->ws_split >= split && pl->ws_c) return VP_OK;
   R = std::max(R, pl->ws_rhs);
   split = std::max(split, pl->ws_split);
-  double* ws[] = {pl->ws_f, pl->ws_c, pl->ws_q, pl->ws_part, pl->ws_u};
-  for (double* p : ws)
-    if (p) (void)hipFree(p);
-  if (pl->ws_q32) (void)hipFree(pl->ws_q32);
-  pl->ws_f = pl->ws_c = pl->ws_q = pl->ws_part = pl->ws_u = nullptr;
-  pl->ws_q32 = nullptr;
   pl->ctx->in_use -= pl->ws_bytes;
+  release_workspace(pl);
   pl->ws_bytes = 0;
   pl->ws_rhs = 0;
   const size_t nF = (size_t)pl->n_tri * pl->n_p * R;
@@ -890,12 +899,13 @@ vp_status ensure_workspace(vp_plan* pl, int64_t R, int64_t split) {
   if (pl->ctx->budget && pl->ctx->in_use + bytes > pl->ctx->budget)
     return fail(VP_ENOMEM, "vp_execute: workspace of %zu bytes exceeds the HBM budget", bytes);
   hipError_t e;
-  if ((e = hipMalloc((void**)&pl->ws_f, 8 * std::max<size_t>(nF, 1))) != hipSuccess ||
-      (e = hipMalloc((void**)&pl->ws_c, 8 * std::max<size_t>(nF, 1))) != hipSuccess ||
-      (e = hipMalloc((void**)&pl->ws_q, 8 * std::max<size_t>(nQ, 1))) != hipSuccess ||
-      (e = hipMalloc((void**)&pl->ws_part, 8 * std::max<size_t>(nP, 1))) != hipSuccess ||
-      (e = hipMalloc((void**)&pl->ws_u, 8 * std::max<size_t>(nU, 1))) != hipSuccess ||
-      (e = hipMalloc((void**)&pl->ws_q32, 4 * std::max<size_t>(nQ, 1))) != hipSuccess ||
+  vp_ctx* c = pl->ctx;
+  if ((e = vp::ctx_alloc(c, (void**)&pl->ws_f, 8 * std::max<size_t>(nF, 1))) != hipSuccess ||
+      (e = vp::ctx_alloc(c, (void**)&pl->ws_c, 8 * std::max<size_t>(nF, 1))) != hipSuccess ||
+      (e = vp::ctx_alloc(c, (void**)&pl->ws_q, 8 * std::max<size_t>(nQ, 1))) != hipSuccess ||
+      (e = vp::ctx_alloc(c, (void**)&pl->ws_part, 8 * std::max<size_t>(nP, 1))) != hipSuccess ||
+      (e = vp::ctx_alloc(c, (void**)&pl->ws_u, 8 * std::max<size_t>(nU, 1))) != hipSuccess ||
+      (e = vp::ctx_alloc(c, (void**)&pl->ws_q32, 4 * std::max<size_t>(nQ, 1))) != hipSuccess ||
       (e = hipMemsetAsync(pl->ws_q, 0, 8 * std::max<size_t>(nQ, 1), pl->ctx->stream)) != hipSuccess) {
     return hip_fail(e, "vp_execute: workspace");
   }
@@ -907,6 +917,74 @@ vp_status ensure_workspace(vp_plan* pl, int64_t R, int64_t split) {
 }
 
 }  // namespace
+
+namespace vp {
+
+hipError_t ctx_alloc(vp_ctx* ctx, void** p, size_t bytes) {
+  *p = nullptr;
+  // sizes rounded so that blocks of nearly equal requests are interchangeable
+  const size_t g = bytes >= (size_t(1) << 20) ? (size_t(2) << 20) : 256;
+  const size_t r = (std::max<size_t>(bytes, 8) + g - 1) / g * g;
+  auto it = ctx->cache.lower_bound(r);
+  if (it != ctx->cache.end() && it->first - r <= r / 4) {
+    *p = it->second;
+    ctx->cached -= it->first;
+    ctx->cache.erase(it);
+    return hipSuccess;
+  }
+  if (ctx->budget && ctx->in_use + ctx->cached + r > ctx->budget) ctx_trim(ctx);
+  hipError_t e = hipMalloc(p, r);
+  if (e == hipErrorOutOfMemory && !ctx->cache.empty()) {
+    (void)hipGetLastError();  // the failed attempt's error, not a later launch's
+    ctx_trim(ctx);
+    e = hipMalloc(p, r);
+  }
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return e;
+  }
+  ctx->block_size[*p] = r;
+  return hipSuccess;
+}
+
+void ctx_release(vp_ctx* ctx, void* p) {
+  if (!p) return;
+  auto it = ctx->block_size.find(p);
+  if (it == ctx->block_size.end()) {
+    (void)hipFree(p);
+    return;
+  }
+  const size_t r = it->second;
+  const bool fits = ctx->cached + r <= kCacheMaxBytes &&
+                    (!ctx->budget || ctx->in_use + ctx->cached + r <= ctx->budget);
+  if (!fits) {
+    ctx->block_size.erase(it);
+    (void)hipFree(p);
+    return;
+  }
+  ctx->cache.emplace(r, p);
+  ctx->cached += r;
+}
+
+void ctx_trim(vp_ctx* ctx) {
+  for (auto& kv : ctx->cache) {
+    ctx->block_size.erase(kv.second);
+    (void)hipFree(kv.second);
+  }
+  ctx->cache.clear();
+  ctx->cached = 0;
+}
+
+hipError_t plan_alloc(vp_plan* pl, void** dst, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 8);
+  hipError_t e = ctx_alloc(pl->ctx, dst, bytes);
+  if (e != hipSuccess) return e;
+  pl->allocs.push_back(*dst);
+  pl->bytes += bytes;
+  return e;
+}
+
+}  // namespace vp
 
 extern "C" {
 

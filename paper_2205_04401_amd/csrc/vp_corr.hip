@@ -152,14 +152,7 @@ hipError_t build_clusters(vp_plan* pl, hipStream_t st) {
     pl->n_cl = 0;
     return hipSuccess;
   }
-  auto alloc = [&](void** p, size_t bytes) -> hipError_t {
-    hipError_t r = hipMalloc(p, bytes ? bytes : 8);
-    if (r == hipSuccess) {
-      pl->allocs.push_back(*p);
-      pl->bytes += bytes;
-    }
-    return r;
-  };
+  auto alloc = [&](void** p, size_t bytes) -> hipError_t { return plan_alloc(pl, p, bytes); };
   const int64_t ncl = pl->n_cl;
   int32_t* cnt = nullptr;
   void* tmp = nullptr;

@@ -887,14 +887,7 @@ int64_t fmm_workspace_doubles(const vp_plan* pl, int64_t R) {
 hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
   const int64_t NS = pl->n_src, NT = pl->n_tgt;
   const int p = pl->fmm_terms;
-  auto alloc = [&](void** ptr, size_t bytes) -> hipError_t {
-    hipError_t r = hipMalloc(ptr, bytes ? bytes : 8);
-    if (r == hipSuccess) {
-      pl->allocs.push_back(*ptr);
-      pl->bytes += bytes;
-    }
-    return r;
-  };
+  auto alloc = [&](void** ptr, size_t bytes) -> hipError_t { return plan_alloc(pl, ptr, bytes); };
   hipError_t e;
   // root square
   const int nred = 256;
@@ -1118,13 +1111,15 @@ hipError_t fmm_prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st) {
   double *vsrc = nullptr, *wtgt = nullptr;
   int2* tt = nullptr;
   hipError_t e;
-  if ((e = hipMalloc((void**)&vsrc, sizeof(double) * NS * pl->fmm_mp)) != hipSuccess ||
-      (e = hipMalloc((void**)&wtgt, sizeof(double) * NT * pl->fmm_kp)) != hipSuccess ||
-      (e = hipMalloc((void**)&tt, sizeof(int2) * std::max<size_t>(tiles.size(), 1))) != hipSuccess) {
-    for (void* x : {(void*)vsrc, (void*)wtgt, (void*)tt})
-      if (x) (void)hipFree(x);
+  // the blocks belong to the plan from here on, also when this fails
+  const size_t held = pl->bytes;
+  if ((e = plan_alloc(pl, (void**)&vsrc, sizeof(double) * NS * pl->fmm_mp)) != hipSuccess ||
+      (e = plan_alloc(pl, (void**)&wtgt, sizeof(double) * NT * pl->fmm_kp)) != hipSuccess ||
+      (e = plan_alloc(pl, (void**)&tt, sizeof(int2) * std::max<size_t>(tiles.size(), 1))) != hipSuccess) {
+    pl->ctx->in_use += pl->bytes - held;
     return e;
   }
+  pl->ctx->in_use += pl->bytes - held;
   const double sL = pl->fmm_width / n;
   k_fmm_vsrc<<<blocks_for(NS), kBlock, 0, st>>>(pl->fmm_sxy, NS, pl->fmm_x0, pl->fmm_y0, sL, L, p, pl->fmm_mp, vsrc);
   k_fmm_wtgt<<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, pl->fmm_tgt_perm, NT, pl->fmm_x0, pl->fmm_y0, sL, L, p,
@@ -1133,17 +1128,11 @@ hipError_t fmm_prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st) {
   if (e == hipSuccess && !tiles.empty())
     e = hipMemcpyAsync(tt, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) {
-    for (void* x : {(void*)vsrc, (void*)wtgt, (void*)tt}) (void)hipFree(x);
-    return e;
-  }
-  for (void* x : {(void*)vsrc, (void*)wtgt, (void*)tt}) pl->allocs.push_back(x);
+  if (e != hipSuccess) return e;
   pl->fmm_vsrc = vsrc;
   pl->fmm_wtgt = wtgt;
   pl->fmm_ttile = tt;
   pl->fmm_n_ttiles = (int64_t)tiles.size();
-  pl->bytes += bytes;
-  pl->ctx->in_use += bytes;
   return hipSuccess;
 }
 

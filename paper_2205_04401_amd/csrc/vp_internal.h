@@ -359,6 +359,14 @@ struct vp_ctx {
     size_t bytes = 0;
   };
   std::map<int, FmmOps> fmm_ops;
+  // Device blocks of destroyed plans and outgrown plan workspaces, kept for
+  // the context's later plans (freeing a block of hundreds of MB costs about
+  // a millisecond of host time, and a plan holds a dozen): cache maps a
+  // block's size to the idle block, block_size holds the size of every
+  // block allocated this way, idle or not.
+  std::multimap<size_t, void*> cache;
+  std::map<void*, size_t> block_size;
+  uint64_t cached = 0;
   int live_meshes = 0;
   // profiling: pending event pairs per stage, folded into the totals on read
   bool profile = false;
@@ -482,6 +490,20 @@ struct vp_plan {
 };
 
 namespace vp {
+
+// Device memory of plans, through the context's block cache.  ctx_alloc
+// takes an idle cached block of at least `bytes` (and at most a quarter
+// more), else calls hipMalloc, emptying the cache and trying once more when
+// the device is out of memory.  ctx_release takes a block that no queued
+// device work uses any more: it joins the cache while the cache stays
+// within kCacheMaxBytes (and, with an HBM budget, the budget), else it is
+// freed.  ctx_trim frees every idle block.  plan_alloc allocates a block
+// owned by the plan (released when the plan is destroyed).
+constexpr uint64_t kCacheMaxBytes = uint64_t(16) << 30;
+hipError_t ctx_alloc(vp_ctx* ctx, void** p, size_t bytes);
+void ctx_release(vp_ctx* ctx, void* p);
+void ctx_trim(vp_ctx* ctx);
+hipError_t plan_alloc(vp_plan* pl, void** dst, size_t bytes);
 
 // ---------------------------------------------------------------------------
 // Kernel launchers (vp_*.hip).  All enqueue on `st` and return the launch

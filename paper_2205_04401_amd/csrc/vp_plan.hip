@@ -704,14 +704,7 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
   const vp_mesh* m = pl->mesh;
   const int64_t T = pl->n_tri, NT = pl->n_tgt;
   hipError_t e;
-  auto alloc = [&](void** p, size_t bytes) -> hipError_t {
-    hipError_t r = hipMalloc(p, bytes ? bytes : 8);
-    if (r == hipSuccess) {
-      pl->allocs.push_back(*p);
-      pl->bytes += bytes;
-    }
-    return r;
-  };
+  auto alloc = [&](void** p, size_t bytes) -> hipError_t { return plan_alloc(pl, p, bytes); };
   e = alloc((void**)&pl->row_ptr, sizeof(int64_t) * (NT + 1));
   if (e != hipSuccess) return e;
   if (NT == 0 || T == 0) {

@@ -32,7 +32,7 @@ EXPORTS = ["vp_ctx_create", "vp_ctx_destroy", "vp_last_error", "vp_ref_nodes", "
            "vp_ctx_profile", "vp_ctx_timings", "vp_server_create", "vp_server_destroy", "vp_submit",
            "vp_poll", "vp_wait", "vp_server_stats", "vp_interp_create", "vp_interp_destroy", "vp_interp_locate",
            "vp_interp_eval", "vp_graph_create", "vp_graph_launch", "vp_graph_destroy", "vp_plan_far_config",
-           "vp_plan_set_far_config", "vp_plan_autotune"]
+           "vp_plan_set_far_config", "vp_plan_autotune", "vp_ctx_cached_bytes", "vp_ctx_trim"]
 FAR_SHAPES = {"wide": 0, "narrow1": 1, "narrow2": 2}
 STAGES = ["classify", "rows", "coef", "far", "finish"]
 
@@ -105,6 +105,8 @@ def load(path=LIB_PATH):
         "vp_plan_destroy": [P],
         "vp_sync": [P],
         "vp_ctx_profile": [P, ctypes.c_int],
+        "vp_ctx_cached_bytes": [P, ctypes.POINTER(ctypes.c_uint64)],
+        "vp_ctx_trim": [P],
         "vp_ctx_timings": [P, P, P],
         "vp_server_create": [P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(P)],
         "vp_server_destroy": [P],
@@ -199,6 +201,16 @@ class Context:
     def profile(self, on=True):
         """Turn stage timing on/off (resets the accumulators)."""
         _check(load().vp_ctx_profile(self.h, 1 if on else 0))
+
+    def cached_bytes(self):
+        """Device bytes held in cached blocks of destroyed plans."""
+        n = ctypes.c_uint64(0)
+        _check(load().vp_ctx_cached_bytes(self.h, ctypes.byref(n)))
+        return int(n.value)
+
+    def trim(self):
+        """Free the cached blocks of destroyed plans."""
+        _check(load().vp_ctx_trim(self.h))
 
     def timings(self):
         """{stage: (total ms, launches)} accumulated since profile(True)."""
