@@ -616,7 +616,8 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
   {
     double* scratch = nullptr;
     const size_t sbytes = sizeof(double) * (2 * NP + 2 * NP * NP) + sizeof(int) * 2;
-    if ((e = hipMalloc((void**)&scratch, sbytes)) != hipSuccess) return hip_fail(e, "vp_plan_create: hipMalloc");
+    vp::Scratch scr(ctx, st);
+    if ((e = scr.alloc((void**)&scratch, sbytes)) != hipSuccess) return hip_fail(e, "vp_plan_create: hipMalloc");
     std::vector<double> nxy(2 * NP);
     for (int i = 0; i < NP; ++i) {
       nxy[i] = nodes.x[i];
@@ -629,11 +630,8 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
         (e = hipMemsetAsync(d_bad, 0, sizeof(int), st)) != hipSuccess ||
         (e = vp::launch_basis_tables(pl, scratch, st)) != hipSuccess ||
         (e = hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (e = hipStreamSynchronize(st)) != hipSuccess) {
-      (void)hipFree(scratch);
+        (e = hipStreamSynchronize(st)) != hipSuccess)
       return hip_fail(e, "vp_plan_create: basis tables");
-    }
-    (void)hipFree(scratch);
     if (bad) return fail(VP_EINTERNAL, "vp_plan_create: singular Vandermonde matrix");
   }
   // sources and targets
@@ -664,24 +662,17 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
     double* d_xy = nullptr;
     int* d_bad = nullptr;
     int bad = 0;
-    if ((e = hipMalloc((void**)&d_xy, sizeof(double) * 2 * std::max<int64_t>(n_tgt, 1))) != hipSuccess)
+    vp::Scratch scr(ctx, st);
+    if ((e = scr.alloc((void**)&d_xy, sizeof(double) * 2 * std::max<int64_t>(n_tgt, 1))) != hipSuccess ||
+        (e = scr.alloc((void**)&d_bad, sizeof(int))) != hipSuccess)
       return hip_fail(e, "vp_plan_create: hipMalloc");
-    if ((e = hipMalloc((void**)&d_bad, sizeof(int))) != hipSuccess) {
-      (void)hipFree(d_xy);
-      return hip_fail(e, "vp_plan_create: hipMalloc");
-    }
     const hipMemcpyKind kind = (o.flags & VP_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     if ((e = hipMemsetAsync(d_bad, 0, sizeof(int), st)) != hipSuccess ||
         (n_tgt && (e = hipMemcpyAsync(d_xy, tgt_xy, sizeof(double) * 2 * n_tgt, kind, st)) != hipSuccess) ||
         (e = vp::launch_split_xy(d_xy, n_tgt, pl->xt, pl->yt, d_bad, st)) != hipSuccess ||
         (e = hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (e = hipStreamSynchronize(st)) != hipSuccess) {
-      (void)hipFree(d_xy);
-      (void)hipFree(d_bad);
+        (e = hipStreamSynchronize(st)) != hipSuccess)
       return hip_fail(e, "vp_plan_create: targets");
-    }
-    (void)hipFree(d_xy);
-    (void)hipFree(d_bad);
     if (bad) return fail(VP_EINVAL, "vp_plan_create: non-finite target coordinate");
   }
   // near-field pair list
@@ -721,11 +712,10 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
   {
     int* d_flag = nullptr;
     int64_t* d_stats = nullptr;
-    if ((e = hipMalloc((void**)&d_flag, sizeof(int))) != hipSuccess) return hip_fail(e, "vp_plan_create: hipMalloc");
-    if ((e = hipMalloc((void**)&d_stats, sizeof(int64_t) * 4)) != hipSuccess) {
-      (void)hipFree(d_flag);
+    vp::Scratch scr(ctx, st);
+    if ((e = scr.alloc((void**)&d_flag, sizeof(int))) != hipSuccess ||
+        (e = scr.alloc((void**)&d_stats, sizeof(int64_t) * 4)) != hipSuccess)
       return hip_fail(e, "vp_plan_create: hipMalloc");
-    }
     int flag = 0;
     if ((e = hipMemsetAsync(d_flag, 0, sizeof(int), st)) != hipSuccess ||
         (e = hipMemsetAsync(d_stats, 0, sizeof(int64_t) * 4, st)) != hipSuccess ||
@@ -733,13 +723,8 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
         (e = hipEventRecord(ev2, st)) != hipSuccess || (tm_rows.stop(1), false) ||
         (e = hipMemcpyAsync(&flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipMemcpyAsync(pl->stats, d_stats, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (e = hipStreamSynchronize(st)) != hipSuccess) {
-      (void)hipFree(d_flag);
-      (void)hipFree(d_stats);
+        (e = hipStreamSynchronize(st)) != hipSuccess)
       return hip_fail(e, "vp_plan_create: correction rows");
-    }
-    (void)hipFree(d_flag);
-    (void)hipFree(d_stats);
     if (flag == 1) return fail(VP_EINTERNAL, "vp_plan_create: near subdivision exceeded its depth-first stack");
     if (flag) return fail(VP_EINTERNAL, "vp_plan_create: a self pair's point location on a curved triangle failed");
   }

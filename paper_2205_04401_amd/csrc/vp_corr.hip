@@ -157,20 +157,18 @@ hipError_t build_clusters(vp_plan* pl, hipStream_t st) {
   int32_t* cnt = nullptr;
   void* tmp = nullptr;
   hipError_t e;
+  Scratch scr(pl->ctx, st);
   if ((e = alloc((void**)&pl->cl_ptr, sizeof(int64_t) * (ncl + 1))) != hipSuccess) return e;
-  if ((e = hipMalloc((void**)&cnt, sizeof(int32_t) * ncl)) != hipSuccess) return e;
-  if ((e = hipMalloc(&tmp, exclusive_scan_tmp_bytes(ncl))) != hipSuccess) {
-    (void)hipFree(cnt);
+  if ((e = scr.alloc((void**)&cnt, sizeof(int32_t) * ncl)) != hipSuccess ||
+      (e = scr.alloc(&tmp, exclusive_scan_tmp_bytes(ncl))) != hipSuccess)
     return e;
-  }
   const unsigned nb = blocks_for(ncl * kCl);
   k_cluster_union<<<nb, kBlock, 0, st>>>(pl->row_ptr, pl->pair_tri, NT, ncl, nullptr, cnt, nullptr, nullptr);
   int64_t ne = 0;
   if ((e = hipGetLastError()) == hipSuccess && (e = exclusive_scan_i32(cnt, pl->cl_ptr, ncl, tmp, st)) == hipSuccess &&
       (e = hipMemcpyAsync(&ne, pl->cl_ptr + ncl, sizeof(int64_t), hipMemcpyDeviceToHost, st)) == hipSuccess)
     e = hipStreamSynchronize(st);
-  (void)hipFree(cnt);
-  (void)hipFree(tmp);
+  scr.release();
   if (e != hipSuccess) return e;
   pl->n_entries = ne;
   if ((e = alloc((void**)&pl->ent_tri, sizeof(int32_t) * ne)) != hipSuccess ||

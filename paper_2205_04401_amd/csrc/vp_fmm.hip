@@ -892,13 +892,15 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
   // root square
   const int nred = 256;
   double* part = nullptr;
-  if ((e = hipMalloc((void**)&part, sizeof(double) * 4 * nred)) != hipSuccess) return e;
-  k_fmm_bbox_partial<<<nred, kBlock, 0, st>>>(pl->sxy, NS, pl->xt, pl->yt, NT, part);
   std::vector<double> hp(4 * nred);
-  if ((e = hipGetLastError()) == hipSuccess &&
-      (e = hipMemcpyAsync(hp.data(), part, sizeof(double) * 4 * nred, hipMemcpyDeviceToHost, st)) == hipSuccess)
-    e = hipStreamSynchronize(st);
-  (void)hipFree(part);
+  {
+    Scratch tb(pl->ctx, st);
+    if ((e = tb.alloc((void**)&part, sizeof(double) * 4 * nred)) != hipSuccess) return e;
+    k_fmm_bbox_partial<<<nred, kBlock, 0, st>>>(pl->sxy, NS, pl->xt, pl->yt, NT, part);
+    if ((e = hipGetLastError()) == hipSuccess &&
+        (e = hipMemcpyAsync(hp.data(), part, sizeof(double) * 4 * nred, hipMemcpyDeviceToHost, st)) == hipSuccess)
+      e = hipStreamSynchronize(st);
+  }
   if (e != hipSuccess) return e;
   double x0 = 1e300, y0 = 1e300, x1 = -1e300, y1 = -1e300;
   for (int i = 0; i < nred; ++i) {
@@ -923,15 +925,9 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
   int32_t *sval = nullptr, *tval = nullptr, *cnt = nullptr;
   void* tmp = nullptr;
   size_t tmp_s = 0, tmp_t = 0;
-  std::vector<void*> tmps;
-  auto talloc = [&](void** ptr, size_t bytes) -> hipError_t {
-    hipError_t r = hipMalloc(ptr, bytes ? bytes : 8);
-    if (r == hipSuccess) tmps.push_back(*ptr);
-    return r;
-  };
-  auto cleanup = [&]() {
-    for (void* x : tmps) (void)hipFree(x);
-  };
+  Scratch tmps(pl->ctx, st);
+  auto talloc = [&](void** ptr, size_t bytes) { return tmps.alloc(ptr, bytes); };
+  auto cleanup = [&]() { tmps.release(); };
   if ((e = alloc((void**)&pl->fmm_src_perm, sizeof(int32_t) * NS)) != hipSuccess ||
       (e = alloc((void**)&pl->fmm_tgt_perm, sizeof(int32_t) * NT)) != hipSuccess ||
       (e = alloc((void**)&pl->fmm_sxy, sizeof(double2) * NS)) != hipSuccess ||
@@ -1070,7 +1066,8 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
   {
     unsigned long long* d_cnt = nullptr;
     unsigned long long h_cnt[2] = {0, 0};
-    if ((e = hipMalloc((void**)&d_cnt, sizeof(h_cnt))) != hipSuccess) return e;
+    Scratch tc(pl->ctx, st);
+    if ((e = tc.alloc((void**)&d_cnt, sizeof(h_cnt))) != hipSuccess) return e;
     e = hipMemsetAsync(d_cnt, 0, sizeof(h_cnt), st);
     for (int l = 2; l <= L && e == hipSuccess; ++l) {
       k_fmm_work<<<blocks_for((int64_t)1 << (2 * l)), kBlock, 0, st>>>(pl->fmm_cnt_src + off[l], pl->fmm_cnt_tgt + off[l],
@@ -1079,7 +1076,7 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
     }
     if (e == hipSuccess) e = hipMemcpyAsync(h_cnt, d_cnt, sizeof(h_cnt), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(d_cnt);
+    tc.release();
     if (e != hipSuccess) return e;
     pl->fmm_near_pairs = (int64_t)h_cnt[0];
     pl->fmm_m2l_pairs = (int64_t)h_cnt[1];

@@ -505,6 +505,30 @@ void ctx_release(vp_ctx* ctx, void* p);
 void ctx_trim(vp_ctx* ctx);
 hipError_t plan_alloc(vp_plan* pl, void** dst, size_t bytes);
 
+// Temporaries of a plan build used on stream st only, from the context's
+// block cache: release() (also run by the destructor) waits for st and hands
+// them back, so a later allocation can take them without a device wait.
+struct Scratch {
+  vp_ctx* ctx;
+  hipStream_t st;
+  std::vector<void*> blocks;
+  Scratch(vp_ctx* c, hipStream_t s) : ctx(c), st(s) {}
+  Scratch(const Scratch&) = delete;
+  Scratch& operator=(const Scratch&) = delete;
+  ~Scratch() { release(); }
+  hipError_t alloc(void** p, size_t bytes) {
+    hipError_t r = ctx_alloc(ctx, p, bytes ? bytes : 8);
+    if (r == hipSuccess) blocks.push_back(*p);
+    return r;
+  }
+  void release() {
+    if (blocks.empty()) return;
+    (void)hipStreamSynchronize(st);
+    for (void* p : blocks) ctx_release(ctx, p);
+    blocks.clear();
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (vp_*.hip).  All enqueue on `st` and return the launch
 // status.

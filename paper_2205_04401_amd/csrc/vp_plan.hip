@@ -717,15 +717,9 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
     return e;
   }
   // temporaries
-  std::vector<void*> tmp;
-  auto talloc = [&](void** p, size_t bytes) -> hipError_t {
-    hipError_t r = hipMalloc(p, bytes ? bytes : 8);
-    if (r == hipSuccess) tmp.push_back(*p);
-    return r;
-  };
-  auto cleanup = [&]() {
-    for (void* p : tmp) (void)hipFree(p);
-  };
+  Scratch tmp(pl->ctx, st);
+  auto talloc = [&](void** p, size_t bytes) { return tmp.alloc(p, bytes); };
+  auto cleanup = [&]() { tmp.release(); };
   double *thr = nullptr, *box = nullptr, *part = nullptr;
   const int nred = 256;
   if ((e = talloc((void**)&thr, sizeof(double) * 3 * T)) != hipSuccess ||
