@@ -126,8 +126,10 @@ struct ReduceScatter<1, 0> {
 };
 
 // kCurved: the mesh has curved triangles (the straight-only instance carries
-// none of their code)
-template <int P, bool kCurved>
+// none of their code).  KIND: 0 every pair, 1 near pairs only, 2 self pairs
+// only (each of the two then carries only its own branch, with fewer live
+// registers than both together)
+template <int P, bool kCurved, int KIND>
 __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
   __shared__ double lv[2][kCap * 3];
@@ -175,6 +177,7 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
   const int32_t t = a.pair_tri[pr];
   const int32_t it = a.pair_tgt[pr];
   const int kind = a.pair_kind[pr];
+  if ((KIND == 1 && kind != 1) || (KIND == 2 && kind == 1)) continue;  // the whole workgroup
   const double x = a.xt[it], y = a.yt[it];
   const double Ax = a.ax[t], Ay = a.ay[t], Bx = a.bx[t], By = a.by[t], Cx = a.cx[t], Cy = a.cy[t];
   const double D = a.det[t];
@@ -232,7 +235,7 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
   add_far_rule();
 
   int64_t n_leaves = 0, n_panels = 0, n_capped = 0;
-  if (kind == 1) {
+  if (KIND == 1 || (KIND == 0 && kind == 1)) {
     // ---- A, near pair: breadth-first subdivision ----
     // The ellipses of a level-L sub-triangle (|s| = 2^-L, area 4^-L of the
     // triangle's) have rho_e = rho0_e 2^(-2L/N_n) and edges l_e 2^-L.
@@ -651,12 +654,24 @@ hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t s
   dim3 grid((unsigned)std::min<int64_t>((pl->n_pairs + kPairsPerGroup - 1) / kPairsPerGroup, 1 << 25));
   const bool curved = m->n_curved > 0;
   const size_t lds = sizeof(double) * (3 * (size_t)a.nn + 2 * (size_t)a.nl + 3 * (size_t)a.nr + 3 * (size_t)a.n_rc);
+  // Straight meshes with many self pairs (a quarter or more: coarse far
+  // rules, where few targets have near pairs) run near and self pairs as two
+  // launches, each sized to its pairs; with fewer the one kernel is faster.
+  const int64_t n_near = pl->n_pairs - pl->n_self;
+  const bool split = !curved && pl->n_self > 0 && n_near > 0 && 4 * pl->n_self >= pl->n_pairs;
+  auto groups = [&](int64_t n) {
+    return dim3((unsigned)std::min<int64_t>((n + kPairsPerGroup - 1) / kPairsPerGroup, 1 << 25));
+  };
 #define VP_ROWS(PV)                                                   \
   case PV:                                                            \
-    if (curved)                                                       \
-      k_rows<PV, true><<<grid, 64, lds, st>>>(a);                     \
-    else                                                              \
-      k_rows<PV, false><<<grid, 64, lds, st>>>(a);                    \
+    if (curved) {                                                     \
+      k_rows<PV, true, 0><<<grid, 64, lds, st>>>(a);                  \
+    } else if (split) {                                               \
+      k_rows<PV, false, 1><<<groups(n_near), 64, lds, st>>>(a);       \
+      k_rows<PV, false, 2><<<groups(pl->n_self), 64, lds, st>>>(a);   \
+    } else {                                                          \
+      k_rows<PV, false, 0><<<grid, 64, lds, st>>>(a);                 \
+    }                                                                 \
     break
   switch (pl->p) {
     VP_ROWS(1);
