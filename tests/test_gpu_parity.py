@@ -836,6 +836,52 @@ def test_star_full_size_sampled(vp_ctx, q):
     mesh.close()
 
 
+def test_rows_near_and_self_launched_apart(vp_ctx):
+    """At q = 16 on a star a quarter or more of the pairs are self pairs, so
+    near and self rows come from two separate launches: each row equals the
+    oracle's, and the end-to-end result meets the bar."""
+    p, q, eps = 6, 16, 1e-13
+    vq, tq = W.star_mesh(n_tri=1500, n_boundary=250, seed=60)  # a third of the pairs are self pairs
+    vt, tt = W.star_mesh(n_tri=1500, n_boundary=250, seed=61, staggered=True)
+    nodes = rules.interp_nodes(p)
+    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    F = W.sample_density(W.gaussian_sum(62, vq, tq), vq, tq, nodes)
+    mesh = vp_ctx.mesh(vq, tq)
+    plan = vp_ctx.plan(mesh, p, q, eps, tg)
+    info = plan.info()
+    say("split rows: pairs", info["n_pairs"], "self", info["n_self"])
+    assert 4 * info["n_self"] >= info["n_pairs"] > info["n_self"] > 0
+    rp, tri, kind = plan.pairs()
+    rows = plan.rows()
+    o = potential.Oracle(vq, tq, p, q, eps)
+    rng = np.random.default_rng(63)
+    sample = np.sort(rng.choice(len(tg), 40, replace=False))
+    # a row is a near integral minus its far-rule sum, both of the size of the
+    # triangle's area times a logarithm: the bar is 10 eps times the area
+    e1, e2 = vq[tq[:, 1]] - vq[tq[:, 0]], vq[tq[:, 2]] - vq[tq[:, 0]]
+    area = 0.5 * np.abs(e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0])
+    worst, n_self, n_near = 0.0, 0, 0
+    for i in sample:
+        ref = {t: (k, o.row(t, tg[i], k)) for t, k in o.classify_target(tg[i])}
+        for p_ in range(rp[i], rp[i + 1]):
+            t = int(tri[p_])
+            if t not in ref or ref[t][0] != int(kind[p_]):
+                continue  # a pair on a decision boundary (checked by the pair-list tests)
+            n_self += ref[t][0] == 0
+            n_near += ref[t][0] == 1
+            worst = max(worst, np.abs(rows[p_] - ref[t][1]).max() / area[t])
+    u = plan.execute(F)
+    ref_u = o.evaluate(F, tg[sample])
+    e_all = np.abs(u[sample] - ref_u).max() / np.abs(ref_u).max()
+    say("split rows: compared", n_self, "self and", n_near, "near rows, worst difference / area", worst,
+        "end-to-end", e_all)
+    assert n_self > 0 and n_near > 0
+    assert worst <= 10 * eps
+    assert e_all <= REL_E2E
+    plan.close()
+    mesh.close()
+
+
 # ---------------------------------------------------------------------------
 # serving: each result is the same alone and in the mix
 # ---------------------------------------------------------------------------
