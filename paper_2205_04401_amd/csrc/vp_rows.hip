@@ -654,11 +654,15 @@ hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t s
   dim3 grid((unsigned)std::min<int64_t>((pl->n_pairs + kPairsPerGroup - 1) / kPairsPerGroup, 1 << 25));
   const bool curved = m->n_curved > 0;
   const size_t lds = sizeof(double) * (3 * (size_t)a.nn + 2 * (size_t)a.nl + 3 * (size_t)a.nr + 3 * (size_t)a.n_rc);
-  // Straight meshes with many self pairs (a quarter or more: coarse far
-  // rules, where few targets have near pairs) run near and self pairs as two
-  // launches, each sized to its pairs; with fewer the one kernel is faster.
+  // Straight meshes with many self pairs (a quarter or more: fine far rules,
+  // where few targets have near pairs) at tight tolerances (deep near
+  // subdivisions) run near and self pairs as two launches, each sized to its
+  // pairs.  Measured on the star: q = 16 at eps = 1e-13 (37% self pairs) 8%
+  // faster apart; q = 8 at eps = 1e-13 (13%) and at eps = 1e-8 (46%, shallow
+  // near subdivisions) 8-10% faster in one launch.
   const int64_t n_near = pl->n_pairs - pl->n_self;
-  const bool split = !curved && pl->n_self > 0 && n_near > 0 && 4 * pl->n_self >= pl->n_pairs;
+  const bool split =
+      !curved && pl->n_self > 0 && n_near > 0 && 4 * pl->n_self >= pl->n_pairs && pl->eps <= 1e-10;
   auto groups = [&](int64_t n) {
     return dim3((unsigned)std::min<int64_t>((n + kPairsPerGroup - 1) / kPairsPerGroup, 1 << 25));
   };
