@@ -712,19 +712,25 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
   {
     int* d_flag = nullptr;
     int64_t* d_stats = nullptr;
+    constexpr size_t kStatBytes = sizeof(int64_t) * vp::kRowStatSlots * vp::kRowStatStride;
     vp::Scratch scr(ctx, st);
     if ((e = scr.alloc((void**)&d_flag, sizeof(int))) != hipSuccess ||
-        (e = scr.alloc((void**)&d_stats, sizeof(int64_t) * 4)) != hipSuccess)
+        (e = scr.alloc((void**)&d_stats, kStatBytes)) != hipSuccess)
       return hip_fail(e, "vp_plan_create: hipMalloc");
     int flag = 0;
+    std::vector<int64_t> slots((size_t)vp::kRowStatSlots * vp::kRowStatStride);
     if ((e = hipMemsetAsync(d_flag, 0, sizeof(int), st)) != hipSuccess ||
-        (e = hipMemsetAsync(d_stats, 0, sizeof(int64_t) * 4, st)) != hipSuccess ||
+        (e = hipMemsetAsync(d_stats, 0, kStatBytes, st)) != hipSuccess ||
         (e = vp::launch_rows(pl, d_flag, d_stats, st)) != hipSuccess ||
         (e = hipEventRecord(ev2, st)) != hipSuccess || (tm_rows.stop(1), false) ||
         (e = hipMemcpyAsync(&flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess ||
-        (e = hipMemcpyAsync(pl->stats, d_stats, sizeof(int64_t) * 4, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(slots.data(), d_stats, kStatBytes, hipMemcpyDeviceToHost, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess)
       return hip_fail(e, "vp_plan_create: correction rows");
+    for (int i = 0; i < 4; ++i) {
+      pl->stats[i] = 0;
+      for (int sl = 0; sl < vp::kRowStatSlots; ++sl) pl->stats[i] += slots[(size_t)sl * vp::kRowStatStride + i];
+    }
     if (flag == 1) return fail(VP_EINTERNAL, "vp_plan_create: near subdivision exceeded its depth-first stack");
     if (flag) return fail(VP_EINTERNAL, "vp_plan_create: a self pair's point location on a curved triangle failed");
   }

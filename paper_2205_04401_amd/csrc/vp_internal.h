@@ -543,6 +543,11 @@ hipError_t launch_vinv(int p, const double* nx, const double* ny, double* aug, d
                        hipStream_t st);
 constexpr int kCurvedRadial = 12;  // points per part of the radial rule on curved self pieces
 hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err);  // near-list construction
+// Diagnostics of the correction rows (near leaves, self panels, capped
+// leaves, depth-first pairs): kRowStatSlots slots of kRowStatStride int64
+// (one cache line each), zeroed by the caller and summed over the slots.
+constexpr int kRowStatSlots = 256;
+constexpr int kRowStatStride = 16;
 hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t st);
 hipError_t launch_coefficients(const vp_plan* pl, const double* F, int64_t R, double* C, double* Q,
                                hipStream_t st);

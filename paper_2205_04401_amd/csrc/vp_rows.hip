@@ -173,6 +173,10 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
     s_cb[i] = a.rad_c_b[i];
   }
   __syncthreads();
+  // this workgroup's diagnostics (near leaves, self panels, capped leaves,
+  // depth-first pairs), added to the device counters once at the end: one
+  // atomic per pair on shared counters serialises the whole launch
+  int64_t tot_leaves = 0, tot_panels = 0, tot_capped = 0, tot_df = 0;
   for (int64_t pr = blockIdx.x; pr < a.n_pairs; pr += gridDim.x) {
   const int32_t t = a.pair_tri[pr];
   const int32_t it = a.pair_tgt[pr];
@@ -359,7 +363,7 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
       n_cur = n_next;
     }
     if (overflow) {
-      if (lane == 0) atomicAdd((unsigned long long*)&a.stats[3], 1ull);
+      ++tot_df;
       // Depth-first walk of the same subdivision, one sub-triangle at a
       // time (lanes share its near-rule nodes); the stack holds at most
       // 3 depth_cap + 1 entries, within the two level buffers.
@@ -579,13 +583,19 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
     for (int i = 0; i < 2; ++i)
       if (i < len) out[base + i] = acc[i] * kInv2Pi;
   }
-  if (lane == 0) {
-    if (n_leaves) atomicAdd((unsigned long long*)&a.stats[0], (unsigned long long)n_leaves);
-    if (n_panels) atomicAdd((unsigned long long*)&a.stats[1], (unsigned long long)n_panels);
-    if (n_capped) atomicAdd((unsigned long long*)&a.stats[2], (unsigned long long)n_capped);
-  }
+  tot_leaves += n_leaves;
+  tot_panels += n_panels;
+  tot_capped += n_capped;
   __syncthreads();
   }  // pair loop
+  if (lane == 0) {
+    // spread over kRowStatSlots cache lines (summed on the host)
+    unsigned long long* st = (unsigned long long*)(a.stats + (int64_t)(blockIdx.x & (kRowStatSlots - 1)) * kRowStatStride);
+    if (tot_leaves) atomicAdd(st + 0, (unsigned long long)tot_leaves);
+    if (tot_panels) atomicAdd(st + 1, (unsigned long long)tot_panels);
+    if (tot_capped) atomicAdd(st + 2, (unsigned long long)tot_capped);
+    if (tot_df) atomicAdd(st + 3, (unsigned long long)tot_df);
+  }
 }
 
 }  // namespace
