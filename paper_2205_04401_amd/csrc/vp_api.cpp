@@ -731,6 +731,7 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
       pl->stats[i] = 0;
       for (int sl = 0; sl < vp::kRowStatSlots; ++sl) pl->stats[i] += slots[(size_t)sl * vp::kRowStatStride + i];
     }
+    pl->stats[0] += pl->tab_leaves;
     if (flag == 1) return fail(VP_EINTERNAL, "vp_plan_create: near subdivision exceeded its depth-first stack");
     if (flag) return fail(VP_EINTERNAL, "vp_plan_create: a self pair's point location on a curved triangle failed");
   }

@@ -413,6 +413,7 @@ struct vp_plan {
   vp_plan_opts opts{};
   int64_t n_tri = 0, n_src = 0, n_tgt = 0, n_pairs = 0, n_self = 0;
   int64_t stats[4] = {0, 0, 0, 0};  // near leaves, self panels, capped leaves, depth-first pairs
+  int64_t tab_pairs = 0, tab_leaves = 0;  // near pairs (and their leaves) of the matrix-core row path
   double ms_classify = 0.0, ms_rows = 0.0;
   // rule tables (device)
   double* vinv = nullptr;   // [n_p][n_p]

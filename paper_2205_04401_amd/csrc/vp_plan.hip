@@ -2,7 +2,10 @@
 // near-field pair list (Def. of far/near field, Sec. 3.2; Bernstein-ellipse
 // union, Sec. 4.1, eqs. rho0 and threeE; nearby-element query, App. A.5,
 // replaced by a uniform grid of cells over the targets).
+#include <hipcub/hipcub.hpp>
+
 #include <algorithm>
+#include <climits>
 #include <cmath>
 
 #include "vp_internal.h"
@@ -358,34 +361,32 @@ __global__ void k_cell_count(const double* __restrict__ box, int64_t n_tri, Grid
     for (int i = i0; i <= i1; ++i) atomicAdd(&cnt[(int64_t)j * g.nx + i], 1);
 }
 
-__global__ void k_cell_fill(const double* __restrict__ box, int64_t n_tri, Grid g, const int64_t* __restrict__ ptr,
-                            int32_t* fill, int32_t* cell_tri) {
+// cells covered by each triangle's box (the number of entries it emits)
+__global__ void k_cell_tcount(const double* __restrict__ box, int64_t n_tri, Grid g, int32_t* tcnt) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tri) return;
+  int i0, i1, j0, j1;
+  tcnt[t] = box_cells(g, box[t], box[n_tri + t], box[2 * n_tri + t], box[3 * n_tri + t], i0, i1, j0, j1)
+                ? (i1 - i0 + 1) * (j1 - j0 + 1)
+                : 0;
+}
+
+// (cell, triangle) entries in triangle order at the triangle's offset; a
+// stable sort by cell then gives every cell's list in ascending triangle
+// order, independent of the launch
+__global__ void k_cell_emit(const double* __restrict__ box, int64_t n_tri, Grid g, const int64_t* __restrict__ toff,
+                            int32_t* __restrict__ key, int32_t* __restrict__ val) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_tri) return;
   int i0, i1, j0, j1;
   if (!box_cells(g, box[t], box[n_tri + t], box[2 * n_tri + t], box[3 * n_tri + t], i0, i1, j0, j1)) return;
+  int64_t o = toff[t];
   for (int j = j0; j <= j1; ++j)
     for (int i = i0; i <= i1; ++i) {
-      int64_t c = (int64_t)j * g.nx + i;
-      int slot = atomicAdd(&fill[c], 1);
-      cell_tri[ptr[c] + slot] = (int32_t)t;
+      key[o] = j * g.nx + i;
+      val[o] = (int32_t)t;
+      ++o;
     }
-}
-
-// deterministic order inside each cell (ascending triangle index)
-__global__ void k_cell_sort(const int64_t* __restrict__ ptr, int64_t n_cells, int32_t* cell_tri) {
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_cells) return;
-  int64_t b = ptr[c], e = ptr[c + 1];
-  for (int64_t i = b + 1; i < e; ++i) {
-    int32_t v = cell_tri[i];
-    int64_t j = i - 1;
-    while (j >= b && cell_tri[j] > v) {
-      cell_tri[j + 1] = cell_tri[j];
-      --j;
-    }
-    cell_tri[j + 1] = v;
-  }
 }
 
 struct TriView {
@@ -766,38 +767,66 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
   g.nx = std::max(1, (int)std::ceil(wx / h) + 1);
   g.ny = std::max(1, (int)std::ceil(wy / h) + 1);
   const int64_t nc = (int64_t)g.nx * g.ny;
-  int32_t *ccnt = nullptr, *cfill = nullptr, *ctri = nullptr, *pcnt = nullptr, *scnt = nullptr;
-  int64_t* cptr = nullptr;
+  int32_t *ccnt = nullptr, *tcnt = nullptr, *ctri = nullptr, *pcnt = nullptr, *scnt = nullptr;
+  int64_t *cptr = nullptr, *toff = nullptr;
   void* stmp = nullptr;
-  const int64_t nscan = std::max(nc, NT);
+  const int64_t nscan = std::max(std::max(nc, NT), T);
   if ((e = talloc((void**)&ccnt, sizeof(int32_t) * nc)) != hipSuccess ||
-      (e = talloc((void**)&cfill, sizeof(int32_t) * nc)) != hipSuccess ||
+      (e = talloc((void**)&tcnt, sizeof(int32_t) * T)) != hipSuccess ||
       (e = talloc((void**)&cptr, sizeof(int64_t) * (nc + 1))) != hipSuccess ||
+      (e = talloc((void**)&toff, sizeof(int64_t) * (T + 1))) != hipSuccess ||
       (e = talloc(&stmp, exclusive_scan_tmp_bytes(nscan))) != hipSuccess ||
       (e = talloc((void**)&pcnt, sizeof(int32_t) * NT)) != hipSuccess ||
       (e = talloc((void**)&scnt, sizeof(int32_t) * NT)) != hipSuccess) {
     cleanup();
     return e;
   }
-  if ((e = hipMemsetAsync(ccnt, 0, sizeof(int32_t) * nc, st)) != hipSuccess ||
-      (e = hipMemsetAsync(cfill, 0, sizeof(int32_t) * nc, st)) != hipSuccess) {
+  if ((e = hipMemsetAsync(ccnt, 0, sizeof(int32_t) * nc, st)) != hipSuccess) {
     cleanup();
     return e;
   }
   k_cell_count<<<blocks_for(T), kBlock, 0, st>>>(box, T, g, ccnt);
+  k_cell_tcount<<<blocks_for(T), kBlock, 0, st>>>(box, T, g, tcnt);
   int64_t n_entries = 0;
   if ((e = exclusive_scan_i32(ccnt, cptr, nc, stmp, st)) != hipSuccess ||
+      (e = exclusive_scan_i32(tcnt, toff, T, stmp, st)) != hipSuccess ||
       (e = hipMemcpyAsync(&n_entries, cptr + nc, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess) {
     cleanup();
     return e;
   }
-  if ((e = talloc((void**)&ctri, sizeof(int32_t) * std::max<int64_t>(n_entries, 1))) != hipSuccess) {
+  if (n_entries >= (int64_t)INT_MAX) {
+    err = "near-field grid: too many (cell, triangle) entries";
     cleanup();
-    return e;
+    return hipErrorOutOfMemory;
   }
-  k_cell_fill<<<blocks_for(T), kBlock, 0, st>>>(box, T, g, cptr, cfill, ctri);
-  k_cell_sort<<<blocks_for(nc), kBlock, 0, st>>>(cptr, nc, ctri);
+  {
+    // entries in triangle order, then a stable radix sort by cell
+    int32_t *key = nullptr, *key2 = nullptr, *val = nullptr;
+    void* sort_tmp = nullptr;
+    size_t sort_bytes = 0;
+    const size_t ne = (size_t)std::max<int64_t>(n_entries, 1);
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) < nc) ++bits;
+    if ((e = talloc((void**)&ctri, sizeof(int32_t) * ne)) != hipSuccess ||
+        (e = talloc((void**)&key, sizeof(int32_t) * ne)) != hipSuccess ||
+        (e = talloc((void**)&key2, sizeof(int32_t) * ne)) != hipSuccess ||
+        (e = talloc((void**)&val, sizeof(int32_t) * ne)) != hipSuccess ||
+        (e = hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, key, key2, val, ctri, (int)n_entries, 0, bits,
+                                                st)) != hipSuccess ||
+        (e = talloc(&sort_tmp, std::max<size_t>(sort_bytes, 16))) != hipSuccess) {
+      cleanup();
+      return e;
+    }
+    if (n_entries > 0) {
+      k_cell_emit<<<blocks_for(T), kBlock, 0, st>>>(box, T, g, toff, key, val);
+      if ((e = hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes, key, key2, val, ctri, (int)n_entries, 0, bits,
+                                                  st)) != hipSuccess) {
+        cleanup();
+        return e;
+      }
+    }
+  }
   TriView tv{m->ax, m->ay, m->bx, m->by, m->cx, m->cy, m->det, thr, T, pl->opts.near_model == VP_NEAR_BALL ? 1 : 0,
              pl->opts.ball_factor, m->curves()};
   k_pair_count<<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, tv, pl->opts.tau, pcnt);

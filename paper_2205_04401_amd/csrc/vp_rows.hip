@@ -41,6 +41,8 @@ struct RowsArgs {
   const int32_t* pair_tgt;
   const uint8_t* pair_kind;
   int64_t n_pairs;
+  const uint32_t* list;  // pairs to compute (n_list of them), or null for all n_pairs
+  int64_t n_list;
   const double *xt, *yt;
   const double *ax, *ay, *bx, *by, *cx, *cy, *det;
   const double *far_x, *far_y, *far_w, *efar;
@@ -125,6 +127,47 @@ struct ReduceScatter<1, 0> {
   static __device__ __forceinline__ void run(double*, int, int&, int&) {}
 };
 
+// Focal-sum thresholds of the three near-rule ellipses of a level-L
+// sub-triangle (|s| = 2^-L): rho_e = rho0_e 2^(-2L/N_n), edges l_e 2^-L;
+// negative for an empty ellipse (rho <= 1).
+__device__ __forceinline__ void near_level_thr(const double rho0[3], const double ell0[3], int level,
+                                               double inv_near_order, double thr[3]) {
+  const double f = exp2(-2.0 * level * inv_near_order);
+  const double hl = ldexp(0.5, -level);
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const double rho = rho0[e] * f;
+    thr[e] = (rho > 1.0) ? hl * ell0[e] * (rho + 1.0 / rho) : -1.0;
+  }
+}
+
+// True if the target lies in one of the three ellipses of the straight
+// sub-triangle (sa, sb, ss) of the triangle A + xi1 e1 + xi2 e2.
+__device__ __forceinline__ bool near_sub_split(double x, double y, double Ax, double Ay, double e1x, double e1y,
+                                               double e2x, double e2y, double sa, double sb, double ss,
+                                               const double thr[3]) {
+  const double p0x = Ax + sa * e1x + sb * e2x, p0y = Ay + sa * e1y + sb * e2y;
+  const double p1x = p0x + ss * e1x, p1y = p0y + ss * e1y;
+  const double p2x = p0x + ss * e2x, p2y = p0y + ss * e2y;
+  const double d0 = sqrt((x - p0x) * (x - p0x) + (y - p0y) * (y - p0y));
+  const double d1 = sqrt((x - p1x) * (x - p1x) + (y - p1y) * (y - p1y));
+  const double d2 = sqrt((x - p2x) * (x - p2x) + (y - p2y) * (y - p2y));
+  return d0 + d1 < thr[0] || d1 + d2 < thr[1] || d2 + d0 < thr[2];
+}
+
+// rho0 and edge lengths of the near rule's ellipses for a straight triangle
+__device__ __forceinline__ void near_root(double Ax, double Ay, double Bx, double By, double Cx, double Cy,
+                                          double deff, const double wh[3], double eps_cn, double inv_near_order,
+                                          double rho0[3], double ell0[3]) {
+  const double px[3] = {Ax, Bx, Cx}, py[3] = {Ay, By, Cy};
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    rho0[e] = pow(wh[e] * deff / eps_cn, inv_near_order);
+    const double ex = px[(e + 1) % 3] - px[e], ey = py[(e + 1) % 3] - py[e];
+    ell0[e] = sqrt(ex * ex + ey * ey);
+  }
+}
+
 // kCurved: the mesh has curved triangles (the straight-only instance carries
 // none of their code).  KIND: 0 every pair, 1 near pairs only, 2 self pairs
 // only (each of the two then carries only its own branch, with fewer live
@@ -177,7 +220,9 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
   // depth-first pairs), added to the device counters once at the end: one
   // atomic per pair on shared counters serialises the whole launch
   int64_t tot_leaves = 0, tot_panels = 0, tot_capped = 0, tot_df = 0;
-  for (int64_t pr = blockIdx.x; pr < a.n_pairs; pr += gridDim.x) {
+  const int64_t n_work = a.list ? a.n_list : a.n_pairs;
+  for (int64_t wi = blockIdx.x; wi < n_work; wi += gridDim.x) {
+  const int64_t pr = a.list ? (int64_t)a.list[wi] : wi;
   const int32_t t = a.pair_tri[pr];
   const int32_t it = a.pair_tgt[pr];
   const int kind = a.pair_kind[pr];
@@ -243,15 +288,9 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
     // ---- A, near pair: breadth-first subdivision ----
     // The ellipses of a level-L sub-triangle (|s| = 2^-L, area 4^-L of the
     // triangle's) have rho_e = rho0_e 2^(-2L/N_n) and edges l_e 2^-L.
-    const double px[3] = {Ax, Bx, Cx}, py[3] = {Ay, By, Cy};
     const double wh[3] = {a.nwhat0, a.nwhat1, a.nwhat2};
     double rho0[3], ell0[3];
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-      rho0[e] = pow(wh[e] * a.deff[t] / a.eps_cn, a.inv_near_order);
-      const double ex = px[(e + 1) % 3] - px[e], ey = py[(e + 1) % 3] - py[e];
-      ell0[e] = sqrt(ex * ex + ey * ey);
-    }
+    near_root(Ax, Ay, Bx, By, Cx, Cy, a.deff[t], wh, a.eps_cn, a.inv_near_order, rho0, ell0);
     double* cur = lv[0];
     double* nxt = lv[1];
     if (lane == 0) {
@@ -266,14 +305,7 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
       int n_next = 0, n_leaf = 0;
       double thr[3];
       const double f = exp2(-2.0 * level * a.inv_near_order);
-      {
-        const double hl = ldexp(0.5, -level);
-#pragma unroll
-        for (int e = 0; e < 3; ++e) {
-          const double rho = rho0[e] * f;
-          thr[e] = (rho > 1.0) ? hl * ell0[e] * (rho + 1.0 / rho) : -1.0;
-        }
-      }
+      near_level_thr(rho0, ell0, level, a.inv_near_order, thr);
       for (int base = 0; base < n_cur; base += kWave) {
         const int i = base + lane;
         bool valid = i < n_cur;
@@ -291,18 +323,11 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
           sa = cur[3 * i];
           sb = cur[3 * i + 1];
           ss = cur[3 * i + 2];
-          // physical vertices of the sub-triangle
-          const double p0x = Ax + sa * e1x + sb * e2x, p0y = Ay + sa * e1y + sb * e2y;
-          const double p1x = p0x + ss * e1x, p1y = p0y + ss * e1y;
-          const double p2x = p0x + ss * e2x, p2y = p0y + ss * e2y;
           if (a.ball) {
             split = (level < a.depth_cap) && in_ball_sub(x, y, Ax, Ay, e1x, e1y, e2x, e2y, sa, sb, ss,
                                                          a.ball_factor);
           } else {
-            const double d0 = sqrt((x - p0x) * (x - p0x) + (y - p0y) * (y - p0y));
-            const double d1 = sqrt((x - p1x) * (x - p1x) + (y - p1y) * (y - p1y));
-            const double d2 = sqrt((x - p2x) * (x - p2x) + (y - p2y) * (y - p2y));
-            split = (level < a.depth_cap) && (d0 + d1 < thr[0] || d1 + d2 < thr[1] || d2 + d0 < thr[2]);
+            split = (level < a.depth_cap) && near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, sa, sb, ss, thr);
           }
         }
         const bool is_leaf = valid && !split;
@@ -387,7 +412,6 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
         __syncthreads();
         const int level = -ilogb(fabs(ss));
         const double f = exp2(-2.0 * level * a.inv_near_order);
-        const double hl = ldexp(0.5, -level);
         bool split = false;
         if (level < a.depth_cap && cf) {
           double rho[3];
@@ -397,18 +421,9 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
         } else if (level < a.depth_cap && a.ball) {
           split = in_ball_sub(x, y, Ax, Ay, e1x, e1y, e2x, e2y, sa, sb, ss, a.ball_factor);
         } else if (level < a.depth_cap) {
-          const double p0x = Ax + sa * e1x + sb * e2x, p0y = Ay + sa * e1y + sb * e2y;
-          const double p1x = p0x + ss * e1x, p1y = p0y + ss * e1y;
-          const double p2x = p0x + ss * e2x, p2y = p0y + ss * e2y;
-          const double d0 = sqrt((x - p0x) * (x - p0x) + (y - p0y) * (y - p0y));
-          const double d1 = sqrt((x - p1x) * (x - p1x) + (y - p1y) * (y - p1y));
-          const double d2 = sqrt((x - p2x) * (x - p2x) + (y - p2y) * (y - p2y));
-          const double dd[3] = {d0 + d1, d1 + d2, d2 + d0};
-#pragma unroll
-          for (int e = 0; e < 3; ++e) {
-            const double rho = rho0[e] * f;
-            if (rho > 1.0 && dd[e] < hl * ell0[e] * (rho + 1.0 / rho)) split = true;
-          }
+          double thr[3];
+          near_level_thr(rho0, ell0, level, a.inv_near_order, thr);
+          split = near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, sa, sb, ss, thr);
         }
         if (split) {
           if (sp + 4 > kStack) {
@@ -598,7 +613,383 @@ __global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Shallow near pairs on the matrix cores.
+//
+// A near pair whose subdivision stops at the triangle itself (depth class 0)
+// or after one split into four leaves (class 1) integrates the near rule at
+// nodes fixed in the reference simplex, so the Koornwinder values there are
+// one table per class: with g_j the weighted logarithm at node j of the far
+// rule (subtracted, B) and of the leaves (A), the row is g^T Tab.  Sixteen
+// pairs at a time, g is the A operand of v_mfma_f64_16x16x4f64 (lane l: pair
+// l & 15, node 4 s + (l >> 4) of step s) and the table the B operand (node
+// 4 s + (l >> 4), basis function 16 n + (l & 15)); the lanes evaluate only
+// logarithms.  The pairs are sorted by class first: 0, 1, deeper near pairs
+// (2) and self pairs (3), the last two for k_rows.
+// ---------------------------------------------------------------------------
+constexpr int kClsThreads = 256;
+constexpr int kClsPer = 4;                              // pairs per thread
+constexpr int kClsChunk = kClsThreads * kClsPer;        // pairs per block
+constexpr int kTabNearMax = 64;                         // near-rule nodes of the table path (q_near <= 8)
+
+struct ClassArgs {
+  const int32_t *pair_tri, *pair_tgt;
+  const uint8_t* pair_kind;
+  int64_t n_pairs, n_blk;
+  const double *xt, *yt;
+  const double *ax, *ay, *bx, *by, *cx, *cy, *det, *deff;
+  double nwhat0, nwhat1, nwhat2, eps_cn, inv_near_order;
+  int depth_cap;
+  uint8_t* cls;     // [n_pairs] class of every pair
+  int32_t* bcnt;    // [4][n_blk] pairs of each class per block
+  const int64_t* boff;  // [4 n_blk + 1] exclusive scan of bcnt (scatter pass)
+  uint32_t* list;       // [n_pairs] pair indices sorted by class (scatter pass)
+};
+
+// depth class of near pair pr: the tests of k_rows' first two levels
+__device__ __forceinline__ int pair_class(const ClassArgs& a, int64_t pr) {
+  if (a.pair_kind[pr] != 1) return 3;
+  const int32_t t = a.pair_tri[pr];
+  const int32_t it = a.pair_tgt[pr];
+  const double x = a.xt[it], y = a.yt[it];
+  const double Ax = a.ax[t], Ay = a.ay[t], Bx = a.bx[t], By = a.by[t], Cx = a.cx[t], Cy = a.cy[t];
+  const double e1x = Bx - Ax, e1y = By - Ay, e2x = Cx - Ax, e2y = Cy - Ay;
+  const double wh[3] = {a.nwhat0, a.nwhat1, a.nwhat2};
+  double rho0[3], ell0[3], thr[3];
+  near_root(Ax, Ay, Bx, By, Cx, Cy, a.deff[t], wh, a.eps_cn, a.inv_near_order, rho0, ell0);
+  near_level_thr(rho0, ell0, 0, a.inv_near_order, thr);
+  if (!(0 < a.depth_cap && near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.0, 0.0, 1.0, thr))) return 0;
+  if (!(1 < a.depth_cap)) return 1;
+  near_level_thr(rho0, ell0, 1, a.inv_near_order, thr);
+  if (near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.0, 0.0, 0.5, thr) ||
+      near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.5, 0.0, 0.5, thr) ||
+      near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.0, 0.5, 0.5, thr) ||
+      near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.5, 0.5, -0.5, thr))
+    return 2;
+  return 1;
+}
+
+// count pass: class of every pair, pairs of each class per block
+__global__ __launch_bounds__(kClsThreads) void k_pair_class(ClassArgs a) {
+  __shared__ int cnt[4];
+  if (threadIdx.x < 4) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kClsChunk;
+  int my[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int i = 0; i < kClsPer; ++i) {
+    const int64_t pr = base + i * kClsThreads + threadIdx.x;
+    if (pr < a.n_pairs) {
+      const int c = pair_class(a, pr);
+      a.cls[pr] = (uint8_t)c;
+      my[c] += 1;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    int v = my[c];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(&cnt[c], v);
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) a.bcnt[threadIdx.x * a.n_blk + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// scatter pass: pair indices by class, in pair order within a class
+__global__ __launch_bounds__(kClsThreads) void k_pair_scatter(ClassArgs a) {
+  __shared__ int wtot[kClsThreads / 64][4];
+  const int64_t base = (int64_t)blockIdx.x * kClsChunk;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int64_t off[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) off[c] = a.boff[c * a.n_blk + blockIdx.x];
+  for (int i = 0; i < kClsPer; ++i) {
+    const int64_t pr = base + i * kClsThreads + threadIdx.x;
+    const int c = pr < a.n_pairs ? (int)a.cls[pr] : -1;
+    uint64_t m[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m[k] = __ballot(c == k);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wtot[w][k] = __popcll(m[k]);
+    }
+    __syncthreads();
+    if (c >= 0) {
+      int64_t o = off[c];
+      for (int v = 0; v < w; ++v) o += wtot[v][c];
+      a.list[o + __popcll(m[c] & lt)] = (uint32_t)pr;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      for (int v = 0; v < kClsThreads / 64; ++v) off[k] += wtot[v][k];
+    __syncthreads();
+  }
+}
+
+// Reference data of the two classes: node tables [rows][3] (xi1, xi2 and
+// the weight factor w_j s^2 of the leaf) and Koornwinder tables
+// [nf4 + rows][NPP] (far nodes first, zero rows and columns as padding).
+// Class 0: the near rule on the simplex; class 1: on its four children
+// (a, s) = ((0,0), 1/2), ((1/2,0), 1/2), ((0,1/2), 1/2), ((1/2,1/2), -1/2).
+template <int P>
+__global__ void k_tab_build(const double* __restrict__ fx, const double* __restrict__ fy, int nf, int nf4,
+                            const double* __restrict__ nx, const double* __restrict__ ny,
+                            const double* __restrict__ nw, int nn, int nn4, double* __restrict__ nod0,
+                            double* __restrict__ nod1, double* __restrict__ tab0, double* __restrict__ tab1) {
+  constexpr int NP = (P + 1) * (P + 2) / 2;
+  constexpr int NPP = 16 * ((NP + 15) / 16);
+  const int rows0 = nf4 + nn4, rows1 = nf4 + 4 * nn;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= rows0 + rows1) return;
+  const bool one = g >= rows0;
+  const int r = one ? g - rows0 : g;
+  double* row = (one ? tab1 : tab0) + (size_t)r * NPP;
+  for (int k = 0; k < NPP; ++k) row[k] = 0.0;
+  double xi1 = 0.0, xi2 = 0.0;
+  bool live = false;
+  if (r < nf) {
+    xi1 = fx[r];
+    xi2 = fy[r];
+    live = true;
+  } else if (r >= nf4) {
+    const int j = r - nf4;
+    if (!one && j < nn4) {
+      const bool v = j < nn;
+      nod0[3 * j] = v ? nx[j] : 0.0;
+      nod0[3 * j + 1] = v ? ny[j] : 0.0;
+      nod0[3 * j + 2] = v ? nw[j] : 0.0;
+      if (v) {
+        xi1 = nx[j];
+        xi2 = ny[j];
+        live = true;
+      }
+    } else if (one) {
+      const int c = j / nn, i = j - c * nn;
+      const double sa = (c == 1 || c == 3) ? 0.5 : 0.0, sb = (c >= 2) ? 0.5 : 0.0, ss = (c == 3) ? -0.5 : 0.5;
+      xi1 = sa + ss * nx[i];
+      xi2 = sb + ss * ny[i];
+      nod1[3 * j] = xi1;
+      nod1[3 * j + 1] = xi2;
+      nod1[3 * j + 2] = nw[i] * ss * ss;
+      live = true;
+    }
+  }
+  if (live) koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { row[k] = v; });
+}
+
+typedef double vp_d4 __attribute__((ext_vector_type(4)));
+
+struct TabArgs {
+  const uint32_t* list;  // class 0 pairs, then class 1 pairs
+  int64_t n0, n1;
+  const int32_t *pair_tri, *pair_tgt;
+  const double *xt, *yt;
+  const double *ax, *ay, *bx, *by, *cx, *cy, *det;
+  const double2* sxy;  // the far sources and their weights (as in the far sums)
+  const double* swj;
+  int nf, nf4, nn, nn4;
+  const double *nod0, *nod1, *tab0, *tab1;
+  const double2* logtab;
+  double* rows;
+};
+
+template <int P>
+__global__ __launch_bounds__(256) void k_rows_tab(TabArgs a) {
+  constexpr int NP = (P + 1) * (P + 2) / 2;
+  constexpr int NT = (NP + 15) / 16;
+  constexpr int NPP = 16 * NT;
+  __shared__ double2 tab[kLogTab + 1];
+  __shared__ double nod[3 * 5 * kTabNearMax];
+  for (int i = threadIdx.x; i <= kLogTab; i += blockDim.x) tab[i] = a.logtab[i];
+  for (int i = threadIdx.x; i < 3 * a.nn4; i += blockDim.x) nod[i] = a.nod0[i];
+  for (int i = threadIdx.x; i < 12 * a.nn; i += blockDim.x) nod[3 * a.nn4 + i] = a.nod1[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, kq = lane >> 4, col = lane & 15;
+  const int64_t t0 = (a.n0 + 15) / 16, n_tiles = t0 + (a.n1 + 15) / 16;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < n_tiles; tile += (int64_t)gridDim.x * 4) {
+    const bool one = tile >= t0;
+    const int64_t base = one ? a.n0 + (tile - t0) * 16 : tile * 16;
+    const int64_t end = one ? a.n0 + a.n1 : a.n0;
+    const bool valid = base + col < end;
+    const uint32_t pr = a.list[valid ? base + col : base];
+    const int32_t t = a.pair_tri[pr];
+    const int32_t it = a.pair_tgt[pr];
+    const double x = a.xt[it], y = a.yt[it];
+    const double Ax = a.ax[t], Ay = a.ay[t];
+    const double e1x = a.bx[t] - Ax, e1y = a.by[t] - Ay, e2x = a.cx[t] - Ax, e2y = a.cy[t] - Ay;
+    const double D = a.det[t];
+    const double* T = one ? a.tab1 : a.tab0;
+    const double* N = one ? nod + 3 * a.nn4 : nod;
+    const int n_near = one ? 4 * a.nn : a.nn;
+    const int n_slots = a.nf4 + (one ? 4 * a.nn : a.nn4);
+    const double2* src = a.sxy + (int64_t)t * a.nf;
+    const double* wsrc = a.swj + (int64_t)t * a.nf;
+    vp_d4 acc[NT];
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[n] = vp_d4{0.0, 0.0, 0.0, 0.0};
+    for (int s0 = 0; s0 < n_slots; s0 += 4) {
+      const int slot = s0 + kq;
+      double g = 0.0;
+      if (slot < a.nf) {
+        // the far rule's own contribution, subtracted (the far sums' expression)
+        const double2 sj = src[slot];
+        const double dx = x - sj.x, dy = y - sj.y;
+        const double r2 = fma(dy, dy, fma(dx, dx, kR2Bias));
+        g = -0.5 * vp_log(r2, tab) * wsrc[slot];
+      } else if (slot >= a.nf4 && slot - a.nf4 < n_near) {
+        const int j = slot - a.nf4;
+        const double xi1 = N[3 * j], xi2 = N[3 * j + 1];
+        const double yx = Ax + xi1 * e1x + xi2 * e2x;
+        const double yy = Ay + xi1 * e1y + xi2 * e2y;
+        const double dx = x - yx, dy = y - yy;
+        g = 0.5 * vp_log(dx * dx + dy * dy, tab) * N[3 * j + 2] * D;
+      }
+      if (!valid) g = 0.0;
+      const double* Trow = T + (size_t)slot * NPP + col;
+#pragma unroll
+      for (int n = 0; n < NT; ++n) acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(g, Trow[16 * n], acc[n], 0, 0, 0);
+    }
+    // element v of lane l: pair kq + 4 v of the tile, basis function 16 n + col
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int rrow = kq + 4 * v;
+      const uint32_t prow = (uint32_t)__shfl((int)pr, rrow);
+      if (base + rrow < end) {
+        double* out = a.rows + (size_t)prow * NP;
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+          if (16 * n + col < NP) out[16 * n + col] = acc[n][v] * kInv2Pi;
+      }
+    }
+  }
+}
+
 }  // namespace
+
+// The class-sorted launches of launch_rows (straight triangles, ellipse
+// model, q_near <= 8): class pass, scatter, then k_rows_tab over classes 0
+// and 1 and k_rows over deeper near pairs and over self pairs.
+template <int P>
+hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
+  constexpr int NP = (P + 1) * (P + 2) / 2;
+  constexpr int NPP = 16 * ((NP + 15) / 16);
+  const vp_mesh* m = pl->mesh;
+  const int64_t n = pl->n_pairs;
+  const int64_t n_blk = (n + kClsChunk - 1) / kClsChunk;
+  const int nf = pl->n_f, nf4 = (nf + 3) & ~3, nn = a.nn, nn4 = (nn + 3) & ~3;
+  const int rows0 = nf4 + nn4, rows1 = nf4 + 4 * nn;
+  Scratch tmp(pl->ctx, st);
+  uint8_t* cls = nullptr;
+  int32_t* bcnt = nullptr;
+  int64_t* boff = nullptr;
+  uint32_t* list = nullptr;
+  double *nod0 = nullptr, *nod1 = nullptr, *tab0 = nullptr, *tab1 = nullptr;
+  void* stmp = nullptr;
+  hipError_t e;
+  if ((e = tmp.alloc((void**)&cls, (size_t)n)) != hipSuccess ||
+      (e = tmp.alloc((void**)&bcnt, sizeof(int32_t) * 4 * n_blk)) != hipSuccess ||
+      (e = tmp.alloc((void**)&boff, sizeof(int64_t) * (4 * n_blk + 1))) != hipSuccess ||
+      (e = tmp.alloc((void**)&list, sizeof(uint32_t) * n)) != hipSuccess ||
+      (e = tmp.alloc(&stmp, exclusive_scan_tmp_bytes(4 * n_blk))) != hipSuccess ||
+      (e = tmp.alloc((void**)&nod0, sizeof(double) * 3 * nn4)) != hipSuccess ||
+      (e = tmp.alloc((void**)&nod1, sizeof(double) * 12 * nn)) != hipSuccess ||
+      (e = tmp.alloc((void**)&tab0, sizeof(double) * rows0 * NPP)) != hipSuccess ||
+      (e = tmp.alloc((void**)&tab1, sizeof(double) * rows1 * NPP)) != hipSuccess)
+    return e;
+  ClassArgs c;
+  c.pair_tri = pl->pair_tri;
+  c.pair_tgt = pl->pair_tgt;
+  c.pair_kind = pl->pair_kind;
+  c.n_pairs = n;
+  c.n_blk = n_blk;
+  c.xt = pl->xt;
+  c.yt = pl->yt;
+  c.ax = m->ax;
+  c.ay = m->ay;
+  c.bx = m->bx;
+  c.by = m->by;
+  c.cx = m->cx;
+  c.cy = m->cy;
+  c.det = m->det;
+  c.deff = pl->deff;
+  c.nwhat0 = a.nwhat0;
+  c.nwhat1 = a.nwhat1;
+  c.nwhat2 = a.nwhat2;
+  c.eps_cn = a.eps_cn;
+  c.inv_near_order = a.inv_near_order;
+  c.depth_cap = a.depth_cap;
+  c.cls = cls;
+  c.bcnt = bcnt;
+  c.boff = boff;
+  c.list = list;
+  k_pair_class<<<(unsigned)n_blk, kClsThreads, 0, st>>>(c);
+  k_tab_build<P><<<(rows0 + rows1 + 127) / 128, 128, 0, st>>>(pl->far_x, pl->far_y, nf, nf4, pl->near_x, pl->near_y,
+                                                              pl->near_w, nn, nn4, nod0, nod1, tab0, tab1);
+  int64_t tot[5] = {0, 0, 0, 0, 0};
+  if ((e = hipGetLastError()) != hipSuccess || (e = exclusive_scan_i32(bcnt, boff, 4 * n_blk, stmp, st)) != hipSuccess)
+    return e;
+  for (int k = 0; k < 4; ++k)
+    if ((e = hipMemcpyAsync(&tot[k], boff + k * n_blk, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
+      return e;
+  if ((e = hipMemcpyAsync(&tot[4], boff + 4 * n_blk, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return e;
+  const int64_t n0 = tot[1] - tot[0], n1 = tot[2] - tot[1], n2 = tot[3] - tot[2], n3 = tot[4] - tot[3];
+  if (n0 + n1 + n2 + n3 != n) return hipErrorUnknown;
+  k_pair_scatter<<<(unsigned)n_blk, kClsThreads, 0, st>>>(c);
+  if (n0 + n1 > 0) {
+    TabArgs ta;
+    ta.list = list;
+    ta.n0 = n0;
+    ta.n1 = n1;
+    ta.pair_tri = pl->pair_tri;
+    ta.pair_tgt = pl->pair_tgt;
+    ta.xt = pl->xt;
+    ta.yt = pl->yt;
+    ta.ax = m->ax;
+    ta.ay = m->ay;
+    ta.bx = m->bx;
+    ta.by = m->by;
+    ta.cx = m->cx;
+    ta.cy = m->cy;
+    ta.det = m->det;
+    ta.sxy = pl->sxy;
+    ta.swj = pl->swj;
+    ta.nf = nf;
+    ta.nf4 = nf4;
+    ta.nn = nn;
+    ta.nn4 = nn4;
+    ta.nod0 = nod0;
+    ta.nod1 = nod1;
+    ta.tab0 = tab0;
+    ta.tab1 = tab1;
+    ta.logtab = pl->logtab;
+    ta.rows = pl->rows;
+    const int64_t tiles = (n0 + 15) / 16 + (n1 + 15) / 16;
+    k_rows_tab<P><<<(unsigned)std::min<int64_t>((tiles + 3) / 4, 1 << 20), 256, 0, st>>>(ta);
+  }
+  constexpr int64_t kPairsPerGroup = 8;
+  auto groups = [&](int64_t k) {
+    return dim3((unsigned)std::min<int64_t>((k + kPairsPerGroup - 1) / kPairsPerGroup, 1 << 25));
+  };
+  if (n2 > 0) {
+    a.list = list + n0 + n1;
+    a.n_list = n2;
+    k_rows<P, false, 1><<<groups(n2), 64, lds, st>>>(a);
+  }
+  if (n3 > 0) {
+    a.list = list + n0 + n1 + n2;
+    a.n_list = n3;
+    k_rows<P, false, 2><<<groups(n3), 64, lds, st>>>(a);
+  }
+  // the table path's leaves: one per class-0 pair, four per class-1 pair
+  pl->tab_leaves = n0 + 4 * n1;
+  pl->tab_pairs = n0 + n1;
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  tmp.release();
+  return hipSuccess;
+}
 
 hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t st) {
   if (pl->n_pairs == 0) return hipSuccess;
@@ -655,6 +1046,8 @@ hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t s
   a.rows = pl->rows;
   a.flag = d_flag;
   a.stats = d_stats;
+  a.list = nullptr;
+  a.n_list = 0;
   // one 64-lane workgroup per 8 pairs (strided over the pair list), so that
   // the tables a workgroup stages in LDS serve several pairs while the
   // dispatcher still balances workgroups of uneven cost; grid-stride beyond
@@ -664,6 +1057,24 @@ hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t s
   dim3 grid((unsigned)std::min<int64_t>((pl->n_pairs + kPairsPerGroup - 1) / kPairsPerGroup, 1 << 25));
   const bool curved = m->n_curved > 0;
   const size_t lds = sizeof(double) * (3 * (size_t)a.nn + 2 * (size_t)a.nl + 3 * (size_t)a.nr + 3 * (size_t)a.n_rc);
+  // straight meshes with the ellipse model: pairs sorted by depth class,
+  // shallow near pairs on the matrix cores, deeper near pairs and self
+  // pairs by k_rows, each launch sized to its pairs
+  if (!curved && !a.ball && a.nn <= kTabNearMax && pl->n_pairs < ((int64_t)1 << 32)) {
+    switch (pl->p) {
+      case 1: return rows_by_class<1>(pl, a, lds, st);
+      case 2: return rows_by_class<2>(pl, a, lds, st);
+      case 3: return rows_by_class<3>(pl, a, lds, st);
+      case 4: return rows_by_class<4>(pl, a, lds, st);
+      case 5: return rows_by_class<5>(pl, a, lds, st);
+      case 6: return rows_by_class<6>(pl, a, lds, st);
+      case 7: return rows_by_class<7>(pl, a, lds, st);
+      case 8: return rows_by_class<8>(pl, a, lds, st);
+      case 9: return rows_by_class<9>(pl, a, lds, st);
+      case 10: return rows_by_class<10>(pl, a, lds, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   // Straight meshes with many self pairs (a quarter or more: fine far rules,
   // where few targets have near pairs) at tight tolerances (deep near
   // subdivisions) run near and self pairs as two launches, each sized to its

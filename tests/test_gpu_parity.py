@@ -882,6 +882,72 @@ def test_rows_near_and_self_launched_apart(vp_ctx):
     mesh.close()
 
 
+def near_depth_class(o, t, x):
+    """Depth class of a near pair in the oracle's subdivision: 0 if the
+    triangle itself is a leaf, 1 if it splits once into four leaves, else 2."""
+    A, B, C, D = o.A[t], o.B[t], o.C[t], o.D[t]
+    Nn = 2 * o.q_near - 1
+    stack = [(np.array([0.0, 0.0]), np.array([1.0, 0.0]), np.array([0.0, 1.0]), 0)]
+    deepest = 0
+    while stack:
+        a, b, c, d = stack.pop()
+        ra = abs((b[0] - a[0]) * (c[1] - a[1]) - (b[1] - a[1]) * (c[0] - a[0]))
+        P3 = potential.to_physical(A, B, C, np.stack([a, b, c]))
+        if o.in_ellipses(x, P3, ra * D, o.near_what, Nn):
+            m_ab, m_bc, m_ca = (a + b) / 2, (b + c) / 2, (c + a) / 2
+            stack += [(a, m_ab, m_ca, d + 1), (m_ab, b, m_bc, d + 1), (m_ca, m_bc, c, d + 1), (m_bc, m_ca, m_ab, d + 1)]
+        else:
+            deepest = max(deepest, d)
+    return min(deepest, 2)
+
+
+@pytest.mark.parametrize("p", [4, 6])
+def test_rows_of_every_depth_class(vp_ctx, p):
+    """Near pairs whose subdivision stops at the triangle (class 0) or after
+    one split (class 1) take the matrix-core row path, deeper near pairs and
+    self pairs the per-pair path: on a graded L-shape at q = 4, where all
+    four kinds are common, every sampled row of each kind equals the
+    oracle's, and the end-to-end result meets the bar."""
+    q, eps = 4, 1e-13
+    vq, tq = W.l_shape_graded(n_tri=3000, seed=70)
+    vt, tt = W.l_shape_graded(n_tri=3000, seed=71, staggered=True)
+    nodes = rules.interp_nodes(p)
+    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    F = W.sample_density(W.l_shape_density(72), vq, tq, nodes)
+    mesh = vp_ctx.mesh(vq, tq)
+    plan = vp_ctx.plan(mesh, p, q, eps, tg)
+    info = plan.info()
+    rp, tri, kind = plan.pairs()
+    rows = plan.rows()
+    o = potential.Oracle(vq, tq, p, q, eps)
+    rng = np.random.default_rng(73)
+    sample = np.sort(np.concatenate([rng.choice(len(tg), 40, replace=False),
+                                     np.argsort(np.hypot(tg[:, 0], tg[:, 1]))[:4]]))
+    e1, e2 = vq[tq[:, 1]] - vq[tq[:, 0]], vq[tq[:, 2]] - vq[tq[:, 0]]
+    area = 0.5 * np.abs(e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0])
+    worst = {0: 0.0, 1: 0.0, 2: 0.0, "self": 0.0}
+    seen = {0: 0, 1: 0, 2: 0, "self": 0}
+    for i in sample:
+        ref = {t: (k, o.row(t, tg[i], k)) for t, k in o.classify_target(tg[i])}
+        for p_ in range(rp[i], rp[i + 1]):
+            t = int(tri[p_])
+            if t not in ref or ref[t][0] != int(kind[p_]):
+                continue  # a pair on a decision boundary (checked by the pair-list tests)
+            cls = "self" if ref[t][0] == 0 else near_depth_class(o, t, tg[i])
+            seen[cls] += 1
+            worst[cls] = max(worst[cls], np.abs(rows[p_] - ref[t][1]).max() / area[t])
+    u = plan.execute(F)
+    ref_u = o.evaluate(F, tg[sample])
+    e_all = np.abs(u[sample] - ref_u).max() / np.abs(ref_u).max()
+    say("depth classes: pairs", info["n_pairs"], "compared", seen, "worst difference / area", worst,
+        "end-to-end", e_all)
+    assert all(v > 0 for v in seen.values()), seen
+    assert max(worst.values()) <= 10 * eps
+    assert e_all <= REL_E2E
+    plan.close()
+    mesh.close()
+
+
 # ---------------------------------------------------------------------------
 # serving: each result is the same alone and in the mix
 # ---------------------------------------------------------------------------
