@@ -242,6 +242,25 @@ vp_status vp_plan_rows(const vp_plan* plan, double* rows_out);
 vp_status vp_execute(vp_plan* plan, int64_t n_rhs, const double* density, double* u_out,
                      vp_precision prec, uint32_t flags);
 
+/* The same evaluation without allocating device memory, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments as in vp_execute; flags must
+ * include VP_DEVICE_PTRS (density and u_out are caller-owned device
+ * arrays) and may add VP_FAR_ONLY and VP_ASYNC.  The workspace
+ * (coefficients, far charges, their FP32 copy in VP_MIXED, far partial
+ * sums) comes from one fixed device array of VP_NOALLOC_SCRATCH_BYTES per
+ * device, held from the first vp_ctx_create on that device until the
+ * process ends and shared by every call on that device: calls that overlap
+ * on one device (other streams, other threads, VP_ASYNC calls whose work
+ * is still queued on another context's stream) race on it.  A call whose
+ * workspace would exceed VP_NOALLOC_SCRATCH_BYTES returns VP_EINVAL; so
+ * does an FMM plan with 16 or more densities before a vp_execute with 16 or
+ * more densities has built the plan's FMM tables for such blocks.  The call
+ * makes no hipMalloc, hipFree or other allocating call. */
+#define VP_NOALLOC_SCRATCH_BYTES (256ull << 20)
+vp_status vp_execute_noalloc(vp_plan* plan, int64_t n_rhs, const double* density, double* u_out,
+                             vp_precision prec, uint32_t flags);
+
 /* Intermediates of vp_execute, for inspection: coefficients
  * [n_tri][n_p][n_rhs] (Sec. 2.2: c = V^{-1} F per triangle) and far charges
  * [n_src][n_rhs] = w_j |J| f_h(y_j) / (4 pi) (the 1/2 of log r = log(r^2)/2

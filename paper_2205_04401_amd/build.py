@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvp.so")
-SOURCES = ["vp_rules.cpp", "vp_api.cpp", "vp_serve.cpp", "vp_plan.hip", "vp_exec.hip", "vp_corr.hip", "vp_fmm.hip", "vp_rows.hip",
+SOURCES = ["vp_rules.cpp", "vp_api.cpp", "vp_serve.cpp", "vp_noalloc.cpp", "vp_plan.hip", "vp_exec.hip", "vp_corr.hip", "vp_fmm.hip", "vp_rows.hip",
            "vp_interp.hip"]
 ARCH = os.environ.get("VP_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

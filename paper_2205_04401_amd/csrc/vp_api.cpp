@@ -171,6 +171,7 @@ vp_status vp_ctx_create(int device, void* stream, uint64_t budget, vp_ctx** out)
   VP_HIP(hipGetDeviceCount(&n), "hipGetDeviceCount");
   if (device < 0 || device >= n) return fail(VP_EINVAL, "vp_ctx_create: device %d of %d", device, n);
   VP_HIP(hipSetDevice(device), "hipSetDevice");
+  VP_HIP(vp::noalloc_setup(device), "vp_ctx_create: address of the allocation-free workspace");
   vp_ctx* c = new vp_ctx;
   c->device = device;
   c->stream = (hipStream_t)stream;

@@ -580,6 +580,9 @@ hipError_t fmm_prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st);
 hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out, double* ws, hipStream_t st,
                       int64_t* n_launches);
 void set_last_error(const char* msg);
+// Records the device address of the allocation-free evaluation's workspace
+// array on `device` (current), once per device.
+hipError_t noalloc_setup(int device);
 // dst[i][c0 + r] = src[i][r] for i < rows, r < src_cols (dst has dst_cols)
 hipError_t launch_pack_columns(const double* src, int64_t rows, int64_t src_cols, double* dst, int64_t dst_cols,
                                int64_t c0, hipStream_t st);

@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "VP_OK", 1: "VP_EINVAL", 2: "VP_ENOMEM", 3: "VP_EDEVICE", 4: 
 # every symbol include/vp.h declares
 EXPORTS = ["vp_ctx_create", "vp_ctx_destroy", "vp_last_error", "vp_ref_nodes", "vp_ref_rule", "vp_mesh_create",
            "vp_mesh_destroy", "vp_mesh_set_curved_sides", "vp_mesh_map_points", "vp_plan_create", "vp_plan_info", "vp_plan_pairs", "vp_plan_rows",
-           "vp_execute", "vp_coefficients", "vp_plan_sources", "vp_plan_destroy", "vp_sync",
+           "vp_execute", "vp_execute_noalloc", "vp_coefficients", "vp_plan_sources", "vp_plan_destroy", "vp_sync",
            "vp_ctx_profile", "vp_ctx_timings", "vp_server_create", "vp_server_destroy", "vp_submit",
            "vp_poll", "vp_wait", "vp_server_stats", "vp_interp_create", "vp_interp_destroy", "vp_interp_locate",
            "vp_interp_eval", "vp_graph_create", "vp_graph_launch", "vp_graph_destroy", "vp_plan_far_config",
@@ -100,6 +100,7 @@ def load(path=LIB_PATH):
         "vp_plan_pairs": [P, P, P, P],
         "vp_plan_rows": [P, P],
         "vp_execute": [P, I64, P, P, ctypes.c_int, ctypes.c_uint32],
+        "vp_execute_noalloc": [P, I64, P, P, ctypes.c_int, ctypes.c_uint32],
         "vp_coefficients": [P, I64, P, P, P, ctypes.c_uint32],
         "vp_plan_sources": [P, P],
         "vp_plan_destroy": [P],
@@ -469,6 +470,16 @@ class Plan:
             out = np.empty((self.n_tgt, R))
         _check(load().vp_execute(self.h, R, _ptr(Fc), _ptr(out), VP_MIXED if mixed else VP_FP64, flags))
         return out[:, 0] if single else out
+
+    def execute_noalloc(self, F, out, far_only=False, asynchronous=False, mixed=False):
+        """vp_execute_noalloc: device tensors F [n_tri, n_p(, R)] and out
+        [n_tgt, R]; the workspace is the library's fixed device array."""
+        if not (_is_device(F) and _is_device(out)):
+            raise VPError(VP_EINVAL, "execute_noalloc() takes device tensors")
+        Fc, R, _ = self._density(F)
+        flags = VP_DEVICE_PTRS | (VP_FAR_ONLY if far_only else 0) | (VP_ASYNC if asynchronous else 0)
+        _check(load().vp_execute_noalloc(self.h, R, _ptr(Fc), _ptr(out), VP_MIXED if mixed else VP_FP64, flags))
+        return out
 
     def coefficients(self, F):
         """(coefficients [n_tri, n_p, R], charges [n_src, R]) as host arrays."""
