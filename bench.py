@@ -1,19 +1,26 @@
-"""Benchmark: potential evaluations per second on one MI355X (FP64 path).
+"""Benchmark: potential evaluations per second on one MI355X.
 
-One step is one pass of the whole hot path for one density on the star
-workload: plan creation (far sources, near-field pair lists from the
-Bernstein-ellipse test, FP64 correction rows) followed by one evaluation
-(coefficients and far charges, the direct far-field sum, the correction
-apply).  Mesh, targets and density are resident in device memory before the
-timed region; the output stays on the device.
+Headline workload: the graded L-shaped domain [-1,1]^2 minus [0,1]^2
+(249 721 triangles, mesh size h ~ r^0.5 toward the re-entrant corner), its
+staggered target mesh's 3 749 550 order-4 nodes as targets, p = 4, a 4 x 4
+collapsed Gauss far rule (3 995 536 far sources), eps = 1e-13, one density,
+FP64.  One step is one pass of the whole hot path: plan creation (far
+sources, near-field pair lists from the Bernstein-ellipse test, FP64
+correction rows) followed by one evaluation (coefficients and far charges,
+the far-field sum, the correction apply).  The headline's far sum is the
+plan option that sums the far rule's point charges by the fast multipole
+method (the paper's own coupling of Sec. 3.6); the tiled direct sum of the
+same step is timed beside it.  Mesh, targets and density are resident in
+device memory before the timed region; the output stays on the device.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--q 8] [--sweep]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-Prints one JSON line (the contract); --sweep first prints one line per far
-order q (the near/far trade-off, Sec. 4.2).  Beside the FP64 headline the
-line carries the mixed-precision path, a batched section (64 densities per
-evaluation, far sum on the matrix cores), the serving run and the oracle's
-own rate on the host.
+Prints one JSON line (the contract) after progress lines.  Beside the
+headline it carries: the same step with the direct far sum and in mixed
+precision, the error of each against the oracle at sampled targets, the
+far-order sweep on the star (Sec. 4.2) and on the 100k-triangle star with
+64 densities, the batched and small-case sections, the serving run, and the
+oracle's own rate on the host's cores.
 """
 
 import argparse
@@ -35,103 +42,347 @@ PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 FLOPS_PER_PAIR = 8  # 2 sub, 1 mul, 1 FMA (r^2), 1 FMA (accumulate), log counted as 1
+# vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64
+# instruction occupies a 16-lane SIMD for 4 cycles)
+PEAK_VALU_LANE_INSTS = 256 * 4 * 16 * 2.4e9
+FMM = {"fmm_terms": 32, "fmm_leaf": 64}
 
 
-def workload(p):
-    from paper_2205_04401_amd import vp
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# workloads (seeded, synthetic; the generators hold none of the method)
+# ---------------------------------------------------------------------------
+
+def l_shape(p=4):
     from paper_2205_04401_amd import workloads as W
-    vq, tq = W.star_mesh(n_tri=20000, n_boundary=2000, seed=20)
-    vt, tt = W.star_mesh(n_tri=20000, n_boundary=2000, seed=21, staggered=True)
-    nodes = vp.ref_nodes(p)
-    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
-    F = W.sample_density(W.gaussian_sum(22, vq, tq), vq, tq, nodes)
+    from paper_2205_04401_amd import vp
+    vq, tq = W.l_shape_graded(n_tri=250000, seed=50)
+    vt, tt = W.l_shape_graded(n_tri=250000, seed=51, staggered=True)
+    tg = W.node_positions(vt, tt, vp.ref_nodes(p)).reshape(-1, 2)
+    F = W.sample_density(W.l_shape_density(52), vq, tq, vp.ref_nodes(p))
     return vq, tq, tg, F
 
 
-def cpu_baseline(vq, tq, tg, F, p, q, eps, n_sample):
-    """The oracle (unchanged) on a seeded sample of targets of the same
-    workload, single-threaded; evals/s = sampled targets / seconds."""
-    from threadpoolctl import threadpool_limits
+def star(n_tri, seeds=(20, 21, 22), p=6):
+    from paper_2205_04401_amd import workloads as W
+    from paper_2205_04401_amd import vp
+    vq, tq = W.star_mesh(n_tri=n_tri, n_boundary=2000, seed=seeds[0])
+    vt, tt = W.star_mesh(n_tri=n_tri, n_boundary=2000, seed=seeds[1], staggered=True)
+    nodes = vp.ref_nodes(p)
+    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    F = W.sample_density(W.gaussian_sum(seeds[2], vq, tq), vq, tq, nodes)
+    return vq, tq, tg, F
 
+
+# ---------------------------------------------------------------------------
+# the oracle on the host's cores (worker processes started before any GPU
+# call; they import no GPU code)
+# ---------------------------------------------------------------------------
+
+def _oracle_chunk(args):
+    """Oracle u at a chunk of targets; returns (u, seconds)."""
+    vq, tq, p, q, eps, F, targets = args
     from oracle import potential
-    rng = np.random.default_rng(7)
-    sample = np.sort(rng.choice(len(tg), n_sample, replace=False))
-    with threadpool_limits(limits=1):
+    t0 = time.perf_counter()
+    u = potential.Oracle(vq, tq, p, q, eps).evaluate(F, targets)
+    return u, time.perf_counter() - t0
+
+
+def cpu_info():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def start_pool(n):
+    import multiprocessing as mp
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    return mp.get_context("spawn").Pool(n)
+
+
+def oracle_at(pool, n_workers, vq, tq, p, q, eps, F, targets):
+    """The oracle at `targets`, split over the pool; (u, wall seconds)."""
+    chunks = np.array_split(np.arange(len(targets)), n_workers)
+    t0 = time.perf_counter()
+    res = pool.map(_oracle_chunk, [(vq, tq, p, q, eps, F, targets[c]) for c in chunks if len(c)])
+    wall = time.perf_counter() - t0
+    return np.concatenate([r[0] for r in res]), wall
+
+
+def rel_err(u, ref):
+    return float(np.abs(u - ref).max() / np.abs(ref).max())
+
+
+# ---------------------------------------------------------------------------
+# rooflines
+# ---------------------------------------------------------------------------
+
+# Algorithmic FP64 flops of one node evaluation in the correction rows:
+# geometry and weight 10, the log counted as 1, then per basis function
+# 3 for the Koornwinder recurrence and 2 to accumulate (k_rows); with the
+# Koornwinder values from a table (k_rows_tab) only the 2 of the
+# contraction, on the matrix cores.
+def rows_flops_per_node(n_p):
+    return 11 + 5 * n_p
+
+
+def tab_flops_per_node(n_p):
+    return 11 + 2 * n_p
+
+
+def stage_rooflines(info, tm, steps, q_near=7, n_l=16):
+    """Every stage of a step against the resource that bounds it (per launch:
+    work over the stage's average device time)."""
+    n_p, n_tgt, n_pairs, T = info["n_p"], info["n_tgt"], info["n_pairs"], info["n_tri"]
+    n_f, nn = info["n_f"], q_near * q_near
+    n_r = 2 * max(4, (info["p"] + 3) // 2)
+    n_self, tab_pairs, tab_leaves = info["n_self"], info["tab_pairs"], info["tab_leaves"]
+    out = {}
+
+    def alu(name, stage, nodes, fpn, kernel):
+        ms, n = tm.get(stage, (0.0, 0))
+        if not n:
+            return
+        sec = ms / 1e3 / n
+        ach = nodes * fpn / sec / 1e12
+        out[name] = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "node_evaluations": nodes, "flops_per_node": fpn,
+                     "avg_launch_ms": sec * 1e3, "kernel": kernel}
+
+    near_deep = n_pairs - n_self - tab_pairs
+    p = info["p"]
+    alu("rows_tab", "rows_tab", tab_pairs * n_f + tab_leaves * nn, tab_flops_per_node(n_p), f"k_rows_tab<{p}>")
+    alu("rows_near", "rows_near", (info["near_subtri"] - tab_leaves) * nn + near_deep * n_f,
+        rows_flops_per_node(n_p), f"k_rows<{p}, false, 1>")
+    alu("rows_self", "rows_self", info["self_panels"] * n_l * n_r + n_self * n_f, rows_flops_per_node(n_p),
+        f"k_rows<{p}, false, 2>")
+    if "rows_tab" not in out and "rows_near" not in out:
+        nodes = info["near_subtri"] * nn + info["self_panels"] * n_l * n_r + n_pairs * n_f
+        alu("rows", "rows", nodes, rows_flops_per_node(n_p), f"k_rows<{p}>")
+    # near lists: targets read in the count and fill passes, CSR and pairs written
+    ms, n = tm.get("classify", (0.0, 0))
+    if n:
+        nbytes = 2 * 16 * n_tgt + 8 * (n_tgt + 1) + 9 * n_pairs
+        sec = ms / 1e3 / n
+        out["near_lists"] = {"bound": "hbm", "achieved": nbytes / sec / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                             "frac": nbytes / sec / 1e9 / PEAK_HBM_GBS, "bytes": nbytes, "avg_ms": sec * 1e3}
+    # correction apply + partial-sum join: far partials, rows, row pointers,
+    # pair triangles, coefficients, output
+    ms, n = tm.get("finish", (0.0, 0))
+    if n:
+        nbytes = 8 * (info["far_split"] * n_tgt + n_pairs * n_p + (n_tgt + 1) + T * n_p + n_tgt) + 4 * n_pairs
+        sec = ms / 1e3 / n
+        out["correction_apply"] = {"bound": "hbm", "achieved": nbytes / sec / 1e9, "peak": PEAK_HBM_GBS,
+                                   "unit": "GB/s", "frac": nbytes / sec / 1e9 / PEAK_HBM_GBS,
+                                   "bytes_per_launch": nbytes, "avg_launch_ms": sec * 1e3,
+                                   "kernel": f"k_finish<{p}> / k_finish_flat<{p}, 16>"}
+    return out
+
+
+def far_roofline(n_src, n_tgt, far_ms, launches, kernel, peak):
+    sec = far_ms / 1e3 / max(launches, 1)
+    pairs = n_src * n_tgt
+    ach = FLOPS_PER_PAIR * pairs / sec / 1e12
+    return {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+            "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs, "avg_launch_ms": sec * 1e3,
+            "pairs_per_s": pairs / sec, "kernel": kernel}
+
+
+def counter_summary(name):
+    """Fields of a committed counter summary under profiles/ (rocprofv3 --pmc
+    runs), or {} when absent."""
+    path = os.path.join(ROOT, "profiles", name)
+    fields = {}
+    if os.path.exists(path):
+        for line in open(path):
+            if ":" in line and not line.startswith(("|", "#", "`")):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    return fields
+
+
+def source_digest(parts):
+    """First 16 hex digits of the SHA-256 of the named source regions:
+    [(file under csrc, first marker, last marker)]: each region runs from the
+    first marker to the end of the function that follows the last."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2205_04401_amd", "csrc")
+    text = ""
+    for fname, a, b in parts:
+        src = open(os.path.join(csrc, fname)).read()
+        i = src.index(a)
+        j = src.index("\n}\n", src.index(b, i)) + 3
+        text += src[i:j]
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
+ROWS_DIGEST_PARTS = [("vp_rows.hip", "__device__ __forceinline__ int dyadic_count", "void k_rows(RowsArgs a)"),
+                     ("vp_rows.hip", "struct TabArgs {", "void k_rows_tab(TabArgs a)")]
+
+
+def traffic_from(summary, digest, kernel_key):
+    f = counter_summary(summary)
+    if f.get("kernel_source_sha256_16") != digest:
+        return None
+    v = f.get(f"{kernel_key}_traffic_bytes_per_launch")
+    return float(v) if v else None
+
+
+# ---------------------------------------------------------------------------
+# sections
+# ---------------------------------------------------------------------------
+
+def timed_steps(ctx, step, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    marks = []
+    for _ in range(steps):
+        info = step()
+        marks.append(time.perf_counter())
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    gaps = np.diff(np.concatenate([[t0], marks])) * 1e3
+    say(f"  {steps} steps: host return times per step (ms) min {gaps.min():.1f} median {np.median(gaps):.1f} "
+        f"max {gaps.max():.1f}")
+    tm = ctx.timings()
+    ctx.profile(False)
+    return dt, info, tm
+
+
+def sweep_star(ctx, qs, steps=1):
+    """Far order q on the star (Sec. 4.2 trade-off): per q the plan + one
+    evaluation with the direct far sum and with the FMM far sum."""
+    import torch
+    p, eps = 6, 1e-13
+    vq, tq, tg, F = star(20000)
+    mesh = ctx.mesh(vq, tq)
+    tg_d = torch.from_numpy(tg).cuda()
+    F_d = torch.from_numpy(F).cuda()
+    out = torch.empty((len(tg), 1), dtype=torch.float64, device="cuda")
+    lines = []
+    for q in qs:
+        for far, opts in (("direct", {}), ("fmm", FMM)):
+            def step():
+                plan = ctx.plan(mesh, p, q, eps, tg_d, **opts)
+                plan.execute(F_d, out=out)
+                info = plan.info()
+                plan.close()
+                return info
+            dt, info, tm = timed_steps(ctx, step, steps, 1)
+            line = {"q": q, "far": far, "ms_per_step": dt * 1e3, "evals_per_s": len(tg) / dt,
+                    "far_ms": tm["far"][0] / steps, "classify_ms": tm["classify"][0] / steps,
+                    "rows_ms": tm["rows"][0] / steps, "finish_ms": tm["finish"][0] / steps,
+                    "n_pairs": info["n_pairs"], "pairs_per_target": info["n_pairs"] / len(tg),
+                    "n_src": info["n_src"]}
+            lines.append(line)
+            say(json.dumps({"sweep_star20k": line}))
+    mesh.close()
+    return {"workload": f"star r=1+0.3cos(5t): {len(tq)} triangles (seed 20), {len(tg)} targets (seed 21), "
+                        f"p={p}, eps={eps}, 1 density; step = plan + evaluation", "lines": lines}
+
+
+def sweep_batched(ctx, qs, R=64):
+    """The 100k-triangle star with 64 densities (seeds 1000..), far sum by
+    the FMM in passes of 16 densities on the FP64 matrix cores, far order
+    q swept: per q the plan and one evaluation of all 64 densities."""
+    import torch
+    from paper_2205_04401_amd import workloads as W
+    from paper_2205_04401_amd import vp
+    p, eps = 6, 1e-13
+    vq, tq = W.star_mesh(n_tri=100000, n_boundary=2000, seed=30)
+    vt, tt = W.star_mesh(n_tri=100000, n_boundary=2000, seed=31, staggered=True)
+    nodes = vp.ref_nodes(p)
+    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    FR = np.ascontiguousarray(np.stack(
+        [W.sample_density(W.gaussian_sum(1000 + r, vq, tq), vq, tq, nodes) for r in range(R)], -1))
+    mesh = ctx.mesh(vq, tq)
+    tg_d = torch.from_numpy(tg).cuda()
+    FR_d = torch.from_numpy(FR).cuda()
+    u = torch.empty((len(tg), R), dtype=torch.float64, device="cuda")
+    lines = []
+    for q in qs:
+        torch.cuda.synchronize()
+        ctx.profile(True)
         t0 = time.perf_counter()
-        o = potential.Oracle(vq, tq, p, q, eps)
-        o.evaluate(F, tg[sample])
-        dt = time.perf_counter() - t0
-    return {"value": n_sample / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_sample} seeded targets of the same star workload (all {len(tq) * q * q} far sources, "
-                      f"their self/near corrections), {dt:.1f} s single-threaded"}
+        plan = ctx.plan(mesh, p, q, eps, tg_d, **FMM)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        plan.execute(FR_d, out=u)  # builds the 16-density tables on first use
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        plan.execute(FR_d, out=u)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        tm = ctx.timings()
+        ctx.profile(False)
+        info = plan.info()
+        plan.close()
+        line = {"q": q, "plan_ms": (t1 - t0) * 1e3, "execute_ms": (t3 - t2) * 1e3,
+                "evals_per_s_execute": len(tg) * R / (t3 - t2), "evals_per_s_with_plan": len(tg) * R / (t3 - t2 + t1 - t0),
+                "rows_ms": tm["rows"][0], "classify_ms": tm["classify"][0], "n_pairs": info["n_pairs"],
+                "pairs_per_target": info["n_pairs"] / len(tg), "n_src": info["n_src"]}
+        lines.append(line)
+        say(json.dumps({"sweep_star100k_64": line}))
+    mesh.close()
+    return {"workload": f"star {len(tq)} triangles (seed 30), {len(tg)} targets (seed 31), p={p}, eps={eps}, "
+                        f"{R} densities (seeds 1000..{1000 + R - 1}), FP64, far sum by the FMM", "lines": lines}
 
 
-def batched(ctx, mesh, tg_d, vq, tq, p, q, R, steps):
-    """Many densities per evaluation: R seeded Gaussian-sum densities (seeds
-    1000...), plan built once, one step = one vp_execute over all R.  The far
-    sum runs in blocks of 64 right-hand sides on the matrix cores (FP64 MFMA,
-    or FP32 MFMA in mixed precision); its roofline counts 2 flops per
-    (pair, RHS) against the MFMA peak of that precision."""
+def batched(ctx, R=64, steps=2):
+    """64 densities per evaluation on the 20k star at q = 8, plan built once,
+    direct far sum on the matrix cores (FP64 MFMA; mixed: FP32 MFMA): the
+    MFMA rooflines of the far sum and of the correction apply."""
     import torch
     from paper_2205_04401_amd import vp
     from paper_2205_04401_amd import workloads as W
+    p, q = 6, 8
+    vq, tq, tg, _ = star(20000)
     nodes = vp.ref_nodes(p)
     FR = np.ascontiguousarray(np.stack(
         [W.sample_density(W.gaussian_sum(1000 + r, vq, tq), vq, tq, nodes) for r in range(R)], -1))
     FR_d = torch.from_numpy(FR).cuda()
+    mesh = ctx.mesh(vq, tq)
+    tg_d = torch.from_numpy(tg).cuda()
     out = []
     for mixed, eps_plan in ((False, 1e-13), (True, 1e-8)):
         plan = ctx.plan(mesh, p, q, eps_plan, tg_d)
         info = plan.info()
         u = torch.empty((info["n_tgt"], R), dtype=torch.float64, device="cuda:0")
         plan.execute(FR_d, out=u, mixed=mixed)
-        torch.cuda.synchronize()
-        ctx.profile(True)
-        t0 = time.perf_counter()
-        for _ in range(steps):
+        def step():
             plan.execute(FR_d, out=u, mixed=mixed)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
-        tm = ctx.timings()
-        ctx.profile(False)
+        dt, _, tm = timed_steps(ctx, step, steps, 0)
+        info = plan.info()
         plan.close()
         far_s = tm["far"][0] / 1e3 / steps
         pair_rhs = info["n_src"] * info["n_tgt"] * R
         peak = PEAK_FP32_MFMA_TFLOPS if mixed else PEAK_FP64_MFMA_TFLOPS
         achieved = 2.0 * pair_rhs / far_s / 1e12
-        out.append({
-            "precision": "mixed" if mixed else "fp64", "plan_eps": eps_plan, "n_rhs": R,
-            "evals_per_s": info["n_tgt"] * R / dt, "ms_per_execute": dt * 1e3,
-            "plan_ms": info["ms_classify"] + info["ms_rows"],
-            "far_pair_rhs_per_s": pair_rhs / far_s,
-            "far_roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                             "frac": achieved / peak, "flops_per_pair_rhs": 2,
-                             "kernel": "k_far_mfma32<4, 4>" if mixed else "k_far_mfma64<4, 4>"},
-            "corr_roofline": corr_mfma_roofline(info, tm, steps, R),
-            "breakdown_ms": {k: v[0] / steps for k, v in tm.items() if v[1]},
-        })
-        print(json.dumps({"batched": out[-1]}), flush=True)
-    # the same densities with the far sum by the FMM (blocks of 16 densities
-    # on the matrix cores), FP64
-    plan = ctx.plan(mesh, p, q, 1e-13, tg_d, fmm_terms=32, fmm_leaf=64)
-    info = plan.info()
-    u = torch.empty((info["n_tgt"], R), dtype=torch.float64, device="cuda:0")
-    plan.execute(FR_d, out=u)
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        plan.execute(FR_d, out=u)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    tm = ctx.timings()
-    ctx.profile(False)
-    plan.close()
-    out.append({"precision": "fp64", "far": "fmm", "fmm_terms": info["fmm_terms"], "fmm_levels": info["fmm_levels"],
-                "plan_eps": 1e-13, "n_rhs": R, "evals_per_s": info["n_tgt"] * R / dt, "ms_per_execute": dt * 1e3,
-                "plan_ms": info["ms_classify"] + info["ms_rows"],
-                "breakdown_ms": {k: v[0] / steps for k, v in tm.items() if v[1]}})
-    print(json.dumps({"batched": out[-1]}), flush=True)
+        line = {"precision": "mixed" if mixed else "fp64", "plan_eps": eps_plan, "n_rhs": R,
+                "evals_per_s": info["n_tgt"] * R / dt, "ms_per_execute": dt * 1e3,
+                "far_pair_rhs_per_s": pair_rhs / far_s,
+                "far_roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                                 "frac": achieved / peak, "flops_per_pair_rhs": 2,
+                                 "kernel": "k_far_mfma32<4, 4>" if mixed else "k_far_mfma64<4, 4>"},
+                "corr_roofline": corr_mfma_roofline(info, tm, steps, R),
+                "breakdown_ms": {k: v[0] / steps for k, v in tm.items() if v[1]}}
+        out.append(line)
+        say(json.dumps({"batched": line}))
+    mesh.close()
     return out
 
 
@@ -141,14 +392,13 @@ def corr_mfma_roofline(info, tm, steps, R):
     peak; `issued_frac` counts the padded 16-target x 4k blocks the MFMA
     steps actually run, `row_fill` the share of those rows that are pairs."""
     sec = tm["finish"][0] / 1e3 / steps
-    n_p, ent = info["n_p"], info["cluster_entries"]
+    n_p, ent = info["n_p"], max(1, info["cluster_entries"])
     useful = 2.0 * info["n_pairs"] * n_p * R
     issued = 2.0 * ent * 16 * 4 * ((n_p + 3) // 4) * R
     ach = useful / sec / 1e12
     return {"bound": "mfma", "achieved": ach, "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
             "frac": ach / PEAK_FP64_MFMA_TFLOPS, "issued_frac": issued / sec / 1e12 / PEAK_FP64_MFMA_TFLOPS,
-            "row_fill": info["n_pairs"] / max(1, 16 * ent), "avg_ms": sec * 1e3,
-            "kernel": f"k_corr_mfma<{info['p']}, 4>"}
+            "row_fill": info["n_pairs"] / (16 * ent), "avg_ms": sec * 1e3, "kernel": f"k_corr_mfma<{info['p']}, 4>"}
 
 
 def small_case(ctx, n=300):
@@ -192,110 +442,8 @@ def small_case(ctx, n=300):
         g.close()
     plan.close()
     mesh.close()
-    print(json.dumps({"small_case": out}), flush=True)
+    say(json.dumps({"small_case": out}))
     return out
-
-
-# Algorithmic FP64 flops of one node evaluation in the correction rows:
-# geometry and weight 10, the log counted as 1, then per basis function
-# 3 for the Koornwinder recurrence and 2 to accumulate (n_p functions).
-def rows_flops_per_node(n_p):
-    return 11 + 5 * n_p
-
-
-def stage_rooflines(info, tm, steps, q_near=7, n_l=16):
-    """Every stage of the step against the resource that bounds it:
-    correction rows (FP64 vector, the node-evaluation convention above),
-    near lists and coefficients/charges (algorithmic HBM bytes)."""
-    n_p, n_tgt, n_pairs, T = info["n_p"], info["n_tgt"], info["n_pairs"], info["n_tri"]
-    n_r = 2 * max(4, (info["p"] + 3) // 2)
-    nodes = (info["near_subtri"] * q_near * q_near + info["self_panels"] * n_l * n_r + n_pairs * info["n_f"])
-    out = {}
-    sec = tm["rows"][0] / 1e3 / steps
-    ach = nodes * rows_flops_per_node(n_p) / sec / 1e12
-    out["k_rows"] = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "node_evaluations": nodes,
-                     "flops_per_node": rows_flops_per_node(n_p), "avg_ms": sec * 1e3}
-    # near lists: targets read in the count and fill passes, CSR and pairs written
-    nbytes = 2 * 16 * n_tgt + 8 * (n_tgt + 1) + 9 * n_pairs
-    sec = tm["classify"][0] / 1e3 / steps
-    out["near_lists"] = {"bound": "hbm", "achieved": nbytes / sec / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                         "frac": nbytes / sec / 1e9 / PEAK_HBM_GBS, "bytes": nbytes, "avg_ms": sec * 1e3}
-    # coefficients and charges, one RHS: F in, C out, C in, Q out
-    nbytes = 8 * (3 * T * n_p + info["n_src"])
-    sec = tm["coef"][0] / 1e3 / steps
-    out["coefficients_charges"] = {"bound": "hbm", "achieved": nbytes / sec / 1e9, "peak": PEAK_HBM_GBS,
-                                   "unit": "GB/s", "frac": nbytes / sec / 1e9 / PEAK_HBM_GBS, "bytes": nbytes,
-                                   "avg_ms": sec * 1e3}
-    return out
-
-
-def finish_roofline(info, tm, steps):
-    """Correction apply + partial-sum join (k_finish), one RHS: algorithmic
-    HBM bytes = far partials (far_split per target) + rows + row pointers +
-    pair triangles + coefficients + output, against the HBM peak."""
-    n_tgt, n_pairs, n_p = info["n_tgt"], info["n_pairs"], info["n_p"]
-    nbytes = 8 * (info["far_split"] * n_tgt + n_pairs * n_p + (n_tgt + 1) + info["n_tri"] * n_p + n_tgt) + 4 * n_pairs
-    sec = tm["finish"][0] / 1e3 / steps
-    achieved = nbytes / sec / 1e9
-    return {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS, "bytes_per_launch": nbytes, "avg_launch_ms": sec * 1e3,
-            "kernel": "k_finish<6>"}
-
-
-def far_kernel_digest():
-    """First 16 hex digits of the SHA-256 of the source text the FP64
-    one-RHS far kernel is built from: FarShape and k_far in vp_exec.hip,
-    and the bias constants and the wide-table logarithm in vp_internal.h."""
-    import hashlib
-    csrc = os.path.join(ROOT, "paper_2205_04401_amd", "csrc")
-    exe = open(os.path.join(csrc, "vp_exec.hip")).read()
-    hdr = open(os.path.join(csrc, "vp_internal.h")).read()
-    a = exe.index("template <int S, int RB>\nstruct FarShape")
-    b = exe.index("\n}\n", exe.index("void k_far(", a)) + 3
-    c = hdr.index("constexpr double kR2Bias")
-    d = hdr.index("\n}\n", hdr.index("void vp_log_wide_parts(", c)) + 3
-    return hashlib.sha256((exe[a:b] + hdr[c:d]).encode()).hexdigest()[:16]
-
-
-def counter_field(q, name):
-    """A figure of the committed counter summary of the far kernel
-    (rocprofv3 --pmc runs on this workload), or None when that summary was
-    taken on another workload or on a different version of the kernel
-    source."""
-    path = os.path.join(ROOT, "profiles", f"k_far_fp64_star20k_q{q}_counters.md")
-    if not os.path.exists(path):
-        return None
-    fields = {}
-    for line in open(path):
-        if ":" in line and not line.startswith(("|", "#", "`")):
-            k, v = line.split(":", 1)
-            fields[k.strip()] = v.strip()
-    if fields.get("kernel_source_sha256_16") != far_kernel_digest() or name not in fields:
-        return None
-    return float(fields[name])
-
-
-def measured_traffic(q):
-    """HBM bytes per far-kernel launch (FETCH_SIZE and WRITE_SIZE, calibrated
-    on a plain copy)."""
-    return counter_field(q, "traffic_bytes_per_launch")
-
-
-# vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64
-# instruction occupies a 16-lane SIMD for 4 cycles)
-PEAK_VALU_LANE_INSTS = 256 * 4 * 16 * 2.4e9
-
-
-def valu_issue(q, pairs_per_s):
-    """The far kernel against the vector issue rate: measured vector
-    instructions per pair (SQ_INSTS_VALU x 64 / pairs) times pairs/s."""
-    ipp = counter_field(q, "valu_instructions_per_pair")
-    if ipp is None:
-        return None
-    achieved = ipp * pairs_per_s
-    return {"instructions_per_pair": ipp, "achieved_lane_insts_per_s": achieved,
-            "peak_lane_insts_per_s": PEAK_VALU_LANE_INSTS, "frac": achieved / PEAK_VALU_LANE_INSTS}
 
 
 def copy_probe(n_bytes=1 << 29, reps=3):
@@ -311,107 +459,52 @@ def copy_probe(n_bytes=1 << 29, reps=3):
     print(json.dumps({"copy_probe_bytes": n_bytes, "reps": reps}), flush=True)
 
 
-def interp_section(ctx, u_d, p, n_pts=1 << 20, reps=5):
-    """The potential anywhere (Sec. 3.5): the evaluation's result at the
-    staggered target mesh's nodes interpolated at n_pts seeded points of the
-    star (radius fraction sqrt(U) of 0.98 r(theta)).  Point location runs
-    once with host arrays (PCIe-inclusive); the evaluation with device
-    arrays is timed over reps calls on the context's stream."""
-    import torch
-    from paper_2205_04401_amd import vp
-    from paper_2205_04401_amd import workloads as W
-    vt, tt = W.star_mesh(n_tri=20000, n_boundary=2000, seed=21, staggered=True)
-    tmesh = ctx.mesh(vt, tt)
-    it = vp.Interp(ctx, tmesh, p)
-    rng = np.random.default_rng(23)
-    th = rng.uniform(0.0, 2.0 * math.pi, n_pts)
-    rad = np.sqrt(rng.uniform(0.0, 1.0, n_pts)) * 0.98 * W.star_radius(th)
-    pts = np.stack([rad * np.cos(th), rad * np.sin(th)], axis=1)
-    t0 = time.perf_counter()
-    tri, ref = it.locate(pts)
-    t_loc = time.perf_counter() - t0
-    found = tri >= 0
-    tri_d = torch.from_numpy(np.ascontiguousarray(tri[found])).cuda()
-    ref_d = torch.from_numpy(np.ascontiguousarray(ref[found])).cuda()
-    n = int(found.sum())
-    u_nodes = u_d.reshape(len(tt), -1, 1).contiguous()
-    res = torch.empty((n, 1), dtype=torch.float64, device=u_d.device)
-    lib = vp.load()
+# ---------------------------------------------------------------------------
+# the run
+# ---------------------------------------------------------------------------
 
-    def ev():
-        vp._check(lib.vp_interp_eval(it.h, 1, vp._ptr(u_nodes), n, vp._ptr(tri_d), vp._ptr(ref_d), vp._ptr(res),
-                                     vp.VP_DEVICE_PTRS))
-    ev()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        ev()
-    torch.cuda.synchronize()
-    t_ev = (time.perf_counter() - t0) / reps
-    it.close()
-    tmesh.close()
-    return {"workload": f"{n_pts} seeded points in the star, u at the {len(tt)}-triangle target mesh's "
-                        f"order-{p} nodes", "located": n, "locate_points_per_s_host_arrays": n_pts / t_loc,
-            "eval_points_per_s": n / t_ev, "eval_ms": t_ev * 1e3}
-
-
-def run(args):
+def run(args, pool, n_workers):
     import torch
     from paper_2205_04401_amd import vp
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     dev = torch.device("cuda:0")
-    p, eps = 6, 1e-13
-    vq, tq, tg, F = workload(p)
-    stream = torch.cuda.current_stream()
-    ctx = vp.Context(0, stream=stream.cuda_stream)
+    t_start = time.perf_counter()
+    p, q, eps = 4, 4, 1e-13
+    say("C5 workload: generating the graded L-shape meshes")
+    vq, tq, tg, F = l_shape(p)
+    n_tgt = len(tg)
+    ctx = vp.Context(0, stream=torch.cuda.current_stream().cuda_stream)
     mesh = ctx.mesh(vq, tq)
     tg_d = torch.from_numpy(tg).to(dev)
     F_d = torch.from_numpy(F).to(dev)
-    out = torch.empty((len(tg), 1), dtype=torch.float64, device=dev)
+    out = torch.empty((n_tgt, 1), dtype=torch.float64, device=dev)
+    rng = np.random.default_rng(7)
+    sample = np.unique(np.concatenate([rng.choice(n_tgt, args.cpu_sample - 8, replace=False),
+                                       np.argsort(np.hypot(tg[:, 0], tg[:, 1]))[:8]]))  # 8 next to the corner
+    sample_d = torch.from_numpy(sample).to(dev)
 
-    def step(q, eps_plan=eps, mixed=False):
-        plan = ctx.plan(mesh, p, q, eps_plan, tg_d)
-        plan.execute(F_d, out=out, mixed=mixed)
-        info = plan.info()
-        plan.close()
-        return info
+    def step_of(eps_plan=eps, mixed=False, **opts):
+        def step():
+            plan = ctx.plan(mesh, p, q, eps_plan, tg_d, **opts)
+            plan.execute(F_d, out=out, mixed=mixed)
+            info = plan.info()
+            plan.close()
+            return info
+        return step
 
-    def measure(q, steps, warmup, eps_plan=eps, mixed=False):
-        for _ in range(warmup):
-            step(q, eps_plan, mixed)
-        torch.cuda.synchronize()
-        ctx.profile(True)
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            info = step(q, eps_plan, mixed)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
-        tm = ctx.timings()
-        ctx.profile(False)
-        return dt, info, tm
-
-    sweep = []
-    if args.sweep:
-        for q in (4, 5, 6, 8, 10, 12, 16):
-            dt, info, tm = measure(q, 2, 1)
-            line = {"q": q, "ms_per_step": dt * 1e3, "evals_per_s": len(tg) / dt,
-                    "far_ms": tm["far"][0] / 2, "rows_ms": tm["rows"][0] / 2, "classify_ms": tm["classify"][0] / 2,
-                    "n_pairs": info["n_pairs"], "pairs_per_target": info["n_pairs"] / len(tg),
-                    "near_subtri": info["near_subtri"], "n_src": info["n_src"]}
-            sweep.append(line)
-            print(json.dumps({"sweep": line}), flush=True)
-
-    q = args.q
-    dt, info, tm = measure(q, args.steps, args.warmup)
-    n_tgt, n_src = info["n_tgt"], info["n_src"]
-    far_ms, far_launches = tm["far"]
-    far_avg_s = far_ms / 1e3 / max(far_launches, 1)
-    pairs = n_src * n_tgt  # one launch covers all pairs for one RHS
-    achieved = FLOPS_PER_PAIR * pairs / far_avg_s / 1e12
-    exec_ms = (tm["coef"][0] + tm["far"][0] + tm["finish"][0]) / args.steps
-    plan_ms = (tm["classify"][0] + tm["rows"][0]) / args.steps
+    # --- headline: FP64, far sum by the FMM ---------------------------------
+    say(f"headline: {args.warmup} warm-up + {args.steps} timed steps")
+    dt, info, tm = timed_steps(ctx, step_of(**FMM), args.steps, args.warmup)
+    u_fmm = out[sample_d, 0].cpu().numpy()
+    stages = stage_rooflines(info, tm, args.steps)
+    timed = {k: v for k, v in stages.items() if "avg_launch_ms" in v}
+    dom_name = max(timed, key=lambda k: timed[k]["avg_launch_ms"])
+    dom = dict(timed[dom_name])
+    digest = source_digest(ROWS_DIGEST_PARTS)
+    dom["traffic"] = traffic_from("k_rows_lshape250k_q4_counters.md", digest, dom_name)
+    dom["stage"] = dom_name
     result = {
         "metric": METRIC,
         "value": n_tgt / dt,
@@ -426,102 +519,92 @@ def run(args):
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"star r=1+0.3cos(5t): {len(tq)} triangles (2000 boundary points, seed 20), staggered "
-                        f"target mesh (seed 21) -> {n_tgt} targets; p={p} ({info['n_p']} nodes/triangle), "
-                        f"q={q} collapsed Gauss ({q * q} nodes/triangle -> {n_src} sources), eps={eps}, "
-                        f"1 density (10-Gaussian sum, seed 22); step = plan (near lists + FP64 rows) + evaluation",
-            "p": p, "q": q, "eps": eps, "n_rhs": 1, "precision": "fp64",
+            "workload": f"graded L-shape [-1,1]^2 minus [0,1]^2, h ~ r^0.5: {len(tq)} triangles (seed 50), "
+                        f"staggered target mesh (seed 51) -> {n_tgt} targets; p={p} ({info['n_p']} nodes/triangle), "
+                        f"q={q} collapsed Gauss ({q * q} nodes/triangle -> {info['n_src']} sources), eps={eps}, "
+                        f"1 density (r^(2/3) sin(2t/3) e^(-r^2) + 10-Gaussian sum, seed 52); "
+                        f"step = plan (near lists + FP64 rows + FMM tree) + evaluation; far sum by the FMM "
+                        f"({FMM['fmm_terms']} terms)",
+            "p": p, "q": q, "eps": eps, "n_rhs": 1, "precision": "fp64", "far": "fmm",
         },
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved,
-            "peak": PEAK_FP64_VECTOR_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_VECTOR_TFLOPS,
-            "traffic": measured_traffic(q),
-            "valu_issue": valu_issue(q, pairs / far_avg_s),
-            "kernel": "k_far (FP64 direct far sum)",
-            "flops_per_pair": FLOPS_PER_PAIR,
-            "pairs_per_launch": pairs,
-            "avg_launch_ms": far_avg_s * 1e3,
-        },
-        "breakdown_ms": {k: v[0] / args.steps for k, v in tm.items()},
-        "execute_ms": exec_ms,
-        "plan_ms": plan_ms,
-        "far_pairs_per_s": pairs / far_avg_s,
+        "roofline": dom,
+        "breakdown_ms": {k: v[0] / args.steps for k, v in tm.items() if v[1]},
+        "plan_ms": (tm["classify"][0] + tm["rows"][0]) / args.steps,
+        "execute_ms": (tm["coef"][0] + tm["far"][0] + tm["finish"][0]) / args.steps,
         "pairs_per_target": info["n_pairs"] / n_tgt,
+        "n_pairs": info["n_pairs"], "n_self": info["n_self"], "tab_pairs": info["tab_pairs"],
         "near_subtri_per_near_pair": info["near_subtri"] / max(1, info["n_pairs"] - info["n_self"]),
         "self_panels_per_self_pair": info["self_panels"] / max(1, info["n_self"]),
-        "correction_apply_roofline": finish_roofline(info, tm, args.steps),
-        "stage_rooflines": stage_rooflines(info, tm, args.steps),
+        "bytes_resident": info["bytes_resident"],
+        "stage_rooflines": stages,
         "rows_pairs_per_s": info["n_pairs"] / (tm["rows"][0] / 1e3 / args.steps),
     }
-    # mixed precision: FP32 far sum, FP64 rows, plan at eps = 1e-8 (its error
-    # is bounded by 1e-6 against the FP64 eps = 1e-13 oracle in the GPU tests)
-    dt_m, info_m, tm_m = measure(q, args.steps, 1, eps_plan=1e-8, mixed=True)
-    far_m = tm_m["far"][0] / 1e3 / max(tm_m["far"][1], 1)
-    result["mixed"] = {
-        "value": n_tgt / dt_m, "unit": "evals/s", "ms_per_step": dt_m * 1e3, "rel_err_bound": 1e-6,
-        "plan_eps": 1e-8, "far_pairs_per_s": pairs / far_m, "pairs_per_target": info_m["n_pairs"] / n_tgt,
-        "breakdown_ms": {k: v[0] / args.steps for k, v in tm_m.items()},
-        "far_fp32_tflops_8flop": FLOPS_PER_PAIR * pairs / far_m / 1e12,
-    }
-    if sweep:
-        result["q_sweep"] = sweep
-    if args.ablation:
-        from paper_2205_04401_amd import ablation
-        res = ablation.run(ctx)
-        print(ablation.table(res), file=sys.stderr, flush=True)
-        result["ablation"] = {k: v for k, v in res.items() if k not in ("problem", "sample_same", "sample_stag")}
-    if not args.no_fmm:
-        # the same step with the far sum by the FMM (plan option), at the
-        # size rule's q and at q = 16 (smaller near field, cheaper rows)
-        step(q)  # the FP64 direct-sum result to compare against
-        u_direct = out.clone()
-        result["fmm"] = []
-        for qf in sorted({q, 16}):
-            def step_fmm():
-                plan = ctx.plan(mesh, p, qf, eps, tg_d, fmm_terms=args.fmm_terms, fmm_leaf=64)
-                plan.execute(F_d, out=out)
-                info = plan.info()
-                plan.close()
-                return info
-            step_fmm()
-            torch.cuda.synchronize()
-            ctx.profile(True)
-            t0 = time.perf_counter()
-            for _ in range(args.steps):
-                info_f = step_fmm()
-            torch.cuda.synchronize()
-            dt_f = (time.perf_counter() - t0) / args.steps
-            tm_f = ctx.timings()
-            ctx.profile(False)
-            line = {"q": qf, "fmm_terms": info_f["fmm_terms"], "fmm_levels": info_f["fmm_levels"],
-                    "value": n_tgt / dt_f, "unit": "evals/s", "ms_per_step": dt_f * 1e3,
-                    "far_ms": tm_f["far"][0] / args.steps, "rows_ms": tm_f["rows"][0] / args.steps,
-                    "pairs_per_target": info_f["n_pairs"] / n_tgt,
-                    "fmm_near_pairs": info_f["fmm_near_pairs"], "fmm_m2l_pairs": info_f["fmm_m2l_pairs"],
-                    "breakdown_ms": {k: v[0] / args.steps for k, v in tm_f.items()}}
-            if qf == q:
-                line["rel_diff_vs_direct"] = float((out - u_direct).abs().max() / u_direct.abs().max())
-            result["fmm"].append(line)
-            print(json.dumps({"fmm": line}), flush=True)
-    if not args.no_interp:
-        step(q)  # u at the targets (the target mesh's nodes) into out
-        result["interp"] = interp_section(ctx, out, p)
-        print(json.dumps({"interp": result["interp"]}), flush=True)
+    say(json.dumps({"headline": {k: result[k] for k in ("value", "ms_per_step", "breakdown_ms")}}))
+
+    if args.headline_only:
+        print(json.dumps(result), flush=True)
+        return
+    # --- the same step with the direct far sum (FP64) -------------------------
+    dt_d, info_d, tm_d = timed_steps(ctx, step_of(), args.direct_steps, 1)
+    u_dir = out[sample_d, 0].cpu().numpy()
+    far_d = far_roofline(info_d["n_src"], n_tgt, tm_d["far"][0], tm_d["far"][1], "k_far<1, WIDE> (FP64)",
+                         PEAK_FP64_VECTOR_TFLOPS)
+    ipp = counter_summary("k_far_fp64_star20k_q8_counters.md").get("valu_instructions_per_pair")
+    if ipp:
+        far_d["valu_issue"] = {"instructions_per_pair_star20k_q8": float(ipp),
+                               "frac": float(ipp) * far_d["pairs_per_s"] / PEAK_VALU_LANE_INSTS}
+    result["direct"] = {"value": n_tgt / dt_d, "unit": "evals/s", "ms_per_step": dt_d * 1e3, "steps": args.direct_steps,
+                        "far_roofline": far_d,
+                        "breakdown_ms": {k: v[0] / args.direct_steps for k, v in tm_d.items() if v[1]}}
+    say(json.dumps({"direct": result["direct"]}))
+
+    # --- mixed precision: FP32 direct far sum, FP64 rows at eps = 1e-8 --------
+    dt_m, info_m, tm_m = timed_steps(ctx, step_of(1e-8, True), args.mixed_steps, 1)
+    u_mix = out[sample_d, 0].cpu().numpy()
+    far_m = far_roofline(info_m["n_src"], n_tgt, tm_m["far"][0], tm_m["far"][1], "k_far32 (FP32)", 157.3)
+    result["mixed"] = {"value": n_tgt / dt_m, "unit": "evals/s", "ms_per_step": dt_m * 1e3, "steps": args.mixed_steps,
+                       "plan_eps": 1e-8, "pairs_per_target": info_m["n_pairs"] / n_tgt, "far_roofline": far_m,
+                       "breakdown_ms": {k: v[0] / args.mixed_steps for k, v in tm_m.items() if v[1]}}
+    say(json.dumps({"mixed": result["mixed"]}))
+    mesh.close()
+
+    # --- secondary sections ---------------------------------------------------
+    if not args.no_sweep:
+        result["sweep"] = {"star20k": sweep_star(ctx, (4, 5, 6, 8, 10, 12, 16)),
+                           "star100k_64rhs": sweep_batched(ctx, (8, 10, 12, 14, 16, 18, 20))}
+    if not args.no_batched:
+        result["batched"] = batched(ctx)
     if not args.no_small:
         result["small_case"] = small_case(ctx)
-    if args.batched_rhs:
-        result["batched"] = batched(ctx, mesh, tg_d, vq, tq, p, q, args.batched_rhs, args.batched_steps)
     if not args.no_serving:
         from paper_2205_04401_amd import serving
         result["serving"] = [serving.run(ctx, n_requests=args.serving_requests, mixed=m) for m in (False, True)]
         result["serving"].append(serving.run(ctx, n_requests=args.serving_requests, mixed=False, fmm_terms=32))
-    if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(vq, tq, tg, F, p, q, eps, args.cpu_sample)
-    mesh.close()
+        for s in result["serving"]:
+            say(json.dumps({"serving": s}))
     ctx.close()
+    result["gpu_sections_s"] = time.perf_counter() - t_start
+
+    # --- the oracle on the host, and the error of every line against it ------
+    if pool is not None:
+        say(f"oracle on {len(sample)} sampled targets ({n_workers} processes)")
+        ref, wall = oracle_at(pool, n_workers, vq, tq, p, q, eps, F, tg[sample])
+        model, ncpu = cpu_info()
+        one = min(len(sample), args.cpu_single)
+        ref1, wall1 = oracle_at(pool, 1, vq, tq, p, q, eps, F, tg[sample[:one]])
+        result["cpu_baseline"] = {
+            "value": len(sample) / wall, "unit": "evals/s", "cores": n_workers, "kind": "oracle",
+            "sample": f"{len(sample)} seeded targets of the same workload (8 next to the re-entrant corner; all "
+                      f"{info['n_src']} far sources and the targets' self/near corrections), {wall:.1f} s on "
+                      f"{n_workers} worker processes of one thread each",
+            "single_core": {"value": one / wall1, "unit": "evals/s", "targets": one, "seconds": wall1},
+            "cpu_model": model, "nproc": ncpu,
+        }
+        result["accuracy"] = {
+            "reference": f"oracle (FP64, eps = {eps}) at the {len(sample)} cpu_baseline targets; relative L-inf",
+            "fp64_fmm": rel_err(u_fmm, ref), "fp64_direct": rel_err(u_dir, ref), "mixed": rel_err(u_mix, ref),
+            "bars": {"fp64": 1e-11, "mixed": 1e-6}}
+        say(json.dumps({"cpu_baseline": result["cpu_baseline"], "accuracy": result["accuracy"]}))
     print(json.dumps(result), flush=True)
 
 
@@ -530,20 +613,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--q", type=int, default=8)
-    ap.add_argument("--sweep", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=600)
+    ap.add_argument("--direct-steps", type=int, default=2, help="timed steps of the direct-far-sum line")
+    ap.add_argument("--mixed-steps", type=int, default=2, help="timed steps of the mixed-precision line")
+    ap.add_argument("--cpu-sample", type=int, default=256, help="targets of the oracle timing and error checks")
+    ap.add_argument("--cpu-single", type=int, default=24, help="of them, timed on one core")
+    ap.add_argument("--cpu-workers", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--headline-only", action="store_true", help="only the headline step (no other sections)")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-small", action="store_true", help="skip the unit-square latency section")
-    ap.add_argument("--no-fmm", action="store_true", help="skip the FMM far-sum section")
-    ap.add_argument("--no-interp", action="store_true", help="skip the interpolation section")
-    ap.add_argument("--fmm-terms", type=int, default=32)
     ap.add_argument("--serving-requests", type=int, default=160)
-    ap.add_argument("--batched-rhs", type=int, default=64, help="densities of the batched section (0: skip)")
-    ap.add_argument("--batched-steps", type=int, default=2)
-    ap.add_argument("--ablation", action="store_true",
-                    help="ellipse vs naive-ball near field, staggered vs same-mesh targets (star, 5k triangles)")
     ap.add_argument("--copy-probe", action="store_true", help="only run a 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -555,7 +636,17 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
-    run(args)
+    # the oracle's worker processes start before anything touches the GPU
+    pool, n_workers = None, 0
+    if not args.no_cpu_baseline:
+        n_workers = max(1, min(args.cpu_workers, os.cpu_count() or 1))
+        pool = start_pool(n_workers)
+    try:
+        run(args, pool, n_workers)
+    finally:
+        if pool is not None:
+            pool.close()
+            pool.join()
 
 
 if __name__ == "__main__":

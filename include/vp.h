@@ -137,12 +137,20 @@ typedef struct {
   int32_t fmm_levels;      /* quadtree levels below the root (leaf level) */
   int64_t fmm_near_pairs;  /* target-source pairs the FMM sums directly (adjacent leaf boxes) */
   int64_t fmm_m2l_pairs;   /* (target box, source box) M2L translations over all levels */
+  int64_t tab_pairs;       /* near pairs whose subdivision stops at the triangle or after one split
+                              (their rows by fixed Koornwinder tables on the matrix cores) */
+  int64_t tab_leaves;      /* their near-rule leaves (one or four per pair), part of near_subtri */
 } vp_plan_stats;
 
 /* Context on HIP device `device`.  `hip_stream_or_null` is a hipStream_t the
  * context issues all work on (NULL: the device's null stream).
- * `hbm_budget_bytes` caps the device memory its meshes and plans may hold
- * (0: no cap).  *out receives the context. */
+ * `hbm_budget_bytes` caps the device memory its meshes, plans, plan
+ * workspaces, server slots, captured evaluations and interpolation objects
+ * may hold, together with the blocks its cache keeps (0: no cap).  The
+ * cache keeps the blocks of destroyed plans and outgrown workspaces for
+ * later plans, up to a quarter of the device's memory; vp_ctx_trim empties
+ * it.  *out receives the context.  vp_ctx_destroy returns VP_EBUSY while
+ * meshes or servers of the context are alive. */
 vp_status vp_ctx_create(int device, void* hip_stream_or_null, uint64_t hbm_budget_bytes, vp_ctx** out);
 vp_status vp_ctx_destroy(vp_ctx* ctx);
 
@@ -274,18 +282,23 @@ vp_status vp_coefficients(vp_plan* plan, int64_t n_rhs, const double* density, d
 vp_status vp_plan_sources(const vp_plan* plan, double* xy_out);
 
 /* Destroys the plan.  Waits for all work queued on the device (as hipFree
- * does) and hands the plan's device blocks to its context, which keeps up to
- * 16 GiB of them (and, with an HBM budget, no more than the budget leaves
- * free) for later plans of similar sizes: a plan that is built and destroyed
- * every step then neither allocates nor frees device memory after the first.
- * Blocks beyond that limit are freed.  The context frees its cached blocks
- * when an allocation finds the device out of memory, on vp_ctx_trim and on
- * vp_ctx_destroy. */
+ * does) and hands the plan's device blocks to its context, which keeps them
+ * up to a quarter of the device's memory (and, with an HBM budget, within
+ * the budget together with everything the context holds) for later plans
+ * of similar sizes: a plan that is built and destroyed every step then
+ * neither allocates nor frees device memory after the first.  Blocks beyond
+ * that limit are freed.  The context frees its cached blocks when an
+ * allocation finds the device out of memory or the budget full, on
+ * vp_ctx_trim and on vp_ctx_destroy. */
 vp_status vp_plan_destroy(vp_plan* plan);
 
 /* Device bytes the context holds in cached blocks of destroyed plans
  * (*bytes_out), and vp_ctx_trim: free all of them now. */
 vp_status vp_ctx_cached_bytes(const vp_ctx* ctx, uint64_t* bytes_out);
+/* Device bytes the context holds: in use (meshes, plans, workspaces, server
+ * slots, captured evaluations, interpolation objects, FMM operators) and in
+ * its cache.  With an HBM budget their sum stays within it. */
+vp_status vp_ctx_memory(const vp_ctx* ctx, uint64_t* in_use_out, uint64_t* cached_out);
 vp_status vp_ctx_trim(vp_ctx* ctx);
 
 /* Wait for all work issued on the context's stream. */
@@ -303,7 +316,11 @@ typedef enum {
   VP_STAGE_COEF = 2,     /* coefficients and far charges (Sec. 2.2, 3.6) */
   VP_STAGE_FAR = 3,      /* far-field direct sum: one launch per RHS block */
   VP_STAGE_FINISH = 4,   /* partial sums + corrections */
-  VP_N_STAGES = 5
+  VP_STAGE_ROWS_TAB = 5,  /* part of VP_STAGE_ROWS: near pairs whose subdivision stops at the triangle
+                             or after one split, on the matrix cores */
+  VP_STAGE_ROWS_NEAR = 6, /* part of VP_STAGE_ROWS: the other near pairs */
+  VP_STAGE_ROWS_SELF = 7, /* part of VP_STAGE_ROWS: self pairs */
+  VP_N_STAGES = 8
 } vp_stage;
 vp_status vp_ctx_profile(vp_ctx* ctx, int on);
 vp_status vp_ctx_timings(vp_ctx* ctx, double* ms_out /* [VP_N_STAGES] */, int64_t* launches_out /* [VP_N_STAGES] */);
@@ -322,10 +339,18 @@ vp_status vp_ctx_timings(vp_ctx* ctx, double* ms_out /* [VP_N_STAGES] */, int64_
  * Progress (completion checks and admission) happens inside vp_submit,
  * vp_poll and vp_wait.  density [n_tri][n_p][n_rhs] and u_out [n_tgt][n_rhs]
  * are DEVICE pointers owned by the caller and must stay valid until the
- * request is done.  A request's result equals vp_execute of the same
- * arguments up to rounding (the far sum of a column does not depend on the
- * other columns of its batch).  Errors: VP_EINVAL (bad arguments),
- * VP_ENOMEM (a request larger than the whole budget), VP_EDEVICE.
+ * request is done; the density must be complete on the context's stream
+ * when vp_submit is called (vp_submit records an event there that the slot
+ * waits for; work on other streams must be ordered before it by the
+ * caller).  A slot's workspace comes from the context's block cache: when a
+ * batch does not fit the budget, the idle slots' workspaces go back to the
+ * cache first; the batch then waits for a running one to retire, and fails
+ * with VP_ENOMEM only when nothing is running and it still does not fit.
+ * A request's result equals vp_execute of the same arguments up to rounding
+ * (the far sum of a column does not depend on the other columns of its
+ * batch).  Errors: VP_EINVAL (bad arguments), VP_ENOMEM (a request larger
+ * than the whole budget), VP_EDEVICE.  A server keeps its context alive
+ * (vp_ctx_destroy returns VP_EBUSY until vp_server_destroy).
  * ------------------------------------------------------------------------ */
 typedef struct vp_server vp_server;
 typedef int64_t vp_ticket;
@@ -337,6 +362,9 @@ vp_status vp_poll(vp_server* srv, vp_ticket ticket, int* done_out);
 vp_status vp_wait(vp_server* srv, vp_ticket ticket);
 /* Counters: requests completed, batches launched, RHS columns launched. */
 vp_status vp_server_stats(const vp_server* srv, int64_t* requests_done, int64_t* batches, int64_t* columns);
+/* Admission counters: times a batch waited for a running one to free memory
+ * under the context's budget, and requests failed with VP_ENOMEM. */
+vp_status vp_server_admission(const vp_server* srv, int64_t* budget_waits, int64_t* rejected);
 
 /* A captured evaluation (HIP graph) for repeated solves with new density
  * values in the same device buffer: the launches of vp_execute (FP64 or

@@ -12,6 +12,8 @@
 
 #include "vp_internal.h"
 
+using vp::StageTimer;
+
 namespace {
 
 thread_local std::string g_err;
@@ -64,6 +66,7 @@ void release_workspace(vp_plan* pl) {
     if (p) vp::ctx_release(pl->ctx, p);
   pl->ws_f = pl->ws_c = pl->ws_q = pl->ws_part = pl->ws_u = nullptr;
   pl->ws_q32 = nullptr;
+  pl->ws_bytes = 0;
 }
 
 void free_plan_memory(vp_plan* pl) {
@@ -97,29 +100,6 @@ hipError_t upload(vp_plan* pl, T** dst, const T* src, size_t n, hipStream_t st) 
 
 // Stage bracket: records an event pair on the context's stream when
 // profiling is on.
-struct StageTimer {
-  vp_ctx* ctx;
-  int stage;
-  hipEvent_t a = nullptr, b = nullptr;
-  StageTimer(vp_ctx* c, int s) : ctx(c), stage(s) {
-    if (!ctx->profile) return;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
-      ctx->profile = false;
-      return;
-    }
-    (void)hipEventRecord(a, ctx->stream);
-  }
-  void stop(int64_t launches) {
-    if (!a || !ctx->profile) return;
-    (void)hipEventRecord(b, ctx->stream);
-    ctx->pending.push_back({stage, a, b, launches});
-    a = b = nullptr;
-  }
-  ~StageTimer() {
-    if (a) (void)hipEventDestroy(a);
-    if (b) (void)hipEventDestroy(b);
-  }
-};
 
 void fold_timings(vp_ctx* ctx) {
   for (auto& p : ctx->pending) {
@@ -172,7 +152,10 @@ vp_status vp_ctx_create(int device, void* stream, uint64_t budget, vp_ctx** out)
   if (device < 0 || device >= n) return fail(VP_EINVAL, "vp_ctx_create: device %d of %d", device, n);
   VP_HIP(hipSetDevice(device), "hipSetDevice");
   VP_HIP(vp::noalloc_setup(device), "vp_ctx_create: address of the allocation-free workspace");
+  size_t dev_free = 0, dev_total = 0;
+  VP_HIP(hipMemGetInfo(&dev_free, &dev_total), "vp_ctx_create: hipMemGetInfo");
   vp_ctx* c = new vp_ctx;
+  c->cache_cap = dev_total / 4;
   c->device = device;
   c->stream = (hipStream_t)stream;
   c->budget = budget;
@@ -183,6 +166,7 @@ vp_status vp_ctx_create(int device, void* stream, uint64_t budget, vp_ctx** out)
 vp_status vp_ctx_destroy(vp_ctx* ctx) {
   if (!ctx) return VP_OK;
   if (ctx->live_meshes) return fail(VP_EBUSY, "vp_ctx_destroy: %d meshes still alive", ctx->live_meshes);
+  if (ctx->live_servers) return fail(VP_EBUSY, "vp_ctx_destroy: %d servers still alive", ctx->live_servers);
   (void)hipSetDevice(ctx->device);
   fold_timings(ctx);
   for (auto& kv : ctx->fmm_ops)
@@ -196,6 +180,13 @@ vp_status vp_ctx_destroy(vp_ctx* ctx) {
 vp_status vp_ctx_cached_bytes(const vp_ctx* ctx, uint64_t* bytes_out) {
   if (!ctx || !bytes_out) return fail(VP_EINVAL, "vp_ctx_cached_bytes: NULL argument");
   *bytes_out = ctx->cached;
+  return VP_OK;
+}
+
+vp_status vp_ctx_memory(const vp_ctx* ctx, uint64_t* in_use_out, uint64_t* cached_out) {
+  if (!ctx) return fail(VP_EINVAL, "vp_ctx_memory: ctx is NULL");
+  if (in_use_out) *in_use_out = ctx->in_use;
+  if (cached_out) *cached_out = ctx->cached;
   return VP_OK;
 }
 
@@ -274,8 +265,7 @@ vp_status vp_mesh_create(vp_ctx* ctx, int64_t n_vert, const double* vert, int64_
   if (n_tri > 0 && (!vert || !tri)) return fail(VP_EINVAL, "vp_mesh_create: NULL arrays");
   VP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   const size_t bytes = 7 * sizeof(double) * std::max<int64_t>(n_tri, 1);
-  if (ctx->budget && ctx->in_use + bytes > ctx->budget)
-    return fail(VP_ENOMEM, "vp_mesh_create: %zu bytes exceed the HBM budget", bytes);
+  if (!vp::ctx_fits(ctx, bytes)) return fail(VP_ENOMEM, "vp_mesh_create: %zu bytes exceed the HBM budget", bytes);
   vp_mesh* m = new vp_mesh;
   m->ctx = ctx;
   m->n_tri = n_tri;
@@ -483,7 +473,7 @@ vp_status vp_mesh_set_curved_sides(vp_mesh* m, int64_t n, const int32_t* tri, co
     ctri[i] = t;
   }
   const size_t bytes = sizeof(int32_t) * (T + n) + sizeof(double) * (coef.size() + box.size());
-  if (m->ctx->budget && m->ctx->in_use + bytes > m->ctx->budget)
+  if (!vp::ctx_fits(m->ctx, bytes))
     return fail(VP_ENOMEM, "vp_mesh_set_curved_sides: %zu bytes exceed the HBM budget", bytes);
   hipError_t e;
   if ((e = hipMalloc((void**)&m->curve_of, sizeof(int32_t) * T)) != hipSuccess ||
@@ -698,7 +688,6 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
       if (!err.empty()) return fail(VP_ENOMEM, "vp_plan_create: %s", err.c_str());
       return hip_fail(e, "vp_plan_create: near-field list");
     }
-    if ((e = vp::build_clusters(pl, st)) != hipSuccess) return hip_fail(e, "vp_plan_create: target clusters");
     if (o.fmm_terms > 0 && pl->n_src > 0 && pl->n_tgt > 0) {
       pl->fmm_terms = o.fmm_terms;
       if ((e = vp::build_fmm(pl, o.fmm_leaf, st)) != hipSuccess) return hip_fail(e, "vp_plan_create: FMM tree");
@@ -741,9 +730,6 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
   (void)hipEventElapsedTime(&ms2, ev1, ev2);
   pl->ms_classify = ms1;
   pl->ms_rows = ms2;
-  if (ctx->budget && ctx->in_use + pl->bytes > ctx->budget)
-    return fail(VP_ENOMEM, "vp_plan_create: %zu bytes exceed the HBM budget", pl->bytes);
-  ctx->in_use += pl->bytes;
   const_cast<vp_mesh*>(mesh)->live_plans++;
   guard.keep = true;
   *out = pl;
@@ -775,6 +761,8 @@ vp_status vp_plan_info(const vp_plan* pl, vp_plan_stats* out) {
   out->fmm_levels = pl->fmm_levels;
   out->fmm_near_pairs = pl->fmm_near_pairs;
   out->fmm_m2l_pairs = pl->fmm_m2l_pairs;
+  out->tab_pairs = pl->tab_pairs;
+  out->tab_leaves = pl->tab_leaves;
   return VP_OK;
 }
 
@@ -880,7 +868,6 @@ vp_status ensure_workspace(vp_plan* pl, int64_t R, int64_t split) {
   if (pl->ws_rhs >= R && pl->ws_split >= split && pl->ws_c) return VP_OK;
   R = std::max(R, pl->ws_rhs);
   split = std::max(split, pl->ws_split);
-  pl->ctx->in_use -= pl->ws_bytes;
   release_workspace(pl);
   pl->ws_bytes = 0;
   pl->ws_rhs = 0;
@@ -889,23 +876,24 @@ vp_status ensure_workspace(vp_plan* pl, int64_t R, int64_t split) {
   const size_t nP = (size_t)vp::far_partial_doubles(pl, split, R);
   const size_t nU = (size_t)pl->n_tgt * R;
   const size_t bytes = 8 * (2 * nF + nQ + nP + nU) + 4 * nQ + 6 * 8;
-  if (pl->ctx->budget && pl->ctx->in_use + bytes > pl->ctx->budget)
-    return fail(VP_ENOMEM, "vp_execute: workspace of %zu bytes exceeds the HBM budget", bytes);
   hipError_t e;
   vp_ctx* c = pl->ctx;
-  if ((e = vp::ctx_alloc(c, (void**)&pl->ws_f, 8 * std::max<size_t>(nF, 1))) != hipSuccess ||
-      (e = vp::ctx_alloc(c, (void**)&pl->ws_c, 8 * std::max<size_t>(nF, 1))) != hipSuccess ||
-      (e = vp::ctx_alloc(c, (void**)&pl->ws_q, 8 * std::max<size_t>(nQ, 1))) != hipSuccess ||
-      (e = vp::ctx_alloc(c, (void**)&pl->ws_part, 8 * std::max<size_t>(nP, 1))) != hipSuccess ||
-      (e = vp::ctx_alloc(c, (void**)&pl->ws_u, 8 * std::max<size_t>(nU, 1))) != hipSuccess ||
-      (e = vp::ctx_alloc(c, (void**)&pl->ws_q32, 4 * std::max<size_t>(nQ, 1))) != hipSuccess ||
+  size_t got[6] = {0, 0, 0, 0, 0, 0};
+  if ((e = vp::ctx_alloc(c, (void**)&pl->ws_f, 8 * std::max<size_t>(nF, 1), &got[0])) != hipSuccess ||
+      (e = vp::ctx_alloc(c, (void**)&pl->ws_c, 8 * std::max<size_t>(nF, 1), &got[1])) != hipSuccess ||
+      (e = vp::ctx_alloc(c, (void**)&pl->ws_q, 8 * std::max<size_t>(nQ, 1), &got[2])) != hipSuccess ||
+      (e = vp::ctx_alloc(c, (void**)&pl->ws_part, 8 * std::max<size_t>(nP, 1), &got[3])) != hipSuccess ||
+      (e = vp::ctx_alloc(c, (void**)&pl->ws_u, 8 * std::max<size_t>(nU, 1), &got[4])) != hipSuccess ||
+      (e = vp::ctx_alloc(c, (void**)&pl->ws_q32, 4 * std::max<size_t>(nQ, 1), &got[5])) != hipSuccess ||
       (e = hipMemsetAsync(pl->ws_q, 0, 8 * std::max<size_t>(nQ, 1), pl->ctx->stream)) != hipSuccess) {
+    release_workspace(pl);
+    if (e == hipErrorOutOfMemory)
+      return fail(VP_ENOMEM, "vp_execute: workspace of %zu bytes exceeds the device memory or the HBM budget", bytes);
     return hip_fail(e, "vp_execute: workspace");
   }
   pl->ws_rhs = R;
   pl->ws_split = split;
-  pl->ws_bytes = bytes;
-  pl->ctx->in_use += bytes;
+  pl->ws_bytes = got[0] + got[1] + got[2] + got[3] + got[4] + got[5];
   return VP_OK;
 }
 
@@ -913,7 +901,13 @@ vp_status ensure_workspace(vp_plan* pl, int64_t R, int64_t split) {
 
 namespace vp {
 
-hipError_t ctx_alloc(vp_ctx* ctx, void** p, size_t bytes) {
+bool ctx_fits(vp_ctx* ctx, uint64_t bytes) {
+  if (!ctx->budget) return true;
+  if (ctx->in_use + ctx->cached + bytes > ctx->budget) ctx_trim(ctx);
+  return ctx->in_use + bytes <= ctx->budget;
+}
+
+hipError_t ctx_alloc(vp_ctx* ctx, void** p, size_t bytes, size_t* got) {
   *p = nullptr;
   // sizes rounded so that blocks of nearly equal requests are interchangeable
   const size_t g = bytes >= (size_t(1) << 20) ? (size_t(2) << 20) : 256;
@@ -922,10 +916,12 @@ hipError_t ctx_alloc(vp_ctx* ctx, void** p, size_t bytes) {
   if (it != ctx->cache.end() && it->first - r <= r / 4) {
     *p = it->second;
     ctx->cached -= it->first;
+    ctx->in_use += it->first;
+    if (got) *got = it->first;
     ctx->cache.erase(it);
     return hipSuccess;
   }
-  if (ctx->budget && ctx->in_use + ctx->cached + r > ctx->budget) ctx_trim(ctx);
+  if (!ctx_fits(ctx, r)) return hipErrorOutOfMemory;
   hipError_t e = hipMalloc(p, r);
   if (e == hipErrorOutOfMemory && !ctx->cache.empty()) {
     (void)hipGetLastError();  // the failed attempt's error, not a later launch's
@@ -937,6 +933,8 @@ hipError_t ctx_alloc(vp_ctx* ctx, void** p, size_t bytes) {
     return e;
   }
   ctx->block_size[*p] = r;
+  ctx->in_use += r;
+  if (got) *got = r;
   return hipSuccess;
 }
 
@@ -948,9 +946,9 @@ void ctx_release(vp_ctx* ctx, void* p) {
     return;
   }
   const size_t r = it->second;
-  const bool fits = ctx->cached + r <= kCacheMaxBytes &&
-                    (!ctx->budget || ctx->in_use + ctx->cached + r <= ctx->budget);
-  if (!fits) {
+  ctx->in_use -= r;
+  // (with a budget, in_use + cached stays within it: the block was counted)
+  if (ctx->cached + r > ctx->cache_cap) {
     ctx->block_size.erase(it);
     (void)hipFree(p);
     return;
@@ -969,11 +967,11 @@ void ctx_trim(vp_ctx* ctx) {
 }
 
 hipError_t plan_alloc(vp_plan* pl, void** dst, size_t bytes) {
-  bytes = std::max<size_t>(bytes, 8);
-  hipError_t e = ctx_alloc(pl->ctx, dst, bytes);
+  size_t got = 0;
+  hipError_t e = ctx_alloc(pl->ctx, dst, std::max<size_t>(bytes, 8), &got);
   if (e != hipSuccess) return e;
   pl->allocs.push_back(*dst);
-  pl->bytes += bytes;
+  pl->bytes += got;
   return e;
 }
 
@@ -994,7 +992,7 @@ vp_status vp_execute(vp_plan* pl, int64_t R, const double* density, double* u_ou
   vp_status s = ensure_workspace(pl, R, cfg.n_split);
   if (s != VP_OK) return s;
   hipStream_t st = pl->ctx->stream;
-  VP_HIP(vp::fmm_prepare_blocks(pl, R, st), "vp_execute: FMM tables");
+  VP_HIP(vp::prepare_blocks(pl, R, st), "vp_execute: tables for blocks of 16 densities");
   const size_t nF = (size_t)pl->n_tri * pl->n_p * R;
   const double* F = density;
   if (!dev && nF) {
@@ -1081,29 +1079,30 @@ vp_status vp_graph_create(vp_plan* pl, int64_t R, const double* density, double*
   const int64_t split = cfg.n_split;
   const size_t nC = (size_t)pl->n_tri * pl->n_p * R, nQ = (size_t)pl->n_src_pad * R,
                nP = (size_t)vp::far_partial_doubles(pl, split, R);
-  g->bytes = 8 * (nC + nQ + nP) + (prec == VP_MIXED ? 4 * nQ : 0);
+  vp_ctx* ctx = pl->ctx;
   auto drop = [&](vp_graph* x) {
     if (x->exec) (void)hipGraphExecDestroy(x->exec);
     if (x->graph) (void)hipGraphDestroy(x->graph);
     if (x->cap) (void)hipStreamDestroy(x->cap);
     for (void* p : {(void*)x->c, (void*)x->q, (void*)x->part, (void*)x->q32})
-      if (p) (void)hipFree(p);
+      if (p) vp::ctx_release(ctx, p);
     delete x;
   };
-  if (pl->ctx->budget && pl->ctx->in_use + g->bytes > pl->ctx->budget) {
-    drop(g);
-    return fail(VP_ENOMEM, "vp_graph_create: workspace of %zu bytes exceeds the HBM budget", g->bytes);
-  }
   hipError_t e;
-  if ((e = hipMalloc((void**)&g->c, 8 * std::max<size_t>(nC, 1))) != hipSuccess ||
-      (e = hipMalloc((void**)&g->q, 8 * std::max<size_t>(nQ, 1))) != hipSuccess ||
-      (e = hipMalloc((void**)&g->part, 8 * std::max<size_t>(nP, 1))) != hipSuccess ||
-      (prec == VP_MIXED && (e = hipMalloc((void**)&g->q32, 4 * std::max<size_t>(nQ, 1))) != hipSuccess) ||
+  size_t got[4] = {0, 0, 0, 0};
+  if ((e = vp::ctx_alloc(ctx, (void**)&g->c, 8 * std::max<size_t>(nC, 1), &got[0])) != hipSuccess ||
+      (e = vp::ctx_alloc(ctx, (void**)&g->q, 8 * std::max<size_t>(nQ, 1), &got[1])) != hipSuccess ||
+      (e = vp::ctx_alloc(ctx, (void**)&g->part, 8 * std::max<size_t>(nP, 1), &got[2])) != hipSuccess ||
+      (prec == VP_MIXED && (e = vp::ctx_alloc(ctx, (void**)&g->q32, 4 * std::max<size_t>(nQ, 1), &got[3])) !=
+                               hipSuccess) ||
       (e = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking)) != hipSuccess) {
     drop(g);
+    if (e == hipErrorOutOfMemory)
+      return fail(VP_ENOMEM, "vp_graph_create: workspace exceeds the device memory or the HBM budget");
     return hip_fail(e, "vp_graph_create");
   }
-  if ((e = vp::fmm_prepare_blocks(pl, R, pl->ctx->stream)) != hipSuccess) {
+  g->bytes = got[0] + got[1] + got[2] + got[3];
+  if ((e = vp::prepare_blocks(pl, R, pl->ctx->stream)) != hipSuccess) {
     drop(g);
     return hip_fail(e, "vp_graph_create: FMM tables");
   }
@@ -1125,7 +1124,6 @@ vp_status vp_graph_create(vp_plan* pl, int64_t R, const double* density, double*
     drop(g);
     return hip_fail(e, "vp_graph_create: capture");
   }
-  pl->ctx->in_use += g->bytes;
   pl->live_requests++;
   *out = g;
   return VP_OK;
@@ -1142,13 +1140,12 @@ vp_status vp_graph_destroy(vp_graph* g) {
   if (!g) return VP_OK;
   (void)hipSetDevice(g->plan->ctx->device);
   (void)hipStreamSynchronize(g->plan->ctx->stream);
-  g->plan->ctx->in_use -= g->bytes;
   g->plan->live_requests--;
   (void)hipGraphExecDestroy(g->exec);
   (void)hipGraphDestroy(g->graph);
   (void)hipStreamDestroy(g->cap);
   for (void* p : {(void*)g->c, (void*)g->q, (void*)g->part, (void*)g->q32})
-    if (p) (void)hipFree(p);
+    if (p) vp::ctx_release(g->plan->ctx, p);
   delete g;
   return VP_OK;
 }
@@ -1230,7 +1227,7 @@ vp_status vp_plan_autotune(vp_plan* pl, int64_t R, vp_precision prec, int reps, 
   vp_status s = ensure_workspace(pl, R, need_split);
   if (s != VP_OK) return s;
   hipStream_t st = pl->ctx->stream;
-  VP_HIP(vp::fmm_prepare_blocks(pl, R, st), "vp_plan_autotune: FMM tables");
+  VP_HIP(vp::prepare_blocks(pl, R, st), "vp_plan_autotune: tables for blocks of 16 densities");
   VP_HIP(hipMemsetAsync(pl->ws_c, 0, 8 * std::max<size_t>((size_t)pl->n_tri * pl->n_p * R, 1), st),
          "vp_plan_autotune: clear");
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -1273,7 +1270,6 @@ vp_status vp_plan_destroy(vp_plan* pl) {
     return fail(VP_EBUSY, "vp_plan_destroy: %d server requests still use this plan", pl->live_requests);
   (void)hipSetDevice(pl->ctx->device);
   (void)hipStreamSynchronize(pl->ctx->stream);
-  pl->ctx->in_use -= pl->bytes + pl->ws_bytes;
   const_cast<vp_mesh*>(pl->mesh)->live_plans--;
   free_plan_memory(pl);
   delete pl;

@@ -179,6 +179,25 @@ hipError_t build_clusters(vp_plan* pl, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st) {
+  hipError_t e = fmm_prepare_blocks(pl, R, st);
+  if (e != hipSuccess || R < 16 || pl->cl_tried) return e;
+  pl->cl_tried = true;
+  // at most 68 bytes per pair (an entry per pair, its 16 pair slots and triangle)
+  if (!ctx_fits(pl->ctx, 68 * (uint64_t)pl->n_pairs)) {
+    pl->n_cl = 0;
+    return hipSuccess;
+  }
+  e = build_clusters(pl, st);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    pl->n_cl = 0;
+    pl->n_entries = 0;
+    return hipSuccess;
+  }
+  return e;
+}
+
 #define VP_DISPATCH_P(p, CALL)                    \
   switch (p) {                                    \
     case 1: { constexpr int P = 1; CALL; } break;  \

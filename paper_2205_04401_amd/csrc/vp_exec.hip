@@ -539,6 +539,45 @@ __global__ __launch_bounds__(kBlock) void k_finish(const double* __restrict__ pa
   }
 }
 
+// The same sum with the G lanes of a target striding over its rows as one
+// flat array of pairs x n_p values, so that consecutive lanes read
+// consecutive row values (coalesced): for targets with long near lists,
+// where the rows' bytes set the time.
+template <int P, int G>
+__global__ __launch_bounds__(kBlock) void k_finish_flat(const double* __restrict__ partial, int64_t n_split,
+                                                        int64_t n_tgt, int64_t R, int64_t r0,
+                                                        const int64_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ pair_tri,
+                                                        const double* __restrict__ rows,
+                                                        const double* __restrict__ C, int far_only,
+                                                        double* __restrict__ U) {
+  constexpr int NP = (P + 1) * (P + 2) / 2;
+  const int lane = (int)(threadIdx.x % G);
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / G);
+  const int64_t Rr = R - r0;
+  for (int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; g < n_tgt * Rr; g += stride) {
+    const int64_t t = g / Rr, r = r0 + (g - t * Rr);
+    double u = 0.0;
+    for (int64_t s = lane; s < n_split; s += G) u += partial[((size_t)s * n_tgt + t) * R + r];
+    if (!far_only) {
+      const int64_t p0 = row_ptr[t];
+      const int64_t nv = (row_ptr[t + 1] - p0) * NP;
+      const double* rw = rows + (size_t)p0 * NP;
+      double corr = 0.0;
+#pragma unroll 4
+      for (int64_t f = lane; f < nv; f += G) {
+        const int64_t j = f / NP;
+        const int k = (int)(f - j * NP);
+        corr = fma(rw[f], C[((size_t)pair_tri[p0 + j] * NP + k) * R + r], corr);
+      }
+      u += corr;
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) u += __shfl_xor(u, off, G);
+    if (lane == 0) U[t * R + r] = u;
+  }
+}
+
 }  // namespace
 
 #define VP_DISPATCH_P(p, CALL)   \
@@ -722,6 +761,14 @@ hipError_t launch_finish(const vp_plan* pl, const double* partial, int64_t n_spl
   // the rest on the vector ALUs; lanes per (target, rhs): enough
   // work-items to fill the device
   const int64_t n = NT * (R - r0);
+  // long near lists (8 or more pairs per target on average) at sizes that
+  // fill the device: 16 lanes per (target, rhs) reading the rows flat
+  if (n >= (1 << 17) && pl->n_pairs >= 8 * NT) {
+    VP_DISPATCH_P(pl->p, (k_finish_flat<P, 16><<<blocks_for(n * 16), kBlock, 0, st>>>(
+                              partial, n_split, NT, R, r0, pl->row_ptr, pl->pair_tri, pl->rows, C, far_only ? 1 : 0,
+                              U)));
+    return hipGetLastError();
+  }
   const int G = n >= (1 << 17) ? 1 : n >= (1 << 15) ? 4 : 16;
 #define VP_FINISH(GV)                                                                                      \
   VP_DISPATCH_P(pl->p, (k_finish<P, GV><<<blocks_for(n * GV), kBlock, 0, st>>>(                            \

@@ -1104,19 +1104,15 @@ hipError_t fmm_prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st) {
     for (int64_t i = tp[b]; i < tp[b + 1]; i += 16) tiles.push_back(make_int2((int)b, (int)i));
   const size_t bytes =
       sizeof(double) * (NS * pl->fmm_mp + NT * pl->fmm_kp) + sizeof(int2) * std::max<size_t>(tiles.size(), 1);
-  if (pl->ctx->budget && pl->ctx->in_use + bytes > pl->ctx->budget) return hipErrorOutOfMemory;
+  if (!ctx_fits(pl->ctx, bytes)) return hipErrorOutOfMemory;
   double *vsrc = nullptr, *wtgt = nullptr;
   int2* tt = nullptr;
   hipError_t e;
   // the blocks belong to the plan from here on, also when this fails
-  const size_t held = pl->bytes;
   if ((e = plan_alloc(pl, (void**)&vsrc, sizeof(double) * NS * pl->fmm_mp)) != hipSuccess ||
       (e = plan_alloc(pl, (void**)&wtgt, sizeof(double) * NT * pl->fmm_kp)) != hipSuccess ||
-      (e = plan_alloc(pl, (void**)&tt, sizeof(int2) * std::max<size_t>(tiles.size(), 1))) != hipSuccess) {
-    pl->ctx->in_use += pl->bytes - held;
+      (e = plan_alloc(pl, (void**)&tt, sizeof(int2) * std::max<size_t>(tiles.size(), 1))) != hipSuccess)
     return e;
-  }
-  pl->ctx->in_use += pl->bytes - held;
   const double sL = pl->fmm_width / n;
   k_fmm_vsrc<<<blocks_for(NS), kBlock, 0, st>>>(pl->fmm_sxy, NS, pl->fmm_x0, pl->fmm_y0, sL, L, p, pl->fmm_mp, vsrc);
   k_fmm_wtgt<<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, pl->fmm_tgt_perm, NT, pl->fmm_x0, pl->fmm_y0, sL, L, p,

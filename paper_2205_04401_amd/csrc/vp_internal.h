@@ -350,7 +350,8 @@ struct vp_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   uint64_t budget = 0;
-  uint64_t in_use = 0;
+  uint64_t in_use = 0;     // device bytes held (plans, workspaces, meshes, ...), cached blocks excluded
+  uint64_t cache_cap = 0;  // most bytes the block cache keeps (a quarter of the device's memory)
   // FMM translation operators per expansion order, shared by the context's
   // plans (device memory, freed with the context)
   struct FmmOps {
@@ -368,6 +369,7 @@ struct vp_ctx {
   std::map<void*, size_t> block_size;
   uint64_t cached = 0;
   int live_meshes = 0;
+  int live_servers = 0;
   // profiling: pending event pairs per stage, folded into the totals on read
   bool profile = false;
   struct Pending {
@@ -376,8 +378,8 @@ struct vp_ctx {
     int64_t launches;
   };
   std::vector<Pending> pending;
-  double ms[VP_N_STAGES] = {0, 0, 0, 0, 0};
-  int64_t launches[VP_N_STAGES] = {0, 0, 0, 0, 0};
+  double ms[VP_N_STAGES] = {};
+  int64_t launches[VP_N_STAGES] = {};
 };
 
 struct vp_mesh {
@@ -455,6 +457,7 @@ struct vp_plan {
   // clusters of 16 consecutive targets for the matrix-core correction apply
   // (0 clusters: not built, the apply stays on the vector ALUs)
   int64_t n_cl = 0, n_entries = 0;
+  bool cl_tried = false;  // clusters built (or given up) by the first evaluation of 16+ densities
   int64_t* cl_ptr = nullptr;    // [n_cl+1] entries of each cluster
   int32_t* ent_tri = nullptr;   // [n_entries] triangle of the entry (ascending within a cluster)
   int32_t* ent_pair = nullptr;  // [n_entries][16] pair index per cluster target, -1 if absent
@@ -492,18 +495,25 @@ struct vp_plan {
 
 namespace vp {
 
-// Device memory of plans, through the context's block cache.  ctx_alloc
-// takes an idle cached block of at least `bytes` (and at most a quarter
-// more), else calls hipMalloc, emptying the cache and trying once more when
-// the device is out of memory.  ctx_release takes a block that no queued
-// device work uses any more: it joins the cache while the cache stays
-// within kCacheMaxBytes (and, with an HBM budget, the budget), else it is
-// freed.  ctx_trim frees every idle block.  plan_alloc allocates a block
-// owned by the plan (released when the plan is destroyed).
-constexpr uint64_t kCacheMaxBytes = uint64_t(16) << 30;
-hipError_t ctx_alloc(vp_ctx* ctx, void** p, size_t bytes);
+// Device memory of plans, their workspaces, server slots and captured
+// evaluations, through the context's block cache.  ctx_alloc takes an idle
+// cached block of at least `bytes` (and at most a quarter more), else calls
+// hipMalloc, emptying the cache and trying once more when the device is out
+// of memory; the block's size (`*got`) counts in ctx->in_use until
+// ctx_release, which takes a block that no queued device work uses any
+// more: it joins the cache while the cache stays within ctx->cache_cap (a
+// quarter of the device's memory), else it is freed.  With an HBM budget,
+// in_use + cached never exceeds it: ctx_alloc empties the cache first when
+// a new block would cross it, and fails with hipErrorOutOfMemory when the
+// block does not fit even then.  ctx_fits makes the same check (and the same
+// room) for memory allocated outside the cache (meshes, interpolation
+// objects, FMM operators), whose callers add it to in_use themselves.
+// ctx_trim frees every idle block.  plan_alloc allocates a block owned by
+// the plan (released when the plan is destroyed).
+hipError_t ctx_alloc(vp_ctx* ctx, void** p, size_t bytes, size_t* got = nullptr);
 void ctx_release(vp_ctx* ctx, void* p);
 void ctx_trim(vp_ctx* ctx);
+bool ctx_fits(vp_ctx* ctx, uint64_t bytes);
 hipError_t plan_alloc(vp_plan* pl, void** dst, size_t bytes);
 
 // Temporaries of a plan build used on stream st only, from the context's
@@ -559,6 +569,11 @@ hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, const vp_fa
 hipError_t launch_finish(const vp_plan* pl, const double* partial, int64_t n_split, const double* C,
                          int64_t R, bool far_only, double* U, hipStream_t st);
 hipError_t build_clusters(vp_plan* pl, hipStream_t st);  // after the pair list; allocates plan memory
+// Tables that only blocks of 16 or more densities use (the FMM's P2M/L2P
+// rows, the correction apply's target clusters), built by the first
+// evaluation with R >= 16; without clusters (not built, or over the HBM
+// budget) the correction apply stays on the vector ALUs.
+hipError_t prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st);
 // U columns [r0, r0 + 16 nt) on the matrix cores (nt = 1, 2 or 4)
 hipError_t launch_corr_mfma(const vp_plan* pl, const double* partial, int64_t n_split, const double* C, int64_t R,
                             int64_t r0, int nt, bool far_only, double* U, hipStream_t st);
@@ -580,6 +595,32 @@ hipError_t fmm_prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st);
 hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out, double* ws, hipStream_t st,
                       int64_t* n_launches);
 void set_last_error(const char* msg);
+// Device time of a stage on the context's stream (when profiling is on):
+// events around the stage's launches, folded into the totals on read.
+struct StageTimer {
+  vp_ctx* ctx;
+  int stage;
+  hipEvent_t a = nullptr, b = nullptr;
+  explicit StageTimer(vp_ctx* c, int s) : ctx(c), stage(s) {
+    if (!ctx->profile) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      ctx->profile = false;
+      return;
+    }
+    (void)hipEventRecord(a, ctx->stream);
+  }
+  void stop(int64_t launches) {
+    if (!a || !ctx->profile) return;
+    (void)hipEventRecord(b, ctx->stream);
+    ctx->pending.push_back({stage, a, b, launches});
+    a = b = nullptr;
+  }
+  ~StageTimer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
 // Records the device address of the allocation-free evaluation's workspace
 // array on `device` (current), once per device.
 hipError_t noalloc_setup(int device);

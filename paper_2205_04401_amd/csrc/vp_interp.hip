@@ -245,7 +245,7 @@ vp_status vp_interp_create(vp_ctx* ctx, const vp_mesh* mesh, int p, vp_interp** 
     delete x;
   };
   it->bytes = sizeof(double) * NP * NP + sizeof(int64_t) * (nc + 1) + sizeof(int32_t) * ctri.size();
-  if (ctx->budget && ctx->in_use + it->bytes > ctx->budget) {
+  if (!vp::ctx_fits(ctx, it->bytes)) {
     drop(it);
     return ifail(VP_ENOMEM, "vp_interp_create: %zu bytes exceed the HBM budget", it->bytes);
   }

@@ -754,9 +754,11 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
     gy1 = std::max(gy1, hp[5 * i + 3]);
     sum += hp[5 * i + 4];
   }
-  // cell size: the mean extent of the triangles' near-field boxes, enlarged
+  // cell size: a quarter of the mean extent of the triangles' near-field
+  // boxes (a target tests the triangles whose boxes meet its cell: cells of
+  // the boxes' size would test about 4x as many as boxes hold it), enlarged
   // if the grid would exceed 2^24 cells
-  double h = std::max(sum / (double)T, 1e-300);
+  double h = std::max(0.25 * sum / (double)T, 1e-300);
   double wx = std::max(gx1 - gx0, 0.0), wy = std::max(gy1 - gy0, 0.0);
   double cells = (wx / h + 1.0) * (wy / h + 1.0);
   if (cells > 16777216.0) h *= std::sqrt(cells / 16777216.0);

@@ -173,7 +173,7 @@ __device__ __forceinline__ void near_root(double Ax, double Ay, double Bx, doubl
 // only (each of the two then carries only its own branch, with fewer live
 // registers than both together)
 template <int P, bool kCurved, int KIND>
-__global__ __launch_bounds__(64, 2) void k_rows(RowsArgs a) {
+__global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
   __shared__ double lv[2][kCap * 3];
   __shared__ double leaf[kCap * 3];
@@ -631,6 +631,7 @@ constexpr int kClsThreads = 256;
 constexpr int kClsPer = 4;                              // pairs per thread
 constexpr int kClsChunk = kClsThreads * kClsPer;        // pairs per block
 constexpr int kTabNearMax = 64;                         // near-rule nodes of the table path (q_near <= 8)
+constexpr int kTabSlotsMax = 2048;                      // slots of both classes (LDS: 24 bytes each)
 
 struct ClassArgs {
   const int32_t *pair_tri, *pair_tgt;
@@ -638,6 +639,8 @@ struct ClassArgs {
   int64_t n_pairs, n_blk;
   const double *xt, *yt;
   const double *ax, *ay, *bx, *by, *cx, *cy, *det, *deff;
+  const double* nr;  // [6][n_tri] near-rule rho0 and edge lengths (k_near_root)
+  int64_t n_tri;
   double nwhat0, nwhat1, nwhat2, eps_cn, inv_near_order;
   int depth_cap;
   uint8_t* cls;     // [n_pairs] class of every pair
@@ -654,9 +657,12 @@ __device__ __forceinline__ int pair_class(const ClassArgs& a, int64_t pr) {
   const double x = a.xt[it], y = a.yt[it];
   const double Ax = a.ax[t], Ay = a.ay[t], Bx = a.bx[t], By = a.by[t], Cx = a.cx[t], Cy = a.cy[t];
   const double e1x = Bx - Ax, e1y = By - Ay, e2x = Cx - Ax, e2y = Cy - Ay;
-  const double wh[3] = {a.nwhat0, a.nwhat1, a.nwhat2};
   double rho0[3], ell0[3], thr[3];
-  near_root(Ax, Ay, Bx, By, Cx, Cy, a.deff[t], wh, a.eps_cn, a.inv_near_order, rho0, ell0);
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    rho0[e] = a.nr[e * a.n_tri + t];
+    ell0[e] = a.nr[(3 + e) * a.n_tri + t];
+  }
   near_level_thr(rho0, ell0, 0, a.inv_near_order, thr);
   if (!(0 < a.depth_cap && near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.0, 0.0, 1.0, thr))) return 0;
   if (!(1 < a.depth_cap)) return 1;
@@ -667,6 +673,25 @@ __device__ __forceinline__ int pair_class(const ClassArgs& a, int64_t pr) {
       near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.5, 0.5, -0.5, thr))
     return 2;
   return 1;
+}
+
+// near-rule rho0 and edge lengths of every triangle: nr[e][T] = rho0_e,
+// nr[3 + e][T] = l_e (the values k_rows computes for each pair)
+__global__ void k_near_root(const double* __restrict__ ax, const double* __restrict__ ay,
+                            const double* __restrict__ bx, const double* __restrict__ by,
+                            const double* __restrict__ cx, const double* __restrict__ cy,
+                            const double* __restrict__ deff, int64_t n_tri, double w0, double w1, double w2,
+                            double eps_cn, double inv_near_order, double* __restrict__ nr) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tri) return;
+  const double wh[3] = {w0, w1, w2};
+  double rho0[3], ell0[3];
+  near_root(ax[t], ay[t], bx[t], by[t], cx[t], cy[t], deff[t], wh, eps_cn, inv_near_order, rho0, ell0);
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    nr[e * n_tri + t] = rho0[e];
+    nr[(3 + e) * n_tri + t] = ell0[e];
+  }
 }
 
 // count pass: class of every pair, pairs of each class per block
@@ -727,16 +752,19 @@ __global__ __launch_bounds__(kClsThreads) void k_pair_scatter(ClassArgs a) {
   }
 }
 
-// Reference data of the two classes: node tables [rows][3] (xi1, xi2 and
-// the weight factor w_j s^2 of the leaf) and Koornwinder tables
-// [nf4 + rows][NPP] (far nodes first, zero rows and columns as padding).
+// Reference data of the two classes, one row per slot (far nodes first,
+// padded to a multiple of 4, then the near rule's nodes): node tables
+// [rows][3] (xi1, xi2 and the weight: -w_j of the far rule, subtracted, or
+// w_j s^2 of a leaf of scale s; 0 in padding rows, placed at the centroid)
+// and Koornwinder tables [rows][NPP] (zero rows and columns as padding).
 // Class 0: the near rule on the simplex; class 1: on its four children
 // (a, s) = ((0,0), 1/2), ((1/2,0), 1/2), ((0,1/2), 1/2), ((1/2,1/2), -1/2).
 template <int P>
-__global__ void k_tab_build(const double* __restrict__ fx, const double* __restrict__ fy, int nf, int nf4,
-                            const double* __restrict__ nx, const double* __restrict__ ny,
-                            const double* __restrict__ nw, int nn, int nn4, double* __restrict__ nod0,
-                            double* __restrict__ nod1, double* __restrict__ tab0, double* __restrict__ tab1) {
+__global__ void k_tab_build(const double* __restrict__ fx, const double* __restrict__ fy,
+                            const double* __restrict__ fw, int nf, int nf4, const double* __restrict__ nx,
+                            const double* __restrict__ ny, const double* __restrict__ nw, int nn, int nn4,
+                            double* __restrict__ nod0, double* __restrict__ nod1, double* __restrict__ tab0,
+                            double* __restrict__ tab1) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
   constexpr int NPP = 16 * ((NP + 15) / 16);
   const int rows0 = nf4 + nn4, rows1 = nf4 + 4 * nn;
@@ -745,36 +773,34 @@ __global__ void k_tab_build(const double* __restrict__ fx, const double* __restr
   const bool one = g >= rows0;
   const int r = one ? g - rows0 : g;
   double* row = (one ? tab1 : tab0) + (size_t)r * NPP;
+  double* nod = (one ? nod1 : nod0) + 3 * (size_t)r;
   for (int k = 0; k < NPP; ++k) row[k] = 0.0;
-  double xi1 = 0.0, xi2 = 0.0;
+  double xi1 = 1.0 / 3.0, xi2 = 1.0 / 3.0, w = 0.0;
   bool live = false;
   if (r < nf) {
     xi1 = fx[r];
     xi2 = fy[r];
+    w = -fw[r];
     live = true;
   } else if (r >= nf4) {
     const int j = r - nf4;
-    if (!one && j < nn4) {
-      const bool v = j < nn;
-      nod0[3 * j] = v ? nx[j] : 0.0;
-      nod0[3 * j + 1] = v ? ny[j] : 0.0;
-      nod0[3 * j + 2] = v ? nw[j] : 0.0;
-      if (v) {
-        xi1 = nx[j];
-        xi2 = ny[j];
-        live = true;
-      }
+    if (!one && j < nn) {
+      xi1 = nx[j];
+      xi2 = ny[j];
+      w = nw[j];
+      live = true;
     } else if (one) {
       const int c = j / nn, i = j - c * nn;
       const double sa = (c == 1 || c == 3) ? 0.5 : 0.0, sb = (c >= 2) ? 0.5 : 0.0, ss = (c == 3) ? -0.5 : 0.5;
       xi1 = sa + ss * nx[i];
       xi2 = sb + ss * ny[i];
-      nod1[3 * j] = xi1;
-      nod1[3 * j + 1] = xi2;
-      nod1[3 * j + 2] = nw[i] * ss * ss;
+      w = nw[i] * ss * ss;
       live = true;
     }
   }
+  nod[0] = xi1;
+  nod[1] = xi2;
+  nod[2] = w;
   if (live) koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { row[k] = v; });
 }
 
@@ -786,9 +812,7 @@ struct TabArgs {
   const int32_t *pair_tri, *pair_tgt;
   const double *xt, *yt;
   const double *ax, *ay, *bx, *by, *cx, *cy, *det;
-  const double2* sxy;  // the far sources and their weights (as in the far sums)
-  const double* swj;
-  int nf, nf4, nn, nn4;
+  int rows0, rows1;  // slots of class 0 and class 1 (multiples of 4)
   const double *nod0, *nod1, *tab0, *tab1;
   const double2* logtab;
   double* rows;
@@ -800,10 +824,10 @@ __global__ __launch_bounds__(256) void k_rows_tab(TabArgs a) {
   constexpr int NT = (NP + 15) / 16;
   constexpr int NPP = 16 * NT;
   __shared__ double2 tab[kLogTab + 1];
-  __shared__ double nod[3 * 5 * kTabNearMax];
+  extern __shared__ double nod[];  // [rows0 + rows1][3]
   for (int i = threadIdx.x; i <= kLogTab; i += blockDim.x) tab[i] = a.logtab[i];
-  for (int i = threadIdx.x; i < 3 * a.nn4; i += blockDim.x) nod[i] = a.nod0[i];
-  for (int i = threadIdx.x; i < 12 * a.nn; i += blockDim.x) nod[3 * a.nn4 + i] = a.nod1[i];
+  for (int i = threadIdx.x; i < 3 * a.rows0; i += blockDim.x) nod[i] = a.nod0[i];
+  for (int i = threadIdx.x; i < 3 * a.rows1; i += blockDim.x) nod[3 * a.rows0 + i] = a.nod1[i];
   __syncthreads();
   const int lane = threadIdx.x & 63, kq = lane >> 4, col = lane & 15;
   const int64_t t0 = (a.n0 + 15) / 16, n_tiles = t0 + (a.n1 + 15) / 16;
@@ -820,32 +844,28 @@ __global__ __launch_bounds__(256) void k_rows_tab(TabArgs a) {
     const double e1x = a.bx[t] - Ax, e1y = a.by[t] - Ay, e2x = a.cx[t] - Ax, e2y = a.cy[t] - Ay;
     const double D = a.det[t];
     const double* T = one ? a.tab1 : a.tab0;
-    const double* N = one ? nod + 3 * a.nn4 : nod;
-    const int n_near = one ? 4 * a.nn : a.nn;
-    const int n_slots = a.nf4 + (one ? 4 * a.nn : a.nn4);
-    const double2* src = a.sxy + (int64_t)t * a.nf;
-    const double* wsrc = a.swj + (int64_t)t * a.nf;
+    const double* N = one ? nod + 3 * a.rows0 : nod;
+    const int n_slots = one ? a.rows1 : a.rows0;
     vp_d4 acc[NT];
+    // zero accumulators made by the matrix core itself, so that they live in
+    // its registers through the loop
 #pragma unroll
-    for (int n = 0; n < NT; ++n) acc[n] = vp_d4{0.0, 0.0, 0.0, 0.0};
+    for (int n = 0; n < NT; ++n)
+      acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(0.0, 0.0, vp_d4{0.0, 0.0, 0.0, 0.0}, 0, 0, 0);
+    // Every slot alike: the node's position from the triangle's map (for the
+    // far nodes the far sums' own expression, so a pair at distance 0
+    // cancels), r^2 with the far sums' offset (far below any near node's
+    // r^2), and the weight from the table (negative for the far rule's own
+    // contribution, which is subtracted; zero in padding rows).
     for (int s0 = 0; s0 < n_slots; s0 += 4) {
       const int slot = s0 + kq;
-      double g = 0.0;
-      if (slot < a.nf) {
-        // the far rule's own contribution, subtracted (the far sums' expression)
-        const double2 sj = src[slot];
-        const double dx = x - sj.x, dy = y - sj.y;
-        const double r2 = fma(dy, dy, fma(dx, dx, kR2Bias));
-        g = -0.5 * vp_log(r2, tab) * wsrc[slot];
-      } else if (slot >= a.nf4 && slot - a.nf4 < n_near) {
-        const int j = slot - a.nf4;
-        const double xi1 = N[3 * j], xi2 = N[3 * j + 1];
-        const double yx = Ax + xi1 * e1x + xi2 * e2x;
-        const double yy = Ay + xi1 * e1y + xi2 * e2y;
-        const double dx = x - yx, dy = y - yy;
-        g = 0.5 * vp_log(dx * dx + dy * dy, tab) * N[3 * j + 2] * D;
-      }
-      if (!valid) g = 0.0;
+      const double xi1 = N[3 * slot], xi2 = N[3 * slot + 1], w = N[3 * slot + 2];
+      const double yx = Ax + xi1 * e1x + xi2 * e2x;
+      const double yy = Ay + xi1 * e1y + xi2 * e2y;
+      const double dx = x - yx, dy = y - yy;
+      const double r2 = fma(dy, dy, fma(dx, dx, kR2Bias));
+      const double v = 0.5 * vp_log(r2, tab) * (w * D);
+      const double g = valid ? v : 0.0;
       const double* Trow = T + (size_t)slot * NPP + col;
 #pragma unroll
       for (int n = 0; n < NT; ++n) acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(g, Trow[16 * n], acc[n], 0, 0, 0);
@@ -884,16 +904,17 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
   int32_t* bcnt = nullptr;
   int64_t* boff = nullptr;
   uint32_t* list = nullptr;
-  double *nod0 = nullptr, *nod1 = nullptr, *tab0 = nullptr, *tab1 = nullptr;
+  double *nod0 = nullptr, *nod1 = nullptr, *tab0 = nullptr, *tab1 = nullptr, *nr = nullptr;
   void* stmp = nullptr;
   hipError_t e;
   if ((e = tmp.alloc((void**)&cls, (size_t)n)) != hipSuccess ||
+      (e = tmp.alloc((void**)&nr, sizeof(double) * 6 * std::max<int64_t>(pl->n_tri, 1))) != hipSuccess ||
       (e = tmp.alloc((void**)&bcnt, sizeof(int32_t) * 4 * n_blk)) != hipSuccess ||
       (e = tmp.alloc((void**)&boff, sizeof(int64_t) * (4 * n_blk + 1))) != hipSuccess ||
       (e = tmp.alloc((void**)&list, sizeof(uint32_t) * n)) != hipSuccess ||
       (e = tmp.alloc(&stmp, exclusive_scan_tmp_bytes(4 * n_blk))) != hipSuccess ||
-      (e = tmp.alloc((void**)&nod0, sizeof(double) * 3 * nn4)) != hipSuccess ||
-      (e = tmp.alloc((void**)&nod1, sizeof(double) * 12 * nn)) != hipSuccess ||
+      (e = tmp.alloc((void**)&nod0, sizeof(double) * 3 * rows0)) != hipSuccess ||
+      (e = tmp.alloc((void**)&nod1, sizeof(double) * 3 * rows1)) != hipSuccess ||
       (e = tmp.alloc((void**)&tab0, sizeof(double) * rows0 * NPP)) != hipSuccess ||
       (e = tmp.alloc((void**)&tab1, sizeof(double) * rows1 * NPP)) != hipSuccess)
     return e;
@@ -913,6 +934,8 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
   c.cy = m->cy;
   c.det = m->det;
   c.deff = pl->deff;
+  c.nr = nr;
+  c.n_tri = pl->n_tri;
   c.nwhat0 = a.nwhat0;
   c.nwhat1 = a.nwhat1;
   c.nwhat2 = a.nwhat2;
@@ -923,9 +946,14 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
   c.bcnt = bcnt;
   c.boff = boff;
   c.list = list;
+  if (pl->n_tri > 0)
+    k_near_root<<<(unsigned)((pl->n_tri + 255) / 256), 256, 0, st>>>(m->ax, m->ay, m->bx, m->by, m->cx, m->cy,
+                                                                      pl->deff, pl->n_tri, a.nwhat0, a.nwhat1,
+                                                                      a.nwhat2, a.eps_cn, a.inv_near_order, nr);
   k_pair_class<<<(unsigned)n_blk, kClsThreads, 0, st>>>(c);
-  k_tab_build<P><<<(rows0 + rows1 + 127) / 128, 128, 0, st>>>(pl->far_x, pl->far_y, nf, nf4, pl->near_x, pl->near_y,
-                                                              pl->near_w, nn, nn4, nod0, nod1, tab0, tab1);
+  k_tab_build<P><<<(rows0 + rows1 + 127) / 128, 128, 0, st>>>(pl->far_x, pl->far_y, pl->far_w, nf, nf4,
+                                                              pl->near_x, pl->near_y, pl->near_w, nn, nn4, nod0,
+                                                              nod1, tab0, tab1);
   int64_t tot[5] = {0, 0, 0, 0, 0};
   if ((e = hipGetLastError()) != hipSuccess || (e = exclusive_scan_i32(bcnt, boff, 4 * n_blk, stmp, st)) != hipSuccess)
     return e;
@@ -954,12 +982,8 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
     ta.cx = m->cx;
     ta.cy = m->cy;
     ta.det = m->det;
-    ta.sxy = pl->sxy;
-    ta.swj = pl->swj;
-    ta.nf = nf;
-    ta.nf4 = nf4;
-    ta.nn = nn;
-    ta.nn4 = nn4;
+    ta.rows0 = rows0;
+    ta.rows1 = rows1;
     ta.nod0 = nod0;
     ta.nod1 = nod1;
     ta.tab0 = tab0;
@@ -967,7 +991,10 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
     ta.logtab = pl->logtab;
     ta.rows = pl->rows;
     const int64_t tiles = (n0 + 15) / 16 + (n1 + 15) / 16;
-    k_rows_tab<P><<<(unsigned)std::min<int64_t>((tiles + 3) / 4, 1 << 20), 256, 0, st>>>(ta);
+    StageTimer tm(pl->ctx, VP_STAGE_ROWS_TAB);
+    const size_t lds = sizeof(double) * 3 * (size_t)(rows0 + rows1);
+    k_rows_tab<P><<<(unsigned)std::min<int64_t>((tiles + 3) / 4, 1 << 20), 256, lds, st>>>(ta);
+    tm.stop(1);
   }
   constexpr int64_t kPairsPerGroup = 8;
   auto groups = [&](int64_t k) {
@@ -976,12 +1003,16 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
   if (n2 > 0) {
     a.list = list + n0 + n1;
     a.n_list = n2;
+    StageTimer tm(pl->ctx, VP_STAGE_ROWS_NEAR);
     k_rows<P, false, 1><<<groups(n2), 64, lds, st>>>(a);
+    tm.stop(1);
   }
   if (n3 > 0) {
     a.list = list + n0 + n1 + n2;
     a.n_list = n3;
+    StageTimer tm(pl->ctx, VP_STAGE_ROWS_SELF);
     k_rows<P, false, 2><<<groups(n3), 64, lds, st>>>(a);
+    tm.stop(1);
   }
   // the table path's leaves: one per class-0 pair, four per class-1 pair
   pl->tab_leaves = n0 + 4 * n1;
@@ -1060,7 +1091,8 @@ hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t s
   // straight meshes with the ellipse model: pairs sorted by depth class,
   // shallow near pairs on the matrix cores, deeper near pairs and self
   // pairs by k_rows, each launch sized to its pairs
-  if (!curved && !a.ball && a.nn <= kTabNearMax && pl->n_pairs < ((int64_t)1 << 32)) {
+  const int nf4 = (pl->n_f + 3) & ~3, slots = 2 * nf4 + ((a.nn + 3) & ~3) + 4 * a.nn;  // both classes' slots
+  if (!curved && !a.ball && a.nn <= kTabNearMax && slots <= kTabSlotsMax && pl->n_pairs < ((int64_t)1 << 32)) {
     switch (pl->p) {
       case 1: return rows_by_class<1>(pl, a, lds, st);
       case 2: return rows_by_class<2>(pl, a, lds, st);

@@ -40,6 +40,7 @@ struct vp_server {
     vp_precision prec;
     int state;
     vp_status err;
+    hipEvent_t ready;  // recorded on the context's stream at submit: the inputs are complete there
   };
   struct Slot {
     hipStream_t st = nullptr;
@@ -53,13 +54,23 @@ struct vp_server {
   std::vector<Req> reqs;
   std::deque<int64_t> pending;
   std::vector<Slot> slots;
-  int64_t n_done = 0, n_batches = 0, n_columns = 0;
+  int64_t n_done = 0, n_batches = 0, n_columns = 0, n_rejected = 0, n_budget_waits = 0;
 };
 
 namespace {
 
-// Grow the slot's workspace for (plan, R).  Returns VP_ENOMEM when the
-// context budget cannot hold it right now.
+// The slot's workspace back to the context's block cache (the slot is idle).
+void slot_release(vp_server* s, vp_server::Slot& sl) {
+  for (int i = 0; i < 6; ++i) {
+    if (sl.buf[i]) vp::ctx_release(s->ctx, sl.buf[i]);
+    sl.buf[i] = nullptr;
+    sl.cap[i] = 0;
+  }
+}
+
+// Grow the slot's workspace for (plan, R), through the context's block
+// cache.  Returns VP_ENOMEM when the device or the context's budget cannot
+// hold it right now.
 vp_status slot_reserve(vp_server* s, vp_server::Slot& sl, const vp_plan* pl, int64_t R, bool mixed) {
   const int64_t split = vp::far_config(pl, R, mixed).n_split;
   const size_t need[6] = {
@@ -70,27 +81,25 @@ vp_status slot_reserve(vp_server* s, vp_server::Slot& sl, const vp_plan* pl, int
       8 * (size_t)pl->n_tgt * R,            // U (packed)
       4 * (size_t)pl->n_src_pad * R,        // Q32
   };
-  size_t grow = 0;
-  for (int i = 0; i < 6; ++i)
-    if (need[i] > sl.cap[i]) grow += need[i] - sl.cap[i];
-  if (grow == 0) return VP_OK;
   vp_ctx* ctx = s->ctx;
-  if (ctx->budget && ctx->in_use + grow > ctx->budget) return VP_ENOMEM;
   for (int i = 0; i < 6; ++i) {
     if (need[i] <= sl.cap[i]) continue;
     if (sl.buf[i]) {
-      (void)hipFree(sl.buf[i]);
-      ctx->in_use -= sl.cap[i];
+      vp::ctx_release(ctx, sl.buf[i]);
       sl.buf[i] = nullptr;
       sl.cap[i] = 0;
     }
-    hipError_t e = hipMalloc(&sl.buf[i], std::max<size_t>(need[i], 8));
+    size_t got = 0;
+    hipError_t e = vp::ctx_alloc(ctx, &sl.buf[i], std::max<size_t>(need[i], 8), &got);
     if (e != hipSuccess) {
       sl.buf[i] = nullptr;
-      return e == hipErrorOutOfMemory ? VP_ENOMEM : VP_EDEVICE;
+      if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        return VP_ENOMEM;
+      }
+      return VP_EDEVICE;
     }
-    sl.cap[i] = need[i];
-    ctx->in_use += need[i];
+    sl.cap[i] = got;
   }
   return VP_OK;
 }
@@ -112,12 +121,14 @@ vp_status issue(vp_server* s, int slot_id, const std::vector<int64_t>& batch) {
   int64_t c0 = 0;
   for (int64_t id : batch) {
     const vp_server::Req& r = s->reqs[id];
-    if ((e = vp::launch_pack_columns(r.F, pl->n_tri * pl->n_p, r.R, F, R, c0, st)) != hipSuccess) break;
+    if ((e = hipStreamWaitEvent(st, r.ready, 0)) != hipSuccess ||
+        (e = vp::launch_pack_columns(r.F, pl->n_tri * pl->n_p, r.R, F, R, c0, st)) != hipSuccess)
+      break;
     c0 += r.R;
   }
   const vp_far_config cfg = vp::far_config(pl, R, head.prec == VP_MIXED);
   // FMM plans: the tables of 16+ densities are built once, on the context's stream
-  if (e == hipSuccess) e = vp::fmm_prepare_blocks(const_cast<vp_plan*>(pl), R, s->ctx->stream);
+  if (e == hipSuccess) e = vp::prepare_blocks(const_cast<vp_plan*>(pl), R, s->ctx->stream);
   if (e == hipSuccess) e = vp::launch_coefficients(pl, F, R, C, Q, st);
   if (e == hipSuccess)
     e = vp::launch_far(pl, Q, R, cfg, part, st, nullptr, head.prec == VP_MIXED ? Q32 : nullptr);
@@ -162,6 +173,12 @@ vp_status progress(vp_server* s) {
     sl.members.clear();
     sl.busy = false;
   }
+  // events of finished requests go back
+  for (auto& r : s->reqs)
+    if (r.state >= vp_server::kDone && r.ready) {
+      (void)hipEventDestroy(r.ready);
+      r.ready = nullptr;
+    }
   while (!s->pending.empty()) {
     int free_slot = -1;
     bool any_busy = false;
@@ -185,12 +202,23 @@ vp_status progress(vp_server* s) {
     }
     vp_status st = slot_reserve(s, s->slots[free_slot], h.plan, width, h.prec == VP_MIXED);
     if (st == VP_ENOMEM) {
-      if (any_busy) break;  // memory frees up when a running batch retires
+      // the other idle slots' workspaces make room (they grow again when
+      // used), then the context's cache (ctx_alloc empties it under a budget)
+      for (size_t i = 0; i < s->slots.size(); ++i)
+        if (!s->slots[i].busy && (int)i != free_slot) slot_release(s, s->slots[i]);
+      st = slot_reserve(s, s->slots[free_slot], h.plan, width, h.prec == VP_MIXED);
+    }
+    if (st == VP_ENOMEM) {
+      if (any_busy) {  // memory frees up when a running batch retires
+        s->n_budget_waits++;
+        break;
+      }
       // even alone on an idle device the request does not fit: fail it
       s->reqs[head].state = vp_server::kFailed;
       s->reqs[head].err = VP_ENOMEM;
       s->reqs[head].plan->live_requests--;
       s->pending.pop_front();
+      s->n_rejected++;
       continue;
     }
     if (st != VP_OK) return serve_fail(st, "vp serve: workspace allocation failed");
@@ -212,6 +240,7 @@ vp_status vp_server_create(vp_ctx* ctx, int n_slots, int max_batch_rhs, vp_serve
   if (hipSetDevice(ctx->device) != hipSuccess) return serve_fail(VP_EDEVICE, "hipSetDevice failed");
   vp_server* s = new vp_server;
   s->ctx = ctx;
+  ctx->live_servers++;
   s->max_batch = max_batch_rhs;
   s->slots.resize(n_slots);
   for (auto& sl : s->slots) {
@@ -235,14 +264,13 @@ vp_status vp_server_destroy(vp_server* s) {
   }
   for (auto& sl : s->slots) {
     if (sl.st) (void)hipStreamSynchronize(sl.st);
-    for (int i = 0; i < 6; ++i)
-      if (sl.buf[i]) {
-        (void)hipFree(sl.buf[i]);
-        s->ctx->in_use -= sl.cap[i];
-      }
+    slot_release(s, sl);
     if (sl.ev) (void)hipEventDestroy(sl.ev);
     if (sl.st) (void)hipStreamDestroy(sl.st);
   }
+  for (auto& r : s->reqs)
+    if (r.ready) (void)hipEventDestroy(r.ready);
+  s->ctx->live_servers--;
   delete s;
   return VP_OK;
 }
@@ -255,8 +283,14 @@ vp_status vp_submit(vp_server* s, vp_plan* pl, int64_t R, const double* F, doubl
   if ((!F && pl->n_tri) || (!U && pl->n_tgt)) return serve_fail(VP_EINVAL, "vp_submit: NULL array");
   if (prec != VP_FP64 && prec != VP_MIXED) return serve_fail(VP_EINVAL, "vp_submit: unknown precision");
   if (hipSetDevice(s->ctx->device) != hipSuccess) return serve_fail(VP_EDEVICE, "hipSetDevice failed");
+  hipEvent_t ready = nullptr;
+  if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(ready, s->ctx->stream) != hipSuccess) {
+    if (ready) (void)hipEventDestroy(ready);
+    return serve_fail(VP_EDEVICE, "vp_submit: event on the context's stream failed");
+  }
   *ticket = (vp_ticket)s->reqs.size();
-  s->reqs.push_back({pl, R, F, U, prec, vp_server::kPending, VP_OK});
+  s->reqs.push_back({pl, R, F, U, prec, vp_server::kPending, VP_OK, ready});
   pl->live_requests++;
   s->pending.push_back(*ticket);
   return progress(s);
@@ -296,6 +330,13 @@ vp_status vp_wait(vp_server* s, vp_ticket t) {
     if (target < 0) return serve_fail(VP_EINTERNAL, "vp_wait: request %lld cannot start", (long long)t);
     (void)hipEventSynchronize(s->slots[target].ev);
   }
+}
+
+vp_status vp_server_admission(const vp_server* s, int64_t* budget_waits, int64_t* rejected) {
+  if (!s) return serve_fail(VP_EINVAL, "vp_server_admission: NULL server");
+  if (budget_waits) *budget_waits = s->n_budget_waits;
+  if (rejected) *rejected = s->n_rejected;
+  return VP_OK;
 }
 
 vp_status vp_server_stats(const vp_server* s, int64_t* done, int64_t* batches, int64_t* columns) {

@@ -32,9 +32,10 @@ EXPORTS = ["vp_ctx_create", "vp_ctx_destroy", "vp_last_error", "vp_ref_nodes", "
            "vp_ctx_profile", "vp_ctx_timings", "vp_server_create", "vp_server_destroy", "vp_submit",
            "vp_poll", "vp_wait", "vp_server_stats", "vp_interp_create", "vp_interp_destroy", "vp_interp_locate",
            "vp_interp_eval", "vp_graph_create", "vp_graph_launch", "vp_graph_destroy", "vp_plan_far_config",
-           "vp_plan_set_far_config", "vp_plan_autotune", "vp_ctx_cached_bytes", "vp_ctx_trim"]
+           "vp_plan_set_far_config", "vp_plan_autotune", "vp_ctx_cached_bytes", "vp_ctx_trim", "vp_ctx_memory",
+           "vp_server_admission"]
 FAR_SHAPES = {"wide": 0, "narrow1": 1, "narrow2": 2}
-STAGES = ["classify", "rows", "coef", "far", "finish"]
+STAGES = ["classify", "rows", "coef", "far", "finish", "rows_tab", "rows_near", "rows_self"]
 
 
 class VPError(RuntimeError):
@@ -66,7 +67,8 @@ class PlanStats(ctypes.Structure):
                 ("n_p", ctypes.c_int32), ("n_f", ctypes.c_int32), ("eps", ctypes.c_double),
                 ("ms_classify", ctypes.c_double), ("ms_rows", ctypes.c_double), ("far_split", ctypes.c_int64),
                 ("cluster_entries", ctypes.c_int64), ("fmm_terms", ctypes.c_int32), ("fmm_levels", ctypes.c_int32),
-                ("fmm_near_pairs", ctypes.c_int64), ("fmm_m2l_pairs", ctypes.c_int64)]
+                ("fmm_near_pairs", ctypes.c_int64), ("fmm_m2l_pairs", ctypes.c_int64),
+                ("tab_pairs", ctypes.c_int64), ("tab_leaves", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -115,6 +117,8 @@ def load(path=LIB_PATH):
         "vp_poll": [P, I64, ctypes.POINTER(ctypes.c_int)],
         "vp_wait": [P, I64],
         "vp_server_stats": [P, P, P, P],
+        "vp_server_admission": [P, P, P],
+        "vp_ctx_memory": [P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
         "vp_graph_create": [P, I64, P, P, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(P)],
         "vp_graph_launch": [P],
         "vp_graph_destroy": [P],
@@ -209,6 +213,12 @@ class Context:
         _check(load().vp_ctx_cached_bytes(self.h, ctypes.byref(n)))
         return int(n.value)
 
+    def memory(self):
+        """(bytes in use, bytes cached) on the device (vp_ctx_memory)."""
+        a, b = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        _check(load().vp_ctx_memory(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
+
     def trim(self):
         """Free the cached blocks of destroyed plans."""
         _check(load().vp_ctx_trim(self.h))
@@ -260,9 +270,11 @@ class Server:
         self._keep.pop(ticket, None)
 
     def stats(self):
-        a, b, c = I64(), I64(), I64()
+        a, b, c, d, e = I64(), I64(), I64(), I64(), I64()
         _check(load().vp_server_stats(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return {"requests_done": a.value, "batches": b.value, "columns": c.value}
+        _check(load().vp_server_admission(self.h, ctypes.byref(d), ctypes.byref(e)))
+        return {"requests_done": a.value, "batches": b.value, "columns": c.value, "budget_waits": d.value,
+                "rejected": e.value}
 
     def close(self):
         if self.h:

@@ -95,12 +95,40 @@ def test_cache_within_budget():
     # room for the mesh, one plan and its workspace, not for a second plan
     budget = int(1.6 * held) + (8 << 20)
     ctx = vp.Context(0, hbm_budget_bytes=budget)
+
+    def within():
+        in_use, cached = ctx.memory()
+        say("cache budget", budget, "in use", in_use, "cached", cached)
+        assert in_use + cached <= budget
+        return in_use, cached
+
     try:
-        u1, _ = run(ctx, *a, 4, 8, 1e-12)
-        assert ctx.cached_bytes() <= budget
-        u2, _ = run(ctx, *a, 4, 8, 1e-12)
-        assert ctx.cached_bytes() <= budget
-        say("cache budget", budget, "cached", ctx.cached_bytes())
+        vq, tq, tg, F = a
+        mesh = ctx.mesh(vq, tq)
+        plan = ctx.plan(mesh, 4, 8, 1e-12, tg)
+        in_use, _ = within()
+        # every block the plan holds is counted (rounded sizes included)
+        assert in_use >= plan.info()["bytes_resident"]
+        u1 = plan.execute(F)  # the workspace joins the plan
+        in_use2, _ = within()
+        assert in_use2 >= plan.info()["bytes_resident"] > 0
+        plan.close()
+        within()
+        # a second plan on the cached blocks, then one more than the budget
+        # holds next to it: refused, everything still within the budget
+        plan = ctx.plan(mesh, 4, 8, 1e-12, tg)
+        u2 = plan.execute(F)
+        within()
+        with pytest.raises(vp.VPError) as ei:
+            ctx.plan(mesh, 4, 8, 1e-12, tg)
+        assert ei.value.status == vp.VP_ENOMEM
+        within()
         assert float(np.abs(u2 - u1).max() / np.abs(u1).max()) <= 1e-15
+        plan.close()
+        mesh.close()
+        in_use, cached = within()
+        assert in_use == 0
+        ctx.trim()
+        assert ctx.memory() == (0, 0)
     finally:
         ctx.close()
