@@ -130,7 +130,7 @@ typedef struct {
   double ms_rows;          /* device time of the correction-row precompute */
   int64_t far_split;       /* source chunks of the far sum (partial sums per target and RHS) */
   int64_t cluster_entries; /* (16-target cluster, triangle) blocks of the matrix-core correction
-                              apply (used for blocks of 16+ densities; 0: not built, the apply then
+                              apply (used for blocks of densities; 0: not built, the apply then
                               stays on the vector ALUs); n_pairs / (16 cluster_entries) is the
                               share of those blocks' rows that are pairs, not padding */
   int32_t fmm_terms;       /* expansion terms of the FMM far sum (0: direct sum) */
@@ -262,9 +262,9 @@ vp_status vp_execute(vp_plan* plan, int64_t n_rhs, const double* density, double
  * on one device (other streams, other threads, VP_ASYNC calls whose work
  * is still queued on another context's stream) race on it.  A call whose
  * workspace would exceed VP_NOALLOC_SCRATCH_BYTES returns VP_EINVAL; so
- * does an FMM plan with 16 or more densities before a vp_execute with 16 or
- * more densities has built the plan's FMM tables for such blocks.  The call
- * makes no hipMalloc, hipFree or other allocating call. */
+ * does an FMM plan with 2 or more densities before a vp_execute with 2 or
+ * more densities has built the plan's FMM tables for blocks of densities.
+ * The call makes no hipMalloc, hipFree or other allocating call. */
 #define VP_NOALLOC_SCRATCH_BYTES (256ull << 20)
 vp_status vp_execute_noalloc(vp_plan* plan, int64_t n_rhs, const double* density, double* u_out,
                              vp_precision prec, uint32_t flags);

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_corr_mfma(const double* __restrict__
     auto load = [&](int64_t e, double (&a)[KS], double (&b)[KS][NT]) {
       const int32_t pr = ent_pair[e * kCl + col];
       const double* rowp = rows + (size_t)(pr >= 0 ? pr : 0) * NP;
-      const double* cb = C + (size_t)ent_tri[e] * NP * R + r0 + col;
+      const double* cb = C + (size_t)ent_tri[e] * NP * R;
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         const int k = 4 * s + kq;
@@ -105,8 +105,9 @@ __global__ __launch_bounds__(kBlock) void k_corr_mfma(const double* __restrict__
         a[s] = (pr >= 0 && k < NP) ? av : 0.0;
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
-          const double bv = cb[(size_t)kc * R + 16 * n];
-          b[s][n] = k < NP ? bv : 0.0;
+          const int64_t r = r0 + 16 * n + col;
+          const double bv = cb[(size_t)kc * R + (r < R ? r : R - 1)];
+          b[s][n] = (k < NP && r < R) ? bv : 0.0;
         }
       }
     };
@@ -132,6 +133,7 @@ __global__ __launch_bounds__(kBlock) void k_corr_mfma(const double* __restrict__
 #pragma unroll
       for (int n = 0; n < NT; ++n) {
         const int64_t r = r0 + 16 * n + col;
+        if (r >= R) continue;  // the padding of a last, partial block
         double u = acc[n][v];
 #pragma unroll 8
         for (int64_t s = 0; s < n_split; ++s) u += partial[((size_t)s * n_tgt + t) * R + r];
@@ -181,7 +183,7 @@ hipError_t build_clusters(vp_plan* pl, hipStream_t st) {
 
 hipError_t prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st) {
   hipError_t e = fmm_prepare_blocks(pl, R, st);
-  if (e != hipSuccess || R < 16 || pl->cl_tried) return e;
+  if (e != hipSuccess || R < kMinBlockCols || pl->cl_tried) return e;
   pl->cl_tried = true;
   // at most 68 bytes per pair (an entry per pair, its 16 pair slots and triangle)
   if (!ctx_fits(pl->ctx, 68 * (uint64_t)pl->n_pairs)) {
@@ -215,7 +217,7 @@ hipError_t prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st) {
 
 hipError_t launch_corr_mfma(const vp_plan* pl, const double* partial, int64_t n_split, const double* C, int64_t R,
                             int64_t r0, int nt, bool far_only, double* U, hipStream_t st) {
-  if (pl->n_cl == 0 || R - r0 < 16 * nt) return hipErrorInvalidValue;
+  if (pl->n_cl == 0 || R - r0 <= 16 * (nt - 1)) return hipErrorInvalidValue;
   const int64_t nb = (pl->n_cl * 64 + kBlock - 1) / kBlock;
   if (nb >= (1LL << 31)) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)nb);

@@ -751,11 +751,11 @@ hipError_t launch_finish(const vp_plan* pl, const double* partial, int64_t n_spl
   // blocks of 64, 32 or 16 right-hand sides on the matrix cores, once there
   // are enough 16-target clusters (one wavefront each) to fill the device
   int64_t r0 = 0;
-  while (pl->n_cl >= kCorrMfmaMinClusters && R - r0 >= 16) {
+  while (pl->n_cl >= kCorrMfmaMinClusters && R - r0 >= kMinBlockCols) {
     const int nt = R - r0 >= 64 ? 4 : R - r0 >= 32 ? 2 : 1;
     const hipError_t e = launch_corr_mfma(pl, partial, n_split, C, R, r0, nt, far_only, U, st);
     if (e != hipSuccess) return e;
-    r0 += 16 * nt;
+    r0 = std::min<int64_t>(R, r0 + 16 * nt);
   }
   if (r0 == R) return hipSuccess;
   // the rest on the vector ALUs; lanes per (target, rhs): enough

@@ -494,6 +494,7 @@ __global__ __launch_bounds__(kBlock) void k_fmmb_p2m(const double* __restrict__ 
                                                      const int64_t* __restrict__ ptr, const double* __restrict__ Q,
                                                      int64_t R, int64_t c0, int64_t nleaf, int MP, int KP,
                                                      double* __restrict__ Mb) {
+  // columns c0 + 16 u + r16 >= R (the padding of a last, partial pass) read 0
   constexpr int C = 16 * NB;
   const int tiles = MP / 16;
   const int lane = (int)(threadIdx.x & 63), r16 = lane & 15, kq = lane >> 4;
@@ -510,9 +511,13 @@ __global__ __launch_bounds__(kBlock) void k_fmmb_p2m(const double* __restrict__ 
     const bool ok = j < j1;
     const int64_t jc = ok ? j : j0;
     const double av = ok ? vsrc[jc * MP + 16 * t + r16] : 0.0;
-    const double* q = Q + (int64_t)perm[jc] * R + c0 + r16;
+    const double* q = Q + (int64_t)perm[jc] * R;
 #pragma unroll
-    for (int u = 0; u < NB; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, ok ? q[16 * u] : 0.0, acc[u], 0, 0, 0);
+    for (int u = 0; u < NB; ++u) {
+      const int64_t col = c0 + 16 * u + r16;
+      const double qv = q[col < R ? col : R - 1];
+      acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, (ok && col < R) ? qv : 0.0, acc[u], 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -712,9 +717,13 @@ __global__ __launch_bounds__(kBlock) void k_fmmb_leaf(
       double e, rest;
       vp_log_parts(r2, tab, e, rest);
       const double g = (ok && ta) ? fma(e, l2.x, fma(e, l2.y, rest)) : 0.0;
-      const double* q = Q + (int64_t)sperm[jc] * R + c0 + r16;
+      const double* q = Q + (int64_t)sperm[jc] * R;
 #pragma unroll
-      for (int u = 0; u < NB; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(g, ok ? q[16 * u] : 0.0, acc[u], 0, 0, 0);
+      for (int u = 0; u < NB; ++u) {
+        const int64_t col = c0 + 16 * u + r16;
+        const double qv = q[col < R ? col : R - 1];
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(g, (ok && col < R) ? qv : 0.0, acc[u], 0, 0, 0);
+      }
     }
   }
 #pragma unroll
@@ -723,7 +732,8 @@ __global__ __launch_bounds__(kBlock) void k_fmmb_leaf(
     if (i < i1) {
       const int64_t o = (int64_t)tperm[i] * R + c0 + r16;
 #pragma unroll
-      for (int u = 0; u < NB; ++u) out[o + 16 * u] = acc[u][v];
+      for (int u = 0; u < NB; ++u)
+        if (c0 + 16 * u + r16 < R) out[o + 16 * u] = acc[u][v];
     }
   }
 }
@@ -879,7 +889,7 @@ int64_t fmm_workspace_doubles(const vp_plan* pl, int64_t R) {
   // densities: the real-form expansions [box][KP][16 NB]; they share the
   // space; 2 for alignment
   const int64_t one = 3 * 2 * nbox * (pl->fmm_terms + 1) + pl->n_src;
-  const int64_t cols = R >= 64 ? 64 : R >= 32 ? 32 : R >= 16 ? 16 : 0;
+  const int64_t cols = R >= 64 ? 64 : R >= 32 ? 32 : R >= kMinBlockCols ? 16 : 0;
   const int64_t blk = 2 * nbox * pl->fmm_kp * cols;
   return std::max(one, blk) + 2;
 }
@@ -1089,12 +1099,12 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
   return hipStreamSynchronize(st);  // the host vectors above go out of scope
 }
 
-// Tables of the passes of 16+ densities, built at the first evaluation
+// Tables of the passes of blocks of 16 densities, built at the first evaluation
 // that needs them (they cost 8 (N_src MP + N_tgt KP) bytes): P2M rows of
 // the sources, L2P rows of the targets, and the (leaf box, first target)
 // work list of their leaf pass.  Synchronises the stream.
 hipError_t fmm_prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st) {
-  if (pl->fmm_terms <= 0 || R < 16 || pl->fmm_vsrc) return hipSuccess;
+  if (pl->fmm_terms <= 0 || R < kMinBlockCols || pl->fmm_vsrc) return hipSuccess;
   const int64_t NS = pl->n_src, NT = pl->n_tgt;
   const int L = pl->fmm_levels, n = 1 << L, p = pl->fmm_terms;
   const int64_t nleaf = (int64_t)n * n;
@@ -1164,7 +1174,7 @@ hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out
     }
   }
   int64_t c0 = 0;
-  while (pl->fmm_vsrc && R - c0 >= 16) {
+  while (pl->fmm_vsrc && R - c0 >= kMinBlockCols) {
     const int nbk = R - c0 >= 64 ? 4 : R - c0 >= 32 ? 2 : 1;
     const int C = 16 * nbk;
     double* Mb = (double*)Mall;
@@ -1197,7 +1207,7 @@ hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out
     }
 #undef VP_FMMB
     if (n_launches) *n_launches += 2 * L - 1;
-    c0 += C;
+    c0 = std::min<int64_t>(R, c0 + C);
   }
   // the remaining densities one at a time
   for (int64_t r = c0; r < R; ++r) {

@@ -457,7 +457,7 @@ struct vp_plan {
   // clusters of 16 consecutive targets for the matrix-core correction apply
   // (0 clusters: not built, the apply stays on the vector ALUs)
   int64_t n_cl = 0, n_entries = 0;
-  bool cl_tried = false;  // clusters built (or given up) by the first evaluation of 16+ densities
+  bool cl_tried = false;  // clusters built (or given up) by the first evaluation of several densities
   int64_t* cl_ptr = nullptr;    // [n_cl+1] entries of each cluster
   int32_t* ent_tri = nullptr;   // [n_entries] triangle of the entry (ascending within a cluster)
   int32_t* ent_pair = nullptr;  // [n_entries][16] pair index per cluster target, -1 if absent
@@ -569,12 +569,16 @@ hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, const vp_fa
 hipError_t launch_finish(const vp_plan* pl, const double* partial, int64_t n_split, const double* C,
                          int64_t R, bool far_only, double* U, hipStream_t st);
 hipError_t build_clusters(vp_plan* pl, hipStream_t st);  // after the pair list; allocates plan memory
-// Tables that only blocks of 16 or more densities use (the FMM's P2M/L2P
-// rows, the correction apply's target clusters), built by the first
-// evaluation with R >= 16; without clusters (not built, or over the HBM
-// budget) the correction apply stays on the vector ALUs.
+// Tables that only blocks of 16 densities use (the FMM's P2M/L2P rows, the
+// correction apply's target clusters), built by the first evaluation with
+// R >= kMinBlockCols; without clusters (not built, or over the HBM budget)
+// the correction apply stays on the vector ALUs.
 hipError_t prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st);
-// U columns [r0, r0 + 16 nt) on the matrix cores (nt = 1, 2 or 4)
+// Densities from which the blocks of 16 on the matrix cores also take a
+// remainder (padded with zero columns): a padded block costs about as much
+// as two single-density passes of the FMM or of the correction apply.
+constexpr int64_t kMinBlockCols = 2;
+// U columns [r0, min(R, r0 + 16 nt)) on the matrix cores (nt = 1, 2 or 4)
 hipError_t launch_corr_mfma(const vp_plan* pl, const double* partial, int64_t n_split, const double* C, int64_t R,
                             int64_t r0, int nt, bool far_only, double* U, hipStream_t st);
 // targets per block of the far-sum launch that takes the first right-hand
@@ -589,8 +593,9 @@ int64_t far_partial_doubles(const vp_plan* pl, int64_t n_split, int64_t R);
 int64_t fmm_boxes(int levels);
 int64_t fmm_workspace_doubles(const vp_plan* pl, int64_t R);
 hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st);  // after sources and targets; plan memory
-// tables of the passes of 16+ densities (no-op unless an FMM plan, R >= 16
-// and not built yet); call before launch_far (not under graph capture)
+// tables of the passes of blocks of 16 densities (no-op unless an FMM
+// plan, R >= kMinBlockCols and not built yet); call before launch_far (not
+// under graph capture)
 hipError_t fmm_prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st);
 hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out, double* ws, hipStream_t st,
                       int64_t* n_launches);

@@ -68,10 +68,10 @@ vp_status vp_execute_noalloc(vp_plan* pl, int64_t R, const double* density, doub
   if (!(flags & VP_DEVICE_PTRS) || (flags & ~(uint32_t)(VP_DEVICE_PTRS | VP_FAR_ONLY | VP_ASYNC)))
     return nofail(VP_EINVAL, "vp_execute_noalloc: flags must be VP_DEVICE_PTRS [| VP_FAR_ONLY | VP_ASYNC]");
   if ((!density && pl->n_tri) || (!u_out && pl->n_tgt)) return nofail(VP_EINVAL, "vp_execute_noalloc: NULL array");
-  if (pl->fmm_terms > 0 && R >= 16 && !pl->fmm_vsrc)
+  if (pl->fmm_terms > 0 && R >= vp::kMinBlockCols && !pl->fmm_vsrc)
     return nofail(VP_EINVAL,
-                  "vp_execute_noalloc: the FMM tables for blocks of 16 densities are built by a first vp_execute "
-                  "with n_rhs >= 16 on this plan");
+                  "vp_execute_noalloc: the FMM tables for blocks of densities are built by a first vp_execute "
+                  "with n_rhs >= 2 on this plan");
   const bool mixed = prec == VP_MIXED;
   const vp_far_config cfg = vp::far_config(pl, R, mixed);
   const size_t nC = (size_t)pl->n_tri * pl->n_p * R;

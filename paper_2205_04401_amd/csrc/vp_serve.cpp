@@ -127,7 +127,7 @@ vp_status issue(vp_server* s, int slot_id, const std::vector<int64_t>& batch) {
     c0 += r.R;
   }
   const vp_far_config cfg = vp::far_config(pl, R, head.prec == VP_MIXED);
-  // FMM plans: the tables of 16+ densities are built once, on the context's stream
+  // tables of blocks of densities (FMM rows, correction clusters): built once, on the context's stream
   if (e == hipSuccess) e = vp::prepare_blocks(const_cast<vp_plan*>(pl), R, s->ctx->stream);
   if (e == hipSuccess) e = vp::launch_coefficients(pl, F, R, C, Q, st);
   if (e == hipSuccess)

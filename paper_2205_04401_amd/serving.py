@@ -1,14 +1,19 @@
-"""Request-serving workload: Poisson arrivals over several resident meshes.
+"""Request-serving workload: Poisson arrivals over resident meshes.
 
-Several seeded star meshes of different sizes stay resident on the device
-with their plans (near lists and FP64 correction rows); requests of 1-32
-right-hand sides arrive as a Poisson process and go through the library's
-continuous-batching server (vp_server_*).  Reports p50/p99 latency (arrival
-to observed completion) beside throughput in potential evaluations per
-second (targets x right-hand sides).
+Seeded star meshes of log-uniform sizes stay resident on the device with
+their plans (near lists, FP64 correction rows, the far sum's FMM tree);
+requests of 1-32 right-hand sides arrive as a Poisson process and go
+through the library's continuous-batching server (vp_server_*) under a
+stated HBM budget.  Reports p50/p99 latency (arrival to observed
+completion) beside throughput in potential evaluations per second (targets
+x right-hand sides).
 
-Only argument marshalling and clocks live here; all evaluation work runs in
-libvp.
+Each request's densities are a seeded combination of eight Gaussian-sum
+densities of its mesh, formed on the device when the request arrives (input
+generation: the densities of a request on a 200k-triangle mesh are ~1 GB,
+a thousand of them do not fit anywhere at once).  Only argument
+marshalling, input generation and clocks live here; all evaluation work
+runs in libvp.
 """
 
 import math
@@ -19,98 +24,133 @@ import numpy as np
 from . import vp
 from . import workloads as W
 
+N_BASIS = 8  # Gaussian-sum densities per mesh that requests combine
 
-def build_workload(ctx, n_meshes=4, tri_range=(1000, 8000), q=6, eps=1e-13, seed=40, n_requests=300,
-                   max_rhs=32, device="cuda:0", fmm_terms=0):
-    """Meshes (log-uniform triangle counts), plans (p = 4 or 6 per mesh) and
-    a request list (mesh, R, density tensor).  Returns a dict."""
+
+def build_workload(ctx, n_meshes=8, tri_range=(1000, 200000), q=8, eps=1e-13, seed=40, n_requests=1000,
+                   max_rhs=32, device="cuda:0", fmm_terms=32):
+    """Meshes (log-uniform triangle counts; p = 4 or 6 per request), their
+    plans, density bases on the device, and the request list (mesh, p, R,
+    combination seed).  Returns a dict."""
     import torch
     rng = np.random.default_rng(seed)
     sizes = np.round(np.exp(rng.uniform(math.log(tri_range[0]), math.log(tri_range[1]), n_meshes))).astype(int)
-    orders = rng.choice([4, 6], size=n_meshes)
     meshes = []
-    for k, (T, p) in enumerate(zip(sizes, orders)):
-        vq, tq = W.star_mesh(n_tri=int(T), n_boundary=max(200, int(T) // 10), seed=seed + 1 + k)
-        vt, tt = W.star_mesh(n_tri=int(T), n_boundary=max(200, int(T) // 10), seed=seed + 101 + k, staggered=True)
-        nodes = vp.ref_nodes(int(p))
-        tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    for k, T in enumerate(sizes):
+        nb = int(min(2000, max(200, math.sqrt(T) * 4.5)))
+        vq, tq = W.star_mesh(n_tri=int(T), n_boundary=nb, seed=seed + 1 + k)
+        vt, tt = W.star_mesh(n_tri=int(T), n_boundary=nb, seed=seed + 101 + k, staggered=True)
         mesh = ctx.mesh(vq, tq)
-        plan = ctx.plan(mesh, int(p), q, eps, tg, **({"fmm_terms": fmm_terms, "fmm_leaf": 64} if fmm_terms else {}))
-        meshes.append(dict(vq=vq, tq=tq, tg=tg, p=int(p), nodes=nodes, mesh=mesh, plan=plan))
+        entry = dict(vq=vq, tq=tq, mesh=mesh, plans={}, basis={}, tg={})
+        for p in (4, 6):
+            nodes = vp.ref_nodes(p)
+            tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+            cols = [W.sample_density(W.gaussian_sum(seed + 1000 * k + 10 * p + b, vq, tq), vq, tq, nodes)
+                    .reshape(-1) for b in range(N_BASIS)]
+            entry["basis"][p] = torch.from_numpy(np.ascontiguousarray(np.stack(cols, -1))).to(device)
+            entry["tg"][p] = tg
+            opts = {"fmm_terms": fmm_terms, "fmm_leaf": 64} if fmm_terms else {}
+            entry["plans"][p] = ctx.plan(mesh, p, q, eps, torch.from_numpy(tg).to(device), **opts)
+        meshes.append(entry)
     reqs = []
     for i in range(n_requests):
         k = int(rng.integers(n_meshes))
+        p = int(rng.choice([4, 6]))
         R = int(rng.integers(1, max_rhs + 1))
-        m = meshes[k]
-        cols = [W.sample_density(W.gaussian_sum(1000 + 97 * i + r, m["vq"], m["tq"]), m["vq"], m["tq"], m["nodes"])
-                for r in range(R)]
-        F = torch.from_numpy(np.ascontiguousarray(np.stack(cols, -1))).to(device)
-        out = torch.empty((m["plan"].n_tgt, R), dtype=torch.float64, device=device)
-        reqs.append(dict(mesh=k, R=R, F=F, out=out, evals=m["plan"].n_tgt * R))
-    return dict(meshes=meshes, reqs=reqs)
+        plan = meshes[k]["plans"][p]
+        reqs.append(dict(mesh=k, p=p, R=R, seed=10_000 + i, evals=plan.n_tgt * R))
+    return dict(meshes=meshes, reqs=reqs, sizes=[int(s) for s in sizes], q=q, eps=eps)
 
 
-def saturated(server, wl, mixed):
-    """All requests submitted at once; returns (seconds, evals/s)."""
+def request_inputs(wl, r, device="cuda:0"):
+    """The request's densities [n_tri, n_p, R] (a seeded combination of the
+    mesh's basis densities) and an output buffer, on the device."""
     import torch
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    tickets = [server.submit(wl["meshes"][r["mesh"]]["plan"], r["F"], r["out"], mixed=mixed) for r in wl["reqs"]]
-    for t in tickets:
-        server.wait(t)
-    dt = time.perf_counter() - t0
-    return dt, sum(r["evals"] for r in wl["reqs"]) / dt
+    m = wl["meshes"][r["mesh"]]
+    plan = m["plans"][r["p"]]
+    g = torch.Generator(device="cpu").manual_seed(r["seed"])
+    coef = torch.randn((N_BASIS, r["R"]), generator=g, dtype=torch.float64).to(device)
+    F = (m["basis"][r["p"]] @ coef).reshape(plan.n_tri, plan.n_p, r["R"]).contiguous()
+    out = torch.empty((plan.n_tgt, r["R"]), dtype=torch.float64, device=device)
+    return F, out
 
 
-def poisson_run(server, wl, mixed, rate, seed=49):
-    """Requests arrive at the given mean rate (per second); returns
-    per-request latencies (s) and the achieved evals/s."""
+def drive(server, wl, mixed, arrivals=None, max_outstanding=48):
+    """Submit every request (at its arrival time, or as soon as fewer than
+    max_outstanding are in flight when arrivals is None) and poll until all
+    are done.  Returns (latencies s, total s, evals/s)."""
     import torch
-    rng = np.random.default_rng(seed)
-    gaps = rng.exponential(1.0 / rate, len(wl["reqs"]))
-    arrivals = np.cumsum(gaps)
-    done_at = np.zeros(len(wl["reqs"]))
+    n = len(wl["reqs"])
+    done_at = np.zeros(n)
+    start_at = np.zeros(n)
     outstanding = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     i = 0
-    while i < len(wl["reqs"]) or outstanding:
+    while i < n or outstanding:
         now = time.perf_counter() - t0
-        while i < len(wl["reqs"]) and arrivals[i] <= now:
+        while i < n and (arrivals[i] <= now if arrivals is not None else len(outstanding) < max_outstanding):
             r = wl["reqs"][i]
-            outstanding[server.submit(wl["meshes"][r["mesh"]]["plan"], r["F"], r["out"], mixed=mixed)] = i
+            F, out = request_inputs(wl, r)
+            plan = wl["meshes"][r["mesh"]]["plans"][r["p"]]
+            start_at[i] = arrivals[i] if arrivals is not None else time.perf_counter() - t0
+            outstanding[server.submit(plan, F, out, mixed=mixed)] = (i, F, out)
             i += 1
+            now = time.perf_counter() - t0
         for t in list(outstanding):
             if server.poll(t):
-                done_at[outstanding.pop(t)] = time.perf_counter() - t0
-        if not outstanding and i < len(wl["reqs"]):
+                j = outstanding.pop(t)[0]
+                done_at[j] = time.perf_counter() - t0
+        if outstanding and (i >= n or arrivals is None or arrivals[i] > time.perf_counter() - t0):
+            time.sleep(2e-4)
+        elif not outstanding and i < n and arrivals is not None:
             time.sleep(max(0.0, min(1e-3, arrivals[i] - (time.perf_counter() - t0))))
     total = time.perf_counter() - t0
-    return done_at - arrivals, sum(r["evals"] for r in wl["reqs"]) / total
+    return done_at - start_at, total, sum(r["evals"] for r in wl["reqs"]) / total
 
 
-def run(ctx, n_requests=300, mixed=False, eps=None, n_slots=4, max_batch_rhs=32, load=0.8, **kw):
-    """Saturated throughput, then a Poisson run at `load` times the saturated
-    request rate.  Returns a dict of metrics."""
+def run(ctx, n_requests=1000, mixed=False, eps=None, n_slots=4, max_batch_rhs=64, load=0.8, budget_gb=200.0,
+        **kw):
+    """Saturated throughput (requests kept in flight), then a Poisson run at
+    `load` times the saturated request rate.  Returns a dict of metrics.
+    The context passed in is only used for its device; the run makes its own
+    context with the HBM budget."""
+    import torch
     eps = eps if eps is not None else (1e-8 if mixed else 1e-13)
-    wl = build_workload(ctx, n_requests=n_requests, eps=eps, **kw)
-    server = ctx.server(n_slots=n_slots, max_batch_rhs=max_batch_rhs)
-    saturated(server, wl, mixed)  # warm-up (workspaces, code objects)
-    dt_sat, evals_sat = saturated(server, wl, mixed)
+    budget = int(budget_gb * (1 << 30))
+    sctx = vp.Context(ctx.device, stream=torch.cuda.current_stream().cuda_stream, hbm_budget_bytes=budget)
+    t_build = time.perf_counter()
+    wl = build_workload(sctx, n_requests=n_requests, eps=eps, **kw)
+    t_build = time.perf_counter() - t_build
+    server = sctx.server(n_slots=n_slots, max_batch_rhs=max_batch_rhs)
+    warm = dict(wl, reqs=wl["reqs"][:64])
+    drive(server, warm, mixed)  # workspaces, code objects, FMM tables of 16+ densities
+    _, dt_sat, evals_sat = drive(server, wl, mixed)
     rate = load * len(wl["reqs"]) / dt_sat
-    lat, evals = poisson_run(server, wl, mixed, rate)
+    arrivals = np.cumsum(np.random.default_rng(49).exponential(1.0 / rate, len(wl["reqs"])))
+    lat, total, evals = drive(server, wl, mixed, arrivals=arrivals)
     st = server.stats()
+    in_use, cached = sctx.memory()
     server.close()
+    resident = sum(m["plans"][p].info()["bytes_resident"] for m in wl["meshes"] for p in (4, 6))
     for m in wl["meshes"]:
-        m["plan"].close()
+        for p in (4, 6):
+            m["plans"][p].close()
         m["mesh"].close()
+    sctx.close()
     return {
         "precision": "mixed" if mixed else "fp64",
-        "far": "fmm" if kw.get("fmm_terms") else "direct",
+        "far": "fmm" if kw.get("fmm_terms", 32) else "direct",
         "plan_eps": eps,
+        "q": wl["q"],
         "requests": len(wl["reqs"]),
-        "meshes": [int(m["plan"].n_tri) for m in wl["meshes"]],
-        "orders_p": [m["p"] for m in wl["meshes"]],
+        "mesh_triangles": wl["sizes"],
+        "rhs_per_request": "U{1..32}",
+        "setup_s": t_build,
+        "plans_resident_bytes": resident,
+        "hbm_budget_bytes": budget,
+        "in_use_bytes_at_end": in_use,
+        "cached_bytes_at_end": cached,
         "saturated_evals_per_s": evals_sat,
         "arrival_rate_per_s": rate,
         "evals_per_s": evals,
@@ -118,6 +158,8 @@ def run(ctx, n_requests=300, mixed=False, eps=None, n_slots=4, max_batch_rhs=32,
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "batches": st["batches"],
         "columns": st["columns"],
+        "budget_waits": st["budget_waits"],
+        "rejected": st["rejected"],
         "slots": n_slots,
         "max_batch_rhs": max_batch_rhs,
     }

@@ -182,6 +182,43 @@ def test_fmm_star_blocks_of_16_densities(vp_ctx):
     mesh.close()
 
 
+@pytest.mark.parametrize("R", [7, 23])
+def test_fmm_partial_blocks_of_densities(vp_ctx, R):
+    """A number of densities that does not fill the blocks of 16: the rest
+    (7 of 7, 7 of 23) runs as one block padded with zero columns in the FMM
+    passes and in the matrix-core correction apply (84k targets, 5250
+    clusters of 16); every column equals its one-density evaluation and the
+    direct far sum, and sampled targets the oracle."""
+    p, q, eps = 6, 6, 1e-13
+    vq, tq = W.star_mesh(n_tri=3000, n_boundary=300, seed=44)
+    vt, tt = W.star_mesh(n_tri=3000, n_boundary=300, seed=144, staggered=True)
+    nodes = rules.interp_nodes(p)
+    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    base = [W.sample_density(W.gaussian_sum(600 + r, vq, tq), vq, tq, nodes) for r in range(5)]
+    FR = np.ascontiguousarray(np.stack([(1.0 + 0.1 * r) * base[r % 5] - 0.2 * base[(r // 5) % 5] for r in range(R)],
+                                       -1))
+    mesh = vp_ctx.mesh(vq, tq)
+    fmm = vp_ctx.plan(mesh, p, q, eps, tg, fmm_terms=40, fmm_leaf=64)
+    direct = vp_ctx.plan(mesh, p, q, eps, tg)
+    uf = fmm.execute(FR, far_only=True)
+    ud = direct.execute(FR, far_only=True)
+    e = rel_linf(uf, ud)
+    u = fmm.execute(FR)
+    assert fmm.info()["cluster_entries"] > 0
+    cols = sorted({0, R // 2, R - 2, R - 1})
+    e1 = max(rel_linf(u[:, r], fmm.execute(np.ascontiguousarray(FR[:, :, r]))) for r in cols)
+    ud_all = direct.execute(FR)
+    e2 = rel_linf(u, ud_all)
+    sample = np.sort(np.random.default_rng(45 + R).choice(len(tg), 6, replace=False))
+    o = potential.Oracle(vq, tq, p, q, eps)
+    e3 = max(rel_linf(u[sample, r], o.evaluate(np.ascontiguousarray(FR[:, :, r]), tg[sample])) for r in (0, R - 1))
+    say(f"fmm star {R} densities: far rel vs direct", e, "vs one-density", e1, "vs direct path", e2, "vs oracle", e3)
+    assert e <= REL_FAR and e1 <= REL_FAR and e2 <= REL_FAR and e3 <= REL_E2E
+    fmm.close()
+    direct.close()
+    mesh.close()
+
+
 def test_fmm_curved_disk_closed_form(vp_ctx):
     """Unit density on a disk with circular boundary sides (curved
     triangles, blending map), far sum by the FMM: u = r^2/4 - 1/4 inside and
