@@ -702,7 +702,11 @@ hipError_t launch_far(const vp_plan* pl, const double* Q, int64_t R, const vp_fa
   if (NT == 0) return hipSuccess;
   // FMM plans: one partial sum per target, the FMM's workspace after it
   // (FP64 also in mixed precision)
-  if (pl->fmm_terms > 0) return launch_fmm(pl, Q, R, partial, partial + NT * R, st, n_launches);
+  if (pl->fmm_terms > 0) {
+    // mixed precision: the leaf passes of blocks of densities in FP32
+    if (Q32 && R >= kMinBlockCols) k_to_f32_ln2<<<blocks_for(NS * R), kBlock, 0, st>>>(Q, NS * R, Q32);
+    return launch_fmm(pl, Q, R, partial, partial + NT * R, st, n_launches, R >= kMinBlockCols ? Q32 : nullptr);
+  }
   const int64_t n_split = cfg.n_split;
   if (n_split < 1 || n_split > NS) return hipErrorInvalidValue;
   // chunk length: a multiple of 64 sources

@@ -510,13 +510,15 @@ __global__ __launch_bounds__(kBlock) void k_fmmb_p2m(const double* __restrict__ 
     const int64_t j = js + kq;
     const bool ok = j < j1;
     const int64_t jc = ok ? j : j0;
-    const double av = ok ? vsrc[jc * MP + 16 * t + r16] : 0.0;
+    // loads from clamped (in-bounds) indices, always made; invalid entries
+    // are multiplied by 0 rather than selected, so no load waits in a branch
+    const double av = vsrc[jc * MP + 16 * t + r16] * (ok ? 1.0 : 0.0);
     const double* q = Q + (int64_t)perm[jc] * R;
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
       const int64_t col = c0 + 16 * u + r16;
-      const double qv = q[col < R ? col : R - 1];
-      acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, (ok && col < R) ? qv : 0.0, acc[u], 0, 0, 0);
+      const double qv = q[col < R ? col : R - 1] * (col < R ? 1.0 : 0.0);
+      acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, qv, acc[u], 0, 0, 0);
     }
   }
 #pragma unroll
@@ -636,7 +638,8 @@ __global__ __launch_bounds__(kBlock) void k_fmmb_m2l(const double* __restrict__ 
       const double* A = m2l + (int64_t)(o * tiles + t) * (KP / 4) * 64 + lane;
       // (each A operand serves NB MFMA steps, which hide its load: batching
       // the loads of several steps here raised the registers and cost
-      // occupancy instead)
+      // occupancy instead; so did loading the next step's operands ahead,
+      // 23.6 -> 26.3 ms for 64 densities on the 100k star)
       for (int s4 = 0; s4 < KP / 4; ++s4) {
         const double av = A[s4 * 64];
         const double* x = X + (int64_t)(4 * s4 + kq) * C;
@@ -707,28 +710,182 @@ __global__ __launch_bounds__(kBlock) void k_fmmb_leaf(
     if (jy < 0 || jy >= n) continue;
     const int64_t row = (int64_t)jy * n;
     const int64_t j0 = sptr[row + max(ix - 1, 0)], j1 = sptr[row + min(ix + 1, n - 1) + 1];
+    if (j0 >= j1) continue;  // no sources (the pipeline's first loads need one)
+    // software pipeline: the positions and permutation entries of the step
+    // after next and the charges of the next step are loaded while this
+    // step's logarithms are evaluated (from clamped, in-bounds indices,
+    // always; invalid entries carry a factor 0)
+    int64_t cols[NB];
+    double cmask[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int64_t col = c0 + 16 * u + r16;
+      cols[u] = col < R ? col : R - 1;
+      cmask[u] = col < R ? 1.0 : 0.0;
+    }
+    auto idx = [&](int64_t js) { const int64_t j = js + kq; return j < j1 ? j : j0; };
+    int64_t jc = idx(j0), jn = idx(j0 + 4);
+    double2 sw = sxy_s[jc], swn = sxy_s[jn];
+    int32_t spn = sperm[jn];
+    double qv[NB];
+    {
+      const double* q = Q + (int64_t)sperm[jc] * R;
+      const double m = (j0 + kq < j1) ? 1.0 : 0.0;
+#pragma unroll
+      for (int u = 0; u < NB; ++u) qv[u] = q[cols[u]] * (m * cmask[u]);
+    }
     for (int64_t js = j0; js < j1; js += 4) {
-      const int64_t j = js + kq;
-      const bool ok = j < j1;
-      const int64_t jc = ok ? j : j0;
-      const double2 sw = sxy_s[jc];
+      const int64_t jnn = idx(js + 8);
+      const double2 swnn = sxy_s[jnn];
+      const int32_t spnn = sperm[jnn];
+      double qn[NB];
+      {
+        const double* q = Q + (int64_t)spn * R;
+        const double m = (js + 4 + kq < j1) ? 1.0 : 0.0;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) qn[u] = q[cols[u]] * (m * cmask[u]);
+      }
       const double ddx = x - sw.x, ddy = y - sw.y;
       const double r2 = fma(ddy, ddy, fma(ddx, ddx, kR2Bias));
       double e, rest;
       vp_log_parts(r2, tab, e, rest);
-      const double g = (ok && ta) ? fma(e, l2.x, fma(e, l2.y, rest)) : 0.0;
-      const double* q = Q + (int64_t)sperm[jc] * R;
+      const double g = ta ? fma(e, l2.x, fma(e, l2.y, rest)) : 0.0;
 #pragma unroll
-      for (int u = 0; u < NB; ++u) {
-        const int64_t col = c0 + 16 * u + r16;
-        const double qv = q[col < R ? col : R - 1];
-        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(g, (ok && col < R) ? qv : 0.0, acc[u], 0, 0, 0);
-      }
+      for (int u = 0; u < NB; ++u) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(g, qv[u], acc[u], 0, 0, 0);
+      sw = swn;
+      swn = swnn;
+      spn = spnn;
+#pragma unroll
+      for (int u = 0; u < NB; ++u) qv[u] = qn[u];
     }
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int64_t i = i0 + kq + 4 * v;
+    if (i < i1) {
+      const int64_t o = (int64_t)tperm[i] * R + c0 + r16;
+#pragma unroll
+      for (int u = 0; u < NB; ++u)
+        if (c0 + 16 * u + r16 < R) out[o + 16 * u] = acc[u][v];
+    }
+  }
+}
+
+// The leaf pass in mixed precision (VP_MIXED): the same two products on the
+// FP32 matrix cores (v_mfma_f32_16x16x4f32, twice the FP64 rate).  The
+// local expansion and the L2P rows are rounded to FP32; G = log2(r^2 +
+// 2^-100) of the FP32 difference (v_log_f32) and the charges Q32 = Q ln 2
+// in FP32 (the direct far sum's mixed form).  FP32 products are summed over
+// tiles of up to 256 sources and each tile joins an FP64 accumulator.
+// Element v of lane l of a result tile holds column l & 15 of target
+// 4 (l >> 4) + v.
+typedef float vp_f4 __attribute__((ext_vector_type(4)));
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_fmmb_leaf32(
+    const double* __restrict__ Lb, const double* __restrict__ wtgt, const int2* __restrict__ ttile, int64_t n_tiles,
+    const double2* __restrict__ sxy_s, const int32_t* __restrict__ sperm, const int64_t* __restrict__ sptr,
+    const int32_t* __restrict__ tperm, const int64_t* __restrict__ tptr, const double* __restrict__ xt,
+    const double* __restrict__ yt, int L, int KP, const float* __restrict__ Q32, int64_t R, int64_t c0,
+    double* __restrict__ out) {
+  constexpr int C = 16 * NB;
+  const int lane = (int)(threadIdx.x & 63), r16 = lane & 15, kq = lane >> 4;
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (w >= n_tiles) return;  // the whole wavefront
+  const int n = 1 << L;
+  const int2 tl = ttile[w];
+  const int64_t b = tl.x, i0 = tl.y, i1 = tptr[b + 1];
+  const int ix = (int)(b % n), iy = (int)(b / n);
+  // this lane's A-row target
+  const int64_t ia = i0 + r16;
+  const bool ta = ia < i1;
+  const int64_t tg = tperm[ta ? ia : i0];
+  const double x = xt[tg], y = yt[tg];
+  vp_d4 acc[NB];
+  vp_f4 tile[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    acc[u] = vp_d4{0.0, 0.0, 0.0, 0.0};
+    tile[u] = vp_f4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+  auto flush = [&]() {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] += (double)tile[u][v];
+      tile[u] = vp_f4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+  };
+  // local expansion
+  const double* Xl = Lb + b * KP * C + r16;
+  const double* Wt = wtgt + (ta ? ia : i0) * KP;
+  for (int s4 = 0; s4 < KP / 4; ++s4) {
+    const int k = 4 * s4 + kq;
+    const float av = ta ? (float)Wt[k] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+      tile[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, (float)Xl[k * C + 16 * u], tile[u], 0, 0, 0);
+  }
+  flush();
+  // adjacent boxes, row by row (consecutive boxes: one source range)
+  int in_tile = 0;
+  for (int dy = -1; dy <= 1; ++dy) {
+    const int jy = iy + dy;
+    if (jy < 0 || jy >= n) continue;
+    const int64_t row = (int64_t)jy * n;
+    const int64_t j0 = sptr[row + max(ix - 1, 0)], j1 = sptr[row + min(ix + 1, n - 1) + 1];
+    if (j0 >= j1) continue;  // no sources (the pipeline's first loads need one)
+    // software pipeline as in k_fmmb_leaf
+    int64_t cols[NB];
+    float cmask[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int64_t col = c0 + 16 * u + r16;
+      cols[u] = col < R ? col : R - 1;
+      cmask[u] = col < R ? 1.0f : 0.0f;
+    }
+    auto idx = [&](int64_t js) { const int64_t j = js + kq; return j < j1 ? j : j0; };
+    int64_t jc = idx(j0), jn = idx(j0 + 4);
+    double2 sw = sxy_s[jc], swn = sxy_s[jn];
+    int32_t spn = sperm[jn];
+    float qv[NB];
+    {
+      const float* q = Q32 + (int64_t)sperm[jc] * R;
+      const float m = (j0 + kq < j1) ? 1.0f : 0.0f;
+#pragma unroll
+      for (int u = 0; u < NB; ++u) qv[u] = q[cols[u]] * (m * cmask[u]);
+    }
+    for (int64_t js = j0; js < j1; js += 4) {
+      const int64_t jnn = idx(js + 8);
+      const double2 swnn = sxy_s[jnn];
+      const int32_t spnn = sperm[jnn];
+      float qn[NB];
+      {
+        const float* q = Q32 + (int64_t)spn * R;
+        const float m = (js + 4 + kq < j1) ? 1.0f : 0.0f;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) qn[u] = q[cols[u]] * (m * cmask[u]);
+      }
+      const float dx = (float)(x - sw.x), dy2 = (float)(y - sw.y);
+      const float g0 = __builtin_amdgcn_logf(fmaf(dy2, dy2, fmaf(dx, dx, kR2BiasF)));
+      const float g = ta ? g0 : 0.0f;
+#pragma unroll
+      for (int u = 0; u < NB; ++u) tile[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, qv[u], tile[u], 0, 0, 0);
+      sw = swn;
+      swn = swnn;
+      spn = spnn;
+#pragma unroll
+      for (int u = 0; u < NB; ++u) qv[u] = qn[u];
+      if (++in_tile == 64) {  // 256 sources
+        flush();
+        in_tile = 0;
+      }
+    }
+  }
+  flush();
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t i = i0 + 4 * kq + v;
     if (i < i1) {
       const int64_t o = (int64_t)tperm[i] * R + c0 + r16;
 #pragma unroll
@@ -1143,7 +1300,7 @@ hipError_t fmm_prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st) {
 // first n_tgt R doubles of `partial`); ws = the FMM workspace
 // (fmm_workspace_doubles).
 hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out, double* ws, hipStream_t st,
-                      int64_t* n_launches) {
+                      int64_t* n_launches, const float* Q32) {
   const int p = pl->fmm_terms, P1 = p + 1, L = pl->fmm_levels;
   const int64_t nbox = fmm_boxes(L);
   // 16-byte alignment of the complex arrays
@@ -1196,7 +1353,11 @@ hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out
                                                            Lb + pl->fmm_off[l - 1] * KP * C, l, p, KP, C,            \
                                                            pl->fmm_l2l, Lb + pl->fmm_off[l] * KP * C);               \
   }                                                                                                               \
-  if (pl->fmm_n_ttiles > 0)                                                                                       \
+  if (pl->fmm_n_ttiles > 0 && Q32)                                                                               \
+    k_fmmb_leaf32<NBV><<<(unsigned)((pl->fmm_n_ttiles * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(               \
+        Lb + pl->fmm_off[L] * KP * C, pl->fmm_wtgt, pl->fmm_ttile, pl->fmm_n_ttiles, pl->fmm_sxy, pl->fmm_src_perm,  \
+        pl->fmm_src_ptr, pl->fmm_tgt_perm, pl->fmm_tgt_ptr, pl->xt, pl->yt, L, KP, Q32, R, c0, out);                 \
+  else if (pl->fmm_n_ttiles > 0)                                                                                  \
     k_fmmb_leaf<NBV><<<(unsigned)((pl->fmm_n_ttiles * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(                 \
         Lb + pl->fmm_off[L] * KP * C, pl->fmm_wtgt, pl->fmm_ttile, pl->fmm_n_ttiles, pl->fmm_sxy, pl->fmm_src_perm,  \
         pl->fmm_src_ptr, pl->fmm_tgt_perm, pl->fmm_tgt_ptr, pl->xt, pl->yt, L, KP, pl->logtab, Q, R, c0, out)

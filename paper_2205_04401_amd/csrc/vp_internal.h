@@ -597,8 +597,10 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st);  // after sources a
 // plan, R >= kMinBlockCols and not built yet); call before launch_far (not
 // under graph capture)
 hipError_t fmm_prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st);
+// Q32 (FP32 copy of Q times ln 2, or null): the leaf passes of blocks of
+// densities in mixed precision
 hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out, double* ws, hipStream_t st,
-                      int64_t* n_launches);
+                      int64_t* n_launches, const float* Q32 = nullptr);
 void set_last_error(const char* msg);
 // Device time of a stage on the context's stream (when profiling is on):
 // events around the stage's launches, folded into the totals on read.

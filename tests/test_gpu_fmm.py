@@ -219,6 +219,33 @@ def test_fmm_partial_blocks_of_densities(vp_ctx, R):
     mesh.close()
 
 
+@pytest.mark.parametrize("terms", [16, 32])
+def test_fmm_mixed_precision_blocks(vp_ctx, terms):
+    """Mixed precision on an FMM plan (the leaf passes of blocks of
+    densities on the FP32 matrix cores, a plan at eps = 1e-8, 16 or 32
+    expansion terms): 23 densities (a block of 16 and a padded block of 7)
+    within 1e-6 of the FP64 eps = 1e-13 oracle at sampled targets."""
+    p, q = 6, 6
+    vq, tq = W.star_mesh(n_tri=3000, n_boundary=300, seed=46)
+    vt, tt = W.star_mesh(n_tri=3000, n_boundary=300, seed=146, staggered=True)
+    nodes = rules.interp_nodes(p)
+    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    R = 23
+    base = [W.sample_density(W.gaussian_sum(700 + r, vq, tq), vq, tq, nodes) for r in range(5)]
+    FR = np.ascontiguousarray(np.stack([(1.0 + 0.1 * r) * base[r % 5] - 0.2 * base[(r // 5) % 5] for r in range(R)],
+                                       -1))
+    mesh = vp_ctx.mesh(vq, tq)
+    plan = vp_ctx.plan(mesh, p, q, 1e-8, tg, fmm_terms=terms, fmm_leaf=64)
+    u = plan.execute(FR, mixed=True)
+    sample = np.sort(np.random.default_rng(47).choice(len(tg), 8, replace=False))
+    o = potential.Oracle(vq, tq, p, q, 1e-13)
+    e = max(rel_linf(u[sample, r], o.evaluate(np.ascontiguousarray(FR[:, :, r]), tg[sample])) for r in (0, 9, 16, 22))
+    say(f"fmm mixed, {terms} terms, {R} densities: rel vs FP64 oracle", e)
+    assert e <= REL_MIXED
+    plan.close()
+    mesh.close()
+
+
 def test_fmm_curved_disk_closed_form(vp_ctx):
     """Unit density on a disk with circular boundary sides (curved
     triangles, blending map), far sum by the FMM: u = r^2/4 - 1/4 inside and
