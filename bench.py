@@ -578,11 +578,9 @@ def run(args, pool, n_workers):
         result["small_case"] = small_case(ctx)
     if not args.no_serving:
         from paper_2205_04401_amd import serving
-        result["serving"] = []
-        for mixed in (False, True):
-            s = serving.run(ctx, n_requests=args.serving_requests, mixed=mixed, budget_gb=args.serving_budget_gb,
-                            q=args.serving_q)
-            result["serving"].append(s)
+        result["serving"] = serving.run(ctx, n_requests=args.serving_requests, budget_gb=args.serving_budget_gb,
+                                        q=args.serving_q)
+        for s in result["serving"]:
             say(json.dumps({"serving": s}))
     ctx.close()
     result["gpu_sections_s"] = time.perf_counter() - t_start
@@ -627,7 +625,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-small", action="store_true", help="skip the unit-square latency section")
     ap.add_argument("--serving-requests", type=int, default=1000)
-    ap.add_argument("--serving-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serving-budget-gb", type=float, default=128.0)
     ap.add_argument("--serving-q", type=int, default=8)
     ap.add_argument("--copy-probe", action="store_true", help="only run a 512 MiB device copy (counter calibration)")
     args = ap.parse_args()

@@ -184,12 +184,13 @@ hipError_t build_clusters(vp_plan* pl, hipStream_t st) {
 hipError_t prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st) {
   hipError_t e = fmm_prepare_blocks(pl, R, st);
   if (e != hipSuccess || R < kMinBlockCols || pl->cl_tried) return e;
-  pl->cl_tried = true;
-  // at most 68 bytes per pair (an entry per pair, its 16 pair slots and triangle)
+  // at most 68 bytes per pair (an entry per pair, its 16 pair slots and
+  // triangle); over the budget: not now, a later evaluation tries again
   if (!ctx_fits(pl->ctx, 68 * (uint64_t)pl->n_pairs)) {
     pl->n_cl = 0;
     return hipSuccess;
   }
+  pl->cl_tried = true;
   e = build_clusters(pl, st);
   if (e == hipErrorOutOfMemory) {
     (void)hipGetLastError();
@@ -198,6 +199,11 @@ hipError_t prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st) {
     return hipSuccess;
   }
   return e;
+}
+
+bool blocks_ready(const vp_plan* pl, int64_t R) {
+  if (R < kMinBlockCols) return true;
+  return (pl->fmm_terms <= 0 || pl->fmm_vsrc) && pl->cl_tried;
 }
 
 #define VP_DISPATCH_P(p, CALL)                    \

@@ -578,6 +578,9 @@ hipError_t prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st);
 // remainder (padded with zero columns): a padded block costs about as much
 // as two single-density passes of the FMM or of the correction apply.
 constexpr int64_t kMinBlockCols = 2;
+// True if the tables prepare_blocks builds for R densities exist (false
+// while the context's budget keeps them out).
+bool blocks_ready(const vp_plan* pl, int64_t R);
 // U columns [r0, min(R, r0 + 16 nt)) on the matrix cores (nt = 1, 2 or 4)
 hipError_t launch_corr_mfma(const vp_plan* pl, const double* partial, int64_t n_split, const double* C, int64_t R,
                             int64_t r0, int nt, bool far_only, double* U, hipStream_t st);
@@ -594,8 +597,9 @@ int64_t fmm_boxes(int levels);
 int64_t fmm_workspace_doubles(const vp_plan* pl, int64_t R);
 hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st);  // after sources and targets; plan memory
 // tables of the passes of blocks of 16 densities (no-op unless an FMM
-// plan, R >= kMinBlockCols and not built yet); call before launch_far (not
-// under graph capture)
+// plan, R >= kMinBlockCols and not built yet; not built when they do not fit
+// the context's budget, the passes then take one density at a time); call
+// before launch_far (not under graph capture)
 hipError_t fmm_prepare_blocks(vp_plan* pl, int64_t R, hipStream_t st);
 // Q32 (FP32 copy of Q times ln 2, or null): the leaf passes of blocks of
 // densities in mixed precision

@@ -200,6 +200,22 @@ vp_status progress(vp_server* s) {
         width += r.R;
       }
     }
+    // the plan's tables for blocks of densities first (they stay with the
+    // plan); when the budget keeps them out, the idle slots' workspaces make
+    // room, else the batch waits for a running one (without them it would
+    // run one density at a time)
+    vp_plan* hp = h.plan;
+    hipError_t pe = vp::prepare_blocks(hp, width, s->ctx->stream);
+    if (pe == hipSuccess && !vp::blocks_ready(hp, width)) {
+      for (size_t i = 0; i < s->slots.size(); ++i)
+        if (!s->slots[i].busy) slot_release(s, s->slots[i]);
+      pe = vp::prepare_blocks(hp, width, s->ctx->stream);
+      if (pe == hipSuccess && !vp::blocks_ready(hp, width) && any_busy) {
+        s->n_budget_waits++;
+        break;
+      }
+    }
+    if (pe != hipSuccess) return serve_fail(VP_EDEVICE, "vp serve: tables: %s", hipGetErrorString(pe));
     vp_status st = slot_reserve(s, s->slots[free_slot], h.plan, width, h.prec == VP_MIXED);
     if (st == VP_ENOMEM) {
       // the other idle slots' workspaces make room (they grow again when

@@ -27,11 +27,9 @@ from . import workloads as W
 N_BASIS = 8  # Gaussian-sum densities per mesh that requests combine
 
 
-def build_workload(ctx, n_meshes=8, tri_range=(1000, 200000), q=8, eps=1e-13, seed=40, n_requests=1000,
-                   max_rhs=32, device="cuda:0", fmm_terms=32):
-    """Meshes (log-uniform triangle counts; p = 4 or 6 per request), their
-    plans, density bases on the device, and the request list (mesh, p, R,
-    combination seed).  Returns a dict."""
+def build_meshes(ctx, n_meshes=8, tri_range=(1000, 200000), seed=40, device="cuda:0"):
+    """Meshes (log-uniform triangle counts), their staggered target nodes for
+    p = 4 and 6, and density bases on the device."""
     import torch
     rng = np.random.default_rng(seed)
     sizes = np.round(np.exp(rng.uniform(math.log(tri_range[0]), math.log(tri_range[1]), n_meshes))).astype(int)
@@ -40,26 +38,42 @@ def build_workload(ctx, n_meshes=8, tri_range=(1000, 200000), q=8, eps=1e-13, se
         nb = int(min(2000, max(200, math.sqrt(T) * 4.5)))
         vq, tq = W.star_mesh(n_tri=int(T), n_boundary=nb, seed=seed + 1 + k)
         vt, tt = W.star_mesh(n_tri=int(T), n_boundary=nb, seed=seed + 101 + k, staggered=True)
-        mesh = ctx.mesh(vq, tq)
-        entry = dict(vq=vq, tq=tq, mesh=mesh, plans={}, basis={}, tg={})
+        entry = dict(vq=vq, tq=tq, mesh=ctx.mesh(vq, tq), plans={}, basis={}, tg={})
         for p in (4, 6):
             nodes = vp.ref_nodes(p)
-            tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+            entry["tg"][p] = torch.from_numpy(W.node_positions(vt, tt, nodes).reshape(-1, 2)).to(device)
             cols = [W.sample_density(W.gaussian_sum(seed + 1000 * k + 10 * p + b, vq, tq), vq, tq, nodes)
                     .reshape(-1) for b in range(N_BASIS)]
             entry["basis"][p] = torch.from_numpy(np.ascontiguousarray(np.stack(cols, -1))).to(device)
-            entry["tg"][p] = tg
-            opts = {"fmm_terms": fmm_terms, "fmm_leaf": 64} if fmm_terms else {}
-            entry["plans"][p] = ctx.plan(mesh, p, q, eps, torch.from_numpy(tg).to(device), **opts)
         meshes.append(entry)
+    return meshes, [int(s) for s in sizes]
+
+
+def build_plans(ctx, meshes, q, eps, fmm_terms):
+    for m in meshes:
+        for p in (4, 6):
+            opts = {"fmm_terms": fmm_terms, "fmm_leaf": 64} if fmm_terms else {}
+            m["plans"][p] = ctx.plan(m["mesh"], p, q, eps, m["tg"][p], **opts)
+
+
+def close_plans(meshes):
+    for m in meshes:
+        for p in list(m["plans"]):
+            m["plans"].pop(p).close()
+
+
+def requests(meshes, n_requests=1000, max_rhs=32, seed=49):
+    """The request list: mesh, order p (4 or 6), R ~ U{1..max_rhs}, and the
+    seed of its combination of the mesh's basis densities."""
+    rng = np.random.default_rng(seed)
     reqs = []
     for i in range(n_requests):
-        k = int(rng.integers(n_meshes))
+        k = int(rng.integers(len(meshes)))
         p = int(rng.choice([4, 6]))
         R = int(rng.integers(1, max_rhs + 1))
-        plan = meshes[k]["plans"][p]
-        reqs.append(dict(mesh=k, p=p, R=R, seed=10_000 + i, evals=plan.n_tgt * R))
-    return dict(meshes=meshes, reqs=reqs, sizes=[int(s) for s in sizes], q=q, eps=eps)
+        n_tgt = meshes[k]["tg"][p].shape[0]
+        reqs.append(dict(mesh=k, p=p, R=R, seed=10_000 + i, evals=n_tgt * R))
+    return reqs
 
 
 def request_inputs(wl, r, device="cuda:0"):
@@ -75,7 +89,7 @@ def request_inputs(wl, r, device="cuda:0"):
     return F, out
 
 
-def drive(server, wl, mixed, arrivals=None, max_outstanding=48):
+def drive(server, wl, mixed, arrivals=None, max_outstanding=24):
     """Submit every request (at its arrival time, or as soon as fewer than
     max_outstanding are in flight when arrivals is None) and poll until all
     are done.  Returns (latencies s, total s, evals/s)."""
@@ -109,57 +123,52 @@ def drive(server, wl, mixed, arrivals=None, max_outstanding=48):
     return done_at - start_at, total, sum(r["evals"] for r in wl["reqs"]) / total
 
 
-def run(ctx, n_requests=1000, mixed=False, eps=None, n_slots=4, max_batch_rhs=64, load=0.8, budget_gb=200.0,
-        **kw):
-    """Saturated throughput (requests kept in flight), then a Poisson run at
-    `load` times the saturated request rate.  Returns a dict of metrics.
-    The context passed in is only used for its device; the run makes its own
-    context with the HBM budget."""
+def run(ctx, n_requests=1000, modes=("fp64", "mixed"), n_slots=4, max_batch_rhs=32, load=0.8, budget_gb=128.0,
+        q=8, n_meshes=8, tri_range=(1000, 200000), seed=40):
+    """For each mode, on the same meshes and request list: plans, saturated
+    throughput (requests kept in flight), then a Poisson run at `load` times
+    the saturated request rate.  Modes: "fp64" (plans at eps = 1e-13, FMM
+    with 32 terms, FP64 evaluation) and "mixed" (plans at eps = 1e-8, FMM
+    with 16 terms, VP_MIXED evaluation: the FMM's leaf passes on the FP32
+    matrix cores).  The run makes its own context with the HBM budget on
+    ctx's device.  Returns one dict of metrics per mode."""
     import torch
-    eps = eps if eps is not None else (1e-8 if mixed else 1e-13)
     budget = int(budget_gb * (1 << 30))
     sctx = vp.Context(ctx.device, stream=torch.cuda.current_stream().cuda_stream, hbm_budget_bytes=budget)
-    t_build = time.perf_counter()
-    wl = build_workload(sctx, n_requests=n_requests, eps=eps, **kw)
-    t_build = time.perf_counter() - t_build
-    server = sctx.server(n_slots=n_slots, max_batch_rhs=max_batch_rhs)
-    warm = dict(wl, reqs=wl["reqs"][:64])
-    drive(server, warm, mixed)  # workspaces, code objects, FMM tables of 16+ densities
-    _, dt_sat, evals_sat = drive(server, wl, mixed)
-    rate = load * len(wl["reqs"]) / dt_sat
-    arrivals = np.cumsum(np.random.default_rng(49).exponential(1.0 / rate, len(wl["reqs"])))
-    lat, total, evals = drive(server, wl, mixed, arrivals=arrivals)
-    st = server.stats()
-    in_use, cached = sctx.memory()
-    server.close()
-    resident = sum(m["plans"][p].info()["bytes_resident"] for m in wl["meshes"] for p in (4, 6))
-    for m in wl["meshes"]:
-        for p in (4, 6):
-            m["plans"][p].close()
+    t0 = time.perf_counter()
+    meshes, sizes = build_meshes(sctx, n_meshes=n_meshes, tri_range=tri_range, seed=seed)
+    t_meshes = time.perf_counter() - t0
+    reqs = requests(meshes, n_requests=n_requests)
+    out = []
+    for mode in modes:
+        mixed = mode == "mixed"
+        eps, terms = (1e-8, 16) if mixed else (1e-13, 32)
+        t0 = time.perf_counter()
+        build_plans(sctx, meshes, q, eps, terms)
+        t_plans = time.perf_counter() - t0
+        wl = dict(meshes=meshes, reqs=reqs)
+        server = sctx.server(n_slots=n_slots, max_batch_rhs=max_batch_rhs)
+        drive(server, dict(meshes=meshes, reqs=reqs[:64]), mixed)  # workspaces, code objects, FMM tables
+        _, dt_sat, evals_sat = drive(server, wl, mixed)
+        rate = load * len(reqs) / dt_sat
+        arrivals = np.cumsum(np.random.default_rng(49).exponential(1.0 / rate, len(reqs)))
+        lat, total, evals = drive(server, wl, mixed, arrivals=arrivals)
+        st = server.stats()
+        in_use, cached = sctx.memory()
+        server.close()
+        resident = sum(m["plans"][p].info()["bytes_resident"] for m in meshes for p in (4, 6))
+        close_plans(meshes)
+        out.append({
+            "precision": mode, "far": "fmm", "fmm_terms": terms, "plan_eps": eps, "q": q,
+            "requests": len(reqs), "mesh_triangles": sizes, "rhs_per_request": "U{1..32}",
+            "setup_s": {"meshes": t_meshes, "plans": t_plans}, "plans_resident_bytes": resident,
+            "hbm_budget_bytes": budget, "in_use_bytes_at_end": in_use, "cached_bytes_at_end": cached,
+            "saturated_evals_per_s": evals_sat, "arrival_rate_per_s": rate, "evals_per_s": evals,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "batches": st["batches"], "columns": st["columns"], "budget_waits": st["budget_waits"],
+            "rejected": st["rejected"], "slots": n_slots, "max_batch_rhs": max_batch_rhs,
+        })
+    for m in meshes:
         m["mesh"].close()
     sctx.close()
-    return {
-        "precision": "mixed" if mixed else "fp64",
-        "far": "fmm" if kw.get("fmm_terms", 32) else "direct",
-        "plan_eps": eps,
-        "q": wl["q"],
-        "requests": len(wl["reqs"]),
-        "mesh_triangles": wl["sizes"],
-        "rhs_per_request": "U{1..32}",
-        "setup_s": t_build,
-        "plans_resident_bytes": resident,
-        "hbm_budget_bytes": budget,
-        "in_use_bytes_at_end": in_use,
-        "cached_bytes_at_end": cached,
-        "saturated_evals_per_s": evals_sat,
-        "arrival_rate_per_s": rate,
-        "evals_per_s": evals,
-        "p50_ms": float(np.percentile(lat, 50) * 1e3),
-        "p99_ms": float(np.percentile(lat, 99) * 1e3),
-        "batches": st["batches"],
-        "columns": st["columns"],
-        "budget_waits": st["budget_waits"],
-        "rejected": st["rejected"],
-        "slots": n_slots,
-        "max_batch_rhs": max_batch_rhs,
-    }
+    return out
