@@ -239,6 +239,12 @@ vp_status vp_plan_pairs(const vp_plan* plan, int64_t* row_ptr_out, int32_t* tri_
  * vp_plan_pairs: row = (A - B) / 2pi (Sec. 3.6 subtract-and-add). */
 vp_status vp_plan_rows(const vp_plan* plan, double* rows_out);
 
+/* Host copy of the rows of pairs [first_pair, first_pair + count) only,
+ * [count][n_p] doubles, same order and values as vp_plan_rows (for
+ * inspecting a few targets' rows of a plan whose full row array is too large
+ * to copy).  VP_EINVAL when the range leaves [0, n_pairs). */
+vp_status vp_plan_rows_range(const vp_plan* plan, int64_t first_pair, int64_t count, double* rows_out);
+
 /* Evaluate the potential for n_rhs >= 1 densities at once.
  *   density [n_tri][n_p][n_rhs] doubles (values at the interpolation nodes,
  *           right-hand side fastest), u_out [n_tgt][n_rhs] doubles.

@@ -792,6 +792,20 @@ vp_status vp_plan_rows(const vp_plan* pl, double* rows) {
   return VP_OK;
 }
 
+vp_status vp_plan_rows_range(const vp_plan* pl, int64_t first_pair, int64_t count, double* rows) {
+  if (!pl || (!rows && count)) return fail(VP_EINVAL, "vp_plan_rows_range: NULL argument");
+  if (first_pair < 0 || count < 0 || first_pair > pl->n_pairs || count > pl->n_pairs - first_pair)
+    return fail(VP_EINVAL, "vp_plan_rows_range: pairs [%lld, %lld) outside [0, %lld)", (long long)first_pair,
+                (long long)(first_pair + count), (long long)pl->n_pairs);
+  if (!count) return VP_OK;
+  VP_HIP(hipSetDevice(pl->ctx->device), "hipSetDevice");
+  VP_HIP(hipMemcpyAsync(rows, pl->rows + (size_t)first_pair * pl->n_p, sizeof(double) * count * pl->n_p,
+                        hipMemcpyDeviceToHost, pl->ctx->stream),
+         "hipMemcpy");
+  VP_HIP(hipStreamSynchronize(pl->ctx->stream), "hipStreamSynchronize");
+  return VP_OK;
+}
+
 vp_status vp_plan_sources(const vp_plan* pl, double* xy) {
   if (!pl || !xy) return fail(VP_EINVAL, "vp_plan_sources: NULL argument");
   VP_HIP(hipSetDevice(pl->ctx->device), "hipSetDevice");

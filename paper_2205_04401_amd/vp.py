@@ -28,6 +28,7 @@ STATUS_NAMES = {0: "VP_OK", 1: "VP_EINVAL", 2: "VP_ENOMEM", 3: "VP_EDEVICE", 4: 
 # every symbol include/vp.h declares
 EXPORTS = ["vp_ctx_create", "vp_ctx_destroy", "vp_last_error", "vp_ref_nodes", "vp_ref_rule", "vp_mesh_create",
            "vp_mesh_destroy", "vp_mesh_set_curved_sides", "vp_mesh_map_points", "vp_plan_create", "vp_plan_info", "vp_plan_pairs", "vp_plan_rows",
+           "vp_plan_rows_range",
            "vp_execute", "vp_execute_noalloc", "vp_coefficients", "vp_plan_sources", "vp_plan_destroy", "vp_sync",
            "vp_ctx_profile", "vp_ctx_timings", "vp_server_create", "vp_server_destroy", "vp_submit",
            "vp_poll", "vp_wait", "vp_server_stats", "vp_interp_create", "vp_interp_destroy", "vp_interp_locate",
@@ -101,6 +102,7 @@ def load(path=LIB_PATH):
         "vp_plan_info": [P, ctypes.POINTER(PlanStats)],
         "vp_plan_pairs": [P, P, P, P],
         "vp_plan_rows": [P, P],
+        "vp_plan_rows_range": [P, I64, I64, P],
         "vp_execute": [P, I64, P, P, ctypes.c_int, ctypes.c_uint32],
         "vp_execute_noalloc": [P, I64, P, P, ctypes.c_int, ctypes.c_uint32],
         "vp_coefficients": [P, I64, P, P, P, ctypes.c_uint32],
@@ -447,6 +449,12 @@ class Plan:
         st = self.info()
         out = np.empty((st["n_pairs"], st["n_p"]))
         _check(load().vp_plan_rows(self.h, _ptr(out)))
+        return out
+
+    def rows_range(self, first, count):
+        """Rows of pairs [first, first + count): [count, n_p]."""
+        out = np.empty((count, self.n_p))
+        _check(load().vp_plan_rows_range(self.h, int(first), int(count), _ptr(out)))
         return out
 
     def sources(self):

@@ -246,6 +246,48 @@ def test_fmm_mixed_precision_blocks(vp_ctx, terms):
     mesh.close()
 
 
+def test_fmm_star_100k_all_targets_64_densities(vp_ctx):
+    """The batched configuration at full size: the 100k-triangle star, all
+    2.8M staggered targets, 64 densities, q = 8, far sum by the FMM (32
+    terms, leaves of 64) in passes of 16 densities; FP64 and mixed (a plan
+    at eps = 1e-8 with 16 terms, FP32 leaf passes).  16 sampled targets
+    (first, last, 14 seeded) x 8 columns against the oracle, and two columns
+    against their one-density evaluation."""
+    import torch
+    p, q, eps, R = 6, 8, 1e-13, 64
+    vq, tq = W.star_mesh(n_tri=100000, n_boundary=2000, seed=30)
+    vt, tt = W.star_mesh(n_tri=100000, n_boundary=2000, seed=31, staggered=True)
+    nodes = rules.interp_nodes(p)
+    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    F = np.ascontiguousarray(np.stack([W.sample_density(W.gaussian_sum(1000 + r, vq, tq), vq, tq, nodes)
+                                       for r in range(R)], -1))
+    say("star 100k:", len(tq), "triangles", len(tg), "targets", R, "densities")
+    mesh = vp_ctx.mesh(vq, tq)
+    Fd = torch.from_numpy(F).cuda()
+    cols = [0, 9, 17, 31, 40, 52, 58, 63]
+    rest = np.random.default_rng(36).choice(np.arange(1, len(tg) - 1), 14, replace=False)
+    sample = np.sort(np.concatenate([[0, len(tg) - 1], rest]))
+    sample_d = torch.from_numpy(sample).cuda()
+    got = {}
+    for mixed, eps_plan, terms in ((False, eps, 32), (True, 1e-8, 16)):
+        plan = vp_ctx.plan(mesh, p, q, eps_plan, tg, fmm_terms=terms, fmm_leaf=64)
+        u = plan.execute(Fd, mixed=mixed)
+        got[mixed] = u[sample_d].cpu().numpy()
+        if not mixed:
+            for r in (5, 63):
+                one = plan.execute(Fd[:, :, r:r + 1].contiguous())
+                assert rel_linf(got[mixed][:, r], one[sample_d].cpu().numpy()) <= REL_FAR
+        say("plan", "mixed" if mixed else "fp64", {k: plan.info()[k] for k in ("n_pairs", "n_src", "ms_rows")})
+        del u
+        plan.close()
+    ref = potential.Oracle(vq, tq, p, q, eps).evaluate(np.ascontiguousarray(F[:, :, cols]), tg[sample])
+    e = rel_linf(got[False][:, cols], ref)
+    e_mix = rel_linf(got[True][:, cols], ref)
+    say("star 100k, 64 densities, FMM: rel vs oracle", e, "mixed", e_mix)
+    assert e <= REL_E2E and e_mix <= REL_MIXED
+    mesh.close()
+
+
 def test_fmm_curved_disk_closed_form(vp_ctx):
     """Unit density on a disk with circular boundary sides (curved
     triangles, blending map), far sum by the FMM: u = r^2/4 - 1/4 inside and

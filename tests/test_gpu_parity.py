@@ -82,10 +82,11 @@ def margin(o, x, t, kind_gpu):
     return min(m)
 
 
-def compare_pairs(plan, o, targets, sample=None):
-    """Pair lists of the plan vs the oracle's classification.  Returns the
-    number of band flips; fails on any other difference."""
-    rp, tri, kind = plan.pairs()
+def compare_pairs(plan, o, targets, sample=None, pairs=None):
+    """Pair lists of the plan (or `pairs`, its copy from plan.pairs()) vs the
+    oracle's classification.  Returns the number of band flips; fails on any
+    other difference."""
+    rp, tri, kind = plan.pairs() if pairs is None else pairs
     idx = range(len(targets)) if sample is None else sample
     flips = 0
     for i in idx:
@@ -97,6 +98,71 @@ def compare_pairs(plan, o, targets, sample=None):
             assert margin(o, x, t, k) < BAND, (i, t, k, margin(o, x, t, k))
             flips += 1
     return flips
+
+
+def special_targets(vq, tq, seed, n_vert=8, n_edge=8, n_sliver=4):
+    """Targets where the near-field decisions are hardest: interior mesh
+    vertices (self pairs with every triangle around them), points on shared
+    edges (self pairs with both sides), and, on the n_sliver triangles of
+    largest aspect ratio (longest edge squared over area), the centroid, a
+    point just inside each edge's midpoint and a point just outside."""
+    rng = np.random.default_rng(seed)
+    tq = np.asarray(tq)
+    e = np.sort(np.concatenate([tq[:, [0, 1]], tq[:, [1, 2]], tq[:, [2, 0]]]), axis=1)
+    edges, count = np.unique(e, axis=0, return_counts=True)
+    shared = edges[count == 2]
+    interior = np.unique(shared.ravel())
+    on_boundary = np.unique(edges[count == 1].ravel())
+    interior = np.setdiff1d(interior, on_boundary)
+    pts = [vq[rng.choice(interior, n_vert, replace=False)]]
+    pick = shared[rng.choice(len(shared), n_edge, replace=False)]
+    s_ = rng.uniform(0.1, 0.9, n_edge)[:, None]
+    pts.append(vq[pick[:, 0]] + s_ * (vq[pick[:, 1]] - vq[pick[:, 0]]))
+    a, b, c = vq[tq[:, 0]], vq[tq[:, 1]], vq[tq[:, 2]]
+    area = 0.5 * np.abs((b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0]))
+    longest = np.maximum.reduce([np.sum((b - a) ** 2, 1), np.sum((c - b) ** 2, 1), np.sum((a - c) ** 2, 1)])
+    for t in np.argsort(longest / area)[-n_sliver:]:
+        P = vq[tq[t]]
+        cen = P.mean(0)
+        pts.append(cen[None])
+        for k in range(3):
+            mid = 0.5 * (P[k] + P[(k + 1) % 3])
+            pts.append(np.stack([mid + 1e-3 * (cen - mid), mid - 1e-3 * (cen - mid)]))
+    return np.concatenate(pts)
+
+
+def sample_with_special(tg, vq, tq, n_random, seed, extra=()):
+    """Targets with special ones appended (a ragged tail), and the sorted
+    indices of n_random seeded targets plus every appended one."""
+    sp = [special_targets(vq, tq, seed)] + [np.asarray(x, dtype=np.float64).reshape(-1, 2) for x in extra]
+    sp = np.concatenate(sp)
+    rng = np.random.default_rng(seed)
+    sample = np.concatenate([rng.choice(len(tg), n_random, replace=False), len(tg) + np.arange(len(sp))])
+    return np.ascontiguousarray(np.concatenate([tg, sp])), np.sort(sample)
+
+
+def compare_rows(plan, o, tg, sample, rp, tri, kind, area, tol):
+    """Every row of the sampled targets (copied pair range by pair range)
+    against the oracle's row, relative to the triangle's area; pairs whose
+    class differs (a decision on its boundary, checked by compare_pairs)
+    are skipped.  Returns (worst, rows compared per kind)."""
+    worst, seen = 0.0, {0: 0, 1: 0}
+    for i in sample:
+        ref = {t: (k, o.row(t, tg[i], k)) for t, k in o.classify_target(tg[i])}
+        rows = plan.rows_range(rp[i], rp[i + 1] - rp[i])
+        for j, p_ in enumerate(range(rp[i], rp[i + 1])):
+            t = int(tri[p_])
+            if t not in ref or ref[t][0] != int(kind[p_]):
+                continue
+            seen[ref[t][0]] += 1
+            worst = max(worst, np.abs(rows[j] - ref[t][1]).max() / area[t])
+    assert worst <= tol, worst
+    return worst, seen
+
+
+def tri_area(vq, tq):
+    e1, e2 = vq[tq[:, 1]] - vq[tq[:, 0]], vq[tq[:, 2]] - vq[tq[:, 0]]
+    return 0.5 * np.abs(e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0])
 
 
 # ---------------------------------------------------------------------------
@@ -804,13 +870,16 @@ def test_star_mixed_loose_eps_plan(vp_ctx):
 
 @pytest.mark.parametrize("q", [8, 4])
 def test_star_full_size_sampled(vp_ctx, q):
+    """The 20k-triangle star with its 559k staggered targets plus special
+    ones (vertices, shared edges, slivers): pair lists, every row, the far
+    sum and the potential at 64 seeded and all special targets."""
     p, eps = 6, 1e-13
     vq, tq = W.star_mesh(n_tri=20000, seed=20)
     vt, tt = W.star_mesh(n_tri=20000, seed=21, staggered=True)
     nodes = rules.interp_nodes(p)
-    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    tg, sample = sample_with_special(W.node_positions(vt, tt, nodes).reshape(-1, 2), vq, tq, 64, 123 + q)
     F = W.sample_density(W.gaussian_sum(22, vq, tq), vq, tq, nodes)
-    say("star: plan", len(tq), "triangles", len(tg), "targets")
+    say("star: plan", len(tq), "triangles", len(tg), "targets,", len(sample), "sampled")
     mesh = vp_ctx.mesh(vq, tq)
     plan = vp_ctx.plan(mesh, p, q, eps, tg)
     u = plan.execute(F)
@@ -821,16 +890,18 @@ def test_star_full_size_sampled(vp_ctx, q):
     # every near pair integrates at least one leaf, every self pair one panel
     assert info["near_subtri"] >= info["n_pairs"] - info["n_self"]
     assert info["self_panels"] >= info["n_self"]
-    rng = np.random.default_rng(123 + q)
-    sample = np.sort(rng.choice(len(tg), 24 if q >= 8 else 12, replace=False))
     o = potential.Oracle(vq, tq, p, q, eps)
-    compare_pairs(plan, o, tg, sample)
+    rp, tri, kind = plan.pairs()
+    flips = compare_pairs(plan, o, tg, sample, (rp, tri, kind))
+    worst, seen = compare_rows(plan, o, tg, sample, rp, tri, kind, tri_area(vq, tq), 10 * eps)
     ref_u, ref_far, _, _ = o.evaluate(F, tg[sample], return_parts=True)
     e_far = np.abs(u_far[sample] - ref_far).max() / np.abs(ref_far).max()
     e_all = np.abs(u[sample] - ref_u).max() / np.abs(ref_u).max()
     u_mix = plan.execute(F, mixed=True)
     e_mix = np.abs(u_mix[sample] - ref_u).max() / np.abs(ref_u).max()
-    say("star sampled rel far", e_far, "end-to-end", e_all, "mixed", e_mix)
+    say("star sampled: band flips", flips, "rows compared", seen, "worst / area", worst, "rel far", e_far,
+        "end-to-end", e_all, "mixed", e_mix)
+    assert seen[0] > 0 and seen[1] > 0
     assert e_far <= REL_FAR
     assert e_all <= REL_E2E
     assert e_mix <= REL_MIXED
@@ -1020,37 +1091,49 @@ def test_serving_poisson_run_reports_latency(vp_ctx):
 # ---------------------------------------------------------------------------
 
 def test_graded_l_shape_full_size_sampled(vp_ctx):
+    """The graded L-shape at full size (250k triangles, 3.75M targets) plus
+    special targets: interior vertices, shared edges, slivers, the
+    re-entrant corner itself, points approaching it inside the domain and
+    along its two boundary edges, and one in the removed quadrant.  Pair
+    lists and every row of the 64 seeded, 8 nearest-corner and special
+    targets against the oracle, then the potential (FP64 and mixed)."""
     p, q, eps = 4, 4, 1e-13
     vq, tq = W.l_shape_graded(n_tri=250000, seed=50)
     vt, tt = W.l_shape_graded(n_tri=250000, seed=51, staggered=True)
     nodes = rules.interp_nodes(p)
-    tg = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    tg0 = W.node_positions(vt, tt, nodes).reshape(-1, 2)
+    d = np.array([1e-8, 1e-5, 1e-3])[:, None]
+    corner = np.concatenate([[[0.0, 0.0]], d * [-1.0, -1.0], d * [-1.0, 1.0], d * [1.0, -1.0],
+                             d * [0.0, 1.0], d * [1.0, 0.0], [[1e-3, 1e-3]]])
+    near_corner = tg0[np.argsort(np.hypot(tg0[:, 0], tg0[:, 1]))[:8]]
+    tg, sample = sample_with_special(tg0, vq, tq, 64, 55, extra=(corner, near_corner))
     F = W.sample_density(W.l_shape_density(52), vq, tq, nodes)
-    say("L-shape:", len(tq), "triangles", len(tg), "targets")
+    say("L-shape:", len(tq), "triangles", len(tg), "targets,", len(sample), "sampled")
     mesh = vp_ctx.mesh(vq, tq)
     plan = vp_ctx.plan(mesh, p, q, eps, tg)
     info = plan.info()
-    say("L-shape plan", {k: info[k] for k in ("n_pairs", "n_self", "near_subtri", "ms_classify", "ms_rows",
-                                              "capped_leaves", "bytes_resident")})
+    say("L-shape plan", {k: info[k] for k in ("n_pairs", "n_self", "tab_pairs", "near_subtri", "ms_classify",
+                                              "ms_rows", "capped_leaves", "bytes_resident")})
     assert info["near_subtri"] >= info["n_pairs"] - info["n_self"]
     u = plan.execute(F)
     u_mix = plan.execute(F, mixed=True)
-    rng = np.random.default_rng(55)
-    sample = np.sort(np.concatenate([rng.choice(len(tg), 6, replace=False),
-                                     np.argsort(np.hypot(tg[:, 0], tg[:, 1]))[:2]]))  # two next to the corner
     o = potential.Oracle(vq, tq, p, q, eps)
-    compare_pairs(plan, o, tg, sample)
+    rp, tri, kind = plan.pairs()
+    flips = compare_pairs(plan, o, tg, sample, (rp, tri, kind))
+    worst, seen = compare_rows(plan, o, tg, sample, rp, tri, kind, tri_area(vq, tq), 10 * eps)
     ref = o.evaluate(F, tg[sample])
     e = np.abs(u[sample] - ref).max() / np.abs(ref).max()
     e_mix = np.abs(u_mix[sample] - ref).max() / np.abs(ref).max()
-    say("L-shape sampled rel", e, "mixed", e_mix)
+    say("L-shape sampled: band flips", flips, "rows compared", seen, "worst / area", worst, "rel", e,
+        "mixed", e_mix)
+    assert seen[0] > 0 and seen[1] > 0
     assert e <= REL_E2E and e_mix <= REL_MIXED
     plan.close()
     mesh.close()
 
 
-@pytest.mark.parametrize("q", [8, 12])
-def test_batched_star_100k_64_densities(vp_ctx, q):
+@pytest.mark.parametrize("q,n_sample", [(8, 64), (12, 16)])
+def test_batched_star_100k_64_densities(vp_ctx, q, n_sample):
     import torch
     p, eps, R = 6, 1e-13, 64
     vq, tq = W.star_mesh(n_tri=100000, n_boundary=2000, seed=30)
@@ -1068,9 +1151,12 @@ def test_batched_star_100k_64_densities(vp_ctx, q):
     # every column equals its own single-density evaluation (batch invariance)
     for r in (0, 17, 63):
         assert rel_linf(u[:, r], plan.execute(np.ascontiguousarray(F[:, :, r]))) <= 1e-14
-    # oracle on a few targets and columns
-    cols = [0, 31, 63]
-    sample = np.array([5, 700, 2047])
+    # oracle on n_sample targets (the first, the last and seeded ones) and 8
+    # columns (the oracle's extended-precision far sum over the 6.4M / 14.4M
+    # sources takes about a second per target)
+    cols = [0, 9, 17, 31, 40, 52, 58, 63]
+    rest = np.random.default_rng(34 + q).choice(np.arange(1, len(tg) - 1), n_sample - 2, replace=False)
+    sample = np.sort(np.concatenate([[0, len(tg) - 1], rest]))
     ref = potential.Oracle(vq, tq, p, q, eps).evaluate(np.ascontiguousarray(F[:, :, cols]), tg[sample])
     e = rel_linf(u[sample][:, cols], ref)
     e_mix = rel_linf(u_mix[sample][:, cols], ref)
