@@ -398,6 +398,9 @@ struct TriView {
 };
 
 // 0 = self, 1 = near, 2 = far
+// kCurved: the mesh has curved triangles (the straight-only instances carry
+// none of their code)
+template <bool kCurved>
 __device__ __forceinline__ int classify(const TriView& tv, int32_t t, double x, double y, double tau) {
   const double Ax = tv.ax[t], Ay = tv.ay[t], Bx = tv.bx[t], By = tv.by[t], Cx = tv.cx[t], Cy = tv.cy[t];
   const double D = tv.det[t];
@@ -406,8 +409,8 @@ __device__ __forceinline__ int classify(const TriView& tv, int32_t t, double x, 
   const double xi1 = (d0 * e2y - d1 * e2x) / D;
   const double xi2 = (e1x * d1 - e1y * d0) / D;
   const double lmin = fmin(fmin(1.0 - xi1 - xi2, xi1), xi2);
-  const int cc = tv.cv.of ? tv.cv.of[t] : -1;
-  if (cc >= 0) {
+  const int cc = (kCurved && tv.cv.of) ? tv.cv.of[t] : -1;
+  if (kCurved && cc >= 0) {
     // curved element: self if rho^{-1}(x) is in the closed simplex; a point
     // of the chord triangle outside the element is near
     const double* bx4 = tv.cv.box + 4 * cc;
@@ -444,6 +447,7 @@ __device__ __forceinline__ int64_t cell_of(const Grid g, double x, double y) {
   return (int64_t)j * g.nx + i;
 }
 
+template <bool kCurved>
 __global__ void k_pair_count(const double* __restrict__ xt, const double* __restrict__ yt, int64_t n_tgt, Grid g,
                              const int64_t* __restrict__ cptr, const int32_t* __restrict__ ctri, TriView tv,
                              double tau, int32_t* cnt) {
@@ -452,32 +456,57 @@ __global__ void k_pair_count(const double* __restrict__ xt, const double* __rest
   const double x = xt[i], y = yt[i];
   const int64_t c = cell_of(g, x, y);
   int n = 0;
-  for (int64_t k = cptr[c]; k < cptr[c + 1]; ++k) n += (classify(tv, ctri[k], x, y, tau) < 2);
+  for (int64_t k = cptr[c]; k < cptr[c + 1]; ++k) n += (classify<kCurved>(tv, ctri[k], x, y, tau) < 2);
   cnt[i] = n;
 }
 
-__global__ void k_pair_fill(const double* __restrict__ xt, const double* __restrict__ yt, int64_t n_tgt, Grid g,
-                            const int64_t* __restrict__ cptr, const int32_t* __restrict__ ctri, TriView tv,
-                            double tau, const int64_t* __restrict__ row_ptr, int32_t* pair_tri,
-                            int32_t* pair_tgt, uint8_t* pair_kind, int32_t* self_cnt) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_tgt) return;
-  const double x = xt[i], y = yt[i];
-  const int64_t c = cell_of(g, x, y);
-  int64_t o = row_ptr[i];
-  int ns = 0;
-  for (int64_t k = cptr[c]; k < cptr[c + 1]; ++k) {
-    const int32_t t = ctri[k];
-    const int kind = classify(tv, t, x, y, tau);
-    if (kind < 2) {
-      pair_tri[o] = t;
-      pair_tgt[o] = (int32_t)i;
-      pair_kind[o] = (uint8_t)kind;
-      ns += (kind == 0);
-      ++o;
+// Fill pass, one wavefront per target: the lanes classify 64 of the cell's
+// triangles at a time and write the pairs among them at consecutive places
+// (ballot and prefix count), so that the stores of a wavefront are
+// contiguous; the cell lists are ascending, so are the target's pairs.  A
+// target that finds more pairs than the count pass did sets *bad and writes
+// nothing beyond its range.
+constexpr int kFillWaves = 4;
+
+template <bool kCurved>
+__global__ __launch_bounds__(kFillWaves * 64) void k_pair_fill(
+    const double* __restrict__ xt, const double* __restrict__ yt, int64_t n_tgt, Grid g,
+    const int64_t* __restrict__ cptr, const int32_t* __restrict__ ctri, TriView tv, double tau,
+    const int64_t* __restrict__ row_ptr, int32_t* pair_tri, int32_t* pair_tgt, uint8_t* pair_kind,
+    int32_t* self_cnt, int* bad) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int64_t i = (int64_t)blockIdx.x * kFillWaves + (threadIdx.x >> 6); i < n_tgt;
+       i += (int64_t)gridDim.x * kFillWaves) {
+    const double x = xt[i], y = yt[i];
+    const int64_t c = cell_of(g, x, y);
+    const int64_t k0 = cptr[c], k1 = cptr[c + 1];
+    const int64_t end = row_ptr[i + 1];
+    int64_t o = row_ptr[i];
+    int ns = 0;
+    for (int64_t kb = k0; kb < k1; kb += 64) {
+      const int64_t k = kb + lane;
+      int32_t t = 0;
+      int kind = 2;
+      if (k < k1) {
+        t = ctri[k];
+        kind = classify<kCurved>(tv, t, x, y, tau);
+      }
+      const uint64_t m = __ballot(kind < 2);
+      ns += __popcll(__ballot(kind == 0));
+      const int64_t pos = o + __popcll(m & lt);
+      if (kind < 2 && pos < end) {
+        pair_tri[pos] = t;
+        pair_tgt[pos] = (int32_t)i;
+        pair_kind[pos] = (uint8_t)kind;
+      }
+      o += __popcll(m);
+    }
+    if (lane == 0) {
+      self_cnt[i] = ns;
+      if (o != end) atomicOr(bad, 1);
     }
   }
-  self_cnt[i] = ns;
 }
 
 // ---------------------------------------------------------------------------
@@ -831,7 +860,11 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
   }
   TriView tv{m->ax, m->ay, m->bx, m->by, m->cx, m->cy, m->det, thr, T, pl->opts.near_model == VP_NEAR_BALL ? 1 : 0,
              pl->opts.ball_factor, m->curves()};
-  k_pair_count<<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, tv, pl->opts.tau, pcnt);
+  const bool curved = tv.cv.of != nullptr;
+  if (curved)
+    k_pair_count<true><<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, tv, pl->opts.tau, pcnt);
+  else
+    k_pair_count<false><<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, tv, pl->opts.tau, pcnt);
   if ((e = exclusive_scan_i32(pcnt, pl->row_ptr, NT, stmp, st)) != hipSuccess) {
     cleanup();
     return e;
@@ -854,22 +887,33 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
     cleanup();
     return e;
   }
-  k_pair_fill<<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, tv, pl->opts.tau, pl->row_ptr,
-                                                 pl->pair_tri, pl->pair_tgt, pl->pair_kind, scnt);
+  // d_sum: self pairs; d_sum[1]: a target whose fill disagreed with its count
   unsigned long long* d_sum = (unsigned long long*)part;
-  if ((e = hipMemsetAsync(d_sum, 0, sizeof(unsigned long long), st)) != hipSuccess) {
+  if ((e = hipMemsetAsync(d_sum, 0, 2 * sizeof(unsigned long long), st)) != hipSuccess) {
     cleanup();
     return e;
   }
+  if (NT > 0) {
+    const int64_t nb = std::min<int64_t>((NT + kFillWaves - 1) / kFillWaves, (int64_t)1 << 22);
+    auto fill = curved ? k_pair_fill<true> : k_pair_fill<false>;
+    fill<<<(unsigned)nb, kFillWaves * 64, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, tv, pl->opts.tau, pl->row_ptr,
+                                                   pl->pair_tri, pl->pair_tgt, pl->pair_kind, scnt,
+                                                   (int*)(d_sum + 1));
+  }
   k_count_sum<<<blocks_for(NT), kBlock, 0, st>>>(scnt, NT, d_sum);
-  unsigned long long ns = 0;
+  unsigned long long ns[2] = {0, 0};
   if ((e = hipGetLastError()) != hipSuccess ||
-      (e = hipMemcpyAsync(&ns, d_sum, sizeof(ns), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(ns, d_sum, sizeof(ns), hipMemcpyDeviceToHost, st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess) {
     cleanup();
     return e;
   }
-  pl->n_self = (int64_t)ns;
+  if (ns[1]) {
+    err = "near lists: the fill pass disagrees with the count pass";
+    cleanup();
+    return hipErrorUnknown;
+  }
+  pl->n_self = (int64_t)ns[0];
   cleanup();
   return hipSuccess;
 }

@@ -614,6 +614,177 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Deeper near pairs (subdivision two or more levels deep) of straight
+// triangles with the ellipse test.
+//
+// The same subdivision as k_rows, walked level by level with the lanes
+// testing a level's sub-triangles, but the leaves of every level are only
+// collected (in LDS) during the walk and integrated afterwards in one flat
+// loop whose items are the far rule's own nodes (B, subtracted) and the
+// (leaf, near-rule node) pairs (A): each lane takes every 64th item and adds
+// its weighted logarithm times the Koornwinder basis at the item's reference
+// point.  Against k_rows' integration after each level this keeps the lanes
+// full over the whole pair (a deep pair has about 12 leaves of 49 nodes,
+// spread over 2 to 9 levels), drops a barrier per level, and leaves out the
+// self-pair, curved and depth-first code, so that fewer registers and less
+// LDS are live and more wavefronts fit on a SIMD.  The near rule's rho0
+// and edge lengths per triangle come from k_near_root.  A pair with a level
+// wider than kDeepLv sub-triangles or more than kDeepLeaf leaves (a target
+// very close to a sliver's edge) is appended to an overflow list instead;
+// k_rows computes those afterwards.
+// ---------------------------------------------------------------------------
+constexpr int kDeepLv = 64;     // sub-triangles of one level (one per lane)
+constexpr int kDeepLeaf = 128;  // leaves of one pair
+
+template <int P>
+__global__ __launch_bounds__(64) void k_rows_deep(RowsArgs a, const double* __restrict__ nr, int64_t n_tri,
+                                                  uint32_t* __restrict__ ovf, uint32_t* __restrict__ n_ovf) {
+  constexpr int NP = (P + 1) * (P + 2) / 2;
+  __shared__ double lv[2][kDeepLv * 3];
+  __shared__ double leaf[kDeepLeaf * 3];
+  __shared__ double2 tab[kLogTab + 1];
+  // near-rule x, y, w [nn]; far-rule x, y [nf]
+  extern __shared__ double rule_tabs[];
+  double* const s_nx = rule_tabs;
+  double* const s_ny = s_nx + a.nn;
+  double* const s_nw = s_ny + a.nn;
+  double* const s_fx = s_nw + a.nn;
+  double* const s_fy = s_fx + a.nf;
+  const int lane = threadIdx.x;
+  for (int i = lane; i <= kLogTab; i += kWave) tab[i] = a.logtab[i];
+  for (int i = lane; i < a.nn; i += kWave) {
+    s_nx[i] = a.near_x[i];
+    s_ny[i] = a.near_y[i];
+    s_nw[i] = a.near_w[i];
+  }
+  for (int i = lane; i < a.nf; i += kWave) {
+    s_fx[i] = a.far_x[i];
+    s_fy[i] = a.far_y[i];
+  }
+  __syncthreads();
+  const float inv_nn = 1.0f / (float)a.nn;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int64_t tot_leaves = 0, tot_capped = 0;
+  for (int64_t wi = blockIdx.x; wi < a.n_list; wi += gridDim.x) {
+    const int64_t pr = (int64_t)a.list[wi];
+    const int32_t t = a.pair_tri[pr];
+    const int32_t it = a.pair_tgt[pr];
+    const double x = a.xt[it], y = a.yt[it];
+    const double Ax = a.ax[t], Ay = a.ay[t];
+    const double e1x = a.bx[t] - Ax, e1y = a.by[t] - Ay, e2x = a.cx[t] - Ax, e2y = a.cy[t] - Ay;
+    const double D = a.det[t];
+    double rho0[3], ell0[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      rho0[e] = nr[e * n_tri + t];
+      ell0[e] = nr[(3 + e) * n_tri + t];
+    }
+    // ---- the walk: leaves of every level into leaf[] ----
+    double* cur = lv[0];
+    double* nxt = lv[1];
+    if (lane == 0) {
+      cur[0] = 0.0;
+      cur[1] = 0.0;
+      cur[2] = 1.0;
+    }
+    __syncthreads();
+    int n_cur = 1, n_leaf = 0, n_capped = 0;
+    bool over = false;
+    for (int level = 0; n_cur > 0; ++level) {
+      double thr[3];
+      near_level_thr(rho0, ell0, level, a.inv_near_order, thr);
+      const bool valid = lane < n_cur;
+      double sa = 0.0, sb = 0.0, ss = 0.0;
+      bool split = false;
+      if (valid) {
+        sa = cur[3 * lane];
+        sb = cur[3 * lane + 1];
+        ss = cur[3 * lane + 2];
+        split = (level < a.depth_cap) && near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, sa, sb, ss, thr);
+      }
+      const bool is_leaf = valid && !split;
+      const uint64_t msplit = __ballot(split);
+      const uint64_t mleaf = __ballot(is_leaf);
+      const int n_next = 4 * __popcll(msplit);
+      if (n_next > kDeepLv || n_leaf + __popcll(mleaf) > kDeepLeaf) {
+        over = true;
+        break;
+      }
+      if (split) {
+        const double h = 0.5 * ss;
+        double* c = nxt + 12 * __popcll(msplit & lt);
+        c[0] = sa;          c[1] = sb;          c[2] = h;
+        c[3] = sa + h;      c[4] = sb;          c[5] = h;
+        c[6] = sa;          c[7] = sb + h;      c[8] = h;
+        c[9] = sa + h;      c[10] = sb + h;     c[11] = -h;
+      }
+      if (is_leaf) {
+        double* c = leaf + 3 * (n_leaf + __popcll(mleaf & lt));
+        c[0] = sa;
+        c[1] = sb;
+        c[2] = ss;
+      }
+      if (level >= a.depth_cap) n_capped += __popcll(mleaf);
+      n_leaf += __popcll(mleaf);
+      n_cur = n_next;
+      __syncthreads();
+      double* sw = cur;
+      cur = nxt;
+      nxt = sw;
+    }
+    if (over) {
+      if (lane == 0) ovf[atomicAdd(n_ovf, 1u)] = (uint32_t)pr;
+      __syncthreads();
+      continue;
+    }
+    // ---- the integration: far-rule nodes (B) and leaf nodes (A) ----
+    double acc[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) acc[k] = 0.0;
+    const int items = a.nf + n_leaf * a.nn;
+    const double2* sxy = a.sxy + (int64_t)t * a.nf;
+    const double* swj = a.swj + (int64_t)t * a.nf;
+    for (int item = lane; item < items; item += kWave) {
+      double xi1, xi2, r2, wf;
+      if (item < a.nf) {
+        // the far sums' sources and expression, so that a pair at r = 0 cancels
+        const double2 sj = sxy[item];
+        const double dx = x - sj.x, dy = y - sj.y;
+        r2 = fma(dy, dy, fma(dx, dx, kR2Bias));
+        wf = -swj[item];
+        xi1 = s_fx[item];
+        xi2 = s_fy[item];
+      } else {
+        const int q = item - a.nf;
+        const int l = (int)(((float)q + 0.5f) * inv_nn);
+        const int nd = q - l * a.nn;
+        const double sa = leaf[3 * l], sb = leaf[3 * l + 1], ss = leaf[3 * l + 2];
+        xi1 = sa + ss * s_nx[nd];
+        xi2 = sb + ss * s_ny[nd];
+        const double dx = x - (Ax + xi1 * e1x + xi2 * e2x), dy = y - (Ay + xi1 * e1y + xi2 * e2y);
+        r2 = dx * dx + dy * dy;
+        wf = s_nw[nd] * ss * ss * D;
+      }
+      koornwinder_acc<P>(xi1, xi2, 0.5 * vp_log(r2, tab) * wf, acc);
+    }
+    double* out = a.rows + (size_t)pr * NP;
+    int base = 0, len = NP;
+    ReduceScatter<NP, 32>::run(acc, lane, base, len);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      if (i < len) out[base + i] = acc[i] * kInv2Pi;
+    tot_leaves += n_leaf;
+    tot_capped += n_capped;
+    __syncthreads();
+  }
+  if (lane == 0) {
+    unsigned long long* st = (unsigned long long*)(a.stats + (int64_t)(blockIdx.x & (kRowStatSlots - 1)) * kRowStatStride);
+    if (tot_leaves) atomicAdd(st + 0, (unsigned long long)tot_leaves);
+    if (tot_capped) atomicAdd(st + 2, (unsigned long long)tot_capped);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Shallow near pairs on the matrix cores.
 //
 // A near pair whose subdivision stops at the triangle itself (depth class 0)
@@ -1001,11 +1172,28 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
     return dim3((unsigned)std::min<int64_t>((k + kPairsPerGroup - 1) / kPairsPerGroup, 1 << 25));
   };
   if (n2 > 0) {
+    uint32_t* ovf = nullptr;
+    uint32_t* n_ovf = nullptr;
+    if ((e = tmp.alloc((void**)&ovf, sizeof(uint32_t) * n2)) != hipSuccess ||
+        (e = tmp.alloc((void**)&n_ovf, sizeof(uint32_t))) != hipSuccess ||
+        (e = hipMemsetAsync(n_ovf, 0, sizeof(uint32_t), st)) != hipSuccess)
+      return e;
     a.list = list + n0 + n1;
     a.n_list = n2;
     StageTimer tm(pl->ctx, VP_STAGE_ROWS_NEAR);
-    k_rows<P, false, 1><<<groups(n2), 64, lds, st>>>(a);
-    tm.stop(1);
+    const size_t lds_deep = sizeof(double) * (3 * (size_t)nn + 2 * (size_t)nf);
+    k_rows_deep<P><<<groups(n2), 64, lds_deep, st>>>(a, nr, pl->n_tri, ovf, n_ovf);
+    uint32_t h_ovf = 0;
+    if ((e = hipGetLastError()) != hipSuccess ||
+        (e = hipMemcpyAsync(&h_ovf, n_ovf, sizeof(uint32_t), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+      return e;
+    if (h_ovf > 0) {
+      a.list = ovf;
+      a.n_list = h_ovf;
+      k_rows<P, false, 1><<<groups(h_ovf), 64, lds, st>>>(a);
+    }
+    tm.stop(h_ovf > 0 ? 2 : 1);
   }
   if (n3 > 0) {
     a.list = list + n0 + n1 + n2;
