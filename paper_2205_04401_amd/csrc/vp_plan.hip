@@ -876,7 +876,9 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
     return e;
   }
   pl->n_pairs = np;
-  if (pl->ctx->budget && pl->ctx->in_use + pl->bytes + (size_t)np * (9 + 8 * pl->n_p) > pl->ctx->budget) {
+  // the plan's blocks so far are in in_use already; the pairs and rows must
+  // fit beside them (cached blocks are given back for them if needed)
+  if (!ctx_fits(pl->ctx, (size_t)np * (9 + 8 * (size_t)pl->n_p))) {
     err = "plan exceeds the context's HBM budget";
     cleanup();
     return hipErrorOutOfMemory;

@@ -636,9 +636,17 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
 constexpr int kDeepLv = 64;     // sub-triangles of one level (one per lane)
 constexpr int kDeepLeaf = 128;  // leaves of one pair
 
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <int P>
 __global__ __launch_bounds__(64) void k_rows_deep(RowsArgs a, const double* __restrict__ nr, int64_t n_tri,
-                                                  uint32_t* __restrict__ ovf, uint32_t* __restrict__ n_ovf) {
+                                                  const uint8_t* __restrict__ cls, uint32_t* __restrict__ ovf,
+                                                  uint32_t* __restrict__ n_ovf) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
   __shared__ double lv[2][kDeepLv * 3];
   __shared__ double leaf[kDeepLeaf * 3];
@@ -669,6 +677,7 @@ __global__ __launch_bounds__(64) void k_rows_deep(RowsArgs a, const double* __re
     const int64_t pr = (int64_t)a.list[wi];
     const int32_t t = a.pair_tri[pr];
     const int32_t it = a.pair_tgt[pr];
+    const int split1 = cls[pr] >> 4;  // level-1 children that split (class pass)
     const double x = a.xt[it], y = a.yt[it];
     const double Ax = a.ax[t], Ay = a.ay[t];
     const double e1x = a.bx[t] - Ax, e1y = a.by[t] - Ay, e2x = a.cx[t] - Ax, e2y = a.cy[t] - Ay;
@@ -679,20 +688,41 @@ __global__ __launch_bounds__(64) void k_rows_deep(RowsArgs a, const double* __re
       rho0[e] = nr[e * n_tri + t];
       ell0[e] = nr[(3 + e) * n_tri + t];
     }
+    // the ellipse thresholds of every level at once: lane L holds level L's
+    // (the depth cap is at most 60)
+    double thr_l[3];
+    near_level_thr(rho0, ell0, lane, a.inv_near_order, thr_l);
     // ---- the walk: leaves of every level into leaf[] ----
+    // Levels 0 and 1 are known from the class pass: the triangle splits, and
+    // of its children (a, s) = ((0,0), 1/2), ((1/2,0), 1/2), ((0,1/2), 1/2),
+    // ((1/2,1/2), -1/2) those in split1 split again, the others are leaves.
     double* cur = lv[0];
     double* nxt = lv[1];
-    if (lane == 0) {
-      cur[0] = 0.0;
-      cur[1] = 0.0;
-      cur[2] = 1.0;
+    const uint64_t m1 = (uint64_t)split1;
+    if (lane < 4) {
+      const double sa = (lane == 1 || lane == 3) ? 0.5 : 0.0, sb = (lane >= 2) ? 0.5 : 0.0;
+      const double ss = (lane == 3) ? -0.5 : 0.5;
+      if ((split1 >> lane) & 1) {
+        const double h = 0.5 * ss;
+        double* c = cur + 12 * __popcll(m1 & lt);
+        c[0] = sa;          c[1] = sb;          c[2] = h;
+        c[3] = sa + h;      c[4] = sb;          c[5] = h;
+        c[6] = sa;          c[7] = sb + h;      c[8] = h;
+        c[9] = sa + h;      c[10] = sb + h;     c[11] = -h;
+      } else {
+        double* c = leaf + 3 * __popcll(~m1 & 15ull & lt);
+        c[0] = sa;
+        c[1] = sb;
+        c[2] = ss;
+      }
     }
     __syncthreads();
-    int n_cur = 1, n_leaf = 0, n_capped = 0;
+    int n_cur = 4 * __popcll(m1), n_leaf = 4 - __popcll(m1), n_capped = 0;
     bool over = false;
-    for (int level = 0; n_cur > 0; ++level) {
+    for (int level = 2; n_cur > 0; ++level) {
       double thr[3];
-      near_level_thr(rho0, ell0, level, a.inv_near_order, thr);
+#pragma unroll
+      for (int e = 0; e < 3; ++e) thr[e] = readlane_f64(thr_l[e], level);
       const bool valid = lane < n_cur;
       double sa = 0.0, sb = 0.0, ss = 0.0;
       bool split = false;
@@ -820,7 +850,8 @@ struct ClassArgs {
   uint32_t* list;       // [n_pairs] pair indices sorted by class (scatter pass)
 };
 
-// depth class of near pair pr: the tests of k_rows' first two levels
+// depth class of near pair pr: the tests of k_rows' first two levels; for
+// class 2 the bits 4..7 hold which of the four level-1 children split
 __device__ __forceinline__ int pair_class(const ClassArgs& a, int64_t pr) {
   if (a.pair_kind[pr] != 1) return 3;
   const int32_t t = a.pair_tri[pr];
@@ -838,12 +869,11 @@ __device__ __forceinline__ int pair_class(const ClassArgs& a, int64_t pr) {
   if (!(0 < a.depth_cap && near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.0, 0.0, 1.0, thr))) return 0;
   if (!(1 < a.depth_cap)) return 1;
   near_level_thr(rho0, ell0, 1, a.inv_near_order, thr);
-  if (near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.0, 0.0, 0.5, thr) ||
-      near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.5, 0.0, 0.5, thr) ||
-      near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.0, 0.5, 0.5, thr) ||
-      near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.5, 0.5, -0.5, thr))
-    return 2;
-  return 1;
+  const int mask = (near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.0, 0.0, 0.5, thr) ? 1 : 0) |
+                   (near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.5, 0.0, 0.5, thr) ? 2 : 0) |
+                   (near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.0, 0.5, 0.5, thr) ? 4 : 0) |
+                   (near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.5, 0.5, -0.5, thr) ? 8 : 0);
+  return mask ? 2 | (mask << 4) : 1;
 }
 
 // near-rule rho0 and edge lengths of every triangle: nr[e][T] = rho0_e,
@@ -878,7 +908,7 @@ __global__ __launch_bounds__(kClsThreads) void k_pair_class(ClassArgs a) {
     if (pr < a.n_pairs) {
       const int c = pair_class(a, pr);
       a.cls[pr] = (uint8_t)c;
-      my[c] += 1;
+      my[c & 3] += 1;
     }
   }
 #pragma unroll
@@ -902,7 +932,7 @@ __global__ __launch_bounds__(kClsThreads) void k_pair_scatter(ClassArgs a) {
   for (int c = 0; c < 4; ++c) off[c] = a.boff[c * a.n_blk + blockIdx.x];
   for (int i = 0; i < kClsPer; ++i) {
     const int64_t pr = base + i * kClsThreads + threadIdx.x;
-    const int c = pr < a.n_pairs ? (int)a.cls[pr] : -1;
+    const int c = pr < a.n_pairs ? (int)(a.cls[pr] & 3) : -1;
     uint64_t m[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) m[k] = __ballot(c == k);
@@ -1182,7 +1212,7 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
     a.n_list = n2;
     StageTimer tm(pl->ctx, VP_STAGE_ROWS_NEAR);
     const size_t lds_deep = sizeof(double) * (3 * (size_t)nn + 2 * (size_t)nf);
-    k_rows_deep<P><<<groups(n2), 64, lds_deep, st>>>(a, nr, pl->n_tri, ovf, n_ovf);
+    k_rows_deep<P><<<groups(n2), 64, lds_deep, st>>>(a, nr, pl->n_tri, cls, ovf, n_ovf);
     uint32_t h_ovf = 0;
     if ((e = hipGetLastError()) != hipSuccess ||
         (e = hipMemcpyAsync(&h_ovf, n_ovf, sizeof(uint32_t), hipMemcpyDeviceToHost, st)) != hipSuccess ||
