@@ -177,6 +177,9 @@ vp_status vp_ref_nodes(int p, double* xy_out, int* n_p_out);
  *              to int_0^1 r log(r0 r) phi(r) dr (Sec. 3.4)
  *           4  per-edge weights w-hat of the n x n collapsed rule (edges AB,
  *              BC, CA) used in eq. rho0 -> w[0..2]
+ *           5  the radial rule of order n folded onto n + 1 nodes, as the
+ *              plans use it for straight self pairs (same layout as 3; the
+ *              same sums for phi of degree <= n) 
  * *count receives the number of entries; any output may be NULL. */
 vp_status vp_ref_rule(int which, int n, double* x, double* y, double* w, int* count);
 

@@ -246,6 +246,10 @@ vp_status vp_ref_rule(int which, int n, double* x, double* y, double* w, int* co
       rw.resize(3);
       vp::edge_weights(r, n, rw.data());
     } break;
+    case 5: {
+      if (n > vp::kMaxP) return fail(VP_EINVAL, "vp_ref_rule: order %d outside [1, %d]", n, vp::kMaxP);
+      vp::radial_rule_folded(n, rx, ry, rw);
+    } break;
     default:
       return fail(VP_EINVAL, "vp_ref_rule: unknown rule %d", which);
   }
@@ -573,7 +577,7 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
   vp::Rule1D gl = vp::gauss_legendre01(o.n_l);
   vp::Rule2D nodes = vp::interp_nodes(p);
   std::vector<double> rr, ra, rb, rcr, rca, rcb;
-  vp::radial_rule(p, rr, ra, rb);
+  vp::radial_rule_folded(p, rr, ra, rb);  // straight self pieces: p + 1 nodes per ray
   vp::radial_rule(2 * vp::kCurvedRadial - 3, rcr, rca, rcb);  // kCurvedRadial points per part
   vp::edge_weights(far, q, pl->far_what);
   vp::edge_weights(nr, o.q_near, pl->near_what);

@@ -39,6 +39,9 @@ Rule2D interp_nodes(int p);                 // interior Blyth-Pozrikidis nodes
 int radial_half(int p);
 // radial rule: r, alpha (multiplies log r0), beta (constant)
 void radial_rule(int p, std::vector<double>& r, std::vector<double>& alpha, std::vector<double>& beta);
+// the same sums on p + 1 nodes for a basis of degree <= p along each ray
+// (straight self pieces)
+void radial_rule_folded(int p, std::vector<double>& r, std::vector<double>& alpha, std::vector<double>& beta);
 
 // ---------------------------------------------------------------------------
 // Device Koornwinder basis (Sec. 2.1), division-free in the collapsed

@@ -260,6 +260,35 @@ void radial_rule(int p, std::vector<double>& r, std::vector<double>& alpha, std:
   }
 }
 
+void radial_rule_folded(int p, std::vector<double>& r, std::vector<double>& alpha, std::vector<double>& beta) {
+  // Along a ray of a straight self piece the basis is a polynomial of degree
+  // <= p in r, so the radial rule's sum sum_i (alpha_i log r0 + beta_i)
+  // phi(r_i) equals sum_j (A_j log r0 + B_j) phi(rho_j) over any p + 1
+  // nodes rho_j, with A_j = sum_i alpha_i l_j(r_i), B_j = sum_i beta_i
+  // l_j(r_i) (l_j the Lagrange polynomials of the rho_j): the same integrals
+  // int_0^1 r l_j(r) dr and int_0^1 r log(r) l_j(r) dr, with p + 1 basis
+  // evaluations per ray instead of 2 radial_half(p).  rho_j: the (p+1)-point
+  // Gauss-Legendre nodes on [0, 1] (small Lagrange polynomials on [0, 1]).
+  std::vector<double> ri, ai, bi;
+  radial_rule(p, ri, ai, bi);
+  const Rule1D g = gauss_legendre01(p + 1);
+  r.assign(g.x.begin(), g.x.end());
+  alpha.assign(p + 1, 0.0);
+  beta.assign(p + 1, 0.0);
+  for (int j = 0; j <= p; ++j) {
+    ld A = 0.0L, B = 0.0L;
+    for (size_t i = 0; i < ri.size(); ++i) {
+      ld l = 1.0L;
+      for (int k = 0; k <= p; ++k)
+        if (k != j) l *= ((ld)ri[i] - (ld)g.x[k]) / ((ld)g.x[j] - (ld)g.x[k]);
+      A += (ld)ai[i] * l;
+      B += (ld)bi[i] * l;
+    }
+    alpha[j] = (double)A;
+    beta[j] = (double)B;
+  }
+}
+
 // The rules depend on their order alone and every plan asks for several of
 // them (0.4 ms of host time for the 16 x 16 collapsed rule): each is computed
 // once per process and copied out afterwards.

@@ -108,6 +108,30 @@ def test_radial_rule_matches_oracle(p):
     assert np.abs(r - R).max() < 4e-16 and np.abs(a - A).max() < 4e-16 and np.abs(b - B).max() < 4e-16
 
 
+@pytest.mark.parametrize("p", [1, 2, 4, 6, 8, 10])
+def test_folded_radial_rule(p):
+    """The p + 1 node radial rule of the straight self pieces: exact for
+    int_0^1 r^(m+1) dr = 1/(m+2) and int_0^1 r^(m+1) log r dr = -1/(m+2)^2,
+    m <= p, and the same sum as the oracle's radial rule for polynomials of
+    degree <= p and any log r0."""
+    r, a, b = vp.ref_rule(5, p)
+    assert len(r) == p + 1
+    for m in range(p + 1):
+        assert abs(np.sum(a * r ** m) - 1.0 / (m + 2)) < 1e-15
+        assert abs(np.sum(b * r ** m) + 1.0 / (m + 2) ** 2) < 1e-15
+    R, A, B = rules.radial_rule(p)
+    rng = np.random.default_rng(p)
+    for _ in range(5):
+        c = rng.standard_normal(p + 1)
+        lr0 = rng.uniform(-5.0, 1.0)
+        phi = lambda x: np.polynomial.polynomial.polyval(x, c)
+        folded = np.sum((a * lr0 + b) * phi(r))
+        full = np.sum((A * lr0 + B) * phi(R))
+        assert abs(folded - full) <= 1e-14 * max(1.0, abs(full))
+    # a degree p + 1 term is not integrated exactly by the folded rule
+    assert abs(np.sum(b * r ** (p + 1)) + 1.0 / (p + 3) ** 2) > 1e-12
+
+
 def test_invalid_rule_requests_are_rejected():
     with pytest.raises(vp.VPError) as e:
         vp.ref_rule(7, 4)
