@@ -833,6 +833,7 @@ constexpr int kClsPer = 4;                              // pairs per thread
 constexpr int kClsChunk = kClsThreads * kClsPer;        // pairs per block
 constexpr int kTabNearMax = 64;                         // near-rule nodes of the table path (q_near <= 8)
 constexpr int kTabSlotsMax = 2048;                      // slots of both classes (LDS: 24 bytes each)
+constexpr size_t kTabT0LdsMax = 16384;                  // class 0's Koornwinder table in LDS up to this size
 
 struct ClassArgs {
   const int32_t *pair_tri, *pair_tgt;
@@ -955,8 +956,9 @@ __global__ __launch_bounds__(kClsThreads) void k_pair_scatter(ClassArgs a) {
 
 // Reference data of the two classes, one row per slot (far nodes first,
 // padded to a multiple of 4, then the near rule's nodes): node tables
-// [rows][3] (xi1, xi2 and the weight: -w_j of the far rule, subtracted, or
-// w_j s^2 of a leaf of scale s; 0 in padding rows, placed at the centroid)
+// [rows][3] (xi1, xi2 and half the weight: -w_j / 2 of the far rule,
+// subtracted, or w_j s^2 / 2 of a leaf of scale s, the 1/2 of log r^2;
+// 0 in padding rows, placed at the centroid)
 // and Koornwinder tables [rows][NPP] (zero rows and columns as padding).
 // Class 0: the near rule on the simplex; class 1: on its four children
 // (a, s) = ((0,0), 1/2), ((1/2,0), 1/2), ((0,1/2), 1/2), ((1/2,1/2), -1/2).
@@ -1001,7 +1003,7 @@ __global__ void k_tab_build(const double* __restrict__ fx, const double* __restr
   }
   nod[0] = xi1;
   nod[1] = xi2;
-  nod[2] = w;
+  nod[2] = 0.5 * w;  // the kernel's 1/2 of log r^2
   if (live) koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { row[k] = v; });
 }
 
@@ -1019,16 +1021,23 @@ struct TabArgs {
   double* rows;
 };
 
-template <int P>
-__global__ __launch_bounds__(256) void k_rows_tab(TabArgs a) {
+// (at most 80 registers for 6 wavefronts per SIMD at P <= 4; above, the
+// larger accumulators take 5)
+template <int P, bool kT0Lds>
+__global__ __launch_bounds__(256, (P <= 4) ? 6 : 5) void k_rows_tab(TabArgs a) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
   constexpr int NT = (NP + 15) / 16;
   constexpr int NPP = 16 * NT;
   __shared__ double2 tab[kLogTab + 1];
-  extern __shared__ double nod[];  // [rows0 + rows1][3]
+  // node tables [rows0 + rows1][3], then (kT0Lds) class 0's Koornwinder
+  // table [rows0][NPP]: read at every step, from LDS instead of the cache
+  extern __shared__ double nod[];
+  double* const sT0 = nod + 3 * (a.rows0 + a.rows1);
   for (int i = threadIdx.x; i <= kLogTab; i += blockDim.x) tab[i] = a.logtab[i];
   for (int i = threadIdx.x; i < 3 * a.rows0; i += blockDim.x) nod[i] = a.nod0[i];
   for (int i = threadIdx.x; i < 3 * a.rows1; i += blockDim.x) nod[3 * a.rows0 + i] = a.nod1[i];
+  if (kT0Lds)
+    for (int i = threadIdx.x; i < a.rows0 * NPP; i += blockDim.x) sT0[i] = a.tab0[i];
   __syncthreads();
   const int lane = threadIdx.x & 63, kq = lane >> 4, col = lane & 15;
   const int64_t t0 = (a.n0 + 15) / 16, n_tiles = t0 + (a.n1 + 15) / 16;
@@ -1043,8 +1052,7 @@ __global__ __launch_bounds__(256) void k_rows_tab(TabArgs a) {
     const double x = a.xt[it], y = a.yt[it];
     const double Ax = a.ax[t], Ay = a.ay[t];
     const double e1x = a.bx[t] - Ax, e1y = a.by[t] - Ay, e2x = a.cx[t] - Ax, e2y = a.cy[t] - Ay;
-    const double D = a.det[t];
-    const double* T = one ? a.tab1 : a.tab0;
+    const double Dv = valid ? a.det[t] : 0.0;  // a padding row of the tile gets zero weights
     const double* N = one ? nod + 3 * a.rows0 : nod;
     const int n_slots = one ? a.rows1 : a.rows0;
     vp_d4 acc[NT];
@@ -1058,18 +1066,24 @@ __global__ __launch_bounds__(256) void k_rows_tab(TabArgs a) {
     // cancels), r^2 with the far sums' offset (far below any near node's
     // r^2), and the weight from the table (negative for the far rule's own
     // contribution, which is subtracted; zero in padding rows).
-    for (int s0 = 0; s0 < n_slots; s0 += 4) {
-      const int slot = s0 + kq;
-      const double xi1 = N[3 * slot], xi2 = N[3 * slot + 1], w = N[3 * slot + 2];
-      const double yx = Ax + xi1 * e1x + xi2 * e2x;
-      const double yy = Ay + xi1 * e1y + xi2 * e2y;
-      const double dx = x - yx, dy = y - yy;
-      const double r2 = fma(dy, dy, fma(dx, dx, kR2Bias));
-      const double v = 0.5 * vp_log(r2, tab) * (w * D);
-      const double g = valid ? v : 0.0;
-      const double* Trow = T + (size_t)slot * NPP + col;
+    auto steps = [&](auto trow) {
+      for (int s0 = 0; s0 < n_slots; s0 += 4) {
+        const int slot = s0 + kq;
+        const double xi1 = N[3 * slot], xi2 = N[3 * slot + 1], hw = N[3 * slot + 2];
+        const double yx = Ax + xi1 * e1x + xi2 * e2x;
+        const double yy = Ay + xi1 * e1y + xi2 * e2y;
+        const double dx = x - yx, dy = y - yy;
+        const double r2 = fma(dy, dy, fma(dx, dx, kR2Bias));
+        const double g = vp_log(r2, tab) * (hw * Dv);
 #pragma unroll
-      for (int n = 0; n < NT; ++n) acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(g, Trow[16 * n], acc[n], 0, 0, 0);
+        for (int n = 0; n < NT; ++n) acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(g, trow(slot, n), acc[n], 0, 0, 0);
+      }
+    };
+    if (kT0Lds && !one) {
+      steps([&](int slot, int n) { return sT0[slot * NPP + 16 * n + col]; });
+    } else {
+      const double* T = one ? a.tab1 : a.tab0;
+      steps([&](int slot, int n) { return T[(size_t)slot * NPP + 16 * n + col]; });
     }
     // element v of lane l: pair kq + 4 v of the tile, basis function 16 n + col
 #pragma unroll
@@ -1193,8 +1207,14 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
     ta.rows = pl->rows;
     const int64_t tiles = (n0 + 15) / 16 + (n1 + 15) / 16;
     StageTimer tm(pl->ctx, VP_STAGE_ROWS_TAB);
+    // class 0's table in LDS while it is small (the common class)
     const size_t lds = sizeof(double) * 3 * (size_t)(rows0 + rows1);
-    k_rows_tab<P><<<(unsigned)std::min<int64_t>((tiles + 3) / 4, 1 << 20), 256, lds, st>>>(ta);
+    const size_t t0_bytes = sizeof(double) * (size_t)rows0 * NPP;
+    const unsigned nb = (unsigned)std::min<int64_t>((tiles + 3) / 4, 1 << 20);
+    if (t0_bytes <= kTabT0LdsMax)
+      k_rows_tab<P, true><<<nb, 256, lds + t0_bytes, st>>>(ta);
+    else
+      k_rows_tab<P, false><<<nb, 256, lds, st>>>(ta);
     tm.stop(1);
   }
   constexpr int64_t kPairsPerGroup = 8;
