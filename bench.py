@@ -145,7 +145,7 @@ def stage_rooflines(info, tm, steps, q_near=7, n_l=16):
     work over the stage's average device time)."""
     n_p, n_tgt, n_pairs, T = info["n_p"], info["n_tgt"], info["n_pairs"], info["n_tri"]
     n_f, nn = info["n_f"], q_near * q_near
-    n_r = 2 * max(4, (info["p"] + 3) // 2)
+    n_r = info["p"] + 1  # radial nodes per ray of a straight self piece (the folded radial rule)
     n_self, tab_pairs, tab_leaves = info["n_self"], info["tab_pairs"], info["tab_leaves"]
     out = {}
 
@@ -161,9 +161,9 @@ def stage_rooflines(info, tm, steps, q_near=7, n_l=16):
 
     near_deep = n_pairs - n_self - tab_pairs
     p = info["p"]
-    alu("rows_tab", "rows_tab", tab_pairs * n_f + tab_leaves * nn, tab_flops_per_node(n_p), f"k_rows_tab<{p}>")
+    alu("rows_tab", "rows_tab", tab_pairs * n_f + tab_leaves * nn, tab_flops_per_node(n_p), f"k_rows_tab<{p}, *>")
     alu("rows_near", "rows_near", (info["near_subtri"] - tab_leaves) * nn + near_deep * n_f,
-        rows_flops_per_node(n_p), f"k_rows<{p}, false, 1>")
+        rows_flops_per_node(n_p), f"k_rows_deep<{p}>")
     alu("rows_self", "rows_self", info["self_panels"] * n_l * n_r + n_self * n_f, rows_flops_per_node(n_p),
         f"k_rows<{p}, false, 2>")
     if "rows_tab" not in out and "rows_near" not in out:
@@ -226,7 +226,12 @@ def source_digest(parts):
     return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
+LOG_DIGEST_PART = ("vp_internal.h", "constexpr double kR2Bias", "void vp_log_wide_parts(")
+FAR64_DIGEST_PARTS = [("vp_exec.hip", "template <int S, int RB>\nstruct FarShape {", "void k_far("), LOG_DIGEST_PART]
+FAR32_DIGEST_PARTS = [("vp_exec.hip", "template <int RB, int TPT>\n__global__ __launch_bounds__(kBlock) void k_far32(",
+                       "void k_far32("), LOG_DIGEST_PART]
 ROWS_DIGEST_PARTS = [("vp_rows.hip", "__device__ __forceinline__ int dyadic_count", "void k_rows(RowsArgs a)"),
+                     ("vp_rows.hip", "constexpr int kDeepLv", "void k_rows_deep("),
                      ("vp_rows.hip", "struct TabArgs {", "void k_rows_tab(TabArgs a)")]
 
 
@@ -297,8 +302,9 @@ def sweep_star(ctx, qs, steps=1):
 
 def sweep_batched(ctx, qs, R=64):
     """The 100k-triangle star with 64 densities (seeds 1000..), far sum by
-    the FMM in passes of 16 densities on the FP64 matrix cores, far order
-    q swept: per q the plan and one evaluation of all 64 densities."""
+    the FMM in passes of 16 densities, far order q swept: per q the plan and
+    one evaluation of all 64 densities, FP64 (plan eps 1e-13, 32 terms) and
+    mixed (plan eps 1e-8, 16 terms, FP32 leaf passes)."""
     import torch
     from paper_2205_04401_amd import workloads as W
     from paper_2205_04401_amd import vp
@@ -315,31 +321,60 @@ def sweep_batched(ctx, qs, R=64):
     u = torch.empty((len(tg), R), dtype=torch.float64, device="cuda")
     lines = []
     for q in qs:
-        torch.cuda.synchronize()
-        ctx.profile(True)
-        t0 = time.perf_counter()
-        plan = ctx.plan(mesh, p, q, eps, tg_d, **FMM)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        plan.execute(FR_d, out=u)  # builds the 16-density tables on first use
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        plan.execute(FR_d, out=u)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        tm = ctx.timings()
-        ctx.profile(False)
-        info = plan.info()
-        plan.close()
-        line = {"q": q, "plan_ms": (t1 - t0) * 1e3, "execute_ms": (t3 - t2) * 1e3,
-                "evals_per_s_execute": len(tg) * R / (t3 - t2), "evals_per_s_with_plan": len(tg) * R / (t3 - t2 + t1 - t0),
-                "rows_ms": tm["rows"][0], "classify_ms": tm["classify"][0], "n_pairs": info["n_pairs"],
-                "pairs_per_target": info["n_pairs"] / len(tg), "n_src": info["n_src"]}
-        lines.append(line)
-        say(json.dumps({"sweep_star100k_64": line}))
+        for mixed, eps_plan, terms in ((False, eps, 32), (True, 1e-8, 16)):
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            t0 = time.perf_counter()
+            plan = ctx.plan(mesh, p, q, eps_plan, tg_d, fmm_terms=terms, fmm_leaf=FMM["fmm_leaf"])
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            plan.execute(FR_d, out=u, mixed=mixed)  # builds the 16-density tables on first use
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            plan.execute(FR_d, out=u, mixed=mixed)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            tm = ctx.timings()
+            ctx.profile(False)
+            info = plan.info()
+            plan.close()
+            line = {"q": q, "precision": "mixed" if mixed else "fp64", "plan_eps": eps_plan, "fmm_terms": terms,
+                    "plan_ms": (t1 - t0) * 1e3, "execute_ms": (t3 - t2) * 1e3,
+                    "evals_per_s_execute": len(tg) * R / (t3 - t2),
+                    "evals_per_s_with_plan": len(tg) * R / (t3 - t2 + t1 - t0),
+                    "rows_ms": tm["rows"][0], "classify_ms": tm["classify"][0], "n_pairs": info["n_pairs"],
+                    "pairs_per_target": info["n_pairs"] / len(tg), "n_src": info["n_src"]}
+            lines.append(line)
+            say(json.dumps({"sweep_star100k_64": line}))
     mesh.close()
-    return {"workload": f"star {len(tq)} triangles (seed 30), {len(tg)} targets (seed 31), p={p}, eps={eps}, "
-                        f"{R} densities (seeds 1000..{1000 + R - 1}), FP64, far sum by the FMM", "lines": lines}
+    return {"workload": f"star {len(tq)} triangles (seed 30), {len(tg)} targets (seed 31), p={p}, "
+                        f"{R} densities (seeds 1000..{1000 + R - 1}), far sum by the FMM; FP64 (eps {eps}) and "
+                        f"mixed (eps 1e-8)", "lines": lines}
+
+
+def far_order_policy(ctx):
+    """The far-order policy (vp_choose_q, Sec. 4.2 trade-off) on the 20k
+    star, p = 6, eps = 1e-13, one density, with the direct and with the FMM
+    far sum: the order it picks for a plan used once, the times it measured
+    per order, and from those times the order for a plan serving 100
+    evaluations."""
+    import torch
+    vq, tq, tg, _ = star(20000)
+    mesh = ctx.mesh(vq, tq)
+    tg_d = torch.from_numpy(tg).cuda()
+    out = {"workload": f"star {len(tq)} triangles (seed 20), {len(tg)} targets (seed 21), p=6, eps=1e-13, "
+                       f"1 density; cost = plan + n_solves x evaluation", "lines": []}
+    for far, opts, qmax in (("direct", {}, 12), ("fmm", FMM, 16)):
+        t0 = time.perf_counter()
+        q, times = ctx.choose_q(mesh, 6, 1e-13, tg_d, q_min=4, q_max=qmax, n_solves=1, **opts)
+        ok = {k: v for k, v in times.items() if math.isfinite(v[0])}
+        q100 = min(ok, key=lambda k: ok[k][0] + 100 * ok[k][1])
+        line = {"far": far, "q_one_solve": q, "q_100_solves": q100, "policy_s": time.perf_counter() - t0,
+                "plan_ms": {k: v[0] for k, v in times.items()}, "execute_ms": {k: v[1] for k, v in times.items()}}
+        out["lines"].append(line)
+        say(json.dumps({"far_order_policy": {k: line[k] for k in ("far", "q_one_solve", "q_100_solves", "policy_s")}}))
+    mesh.close()
+    return out
 
 
 def batched(ctx, R=64, steps=2):
@@ -446,6 +481,24 @@ def small_case(ctx, n=300):
     return out
 
 
+def mixed_probe():
+    """The mixed line's step (graded L-shape, plan at eps = 1e-8, FP32
+    direct far sum), once."""
+    import torch
+    from paper_2205_04401_amd import vp
+    p, q = 4, 4
+    vq, tq, tg, F = l_shape(p)
+    ctx = vp.Context(0, stream=torch.cuda.current_stream().cuda_stream)
+    mesh = ctx.mesh(vq, tq)
+    plan = ctx.plan(mesh, p, q, 1e-8, torch.from_numpy(tg).cuda())
+    u = plan.execute(torch.from_numpy(F).cuda(), mixed=True)
+    torch.cuda.synchronize()
+    print(json.dumps({"mixed_probe": {"n_src": plan.n_src, "n_tgt": plan.n_tgt, "u0": float(u[0])}}), flush=True)
+    plan.close()
+    mesh.close()
+    ctx.close()
+
+
 def copy_probe(n_bytes=1 << 29, reps=3):
     """A plain device-to-device copy of known size (the calibration kernel
     for the FETCH_SIZE / WRITE_SIZE counters)."""
@@ -549,8 +602,9 @@ def run(args, pool, n_workers):
     u_dir = out[sample_d, 0].cpu().numpy()
     far_d = far_roofline(info_d["n_src"], n_tgt, tm_d["far"][0], tm_d["far"][1], "k_far<1, WIDE> (FP64)",
                          PEAK_FP64_VECTOR_TFLOPS)
-    ipp = counter_summary("k_far_fp64_star20k_q8_counters.md").get("valu_instructions_per_pair")
-    if ipp:
+    f64c = counter_summary("k_far_fp64_star20k_q8_counters.md")
+    ipp = f64c.get("valu_instructions_per_pair")
+    if ipp and f64c.get("kernel_source_sha256_16") == source_digest(FAR64_DIGEST_PARTS):
         far_d["valu_issue"] = {"instructions_per_pair_star20k_q8": float(ipp),
                                "frac": float(ipp) * far_d["pairs_per_s"] / PEAK_VALU_LANE_INSTS}
     result["direct"] = {"value": n_tgt / dt_d, "unit": "evals/s", "ms_per_step": dt_d * 1e3, "steps": args.direct_steps,
@@ -562,6 +616,13 @@ def run(args, pool, n_workers):
     dt_m, info_m, tm_m = timed_steps(ctx, step_of(1e-8, True), args.mixed_steps, 1)
     u_mix = out[sample_d, 0].cpu().numpy()
     far_m = far_roofline(info_m["n_src"], n_tgt, tm_m["far"][0], tm_m["far"][1], "k_far32 (FP32)", 157.3)
+    f32c = counter_summary("k_far32_lshape250k_q4_counters.md")
+    ipp32 = f32c.get("valu_instructions_per_pair")
+    if ipp32 and f32c.get("kernel_source_sha256_16") == source_digest(FAR32_DIGEST_PARTS):
+        # FP32 without packed instructions: one lane operation per cycle and lane
+        far_m["valu_issue"] = {"instructions_per_pair": float(ipp32),
+                               "frac": float(ipp32) * far_m["pairs_per_s"] / PEAK_VALU_LANE_INSTS,
+                               "non_packed_fp32_peak_tflops": 78.6}
     result["mixed"] = {"value": n_tgt / dt_m, "unit": "evals/s", "ms_per_step": dt_m * 1e3, "steps": args.mixed_steps,
                        "plan_eps": 1e-8, "pairs_per_target": info_m["n_pairs"] / n_tgt, "far_roofline": far_m,
                        "breakdown_ms": {k: v[0] / args.mixed_steps for k, v in tm_m.items() if v[1]}}
@@ -572,6 +633,7 @@ def run(args, pool, n_workers):
     if not args.no_sweep:
         result["sweep"] = {"star20k": sweep_star(ctx, (4, 5, 6, 8, 10, 12, 16)),
                            "star100k_64rhs": sweep_batched(ctx, (8, 10, 12, 14, 16, 18, 20))}
+        result["far_order_policy"] = far_order_policy(ctx)
     if not args.no_batched:
         result["batched"] = batched(ctx)
     if not args.no_small:
@@ -628,6 +690,8 @@ def main():
     ap.add_argument("--serving-budget-gb", type=float, default=128.0)
     ap.add_argument("--serving-q", type=int, default=8)
     ap.add_argument("--copy-probe", action="store_true", help="only run a 512 MiB device copy (counter calibration)")
+    ap.add_argument("--mixed-probe", action="store_true",
+                    help="only the mixed line's step, once (counter runs of the FP32 far sum)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -637,6 +701,9 @@ def main():
         raise SystemExit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.mixed_probe:
+        mixed_probe()
         return
     # the oracle's worker processes start before anything touches the GPU
     pool, n_workers = None, 0

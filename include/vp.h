@@ -429,6 +429,24 @@ vp_status vp_plan_set_far_config(vp_plan* plan, int64_t n_rhs, vp_precision prec
 vp_status vp_plan_autotune(vp_plan* plan, int64_t n_rhs, vp_precision prec, int reps, vp_far_config* best_out,
                            double* best_ms_out);
 
+/* The far-order policy (Sec. 4.2, the trade-off between the far rule's
+ * order and the precomputed near corrections): builds the plan for every
+ * far order q in [q_min, q_max] with the given options, runs evaluations of
+ * n_rhs zero densities in precision prec, and returns in *q_best the order
+ * with the least plan time + n_solves x evaluation time.  A larger q makes
+ * the far sum dearer (q^2 sources per triangle) and the near field smaller
+ * (fewer correction rows to build and apply); with the FMM far sum the
+ * balance moves to high q, with the direct sum to low q once the plan serves
+ * many evaluations.  plan_ms / exec_ms (optional, q_max - q_min + 1 entries
+ * each) receive the measured times (ms; the plan time includes tables the
+ * first evaluation builds; NaN for an order skipped because it does not fit
+ * the device, the context's budget or 2^31 sources).  Costs one plan and
+ * three evaluations per order.  Densities and outputs are taken from the
+ * context's memory.  VP_ENOMEM if no order fits. */
+vp_status vp_choose_q(vp_ctx* ctx, const vp_mesh* mesh, int p, double eps, int64_t n_tgt, const double* tgt_xy,
+                      const vp_plan_opts* opts_or_null, int q_min, int q_max, int64_t n_rhs, vp_precision prec,
+                      double n_solves, int* q_best, double* plan_ms, double* exec_ms);
+
 /* Interpolation of the potential over a mesh (Sec. 3.5).  Given u at the
  * order-p interpolation nodes (vp_ref_nodes; vp_mesh_map_points for their
  * positions) of every triangle of `mesh` -- e.g. the staggered target mesh

@@ -3,10 +3,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <string>
 #include <vector>
 
@@ -1188,6 +1190,84 @@ vp_status vp_plan_set_far_config(vp_plan* pl, int64_t R, vp_precision prec, cons
   pl->far_tuned[{R, prec == VP_MIXED ? 1 : 0}] = *cfg;
   return VP_OK;
 }
+
+// The far-order policy: every candidate order is built and run, and the one
+// with the least plan time plus n_solves evaluations is kept.
+vp_status vp_choose_q(vp_ctx* ctx, const vp_mesh* mesh, int p, double eps, int64_t n_tgt, const double* tgt_xy,
+                      const vp_plan_opts* opts, int q_min, int q_max, int64_t n_rhs, vp_precision prec,
+                      double n_solves, int* q_best, double* plan_ms, double* exec_ms) {
+  if (!ctx || !mesh || !q_best) return fail(VP_EINVAL, "vp_choose_q: NULL argument");
+  if (q_min < 2 || q_max > vp::kMaxQ || q_min > q_max)
+    return fail(VP_EINVAL, "vp_choose_q: orders [%d, %d] outside [2, %d]", q_min, q_max, vp::kMaxQ);
+  if (p < 1 || p > vp::kMaxP) return fail(VP_EINVAL, "vp_choose_q: p = %d outside [1, %d]", p, vp::kMaxP);
+  if (n_rhs < 1) return fail(VP_EINVAL, "vp_choose_q: n_rhs must be >= 1");
+  if (prec != VP_FP64 && prec != VP_MIXED) return fail(VP_EINVAL, "vp_choose_q: unknown precision");
+  if (!(n_solves >= 0.0) || !std::isfinite(n_solves)) return fail(VP_EINVAL, "vp_choose_q: n_solves must be >= 0");
+  VP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t st = ctx->stream;
+  // zero densities: the work of an evaluation does not depend on the values
+  const size_t nF = (size_t)mesh->n_tri * vp::n_basis(p) * n_rhs, nU = (size_t)std::max<int64_t>(n_tgt, 1) * n_rhs;
+  void *F = nullptr, *U = nullptr;
+  hipError_t e;
+  if ((e = vp::ctx_alloc(ctx, &F, sizeof(double) * nF, nullptr)) != hipSuccess)
+    return fail(VP_ENOMEM, "vp_choose_q: densities: %s", hipGetErrorString(e));
+  if ((e = vp::ctx_alloc(ctx, &U, sizeof(double) * nU, nullptr)) != hipSuccess) {
+    vp::ctx_release(ctx, F);
+    return fail(VP_ENOMEM, "vp_choose_q: output: %s", hipGetErrorString(e));
+  }
+  struct Release {
+    vp_ctx* c;
+    void *a, *b;
+    ~Release() {
+      (void)hipStreamSynchronize(c->stream);
+      vp::ctx_release(c, a);
+      vp::ctx_release(c, b);
+    }
+  } rel{ctx, F, U};
+  VP_HIP(hipMemsetAsync(F, 0, sizeof(double) * nF, st), "hipMemsetAsync");
+  vp_plan_opts o = opts ? *opts : default_opts();
+  typedef std::chrono::steady_clock clk;
+  auto ms_since = [](clk::time_point t) { return std::chrono::duration<double, std::milli>(clk::now() - t).count(); };
+  double best = std::numeric_limits<double>::infinity();
+  int qb = -1;
+  for (int q = q_min; q <= q_max; ++q) {
+    const int k = q - q_min;
+    if (plan_ms) plan_ms[k] = std::numeric_limits<double>::quiet_NaN();
+    if (exec_ms) exec_ms[k] = std::numeric_limits<double>::quiet_NaN();
+    vp_plan* pl = nullptr;
+    clk::time_point t0 = clk::now();
+    vp_status s = vp_plan_create(ctx, mesh, p, q, eps, n_tgt, tgt_xy, &o, &pl);
+    if (s == VP_ENOMEM || (s == VP_EINVAL && (int64_t)q * q * mesh->n_tri > 0x7fffff00LL)) continue;  // skipped
+    if (s != VP_OK) return s;
+    const double t_create = ms_since(t0);
+    double t_first = 0.0, t_exec = std::numeric_limits<double>::infinity();
+    for (int rep = 0; rep < 3 && s == VP_OK; ++rep) {
+      clk::time_point t1 = clk::now();
+      s = vp_execute(pl, n_rhs, (const double*)F, (double*)U, prec, VP_DEVICE_PTRS);
+      const double t = ms_since(t1);
+      if (rep == 0)
+        t_first = t;
+      else
+        t_exec = std::min(t_exec, t);
+    }
+    vp_plan_destroy(pl);
+    if (s == VP_ENOMEM) continue;
+    if (s != VP_OK) return s;
+    // tables an evaluation builds at its first call belong to the plan
+    const double t_plan = t_create + std::max(0.0, t_first - t_exec);
+    if (plan_ms) plan_ms[k] = t_plan;
+    if (exec_ms) exec_ms[k] = t_exec;
+    const double cost = t_plan + n_solves * t_exec;
+    if (cost < best) {
+      best = cost;
+      qb = q;
+    }
+  }
+  if (qb < 0) return fail(VP_ENOMEM, "vp_choose_q: no order in [%d, %d] fits the device or its budget", q_min, q_max);
+  *q_best = qb;
+  return VP_OK;
+}
+
 
 // Candidates: the shapes that change a launch for this n_rhs (the one-RHS
 // FP64 kernel is the only one with wide blocks; the matrix-core tiles

@@ -33,7 +33,7 @@ EXPORTS = ["vp_ctx_create", "vp_ctx_destroy", "vp_last_error", "vp_ref_nodes", "
            "vp_ctx_profile", "vp_ctx_timings", "vp_server_create", "vp_server_destroy", "vp_submit",
            "vp_poll", "vp_wait", "vp_server_stats", "vp_interp_create", "vp_interp_destroy", "vp_interp_locate",
            "vp_interp_eval", "vp_graph_create", "vp_graph_launch", "vp_graph_destroy", "vp_plan_far_config",
-           "vp_plan_set_far_config", "vp_plan_autotune", "vp_ctx_cached_bytes", "vp_ctx_trim", "vp_ctx_memory",
+           "vp_plan_set_far_config", "vp_plan_autotune", "vp_choose_q", "vp_ctx_cached_bytes", "vp_ctx_trim", "vp_ctx_memory",
            "vp_server_admission"]
 FAR_SHAPES = {"wide": 0, "narrow1": 1, "narrow2": 2}
 STAGES = ["classify", "rows", "coef", "far", "finish", "rows_tab", "rows_near", "rows_self"]
@@ -128,6 +128,8 @@ def load(path=LIB_PATH):
         "vp_plan_set_far_config": [P, I64, ctypes.c_int, ctypes.POINTER(FarConfig)],
         "vp_plan_autotune": [P, I64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(FarConfig),
                              ctypes.POINTER(ctypes.c_double)],
+        "vp_choose_q": [P, P, ctypes.c_int, ctypes.c_double, I64, P, P, ctypes.c_int, ctypes.c_int, I64,
+                        ctypes.c_int, ctypes.c_double, ctypes.POINTER(ctypes.c_int), P, P],
         "vp_interp_create": [P, P, ctypes.c_int, ctypes.POINTER(P)],
         "vp_interp_destroy": [P],
         "vp_interp_locate": [P, I64, P, P, P],
@@ -195,6 +197,10 @@ class Context:
 
     def plan(self, mesh, p, q, eps, targets, **opts):
         return Plan(self, mesh, p, q, eps, targets, **opts)
+
+    def choose_q(self, mesh, p, eps, targets, **kw):
+        """The far-order policy (vp_choose_q); see choose_q()."""
+        return choose_q(self, mesh, p, eps, targets, **kw)
 
     def interp(self, mesh, p):
         return Interp(self, mesh, p)
@@ -388,19 +394,37 @@ class Interp:
             self.h = None
 
 
+def _plan_args(targets, c_n=1.0, q_near=7, n_l=16, tau=1e-13, depth_cap=50, dyadic_cap=60, near_model="ellipse",
+               ball_factor=2.0, fmm_terms=0, fmm_leaf=128):
+    """(targets as a contiguous host array or device tensor, PlanOpts)."""
+    if _is_device(targets):
+        tgt = targets.contiguous()
+        flags = VP_DEVICE_PTRS
+    else:
+        tgt = np.ascontiguousarray(np.asarray(targets, dtype=np.float64).reshape(-1, 2))
+        flags = 0
+    if near_model not in NEAR_MODELS:
+        raise VPError(VP_EINVAL, f"near_model must be one of {sorted(NEAR_MODELS)}")
+    return tgt, PlanOpts(c_n, q_near, n_l, tau, depth_cap, dyadic_cap, flags, NEAR_MODELS[near_model], ball_factor,
+                         fmm_terms, fmm_leaf)
+
+
+def choose_q(ctx, mesh, p, eps, targets, q_min=4, q_max=16, n_rhs=1, mixed=False, n_solves=1.0, **opts):
+    """vp_choose_q: the far order with the least plan time + n_solves
+    evaluations.  Returns (q, {q: (plan_ms, exec_ms)})."""
+    tgt, o = _plan_args(targets, **opts)
+    n = q_max - q_min + 1
+    plan_ms, exec_ms = np.zeros(max(n, 1)), np.zeros(max(n, 1))
+    qb = ctypes.c_int(0)
+    _check(load().vp_choose_q(ctx.h, mesh.h, p, eps, tgt.shape[0], _ptr(tgt), ctypes.byref(o), q_min, q_max, n_rhs,
+                              VP_MIXED if mixed else VP_FP64, float(n_solves), ctypes.byref(qb), _ptr(plan_ms),
+                              _ptr(exec_ms)))
+    return qb.value, {q_min + k: (float(plan_ms[k]), float(exec_ms[k])) for k in range(n)}
+
+
 class Plan:
-    def __init__(self, ctx, mesh, p, q, eps, targets, c_n=1.0, q_near=7, n_l=16, tau=1e-13, depth_cap=50,
-                 dyadic_cap=60, near_model="ellipse", ball_factor=2.0, fmm_terms=0, fmm_leaf=128):
-        if _is_device(targets):
-            tgt = targets.contiguous()
-            flags = VP_DEVICE_PTRS
-        else:
-            tgt = np.ascontiguousarray(np.asarray(targets, dtype=np.float64).reshape(-1, 2))
-            flags = 0
-        if near_model not in NEAR_MODELS:
-            raise VPError(VP_EINVAL, f"near_model must be one of {sorted(NEAR_MODELS)}")
-        opts = PlanOpts(c_n, q_near, n_l, tau, depth_cap, dyadic_cap, flags, NEAR_MODELS[near_model], ball_factor,
-                        fmm_terms, fmm_leaf)
+    def __init__(self, ctx, mesh, p, q, eps, targets, **opts):
+        tgt, opts = _plan_args(targets, **opts)
         h = P()
         _check(load().vp_plan_create(ctx.h, mesh.h, p, q, eps, tgt.shape[0], _ptr(tgt), ctypes.byref(opts),
                                      ctypes.byref(h)))
