@@ -619,10 +619,10 @@ def run(args, pool, n_workers):
     f32c = counter_summary("k_far32_lshape250k_q4_counters.md")
     ipp32 = f32c.get("valu_instructions_per_pair")
     if ipp32 and f32c.get("kernel_source_sha256_16") == source_digest(FAR32_DIGEST_PARTS):
-        # FP32 without packed instructions: one lane operation per cycle and lane
+        # vector instructions retired against one wave64 instruction per 4
+        # cycles and SIMD (FP32 without packed instructions)
         far_m["valu_issue"] = {"instructions_per_pair": float(ipp32),
-                               "frac": float(ipp32) * far_m["pairs_per_s"] / PEAK_VALU_LANE_INSTS,
-                               "non_packed_fp32_peak_tflops": 78.6}
+                               "frac": float(ipp32) * far_m["pairs_per_s"] / PEAK_VALU_LANE_INSTS}
     result["mixed"] = {"value": n_tgt / dt_m, "unit": "evals/s", "ms_per_step": dt_m * 1e3, "steps": args.mixed_steps,
                        "plan_eps": 1e-8, "pairs_per_target": info_m["n_pairs"] / n_tgt, "far_roofline": far_m,
                        "breakdown_ms": {k: v[0] / args.mixed_steps for k, v in tm_m.items() if v[1]}}
