@@ -481,19 +481,20 @@ def small_case(ctx, n=300):
     return out
 
 
-def mixed_probe():
-    """The mixed line's step (graded L-shape, plan at eps = 1e-8, FP32
-    direct far sum), once."""
+def far_probe(mixed):
+    """The direct line's step (graded L-shape, FP64 direct far sum) or the
+    mixed line's (plan at eps = 1e-8, FP32 direct far sum), once."""
     import torch
     from paper_2205_04401_amd import vp
     p, q = 4, 4
     vq, tq, tg, F = l_shape(p)
     ctx = vp.Context(0, stream=torch.cuda.current_stream().cuda_stream)
     mesh = ctx.mesh(vq, tq)
-    plan = ctx.plan(mesh, p, q, 1e-8, torch.from_numpy(tg).cuda())
-    u = plan.execute(torch.from_numpy(F).cuda(), mixed=True)
+    plan = ctx.plan(mesh, p, q, 1e-8 if mixed else 1e-13, torch.from_numpy(tg).cuda())
+    u = plan.execute(torch.from_numpy(F).cuda(), mixed=mixed)
     torch.cuda.synchronize()
-    print(json.dumps({"mixed_probe": {"n_src": plan.n_src, "n_tgt": plan.n_tgt, "u0": float(u[0])}}), flush=True)
+    print(json.dumps({"far_probe": {"mixed": mixed, "n_src": plan.n_src, "n_tgt": plan.n_tgt, "u0": float(u[0])}}),
+          flush=True)
     plan.close()
     mesh.close()
     ctx.close()
@@ -602,10 +603,10 @@ def run(args, pool, n_workers):
     u_dir = out[sample_d, 0].cpu().numpy()
     far_d = far_roofline(info_d["n_src"], n_tgt, tm_d["far"][0], tm_d["far"][1], "k_far<1, WIDE> (FP64)",
                          PEAK_FP64_VECTOR_TFLOPS)
-    f64c = counter_summary("k_far_fp64_star20k_q8_counters.md")
+    f64c = counter_summary("k_far_fp64_lshape250k_q4_counters.md")
     ipp = f64c.get("valu_instructions_per_pair")
     if ipp and f64c.get("kernel_source_sha256_16") == source_digest(FAR64_DIGEST_PARTS):
-        far_d["valu_issue"] = {"instructions_per_pair_star20k_q8": float(ipp),
+        far_d["valu_issue"] = {"instructions_per_pair": float(ipp),
                                "frac": float(ipp) * far_d["pairs_per_s"] / PEAK_VALU_LANE_INSTS}
     result["direct"] = {"value": n_tgt / dt_d, "unit": "evals/s", "ms_per_step": dt_d * 1e3, "steps": args.direct_steps,
                         "far_roofline": far_d,
@@ -692,6 +693,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only run a 512 MiB device copy (counter calibration)")
     ap.add_argument("--mixed-probe", action="store_true",
                     help="only the mixed line's step, once (counter runs of the FP32 far sum)")
+    ap.add_argument("--direct-probe", action="store_true",
+                    help="only the direct line's step, once (counter runs of the FP64 far sum)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -702,8 +705,8 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
-    if args.mixed_probe:
-        mixed_probe()
+    if args.mixed_probe or args.direct_probe:
+        far_probe(mixed=args.mixed_probe)
         return
     # the oracle's worker processes start before anything touches the GPU
     pool, n_workers = None, 0

@@ -575,11 +575,25 @@ __global__ void k_scan_add(int64_t* out, int64_t n, const int64_t* __restrict__ 
   }
 }
 
-__global__ void k_count_sum(const int32_t* __restrict__ v, int64_t n, unsigned long long* out) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t s = (i < n) ? v[i] : 0;
+// sum of n counts into *out: a grid of at most kCountSumBlocks blocks strides
+// over the array and adds one partial per block (one atomic per wavefront on
+// a single address serialised the launch: 0.7 ms for 3.75M counts)
+constexpr int kCountSumBlocks = 1024;
+
+__global__ __launch_bounds__(kBlock) void k_count_sum(const int32_t* __restrict__ v, int64_t n,
+                                                      unsigned long long* out) {
+  __shared__ int64_t part[kBlock / 64];
+  int64_t s = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += v[i];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if ((threadIdx.x & 63) == 0 && s) atomicAdd(out, (unsigned long long)s);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t b = 0;
+    for (int w = 0; w < kBlock / 64; ++w) b += part[w];
+    if (b) atomicAdd(out, (unsigned long long)b);
+  }
 }
 
 }  // namespace
@@ -902,7 +916,8 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
                                                    pl->pair_tri, pl->pair_tgt, pl->pair_kind, scnt,
                                                    (int*)(d_sum + 1));
   }
-  k_count_sum<<<blocks_for(NT), kBlock, 0, st>>>(scnt, NT, d_sum);
+  k_count_sum<<<(unsigned)std::min<int64_t>(std::max<int64_t>(blocks_for(NT), 1), kCountSumBlocks), kBlock, 0, st>>>(
+      scnt, NT, d_sum);
   unsigned long long ns[2] = {0, 0};
   if ((e = hipGetLastError()) != hipSuccess ||
       (e = hipMemcpyAsync(ns, d_sum, sizeof(ns), hipMemcpyDeviceToHost, st)) != hipSuccess ||
