@@ -124,6 +124,33 @@ __global__ void k_fmm_tbox(const int64_t* __restrict__ tptr, int64_t nleaf, int3
   for (int64_t i = tptr[b]; i < tptr[b + 1]; ++i) tbox[i] = (int32_t)b;
 }
 
+// Direct pairs of every 16-target tile of the one-density leaf pass (the
+// adjacent boxes' sources of its first and of its last target, the larger),
+// and the tile's index, as the keys and values of a descending sort: the
+// pass then starts with its longest tiles.  On a graded mesh the uniform
+// quadtree leaves a few boxes with thousands of sources; started last, their
+// tiles kept a few wavefronts running long after the rest had finished.
+__global__ void k_fmm_tile_cost(const int32_t* __restrict__ tbox, int64_t n_tgt, const int64_t* __restrict__ sptr,
+                                int L, uint32_t* __restrict__ cost, int32_t* __restrict__ idx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n_tiles = (n_tgt + 15) / 16;
+  if (i >= n_tiles) return;
+  const int n = 1 << L;
+  auto adj = [&](int64_t b) -> int64_t {
+    const int ix = (int)(b % n), iy = (int)(b / n);
+    int64_t c = 0;
+    for (int jy = max(iy - 1, 0); jy <= min(iy + 1, n - 1); ++jy) {
+      const int64_t row = (int64_t)jy * n;
+      c += sptr[row + min(ix + 1, n - 1) + 1] - sptr[row + max(ix - 1, 0)];
+    }
+    return c;
+  };
+  const int64_t last = min(16 * i + 15, n_tgt - 1);
+  const int64_t c = max(adj(tbox[16 * i]), adj(tbox[last]));
+  cost[i] = (uint32_t)min<int64_t>(c, 0xffffffffll);
+  idx[i] = (int32_t)i;
+}
+
 __global__ void k_fmm_gather2(const double2* __restrict__ in, const int32_t* __restrict__ perm, int64_t n,
                               double2* __restrict__ out) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -379,13 +406,14 @@ __global__ __launch_bounds__(kBlock) void k_fmm_leaf(
     const double2* __restrict__ sxy_s, const double* __restrict__ Qs, const int64_t* __restrict__ sptr,
     const int32_t* __restrict__ tperm, const double* __restrict__ xt, const double* __restrict__ yt, int L,
     double x0, double y0, double s, int p, const double2* __restrict__ logtab, int64_t R, int64_t r,
-    double* __restrict__ out) {
+    const int32_t* __restrict__ order, double* __restrict__ out) {
   __shared__ double2 tab[kLogTab + 1];
   for (int i = threadIdx.x; i <= kLogTab; i += kBlock) tab[i] = logtab[i];
   __syncthreads();
   const int lane = (int)(threadIdx.x & 63), r16 = lane & 15, kq = lane >> 4;
-  const int64_t i0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * 16;
-  if (i0 >= n_tgt) return;  // the whole wavefront
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (w * 16 >= n_tgt) return;  // the whole wavefront
+  const int64_t i0 = (order ? (int64_t)order[w] : w) * 16;  // tiles longest first
   const int n = 1 << L;
   const int64_t i = i0 + r16;
   const bool act = i < n_tgt;
@@ -1253,6 +1281,28 @@ hipError_t build_fmm(vp_plan* pl, int leaf, hipStream_t st) {
   if ((e = alloc((void**)&pl->fmm_tbox, sizeof(int32_t) * std::max<int64_t>(NT, 1))) != hipSuccess) return e;
   k_fmm_tbox<<<blocks_for(nleaf), kBlock, 0, st>>>(pl->fmm_tgt_ptr, nleaf, pl->fmm_tbox);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  // the one-density leaf pass's tiles, longest first
+  const int64_t n_tiles = (NT + 15) / 16;
+  if (n_tiles > 0) {
+    if ((e = alloc((void**)&pl->fmm_tile_order, sizeof(int32_t) * n_tiles)) != hipSuccess) return e;
+    Scratch ts(pl->ctx, st);
+    uint32_t *cost = nullptr, *cost2 = nullptr;
+    int32_t* idx = nullptr;
+    void* stmp = nullptr;
+    size_t sbytes = 0;
+    if ((e = ts.alloc((void**)&cost, sizeof(uint32_t) * n_tiles)) != hipSuccess ||
+        (e = ts.alloc((void**)&cost2, sizeof(uint32_t) * n_tiles)) != hipSuccess ||
+        (e = ts.alloc((void**)&idx, sizeof(int32_t) * n_tiles)) != hipSuccess ||
+        (e = hipcub::DeviceRadixSort::SortPairsDescending(nullptr, sbytes, cost, cost2, idx, pl->fmm_tile_order,
+                                                          (int)n_tiles, 0, 32, st)) != hipSuccess ||
+        (e = ts.alloc(&stmp, std::max<size_t>(sbytes, 16))) != hipSuccess)
+      return e;
+    k_fmm_tile_cost<<<blocks_for(n_tiles), kBlock, 0, st>>>(pl->fmm_tbox, NT, pl->fmm_src_ptr, L, cost, idx);
+    if ((e = hipGetLastError()) != hipSuccess ||
+        (e = hipcub::DeviceRadixSort::SortPairsDescending(stmp, sbytes, cost, cost2, idx, pl->fmm_tile_order,
+                                                          (int)n_tiles, 0, 32, st)) != hipSuccess)
+      return e;
+  }
   return hipStreamSynchronize(st);  // the host vectors above go out of scope
 }
 
@@ -1393,7 +1443,7 @@ hipError_t launch_fmm(const vp_plan* pl, const double* Q, int64_t R, double* out
     }
     k_fmm_leaf<<<(unsigned)(((pl->n_tgt + 15) / 16 * 64 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
         Lall + pl->fmm_off[L] * P1, pl->fmm_tbox, pl->n_tgt, pl->fmm_sxy, Qs, pl->fmm_src_ptr, pl->fmm_tgt_perm,
-        pl->xt, pl->yt, L, pl->fmm_x0, pl->fmm_y0, sL, p, pl->logtab, R, r, out);
+        pl->xt, pl->yt, L, pl->fmm_x0, pl->fmm_y0, sL, p, pl->logtab, R, r, pl->fmm_tile_order, out);
     if (n_launches) *n_launches += 2 * L;
   }
   return hipGetLastError();

@@ -485,6 +485,7 @@ struct vp_plan {
   int2* fmm_ttile = nullptr;
   int64_t fmm_n_ttiles = 0;
   int32_t* fmm_tbox = nullptr;  // [n_tgt] leaf box of each target in leaf order
+  int32_t* fmm_tile_order = nullptr;  // [ceil(n_tgt / 16)] leaf-pass tiles, most direct pairs first
   std::vector<int64_t> fmm_tgt_ptr_host;  // host copy of fmm_tgt_ptr (tile list)
   // far-sum launch shapes stored for (n_rhs, precision) by the tuner or the caller
   std::map<std::pair<int64_t, int>, vp_far_config> far_tuned;
