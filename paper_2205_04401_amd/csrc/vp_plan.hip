@@ -447,58 +447,81 @@ __device__ __forceinline__ int64_t cell_of(const Grid g, double x, double y) {
   return (int64_t)j * g.nx + i;
 }
 
+// 32-bit words of decision bits per target: one bit per triangle of its cell
+__global__ void k_pair_words(const double* __restrict__ xt, const double* __restrict__ yt, int64_t n_tgt, Grid g,
+                             const int64_t* __restrict__ cptr, int32_t* __restrict__ words) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_tgt) return;
+  const int64_t c = cell_of(g, xt[i], yt[i]);
+  words[i] = (int32_t)((cptr[c + 1] - cptr[c] + 31) / 32);
+}
+
+// Count pass, one thread per target: classifies every triangle of the
+// target's cell once, keeps the decisions as bits (mk[w].x: self or near,
+// mk[w].y: self; bit j of word w is the cell's triangle 32 w + j) at the
+// target's word offset woff[i], and counts its pairs.
 template <bool kCurved>
 __global__ void k_pair_count(const double* __restrict__ xt, const double* __restrict__ yt, int64_t n_tgt, Grid g,
                              const int64_t* __restrict__ cptr, const int32_t* __restrict__ ctri, TriView tv,
-                             double tau, int32_t* cnt) {
+                             double tau, const int64_t* __restrict__ woff, uint2* __restrict__ mk, int32_t* cnt) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_tgt) return;
   const double x = xt[i], y = yt[i];
   const int64_t c = cell_of(g, x, y);
+  const int64_t k0 = cptr[c], k1 = cptr[c + 1];
+  uint2* out = mk + woff[i];
   int n = 0;
-  for (int64_t k = cptr[c]; k < cptr[c + 1]; ++k) n += (classify<kCurved>(tv, ctri[k], x, y, tau) < 2);
+  for (int64_t kb = k0; kb < k1; kb += 32) {
+    uint32_t pair = 0, self = 0;
+    const int m = (int)min<int64_t>(32, k1 - kb);
+    for (int j = 0; j < m; ++j) {
+      const int kind = classify<kCurved>(tv, ctri[kb + j], x, y, tau);
+      pair |= (kind < 2 ? 1u : 0u) << j;
+      self |= (kind == 0 ? 1u : 0u) << j;
+    }
+    out[(kb - k0) >> 5] = make_uint2(pair, self);
+    n += __popc(pair);
+  }
   cnt[i] = n;
 }
 
-// Fill pass, one wavefront per target: the lanes classify 64 of the cell's
-// triangles at a time and write the pairs among them at consecutive places
-// (ballot and prefix count), so that the stores of a wavefront are
-// contiguous; the cell lists are ascending, so are the target's pairs.  A
-// target that finds more pairs than the count pass did sets *bad and writes
-// nothing beyond its range.
+// Fill pass, one wavefront per target: the lanes take 64 of the cell's
+// triangles at a time with their decision bits from the count pass and
+// write the pairs among them at consecutive places (ballot and prefix
+// count), so that the stores of a wavefront are contiguous; the cell lists
+// are ascending, so are the target's pairs.  A target whose pairs do not
+// fill its range exactly sets *bad (it writes nothing beyond its range).
 constexpr int kFillWaves = 4;
 
-template <bool kCurved>
 __global__ __launch_bounds__(kFillWaves * 64) void k_pair_fill(
     const double* __restrict__ xt, const double* __restrict__ yt, int64_t n_tgt, Grid g,
-    const int64_t* __restrict__ cptr, const int32_t* __restrict__ ctri, TriView tv, double tau,
-    const int64_t* __restrict__ row_ptr, int32_t* pair_tri, int32_t* pair_tgt, uint8_t* pair_kind,
-    int32_t* self_cnt, int* bad) {
+    const int64_t* __restrict__ cptr, const int32_t* __restrict__ ctri, const int64_t* __restrict__ woff,
+    const uint2* __restrict__ mk, const int64_t* __restrict__ row_ptr, int32_t* pair_tri, int32_t* pair_tgt,
+    uint8_t* pair_kind, int32_t* self_cnt, int* bad) {
   const int lane = threadIdx.x & 63;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int64_t i = (int64_t)blockIdx.x * kFillWaves + (threadIdx.x >> 6); i < n_tgt;
        i += (int64_t)gridDim.x * kFillWaves) {
-    const double x = xt[i], y = yt[i];
-    const int64_t c = cell_of(g, x, y);
+    const int64_t c = cell_of(g, xt[i], yt[i]);
     const int64_t k0 = cptr[c], k1 = cptr[c + 1];
+    const uint2* bits = mk + woff[i];
     const int64_t end = row_ptr[i + 1];
     int64_t o = row_ptr[i];
     int ns = 0;
     for (int64_t kb = k0; kb < k1; kb += 64) {
       const int64_t k = kb + lane;
-      int32_t t = 0;
-      int kind = 2;
-      if (k < k1) {
-        t = ctri[k];
-        kind = classify<kCurved>(tv, t, x, y, tau);
-      }
-      const uint64_t m = __ballot(kind < 2);
-      ns += __popcll(__ballot(kind == 0));
+      const bool in = k < k1;
+      const uint2 w = in ? bits[(k - k0) >> 5] : make_uint2(0u, 0u);
+      const int b = (int)((k - k0) & 31);
+      const bool is_pair = in && ((w.x >> b) & 1u);
+      const bool is_self = in && ((w.y >> b) & 1u);
+      const uint64_t m = __ballot(is_pair);
+      ns += __popcll(__ballot(is_self));
       const int64_t pos = o + __popcll(m & lt);
-      if (kind < 2 && pos < end) {
-        pair_tri[pos] = t;
+      if (is_pair && pos < end) {
+        pair_tri[pos] = ctri[k];
         pair_tgt[pos] = (int32_t)i;
-        pair_kind[pos] = (uint8_t)kind;
+        pair_kind[pos] = is_self ? (uint8_t)0 : (uint8_t)1;
       }
       o += __popcll(m);
     }
@@ -874,11 +897,31 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
   }
   TriView tv{m->ax, m->ay, m->bx, m->by, m->cx, m->cy, m->det, thr, T, pl->opts.near_model == VP_NEAR_BALL ? 1 : 0,
              pl->opts.ball_factor, m->curves()};
+  // decision bits of every (target, cell triangle): word offsets per target
+  int32_t* wcnt = nullptr;
+  int64_t* woff = nullptr;
+  uint2* mk = nullptr;
+  int64_t n_words = 0;
+  if ((e = talloc((void**)&wcnt, sizeof(int32_t) * std::max<int64_t>(NT, 1))) != hipSuccess ||
+      (e = talloc((void**)&woff, sizeof(int64_t) * (NT + 1))) != hipSuccess) {
+    cleanup();
+    return e;
+  }
+  if (NT > 0) k_pair_words<<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, wcnt);
+  if ((e = exclusive_scan_i32(wcnt, woff, NT, stmp, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(&n_words, woff + NT, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess ||
+      (e = talloc((void**)&mk, sizeof(uint2) * std::max<int64_t>(n_words, 1))) != hipSuccess) {
+    cleanup();
+    return e;
+  }
   const bool curved = tv.cv.of != nullptr;
   if (curved)
-    k_pair_count<true><<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, tv, pl->opts.tau, pcnt);
+    k_pair_count<true><<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, tv, pl->opts.tau, woff,
+                                                          mk, pcnt);
   else
-    k_pair_count<false><<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, tv, pl->opts.tau, pcnt);
+    k_pair_count<false><<<blocks_for(NT), kBlock, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, tv, pl->opts.tau, woff,
+                                                           mk, pcnt);
   if ((e = exclusive_scan_i32(pcnt, pl->row_ptr, NT, stmp, st)) != hipSuccess) {
     cleanup();
     return e;
@@ -911,10 +954,9 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
   }
   if (NT > 0) {
     const int64_t nb = std::min<int64_t>((NT + kFillWaves - 1) / kFillWaves, (int64_t)1 << 22);
-    auto fill = curved ? k_pair_fill<true> : k_pair_fill<false>;
-    fill<<<(unsigned)nb, kFillWaves * 64, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, tv, pl->opts.tau, pl->row_ptr,
-                                                   pl->pair_tri, pl->pair_tgt, pl->pair_kind, scnt,
-                                                   (int*)(d_sum + 1));
+    k_pair_fill<<<(unsigned)nb, kFillWaves * 64, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, woff, mk, pl->row_ptr,
+                                                          pl->pair_tri, pl->pair_tgt, pl->pair_kind, scnt,
+                                                          (int*)(d_sum + 1));
   }
   k_count_sum<<<(unsigned)std::min<int64_t>(std::max<int64_t>(blocks_for(NT), 1), kCountSumBlocks), kBlock, 0, st>>>(
       scnt, NT, d_sum);
@@ -926,7 +968,7 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
     return e;
   }
   if (ns[1]) {
-    err = "near lists: the fill pass disagrees with the count pass";
+    err = "near lists: a target's pairs do not fill its range";
     cleanup();
     return hipErrorUnknown;
   }
