@@ -825,14 +825,19 @@ __global__ __launch_bounds__(64) void k_rows_deep(RowsArgs a, const double* __re
 // pairs at a time, g is the A operand of v_mfma_f64_16x16x4f64 (lane l: pair
 // l & 15, node 4 s + (l >> 4) of step s) and the table the B operand (node
 // 4 s + (l >> 4), basis function 16 n + (l & 15)); the lanes evaluate only
-// logarithms.  The pairs are sorted by class first: 0, 1, deeper near pairs
-// (2) and self pairs (3), the last two for k_rows.
+// logarithms.  The same holds for a pair whose subdivision splits exactly
+// one level-1 child c and stops at that child's four children (class 2 + c:
+// three level-1 and four level-2 leaves at fixed places).  The pairs are
+// sorted by class first: 0, 1, 2..5, deeper near pairs (6, for k_rows_deep)
+// and self pairs (7, for k_rows).
 // ---------------------------------------------------------------------------
+constexpr int kNCls = 8;
+constexpr int kClsDeep = 6, kClsSelf = 7;
 constexpr int kClsThreads = 256;
 constexpr int kClsPer = 4;                              // pairs per thread
 constexpr int kClsChunk = kClsThreads * kClsPer;        // pairs per block
 constexpr int kTabNearMax = 64;                         // near-rule nodes of the table path (q_near <= 8)
-constexpr int kTabSlotsMax = 2048;                      // slots of both classes (LDS: 24 bytes each)
+constexpr int kTabSlotsMax = 2048;                      // slots of one launch's two classes (LDS: 24 bytes each)
 constexpr size_t kTabT0LdsMax = 16384;                  // class 0's Koornwinder table in LDS up to this size
 
 struct ClassArgs {
@@ -845,16 +850,17 @@ struct ClassArgs {
   int64_t n_tri;
   double nwhat0, nwhat1, nwhat2, eps_cn, inv_near_order;
   int depth_cap;
-  uint8_t* cls;     // [n_pairs] class of every pair
-  int32_t* bcnt;    // [4][n_blk] pairs of each class per block
-  const int64_t* boff;  // [4 n_blk + 1] exclusive scan of bcnt (scatter pass)
+  uint8_t* cls;     // [n_pairs] class of every pair (bits 0..2; bits 4..7: level-1 splits of a deep pair)
+  int32_t* bcnt;    // [kNCls][n_blk] pairs of each class per block
+  const int64_t* boff;  // [kNCls n_blk + 1] exclusive scan of bcnt (scatter pass)
   uint32_t* list;       // [n_pairs] pair indices sorted by class (scatter pass)
 };
 
-// depth class of near pair pr: the tests of k_rows' first two levels; for
-// class 2 the bits 4..7 hold which of the four level-1 children split
+// depth class of near pair pr: the tests of k_rows' first levels; for a
+// deep pair (class 6) the bits 4..7 hold which of the four level-1 children
+// split
 __device__ __forceinline__ int pair_class(const ClassArgs& a, int64_t pr) {
-  if (a.pair_kind[pr] != 1) return 3;
+  if (a.pair_kind[pr] != 1) return kClsSelf;
   const int32_t t = a.pair_tri[pr];
   const int32_t it = a.pair_tgt[pr];
   const double x = a.xt[it], y = a.yt[it];
@@ -874,7 +880,20 @@ __device__ __forceinline__ int pair_class(const ClassArgs& a, int64_t pr) {
                    (near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.5, 0.0, 0.5, thr) ? 2 : 0) |
                    (near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.0, 0.5, 0.5, thr) ? 4 : 0) |
                    (near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.5, 0.5, -0.5, thr) ? 8 : 0);
-  return mask ? 2 | (mask << 4) : 1;
+  if (!mask) return 1;
+  if (mask & (mask - 1)) return kClsDeep | (mask << 4);
+  // one child c splits: class 2 + c if none of its four children splits
+  const int c = __ffs(mask) - 1;
+  if (2 < a.depth_cap) {
+    const double sa = (c == 1 || c == 3) ? 0.5 : 0.0, sb = (c >= 2) ? 0.5 : 0.0, h = (c == 3) ? -0.25 : 0.25;
+    near_level_thr(rho0, ell0, 2, a.inv_near_order, thr);
+    if (near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, sa, sb, h, thr) ||
+        near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, sa + h, sb, h, thr) ||
+        near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, sa, sb + h, h, thr) ||
+        near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, sa + h, sb + h, -h, thr))
+      return kClsDeep | (mask << 4);
+  }
+  return 2 + c;
 }
 
 // near-rule rho0 and edge lengths of every triangle: nr[e][T] = rho0_e,
@@ -898,57 +917,65 @@ __global__ void k_near_root(const double* __restrict__ ax, const double* __restr
 
 // count pass: class of every pair, pairs of each class per block
 __global__ __launch_bounds__(kClsThreads) void k_pair_class(ClassArgs a) {
-  __shared__ int cnt[4];
-  if (threadIdx.x < 4) cnt[threadIdx.x] = 0;
+  __shared__ int cnt[kNCls];
+  if (threadIdx.x < kNCls) cnt[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kClsChunk;
-  int my[4] = {0, 0, 0, 0};
+  int my[kNCls] = {};
 #pragma unroll
   for (int i = 0; i < kClsPer; ++i) {
     const int64_t pr = base + i * kClsThreads + threadIdx.x;
     if (pr < a.n_pairs) {
       const int c = pair_class(a, pr);
       a.cls[pr] = (uint8_t)c;
-      my[c & 3] += 1;
+#pragma unroll
+      for (int k = 0; k < kNCls; ++k) my[k] += (c & 7) == k;
     }
   }
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < kNCls; ++c) {
     int v = my[c];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     if ((threadIdx.x & 63) == 0 && v) atomicAdd(&cnt[c], v);
   }
   __syncthreads();
-  if (threadIdx.x < 4) a.bcnt[threadIdx.x * a.n_blk + blockIdx.x] = cnt[threadIdx.x];
+  if (threadIdx.x < kNCls) a.bcnt[threadIdx.x * a.n_blk + blockIdx.x] = cnt[threadIdx.x];
 }
 
 // scatter pass: pair indices by class, in pair order within a class
 __global__ __launch_bounds__(kClsThreads) void k_pair_scatter(ClassArgs a) {
-  __shared__ int wtot[kClsThreads / 64][4];
+  __shared__ int wtot[kClsThreads / 64][kNCls];
   const int64_t base = (int64_t)blockIdx.x * kClsChunk;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  int64_t off[4];
+  int64_t off[kNCls];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) off[c] = a.boff[c * a.n_blk + blockIdx.x];
+  for (int c = 0; c < kNCls; ++c) off[c] = a.boff[c * a.n_blk + blockIdx.x];
   for (int i = 0; i < kClsPer; ++i) {
     const int64_t pr = base + i * kClsThreads + threadIdx.x;
-    const int c = pr < a.n_pairs ? (int)(a.cls[pr] & 3) : -1;
-    uint64_t m[4];
+    const int c = pr < a.n_pairs ? (int)(a.cls[pr] & 7) : -1;
+    uint64_t m[kNCls];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) m[k] = __ballot(c == k);
+    for (int k = 0; k < kNCls; ++k) m[k] = __ballot(c == k);
     if (lane == 0) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) wtot[w][k] = __popcll(m[k]);
+      for (int k = 0; k < kNCls; ++k) wtot[w][k] = __popcll(m[k]);
     }
     __syncthreads();
     if (c >= 0) {
-      int64_t o = off[c];
+      int64_t o = 0;
+      uint64_t mc = 0;
+#pragma unroll
+      for (int k = 0; k < kNCls; ++k)
+        if (k == c) {
+          o = off[k];
+          mc = m[k];
+        }
       for (int v = 0; v < w; ++v) o += wtot[v][c];
-      a.list[o + __popcll(m[c] & lt)] = (uint32_t)pr;
+      a.list[o + __popcll(mc & lt)] = (uint32_t)pr;
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < kNCls; ++k)
       for (int v = 0; v < kClsThreads / 64; ++v) off[k] += wtot[v][k];
     __syncthreads();
   }
@@ -1004,6 +1031,55 @@ __global__ void k_tab_build(const double* __restrict__ fx, const double* __restr
   nod[0] = xi1;
   nod[1] = xi2;
   nod[2] = 0.5 * w;  // the kernel's 1/2 of log r^2
+  if (live) koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { row[k] = v; });
+}
+
+// The same tables for classes 2 + c (c = 0..3), rows2 slots each (far
+// nodes, then 7 leaves of nn nodes, padded to a multiple of 4): the leaves
+// are the level-1 children other than c, then the four children of c.
+template <int P>
+__global__ void k_tab_build2(const double* __restrict__ fx, const double* __restrict__ fy,
+                             const double* __restrict__ fw, int nf, int nf4, const double* __restrict__ nx,
+                             const double* __restrict__ ny, const double* __restrict__ nw, int nn, int rows2,
+                             double* __restrict__ nod2, double* __restrict__ tab2) {
+  constexpr int NP = (P + 1) * (P + 2) / 2;
+  constexpr int NPP = 16 * ((NP + 15) / 16);
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= 4 * rows2) return;
+  const int c = g / rows2, r = g - c * rows2;
+  double* row = tab2 + (size_t)g * NPP;
+  double* nod = nod2 + 3 * (size_t)g;
+  for (int k = 0; k < NPP; ++k) row[k] = 0.0;
+  double xi1 = 1.0 / 3.0, xi2 = 1.0 / 3.0, w = 0.0;
+  bool live = false;
+  if (r < nf) {
+    xi1 = fx[r];
+    xi2 = fy[r];
+    w = -fw[r];
+    live = true;
+  } else if (r >= nf4 && r < nf4 + 7 * nn) {
+    const int j = r - nf4, l = j / nn, i = j - l * nn;
+    double sa, sb, ss;
+    if (l < 3) {  // a level-1 child k != c
+      const int k = l + (l >= c ? 1 : 0);
+      sa = (k == 1 || k == 3) ? 0.5 : 0.0;
+      sb = (k >= 2) ? 0.5 : 0.0;
+      ss = (k == 3) ? -0.5 : 0.5;
+    } else {  // child l - 3 of c
+      const int k = l - 3;
+      const double ca = (c == 1 || c == 3) ? 0.5 : 0.0, cb = (c >= 2) ? 0.5 : 0.0, h = (c == 3) ? -0.25 : 0.25;
+      sa = ca + ((k == 1 || k == 3) ? h : 0.0);
+      sb = cb + ((k >= 2) ? h : 0.0);
+      ss = (k == 3) ? -h : h;
+    }
+    xi1 = sa + ss * nx[i];
+    xi2 = sb + ss * ny[i];
+    w = nw[i] * ss * ss;
+    live = true;
+  }
+  nod[0] = xi1;
+  nod[1] = xi2;
+  nod[2] = 0.5 * w;
   if (live) koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { row[k] = v; });
 }
 
@@ -1113,25 +1189,28 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
   const int64_t n = pl->n_pairs;
   const int64_t n_blk = (n + kClsChunk - 1) / kClsChunk;
   const int nf = pl->n_f, nf4 = (nf + 3) & ~3, nn = a.nn, nn4 = (nn + 3) & ~3;
-  const int rows0 = nf4 + nn4, rows1 = nf4 + 4 * nn;
+  const int rows0 = nf4 + nn4, rows1 = nf4 + 4 * nn, rows2 = (nf4 + 7 * nn + 3) & ~3;
   Scratch tmp(pl->ctx, st);
   uint8_t* cls = nullptr;
   int32_t* bcnt = nullptr;
   int64_t* boff = nullptr;
   uint32_t* list = nullptr;
   double *nod0 = nullptr, *nod1 = nullptr, *tab0 = nullptr, *tab1 = nullptr, *nr = nullptr;
+  double *nod2 = nullptr, *tab2 = nullptr;
   void* stmp = nullptr;
   hipError_t e;
   if ((e = tmp.alloc((void**)&cls, (size_t)n)) != hipSuccess ||
       (e = tmp.alloc((void**)&nr, sizeof(double) * 6 * std::max<int64_t>(pl->n_tri, 1))) != hipSuccess ||
-      (e = tmp.alloc((void**)&bcnt, sizeof(int32_t) * 4 * n_blk)) != hipSuccess ||
-      (e = tmp.alloc((void**)&boff, sizeof(int64_t) * (4 * n_blk + 1))) != hipSuccess ||
+      (e = tmp.alloc((void**)&bcnt, sizeof(int32_t) * kNCls * n_blk)) != hipSuccess ||
+      (e = tmp.alloc((void**)&boff, sizeof(int64_t) * (kNCls * n_blk + 1))) != hipSuccess ||
       (e = tmp.alloc((void**)&list, sizeof(uint32_t) * n)) != hipSuccess ||
-      (e = tmp.alloc(&stmp, exclusive_scan_tmp_bytes(4 * n_blk))) != hipSuccess ||
+      (e = tmp.alloc(&stmp, exclusive_scan_tmp_bytes(kNCls * n_blk))) != hipSuccess ||
       (e = tmp.alloc((void**)&nod0, sizeof(double) * 3 * rows0)) != hipSuccess ||
       (e = tmp.alloc((void**)&nod1, sizeof(double) * 3 * rows1)) != hipSuccess ||
       (e = tmp.alloc((void**)&tab0, sizeof(double) * rows0 * NPP)) != hipSuccess ||
-      (e = tmp.alloc((void**)&tab1, sizeof(double) * rows1 * NPP)) != hipSuccess)
+      (e = tmp.alloc((void**)&tab1, sizeof(double) * rows1 * NPP)) != hipSuccess ||
+      (e = tmp.alloc((void**)&nod2, sizeof(double) * 3 * 4 * rows2)) != hipSuccess ||
+      (e = tmp.alloc((void**)&tab2, sizeof(double) * 4 * rows2 * NPP)) != hipSuccess)
     return e;
   ClassArgs c;
   c.pair_tri = pl->pair_tri;
@@ -1169,58 +1248,79 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
   k_tab_build<P><<<(rows0 + rows1 + 127) / 128, 128, 0, st>>>(pl->far_x, pl->far_y, pl->far_w, nf, nf4,
                                                               pl->near_x, pl->near_y, pl->near_w, nn, nn4, nod0,
                                                               nod1, tab0, tab1);
-  int64_t tot[5] = {0, 0, 0, 0, 0};
-  if ((e = hipGetLastError()) != hipSuccess || (e = exclusive_scan_i32(bcnt, boff, 4 * n_blk, stmp, st)) != hipSuccess)
+  k_tab_build2<P><<<(4 * rows2 + 127) / 128, 128, 0, st>>>(pl->far_x, pl->far_y, pl->far_w, nf, nf4, pl->near_x,
+                                                          pl->near_y, pl->near_w, nn, rows2, nod2, tab2);
+  // first pair of each class in the sorted list, and the total
+  int64_t tot[kNCls + 1] = {};
+  if ((e = hipGetLastError()) != hipSuccess ||
+      (e = exclusive_scan_i32(bcnt, boff, kNCls * n_blk, stmp, st)) != hipSuccess)
     return e;
-  for (int k = 0; k < 4; ++k)
+  for (int k = 0; k <= kNCls; ++k)
     if ((e = hipMemcpyAsync(&tot[k], boff + k * n_blk, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
       return e;
-  if ((e = hipMemcpyAsync(&tot[4], boff + 4 * n_blk, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess ||
-      (e = hipStreamSynchronize(st)) != hipSuccess)
-    return e;
-  const int64_t n0 = tot[1] - tot[0], n1 = tot[2] - tot[1], n2 = tot[3] - tot[2], n3 = tot[4] - tot[3];
-  if (n0 + n1 + n2 + n3 != n) return hipErrorUnknown;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+  int64_t cnt[kNCls];
+  for (int k = 0; k < kNCls; ++k) cnt[k] = tot[k + 1] - tot[k];
+  if (tot[kNCls] != n) return hipErrorUnknown;
   k_pair_scatter<<<(unsigned)n_blk, kClsThreads, 0, st>>>(c);
-  if (n0 + n1 > 0) {
-    TabArgs ta;
-    ta.list = list;
-    ta.n0 = n0;
-    ta.n1 = n1;
-    ta.pair_tri = pl->pair_tri;
-    ta.pair_tgt = pl->pair_tgt;
-    ta.xt = pl->xt;
-    ta.yt = pl->yt;
-    ta.ax = m->ax;
-    ta.ay = m->ay;
-    ta.bx = m->bx;
-    ta.by = m->by;
-    ta.cx = m->cx;
-    ta.cy = m->cy;
-    ta.det = m->det;
-    ta.rows0 = rows0;
-    ta.rows1 = rows1;
-    ta.nod0 = nod0;
-    ta.nod1 = nod1;
-    ta.tab0 = tab0;
-    ta.tab1 = tab1;
-    ta.logtab = pl->logtab;
-    ta.rows = pl->rows;
-    const int64_t tiles = (n0 + 15) / 16 + (n1 + 15) / 16;
+  TabArgs ta;
+  ta.pair_tri = pl->pair_tri;
+  ta.pair_tgt = pl->pair_tgt;
+  ta.xt = pl->xt;
+  ta.yt = pl->yt;
+  ta.ax = m->ax;
+  ta.ay = m->ay;
+  ta.bx = m->bx;
+  ta.by = m->by;
+  ta.cx = m->cx;
+  ta.cy = m->cy;
+  ta.det = m->det;
+  ta.logtab = pl->logtab;
+  ta.rows = pl->rows;
+  const int64_t n_tab = cnt[0] + cnt[1] + cnt[2] + cnt[3] + cnt[4] + cnt[5];
+  if (n_tab > 0) {
     StageTimer tm(pl->ctx, VP_STAGE_ROWS_TAB);
-    // class 0's table in LDS while it is small (the common class)
-    const size_t lds = sizeof(double) * 3 * (size_t)(rows0 + rows1);
-    const size_t t0_bytes = sizeof(double) * (size_t)rows0 * NPP;
-    const unsigned nb = (unsigned)std::min<int64_t>((tiles + 3) / 4, 1 << 20);
-    if (t0_bytes <= kTabT0LdsMax)
-      k_rows_tab<P, true><<<nb, 256, lds + t0_bytes, st>>>(ta);
-    else
-      k_rows_tab<P, false><<<nb, 256, lds, st>>>(ta);
-    tm.stop(1);
+    int launches = 0;
+    // classes (0, 1), (2, 3) and (4, 5), two per launch: each launch holds
+    // its two classes' node tables in LDS, and class 0's Koornwinder table
+    // while it is small (the common class)
+    for (int k = 0; k < 6; k += 2) {
+      if (cnt[k] + cnt[k + 1] == 0) continue;
+      ta.list = list + tot[k];
+      ta.n0 = cnt[k];
+      ta.n1 = cnt[k + 1];
+      if (k == 0) {
+        ta.rows0 = rows0;
+        ta.rows1 = rows1;
+        ta.nod0 = nod0;
+        ta.nod1 = nod1;
+        ta.tab0 = tab0;
+        ta.tab1 = tab1;
+      } else {
+        const int c0 = k - 2;  // configurations c0 and c0 + 1 of the class-2 tables
+        ta.rows0 = ta.rows1 = rows2;
+        ta.nod0 = nod2 + 3 * (size_t)c0 * rows2;
+        ta.nod1 = nod2 + 3 * (size_t)(c0 + 1) * rows2;
+        ta.tab0 = tab2 + (size_t)c0 * rows2 * NPP;
+        ta.tab1 = tab2 + (size_t)(c0 + 1) * rows2 * NPP;
+      }
+      const int64_t tiles = (ta.n0 + 15) / 16 + (ta.n1 + 15) / 16;
+      const size_t lds = sizeof(double) * 3 * (size_t)(ta.rows0 + ta.rows1);
+      const size_t t0_bytes = sizeof(double) * (size_t)ta.rows0 * NPP;
+      const unsigned nb = (unsigned)std::min<int64_t>((tiles + 3) / 4, 1 << 20);
+      if (t0_bytes <= kTabT0LdsMax)
+        k_rows_tab<P, true><<<nb, 256, lds + t0_bytes, st>>>(ta);
+      else
+        k_rows_tab<P, false><<<nb, 256, lds, st>>>(ta);
+      ++launches;
+    }
+    tm.stop(launches);
   }
   constexpr int64_t kPairsPerGroup = 8;
   auto groups = [&](int64_t k) {
     return dim3((unsigned)std::min<int64_t>((k + kPairsPerGroup - 1) / kPairsPerGroup, 1 << 25));
   };
+  const int64_t n2 = cnt[kClsDeep], n3 = cnt[kClsSelf];
   if (n2 > 0) {
     uint32_t* ovf = nullptr;
     uint32_t* n_ovf = nullptr;
@@ -1228,7 +1328,7 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
         (e = tmp.alloc((void**)&n_ovf, sizeof(uint32_t))) != hipSuccess ||
         (e = hipMemsetAsync(n_ovf, 0, sizeof(uint32_t), st)) != hipSuccess)
       return e;
-    a.list = list + n0 + n1;
+    a.list = list + tot[kClsDeep];
     a.n_list = n2;
     StageTimer tm(pl->ctx, VP_STAGE_ROWS_NEAR);
     const size_t lds_deep = sizeof(double) * (3 * (size_t)nn + 2 * (size_t)nf);
@@ -1246,15 +1346,16 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
     tm.stop(h_ovf > 0 ? 2 : 1);
   }
   if (n3 > 0) {
-    a.list = list + n0 + n1 + n2;
+    a.list = list + tot[kClsSelf];
     a.n_list = n3;
     StageTimer tm(pl->ctx, VP_STAGE_ROWS_SELF);
     k_rows<P, false, 2><<<groups(n3), 64, lds, st>>>(a);
     tm.stop(1);
   }
-  // the table path's leaves: one per class-0 pair, four per class-1 pair
-  pl->tab_leaves = n0 + 4 * n1;
-  pl->tab_pairs = n0 + n1;
+  // the table path's leaves: one per class-0 pair, four per class-1 pair,
+  // seven per class 2..5 pair
+  pl->tab_leaves = cnt[0] + 4 * cnt[1] + 7 * (cnt[2] + cnt[3] + cnt[4] + cnt[5]);
+  pl->tab_pairs = n_tab;
   if ((e = hipGetLastError()) != hipSuccess) return e;
   tmp.release();
   return hipSuccess;
@@ -1329,7 +1430,9 @@ hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t s
   // straight meshes with the ellipse model: pairs sorted by depth class,
   // shallow near pairs on the matrix cores, deeper near pairs and self
   // pairs by k_rows, each launch sized to its pairs
-  const int nf4 = (pl->n_f + 3) & ~3, slots = 2 * nf4 + ((a.nn + 3) & ~3) + 4 * a.nn;  // both classes' slots
+  // LDS slots of the larger launch: classes 0 and 1, or two class-2 tables
+  const int nf4 = (pl->n_f + 3) & ~3, rows2 = (nf4 + 7 * a.nn + 3) & ~3;
+  const int slots = std::max(2 * nf4 + ((a.nn + 3) & ~3) + 4 * a.nn, 2 * rows2);
   if (!curved && !a.ball && a.nn <= kTabNearMax && slots <= kTabSlotsMax && pl->n_pairs < ((int64_t)1 << 32)) {
     switch (pl->p) {
       case 1: return rows_by_class<1>(pl, a, lds, st);
