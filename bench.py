@@ -150,14 +150,18 @@ def stage_rooflines(info, tm, steps, q_near=7, n_l=16):
     out = {}
 
     def alu(name, stage, nodes, fpn, kernel):
+        # nodes are one step's; a stage of several launches per step (the
+        # table path runs one per pair of depth classes) is taken as a whole
         ms, n = tm.get(stage, (0.0, 0))
         if not n:
             return
-        sec = ms / 1e3 / n
+        sec = ms / 1e3 / steps
         ach = nodes * fpn / sec / 1e12
         out[name] = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "node_evaluations": nodes, "flops_per_node": fpn,
-                     "avg_launch_ms": sec * 1e3, "kernel": kernel}
+                     "ms_per_step": sec * 1e3, "launches_per_step": n / steps, "kernel": kernel}
+        if n == steps:
+            out[name]["avg_launch_ms"] = sec * 1e3
 
     near_deep = n_pairs - n_self - tab_pairs
     p = info["p"]
@@ -230,16 +234,15 @@ LOG_DIGEST_PART = ("vp_internal.h", "constexpr double kR2Bias", "void vp_log_wid
 FAR64_DIGEST_PARTS = [("vp_exec.hip", "template <int S, int RB>\nstruct FarShape {", "void k_far("), LOG_DIGEST_PART]
 FAR32_DIGEST_PARTS = [("vp_exec.hip", "template <int RB, int TPT>\n__global__ __launch_bounds__(kBlock) void k_far32(",
                        "void k_far32("), LOG_DIGEST_PART]
-ROWS_DIGEST_PARTS = [("vp_rows.hip", "__device__ __forceinline__ int dyadic_count", "void k_rows(RowsArgs a)"),
-                     ("vp_rows.hip", "constexpr int kDeepLv", "void k_rows_deep("),
-                     ("vp_rows.hip", "struct TabArgs {", "void k_rows_tab(TabArgs a)")]
+# the row kernels and the pair classification that decides which of them takes a pair
+ROWS_DIGEST_PARTS = [("vp_rows.hip", "__device__ __forceinline__ int dyadic_count", "hipError_t rows_by_class(")]
 
 
 def traffic_from(summary, digest, kernel_key):
     f = counter_summary(summary)
     if f.get("kernel_source_sha256_16") != digest:
         return None
-    v = f.get(f"{kernel_key}_traffic_bytes_per_launch")
+    v = f.get(f"{kernel_key}_traffic_bytes_per_step")
     return float(v) if v else None
 
 
@@ -553,11 +556,17 @@ def run(args, pool, n_workers):
     dt, info, tm = timed_steps(ctx, step_of(**FMM), args.steps, args.warmup)
     u_fmm = out[sample_d, 0].cpu().numpy()
     stages = stage_rooflines(info, tm, args.steps)
-    timed = {k: v for k, v in stages.items() if "avg_launch_ms" in v}
-    dom_name = max(timed, key=lambda k: timed[k]["avg_launch_ms"])
+    timed = {k: v for k, v in stages.items() if "ms_per_step" in v}
+    dom_name = max(timed, key=lambda k: timed[k]["ms_per_step"])
     dom = dict(timed[dom_name])
     digest = source_digest(ROWS_DIGEST_PARTS)
     dom["traffic"] = traffic_from("k_rows_lshape250k_q4_counters.md", digest, dom_name)
+    rc = counter_summary("k_rows_lshape250k_q4_counters.md")
+    vi = rc.get(f"{dom_name}_valu_instructions_per_step")
+    if vi and rc.get("kernel_source_sha256_16") == digest:
+        # wave64 vector instructions of the stage against one per 4 cycles on each SIMD
+        dom["valu_issue"] = {"instructions_per_step": float(vi),
+                             "frac": float(vi) * 64 / (dom["ms_per_step"] / 1e3) / PEAK_VALU_LANE_INSTS}
     dom["stage"] = dom_name
     result = {
         "metric": METRIC,
