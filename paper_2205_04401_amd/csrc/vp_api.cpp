@@ -156,9 +156,13 @@ vp_status vp_ctx_create(int device, void* stream, uint64_t budget, vp_ctx** out)
   VP_HIP(vp::noalloc_setup(device), "vp_ctx_create: address of the allocation-free workspace");
   size_t dev_free = 0, dev_total = 0;
   VP_HIP(hipMemGetInfo(&dev_free, &dev_total), "vp_ctx_create: hipMemGetInfo");
+  int n_cu = 0;
+  VP_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device),
+         "vp_ctx_create: compute unit count");
   vp_ctx* c = new vp_ctx;
   c->cache_cap = dev_total / 4;
   c->device = device;
+  c->n_cu = std::max(n_cu, 1);
   c->stream = (hipStream_t)stream;
   c->budget = budget;
   *out = c;

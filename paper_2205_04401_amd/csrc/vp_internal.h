@@ -351,6 +351,7 @@ __device__ __forceinline__ void vp_log_wide_parts(double x, const double2* tab, 
 
 struct vp_ctx {
   int device = 0;
+  int n_cu = 0;  // compute units of the device
   hipStream_t stream = nullptr;
   uint64_t budget = 0;
   uint64_t in_use = 0;     // device bytes held (plans, workspaces, meshes, ...), cached blocks excluded

@@ -229,7 +229,7 @@ __global__ void k_tri_ellipses(const double* __restrict__ ax, const double* __re
                                const double* __restrict__ cx, const double* __restrict__ cy,
                                const double* __restrict__ det, int64_t n_tri, double w0, double w1, double w2,
                                double eps_cn, double inv_order, int ball, double kappa, CurveView cv,
-                               double* thr /* [3][n_tri] */, double* box /* [4][n_tri] */) {
+                               double* thr /* [3][n_tri] */, double* box /* [n_tri][4] */) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_tri) return;
   const double px[3] = {ax[t], bx[t], cx[t]};
@@ -266,10 +266,10 @@ __global__ void k_tri_ellipses(const double* __restrict__ ax, const double* __re
     thr[t] = kappa * R;
     thr[n_tri + t] = -1.0;
     thr[2 * n_tri + t] = -1.0;
-    box[t] = x0;
-    box[n_tri + t] = y0;
-    box[2 * n_tri + t] = x1;
-    box[3 * n_tri + t] = y1;
+    box[4 * t] = x0;
+    box[4 * t + 1] = y0;
+    box[4 * t + 2] = x1;
+    box[4 * t + 3] = y1;
     return;
   }
   for (int e = 0; e < 3; ++e) {
@@ -292,10 +292,10 @@ __global__ void k_tri_ellipses(const double* __restrict__ ax, const double* __re
     }
     thr[e * n_tri + t] = s;
   }
-  box[t] = x0;
-  box[n_tri + t] = y0;
-  box[2 * n_tri + t] = x1;
-  box[3 * n_tri + t] = y1;
+  box[4 * t] = x0;
+  box[4 * t + 1] = y0;
+  box[4 * t + 2] = x1;
+  box[4 * t + 3] = y1;
 }
 
 // bounding box of the targets and mean box extent: partial reductions
@@ -311,7 +311,7 @@ __global__ void k_extent_partial(const double* __restrict__ xt, const double* __
     mxy = fmax(mxy, yt[i]);
   }
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_tri; i += stride) {
-    sum += fmax(box[2 * n_tri + i] - box[i], box[3 * n_tri + i] - box[n_tri + i]);
+    sum += fmax(box[4 * i + 2] - box[4 * i], box[4 * i + 3] - box[4 * i + 1]);
   }
   const int tid = threadIdx.x;
   s[0][tid] = mnx;
@@ -356,7 +356,7 @@ __global__ void k_cell_count(const double* __restrict__ box, int64_t n_tri, Grid
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_tri) return;
   int i0, i1, j0, j1;
-  if (!box_cells(g, box[t], box[n_tri + t], box[2 * n_tri + t], box[3 * n_tri + t], i0, i1, j0, j1)) return;
+  if (!box_cells(g, box[4 * t], box[4 * t + 1], box[4 * t + 2], box[4 * t + 3], i0, i1, j0, j1)) return;
   for (int j = j0; j <= j1; ++j)
     for (int i = i0; i <= i1; ++i) atomicAdd(&cnt[(int64_t)j * g.nx + i], 1);
 }
@@ -366,7 +366,7 @@ __global__ void k_cell_tcount(const double* __restrict__ box, int64_t n_tri, Gri
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_tri) return;
   int i0, i1, j0, j1;
-  tcnt[t] = box_cells(g, box[t], box[n_tri + t], box[2 * n_tri + t], box[3 * n_tri + t], i0, i1, j0, j1)
+  tcnt[t] = box_cells(g, box[4 * t], box[4 * t + 1], box[4 * t + 2], box[4 * t + 3], i0, i1, j0, j1)
                 ? (i1 - i0 + 1) * (j1 - j0 + 1)
                 : 0;
 }
@@ -379,7 +379,7 @@ __global__ void k_cell_emit(const double* __restrict__ box, int64_t n_tri, Grid 
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_tri) return;
   int i0, i1, j0, j1;
-  if (!box_cells(g, box[t], box[n_tri + t], box[2 * n_tri + t], box[3 * n_tri + t], i0, i1, j0, j1)) return;
+  if (!box_cells(g, box[4 * t], box[4 * t + 1], box[4 * t + 2], box[4 * t + 3], i0, i1, j0, j1)) return;
   int64_t o = toff[t];
   for (int j = j0; j <= j1; ++j)
     for (int i = i0; i <= i1; ++i) {
@@ -395,6 +395,11 @@ struct TriView {
   int ball;      // naive ball model (in_ball3)
   double kappa;  // its factor
   CurveView cv;  // curved triangles
+  // near-field boxes [n_tri][4] (k_tri_ellipses); box_reject: a target
+  // outside its triangle's box is far without the tests (the boxes hold the
+  // self region for tau up to 1e-10)
+  const double* box;
+  int box_reject;
 };
 
 // 0 = self, 1 = near, 2 = far
@@ -402,6 +407,10 @@ struct TriView {
 // none of their code)
 template <bool kCurved>
 __device__ __forceinline__ int classify(const TriView& tv, int32_t t, double x, double y, double tau) {
+  if (tv.box_reject) {
+    const double4 b = *(const double4*)(tv.box + 4 * (int64_t)t);
+    if (x < b.x || y < b.y || x > b.z || y > b.w) return 2;
+  }
   const double Ax = tv.ax[t], Ay = tv.ay[t], Bx = tv.bx[t], By = tv.by[t], Cx = tv.cx[t], Cy = tv.cy[t];
   const double D = tv.det[t];
   const double d0 = x - Ax, d1 = y - Ay;
@@ -429,15 +438,13 @@ __device__ __forceinline__ int classify(const TriView& tv, int32_t t, double x, 
     const double px[3] = {Ax, Bx, Cx}, py[3] = {Ay, By, Cy};
     return in_ball3(x, y, px, py, tv.kappa) ? 1 : 2;
   }
-  const double px[3] = {Ax, Bx, Cx}, py[3] = {Ay, By, Cy};
-#pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    const double s = tv.thr[e * tv.n_tri + t];
-    if (s <= 0.0) continue;
-    const double Px = px[e], Py = py[e], Qx = px[(e + 1) % 3], Qy = py[(e + 1) % 3];
-    const double fs = sqrt((x - Px) * (x - Px) + (y - Py) * (y - Py)) + sqrt((x - Qx) * (x - Qx) + (y - Qy) * (y - Qy));
-    if (fs < s) return 1;
-  }
+  // the ellipse of edge e (foci at its ends): the focal sum from the
+  // target's distances to the three vertices
+  const double dA = sqrt((x - Ax) * (x - Ax) + (y - Ay) * (y - Ay));
+  const double dB = sqrt((x - Bx) * (x - Bx) + (y - By) * (y - By));
+  const double dC = sqrt((x - Cx) * (x - Cx) + (y - Cy) * (y - Cy));
+  const double s0 = tv.thr[t], s1 = tv.thr[tv.n_tri + t], s2 = tv.thr[2 * tv.n_tri + t];
+  if ((s0 > 0.0 && dA + dB < s0) || (s1 > 0.0 && dB + dC < s1) || (s2 > 0.0 && dC + dA < s2)) return 1;
   return 2;
 }
 
@@ -895,8 +902,20 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
       }
     }
   }
-  TriView tv{m->ax, m->ay, m->bx, m->by, m->cx, m->cy, m->det, thr, T, pl->opts.near_model == VP_NEAR_BALL ? 1 : 0,
-             pl->opts.ball_factor, m->curves()};
+  TriView tv{m->ax,
+             m->ay,
+             m->bx,
+             m->by,
+             m->cx,
+             m->cy,
+             m->det,
+             thr,
+             T,
+             pl->opts.near_model == VP_NEAR_BALL ? 1 : 0,
+             pl->opts.ball_factor,
+             m->curves(),
+             box,
+             pl->opts.tau <= 1e-10 ? 1 : 0};
   // decision bits of every (target, cell triangle): word offsets per target
   int32_t* wcnt = nullptr;
   int64_t* woff = nullptr;

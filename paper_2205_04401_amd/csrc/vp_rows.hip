@@ -837,8 +837,12 @@ constexpr int kClsThreads = 256;
 constexpr int kClsPer = 4;                              // pairs per thread
 constexpr int kClsChunk = kClsThreads * kClsPer;        // pairs per block
 constexpr int kTabNearMax = 64;                         // near-rule nodes of the table path (q_near <= 8)
-constexpr int kTabSlotsMax = 2048;                      // slots of one launch's two classes (LDS: 24 bytes each)
-constexpr size_t kTabT0LdsMax = 16384;                  // class 0's Koornwinder table in LDS up to this size
+constexpr int kTabSlotsMax = 2048;                      // slots of one launch's two classes (LDS: 16 bytes each)
+constexpr int kTabThreads = 512;                        // 8 wavefronts share one block's LDS tables
+constexpr int kTabWaves = kTabThreads / 64;
+constexpr size_t kTabLdsBlock = 53248;                  // LDS of one block for 3 blocks (24 wavefronts) per CU
+constexpr size_t kTabT0LdsMax = 16384;                  // class 0's Koornwinder table alone in LDS up to this size
+constexpr int kTabBlocksPerCu = 12;                     // grid: 4 rounds of 3 resident blocks per CU
 
 struct ClassArgs {
   const int32_t *pair_tri, *pair_tgt;
@@ -846,7 +850,7 @@ struct ClassArgs {
   int64_t n_pairs, n_blk;
   const double *xt, *yt;
   const double *ax, *ay, *bx, *by, *cx, *cy, *det, *deff;
-  const double* nr;  // [6][n_tri] near-rule rho0 and edge lengths (k_near_root)
+  const double* nr;  // [15][n_tri] near-rule rho0, edge lengths, thresholds of levels 0-2 (k_near_root)
   int64_t n_tri;
   double nwhat0, nwhat1, nwhat2, eps_cn, inv_near_order;
   int depth_cap;
@@ -858,46 +862,58 @@ struct ClassArgs {
 
 // depth class of near pair pr: the tests of k_rows' first levels; for a
 // deep pair (class 6) the bits 4..7 hold which of the four level-1 children
-// split
+// split.  The tests of levels 0-2 take their focal-sum thresholds from the
+// triangle's table (k_near_root) and the target's distance to each vertex of
+// the sub-triangles once: the 3 vertices and 3 edge midpoints of the triangle,
+// then the 3 edge midpoints of the one child that splits.
 __device__ __forceinline__ int pair_class(const ClassArgs& a, int64_t pr) {
   if (a.pair_kind[pr] != 1) return kClsSelf;
   const int32_t t = a.pair_tri[pr];
   const int32_t it = a.pair_tgt[pr];
   const double x = a.xt[it], y = a.yt[it];
-  const double Ax = a.ax[t], Ay = a.ay[t], Bx = a.bx[t], By = a.by[t], Cx = a.cx[t], Cy = a.cy[t];
-  const double e1x = Bx - Ax, e1y = By - Ay, e2x = Cx - Ax, e2y = Cy - Ay;
-  double rho0[3], ell0[3], thr[3];
-#pragma unroll
-  for (int e = 0; e < 3; ++e) {
-    rho0[e] = a.nr[e * a.n_tri + t];
-    ell0[e] = a.nr[(3 + e) * a.n_tri + t];
-  }
-  near_level_thr(rho0, ell0, 0, a.inv_near_order, thr);
-  if (!(0 < a.depth_cap && near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.0, 0.0, 1.0, thr))) return 0;
+  const double Ax = a.ax[t], Ay = a.ay[t];
+  const double e1x = a.bx[t] - Ax, e1y = a.by[t] - Ay, e2x = a.cx[t] - Ax, e2y = a.cy[t] - Ay;
+  const double* thr = a.nr + 6 * a.n_tri + t;  // thr[(3 L + e) n_tri]: level L, edge e
+  auto T = [&](int level, int e) { return thr[(3 * level + e) * a.n_tri]; };
+  // distance from the target to the point (u, v) of the reference simplex
+  auto dist = [&](double u, double v) {
+    const double px = fma(v, e2x, fma(u, e1x, Ax)), py = fma(v, e2y, fma(u, e1y, Ay));
+    return sqrt((x - px) * (x - px) + (y - py) * (y - py));
+  };
+  // a sub-triangle with vertex distances d0, d1, d2 (edges p0p1, p1p2, p2p0)
+  auto split = [&](int level, double d0, double d1, double d2) {
+    return d0 + d1 < T(level, 0) || d1 + d2 < T(level, 1) || d2 + d0 < T(level, 2);
+  };
+  if (!(0 < a.depth_cap)) return 0;
+  const double dA = dist(0.0, 0.0), dB = dist(1.0, 0.0), dC = dist(0.0, 1.0);
+  if (!split(0, dA, dB, dC)) return 0;
   if (!(1 < a.depth_cap)) return 1;
-  near_level_thr(rho0, ell0, 1, a.inv_near_order, thr);
-  const int mask = (near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.0, 0.0, 0.5, thr) ? 1 : 0) |
-                   (near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.5, 0.0, 0.5, thr) ? 2 : 0) |
-                   (near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.0, 0.5, 0.5, thr) ? 4 : 0) |
-                   (near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, 0.5, 0.5, -0.5, thr) ? 8 : 0);
+  const double dAB = dist(0.5, 0.0), dAC = dist(0.0, 0.5), dBC = dist(0.5, 0.5);
+  // children (a, s): ((0,0), 1/2), ((1/2,0), 1/2), ((0,1/2), 1/2), ((1/2,1/2), -1/2)
+  const int mask = (split(1, dA, dAB, dAC) ? 1 : 0) | (split(1, dAB, dB, dBC) ? 2 : 0) |
+                   (split(1, dAC, dBC, dC) ? 4 : 0) | (split(1, dBC, dAC, dAB) ? 8 : 0);
   if (!mask) return 1;
   if (mask & (mask - 1)) return kClsDeep | (mask << 4);
   // one child c splits: class 2 + c if none of its four children splits
   const int c = __ffs(mask) - 1;
   if (2 < a.depth_cap) {
     const double sa = (c == 1 || c == 3) ? 0.5 : 0.0, sb = (c >= 2) ? 0.5 : 0.0, h = (c == 3) ? -0.25 : 0.25;
-    near_level_thr(rho0, ell0, 2, a.inv_near_order, thr);
-    if (near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, sa, sb, h, thr) ||
-        near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, sa + h, sb, h, thr) ||
-        near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, sa, sb + h, h, thr) ||
-        near_sub_split(x, y, Ax, Ay, e1x, e1y, e2x, e2y, sa + h, sb + h, -h, thr))
+    // the child's vertices p0 = (sa, sb), p1 = p0 + 2h e1, p2 = p0 + 2h e2
+    // and its edge midpoints
+    const double q0 = c == 0 ? dA : c == 1 ? dAB : c == 2 ? dAC : dBC;
+    const double q1 = c == 0 ? dAB : c == 1 ? dB : c == 2 ? dBC : dAC;
+    const double q2 = c == 0 ? dAC : c == 1 ? dBC : c == 2 ? dC : dAB;
+    const double m01 = dist(sa + h, sb), m02 = dist(sa, sb + h), m12 = dist(sa + h, sb + h);
+    if (split(2, q0, m01, m02) || split(2, m01, q1, m12) || split(2, m02, m12, q2) || split(2, m12, m02, m01))
       return kClsDeep | (mask << 4);
   }
   return 2 + c;
 }
 
-// near-rule rho0 and edge lengths of every triangle: nr[e][T] = rho0_e,
-// nr[3 + e][T] = l_e (the values k_rows computes for each pair)
+// near-rule rho0, edge lengths and the focal-sum thresholds of levels 0-2
+// of every triangle: nr[e][T] = rho0_e, nr[3 + e][T] = l_e (the values
+// k_rows computes for each pair), nr[6 + 3 L + e][T] = threshold of edge e
+// at level L
 __global__ void k_near_root(const double* __restrict__ ax, const double* __restrict__ ay,
                             const double* __restrict__ bx, const double* __restrict__ by,
                             const double* __restrict__ cx, const double* __restrict__ cy,
@@ -912,6 +928,13 @@ __global__ void k_near_root(const double* __restrict__ ax, const double* __restr
   for (int e = 0; e < 3; ++e) {
     nr[e * n_tri + t] = rho0[e];
     nr[(3 + e) * n_tri + t] = ell0[e];
+  }
+#pragma unroll
+  for (int level = 0; level < 3; ++level) {
+    double thr[3];
+    near_level_thr(rho0, ell0, level, inv_near_order, thr);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) nr[(6 + 3 * level + e) * n_tri + t] = thr[e];
   }
 }
 
@@ -983,17 +1006,17 @@ __global__ __launch_bounds__(kClsThreads) void k_pair_scatter(ClassArgs a) {
 
 // Reference data of the two classes, one row per slot (far nodes first,
 // padded to a multiple of 4, then the near rule's nodes): node tables
-// [rows][3] (xi1, xi2 and half the weight: -w_j / 2 of the far rule,
-// subtracted, or w_j s^2 / 2 of a leaf of scale s, the 1/2 of log r^2;
-// 0 in padding rows, placed at the centroid)
-// and Koornwinder tables [rows][NPP] (zero rows and columns as padding).
+// [rows] (xi1, xi2; the centroid in padding rows) and Koornwinder tables
+// [rows][NPP] scaled by half the node's weight: -w_j / 2 of the far rule,
+// subtracted, or w_j s^2 / 2 of a leaf of scale s, the 1/2 of log r^2 (zero
+// rows and columns as padding).
 // Class 0: the near rule on the simplex; class 1: on its four children
 // (a, s) = ((0,0), 1/2), ((1/2,0), 1/2), ((0,1/2), 1/2), ((1/2,1/2), -1/2).
 template <int P>
 __global__ void k_tab_build(const double* __restrict__ fx, const double* __restrict__ fy,
                             const double* __restrict__ fw, int nf, int nf4, const double* __restrict__ nx,
                             const double* __restrict__ ny, const double* __restrict__ nw, int nn, int nn4,
-                            double* __restrict__ nod0, double* __restrict__ nod1, double* __restrict__ tab0,
+                            double2* __restrict__ nod0, double2* __restrict__ nod1, double* __restrict__ tab0,
                             double* __restrict__ tab1) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
   constexpr int NPP = 16 * ((NP + 15) / 16);
@@ -1003,7 +1026,7 @@ __global__ void k_tab_build(const double* __restrict__ fx, const double* __restr
   const bool one = g >= rows0;
   const int r = one ? g - rows0 : g;
   double* row = (one ? tab1 : tab0) + (size_t)r * NPP;
-  double* nod = (one ? nod1 : nod0) + 3 * (size_t)r;
+  double2* nod = (one ? nod1 : nod0) + r;
   for (int k = 0; k < NPP; ++k) row[k] = 0.0;
   double xi1 = 1.0 / 3.0, xi2 = 1.0 / 3.0, w = 0.0;
   bool live = false;
@@ -1028,10 +1051,9 @@ __global__ void k_tab_build(const double* __restrict__ fx, const double* __restr
       live = true;
     }
   }
-  nod[0] = xi1;
-  nod[1] = xi2;
-  nod[2] = 0.5 * w;  // the kernel's 1/2 of log r^2
-  if (live) koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { row[k] = v; });
+  *nod = make_double2(xi1, xi2);
+  const double hw = 0.5 * w;  // the kernel's 1/2 of log r^2
+  if (live) koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { row[k] = hw * v; });
 }
 
 // The same tables for classes 2 + c (c = 0..3), rows2 slots each (far
@@ -1041,14 +1063,14 @@ template <int P>
 __global__ void k_tab_build2(const double* __restrict__ fx, const double* __restrict__ fy,
                              const double* __restrict__ fw, int nf, int nf4, const double* __restrict__ nx,
                              const double* __restrict__ ny, const double* __restrict__ nw, int nn, int rows2,
-                             double* __restrict__ nod2, double* __restrict__ tab2) {
+                             double2* __restrict__ nod2, double* __restrict__ tab2) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
   constexpr int NPP = 16 * ((NP + 15) / 16);
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= 4 * rows2) return;
   const int c = g / rows2, r = g - c * rows2;
   double* row = tab2 + (size_t)g * NPP;
-  double* nod = nod2 + 3 * (size_t)g;
+  double2* nod = nod2 + g;
   for (int k = 0; k < NPP; ++k) row[k] = 0.0;
   double xi1 = 1.0 / 3.0, xi2 = 1.0 / 3.0, w = 0.0;
   bool live = false;
@@ -1077,10 +1099,9 @@ __global__ void k_tab_build2(const double* __restrict__ fx, const double* __rest
     w = nw[i] * ss * ss;
     live = true;
   }
-  nod[0] = xi1;
-  nod[1] = xi2;
-  nod[2] = 0.5 * w;
-  if (live) koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { row[k] = v; });
+  *nod = make_double2(xi1, xi2);
+  const double hw = 0.5 * w;
+  if (live) koornwinder_emit<P>(xi1, xi2, [&](int k, double v) { row[k] = hw * v; });
 }
 
 typedef double vp_d4 __attribute__((ext_vector_type(4)));
@@ -1092,32 +1113,41 @@ struct TabArgs {
   const double *xt, *yt;
   const double *ax, *ay, *bx, *by, *cx, *cy, *det;
   int rows0, rows1;  // slots of class 0 and class 1 (multiples of 4)
-  const double *nod0, *nod1, *tab0, *tab1;
+  const double2 *nod0, *nod1;
+  const double *tab0, *tab1;
   const double2* logtab;
   double* rows;
 };
 
 // (at most 80 registers for 6 wavefronts per SIMD at P <= 4; above, the
-// larger accumulators take 5)
-template <int P, bool kT0Lds>
-__global__ __launch_bounds__(256, (P <= 4) ? 6 : 5) void k_rows_tab(TabArgs a) {
+// larger accumulators take 5).  kLds: 2 both classes' Koornwinder tables in
+// LDS, 1 class 0's only, 0 none (read through the caches).  A block's
+// wavefronts take tiles in turn over the whole list, so the LDS fill of a
+// block is paid once per block of a grid sized to the device.
+template <int P, int kLds>
+__global__ __launch_bounds__(kTabThreads, (P <= 4) ? 6 : 5) void k_rows_tab(TabArgs a) {
   constexpr int NP = (P + 1) * (P + 2) / 2;
   constexpr int NT = (NP + 15) / 16;
   constexpr int NPP = 16 * NT;
   __shared__ double2 tab[kLogTab + 1];
-  // node tables [rows0 + rows1][3], then (kT0Lds) class 0's Koornwinder
-  // table [rows0][NPP]: read at every step, from LDS instead of the cache
-  extern __shared__ double nod[];
-  double* const sT0 = nod + 3 * (a.rows0 + a.rows1);
+  // node tables [rows0 + rows1], then the Koornwinder tables in LDS:
+  // class 0's [rows0][NPP] (kLds >= 1), class 1's [rows1][NPP] (kLds == 2)
+  extern __shared__ double2 nod[];
+  double* const sT0 = (double*)(nod + a.rows0 + a.rows1);
+  double* const sT1 = sT0 + (size_t)a.rows0 * NPP;
   for (int i = threadIdx.x; i <= kLogTab; i += blockDim.x) tab[i] = a.logtab[i];
-  for (int i = threadIdx.x; i < 3 * a.rows0; i += blockDim.x) nod[i] = a.nod0[i];
-  for (int i = threadIdx.x; i < 3 * a.rows1; i += blockDim.x) nod[3 * a.rows0 + i] = a.nod1[i];
-  if (kT0Lds)
+  for (int i = threadIdx.x; i < a.rows0; i += blockDim.x) nod[i] = a.nod0[i];
+  for (int i = threadIdx.x; i < a.rows1; i += blockDim.x) nod[a.rows0 + i] = a.nod1[i];
+  if (kLds >= 1)
     for (int i = threadIdx.x; i < a.rows0 * NPP; i += blockDim.x) sT0[i] = a.tab0[i];
+  if (kLds == 2)
+    for (int i = threadIdx.x; i < a.rows1 * NPP; i += blockDim.x) sT1[i] = a.tab1[i];
   __syncthreads();
   const int lane = threadIdx.x & 63, kq = lane >> 4, col = lane & 15;
   const int64_t t0 = (a.n0 + 15) / 16, n_tiles = t0 + (a.n1 + 15) / 16;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < n_tiles; tile += (int64_t)gridDim.x * 4) {
+  // the tile index is the same in every lane: kept in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  for (int64_t tile = (int64_t)blockIdx.x * kTabWaves + wave; tile < n_tiles; tile += (int64_t)gridDim.x * kTabWaves) {
     const bool one = tile >= t0;
     const int64_t base = one ? a.n0 + (tile - t0) * 16 : tile * 16;
     const int64_t end = one ? a.n0 + a.n1 : a.n0;
@@ -1128,8 +1158,8 @@ __global__ __launch_bounds__(256, (P <= 4) ? 6 : 5) void k_rows_tab(TabArgs a) {
     const double x = a.xt[it], y = a.yt[it];
     const double Ax = a.ax[t], Ay = a.ay[t];
     const double e1x = a.bx[t] - Ax, e1y = a.by[t] - Ay, e2x = a.cx[t] - Ax, e2y = a.cy[t] - Ay;
-    const double Dv = valid ? a.det[t] : 0.0;  // a padding row of the tile gets zero weights
-    const double* N = one ? nod + 3 * a.rows0 : nod;
+    const double D = a.det[t];
+    const double2* N = one ? nod + a.rows0 : nod;
     const int n_slots = one ? a.rows1 : a.rows0;
     vp_d4 acc[NT];
     // zero accumulators made by the matrix core itself, so that they live in
@@ -1139,23 +1169,28 @@ __global__ __launch_bounds__(256, (P <= 4) ? 6 : 5) void k_rows_tab(TabArgs a) {
       acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(0.0, 0.0, vp_d4{0.0, 0.0, 0.0, 0.0}, 0, 0, 0);
     // Every slot alike: the node's position from the triangle's map (for the
     // far nodes the far sums' own expression, so a pair at distance 0
-    // cancels), r^2 with the far sums' offset (far below any near node's
-    // r^2), and the weight from the table (negative for the far rule's own
-    // contribution, which is subtracted; zero in padding rows).
+    // cancels) and r^2 with the far sums' offset (far below any near node's
+    // r^2).  The weights are in the table (negative for the far rule's own
+    // contribution, which is subtracted; zero in padding rows), the
+    // triangle's Jacobian scales the finished row.
     auto steps = [&](auto trow) {
       for (int s0 = 0; s0 < n_slots; s0 += 4) {
         const int slot = s0 + kq;
-        const double xi1 = N[3 * slot], xi2 = N[3 * slot + 1], hw = N[3 * slot + 2];
+        const double2 xi = N[slot];
+        const double xi1 = xi.x, xi2 = xi.y;
         const double yx = Ax + xi1 * e1x + xi2 * e2x;
         const double yy = Ay + xi1 * e1y + xi2 * e2y;
         const double dx = x - yx, dy = y - yy;
         const double r2 = fma(dy, dy, fma(dx, dx, kR2Bias));
-        const double g = vp_log(r2, tab) * (hw * Dv);
+        const double g = vp_log(r2, tab);
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(g, trow(slot, n), acc[n], 0, 0, 0);
       }
     };
-    if (kT0Lds && !one) {
+    if (kLds == 2) {
+      const double* T = one ? sT1 : sT0;
+      steps([&](int slot, int n) { return T[slot * NPP + 16 * n + col]; });
+    } else if (kLds == 1 && !one) {
       steps([&](int slot, int n) { return sT0[slot * NPP + 16 * n + col]; });
     } else {
       const double* T = one ? a.tab1 : a.tab0;
@@ -1166,11 +1201,12 @@ __global__ __launch_bounds__(256, (P <= 4) ? 6 : 5) void k_rows_tab(TabArgs a) {
     for (int v = 0; v < 4; ++v) {
       const int rrow = kq + 4 * v;
       const uint32_t prow = (uint32_t)__shfl((int)pr, rrow);
+      const double scale = __shfl(D, rrow) * kInv2Pi;
       if (base + rrow < end) {
         double* out = a.rows + (size_t)prow * NP;
 #pragma unroll
         for (int n = 0; n < NT; ++n)
-          if (16 * n + col < NP) out[16 * n + col] = acc[n][v] * kInv2Pi;
+          if (16 * n + col < NP) out[16 * n + col] = acc[n][v] * scale;
       }
     }
   }
@@ -1195,21 +1231,21 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
   int32_t* bcnt = nullptr;
   int64_t* boff = nullptr;
   uint32_t* list = nullptr;
-  double *nod0 = nullptr, *nod1 = nullptr, *tab0 = nullptr, *tab1 = nullptr, *nr = nullptr;
-  double *nod2 = nullptr, *tab2 = nullptr;
+  double *tab0 = nullptr, *tab1 = nullptr, *nr = nullptr, *tab2 = nullptr;
+  double2 *nod0 = nullptr, *nod1 = nullptr, *nod2 = nullptr;
   void* stmp = nullptr;
   hipError_t e;
   if ((e = tmp.alloc((void**)&cls, (size_t)n)) != hipSuccess ||
-      (e = tmp.alloc((void**)&nr, sizeof(double) * 6 * std::max<int64_t>(pl->n_tri, 1))) != hipSuccess ||
+      (e = tmp.alloc((void**)&nr, sizeof(double) * 15 * std::max<int64_t>(pl->n_tri, 1))) != hipSuccess ||
       (e = tmp.alloc((void**)&bcnt, sizeof(int32_t) * kNCls * n_blk)) != hipSuccess ||
       (e = tmp.alloc((void**)&boff, sizeof(int64_t) * (kNCls * n_blk + 1))) != hipSuccess ||
       (e = tmp.alloc((void**)&list, sizeof(uint32_t) * n)) != hipSuccess ||
       (e = tmp.alloc(&stmp, exclusive_scan_tmp_bytes(kNCls * n_blk))) != hipSuccess ||
-      (e = tmp.alloc((void**)&nod0, sizeof(double) * 3 * rows0)) != hipSuccess ||
-      (e = tmp.alloc((void**)&nod1, sizeof(double) * 3 * rows1)) != hipSuccess ||
+      (e = tmp.alloc((void**)&nod0, sizeof(double2) * rows0)) != hipSuccess ||
+      (e = tmp.alloc((void**)&nod1, sizeof(double2) * rows1)) != hipSuccess ||
       (e = tmp.alloc((void**)&tab0, sizeof(double) * rows0 * NPP)) != hipSuccess ||
       (e = tmp.alloc((void**)&tab1, sizeof(double) * rows1 * NPP)) != hipSuccess ||
-      (e = tmp.alloc((void**)&nod2, sizeof(double) * 3 * 4 * rows2)) != hipSuccess ||
+      (e = tmp.alloc((void**)&nod2, sizeof(double2) * 4 * rows2)) != hipSuccess ||
       (e = tmp.alloc((void**)&tab2, sizeof(double) * 4 * rows2 * NPP)) != hipSuccess)
     return e;
   ClassArgs c;
@@ -1299,19 +1335,24 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
       } else {
         const int c0 = k - 2;  // configurations c0 and c0 + 1 of the class-2 tables
         ta.rows0 = ta.rows1 = rows2;
-        ta.nod0 = nod2 + 3 * (size_t)c0 * rows2;
-        ta.nod1 = nod2 + 3 * (size_t)(c0 + 1) * rows2;
+        ta.nod0 = nod2 + (size_t)c0 * rows2;
+        ta.nod1 = nod2 + (size_t)(c0 + 1) * rows2;
         ta.tab0 = tab2 + (size_t)c0 * rows2 * NPP;
         ta.tab1 = tab2 + (size_t)(c0 + 1) * rows2 * NPP;
       }
       const int64_t tiles = (ta.n0 + 15) / 16 + (ta.n1 + 15) / 16;
-      const size_t lds = sizeof(double) * 3 * (size_t)(ta.rows0 + ta.rows1);
+      const size_t lds = sizeof(double2) * (size_t)(ta.rows0 + ta.rows1);
       const size_t t0_bytes = sizeof(double) * (size_t)ta.rows0 * NPP;
-      const unsigned nb = (unsigned)std::min<int64_t>((tiles + 3) / 4, 1 << 20);
-      if (t0_bytes <= kTabT0LdsMax)
-        k_rows_tab<P, true><<<nb, 256, lds + t0_bytes, st>>>(ta);
+      const size_t t1_bytes = sizeof(double) * (size_t)ta.rows1 * NPP;
+      const size_t fixed = sizeof(double2) * (kLogTab + 1);
+      const unsigned nb = (unsigned)std::min<int64_t>((tiles + kTabWaves - 1) / kTabWaves,
+                                                      (int64_t)kTabBlocksPerCu * pl->ctx->n_cu);
+      if (fixed + lds + t0_bytes + t1_bytes <= kTabLdsBlock)
+        k_rows_tab<P, 2><<<nb, kTabThreads, lds + t0_bytes + t1_bytes, st>>>(ta);
+      else if (t0_bytes <= kTabT0LdsMax)
+        k_rows_tab<P, 1><<<nb, kTabThreads, lds + t0_bytes, st>>>(ta);
       else
-        k_rows_tab<P, false><<<nb, 256, lds, st>>>(ta);
+        k_rows_tab<P, 0><<<nb, kTabThreads, lds, st>>>(ta);
       ++launches;
     }
     tm.stop(launches);
