@@ -607,6 +607,10 @@ vp_status vp_plan_create(vp_ctx* ctx, const vp_mesh* mesh, int p, int q, double 
   UP(pl->rad_c_a, rca);
   UP(pl->rad_c_b, rcb);
   pl->n_rc = (int)rcr.size();
+  if (p <= vp::kBasisLegMax) {
+    const std::vector<double> bg = vp::basis_connection(p);
+    UP(pl->basis_g, bg);
+  }
 #undef UP
   const int NP = pl->n_p;
   if ((e = vp::plan_alloc(pl, (void**)&pl->vinv, sizeof(double) * NP * NP)) != hipSuccess ||

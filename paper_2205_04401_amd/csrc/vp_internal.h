@@ -42,6 +42,13 @@ void radial_rule(int p, std::vector<double>& r, std::vector<double>& alpha, std:
 // the same sums on p + 1 nodes for a basis of degree <= p along each ray
 // (straight self pieces)
 void radial_rule_folded(int p, std::vector<double>& r, std::vector<double>& alpha, std::vector<double>& beta);
+// Up to this order the row kernels accumulate in the product basis of
+// basis_acc and convert to Koornwinder coefficients once per pair
+// (basis_row).
+constexpr int kBasisLegMax = 6;
+// the conversion's coefficients for order p <= kBasisLegMax: g[i][j],
+// [n_p][p + 1], for Koornwinder index i = n(n+1)/2 + m and j <= n - m
+std::vector<double> basis_connection(int p);
 
 // ---------------------------------------------------------------------------
 // Device Koornwinder basis (Sec. 2.1), division-free in the collapsed
@@ -157,6 +164,60 @@ __device__ __forceinline__ void koornwinder_acc(double x, double y, double w, do
       qm = qn;
     }
   }
+}
+
+// The product basis of the accumulation (orders up to kBasisLegMax): for
+// each m the homogeneous monic Legendre polynomial Qm_m(x, y) = (1-x)^m
+// Pm_m((2y-1+x)/(1-x)) times the monic Legendre polynomials Pm_j(2x-1),
+// j <= P - m, at the Koornwinder index n(n+1)/2 + m (n = m + j).  Pm_j
+// follows Pm_{j+1} = z Pm_j - j^2/(4j^2-1) Pm_{j-1}, so all the z factors
+// come from one recurrence shared by every m instead of one Jacobi
+// sequence per m; K_{m,k} = c_mn P^{(2m+1,0)}_k Q_m is a combination of
+// the Pm_j, j <= k, with the same Qm_m, which basis_finish applies to the
+// accumulated sums.
+template <int P>
+__device__ __forceinline__ void basis_acc(double x, double y, double w, double* acc) {
+  if constexpr (P > kBasisLegMax) {
+    koornwinder_acc<P>(x, y, w, acc);
+  } else {
+    const double t = 1.0 - x;
+    const double s = 2.0 * y - t;
+    const double tt = t * t;
+    const double z = 2.0 * x - 1.0;
+    double L[P + 1];
+    L[0] = 1.0;
+    if (P >= 1) L[1] = z;
+#pragma unroll
+    for (int j = 1; j < P; ++j) L[j + 1] = fma(z, L[j], -((double)(j * j) / (4.0 * j * j - 1.0)) * L[j - 1]);
+    double qm1 = 0.0, qm = 1.0;
+#pragma unroll
+    for (int m = 0; m <= P; ++m) {
+      const double wq = w * qm;
+#pragma unroll
+      for (int j = 0; j + m <= P; ++j) {
+        const int n = m + j;
+        acc[n * (n + 1) / 2 + m] = fma(wq, L[j], acc[n * (n + 1) / 2 + m]);
+      }
+      if (m < P) {
+        const double qn = (m == 0) ? s : fma(s, qm, -((double)(m * m) / (4.0 * m * m - 1.0)) * (tt * qm1));
+        qm1 = qm;
+        qm = qn;
+      }
+    }
+  }
+}
+
+// Koornwinder coefficient i = n(n+1)/2 + m of a pair from the pair's sums
+// of the product basis (sb, at the same indices): sum over j <= k = n - m
+// of g[i][j] times the sum of Qm_m Pm_j; g is [n_p][P + 1]
+template <int P>
+__device__ __forceinline__ double basis_row(const double* sb, const double* __restrict__ g, int i) {
+  int n = 0;
+  while ((n + 1) * (n + 2) / 2 <= i) ++n;
+  const int m = i - n * (n + 1) / 2, k = n - m;
+  double r = 0.0;
+  for (int j = 0; j <= k; ++j) r = fma(g[i * (P + 1) + j], sb[(m + j) * (m + j + 1) / 2 + m], r);
+  return r;
 }
 
 // The naive ball test of the near-field ablation (near: within kappa R of
@@ -434,6 +495,7 @@ struct vp_plan {
   double* gl_s = nullptr;  // [n_l]
   double* gl_w = nullptr;
   double* rad_r = nullptr;  // [n_r]
+  double* basis_g = nullptr;  // [n_p][p + 1] basis_row's coefficients (p <= kBasisLegMax)
   double* rad_a = nullptr;
   double* rad_b = nullptr;
   int n_r = 0;

@@ -69,6 +69,7 @@ struct RowsArgs {
   double* rows;
   int* flag;
   int64_t* stats;  // near leaves, self panels, capped leaves, depth-first pairs
+  const double* basis_g;  // basis_row's coefficients (orders <= kBasisLegMax)
 };
 
 __device__ __forceinline__ int dyadic_count(double len, double d, int cap) {
@@ -168,6 +169,28 @@ __device__ __forceinline__ void near_root(double Ax, double Ay, double Bx, doubl
   }
 }
 
+// A pair's row from the reduced sums (lane holds acc[0 .. len) at base):
+// Koornwinder sums stored as they are; the product basis's sums (orders up
+// to kBasisLegMax) pass through sb (LDS, n_p doubles of the one-wavefront
+// workgroup) and basis_row
+template <int P>
+__device__ __forceinline__ void store_row(const double* acc, int base, int len, int lane, double* sb,
+                                          const double* __restrict__ g, double* out) {
+  constexpr int NP = (P + 1) * (P + 2) / 2;
+  if constexpr (P <= kBasisLegMax) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      if (i < len) sb[base + i] = acc[i];
+    __syncthreads();
+    if (lane < NP) out[lane] = basis_row<P>(sb, g, lane) * kInv2Pi;
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      if (i < len) out[base + i] = acc[i] * kInv2Pi;
+  }
+}
+
 // kCurved: the mesh has curved triangles (the straight-only instance carries
 // none of their code).  KIND: 0 every pair, 1 near pairs only, 2 self pairs
 // only (each of the two then carries only its own branch, with fewer live
@@ -178,6 +201,7 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
   __shared__ double lv[2][kCap * 3];
   __shared__ double leaf[kCap * 3];
   __shared__ double2 tab[kLogTab + 1];
+  __shared__ double sb[NP];  // store_row
   // the small rule tables in LDS (read at every node; global loads there
   // would put a cache round trip into each node's dependency chain):
   // near-rule x, y, w [nn]; Gauss-Legendre s, w [nl]; radial r, a, b [nr];
@@ -276,9 +300,7 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
       const double dx = x - sj.x, dy = y - sj.y;
       const double r2 = fma(dy, dy, fma(dx, dx, kR2Bias));
       const double w = -0.5 * vp_log(r2, tab) * a.swj[(int64_t)t * a.nf + j];
-      const double* E = a.efar + (size_t)j * NP;
-#pragma unroll
-      for (int k = 0; k < NP; ++k) acc[k] = fma(w, E[k], acc[k]);
+      basis_acc<P>(a.far_x[j], a.far_y[j], w, acc);
     }
   };
   add_far_rule();
@@ -379,7 +401,7 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
         }
         const double dx = x - yx, dy = y - yy;
         const double w = 0.5 * vp_log(dx * dx + dy * dy, tab) * s_nw[nd] * ss * ss * jac;
-        koornwinder_acc<P>(xi1, xi2, w, acc);
+        basis_acc<P>(xi1, xi2, w, acc);
       }
       __syncthreads();
       double* sw = cur;
@@ -454,7 +476,7 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
             }
             const double dx = x - yx, dy = y - yy;
             const double w = 0.5 * vp_log(dx * dx + dy * dy, tab) * s_nw[nd] * ss * ss * jac;
-            koornwinder_acc<P>(xi1, xi2, w, acc);
+            basis_acc<P>(xi1, xi2, w, acc);
           }
         }
       }
@@ -523,7 +545,7 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
           const double jac = vp_blend_jac(Ax, Ay, Bx, By, Cx, Cy, cf, a.cv.deg, yr1, yr2, qx, qy);
           const double lam = 0.5 * vp_log((qx - x) * (qx - x) + (qy - y) * (qy - y), tab) - vp_log(rr, tab);
           const double w = h * ws * (s_ca[ir] * lam + s_cb[ir]) * jac;
-          koornwinder_acc<P>(yr1, yr2, w, acc);
+          basis_acc<P>(yr1, yr2, w, acc);
         }
       }
     } else {
@@ -582,7 +604,7 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
         for (int ir = 0; ir < a.nr; ++ir) {
           const double rr = s_rr[ir];
           const double w = hws * fma(s_ra[ir], hlog, s_rb[ir]);
-          koornwinder_acc<P>(fma(rr, d1, z1), fma(rr, d2, z2), w, acc);
+          basis_acc<P>(fma(rr, d1, z1), fma(rr, d2, z2), w, acc);
         }
       }
     }
@@ -594,9 +616,7 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
   {
     int base = 0, len = NP;
     ReduceScatter<NP, 32>::run(acc, lane, base, len);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-      if (i < len) out[base + i] = acc[i] * kInv2Pi;
+    store_row<P>(acc, base, len, lane, sb, a.basis_g, out);
   }
   tot_leaves += n_leaves;
   tot_panels += n_panels;
@@ -651,6 +671,7 @@ __global__ __launch_bounds__(64) void k_rows_deep(RowsArgs a, const double* __re
   __shared__ double lv[2][kDeepLv * 3];
   __shared__ double leaf[kDeepLeaf * 3];
   __shared__ double2 tab[kLogTab + 1];
+  __shared__ double sb[NP];  // store_row
   // near-rule x, y, w [nn]; far-rule x, y [nf]
   extern __shared__ double rule_tabs[];
   double* const s_nx = rule_tabs;
@@ -795,14 +816,12 @@ __global__ __launch_bounds__(64) void k_rows_deep(RowsArgs a, const double* __re
         r2 = dx * dx + dy * dy;
         wf = s_nw[nd] * ss * ss * D;
       }
-      koornwinder_acc<P>(xi1, xi2, 0.5 * vp_log(r2, tab) * wf, acc);
+      basis_acc<P>(xi1, xi2, 0.5 * vp_log(r2, tab) * wf, acc);
     }
     double* out = a.rows + (size_t)pr * NP;
     int base = 0, len = NP;
     ReduceScatter<NP, 32>::run(acc, lane, base, len);
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-      if (i < len) out[base + i] = acc[i] * kInv2Pi;
+    store_row<P>(acc, base, len, lane, sb, a.basis_g, out);
     tot_leaves += n_leaf;
     tot_capped += n_capped;
     __syncthreads();
@@ -1423,6 +1442,7 @@ hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t s
   a.far_y = pl->far_y;
   a.far_w = pl->far_w;
   a.efar = pl->efar;
+  a.basis_g = pl->basis_g;
   a.nf = pl->n_f;
   a.near_x = pl->near_x;
   a.near_y = pl->near_y;

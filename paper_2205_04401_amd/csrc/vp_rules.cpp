@@ -289,6 +289,57 @@ void radial_rule_folded(int p, std::vector<double>& r, std::vector<double>& alph
   }
 }
 
+std::vector<double> basis_connection(int p) {
+  const int np = (p + 1) * (p + 2) / 2;
+  std::vector<double> g((size_t)np * (p + 1), 0.0);
+  // P^{(a,0)}_k(z) for a = 2m + 1 in monomials (the three-term recurrence
+  // of the device basis), then in the monic Legendre polynomials Pm_j
+  // (highest degree first: Pm_j is monic), times c_mn and the leading
+  // coefficient (2m)! / (2^m m!^2) of the Legendre polynomial in Q_m
+  std::vector<std::vector<ld>> pm(p + 1);
+  pm[0] = {1.0L};
+  if (p >= 1) pm[1] = {0.0L, 1.0L};
+  for (int j = 1; j < p; ++j) {
+    std::vector<ld> nx(j + 2, 0.0L);
+    for (int i = 0; i <= j; ++i) nx[i + 1] += pm[j][i];
+    const ld e = (ld)(j * j) / (ld)(4 * j * j - 1);
+    for (int i = 0; i < j; ++i) nx[i] -= e * pm[j - 1][i];
+    pm[j + 1] = nx;
+  }
+  ld lead = 1.0L;  // (2m)! / (2^m m!^2)
+  for (int m = 0; m <= p; ++m) {
+    if (m > 0) lead *= (ld)(2 * m - 1) / (ld)m;
+    const int K = p - m;
+    const ld a = 2.0L * m + 1.0L;
+    std::vector<std::vector<ld>> jac(K + 1);
+    jac[0] = {1.0L};
+    if (K >= 1) jac[1] = {0.5L * a, 0.5L * (a + 2.0L)};
+    for (int k = 2; k <= K; ++k) {
+      const ld c1 = 2.0L * k + a - 1.0L, c2 = (2.0L * k + a) * (2.0L * k + a - 2.0L);
+      const ld c3 = 2.0L * (k + a - 1.0L) * (k - 1.0L) * (2.0L * k + a);
+      const ld inv = 1.0L / (2.0L * k * (k + a) * (2.0L * k + a - 2.0L));
+      std::vector<ld> nx(k + 1, 0.0L);
+      for (int i = 0; i < k; ++i) {
+        nx[i + 1] += c1 * c2 * jac[k - 1][i] * inv;
+        nx[i] += c1 * a * a * jac[k - 1][i] * inv;
+      }
+      for (int i = 0; i < k - 1; ++i) nx[i] -= c3 * jac[k - 2][i] * inv;
+      jac[k] = nx;
+    }
+    for (int k = 0; k <= K; ++k) {
+      const ld c = std::sqrt((ld)(2 * (2 * m + 1) * (m + k + 1))) * lead;
+      std::vector<ld> rem = jac[k];
+      for (int j = k; j >= 0; --j) {
+        const ld cj = rem[j];
+        for (int i = 0; i <= j; ++i) rem[i] -= cj * pm[j][i];
+        const int n = m + k;
+        g[(size_t)(n * (n + 1) / 2 + m) * (p + 1) + j] = (double)(c * cj);
+      }
+    }
+  }
+  return g;
+}
+
 // The rules depend on their order alone and every plan asks for several of
 // them (0.4 ms of host time for the 16 x 16 collapsed rule): each is computed
 // once per process and copied out afterwards.
