@@ -670,7 +670,9 @@ __global__ __launch_bounds__(64) void k_rows_deep(RowsArgs a, const double* __re
   constexpr int NP = (P + 1) * (P + 2) / 2;
   __shared__ double lv[2][kDeepLv * 3];
   __shared__ double leaf[kDeepLeaf * 3];
-  __shared__ double2 tab[kLogTab + 1];
+  // the logarithm's table through the caches: without its 4 KiB in LDS a
+  // fourth wavefront fits on each SIMD (the registers allow four)
+  const double2* __restrict__ tab = a.logtab;
   __shared__ double sb[NP];  // store_row
   // near-rule x, y, w [nn]; far-rule x, y [nf]
   extern __shared__ double rule_tabs[];
@@ -680,7 +682,6 @@ __global__ __launch_bounds__(64) void k_rows_deep(RowsArgs a, const double* __re
   double* const s_fx = s_nw + a.nn;
   double* const s_fy = s_fx + a.nf;
   const int lane = threadIdx.x;
-  for (int i = lane; i <= kLogTab; i += kWave) tab[i] = a.logtab[i];
   for (int i = lane; i < a.nn; i += kWave) {
     s_nx[i] = a.near_x[i];
     s_ny[i] = a.near_y[i];
@@ -1174,8 +1175,9 @@ __global__ __launch_bounds__(kTabThreads, (P <= 4) ? 6 : 5) void k_rows_tab(TabA
     const uint32_t pr = a.list[valid ? base + col : base];
     const int32_t t = a.pair_tri[pr];
     const int32_t it = a.pair_tgt[pr];
-    const double x = a.xt[it], y = a.yt[it];
     const double Ax = a.ax[t], Ay = a.ay[t];
+    // the target relative to the vertex A (exact for a target near A)
+    const double px = a.xt[it] - Ax, py = a.yt[it] - Ay;
     const double e1x = a.bx[t] - Ax, e1y = a.by[t] - Ay, e2x = a.cx[t] - Ax, e2y = a.cy[t] - Ay;
     const double D = a.det[t];
     const double2* N = one ? nod + a.rows0 : nod;
@@ -1186,21 +1188,19 @@ __global__ __launch_bounds__(kTabThreads, (P <= 4) ? 6 : 5) void k_rows_tab(TabA
 #pragma unroll
     for (int n = 0; n < NT; ++n)
       acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(0.0, 0.0, vp_d4{0.0, 0.0, 0.0, 0.0}, 0, 0, 0);
-    // Every slot alike: the node's position from the triangle's map (for the
-    // far nodes the far sums' own expression, so a pair at distance 0
-    // cancels) and r^2 with the far sums' offset (far below any near node's
-    // r^2).  The weights are in the table (negative for the far rule's own
-    // contribution, which is subtracted; zero in padding rows), the
-    // triangle's Jacobian scales the finished row.
+    // Every slot alike: the target's offset from the node, r^2 and its
+    // logarithm.  The target of a near pair lies outside the triangle and
+    // every node inside, so r^2 > 0 without the far sums' offset (which
+    // would change nothing here).  The weights are in the table (negative
+    // for the far rule's own contribution, which is subtracted; zero in
+    // padding rows), the triangle's Jacobian scales the finished row.
     auto steps = [&](auto trow) {
       for (int s0 = 0; s0 < n_slots; s0 += 4) {
         const int slot = s0 + kq;
         const double2 xi = N[slot];
-        const double xi1 = xi.x, xi2 = xi.y;
-        const double yx = Ax + xi1 * e1x + xi2 * e2x;
-        const double yy = Ay + xi1 * e1y + xi2 * e2y;
-        const double dx = x - yx, dy = y - yy;
-        const double r2 = fma(dy, dy, fma(dx, dx, kR2Bias));
+        const double dx = fma(-xi.y, e2x, fma(-xi.x, e1x, px));
+        const double dy = fma(-xi.y, e2y, fma(-xi.x, e1y, py));
+        const double r2 = fma(dx, dx, dy * dy);
         const double g = vp_log(r2, tab);
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[n] = __builtin_amdgcn_mfma_f64_16x16x4f64(g, trow(slot, n), acc[n], 0, 0, 0);
