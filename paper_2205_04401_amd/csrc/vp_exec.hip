@@ -561,14 +561,15 @@ __global__ __launch_bounds__(kBlock) void k_finish_flat(const double* __restrict
     for (int64_t s = lane; s < n_split; s += G) u += partial[((size_t)s * n_tgt + t) * R + r];
     if (!far_only) {
       const int64_t p0 = row_ptr[t];
-      const int64_t nv = (row_ptr[t + 1] - p0) * NP;
+      // one target's values (its pairs x n_p) stay far below 2^31
+      const uint32_t nv = (uint32_t)((row_ptr[t + 1] - p0) * NP);
       const double* rw = rows + (size_t)p0 * NP;
+      const int32_t* tri = pair_tri + p0;
       double corr = 0.0;
 #pragma unroll 4
-      for (int64_t f = lane; f < nv; f += G) {
-        const int64_t j = f / NP;
-        const int k = (int)(f - j * NP);
-        corr = fma(rw[f], C[((size_t)pair_tri[p0 + j] * NP + k) * R + r], corr);
+      for (uint32_t f = lane; f < nv; f += G) {
+        const uint32_t j = f / NP, k = f - j * NP;
+        corr = fma(rw[f], C[((size_t)tri[j] * NP + k) * R + r], corr);
       }
       u += corr;
     }

@@ -551,6 +551,12 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
     } else {
     const double area = 0.5 * D;
     const double vx[3] = {Ax, Bx, Cx}, vy[3] = {Ay, By, Cy};
+    // the target in reference coordinates: the apex of every ray, the
+    // radial rule's node r = 0 (s_rr[0] = 0), whose weights the lanes sum
+    // and whose basis values join once per pair
+    const double ox = x - Ax, oy = y - Ay;
+    const double z1 = (ox * e2y - oy * e2x) * invD, z2 = (e1x * oy - e1y * ox) * invD;
+    double w_apex = 0.0;
     for (int side = 0; side < 3; ++side) {
       const double Px = vx[side], Py = vy[side], Qx = vx[(side + 1) % 3], Qy = vy[(side + 1) % 3];
       const double sub = 0.5 * fabs((Px - x) * (Qy - y) - (Py - y) * (Qx - x));
@@ -598,16 +604,17 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
         const double r0sq = (gx - x) * (gx - x) + (gy - y) * (gy - y);
         const double hlog = 0.5 * vp_log(r0sq, tab);
         // the ray from x to g in reference coordinates
-        const double ox = x - Ax, oy = y - Ay, gdx = gx - x, gdy = gy - y;
-        const double z1 = (ox * e2y - oy * e2x) * invD, z2 = (e1x * oy - e1y * ox) * invD;
+        const double gdx = gx - x, gdy = gy - y;
         const double d1 = (gdx * e2y - gdy * e2x) * invD, d2 = (e1x * gdy - e1y * gdx) * invD;
-        for (int ir = 0; ir < a.nr; ++ir) {
+        w_apex = fma(hws, fma(s_ra[0], hlog, s_rb[0]), w_apex);
+        for (int ir = 1; ir < a.nr; ++ir) {
           const double rr = s_rr[ir];
           const double w = hws * fma(s_ra[ir], hlog, s_rb[ir]);
           basis_acc<P>(fma(rr, d1, z1), fma(rr, d2, z2), w, acc);
         }
       }
     }
+    basis_acc<P>(z1, z2, w_apex, acc);
     }  // straight self pair
   }
 

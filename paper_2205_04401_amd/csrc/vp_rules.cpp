@@ -267,12 +267,15 @@ void radial_rule_folded(int p, std::vector<double>& r, std::vector<double>& alph
   // nodes rho_j, with A_j = sum_i alpha_i l_j(r_i), B_j = sum_i beta_i
   // l_j(r_i) (l_j the Lagrange polynomials of the rho_j): the same integrals
   // int_0^1 r l_j(r) dr and int_0^1 r log(r) l_j(r) dr, with p + 1 basis
-  // evaluations per ray instead of 2 radial_half(p).  rho_j: the (p+1)-point
+  // evaluations per ray instead of 2 radial_half(p).  rho_0 = 0, the ray's
+  // apex (the target itself, the same point on every ray of a piece, so
+  // its basis values are needed once per pair), then the p-point
   // Gauss-Legendre nodes on [0, 1] (small Lagrange polynomials on [0, 1]).
   std::vector<double> ri, ai, bi;
   radial_rule(p, ri, ai, bi);
-  const Rule1D g = gauss_legendre01(p + 1);
-  r.assign(g.x.begin(), g.x.end());
+  const Rule1D g = gauss_legendre01(p);
+  r.assign(1, 0.0);
+  r.insert(r.end(), g.x.begin(), g.x.end());
   alpha.assign(p + 1, 0.0);
   beta.assign(p + 1, 0.0);
   for (int j = 0; j <= p; ++j) {
@@ -280,7 +283,7 @@ void radial_rule_folded(int p, std::vector<double>& r, std::vector<double>& alph
     for (size_t i = 0; i < ri.size(); ++i) {
       ld l = 1.0L;
       for (int k = 0; k <= p; ++k)
-        if (k != j) l *= ((ld)ri[i] - (ld)g.x[k]) / ((ld)g.x[j] - (ld)g.x[k]);
+        if (k != j) l *= ((ld)ri[i] - (ld)r[k]) / ((ld)r[j] - (ld)r[k]);
       A += (ld)ai[i] * l;
       B += (ld)bi[i] * l;
     }
