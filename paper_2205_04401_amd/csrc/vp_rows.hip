@@ -202,6 +202,8 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
   __shared__ double leaf[kCap * 3];
   __shared__ double2 tab[kLogTab + 1];
   __shared__ double sb[NP];  // store_row
+  __shared__ double4 piece_d[3][2];  // straight self pair: its three pieces' parameters
+  __shared__ int2 piece_i[3];
   // the small rule tables in LDS (read at every node; global loads there
   // would put a cache round trip into each node's dependency chain):
   // near-rule x, y, w [nn]; Gauss-Legendre s, w [nl]; radial r, a, b [nr];
@@ -557,61 +559,83 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
     const double ox = x - Ax, oy = y - Ay;
     const double z1 = (ox * e2y - oy * e2x) * invD, z2 = (e1x * oy - e1y * ox) * invD;
     double w_apex = 0.0;
+    // The three pieces' parameters first (the same in every lane; lane 0
+    // keeps them in LDS), then one flat loop over every (piece, panel, arc
+    // node) of the pair, so that the lanes stay full across the pieces:
+    // per piece its start P, direction u, height h, foot position st,
+    // length L, L - st, and the dyadic panel counts n1, n2.
+    int off1 = 0, off2 = 0, n_items = 0;
     for (int side = 0; side < 3; ++side) {
       const double Px = vx[side], Py = vy[side], Qx = vx[(side + 1) % 3], Qy = vy[(side + 1) % 3];
       const double sub = 0.5 * fabs((Px - x) * (Qy - y) - (Py - y) * (Qx - x));
-      if (sub <= a.tau * area) continue;
-      const double L = sqrt((Qx - Px) * (Qx - Px) + (Qy - Py) * (Qy - Py));
-      const double ux = (Qx - Px) / L, uy = (Qy - Py) / L;
-      const double h = fabs((Px - x) * (Qy - Py) - (Py - y) * (Qx - Px)) / L;
-      const double st = fmin(fmax((x - Px) * ux + (y - Py) * uy, 0.0), L);
-      const double fx = Px + st * ux, fy = Py + st * uy;
-      const double d = sqrt((x - fx) * (x - fx) + (y - fy) * (y - fy));
-      const double rest = L - st;
-      const int n1 = (st > 0.0) ? dyadic_count(st, d, a.dyadic_cap) : -1;
-      const int n2 = (rest > 0.0) ? dyadic_count(rest, d, a.dyadic_cap) : -1;
-      const int nleft = n1 + 1, nright = n2 + 1;  // panels per side (0 if empty)
-      const int np = nleft + nright;
+      int np = 0;
+      if (sub > a.tau * area) {
+        const double L = sqrt((Qx - Px) * (Qx - Px) + (Qy - Py) * (Qy - Py));
+        const double ux = (Qx - Px) / L, uy = (Qy - Py) / L;
+        const double h = fabs((Px - x) * (Qy - Py) - (Py - y) * (Qx - Px)) / L;
+        const double st = fmin(fmax((x - Px) * ux + (y - Py) * uy, 0.0), L);
+        const double fx = Px + st * ux, fy = Py + st * uy;
+        const double d = sqrt((x - fx) * (x - fx) + (y - fy) * (y - fy));
+        const double rest = L - st;
+        const int n1 = (st > 0.0) ? dyadic_count(st, d, a.dyadic_cap) : -1;
+        const int n2 = (rest > 0.0) ? dyadic_count(rest, d, a.dyadic_cap) : -1;
+        np = (n1 + 1) + (n2 + 1);  // panels toward the foot and beyond it (0 if empty)
+        if (lane == 0) {
+          piece_d[side][0] = make_double4(Px, Py, ux, uy);
+          piece_d[side][1] = make_double4(h, st, L, rest);
+          piece_i[side] = make_int2(n1, n2);
+        }
+      }
       n_panels += np;
-      // lanes over (panel, arc node); the radial nodes of the ray share the
-      // ray's arc position and its log r0 term
-      const int items = np * a.nl;
-      for (int item = lane; item < items; item += kWave) {
-        const int ip = item / a.nl;
-        const int il = item - ip * a.nl;
-        double s0, s1;
-        if (ip < nleft) {
-          if (ip < n1) {
-            s0 = (1.0 - ldexp(1.0, -ip)) * st;
-            s1 = (1.0 - ldexp(1.0, -(ip + 1))) * st;
-          } else {
-            s0 = (1.0 - ldexp(1.0, -n1)) * st;
-            s1 = st;
-          }
+      if (side == 0) off1 = np * a.nl;
+      if (side == 1) off2 = off1 + np * a.nl;
+      if (side == 2) n_items = off2 + np * a.nl;
+    }
+    __syncthreads();
+    // lanes over (piece, panel, arc node); the radial nodes of the ray share
+    // the ray's arc position and its log r0 term
+    for (int item = lane; item < n_items; item += kWave) {
+      const int side = item >= off2 ? 2 : (item >= off1 ? 1 : 0);
+      const int rel = item - (side == 2 ? off2 : (side == 1 ? off1 : 0));
+      const int ip = rel / a.nl;
+      const int il = rel - ip * a.nl;
+      const double4 pa = piece_d[side][0], pb = piece_d[side][1];
+      const int2 pn = piece_i[side];
+      const double Px = pa.x, Py = pa.y, ux = pa.z, uy = pa.w;
+      const double h = pb.x, st = pb.y, L = pb.z, rest = pb.w;
+      const int n1 = pn.x, n2 = pn.y, nleft = n1 + 1;
+      double s0, s1;
+      if (ip < nleft) {
+        if (ip < n1) {
+          s0 = (1.0 - ldexp(1.0, -ip)) * st;
+          s1 = (1.0 - ldexp(1.0, -(ip + 1))) * st;
         } else {
-          const int jp = ip - nleft;
-          if (jp < n2) {
-            s0 = L - (1.0 - ldexp(1.0, -(jp + 1))) * rest;
-            s1 = L - (1.0 - ldexp(1.0, -jp)) * rest;
-          } else {
-            s0 = st;
-            s1 = L - (1.0 - ldexp(1.0, -n2)) * rest;
-          }
+          s0 = (1.0 - ldexp(1.0, -n1)) * st;
+          s1 = st;
         }
-        const double s = s0 + (s1 - s0) * s_gs[il];
-        const double hws = h * (s1 - s0) * s_gw[il];
-        const double gx = Px + s * ux, gy = Py + s * uy;
-        const double r0sq = (gx - x) * (gx - x) + (gy - y) * (gy - y);
-        const double hlog = 0.5 * vp_log(r0sq, tab);
-        // the ray from x to g in reference coordinates
-        const double gdx = gx - x, gdy = gy - y;
-        const double d1 = (gdx * e2y - gdy * e2x) * invD, d2 = (e1x * gdy - e1y * gdx) * invD;
-        w_apex = fma(hws, fma(s_ra[0], hlog, s_rb[0]), w_apex);
-        for (int ir = 1; ir < a.nr; ++ir) {
-          const double rr = s_rr[ir];
-          const double w = hws * fma(s_ra[ir], hlog, s_rb[ir]);
-          basis_acc<P>(fma(rr, d1, z1), fma(rr, d2, z2), w, acc);
+      } else {
+        const int jp = ip - nleft;
+        if (jp < n2) {
+          s0 = L - (1.0 - ldexp(1.0, -(jp + 1))) * rest;
+          s1 = L - (1.0 - ldexp(1.0, -jp)) * rest;
+        } else {
+          s0 = st;
+          s1 = L - (1.0 - ldexp(1.0, -n2)) * rest;
         }
+      }
+      const double s = s0 + (s1 - s0) * s_gs[il];
+      const double hws = h * (s1 - s0) * s_gw[il];
+      const double gx = Px + s * ux, gy = Py + s * uy;
+      const double r0sq = (gx - x) * (gx - x) + (gy - y) * (gy - y);
+      const double hlog = 0.5 * vp_log(r0sq, tab);
+      // the ray from x to g in reference coordinates
+      const double gdx = gx - x, gdy = gy - y;
+      const double d1 = (gdx * e2y - gdy * e2x) * invD, d2 = (e1x * gdy - e1y * gdx) * invD;
+      w_apex = fma(hws, fma(s_ra[0], hlog, s_rb[0]), w_apex);
+      for (int ir = 1; ir < a.nr; ++ir) {
+        const double rr = s_rr[ir];
+        const double w = hws * fma(s_ra[ir], hlog, s_rb[ir]);
+        basis_acc<P>(fma(rr, d1, z1), fma(rr, d2, z2), w, acc);
       }
     }
     basis_acc<P>(z1, z2, w_apex, acc);
