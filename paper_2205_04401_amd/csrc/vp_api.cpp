@@ -274,7 +274,7 @@ vp_status vp_mesh_create(vp_ctx* ctx, int64_t n_vert, const double* vert, int64_
   if (n_vert < 0 || n_tri < 0 || n_tri > 0x7fffffffLL) return fail(VP_EINVAL, "vp_mesh_create: bad sizes");
   if (n_tri > 0 && (!vert || !tri)) return fail(VP_EINVAL, "vp_mesh_create: NULL arrays");
   VP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-  const size_t bytes = 7 * sizeof(double) * std::max<int64_t>(n_tri, 1);
+  const size_t bytes = 15 * sizeof(double) * std::max<int64_t>(n_tri, 1);
   if (!vp::ctx_fits(ctx, bytes)) return fail(VP_ENOMEM, "vp_mesh_create: %zu bytes exceed the HBM budget", bytes);
   vp_mesh* m = new vp_mesh;
   m->ctx = ctx;
@@ -286,13 +286,14 @@ vp_status vp_mesh_create(vp_ctx* ctx, int64_t n_vert, const double* vert, int64_
     return hip_fail(e, "vp_mesh_create: hipMalloc");
   }
   const size_t T = std::max<int64_t>(n_tri, 1);
-  m->ax = base;
-  m->ay = base + T;
-  m->bx = base + 2 * T;
-  m->by = base + 3 * T;
-  m->cx = base + 4 * T;
-  m->cy = base + 5 * T;
-  m->det = base + 6 * T;
+  m->geo = (double4*)base;  // first: 32-byte aligned
+  m->ax = base + 8 * T;
+  m->ay = base + 9 * T;
+  m->bx = base + 10 * T;
+  m->by = base + 11 * T;
+  m->cx = base + 12 * T;
+  m->cy = base + 13 * T;
+  m->det = base + 14 * T;
   m->bytes = bytes;
   hipStream_t st = ctx->stream;
   double* d_vert = nullptr;
@@ -340,7 +341,7 @@ vp_status vp_mesh_destroy(vp_mesh* m) {
   if (!m) return VP_OK;
   if (m->live_plans) return fail(VP_EBUSY, "vp_mesh_destroy: %d plans still use this mesh", m->live_plans);
   (void)hipSetDevice(m->ctx->device);
-  (void)hipFree(m->ax);
+  (void)hipFree(m->geo);  // the base of the mesh block
   for (void* q : {(void*)m->curve_of, (void*)m->curve_tri, (void*)m->curve_coef, (void*)m->curve_box})
     if (q) (void)hipFree(q);
   m->ctx->in_use -= m->bytes;
@@ -482,6 +483,19 @@ vp_status vp_mesh_set_curved_sides(vp_mesh* m, int64_t n, const int32_t* tri, co
     of[t] = (int32_t)i;
     ctri[i] = t;
   }
+  // the packed copy of the geometry, with the curved triangles' new vertex order
+  std::vector<double> gp((size_t)8 * T);
+  for (int64_t t = 0; t < T; ++t) {
+    double* q = gp.data() + 8 * t;
+    q[0] = ax[t];
+    q[1] = ay[t];
+    q[2] = bx[t];
+    q[3] = by[t];
+    q[4] = cx[t];
+    q[5] = cy[t];
+    q[6] = det[t];
+    q[7] = 0.0;
+  }
   const size_t bytes = sizeof(int32_t) * (T + n) + sizeof(double) * (coef.size() + box.size());
   if (!vp::ctx_fits(m->ctx, bytes))
     return fail(VP_ENOMEM, "vp_mesh_set_curved_sides: %zu bytes exceed the HBM budget", bytes);
@@ -498,6 +512,7 @@ vp_status vp_mesh_set_curved_sides(vp_mesh* m, int64_t n, const int32_t* tri, co
       (e = hipMemcpyAsync(m->curve_box, box.data(), sizeof(double) * box.size(), hipMemcpyHostToDevice, st)) !=
           hipSuccess ||
       (e = hipMemcpyAsync(m->ax, g.data(), sizeof(double) * 7 * T, hipMemcpyHostToDevice, st)) != hipSuccess ||
+      (e = hipMemcpyAsync(m->geo, gp.data(), sizeof(double) * 8 * T, hipMemcpyHostToDevice, st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess) {
     for (void* q : {(void*)m->curve_of, (void*)m->curve_tri, (void*)m->curve_coef, (void*)m->curve_box})
       if (q) (void)hipFree(q);

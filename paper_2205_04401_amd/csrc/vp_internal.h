@@ -447,12 +447,24 @@ struct vp_ctx {
   int64_t launches[VP_N_STAGES] = {};
 };
 
+// one triangle's packed geometry (vp_mesh::geo)
+struct TriGeo {
+  double ax, ay, bx, by, cx, cy, det;
+};
+__device__ __forceinline__ TriGeo tri_geo(const double4* __restrict__ geo, int64_t t) {
+  const double4 p = geo[2 * t], q = geo[2 * t + 1];
+  return TriGeo{p.x, p.y, p.z, p.w, q.x, q.y, q.z};
+}
+
 struct vp_mesh {
   vp_ctx* ctx = nullptr;
   int64_t n_tri = 0;
   // oriented geometry, SoA [n_tri] each: A, B, C, D = det[B-A, C-A] > 0
   double *ax = nullptr, *ay = nullptr, *bx = nullptr, *by = nullptr, *cx = nullptr, *cy = nullptr,
          *det = nullptr;
+  // the same packed per triangle, [n_tri][2]: (Ax, Ay, Bx, By), (Cx, Cy, D, 0)
+  // (the per-pair kernels read a triangle from one 64-byte line)
+  double4* geo = nullptr;
   size_t bytes = 0;
   int live_plans = 0;
   // curved boundary triangles (vp_mesh_set_curved_sides): device arrays

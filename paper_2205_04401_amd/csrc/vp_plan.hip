@@ -23,7 +23,7 @@ inline unsigned blocks_for(int64_t n, int b = kBlock) { return (unsigned)((n + b
 // ---------------------------------------------------------------------------
 __global__ void k_mesh_geom(const double* __restrict__ vert, int64_t n_vert, const int32_t* __restrict__ tri,
                             int64_t n_tri, double* ax, double* ay, double* bx, double* by, double* cx,
-                            double* cy, double* det, int* bad) {
+                            double* cy, double* det, double4* geo, int* bad) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_tri) return;
   int32_t i0 = tri[3 * t], i1 = tri[3 * t + 1], i2 = tri[3 * t + 2];
@@ -60,6 +60,8 @@ __global__ void k_mesh_geom(const double* __restrict__ vert, int64_t n_vert, con
   cx[t] = x2;
   cy[t] = y2;
   det[t] = d;
+  geo[2 * t] = make_double4(x0, y0, x1, y1);
+  geo[2 * t + 1] = make_double4(x2, y2, d, 0.0);
 }
 
 __global__ void k_split_xy(const double* __restrict__ xy, int64_t n, double* x, double* y, int* bad) {
@@ -400,6 +402,7 @@ struct TriView {
   // self region for tau up to 1e-10)
   const double* box;
   int box_reject;
+  const double4* geo;  // the geometry packed per triangle
 };
 
 // 0 = self, 1 = near, 2 = far
@@ -411,8 +414,9 @@ __device__ __forceinline__ int classify(const TriView& tv, int32_t t, double x, 
     const double4 b = *(const double4*)(tv.box + 4 * (int64_t)t);
     if (x < b.x || y < b.y || x > b.z || y > b.w) return 2;
   }
-  const double Ax = tv.ax[t], Ay = tv.ay[t], Bx = tv.bx[t], By = tv.by[t], Cx = tv.cx[t], Cy = tv.cy[t];
-  const double D = tv.det[t];
+  const TriGeo tg = tri_geo(tv.geo, t);
+  const double Ax = tg.ax, Ay = tg.ay, Bx = tg.bx, By = tg.by, Cx = tg.cx, Cy = tg.cy;
+  const double D = tg.det;
   const double d0 = x - Ax, d1 = y - Ay;
   const double e1x = Bx - Ax, e1y = By - Ay, e2x = Cx - Ax, e2y = Cy - Ay;
   const double xi1 = (d0 * e2y - d1 * e2x) / D;
@@ -650,7 +654,7 @@ hipError_t launch_mesh_geom(const double* vert, int64_t n_vert, const int32_t* t
                             int* d_bad, hipStream_t st) {
   if (n_tri > 0)
     k_mesh_geom<<<blocks_for(n_tri), kBlock, 0, st>>>(vert, n_vert, tri, n_tri, m->ax, m->ay, m->bx, m->by, m->cx,
-                                                      m->cy, m->det, d_bad);
+                                                      m->cy, m->det, m->geo, d_bad);
   return hipGetLastError();
 }
 
@@ -915,7 +919,8 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
              pl->opts.ball_factor,
              m->curves(),
              box,
-             pl->opts.tau <= 1e-10 ? 1 : 0};
+             pl->opts.tau <= 1e-10 ? 1 : 0,
+             m->geo};
   // decision bits of every (target, cell triangle): word offsets per target
   int32_t* wcnt = nullptr;
   int64_t* woff = nullptr;

@@ -45,6 +45,7 @@ struct RowsArgs {
   int64_t n_list;
   const double *xt, *yt;
   const double *ax, *ay, *bx, *by, *cx, *cy, *det;
+  const double4* geo;  // the same, packed per triangle
   const double *far_x, *far_y, *far_w, *efar;
   int nf;
   const double *near_x, *near_y, *near_w;
@@ -254,8 +255,9 @@ __global__ __launch_bounds__(64) void k_rows(RowsArgs a) {
   const int kind = a.pair_kind[pr];
   if ((KIND == 1 && kind != 1) || (KIND == 2 && kind == 1)) continue;  // the whole workgroup
   const double x = a.xt[it], y = a.yt[it];
-  const double Ax = a.ax[t], Ay = a.ay[t], Bx = a.bx[t], By = a.by[t], Cx = a.cx[t], Cy = a.cy[t];
-  const double D = a.det[t];
+  const TriGeo tg = tri_geo(a.geo, t);
+  const double Ax = tg.ax, Ay = tg.ay, Bx = tg.bx, By = tg.by, Cx = tg.cx, Cy = tg.cy;
+  const double D = tg.det;
   const double e1x = Bx - Ax, e1y = By - Ay, e2x = Cx - Ax, e2y = Cy - Ay;
   const double invD = 1.0 / D;
   const int cvi = (kCurved && a.cv.of) ? a.cv.of[t] : -1;  // curve of a curved triangle, -1 if straight
@@ -732,14 +734,15 @@ __global__ __launch_bounds__(64) void k_rows_deep(RowsArgs a, const double* __re
     const int32_t it = a.pair_tgt[pr];
     const int split1 = cls[pr] >> 4;  // level-1 children that split (class pass)
     const double x = a.xt[it], y = a.yt[it];
-    const double Ax = a.ax[t], Ay = a.ay[t];
-    const double e1x = a.bx[t] - Ax, e1y = a.by[t] - Ay, e2x = a.cx[t] - Ax, e2y = a.cy[t] - Ay;
-    const double D = a.det[t];
+    const TriGeo tg = tri_geo(a.geo, t);
+    const double Ax = tg.ax, Ay = tg.ay;
+    const double e1x = tg.bx - Ax, e1y = tg.by - Ay, e2x = tg.cx - Ax, e2y = tg.cy - Ay;
+    const double D = tg.det;
     double rho0[3], ell0[3];
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
-      rho0[e] = nr[e * n_tri + t];
-      ell0[e] = nr[(3 + e) * n_tri + t];
+      rho0[e] = nr[16 * (int64_t)t + e];
+      ell0[e] = nr[16 * (int64_t)t + 3 + e];
     }
     // the ellipse thresholds of every level at once: lane L holds level L's
     // (the depth cap is at most 60)
@@ -901,7 +904,8 @@ struct ClassArgs {
   int64_t n_pairs, n_blk;
   const double *xt, *yt;
   const double *ax, *ay, *bx, *by, *cx, *cy, *det, *deff;
-  const double* nr;  // [15][n_tri] near-rule rho0, edge lengths, thresholds of levels 0-2 (k_near_root)
+  const double4* geo;  // the same, packed per triangle
+  const double* nr;  // [n_tri][16] near-rule rho0, edge lengths, thresholds of levels 0-2 (k_near_root)
   int64_t n_tri;
   double nwhat0, nwhat1, nwhat2, eps_cn, inv_near_order;
   int depth_cap;
@@ -922,10 +926,11 @@ __device__ __forceinline__ int pair_class(const ClassArgs& a, int64_t pr) {
   const int32_t t = a.pair_tri[pr];
   const int32_t it = a.pair_tgt[pr];
   const double x = a.xt[it], y = a.yt[it];
-  const double Ax = a.ax[t], Ay = a.ay[t];
-  const double e1x = a.bx[t] - Ax, e1y = a.by[t] - Ay, e2x = a.cx[t] - Ax, e2y = a.cy[t] - Ay;
-  const double* thr = a.nr + 6 * a.n_tri + t;  // thr[(3 L + e) n_tri]: level L, edge e
-  auto T = [&](int level, int e) { return thr[(3 * level + e) * a.n_tri]; };
+  const TriGeo tg = tri_geo(a.geo, t);
+  const double Ax = tg.ax, Ay = tg.ay;
+  const double e1x = tg.bx - Ax, e1y = tg.by - Ay, e2x = tg.cx - Ax, e2y = tg.cy - Ay;
+  const double* thr = a.nr + 16 * (int64_t)t + 6;  // thr[3 L + e]: level L, edge e
+  auto T = [&](int level, int e) { return thr[3 * level + e]; };
   // distance from the target to the point (u, v) of the reference simplex
   auto dist = [&](double u, double v) {
     const double px = fma(v, e2x, fma(u, e1x, Ax)), py = fma(v, e2y, fma(u, e1y, Ay));
@@ -962,9 +967,9 @@ __device__ __forceinline__ int pair_class(const ClassArgs& a, int64_t pr) {
 }
 
 // near-rule rho0, edge lengths and the focal-sum thresholds of levels 0-2
-// of every triangle: nr[e][T] = rho0_e, nr[3 + e][T] = l_e (the values
-// k_rows computes for each pair), nr[6 + 3 L + e][T] = threshold of edge e
-// at level L
+// of every triangle, one 128-byte line each: nr[T][e] = rho0_e, nr[T][3 + e]
+// = l_e (the values k_rows computes for each pair), nr[T][6 + 3 L + e] =
+// threshold of edge e at level L
 __global__ void k_near_root(const double* __restrict__ ax, const double* __restrict__ ay,
                             const double* __restrict__ bx, const double* __restrict__ by,
                             const double* __restrict__ cx, const double* __restrict__ cy,
@@ -975,18 +980,20 @@ __global__ void k_near_root(const double* __restrict__ ax, const double* __restr
   const double wh[3] = {w0, w1, w2};
   double rho0[3], ell0[3];
   near_root(ax[t], ay[t], bx[t], by[t], cx[t], cy[t], deff[t], wh, eps_cn, inv_near_order, rho0, ell0);
+  double* row = nr + 16 * t;
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
-    nr[e * n_tri + t] = rho0[e];
-    nr[(3 + e) * n_tri + t] = ell0[e];
+    row[e] = rho0[e];
+    row[3 + e] = ell0[e];
   }
 #pragma unroll
   for (int level = 0; level < 3; ++level) {
     double thr[3];
     near_level_thr(rho0, ell0, level, inv_near_order, thr);
 #pragma unroll
-    for (int e = 0; e < 3; ++e) nr[(6 + 3 * level + e) * n_tri + t] = thr[e];
+    for (int e = 0; e < 3; ++e) row[6 + 3 * level + e] = thr[e];
   }
+  row[15] = 0.0;
 }
 
 // count pass: class of every pair, pairs of each class per block
@@ -1163,6 +1170,7 @@ struct TabArgs {
   const int32_t *pair_tri, *pair_tgt;
   const double *xt, *yt;
   const double *ax, *ay, *bx, *by, *cx, *cy, *det;
+  const double4* geo;  // the same, packed per triangle
   int rows0, rows1;  // slots of class 0 and class 1 (multiples of 4)
   const double2 *nod0, *nod1;
   const double *tab0, *tab1;
@@ -1206,11 +1214,11 @@ __global__ __launch_bounds__(kTabThreads, (P <= 4) ? 6 : 5) void k_rows_tab(TabA
     const uint32_t pr = a.list[valid ? base + col : base];
     const int32_t t = a.pair_tri[pr];
     const int32_t it = a.pair_tgt[pr];
-    const double Ax = a.ax[t], Ay = a.ay[t];
+    const TriGeo tg = tri_geo(a.geo, t);
     // the target relative to the vertex A (exact for a target near A)
-    const double px = a.xt[it] - Ax, py = a.yt[it] - Ay;
-    const double e1x = a.bx[t] - Ax, e1y = a.by[t] - Ay, e2x = a.cx[t] - Ax, e2y = a.cy[t] - Ay;
-    const double D = a.det[t];
+    const double px = a.xt[it] - tg.ax, py = a.yt[it] - tg.ay;
+    const double e1x = tg.bx - tg.ax, e1y = tg.by - tg.ay, e2x = tg.cx - tg.ax, e2y = tg.cy - tg.ay;
+    const double D = tg.det;
     const double2* N = one ? nod + a.rows0 : nod;
     const int n_slots = one ? a.rows1 : a.rows0;
     vp_d4 acc[NT];
@@ -1286,7 +1294,7 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
   void* stmp = nullptr;
   hipError_t e;
   if ((e = tmp.alloc((void**)&cls, (size_t)n)) != hipSuccess ||
-      (e = tmp.alloc((void**)&nr, sizeof(double) * 15 * std::max<int64_t>(pl->n_tri, 1))) != hipSuccess ||
+      (e = tmp.alloc((void**)&nr, sizeof(double) * 16 * std::max<int64_t>(pl->n_tri, 1))) != hipSuccess ||
       (e = tmp.alloc((void**)&bcnt, sizeof(int32_t) * kNCls * n_blk)) != hipSuccess ||
       (e = tmp.alloc((void**)&boff, sizeof(int64_t) * (kNCls * n_blk + 1))) != hipSuccess ||
       (e = tmp.alloc((void**)&list, sizeof(uint32_t) * n)) != hipSuccess ||
@@ -1313,6 +1321,7 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
   c.cx = m->cx;
   c.cy = m->cy;
   c.det = m->det;
+  c.geo = m->geo;
   c.deff = pl->deff;
   c.nr = nr;
   c.n_tri = pl->n_tri;
@@ -1361,6 +1370,7 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
   ta.cx = m->cx;
   ta.cy = m->cy;
   ta.det = m->det;
+  ta.geo = m->geo;
   ta.logtab = pl->logtab;
   ta.rows = pl->rows;
   const int64_t n_tab = cnt[0] + cnt[1] + cnt[2] + cnt[3] + cnt[4] + cnt[5];
@@ -1469,6 +1479,7 @@ hipError_t launch_rows(vp_plan* pl, int* d_flag, int64_t* d_stats, hipStream_t s
   a.cx = m->cx;
   a.cy = m->cy;
   a.det = m->det;
+  a.geo = m->geo;
   a.far_x = pl->far_x;
   a.far_y = pl->far_y;
   a.far_w = pl->far_w;
