@@ -496,38 +496,44 @@ __global__ void k_pair_count(const double* __restrict__ xt, const double* __rest
   cnt[i] = n;
 }
 
-// Fill pass, one wavefront per target: the lanes take 64 of the cell's
-// triangles at a time with their decision bits from the count pass and
-// write the pairs among them at consecutive places (ballot and prefix
-// count), so that the stores of a wavefront are contiguous; the cell lists
-// are ascending, so are the target's pairs.  A target whose pairs do not
-// fill its range exactly sets *bad (it writes nothing beyond its range).
+// Fill pass, 16 lanes per target (four targets per wavefront, so that the
+// loads that locate a target's cell and bits overlap for four targets):
+// the lanes take 16 of the cell's triangles at a time with their decision
+// bits from the count pass and write the pairs among them at consecutive
+// places (ballot and prefix count within the 16), so that the stores of a
+// target are contiguous; the cell lists are ascending, so are the
+// target's pairs.  A target whose pairs do not fill its range exactly sets
+// *bad (it writes nothing beyond its range).
 constexpr int kFillWaves = 4;
+constexpr int kFillLanes = 16;  // lanes per target
+constexpr int kFillPerWave = 64 / kFillLanes;
 
 __global__ __launch_bounds__(kFillWaves * 64) void k_pair_fill(
     const double* __restrict__ xt, const double* __restrict__ yt, int64_t n_tgt, Grid g,
     const int64_t* __restrict__ cptr, const int32_t* __restrict__ ctri, const int64_t* __restrict__ woff,
     const uint2* __restrict__ mk, const int64_t* __restrict__ row_ptr, int32_t* pair_tri, int32_t* pair_tgt,
     uint8_t* pair_kind, int32_t* self_cnt, int* bad) {
-  const int lane = threadIdx.x & 63;
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int64_t i = (int64_t)blockIdx.x * kFillWaves + (threadIdx.x >> 6); i < n_tgt;
-       i += (int64_t)gridDim.x * kFillWaves) {
+  const int lane = threadIdx.x & 63, sub = lane / kFillLanes, gl = lane % kFillLanes;
+  const uint64_t gmask = ((1ull << kFillLanes) - 1) << (kFillLanes * sub);  // this target's lanes
+  const uint64_t lt = ((1ull << gl) - 1) << (kFillLanes * sub);            // its lanes below this one
+  const int64_t per_block = (int64_t)kFillWaves * kFillPerWave;
+  for (int64_t i = (int64_t)blockIdx.x * per_block + (threadIdx.x >> 6) * kFillPerWave + sub; i < n_tgt;
+       i += (int64_t)gridDim.x * per_block) {
     const int64_t c = cell_of(g, xt[i], yt[i]);
     const int64_t k0 = cptr[c], k1 = cptr[c + 1];
     const uint2* bits = mk + woff[i];
     const int64_t end = row_ptr[i + 1];
     int64_t o = row_ptr[i];
     int ns = 0;
-    for (int64_t kb = k0; kb < k1; kb += 64) {
-      const int64_t k = kb + lane;
+    for (int64_t kb = k0; kb < k1; kb += kFillLanes) {
+      const int64_t k = kb + gl;
       const bool in = k < k1;
       const uint2 w = in ? bits[(k - k0) >> 5] : make_uint2(0u, 0u);
       const int b = (int)((k - k0) & 31);
       const bool is_pair = in && ((w.x >> b) & 1u);
       const bool is_self = in && ((w.y >> b) & 1u);
-      const uint64_t m = __ballot(is_pair);
-      ns += __popcll(__ballot(is_self));
+      const uint64_t m = __ballot(is_pair) & gmask;
+      ns += __popcll(__ballot(is_self) & gmask);
       const int64_t pos = o + __popcll(m & lt);
       if (is_pair && pos < end) {
         pair_tri[pos] = ctri[k];
@@ -536,7 +542,7 @@ __global__ __launch_bounds__(kFillWaves * 64) void k_pair_fill(
       }
       o += __popcll(m);
     }
-    if (lane == 0) {
+    if (gl == 0) {
       self_cnt[i] = ns;
       if (o != end) atomicOr(bad, 1);
     }
@@ -977,7 +983,8 @@ hipError_t build_pairs(vp_plan* pl, hipStream_t st, std::string& err) {
     return e;
   }
   if (NT > 0) {
-    const int64_t nb = std::min<int64_t>((NT + kFillWaves - 1) / kFillWaves, (int64_t)1 << 22);
+    const int64_t nb = std::min<int64_t>((NT + kFillWaves * kFillPerWave - 1) / (kFillWaves * kFillPerWave),
+                                         (int64_t)1 << 22);
     k_pair_fill<<<(unsigned)nb, kFillWaves * 64, 0, st>>>(pl->xt, pl->yt, NT, g, cptr, ctri, woff, mk, pl->row_ptr,
                                                           pl->pair_tri, pl->pair_tgt, pl->pair_kind, scnt,
                                                           (int*)(d_sum + 1));
