@@ -128,12 +128,17 @@ def rel_err(u, ref):
 # ---------------------------------------------------------------------------
 
 # Algorithmic FP64 flops of one node evaluation in the correction rows:
-# geometry and weight 10, the log counted as 1, then per basis function
-# 3 for the Koornwinder recurrence and 2 to accumulate (k_rows); with the
+# geometry and weight 10, the log counted as 1, 2 per basis function to
+# accumulate, and the basis values: up to order 6 the product basis of the
+# row kernels (4 for the collapsed coordinates, 2 per step of the Legendre
+# recurrence in 2x-1 and 3 per step of the one in the collapsed direction,
+# p - 1 steps each, and p + 1 products with the weight), above it 3 per
+# basis function for the Koornwinder recurrences (k_rows); with the
 # Koornwinder values from a table (k_rows_tab) only the 2 of the
 # contraction, on the matrix cores.
-def rows_flops_per_node(n_p):
-    return 11 + 5 * n_p
+def rows_flops_per_node(n_p, p):
+    basis = 4 + 5 * (p - 1) + (p + 1) if p <= 6 else 3 * n_p
+    return 11 + 2 * n_p + basis
 
 
 def tab_flops_per_node(n_p):
@@ -145,7 +150,10 @@ def stage_rooflines(info, tm, steps, q_near=7, n_l=16):
     work over the stage's average device time)."""
     n_p, n_tgt, n_pairs, T = info["n_p"], info["n_tgt"], info["n_pairs"], info["n_tri"]
     n_f, nn = info["n_f"], q_near * q_near
-    n_r = info["p"] + 1  # radial nodes per ray of a straight self piece (the folded radial rule)
+    # radial nodes per ray of a straight self piece (the folded radial rule)
+    # other than its apex, which is the target on every ray: evaluated once
+    # per pair
+    n_r = info["p"]
     n_self, tab_pairs, tab_leaves = info["n_self"], info["tab_pairs"], info["tab_leaves"]
     out = {}
 
@@ -167,12 +175,12 @@ def stage_rooflines(info, tm, steps, q_near=7, n_l=16):
     p = info["p"]
     alu("rows_tab", "rows_tab", tab_pairs * n_f + tab_leaves * nn, tab_flops_per_node(n_p), f"k_rows_tab<{p}, *>")
     alu("rows_near", "rows_near", (info["near_subtri"] - tab_leaves) * nn + near_deep * n_f,
-        rows_flops_per_node(n_p), f"k_rows_deep<{p}>")
-    alu("rows_self", "rows_self", info["self_panels"] * n_l * n_r + n_self * n_f, rows_flops_per_node(n_p),
+        rows_flops_per_node(n_p, p), f"k_rows_deep<{p}>")
+    alu("rows_self", "rows_self", info["self_panels"] * n_l * n_r + n_self * (n_f + 1), rows_flops_per_node(n_p, p),
         f"k_rows<{p}, false, 2>")
     if "rows_tab" not in out and "rows_near" not in out:
-        nodes = info["near_subtri"] * nn + info["self_panels"] * n_l * n_r + n_pairs * n_f
-        alu("rows", "rows", nodes, rows_flops_per_node(n_p), f"k_rows<{p}>")
+        nodes = info["near_subtri"] * nn + info["self_panels"] * n_l * n_r + n_pairs * n_f + n_self
+        alu("rows", "rows", nodes, rows_flops_per_node(n_p, p), f"k_rows<{p}>")
     # near lists: targets read in the count and fill passes, CSR and pairs written
     ms, n = tm.get("classify", (0.0, 0))
     if n:
