@@ -179,7 +179,8 @@ vp_status vp_ref_nodes(int p, double* xy_out, int* n_p_out);
  *              BC, CA) used in eq. rho0 -> w[0..2]
  *           5  the radial rule of order n folded onto n + 1 nodes, as the
  *              plans use it for straight self pairs (same layout as 3; the
- *              same sums for phi of degree <= n) 
+ *              same sums for phi of degree <= n): r = 0 (the ray's apex)
+ *              and the n-point Gauss-Legendre nodes on [0,1]
  * *count receives the number of entries; any output may be NULL. */
 vp_status vp_ref_rule(int which, int n, double* x, double* y, double* w, int* count);
 
