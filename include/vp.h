@@ -181,6 +181,12 @@ vp_status vp_ref_nodes(int p, double* xy_out, int* n_p_out);
  *              plans use it for straight self pairs (same layout as 3; the
  *              same sums for phi of degree <= n): r = 0 (the ray's apex)
  *              and the n-point Gauss-Legendre nodes on [0,1]
+ *           6  the row kernels' conversion from their product basis to the
+ *              Koornwinder basis of order n <= 6 (Sec. 2.1) -> w only,
+ *              [n_p][n + 1]: K_i(x,y) = sum_{j <= n_i - m_i} w[i][j]
+ *              Qm_{m_i}(x,y) Pm_j(2x-1) for i = n_i(n_i+1)/2 + m_i, with Pm_j
+ *              the monic Legendre polynomials (Pm_{j+1} = z Pm_j - j^2/(4j^2-1)
+ *              Pm_{j-1}) and Qm_m = (1-x)^m Pm_m((2y-1+x)/(1-x))
  * *count receives the number of entries; any output may be NULL. */
 vp_status vp_ref_rule(int which, int n, double* x, double* y, double* w, int* count);
 

@@ -256,6 +256,11 @@ vp_status vp_ref_rule(int which, int n, double* x, double* y, double* w, int* co
       if (n > vp::kMaxP) return fail(VP_EINVAL, "vp_ref_rule: order %d outside [1, %d]", n, vp::kMaxP);
       vp::radial_rule_folded(n, rx, ry, rw);
     } break;
+    case 6: {
+      if (n > vp::kBasisLegMax)
+        return fail(VP_EINVAL, "vp_ref_rule: the product basis is used up to order %d, not %d", vp::kBasisLegMax, n);
+      rw = vp::basis_connection(n);
+    } break;
     default:
       return fail(VP_EINVAL, "vp_ref_rule: unknown rule %d", which);
   }

@@ -132,6 +132,41 @@ def test_folded_radial_rule(p):
     assert abs(np.sum(b * r ** (p + 1)) + 1.0 / (p + 3) ** 2) > 1e-12
 
 
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+def test_basis_connection_reproduces_koornwinder(p):
+    """The row kernels' product basis (monic Legendre in 2x-1 times the
+    homogeneous monic Legendre polynomial in the collapsed direction), through
+    the library's connection table, gives the oracle's Koornwinder basis
+    (Sec. 2.1) at points of the simplex, its vertices and edges included."""
+    _, _, g = vp.ref_rule(6, p)
+    n_p = rules.n_basis(p)
+    g = np.asarray(g).reshape(n_p, p + 1)
+    rng = np.random.default_rng(60 + p)
+    u, v = rng.random(200), rng.random(200)
+    flip = u + v > 1.0
+    u[flip], v[flip] = 1.0 - u[flip], 1.0 - v[flip]
+    x = np.concatenate([u, [0.0, 1.0, 0.0, 0.5, 0.0, 0.5, 1.0 / 3.0]])
+    y = np.concatenate([v, [0.0, 0.0, 1.0, 0.0, 0.5, 0.5, 1.0 / 3.0]])
+    t, z = 1.0 - x, 2.0 * x - 1.0
+    s = 2.0 * y - t
+    pm = [np.ones_like(z), z]
+    qm = [np.ones_like(z), s]
+    for j in range(1, p):
+        e = j * j / (4.0 * j * j - 1.0)
+        pm.append(z * pm[j] - e * pm[j - 1])
+        qm.append(s * qm[j] - e * t * t * qm[j - 1])
+    got = np.zeros((len(x), n_p))
+    for n in range(p + 1):
+        for m in range(n + 1):
+            i = n * (n + 1) // 2 + m
+            assert np.all(g[i, n - m + 1:] == 0.0)
+            got[:, i] = sum(g[i, j] * qm[m] * pm[j] for j in range(n - m + 1))
+    ref = rules.koornwinder(p, x, y)
+    assert np.abs(got - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max())
+    with pytest.raises(vp.VPError):
+        vp.ref_rule(6, 7)
+
+
 def test_invalid_rule_requests_are_rejected():
     with pytest.raises(vp.VPError) as e:
         vp.ref_rule(7, 4)
