@@ -511,6 +511,17 @@ def far_probe(mixed):
     ctx.close()
 
 
+def batched_probe():
+    """The 100k-star section with 64 densities at q = 8 alone (FP64 and
+    mixed: plan and two evaluations each), for kernel traces."""
+    import torch
+    from paper_2205_04401_amd import vp
+    ctx = vp.Context(0, stream=torch.cuda.current_stream().cuda_stream)
+    res = sweep_batched(ctx, [8])
+    print(json.dumps({"batched_probe": res}), flush=True)
+    ctx.close()
+
+
 def copy_probe(n_bytes=1 << 29, reps=3):
     """A plain device-to-device copy of known size (the calibration kernel
     for the FETCH_SIZE / WRITE_SIZE counters)."""
@@ -712,6 +723,8 @@ def main():
                     help="only the mixed line's step, once (counter runs of the FP32 far sum)")
     ap.add_argument("--direct-probe", action="store_true",
                     help="only the direct line's step, once (counter runs of the FP64 far sum)")
+    ap.add_argument("--batched-probe", action="store_true",
+                    help="only the 100k star with 64 densities at q = 8 (kernel traces of the batched FMM path)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -724,6 +737,9 @@ def main():
         return
     if args.mixed_probe or args.direct_probe:
         far_probe(mixed=args.mixed_probe)
+        return
+    if args.batched_probe:
+        batched_probe()
         return
     # the oracle's worker processes start before anything touches the GPU
     pool, n_workers = None, 0
