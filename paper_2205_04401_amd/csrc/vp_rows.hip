@@ -913,6 +913,7 @@ struct ClassArgs {
   int32_t* bcnt;    // [kNCls][n_blk] pairs of each class per block
   const int64_t* boff;  // [kNCls n_blk + 1] exclusive scan of bcnt (scatter pass)
   uint32_t* list;       // [n_pairs] pair indices sorted by class (scatter pass)
+  int2* stt;            // [pairs of classes 0-5] their (triangle, target), in the same order
 };
 
 // depth class of near pair pr: the tests of k_rows' first levels; for a
@@ -1054,6 +1055,7 @@ __global__ __launch_bounds__(kClsThreads) void k_pair_scatter(ClassArgs a) {
         }
       for (int v = 0; v < w; ++v) o += wtot[v][c];
       a.list[o + __popcll(mc & lt)] = (uint32_t)pr;
+      if (c < kClsDeep) a.stt[o + __popcll(mc & lt)] = make_int2(a.pair_tri[pr], a.pair_tgt[pr]);
     }
 #pragma unroll
     for (int k = 0; k < kNCls; ++k)
@@ -1166,6 +1168,7 @@ typedef double vp_d4 __attribute__((ext_vector_type(4)));
 
 struct TabArgs {
   const uint32_t* list;  // class 0 pairs, then class 1 pairs
+  const int2* stt;       // their (triangle, target), in the same order
   int64_t n0, n1;
   const int32_t *pair_tri, *pair_tgt;
   const double *xt, *yt;
@@ -1211,9 +1214,12 @@ __global__ __launch_bounds__(kTabThreads, (P <= 4) ? 6 : 5) void k_rows_tab(TabA
     const int64_t base = one ? a.n0 + (tile - t0) * 16 : tile * 16;
     const int64_t end = one ? a.n0 + a.n1 : a.n0;
     const bool valid = base + col < end;
-    const uint32_t pr = a.list[valid ? base + col : base];
-    const int32_t t = a.pair_tri[pr];
-    const int32_t it = a.pair_tgt[pr];
+    const int64_t at = valid ? base + col : base;
+    // the pair index (for the row) and its triangle and target, side by side
+    const uint32_t pr = a.list[at];
+    const int2 tt = a.stt[at];
+    const int32_t t = tt.x;
+    const int32_t it = tt.y;
     const TriGeo tg = tri_geo(a.geo, t);
     // the target relative to the vertex A (exact for a target near A)
     const double px = a.xt[it] - tg.ax, py = a.yt[it] - tg.ay;
@@ -1357,6 +1363,9 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
   int64_t cnt[kNCls];
   for (int k = 0; k < kNCls; ++k) cnt[k] = tot[k + 1] - tot[k];
   if (tot[kNCls] != n) return hipErrorUnknown;
+  int2* stt = nullptr;
+  if ((e = tmp.alloc((void**)&stt, sizeof(int2) * std::max<int64_t>(tot[kClsDeep], 1))) != hipSuccess) return e;
+  c.stt = stt;
   k_pair_scatter<<<(unsigned)n_blk, kClsThreads, 0, st>>>(c);
   TabArgs ta;
   ta.pair_tri = pl->pair_tri;
@@ -1383,6 +1392,7 @@ hipError_t rows_by_class(vp_plan* pl, RowsArgs a, size_t lds, hipStream_t st) {
     for (int k = 0; k < 6; k += 2) {
       if (cnt[k] + cnt[k + 1] == 0) continue;
       ta.list = list + tot[k];
+      ta.stt = stt + tot[k];
       ta.n0 = cnt[k];
       ta.n1 = cnt[k + 1];
       if (k == 0) {
